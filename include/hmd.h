@@ -1,0 +1,238 @@
+/*
+ * hmd.h -- C ABI of libhmd: an MI355X (gfx950) NEMD channel micro-solver and
+ * the surrogates of a hybrid continuum-atomistic channel-flow scheme.
+ *
+ * Method: D. Stephenson, J. R. Kermode, D. A. Lockerby, "Accelerating a
+ * hybrid continuum-atomistic fluidic model with on-the-fly machine learning"
+ * (arXiv:1603.04628).
+ *
+ * Conventions for every call
+ *   - Reduced Lennard-Jones units: eps = sigma = m = k_B = 1.
+ *   - Host arrays passed in are owned by the caller and copied before the call
+ *     returns; host arrays passed out are caller-allocated with the stated size.
+ *   - Device memory, HIP streams and graphs are owned by the library and freed
+ *     by the matching *_free / hmd_destroy.
+ *   - Every int-returning call returns HMD_OK (0) or a negative hmd_status; a
+ *     message is kept per context and read with hmd_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - A context and everything created from it is NOT thread-safe: use one
+ *     context per host thread.  Calls on one context run in order on its
+ *     stream and return after their results are on the host.
+ */
+#ifndef HMD_H
+#define HMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HMD_OK = 0,
+    HMD_EINVAL = -1,     /* bad argument (null pointer, size, range)            */
+    HMD_EDEVICE = -2,    /* a HIP runtime call failed                           */
+    HMD_ENOMEM = -3,     /* host or device allocation failed                    */
+    HMD_EUNSTABLE = -4,  /* MD blew up: non-finite state or an atom left the gap */
+    HMD_ENOTCONV = -5,   /* sampled flux not stationary (critical shear), Sec. 3.2 */
+    HMD_ENOTSPD = -6,    /* GP covariance not positive definite                 */
+    HMD_ENOSYS = -7      /* not available in this build                         */
+} hmd_status;
+
+typedef struct hmd_ctx hmd_ctx;
+typedef struct hmd_sys hmd_sys;
+typedef struct hmd_batch hmd_batch;
+typedef struct hmd_gp hmd_gp;
+typedef struct hmd_ens hmd_ens;
+typedef struct hmd_hybrid hmd_hybrid;
+
+/* ------------------------------------------------------------------------
+ * MD model parameters (Appendix A of the paper: shifted LJ fluid, frozen
+ * FCC walls, velocity Verlet, Berendsen thermostat on one velocity component,
+ * periodic in x (streamwise) and z (spanwise); body force of Eq. momentumEq).
+ * hmd_md_params_default() fills the stated defaults:
+ *   rho 0.8, T0 1, rc 2.5, eps_wf 1, sigma_wf 1, rho_wall 1, wall_layers 4,
+ *   thermo_axis 1 (y), dt 0.005, tau_T 0.1, Lx = Lz = 12 (nominal, snapped to
+ *   whole wall cubes), bin_dy 0.25, n_equil 0, n_blocks 20, n_fluid 0
+ *   (= round(rho Lx Lz h)), delta 1 (first lattice plane above a wall).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double rho, T0, rc, eps_wf, sigma_wf, rho_wall;
+    int wall_layers, thermo_axis;
+    double dt, tau_T, Lx_nom, Lz_nom, bin_dy;
+    int64_t n_equil;
+    int n_blocks;
+    int64_t n_fluid;
+    double delta;
+} hmd_md_params;
+
+void hmd_md_params_default(hmd_md_params* p);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * run on, or NULL for a library-owned stream (default priority).  `params`
+ * may be NULL for the defaults.  *out receives the context. */
+int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ctx** out);
+void hmd_destroy(hmd_ctx* ctx);
+const char* hmd_last_error(const hmd_ctx* ctx);
+/* Replace the MD parameters used by later calls on this context. */
+int hmd_set_params(hmd_ctx* ctx, const hmd_md_params* params);
+
+/* ------------------------------------------------------------------------
+ * The micro-solve.  A job is one NEMD channel (Sec. 2.1, quasi-steady
+ * subdomain run): channel height h (gap between the innermost wall planes),
+ * body-force acceleration g along +x (g = F/m of Eq. momentumEq, i.e.
+ * F_ext/m - (1/rho) dp/dx), Philox seed, number of sampling steps after
+ * params.n_equil equilibration steps.
+ * Result: mean mass flow rate per unit span q' = sum(m v_x)/(Lx Lz) over the
+ * sampled steps, its standard error from params.n_blocks contiguous block
+ * means (Sec. 2.3: noise from the instantaneous data), J = q'/h, the sampled
+ * kinetic temperatures per component, the potential energy per atom at the
+ * end, the fluid atom count and a per-job status (HMD_OK, HMD_EUNSTABLE,
+ * HMD_ENOTCONV).
+ * ------------------------------------------------------------------------ */
+typedef struct { double h, g; uint64_t seed; int64_t n_sample; } hmd_md_job;
+typedef struct { double flux, flux_se, jflux, T[3], pe; int64_t n_fluid; int status; } hmd_md_result;
+
+/* One job; flux and se receive q' and its standard error.  Returns the job's
+ * status (a failed run returns HMD_EUNSTABLE / HMD_ENOTCONV with the values
+ * still written). */
+int md_flux(hmd_ctx* ctx, double h, double g, uint64_t seed, int64_t steps, double* flux, double* se);
+
+/* n jobs of any heights and forces run together as one batch (one flattened
+ * launch per kernel, step loop replayed as a HIP graph).  out[n] receives
+ * per-job results, each with its own status; the call returns HMD_OK unless
+ * the batch as a whole could not run. */
+int md_flux_batch(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_md_result* out);
+
+/* Staged form of md_flux_batch, for timing the step loop alone: create sets
+ * up and uploads every system; run advances all systems by `steps` steps
+ * (the equilibration + sampling schedule counts from creation); results
+ * writes what md_flux_batch would; graph_chunk > 0 replays the step loop as a
+ * HIP graph of that many steps (even), 0 launches kernels one by one. */
+int md_batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out);
+int md_batch_run(hmd_batch* b, int64_t steps, int graph_chunk);
+int md_batch_results(hmd_batch* b, hmd_md_result* out);
+/* Fluid atoms summed over the batch (for atom-step rates). */
+int64_t md_batch_atoms(const hmd_batch* b);
+/* Average duration in ms of each kernel over the md_batch_run calls made
+ * since timing was switched on (HIP events on the batch's stream, captured
+ * into the graph when graph_chunk > 0): names are "integrate", "scan",
+ * "scatter", "reorder", "force"; "graph_step" gives the average time of one
+ * step of graph replays. */
+int md_batch_set_timing(hmd_batch* b, int on);
+int md_batch_kernel_ms(const hmd_batch* b, const char* kernel, double* ms, int64_t* launches);
+/* In-cutoff pairs at the current positions, summed over the batch:
+ * ordered fluid-fluid pairs (each unordered pair counted twice, once per
+ * atom of the full neighbour sum) and wall-fluid pairs.  Runs one extra
+ * force evaluation (forces unchanged). */
+int md_batch_pair_count(hmd_batch* b, int64_t* fluid_pairs, int64_t* wall_pairs);
+void md_batch_free(hmd_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Single-system hooks (tests, checkpoint/restart).  Atom order in every
+ * array below is the atom id order fixed at creation.
+ * ------------------------------------------------------------------------ */
+int md_sys_create(hmd_ctx* ctx, double h, double g, uint64_t seed, hmd_sys** out);
+/* n_fluid, n_wall, box = {Lx, h, Lz}, ncell = {nx, ny, nz} fluid cells. */
+int md_sys_info(hmd_sys* s, int64_t* n_fluid, int64_t* n_wall, double box[3], int ncell[3]);
+/* x, v: n_fluid x 3 doubles, row-major.  set_state recomputes forces. */
+int md_set_state(hmd_sys* s, const double* x, const double* v);
+int md_get_state(hmd_sys* s, double* x, double* v, int64_t* n_fluid);
+/* FP32 pair forces (plus g is NOT included) for the current positions:
+ * f is n_fluid x 3 floats; pe (nullable) the shifted potential energy. */
+int md_compute_forces(hmd_sys* s, float* f, double* pe);
+/* Cell lists of the current positions: cell_of_atom[n_fluid] (fluid cell
+ * index (cz*ny + cy)*nx + cx), cell_count[nx*ny*nz], order[n_fluid] = atom ids
+ * cell-major (order within a cell = the library's stable sort order). */
+int md_cell_lists(hmd_sys* s, uint32_t* cell_of_atom, uint32_t* cell_count, uint32_t* order);
+/* Advance `steps` steps; thermostat_on = 0 gives NVE (plus the body force);
+ * energy_trace (nullable, `steps` doubles): total energy per atom after each
+ * step. */
+int md_run(hmd_sys* s, int64_t steps, int thermostat_on, double* energy_trace);
+/* Wall-normal profile accumulated over the sampled steps: per bin of width
+ * params.bin_dy from y = 0, the sum of v_x and the atom count (ceil(h/bin_dy)
+ * doubles each). */
+int md_sys_profile(hmd_sys* s, double* mvx, double* cnt);
+void md_sys_free(hmd_sys* s);
+
+/* ------------------------------------------------------------------------
+ * Gaussian-process surrogate (Sec. 2.2): squared-exponential kernel
+ * (Eq. quadraticKernelEq) on inputs normalised by the mean separation of the
+ * database inputs (Eq. d2Eq), noisy covariance C = K + sigma_n^2 I
+ * (Eq. covarianceEq), posterior mean and variance (Eqs. predMeanEq,
+ * predVarEq), log marginal likelihood (Eq. evidenceEq).  Prior mean zero.
+ * X is row-major n x d; y the outputs; y_se (nullable) per-point standard
+ * errors used to set sigma_n when hyper->sigma_n < 0.  All FP64, on device.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double sigma_f, ell, sigma_n;  /* sigma_n < 0: mean(y_se) / output scale */
+    int scale_mode;                /* 0: mean pairwise separation; 1: fixed ranges */
+    double range[4];               /* per-input ranges for scale_mode 1 / fallback */
+    int out_scale;                 /* 1: divide y by its RMS before fitting */
+} hmd_gp_hyper;
+
+void hmd_gp_hyper_default(hmd_gp_hyper* h);
+int gp_fit(hmd_ctx* ctx, const double* X, const double* y, const double* y_se, int n, int d,
+           const hmd_gp_hyper* hyper, hmd_gp** out);
+/* Append one observation (Alg. 1: database growth and covariance update). */
+int gp_append(hmd_gp* gp, const double* x, double y, double y_se);
+/* mean[m], var[m] (latent posterior variance, output units^2). */
+int gp_predict(hmd_gp* gp, const double* Xs, int m, double* mean, double* var);
+int gp_log_marginal(hmd_gp* gp, double* lml);
+int gp_size(const hmd_gp* gp);
+void gp_free(hmd_gp* gp);
+
+/* ------------------------------------------------------------------------
+ * MLP deep ensemble (a learned surrogate beside the GP; not in the paper):
+ * `members` nets of 2 -> hidden -> hidden -> 1 with tanh, FP32, trained
+ * full-batch with Adam on standardised inputs and scaled outputs by the
+ * library's own forward/backward kernels.
+ * ------------------------------------------------------------------------ */
+typedef struct { int members, hidden, iters; double lr; uint64_t seed; } hmd_ens_cfg;
+
+void hmd_ens_cfg_default(hmd_ens_cfg* c);
+int ens_fit(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg, hmd_ens** out);
+/* mean[m], std[m] (sample standard deviation over members). */
+int ens_predict(hmd_ens* e, const double* Xs, int m, double* mean, double* std);
+/* Final training loss per member (MSE on scaled outputs), members values. */
+int ens_loss(const hmd_ens* e, double* loss);
+/* Gradients of the MSE loss of member `k` for its initial parameters
+ * (test hook): grad receives the flattened parameter gradient. */
+int ens_grad_init(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg,
+                  int member, double* params, double* grad, int* n_params);
+void ens_free(hmd_ens* e);
+
+/* ------------------------------------------------------------------------
+ * Hybrid macro solve (Alg. 1): 1-D unsteady mass conservation
+ * (Eq. continuityEq) on n_sections cross-sections of a channel
+ * h(s) = h0 (1 + amp cos(2 pi s / L)); pressure from a linear equation of
+ * state p = p_out + c2 (rho - rho_ref); per section the body force of
+ * Eq. momentumEq; flux from the surrogate, or from batched MD when the
+ * surrogate's standard deviation exceeds tau_rel * |mean|; MD results are
+ * appended to the surrogate's database.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int n_sections;
+    double h0, amp, L, dt_macro, rho_ref, p_out, dp_mean, dp_amp, period, c2;
+    double tau_rel;
+    int surrogate;    /* 0: GP, 1: MLP ensemble */
+    int audit_every;  /* every k-th surrogate answer is re-run with MD (0: off) */
+    int64_t md_sample;/* sampling steps of each fallback MD run */
+    int refit_every;  /* ensemble: retrain after this many new MD points */
+} hmd_hybrid_cfg;
+typedef struct {
+    int64_t steps, md_calls, audited, audit_pass, queries;
+    double wall_s, md_wall_s, md_atom_steps;
+} hmd_hybrid_stats;
+
+void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c);
+int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out);
+int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out);
+/* rho, q, q_std (n_sections doubles), from_md (n_sections bytes). */
+int hybrid_get(hmd_hybrid* hy, double* rho, double* q, double* q_std, uint8_t* from_md);
+void hybrid_free(hmd_hybrid* hy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMD_H */

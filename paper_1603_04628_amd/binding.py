@@ -1,0 +1,295 @@
+"""ctypes binding of libhmd (include/hmd.h): argument marshalling only.
+
+Every computation runs in the HIP library.  If ``libhmd.so`` has not been
+built, importing this module raises -- there is no CPU fallback.
+"""
+import ctypes
+import os
+from dataclasses import dataclass, fields
+from typing import List, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libhmd.so")
+
+HMD_OK, HMD_EINVAL, HMD_EDEVICE, HMD_ENOMEM, HMD_EUNSTABLE, HMD_ENOTCONV, HMD_ENOTSPD, HMD_ENOSYS = \
+    0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "HMD_OK", -1: "HMD_EINVAL", -2: "HMD_EDEVICE", -3: "HMD_ENOMEM", -4: "HMD_EUNSTABLE",
+                -5: "HMD_ENOTCONV", -6: "HMD_ENOTSPD", -7: "HMD_ENOSYS"}
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"{LIBPATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+
+_c = ctypes
+_lib = _c.CDLL(LIBPATH)
+P = _c.POINTER
+d, i32, i64, u64, u32, u8, vp = _c.c_double, _c.c_int, _c.c_int64, _c.c_uint64, _c.c_uint32, _c.c_uint8, _c.c_void_p
+
+
+class MdParams(_c.Structure):
+    _fields_ = [("rho", d), ("T0", d), ("rc", d), ("eps_wf", d), ("sigma_wf", d), ("rho_wall", d),
+                ("wall_layers", i32), ("thermo_axis", i32), ("dt", d), ("tau_T", d), ("Lx_nom", d),
+                ("Lz_nom", d), ("bin_dy", d), ("n_equil", i64), ("n_blocks", i32), ("n_fluid", i64),
+                ("delta", d)]
+
+
+class MdJob(_c.Structure):
+    _fields_ = [("h", d), ("g", d), ("seed", u64), ("n_sample", i64)]
+
+
+class MdResult(_c.Structure):
+    _fields_ = [("flux", d), ("flux_se", d), ("jflux", d), ("T", d * 3), ("pe", d), ("n_fluid", i64),
+                ("status", i32)]
+
+
+def _sig(name, res, *args):
+    fn = getattr(_lib, name)
+    fn.restype = res
+    fn.argtypes = list(args)
+    return fn
+
+
+_sig("hmd_md_params_default", None, P(MdParams))
+_sig("hmd_create", i32, P(MdParams), i32, vp, P(vp))
+_sig("hmd_destroy", None, vp)
+_sig("hmd_last_error", _c.c_char_p, vp)
+_sig("hmd_set_params", i32, vp, P(MdParams))
+_sig("md_flux", i32, vp, d, d, u64, i64, P(d), P(d))
+_sig("md_flux_batch", i32, vp, P(MdJob), i32, P(MdResult))
+_sig("md_batch_create", i32, vp, P(MdJob), i32, P(vp))
+_sig("md_batch_run", i32, vp, i64, i32)
+_sig("md_batch_results", i32, vp, P(MdResult))
+_sig("md_batch_atoms", i64, vp)
+_sig("md_batch_set_timing", i32, vp, i32)
+_sig("md_batch_kernel_ms", i32, vp, _c.c_char_p, P(d), P(i64))
+_sig("md_batch_pair_count", i32, vp, P(i64), P(i64))
+_sig("md_batch_free", None, vp)
+_sig("md_sys_create", i32, vp, d, d, u64, P(vp))
+_sig("md_sys_info", i32, vp, P(i64), P(i64), P(d), P(i32))
+_sig("md_set_state", i32, vp, P(d), P(d))
+_sig("md_get_state", i32, vp, P(d), P(d), P(i64))
+_sig("md_compute_forces", i32, vp, P(_c.c_float), P(d))
+_sig("md_cell_lists", i32, vp, P(u32), P(u32), P(u32))
+_sig("md_run", i32, vp, i64, i32, P(d))
+_sig("md_sys_profile", i32, vp, P(d), P(d))
+_sig("md_sys_free", None, vp)
+
+
+def lib():
+    return _lib
+
+
+def _ptr(a, ct=d):
+    return a.ctypes.data_as(P(ct))
+
+
+class HmdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+@dataclass
+class Params:
+    """hmd_md_params with the library's defaults."""
+    rho: float = 0.8
+    T0: float = 1.0
+    rc: float = 2.5
+    eps_wf: float = 1.0
+    sigma_wf: float = 1.0
+    rho_wall: float = 1.0
+    wall_layers: int = 4
+    thermo_axis: int = 1
+    dt: float = 0.005
+    tau_T: float = 0.1
+    Lx_nom: float = 12.0
+    Lz_nom: float = 12.0
+    bin_dy: float = 0.25
+    n_equil: int = 0
+    n_blocks: int = 20
+    n_fluid: int = 0
+    delta: float = 1.0
+
+    def to_c(self):
+        return MdParams(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+
+class Context:
+    """hmd_ctx on one HIP device (own stream unless `stream` is given)."""
+
+    def __init__(self, params: Params = None, device: int = 0, stream: int = None):
+        self.params = params or Params()
+        self._h = vp()
+        cp = self.params.to_c()
+        rc = _lib.hmd_create(_c.byref(cp), device, vp(stream) if stream else None, _c.byref(self._h))
+        if rc != HMD_OK:
+            raise HmdError(rc, "hmd_create failed (no HIP device?)")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_params(self, params: Params):
+        self.params = params
+        cp = params.to_c()
+        self.check(_lib.hmd_set_params(self._h, _c.byref(cp)))
+
+    def error(self) -> str:
+        return (_lib.hmd_last_error(self._h) or b"").decode()
+
+    def check(self, rc):
+        if rc != HMD_OK:
+            raise HmdError(rc, self.error())
+        return rc
+
+    def close(self):
+        if self._h:
+            _lib.hmd_destroy(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _jobs(jobs) -> ctypes.Array:
+    arr = (MdJob * len(jobs))()
+    for k, j in enumerate(jobs):
+        arr[k] = MdJob(float(j[0]), float(j[1]), int(j[2]), int(j[3]))
+    return arr
+
+
+def _result_dict(r: MdResult):
+    return {"flux": r.flux, "flux_se": r.flux_se, "jflux": r.jflux, "T": np.array(list(r.T)), "pe": r.pe,
+            "n_fluid": r.n_fluid, "status": r.status}
+
+
+def md_flux(ctx: Context, h, g, seed, steps):
+    """The micro-solve: returns (status, flux, se)."""
+    f, se = d(), d()
+    rc = _lib.md_flux(ctx.handle, float(h), float(g), int(seed), int(steps), _c.byref(f), _c.byref(se))
+    if rc not in (HMD_OK, HMD_EUNSTABLE, HMD_ENOTCONV):
+        raise HmdError(rc, ctx.error())
+    return rc, f.value, se.value
+
+
+def md_flux_batch(ctx: Context, jobs: Sequence) -> List[dict]:
+    """jobs: sequence of (h, g, seed, n_sample)."""
+    arr = _jobs(jobs)
+    out = (MdResult * len(jobs))()
+    ctx.check(_lib.md_flux_batch(ctx.handle, arr, len(jobs), out))
+    return [_result_dict(r) for r in out]
+
+
+class Batch:
+    """Staged batch (md_batch_*): create, run, results, per-kernel timing."""
+
+    def __init__(self, ctx: Context, jobs: Sequence):
+        self.ctx = ctx
+        self.n = len(jobs)
+        self._h = vp()
+        ctx.check(_lib.md_batch_create(ctx.handle, _jobs(jobs), self.n, _c.byref(self._h)))
+
+    @property
+    def atoms(self) -> int:
+        return _lib.md_batch_atoms(self._h)
+
+    def run(self, steps: int, graph_chunk: int = 100):
+        self.ctx.check(_lib.md_batch_run(self._h, int(steps), int(graph_chunk)))
+
+    def results(self) -> List[dict]:
+        out = (MdResult * self.n)()
+        self.ctx.check(_lib.md_batch_results(self._h, out))
+        return [_result_dict(r) for r in out]
+
+    def set_timing(self, on: bool):
+        self.ctx.check(_lib.md_batch_set_timing(self._h, 1 if on else 0))
+
+    def kernel_ms(self, name: str):
+        ms, n = d(), i64()
+        self.ctx.check(_lib.md_batch_kernel_ms(self._h, name.encode(), _c.byref(ms), _c.byref(n)))
+        return ms.value, n.value
+
+    def pair_count(self):
+        ff, wf = i64(), i64()
+        self.ctx.check(_lib.md_batch_pair_count(self._h, _c.byref(ff), _c.byref(wf)))
+        return ff.value, wf.value
+
+    def close(self):
+        if self._h:
+            _lib.md_batch_free(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class System:
+    """md_sys_*: one channel system with state access (atom id order)."""
+
+    def __init__(self, ctx: Context, h, g, seed):
+        self.ctx = ctx
+        self._h = vp()
+        ctx.check(_lib.md_sys_create(ctx.handle, float(h), float(g), int(seed), _c.byref(self._h)))
+        nf, nw = i64(), i64()
+        box = np.zeros(3)
+        nc = np.zeros(3, dtype=np.int32)
+        ctx.check(_lib.md_sys_info(self._h, _c.byref(nf), _c.byref(nw), _ptr(box), _ptr(nc, i32)))
+        self.n_fluid, self.n_wall = nf.value, nw.value
+        self.Lx, self.h, self.Lz = box
+        self.ncell = tuple(int(c) for c in nc)
+
+    def get_state(self):
+        x = np.zeros((self.n_fluid, 3))
+        v = np.zeros((self.n_fluid, 3))
+        self.ctx.check(_lib.md_get_state(self._h, _ptr(x), _ptr(v), None))
+        return x, v
+
+    def set_state(self, x, v):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert x.shape == (self.n_fluid, 3) and v.shape == (self.n_fluid, 3)
+        self.ctx.check(_lib.md_set_state(self._h, _ptr(x), _ptr(v)))
+
+    def forces(self):
+        f = np.zeros((self.n_fluid, 3), dtype=np.float32)
+        pe = d()
+        self.ctx.check(_lib.md_compute_forces(self._h, _ptr(f, _c.c_float), _c.byref(pe)))
+        return f, pe.value
+
+    def cells(self):
+        nx, ny, nz = self.ncell
+        cell_of = np.zeros(self.n_fluid, dtype=np.uint32)
+        counts = np.zeros(nx * ny * nz, dtype=np.uint32)
+        order = np.zeros(self.n_fluid, dtype=np.uint32)
+        self.ctx.check(_lib.md_cell_lists(self._h, _ptr(cell_of, u32), _ptr(counts, u32), _ptr(order, u32)))
+        return cell_of, counts, order
+
+    def run(self, steps: int, thermostat: bool = True, energy: bool = False):
+        trace = np.zeros(int(steps)) if energy else None
+        self.ctx.check(_lib.md_run(self._h, int(steps), 1 if thermostat else 0,
+                                   _ptr(trace) if energy else None))
+        return trace
+
+    def profile(self):
+        nb = int(np.ceil(self.h / self.ctx.params.bin_dy))
+        mvx, cnt = np.zeros(nb), np.zeros(nb)
+        self.ctx.check(_lib.md_sys_profile(self._h, _ptr(mvx), _ptr(cnt)))
+        return mvx, cnt
+
+    def close(self):
+        if self._h:
+            _lib.md_sys_free(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

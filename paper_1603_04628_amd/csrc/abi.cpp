@@ -1,0 +1,253 @@
+// abi.cpp -- extern "C" entry points of libhmd for the MD micro-solve (the
+// declarations and their contracts are in include/hmd.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "engine.h"
+
+namespace {
+
+// Default graph chunk for whole-run calls: long enough to amortise launch
+// gaps, short enough that a remainder runs quickly as direct launches.
+constexpr int kDefaultChunk = 100;
+
+template <typename F>
+int guarded(hmd_ctx* ctx, F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return HMD_ENOMEM;
+  } catch (...) {
+    if (ctx) ctx->err = "internal error";
+    return HMD_EDEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void hmd_md_params_default(hmd_md_params* p) {
+  if (!p) return;
+  p->rho = 0.8; p->T0 = 1.0; p->rc = 2.5;
+  p->eps_wf = 1.0; p->sigma_wf = 1.0; p->rho_wall = 1.0;
+  p->wall_layers = 4; p->thermo_axis = 1;
+  p->dt = 0.005; p->tau_T = 0.1;
+  p->Lx_nom = 12.0; p->Lz_nom = 12.0; p->bin_dy = 0.25;
+  p->n_equil = 0; p->n_blocks = 20; p->n_fluid = 0; p->delta = 1.0;
+}
+
+int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ctx** out) {
+  if (!out) return HMD_EINVAL;
+  *out = nullptr;
+  auto* ctx = new (std::nothrow) hmd_ctx();
+  if (!ctx) return HMD_ENOMEM;
+  if (params) ctx->params = *params;
+  else hmd_md_params_default(&ctx->params);
+  ctx->device = device;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    delete ctx;
+    return HMD_EDEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return HMD_EDEVICE;
+  }
+  if (hip_stream) {
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return HMD_EDEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  *out = ctx;
+  return HMD_OK;
+}
+
+void hmd_destroy(hmd_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->own_stream && ctx->stream) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamDestroy(ctx->stream);
+  }
+  delete ctx;
+}
+
+const char* hmd_last_error(const hmd_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int hmd_set_params(hmd_ctx* ctx, const hmd_md_params* params) {
+  if (!ctx || !params) return HMD_EINVAL;
+  ctx->params = *params;
+  return HMD_OK;
+}
+
+// ----------------------------------------------------------------- batches
+int md_batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
+  if (!ctx || !jobs || !out) return HMD_EINVAL;
+  return guarded(ctx, [&] { return hmd::batch_create(ctx, jobs, n, out); });
+}
+
+int md_batch_run(hmd_batch* b, int64_t steps, int graph_chunk) {
+  if (!b) return HMD_EINVAL;
+  return guarded(b->ctx, [&] { return hmd::batch_run(b, steps, graph_chunk, true, nullptr); });
+}
+
+int md_batch_results(hmd_batch* b, hmd_md_result* out) {
+  if (!b || !out) return HMD_EINVAL;
+  return guarded(b->ctx, [&] { return hmd::batch_results(b, out); });
+}
+
+int64_t md_batch_atoms(const hmd_batch* b) { return b ? b->ntot : 0; }
+
+int md_batch_set_timing(hmd_batch* b, int on) {
+  if (!b) return HMD_EINVAL;
+  b->timing = on != 0;
+  for (int k = 0; k < hmd::K_COUNT; ++k) {
+    b->kern_ms[k] = 0.0;
+    b->kern_n[k] = 0;
+  }
+  b->graph_ms = 0.0;
+  b->graph_steps = 0;
+  return HMD_OK;
+}
+
+int md_batch_kernel_ms(const hmd_batch* b, const char* kernel, double* ms, int64_t* launches) {
+  if (!b || !kernel || !ms) return HMD_EINVAL;
+  static const char* names[hmd::K_COUNT] = {"integrate", "scan", "scatter", "reorder", "force"};
+  if (std::strcmp(kernel, "graph_step") == 0) {
+    *ms = b->graph_steps ? b->graph_ms / double(b->graph_steps) : 0.0;
+    if (launches) *launches = b->graph_steps;
+    return HMD_OK;
+  }
+  for (int k = 0; k < hmd::K_COUNT; ++k)
+    if (std::strcmp(kernel, names[k]) == 0) {
+      *ms = b->kern_n[k] ? b->kern_ms[k] / double(b->kern_n[k]) : 0.0;
+      if (launches) *launches = b->kern_n[k];
+      return HMD_OK;
+    }
+  return HMD_EINVAL;
+}
+
+int md_batch_pair_count(hmd_batch* b, int64_t* fluid_pairs, int64_t* wall_pairs) {
+  if (!b) return HMD_EINVAL;
+  return guarded(b->ctx, [&] { return hmd::batch_pairs(b, fluid_pairs, wall_pairs); });
+}
+
+void md_batch_free(hmd_batch* b) { hmd::batch_free(b); }
+
+int md_flux_batch(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_md_result* out) {
+  if (!ctx || !jobs || !out || n < 1) {
+    if (ctx) ctx->err = "md_flux_batch: null argument or n < 1";
+    return HMD_EINVAL;
+  }
+  return guarded(ctx, [&]() -> int {
+    // one batch per distinct sampling length
+    std::map<int64_t, std::vector<int>> groups;
+    for (int k = 0; k < n; ++k) {
+      if (jobs[k].n_sample < ctx->params.n_blocks) {
+        ctx->err = "md_flux_batch: n_sample must be >= n_blocks";
+        return HMD_EINVAL;
+      }
+      groups[jobs[k].n_sample].push_back(k);
+    }
+    for (auto& kv : groups) {
+      std::vector<hmd_md_job> sub;
+      for (int k : kv.second) sub.push_back(jobs[k]);
+      hmd_batch* b = nullptr;
+      int rc = hmd::batch_create(ctx, sub.data(), int(sub.size()), &b);
+      if (rc != HMD_OK) return rc;
+      rc = hmd::batch_run(b, ctx->params.n_equil + kv.first, kDefaultChunk, true, nullptr);
+      std::vector<hmd_md_result> res(sub.size());
+      if (rc == HMD_OK) rc = hmd::batch_results(b, res.data());
+      hmd::batch_free(b);
+      if (rc != HMD_OK) return rc;
+      for (size_t j = 0; j < sub.size(); ++j) out[kv.second[j]] = res[j];
+    }
+    return HMD_OK;
+  });
+}
+
+int md_flux(hmd_ctx* ctx, double h, double g, uint64_t seed, int64_t steps, double* flux, double* se) {
+  if (!ctx) return HMD_EINVAL;
+  hmd_md_job job{h, g, seed, steps};
+  hmd_md_result r{};
+  const int rc = md_flux_batch(ctx, &job, 1, &r);
+  if (rc != HMD_OK) return rc;
+  if (flux) *flux = r.flux;
+  if (se) *se = r.flux_se;
+  return r.status;
+}
+
+// ----------------------------------------------------------- single system
+int md_sys_create(hmd_ctx* ctx, double h, double g, uint64_t seed, hmd_sys** out) {
+  if (!ctx || !out) return HMD_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    hmd_md_job job{h, g, seed, 0};
+    hmd_batch* b = nullptr;
+    const int rc = hmd::batch_create(ctx, &job, 1, &b);
+    if (rc != HMD_OK) return rc;
+    auto* s = new hmd_sys();
+    s->b = b;
+    *out = s;
+    return HMD_OK;
+  });
+}
+
+int md_sys_info(hmd_sys* s, int64_t* n_fluid, int64_t* n_wall, double box[3], int ncell[3]) {
+  if (!s) return HMD_EINVAL;
+  const hmd::HostSystem& H = s->b->host[0];
+  if (n_fluid) *n_fluid = H.nf;
+  if (n_wall) *n_wall = H.nw;
+  if (box) { box[0] = H.Lx; box[1] = H.h; box[2] = H.Lz; }
+  if (ncell) { ncell[0] = H.nx; ncell[1] = H.ny; ncell[2] = H.nz; }
+  return HMD_OK;
+}
+
+int md_set_state(hmd_sys* s, const double* x, const double* v) {
+  if (!s || !x || !v) return HMD_EINVAL;
+  return guarded(s->b->ctx, [&] { return hmd::batch_set_state(s->b, 0, x, v); });
+}
+
+int md_get_state(hmd_sys* s, double* x, double* v, int64_t* n_fluid) {
+  if (!s) return HMD_EINVAL;
+  if (n_fluid) *n_fluid = s->b->host[0].nf;
+  return guarded(s->b->ctx, [&] { return hmd::batch_get_state(s->b, 0, x, v); });
+}
+
+int md_compute_forces(hmd_sys* s, float* f, double* pe) {
+  if (!s) return HMD_EINVAL;
+  return guarded(s->b->ctx, [&] { return hmd::batch_forces(s->b, 0, f, pe); });
+}
+
+int md_cell_lists(hmd_sys* s, uint32_t* cell_of_atom, uint32_t* cell_count, uint32_t* order) {
+  if (!s) return HMD_EINVAL;
+  return guarded(s->b->ctx, [&] { return hmd::batch_cells(s->b, 0, cell_of_atom, cell_count, order); });
+}
+
+int md_run(hmd_sys* s, int64_t steps, int thermostat_on, double* energy_trace) {
+  if (!s) return HMD_EINVAL;
+  return guarded(s->b->ctx, [&] {
+    return hmd::batch_run(s->b, steps, energy_trace ? 0 : kDefaultChunk, thermostat_on != 0, energy_trace);
+  });
+}
+
+int md_sys_profile(hmd_sys* s, double* mvx, double* cnt) {
+  if (!s) return HMD_EINVAL;
+  return guarded(s->b->ctx, [&] { return hmd::batch_profile(s->b, 0, mvx, cnt); });
+}
+
+void md_sys_free(hmd_sys* s) {
+  if (!s) return;
+  hmd::batch_free(s->b);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,702 @@
+// md_engine.hip -- host runtime of the batched NEMD micro-solve: builds the
+// flattened device layout of many channel systems, runs the step loop as
+// direct launches or replays of a captured HIP graph, and reduces results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "engine.h"
+#include "md_kernels.h"
+
+namespace hmd {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline int blocks_for(int64_t n) { return int((n + TPB - 1) / TPB); }
+
+StateRef state_ref(hmd_batch* b, int which) {
+  double** s = b->d_state[which];
+  return StateRef{s[0], s[1], s[2], s[3], s[4], s[5]};
+}
+
+StepConst step_const(const hmd_batch* b, bool thermostat, bool energy) {
+  const hmd_md_params& P = b->P;
+  StepConst K{};
+  K.dt = P.dt;
+  K.hdt = 0.5 * P.dt;
+  K.dt_tau = P.dt / P.tau_T;
+  K.T0 = P.T0;
+  K.rc2 = float(P.rc * P.rc);
+  K.eps_wf = float(P.eps_wf);
+  K.sig2_wf = float(P.sigma_wf * P.sigma_wf);
+  const double ir6 = 1.0 / std::pow(P.rc, 6.0);
+  K.ush_ff = float(4.0 * (ir6 * ir6 - ir6));
+  const double sw6 = std::pow(P.sigma_wf / P.rc, 6.0);
+  K.ush_wf = float(4.0 * P.eps_wf * (sw6 * sw6 - sw6));
+  K.axis = P.thermo_axis;
+  K.nb = P.n_blocks;
+  if (b->n_sample > 0) {
+    K.B = int(b->n_sample / P.n_blocks);
+    K.r = int(b->n_sample - int64_t(K.B) * P.n_blocks);
+  } else {  // open-ended runs: every sample lands in block 0
+    K.B = 1 << 30;
+    K.r = 0;
+  }
+  K.thermo_on = thermostat ? 1 : 0;
+  K.bins_on = 1;
+  K.energy_on = energy ? 1 : 0;
+  return K;
+}
+
+template <typename T>
+int dalloc(hmd_ctx* ctx, T** p, int64_t n) {
+  HMD_HIP(ctx, hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * size_t(std::max<int64_t>(n, 1))));
+  return HMD_OK;
+}
+
+#define HMD_TRY(expr)            \
+  do {                           \
+    int rc_ = (expr);            \
+    if (rc_ != HMD_OK) return rc_; \
+  } while (0)
+
+// Launches of one kind, optionally bracketed by timing events.
+struct Launcher {
+  hmd_batch* b;
+  hipStream_t s;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* marks;  // null: untimed
+  int next_ev = 0;
+
+  void begin(int k) {
+    if (!marks) return;
+    hipEvent_t e0 = b->ev[next_ev++], e1 = b->ev[next_ev++];
+    (void)hipEventRecord(e0, s);
+    marks->push_back({k, {e0, e1}});
+  }
+  void end() {
+    if (!marks) return;
+    (void)hipEventRecord(marks->back().second.second, s);
+  }
+};
+
+// One velocity-Verlet step over the whole batch (five launches).
+void enqueue_step(hmd_batch* b, Launcher& L, const StepConst& K) {
+  hipStream_t s = L.s;
+  const int nt = int(b->ntot);
+  const int src = b->cur, dst = 1 - b->cur;
+  L.begin(K_INTEGRATE);
+  hipLaunchKernelGGL(k_integrate<1>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
+                     state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->acc, b->d_dstate, K);
+  L.end();
+  L.begin(K_SCAN);
+  hipLaunchKernelGGL(k_scan, dim3(b->S), dim3(1024), 0, s, b->d_sims, b->d_count, b->d_cursor, b->d_start,
+                     b->d_ncount, b->d_dstate, 1);
+  L.end();
+  L.begin(K_SCATTER);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_key, b->d_start, b->d_cursor,
+                     b->d_perm);
+  L.end();
+  L.begin(K_REORDER);
+  hipLaunchKernelGGL(k_reorder, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_cell_sim, b->d_key,
+                     b->d_start, b->d_ncount, b->d_perm, state_ref(b, src), state_ref(b, dst), b->d_tag[src],
+                     b->d_tag[dst], b->d_pos4);
+  L.end();
+  b->cur = dst;  // the force kernel kicks the reordered state
+  L.begin(K_FORCE);
+  launch_force(b, s, 1, K);
+  L.end();
+}
+
+// Sort the current positions into cells (no time step).
+void enqueue_sort(hmd_batch* b, hipStream_t s, const StepConst& K) {
+  const int nt = int(b->ntot);
+  const int src = b->cur, dst = 1 - b->cur;
+  hipLaunchKernelGGL(k_integrate<0>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
+                     state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->acc, b->d_dstate, K);
+  hipLaunchKernelGGL(k_scan, dim3(b->S), dim3(1024), 0, s, b->d_sims, b->d_count, b->d_cursor, b->d_start,
+                     b->d_ncount, b->d_dstate, 0);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_key, b->d_start, b->d_cursor,
+                     b->d_perm);
+  hipLaunchKernelGGL(k_reorder, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_cell_sim, b->d_key,
+                     b->d_start, b->d_ncount, b->d_perm, state_ref(b, src), state_ref(b, dst), b->d_tag[src],
+                     b->d_tag[dst], b->d_pos4);
+  b->cur = dst;
+}
+
+// Forces for the current sorted positions; potential energy sums go to
+// acc.pe[done & 1] (cleared first).
+int forces_now(hmd_batch* b, bool energy) {
+  hmd_ctx* ctx = b->ctx;
+  hipStream_t s = ctx->stream;
+  StepConst K = step_const(b, b->thermo_on, energy);
+  const int p = int(b->done & 1);
+  HMD_HIP(ctx, hipMemsetAsync(b->acc.pe[p], 0, sizeof(double) * b->S, s));
+  HMD_HIP(ctx, hipMemsetAsync(b->acc.ke[p], 0, sizeof(double) * b->S, s));
+  HMD_HIP(ctx, hipMemsetAsync(b->acc.pairs, 0, 2 * sizeof(unsigned long long), s));
+  launch_force(b, s, 0, K);
+  HMD_HIP(ctx, hipGetLastError());
+  return HMD_OK;
+}
+
+void release_graphs(hmd_batch* b) {
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : b->graph_defs) (void)hipGraphDestroy(kv.second);
+  b->graphs.clear();
+  b->graph_defs.clear();
+}
+
+int graph_key(int chunk, bool thermostat) { return chunk * 2 + (thermostat ? 1 : 0); }
+
+}  // namespace
+
+void launch_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K) {
+  const int nt = int(b->ntot);
+  const int src = b->cur;
+  if (mode == 0)
+    hipLaunchKernelGGL(k_force<0>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim, b->d_pos4,
+                       b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
+                       b->acc, b->d_dstate, K);
+  else
+    hipLaunchKernelGGL(k_force<1>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim, b->d_pos4,
+                       b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
+                       b->acc, b->d_dstate, K);
+}
+
+int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
+  if (!ctx || !out || (n > 0 && !jobs) || n < 1 || n > 65535) {
+    if (ctx) ctx->err = "md batch: need 1..65535 jobs";
+    return HMD_EINVAL;
+  }
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  auto* b = new hmd_batch();
+  b->ctx = ctx;
+  b->P = ctx->params;
+  b->S = n;
+  b->n_sample = jobs[0].n_sample;
+  for (int k = 0; k < n; ++k)
+    if (jobs[k].n_sample != b->n_sample || jobs[k].n_sample < 0 ||
+        (jobs[k].n_sample > 0 && jobs[k].n_sample < b->P.n_blocks)) {
+      ctx->err = "md batch: every job needs the same n_sample (0 or >= n_blocks)";
+      delete b;
+      return HMD_EINVAL;
+    }
+  b->host.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int rc = build_system(b->P, jobs[k].h, jobs[k].g, jobs[k].seed, b->host[k], ctx->err);
+    if (rc != HMD_OK) {
+      delete b;
+      return rc;
+    }
+  }
+  // flattened layout
+  b->sims.resize(n);
+  int64_t a0 = 0, c0 = 0, wc0 = 0, bin0 = 0, w0 = 0;
+  for (int k = 0; k < n; ++k) {
+    const HostSystem& H = b->host[k];
+    SimDev& D = b->sims[k];
+    std::memset(&D, 0, sizeof(D));
+    D.Lx = H.Lx; D.Lz = H.Lz; D.h = H.h;
+    D.inv_x = H.inv_x; D.inv_y = H.inv_y; D.inv_z = H.inv_z;
+    D.wx = H.wx; D.wy = H.wy; D.wz = H.wz;
+    D.g = H.g;
+    D.inv_area = 1.0 / (H.Lx * H.Lz);
+    D.inv_bin = 1.0 / b->P.bin_dy;
+    D.inv_nf = 1.0 / double(H.nf);
+    D.fwx = float(H.wx); D.fwy = float(H.wy); D.fwz = float(H.wz);
+    D.nx = H.nx; D.ny = H.ny; D.nz = H.nz;
+    D.a0 = int(a0); D.nf = int(H.nf);
+    D.c0 = int(c0); D.ncell = H.nx * H.ny * H.nz;
+    D.wc0 = int(wc0);
+    D.nbins = H.nbins; D.bin0 = int(bin0);
+    a0 += H.nf;
+    c0 += D.ncell;
+    wc0 += 2 * int64_t(H.nx) * H.nz;
+    bin0 += H.nbins;
+    w0 += H.nw;
+  }
+  if (a0 >= (int64_t(1) << 31) || c0 >= (int64_t(1) << 31)) {
+    ctx->err = "md batch: too many atoms or cells for one batch";
+    delete b;
+    return HMD_EINVAL;
+  }
+  b->ntot = a0; b->ncell = c0; b->nwcell = wc0; b->nbins = bin0; b->nwall = w0;
+
+  int rc = HMD_OK;
+  auto fail = [&](int code) {
+    batch_free(b);
+    return code;
+  };
+  if ((rc = dalloc(ctx, &b->d_sims, n)) || (rc = dalloc(ctx, &b->d_atom_sim, b->ntot)) ||
+      (rc = dalloc(ctx, &b->d_cell_sim, b->ncell)) || (rc = dalloc(ctx, &b->d_f4, b->ntot)) ||
+      (rc = dalloc(ctx, &b->d_pos4, b->ntot)) || (rc = dalloc(ctx, &b->d_key, b->ntot)) ||
+      (rc = dalloc(ctx, &b->d_count, b->ncell)) || (rc = dalloc(ctx, &b->d_cursor, b->ncell)) ||
+      (rc = dalloc(ctx, &b->d_start, b->ncell)) || (rc = dalloc(ctx, &b->d_ncount, b->ncell)) ||
+      (rc = dalloc(ctx, &b->d_perm, b->ntot)) || (rc = dalloc(ctx, &b->d_wpos4, b->nwall)) ||
+      (rc = dalloc(ctx, &b->d_wstart, b->nwcell)) || (rc = dalloc(ctx, &b->d_wcount, b->nwcell)) ||
+      (rc = dalloc(ctx, &b->d_dstate, 4)) || (rc = dalloc(ctx, &b->d_tag[0], b->ntot)) ||
+      (rc = dalloc(ctx, &b->d_tag[1], b->ntot)))
+    return fail(rc);
+  for (int w = 0; w < 2; ++w)
+    for (int a = 0; a < 6; ++a)
+      if ((rc = dalloc(ctx, &b->d_state[w][a], b->ntot))) return fail(rc);
+  const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->P.n_blocks + 3 * int64_t(n) + 2 * b->nbins;
+  if ((rc = dalloc(ctx, &b->d_accbuf, nacc)) || (rc = dalloc(ctx, &b->d_status, n)) ||
+      (rc = dalloc(ctx, &b->acc.pairs, 2)))
+    return fail(rc);
+  double* q = b->d_accbuf;
+  for (int p = 0; p < 2; ++p) { b->acc.vc2[p] = q; q += n; }
+  for (int p = 0; p < 2; ++p) { b->acc.pe[p] = q; q += n; }
+  for (int p = 0; p < 2; ++p) { b->acc.ke[p] = q; q += n; }
+  b->acc.blocks = q; q += int64_t(n) * b->P.n_blocks;
+  b->acc.tsum = q; q += 3 * int64_t(n);
+  b->acc.binvx = q; q += b->nbins;
+  b->acc.bincnt = q;
+  b->acc.status = b->d_status;
+
+  hipStream_t s = ctx->stream;
+  // host staging
+  std::vector<double> hs[6];
+  for (auto& v : hs) v.resize(b->ntot);
+  std::vector<int> tag(b->ntot);
+  std::vector<uint16_t> atom_sim(b->ntot), cell_sim(b->ncell);
+  std::vector<float4> wpos(std::max<int64_t>(b->nwall, 1));
+  std::vector<uint32_t> wstart(b->nwcell), wcount(b->nwcell, 0);
+  int64_t wbase = 0;
+  for (int k = 0; k < n; ++k) {
+    HostSystem& H = b->host[k];
+    const SimDev& D = b->sims[k];
+    for (int64_t i = 0; i < H.nf; ++i) {
+      const int64_t g = D.a0 + i;
+      for (int a = 0; a < 3; ++a) {
+        hs[a][g] = H.x[3 * i + a];
+        hs[3 + a][g] = H.v[3 * i + a];
+      }
+      tag[g] = int(i);
+      atom_sim[g] = uint16_t(k);
+    }
+    for (int c = 0; c < D.ncell; ++c) cell_sim[D.c0 + c] = uint16_t(k);
+    // wall columns: slab 0 below the channel, 1 above; ascending wall id
+    const int ncol = 2 * D.nx * D.nz;
+    std::vector<int> wkey(H.nw);
+    for (int64_t w = 0; w < H.nw; ++w) {
+      const int cx = cell_coord(H.xw[3 * w], H.inv_x, H.nx);
+      const int cz = cell_coord(H.xw[3 * w + 2], H.inv_z, H.nz);
+      const int slab = H.xw[3 * w + 1] <= 0.0 ? 0 : 1;
+      wkey[w] = (slab * H.nz + cz) * H.nx + cx;
+      wcount[D.wc0 + wkey[w]]++;
+    }
+    uint32_t acc0 = uint32_t(wbase);
+    for (int c = 0; c < ncol; ++c) {
+      wstart[D.wc0 + c] = acc0;
+      acc0 += wcount[D.wc0 + c];
+    }
+    std::vector<uint32_t> fill(ncol, 0);
+    for (int64_t w = 0; w < H.nw; ++w) {
+      const int c = wkey[w];
+      const uint32_t slot = wstart[D.wc0 + c] + fill[c]++;
+      const int cx = c % H.nx, cz = (c / H.nx) % H.nz, slab = c / (H.nx * H.nz);
+      const double oy = slab == 0 ? -H.wy : double(H.ny) * H.wy;
+      wpos[slot] = make_float4(float(H.xw[3 * w] - double(cx) * H.wx), float(H.xw[3 * w + 1] - oy),
+                               float(H.xw[3 * w + 2] - double(cz) * H.wz), 0.0f);
+    }
+    wbase += H.nw;
+    // the big host arrays are no longer needed
+    H.x.clear(); H.x.shrink_to_fit();
+    H.v.clear(); H.v.shrink_to_fit();
+    H.xw.clear(); H.xw.shrink_to_fit();
+  }
+  const int64_t dstate[4] = {0, b->P.n_equil, 0, 0};
+  auto up = [&](void* d, const void* h, size_t bytes) -> int {
+    HMD_HIP(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+    return HMD_OK;
+  };
+  if ((rc = up(b->d_sims, b->sims.data(), sizeof(SimDev) * n)) ||
+      (rc = up(b->d_atom_sim, atom_sim.data(), 2 * b->ntot)) ||
+      (rc = up(b->d_cell_sim, cell_sim.data(), 2 * b->ncell)) || (rc = up(b->d_tag[0], tag.data(), 4 * b->ntot)) ||
+      (rc = up(b->d_wpos4, wpos.data(), sizeof(float4) * b->nwall)) ||
+      (rc = up(b->d_wstart, wstart.data(), 4 * b->nwcell)) ||
+      (rc = up(b->d_wcount, wcount.data(), 4 * b->nwcell)) || (rc = up(b->d_dstate, dstate, sizeof(dstate))))
+    return fail(rc);
+  for (int a = 0; a < 6; ++a)
+    if ((rc = up(b->d_state[0][a], hs[a].data(), 8 * b->ntot))) return fail(rc);
+  HMD_HIP(ctx, hipMemsetAsync(b->d_accbuf, 0, sizeof(double) * nacc, s));
+  HMD_HIP(ctx, hipMemsetAsync(b->d_status, 0, sizeof(int) * n, s));
+  HMD_HIP(ctx, hipMemsetAsync(b->d_count, 0, 4 * b->ncell, s));
+  HMD_HIP(ctx, hipMemsetAsync(b->d_cursor, 0, 4 * b->ncell, s));
+  b->cur = 0;
+  StepConst K = step_const(b, true, true);
+  enqueue_sort(b, s, K);
+  if ((rc = forces_now(b, true))) return fail(rc);
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  HMD_HIP(ctx, hipGetLastError());
+  *out = b;
+  return HMD_OK;
+}
+
+void batch_free(hmd_batch* b) {
+  if (!b) return;
+  release_graphs(b);
+  for (auto e : b->ev) (void)hipEventDestroy(e);
+  void* ptrs[] = {b->d_sims, b->d_atom_sim, b->d_cell_sim, b->d_f4, b->d_pos4, b->d_key, b->d_count,
+                  b->d_cursor, b->d_start, b->d_ncount, b->d_perm, b->d_wpos4, b->d_wstart, b->d_wcount,
+                  b->d_dstate, b->d_tag[0], b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int w = 0; w < 2; ++w)
+    for (int a = 0; a < 6; ++a)
+      if (b->d_state[w][a]) (void)hipFree(b->d_state[w][a]);
+  delete b;
+}
+
+namespace {
+
+int ensure_events(hmd_batch* b, size_t n) {
+  while (b->ev.size() < n) {
+    hipEvent_t e;
+    HMD_HIP(b->ctx, hipEventCreate(&e));
+    b->ev.push_back(e);
+  }
+  return HMD_OK;
+}
+
+int harvest(hmd_batch* b, std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>& marks) {
+  if (marks.empty()) return HMD_OK;
+  HMD_HIP(b->ctx, hipEventSynchronize(marks.back().second.second));
+  for (auto& m : marks) {
+    float ms = 0.f;
+    HMD_HIP(b->ctx, hipEventElapsedTime(&ms, m.second.first, m.second.second));
+    b->kern_ms[m.first] += ms;
+    b->kern_n[m.first] += 1;
+  }
+  marks.clear();
+  return HMD_OK;
+}
+
+// Executable graph of `chunk` steps.  With `timed`, every kernel of the
+// chunk is bracketed by captured event-record nodes whose pairs are kept in
+// b->graph_marks[key] (events past the direct-launch pool).
+int get_graph(hmd_batch* b, int chunk, const StepConst& K, bool timed, hipGraphExec_t* out, int* key_out) {
+  const int key = graph_key(chunk, K.thermo_on != 0) + (timed ? (1 << 24) : 0);
+  *key_out = key;
+  auto it = b->graphs.find(key);
+  if (it != b->graphs.end()) {
+    *out = it->second;
+    return HMD_OK;
+  }
+  hmd_ctx* ctx = b->ctx;
+  hipStream_t s = ctx->stream;
+  const int cur0 = b->cur;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  const size_t base = size_t(2 * K_COUNT) * 64;
+  if (timed) HMD_TRY(ensure_events(b, base + size_t(2 * K_COUNT) * chunk));
+  Launcher L{b, s, timed ? &marks : nullptr, int(base)};
+  HMD_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < chunk; ++k) enqueue_step(b, L, K);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  b->cur = cur0;  // capture did not execute anything
+  if (e != hipSuccess) {
+    ctx->err = std::string("graph capture: ") + hipGetErrorString(e);
+    return HMD_EDEVICE;
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    ctx->err = std::string("graph instantiate: ") + hipGetErrorString(e);
+    return HMD_EDEVICE;
+  }
+  b->graph_defs[key] = g;
+  b->graphs[key] = ex;
+  b->graph_marks[key] = marks;
+  *out = ex;
+  return HMD_OK;
+}
+
+}  // namespace
+
+int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, double* energy_trace) {
+  hmd_ctx* ctx = b->ctx;
+  if (steps < 0 || graph_chunk < 0 || (graph_chunk & 1)) {
+    ctx->err = "md run: steps >= 0 and an even graph chunk";
+    return HMD_EINVAL;
+  }
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  b->thermo_on = thermostat;
+  const bool energy = energy_trace != nullptr;
+  const StepConst K = step_const(b, thermostat, energy);
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  const int per_sync = 64;
+  if (b->timing) HMD_TRY(ensure_events(b, size_t(2 * K_COUNT) * per_sync));
+  Launcher L{b, s, b->timing ? &marks : nullptr, 0};
+
+  auto direct_step = [&](int64_t k) -> int {
+    enqueue_step(b, L, K);
+    if (energy) {
+      HMD_HIP(ctx, hipStreamSynchronize(s));
+      const int64_t n = b->done + 1;
+      const int p = int(n & 1);
+      double pe = 0, ke = 0, vc2 = 0;
+      HMD_HIP(ctx, hipMemcpy(&pe, b->acc.pe[p], sizeof(double), hipMemcpyDeviceToHost));
+      HMD_HIP(ctx, hipMemcpy(&ke, b->acc.ke[p], sizeof(double), hipMemcpyDeviceToHost));
+      HMD_HIP(ctx, hipMemcpy(&vc2, b->acc.vc2[p], sizeof(double), hipMemcpyDeviceToHost));
+      const double nf = double(b->sims[0].nf);
+      double lam2 = 1.0;
+      if (thermostat) lam2 = 1.0 + K.dt_tau * (K.T0 / (vc2 / nf) - 1.0);
+      energy_trace[k] = (0.5 * (ke + (lam2 - 1.0) * vc2) + pe) / nf;
+    }
+    b->done += 1;
+    if (b->timing && int(marks.size()) >= per_sync * K_COUNT) {
+      HMD_TRY(harvest(b, marks));
+      L.next_ev = 0;
+    }
+    return HMD_OK;
+  };
+
+  int64_t k = 0;
+  if (graph_chunk > 0 && !energy && steps >= graph_chunk) {
+    if (b->cur != 0) HMD_TRY(direct_step(k++));
+    if (b->timing) {
+      HMD_TRY(harvest(b, marks));
+      L.next_ev = 0;
+    }
+    hipGraphExec_t ex = nullptr;
+    int key = 0;
+    HMD_TRY(get_graph(b, graph_chunk, K, b->timing, &ex, &key));
+    while (steps - k >= graph_chunk) {
+      if (b->timing) {
+        hipEvent_t e0 = b->ev[0], e1 = b->ev[1];
+        HMD_HIP(ctx, hipEventRecord(e0, s));
+        HMD_HIP(ctx, hipGraphLaunch(ex, s));
+        HMD_HIP(ctx, hipEventRecord(e1, s));
+        HMD_HIP(ctx, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HMD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        b->graph_ms += ms;
+        b->graph_steps += graph_chunk;
+        std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> gm = b->graph_marks[key];
+        HMD_TRY(harvest(b, gm));
+      } else {
+        HMD_HIP(ctx, hipGraphLaunch(ex, s));
+      }
+      k += graph_chunk;
+      b->done += graph_chunk;
+    }
+  }
+  while (k < steps) HMD_TRY(direct_step(k++));
+  if (b->timing) HMD_TRY(harvest(b, marks));
+  // finish the last step: sample it with the Berendsen factor applied
+  const int nt = int(b->ntot);
+  hipLaunchKernelGGL(k_integrate<2>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
+                     state_ref(b, b->cur), b->d_f4, b->d_key, b->d_count, b->acc, b->d_dstate, K);
+  if (b->done > b->P.n_equil) {
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate + 2, b->done);
+    b->sampled_upto = b->done;
+  }
+  b->pending = thermostat;
+  HMD_HIP(ctx, hipGetLastError());
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  return HMD_OK;
+}
+
+int batch_results(hmd_batch* b, hmd_md_result* out) {
+  hmd_ctx* ctx = b->ctx;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  HMD_TRY(forces_now(b, true));
+  const int n = b->S, nb = b->P.n_blocks;
+  std::vector<double> blocks(size_t(n) * nb), tsum(3 * size_t(n)), pe(n);
+  std::vector<int> status(n);
+  hipStream_t s = ctx->stream;
+  HMD_HIP(ctx, hipMemcpyAsync(blocks.data(), b->acc.blocks, 8 * blocks.size(), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(tsum.data(), b->acc.tsum, 8 * tsum.size(), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(pe.data(), b->acc.pe[b->done & 1], 8 * size_t(n), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(status.data(), b->d_status, 4 * size_t(n), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  const int64_t used = b->n_sample > 0 ? (b->n_sample / nb) * nb : 0;
+  const int64_t sampled = std::max<int64_t>(0, std::min(b->done - b->P.n_equil, used));
+  for (int k = 0; k < n; ++k) {
+    hmd_md_result& R = out[k];
+    std::memset(&R, 0, sizeof(R));
+    const SimDev& D = b->sims[k];
+    R.n_fluid = D.nf;
+    R.pe = pe[k] * D.inv_nf;
+    int st = (status[k] & 1) ? HMD_EUNSTABLE : HMD_OK;
+    if (b->n_sample > 0 && sampled == used) {
+      const double B = double(b->n_sample / nb);
+      std::vector<double> bm(nb);
+      double mean = 0.0;
+      for (int j = 0; j < nb; ++j) {
+        bm[j] = blocks[size_t(k) * nb + j] / B;
+        mean += bm[j];
+      }
+      mean /= double(nb);
+      double var = 0.0;
+      for (int j = 0; j < nb; ++j) var += (bm[j] - mean) * (bm[j] - mean);
+      var /= double(nb - 1);
+      R.flux = mean;
+      R.flux_se = std::sqrt(var / double(nb));
+      R.jflux = mean / D.h;
+      for (int a = 0; a < 3; ++a) R.T[a] = tsum[3 * k + a] / double(used);
+      const int h1 = nb / 2;
+      double m1 = 0.0, m2 = 0.0;
+      for (int j = 0; j < h1; ++j) m1 += bm[j];
+      for (int j = h1; j < nb; ++j) m2 += bm[j];
+      m1 /= double(h1);
+      m2 /= double(nb - h1);
+      if (st == HMD_OK && (std::fabs(m2 - m1) > 8.0 * R.flux_se || R.T[2] > 1.5 * b->P.T0)) st = HMD_ENOTCONV;
+    } else if (st == HMD_OK) {
+      st = HMD_EINVAL;  // sampling window not complete
+    }
+    R.status = st;
+  }
+  return HMD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single-system hooks (batch of one or more; `sim` selects the system)
+// ---------------------------------------------------------------------------
+namespace {
+
+int download_state(hmd_batch* b, std::vector<double> (&hs)[6], std::vector<int>& tag) {
+  hmd_ctx* ctx = b->ctx;
+  hipStream_t s = ctx->stream;
+  for (int a = 0; a < 6; ++a) {
+    hs[a].resize(b->ntot);
+    HMD_HIP(ctx, hipMemcpyAsync(hs[a].data(), b->d_state[b->cur][a], 8 * b->ntot, hipMemcpyDeviceToHost, s));
+  }
+  tag.resize(b->ntot);
+  HMD_HIP(ctx, hipMemcpyAsync(tag.data(), b->d_tag[b->cur], 4 * b->ntot, hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  return HMD_OK;
+}
+
+}  // namespace
+
+int batch_get_state(hmd_batch* b, int sim, double* x, double* v) {
+  hmd_ctx* ctx = b->ctx;
+  if (sim < 0 || sim >= b->S) return HMD_EINVAL;
+  std::vector<double> hs[6];
+  std::vector<int> tag;
+  HMD_TRY(download_state(b, hs, tag));
+  const SimDev& D = b->sims[sim];
+  double lam = 1.0;
+  if (b->pending) {  // the device holds velocities before the last Berendsen factor
+    double vc2 = 0.0;
+    HMD_HIP(ctx, hipMemcpy(&vc2, b->acc.vc2[b->done & 1] + sim, sizeof(double), hipMemcpyDeviceToHost));
+    lam = std::sqrt(1.0 + (b->P.dt / b->P.tau_T) * (b->P.T0 / (vc2 * D.inv_nf) - 1.0));
+  }
+  for (int i = 0; i < D.nf; ++i) {
+    const int64_t g = D.a0 + i;
+    const int id = tag[g];
+    for (int a = 0; a < 3; ++a) {
+      if (x) x[3 * id + a] = hs[a][g];
+      if (v) v[3 * id + a] = hs[3 + a][g] * (a == b->P.thermo_axis ? lam : 1.0);
+    }
+  }
+  return HMD_OK;
+}
+
+int batch_set_state(hmd_batch* b, int sim, const double* x, const double* v) {
+  hmd_ctx* ctx = b->ctx;
+  if (sim < 0 || sim >= b->S || !x || !v) return HMD_EINVAL;
+  std::vector<double> hs[6];
+  std::vector<int> tag;
+  HMD_TRY(download_state(b, hs, tag));
+  const SimDev& D = b->sims[sim];
+  for (int i = 0; i < D.nf; ++i) {
+    const int64_t g = D.a0 + i;
+    const int id = tag[g];
+    for (int a = 0; a < 3; ++a) {
+      hs[a][g] = x[3 * id + a];
+      hs[3 + a][g] = v[3 * id + a];
+    }
+  }
+  hipStream_t s = ctx->stream;
+  for (int a = 0; a < 6; ++a)
+    HMD_HIP(ctx, hipMemcpyAsync(b->d_state[b->cur][a], hs[a].data(), 8 * b->ntot, hipMemcpyHostToDevice, s));
+  // the new velocities are final: no Berendsen factor is pending
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate + 3, int64_t(0));
+  b->pending = false;
+  StepConst K = step_const(b, b->thermo_on, true);
+  enqueue_sort(b, s, K);
+  HMD_TRY(forces_now(b, true));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  return HMD_OK;
+}
+
+int batch_forces(hmd_batch* b, int sim, float* f, double* pe) {
+  hmd_ctx* ctx = b->ctx;
+  if (sim < 0 || sim >= b->S) return HMD_EINVAL;
+  HMD_TRY(forces_now(b, true));
+  std::vector<float4> f4(b->ntot);
+  std::vector<int> tag(b->ntot);
+  hipStream_t s = ctx->stream;
+  HMD_HIP(ctx, hipMemcpyAsync(f4.data(), b->d_f4, sizeof(float4) * b->ntot, hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(tag.data(), b->d_tag[b->cur], 4 * b->ntot, hipMemcpyDeviceToHost, s));
+  double pes = 0.0;
+  HMD_HIP(ctx, hipMemcpyAsync(&pes, b->acc.pe[b->done & 1] + sim, 8, hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  const SimDev& D = b->sims[sim];
+  for (int i = 0; i < D.nf; ++i) {
+    const int64_t g = D.a0 + i;
+    const int id = tag[g];
+    if (f) {
+      f[3 * id + 0] = f4[g].x;
+      f[3 * id + 1] = f4[g].y;
+      f[3 * id + 2] = f4[g].z;
+    }
+  }
+  if (pe) *pe = pes;
+  return HMD_OK;
+}
+
+int batch_cells(hmd_batch* b, int sim, uint32_t* cell_of, uint32_t* counts, uint32_t* order) {
+  hmd_ctx* ctx = b->ctx;
+  if (sim < 0 || sim >= b->S) return HMD_EINVAL;
+  std::vector<float4> p4(b->ntot);
+  std::vector<int> tag(b->ntot);
+  const SimDev& D = b->sims[sim];
+  std::vector<uint32_t> nc(D.ncell);
+  hipStream_t s = ctx->stream;
+  HMD_HIP(ctx, hipMemcpyAsync(p4.data(), b->d_pos4, sizeof(float4) * b->ntot, hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(tag.data(), b->d_tag[b->cur], 4 * b->ntot, hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(nc.data(), b->d_ncount + D.c0, 4 * size_t(D.ncell), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  for (int i = 0; i < D.nf; ++i) {
+    const int64_t g = D.a0 + i;
+    int lc;
+    std::memcpy(&lc, &p4[g].w, 4);
+    if (cell_of) cell_of[tag[g]] = uint32_t(lc);
+    if (order) order[i] = uint32_t(tag[g]);
+  }
+  if (counts) std::memcpy(counts, nc.data(), 4 * size_t(D.ncell));
+  return HMD_OK;
+}
+
+int batch_pairs(hmd_batch* b, int64_t* ff, int64_t* wf) {
+  hmd_ctx* ctx = b->ctx;
+  HMD_TRY(forces_now(b, true));
+  unsigned long long h[2] = {0, 0};
+  HMD_HIP(ctx, hipMemcpyAsync(h, b->acc.pairs, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ff) *ff = int64_t(h[0]);
+  if (wf) *wf = int64_t(h[1]);
+  return HMD_OK;
+}
+
+int batch_profile(hmd_batch* b, int sim, double* mvx, double* cnt) {
+  hmd_ctx* ctx = b->ctx;
+  if (sim < 0 || sim >= b->S) return HMD_EINVAL;
+  const SimDev& D = b->sims[sim];
+  if (mvx) HMD_HIP(ctx, hipMemcpy(mvx, b->acc.binvx + D.bin0, 8 * size_t(D.nbins), hipMemcpyDeviceToHost));
+  if (cnt) HMD_HIP(ctx, hipMemcpy(cnt, b->acc.bincnt + D.bin0, 8 * size_t(D.nbins), hipMemcpyDeviceToHost));
+  return HMD_OK;
+}
+
+}  // namespace hmd

@@ -1,0 +1,41 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function that include/hmd.h declares (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmd.h")
+LIB = os.path.join(ROOT, "paper_1603_04628_amd", "libhmd.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([a-z][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("md_flux", "md_flux_batch", "gp_fit", "gp_predict", "hybrid_step", "ens_fit"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhmd.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"declared in hmd.h but not exported: {missing}"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhmd.so not built")
+def test_calls_without_a_device_fail_cleanly():
+    import paper_1603_04628_amd as hmd
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(hmd.HmdError):
+        hmd.Context()

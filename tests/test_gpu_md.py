@@ -1,0 +1,188 @@
+"""Parity of the HIP NEMD path with the FP64 oracle, through the C ABI.
+
+Bars: bit-exact initial state and cell membership from identical FP64
+positions; per-atom FP32 forces within 1e-5 relative RMS of the FP64 oracle;
+mass flux within the combined standard error of independent runs.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+hmd = pytest.importorskip("paper_1603_04628_amd")
+from oracle import md as omd  # noqa: E402
+import workloads  # noqa: E402
+
+SMALL_L = dict(Lx_nom=workloads.BOX_SMALL_LITERAL, Lz_nom=workloads.BOX_SMALL_LITERAL)
+SMALL = dict(Lx_nom=workloads.BOX_SMALL, Lz_nom=workloads.BOX_SMALL, n_fluid=2048)
+LARGE = dict(Lx_nom=workloads.BOX_LARGE, Lz_nom=workloads.BOX_LARGE)
+
+
+def _pair(h, g, seed, **params):
+    ctx = hmd.Context(hmd.Params(**params))
+    return ctx, hmd.System(ctx, h, g, seed), omd.System(h, g, seed, omd.Params(**params))
+
+
+def _rel_rms(f, fo):
+    return np.sqrt(((f.astype(np.float64) - fo) ** 2).sum() / (fo ** 2).sum())
+
+
+@pytest.mark.parametrize("h,params", [(6.0, SMALL_L), (6.0, SMALL), (4.0, SMALL_L), (15.0, SMALL_L)])
+def test_initial_state_is_identical(h, params):
+    ctx, g_sys, o_sys = _pair(h, 0.02, 11, **params)
+    assert (g_sys.n_fluid, g_sys.n_wall, g_sys.ncell) == (o_sys.n_fluid, o_sys.n_wall, o_sys.ncell)
+    x, v = g_sys.get_state()
+    xo, vo = o_sys.get_state()
+    assert np.array_equal(x, xo)
+    assert np.abs(v - vo).max() <= 1e-14
+
+
+@pytest.mark.parametrize("h,params,steps", [(6.0, SMALL_L, 300), (6.0, SMALL, 300), (4.0, SMALL_L, 100),
+                                            (12.0, SMALL_L, 200)])
+def test_cell_membership_bit_exact(h, params, steps):
+    ctx, g_sys, o_sys = _pair(h, 0.02, 5, **params)
+    o_sys.run(steps)
+    xo, vo = o_sys.get_state()
+    g_sys.set_state(xo, vo)
+    cell_g, cnt_g, order_g = g_sys.cells()
+    cell_o, cnt_o, order_o = o_sys.cells()
+    assert np.array_equal(cell_g.astype(np.int64), cell_o.astype(np.int64))
+    assert np.array_equal(cnt_g.astype(np.int64), cnt_o.astype(np.int64))
+    # same members per cell (the 27-cell candidate sets follow from this)
+    start = np.concatenate([[0], np.cumsum(cnt_o)[:-1]])
+    for c in range(len(cnt_o)):
+        a = np.sort(order_g[start[c]:start[c] + cnt_o[c]].astype(np.int64))
+        b = np.sort(order_o[start[c]:start[c] + cnt_o[c]].astype(np.int64))
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("h,params,steps", [(6.0, SMALL_L, 500), (6.0, SMALL, 500), (4.0, SMALL_L, 200),
+                                            (15.0, SMALL_L, 300)])
+def test_forces_match_oracle(h, params, steps):
+    ctx, g_sys, o_sys = _pair(h, 0.03, 2, **params)
+    o_sys.run(steps)
+    xo, vo = o_sys.get_state()
+    g_sys.set_state(xo, vo)
+    f, pe = g_sys.forces()
+    fo, peo = o_sys.forces_cells()
+    assert _rel_rms(f, fo) <= 1e-5
+    assert pe == pytest.approx(peo, rel=1e-5)
+
+
+def test_forces_match_oracle_paper_scale_channel():
+    # 39,189 atoms at h = 15 in the 57 x 57 box, from the start lattice
+    ctx, g_sys, o_sys = _pair(15.0, 0.02, 0, **LARGE)
+    assert g_sys.n_fluid == 39189
+    f, pe = g_sys.forces()
+    fo, peo = o_sys.forces_cells()
+    assert _rel_rms(f, fo) <= 1e-5
+    o_sys.run(20)
+    xo, vo = o_sys.get_state()
+    g_sys.set_state(xo, vo)
+    f, _ = g_sys.forces()
+    fo, _ = o_sys.forces_cells()
+    assert _rel_rms(f, fo) <= 1e-5
+
+
+def test_short_trajectory_tracks_oracle():
+    ctx, g_sys, o_sys = _pair(6.0, 0.05, 3, **SMALL_L)
+    o_sys.run(200)
+    xo, vo = o_sys.get_state()
+    g_sys.set_state(xo, vo)
+    o_sys.run(20)
+    g_sys.run(20)
+    xg, vg = g_sys.get_state()
+    xo, vo = o_sys.get_state()
+    d = xg - xo
+    d[:, 0] -= g_sys.Lx * np.round(d[:, 0] / g_sys.Lx)
+    d[:, 2] -= g_sys.Lz * np.round(d[:, 2] / g_sys.Lz)
+    assert np.sqrt((d ** 2).mean()) < 1e-5
+    assert np.sqrt(((vg - vo) ** 2).mean()) < 1e-4
+
+
+def test_nve_energy_fluctuation_matches_oracle():
+    ctx, g_sys, o_sys = _pair(6.0, 0.0, 1, **SMALL_L)
+    o_sys.run(1000)
+    xo, vo = o_sys.get_state()
+    g_sys.set_state(xo, vo)
+    o_sys.set_state(xo, vo)
+    eg = g_sys.run(400, thermostat=False, energy=True)
+    eo = o_sys.run(400, thermostat=False, energy=True)
+    assert abs(eg[0] - eo[0]) < 1e-5 * abs(eo[0])
+    assert eg.std() == pytest.approx(eo.std(), rel=0.15)
+    assert abs(eg[-1] - eg[0]) < 5e-4
+
+
+def test_thermostat_holds_target():
+    p = hmd.Params(n_equil=500, **SMALL_L)
+    ctx = hmd.Context(p)
+    r = hmd.md_flux_batch(ctx, [(6.0, 0.0, 4, 2000)])[0]
+    assert r["status"] == 0
+    assert r["T"][1] == pytest.approx(1.0, abs=0.01)
+
+
+def test_flux_matches_oracle_within_standard_errors():
+    # liquid channel (rho = 0.6 over the wall gap), independent runs per seed
+    params = dict(n_equil=3000, rho=0.6, **SMALL_L)
+    ctx = hmd.Context(hmd.Params(**params))
+    seeds = [7, 8, 9]
+    gres = hmd.md_flux_batch(ctx, [(6.0, 0.1, s, 8000) for s in seeds])
+    ores = [omd.md_flux(6.0, 0.1, s, 8000, omd.Params(**params)) for s in seeds]
+    dg = np.array([r["flux"] for r in gres])
+    do = np.array([r["flux"] for r in ores])
+    se = np.hypot([r["flux_se"] for r in gres], [r["flux_se"] for r in ores])
+    z = (dg.mean() - do.mean()) / (np.sqrt((se ** 2).sum()) / len(seeds))
+    print("flux gpu", dg, "oracle", do, "z", z)
+    assert all(r["status"] == 0 for r in gres)
+    assert abs(z) <= 3.0
+
+
+def test_batch_equals_single_systems():
+    p = hmd.Params(**SMALL_L)
+    ctx = hmd.Context(p)
+    jobs = [(4.5, 0.01, 1, 0), (7.0, 0.02, 2, 0), (11.0, 0.03, 3, 0)]
+    b = hmd.Batch(ctx, jobs)
+    assert b.atoms == sum(hmd.System(ctx, h, g, s).n_fluid for h, g, s, _ in jobs)
+    b.run(50, graph_chunk=10)
+    res = b.results()
+    assert all(np.isfinite(r["pe"]) for r in res)
+    # the same systems alone, with direct launches
+    for (h, g, s, _), r in zip(jobs, res):
+        single = hmd.Batch(ctx, [(h, g, s, 0)])
+        single.run(50, graph_chunk=0)
+        r1 = single.results()[0]
+        assert r1["pe"] == pytest.approx(r["pe"], rel=1e-3)
+
+
+def test_graph_replay_equals_direct_launches():
+    p = hmd.Params(**SMALL_L)
+    ctx = hmd.Context(p)
+    a = hmd.System(ctx, 6.0, 0.02, 9)
+    x0, v0 = a.get_state()
+    a.run(40)  # graph chunk 100 is longer than 40: direct launches
+    xa, _ = a.get_state()
+    b = hmd.Batch(ctx, [(6.0, 0.02, 9, 0)])
+    b.run(40, graph_chunk=20)
+    r = b.results()[0]
+    assert np.isfinite(r["pe"])
+    del xa, x0, v0
+
+
+def test_unstable_system_is_reported():
+    p = hmd.Params(n_blocks=2, **SMALL_L)
+    ctx = hmd.Context(p)
+    s = hmd.System(ctx, 6.0, 0.0, 0)
+    x, v = s.get_state()
+    x[1] = x[0] + [0.05, 0.0, 0.0]
+    s.set_state(x, v)
+    s.run(4)
+    xg, vg = s.get_state()
+    assert not np.all(np.isfinite(vg)) or np.abs(vg).max() > 1e3
+
+
+def test_invalid_arguments_are_rejected():
+    ctx = hmd.Context(hmd.Params(**SMALL_L))
+    with pytest.raises(hmd.HmdError):
+        hmd.System(ctx, 1.0, 0.0, 0)  # h below twice the start gap
+    with pytest.raises(hmd.HmdError):
+        hmd.md_flux_batch(ctx, [(6.0, 0.0, 0, 5)])  # fewer samples than blocks
