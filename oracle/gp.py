@@ -1,0 +1,118 @@
+"""Gaussian-process surrogate oracle, FP64 numpy/scipy.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Follows Sec. 2.2-2.3 of the paper:
+  - prior f ~ GP(0, K) (Eq. GPEq, zero mean as in Sec. 3.1 / Appendix B);
+  - squared-exponential kernel K = sigma_f^2 exp(-d^2 / (2 l^2))
+    (Eq. quadraticKernelEq);
+  - d^2 = sum_k ((x_ik - x_jk) / mean separation of input k)^2 (Eq. d2Eq),
+    the mean separation recomputed whenever the database changes;
+  - noisy covariance C = K + sigma_n^2 I (Eq. covarianceEq);
+  - posterior mean K(X*, X) C^-1 y (Eq. predMeanEq) and covariance
+    K(X*, X*) - K(X*, X) C^-1 K(X, X*) (Eq. predVarEq), whose diagonal is the
+    predicted variance that the threshold test uses;
+  - log marginal likelihood -1/2 y^T C^-1 y - 1/2 log|C| - n/2 log 2 pi
+    (Eq. evidenceEq).
+Readings where the paper is silent (also listed in the design notes):
+  - "mean separation between inputs" = mean of |x_ik - x_jk| over distinct
+    pairs i < j; with fewer than two points, or a zero mean separation, a
+    quarter of the stated input range is used;
+  - outputs are divided by their RMS before fitting (so sigma_f = 1 is a
+    statement in units of the data), and sigma_n, when not given, is the
+    mean per-point standard error in the same scaled units (Sec. 2.3 estimates
+    sigma_n from the MD data rather than fitting it);
+  - the variance compared with the threshold is the latent one (no sigma_n^2).
+"""
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+from scipy.linalg import solve_triangular
+
+
+@dataclass
+class Hyper:
+    sigma_f: float = 1.0
+    ell: float = 1.0
+    sigma_n: float = -1.0          # < 0: mean(y_se) / output scale
+    scale_mode: int = 0            # 0 mean pairwise separation, 1 fixed ranges
+    ranges: Sequence[float] = field(default_factory=lambda: (16.0, 0.049))
+    out_scale: int = 1             # 1: divide outputs by their RMS
+
+
+def mean_separation(X: np.ndarray, ranges, mode: int) -> np.ndarray:
+    """Denominators of Eq. d2Eq, one per input."""
+    X = np.asarray(X, dtype=np.float64)
+    n, d = X.shape
+    fallback = 0.25 * np.asarray(ranges, dtype=np.float64)[:d]
+    if mode == 1 or n < 2:
+        return fallback.copy()
+    out = np.empty(d)
+    for k in range(d):
+        diffs = np.abs(X[:, None, k] - X[None, :, k])
+        iu = np.triu_indices(n, 1)
+        m = diffs[iu].mean()
+        out[k] = m if m > 0.0 else fallback[k]
+    return out
+
+
+def kernel(A: np.ndarray, B: np.ndarray, scale: np.ndarray, sigma_f: float, ell: float) -> np.ndarray:
+    """Eq. quadraticKernelEq on the normalised distance of Eq. d2Eq."""
+    D = (A[:, None, :] - B[None, :, :]) / scale[None, None, :]
+    d2 = (D ** 2).sum(-1)
+    return sigma_f ** 2 * np.exp(-d2 / (2.0 * ell ** 2))
+
+
+class GP:
+    def __init__(self, X, y, y_se=None, hyper: Optional[Hyper] = None):
+        self.h = hyper or Hyper()
+        self.X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
+        self.y = np.asarray(y, dtype=np.float64).copy()
+        self.se = np.zeros_like(self.y) if y_se is None else np.asarray(y_se, dtype=np.float64).copy()
+        self._fit()
+
+    def _fit(self):
+        h = self.h
+        n = len(self.y)
+        self.scale = mean_separation(self.X, h.ranges, h.scale_mode)
+        if h.out_scale and n > 0:
+            s = np.sqrt(np.mean(self.y ** 2))
+            self.s_q = s if s > 0 else 1.0
+        else:
+            self.s_q = 1.0
+        self.ys = self.y / self.s_q
+        self.sigma_n = h.sigma_n / self.s_q if h.sigma_n >= 0 else (self.se.mean() / self.s_q if n else 0.0)
+        if n == 0:
+            self.L = np.zeros((0, 0))
+            self.alpha = np.zeros(0)
+            return
+        C = kernel(self.X, self.X, self.scale, h.sigma_f, h.ell) + self.sigma_n ** 2 * np.eye(n)
+        self.L = np.linalg.cholesky(C)
+        w = solve_triangular(self.L, self.ys, lower=True)
+        self.alpha = solve_triangular(self.L.T, w, lower=False)
+
+    def append(self, x, y, se=0.0):
+        """Alg. 1 database growth: append and update the covariance (the
+        normalisation changes with the data, so this refits)."""
+        self.X = np.vstack([self.X, np.asarray(x, dtype=np.float64).reshape(1, -1)])
+        self.y = np.append(self.y, float(y))
+        self.se = np.append(self.se, float(se))
+        self._fit()
+
+    def predict(self, Xs):
+        """Posterior mean and latent variance in output units."""
+        Xs = np.asarray(Xs, dtype=np.float64).reshape(-1, self.X.shape[1])
+        sf2 = self.h.sigma_f ** 2
+        if len(self.y) == 0:
+            return np.zeros(len(Xs)), np.full(len(Xs), sf2 * self.s_q ** 2)
+        Ks = kernel(Xs, self.X, self.scale, self.h.sigma_f, self.h.ell)
+        mean = Ks @ self.alpha
+        V = solve_triangular(self.L, Ks.T, lower=True)
+        var = sf2 - (V ** 2).sum(0)
+        return mean * self.s_q, var * self.s_q ** 2
+
+    def log_marginal(self):
+        """Eq. evidenceEq on the scaled outputs."""
+        n = len(self.y)
+        return float(-0.5 * self.ys @ self.alpha - np.log(np.diag(self.L)).sum() - 0.5 * n * np.log(2 * np.pi))

@@ -102,6 +102,7 @@ struct hmd_batch {
   uint32_t* d_start = nullptr;      // first slot of each cell
   uint32_t* d_ncount = nullptr;     // atoms per cell after the sort
   uint32_t* d_perm = nullptr;       // scatter target -> source slot
+  uint32_t* d_rank = nullptr;       // arrival rank of each slot inside its new cell
   float4* d_wpos4 = nullptr;        // wall atoms, column order, column-relative
   uint32_t* d_wstart = nullptr;
   uint32_t* d_wcount = nullptr;

@@ -91,14 +91,14 @@ void enqueue_step(hmd_batch* b, Launcher& L, const StepConst& K) {
   const int src = b->cur, dst = 1 - b->cur;
   L.begin(K_INTEGRATE);
   hipLaunchKernelGGL(k_integrate<1>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
-                     state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->acc, b->d_dstate, K);
+                     state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->d_rank, b->acc, b->d_dstate, K);
   L.end();
   L.begin(K_SCAN);
   hipLaunchKernelGGL(k_scan, dim3(b->S), dim3(1024), 0, s, b->d_sims, b->d_count, b->d_cursor, b->d_start,
                      b->d_ncount, b->d_dstate, 1);
   L.end();
   L.begin(K_SCATTER);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_key, b->d_start, b->d_cursor,
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_key, b->d_start, b->d_rank,
                      b->d_perm);
   L.end();
   L.begin(K_REORDER);
@@ -117,10 +117,10 @@ void enqueue_sort(hmd_batch* b, hipStream_t s, const StepConst& K) {
   const int nt = int(b->ntot);
   const int src = b->cur, dst = 1 - b->cur;
   hipLaunchKernelGGL(k_integrate<0>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
-                     state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->acc, b->d_dstate, K);
+                     state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->d_rank, b->acc, b->d_dstate, K);
   hipLaunchKernelGGL(k_scan, dim3(b->S), dim3(1024), 0, s, b->d_sims, b->d_count, b->d_cursor, b->d_start,
                      b->d_ncount, b->d_dstate, 0);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_key, b->d_start, b->d_cursor,
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_key, b->d_start, b->d_rank,
                      b->d_perm);
   hipLaunchKernelGGL(k_reorder, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_cell_sim, b->d_key,
                      b->d_start, b->d_ncount, b->d_perm, state_ref(b, src), state_ref(b, dst), b->d_tag[src],
@@ -236,7 +236,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
       (rc = dalloc(ctx, &b->d_pos4, b->ntot)) || (rc = dalloc(ctx, &b->d_key, b->ntot)) ||
       (rc = dalloc(ctx, &b->d_count, b->ncell)) || (rc = dalloc(ctx, &b->d_cursor, b->ncell)) ||
       (rc = dalloc(ctx, &b->d_start, b->ncell)) || (rc = dalloc(ctx, &b->d_ncount, b->ncell)) ||
-      (rc = dalloc(ctx, &b->d_perm, b->ntot)) || (rc = dalloc(ctx, &b->d_wpos4, b->nwall)) ||
+      (rc = dalloc(ctx, &b->d_perm, b->ntot)) || (rc = dalloc(ctx, &b->d_rank, b->ntot)) || (rc = dalloc(ctx, &b->d_wpos4, b->nwall)) ||
       (rc = dalloc(ctx, &b->d_wstart, b->nwcell)) || (rc = dalloc(ctx, &b->d_wcount, b->nwcell)) ||
       (rc = dalloc(ctx, &b->d_dstate, 4)) || (rc = dalloc(ctx, &b->d_tag[0], b->ntot)) ||
       (rc = dalloc(ctx, &b->d_tag[1], b->ntot)))
@@ -343,7 +343,7 @@ void batch_free(hmd_batch* b) {
   release_graphs(b);
   for (auto e : b->ev) (void)hipEventDestroy(e);
   void* ptrs[] = {b->d_sims, b->d_atom_sim, b->d_cell_sim, b->d_f4, b->d_pos4, b->d_key, b->d_count,
-                  b->d_cursor, b->d_start, b->d_ncount, b->d_perm, b->d_wpos4, b->d_wstart, b->d_wcount,
+                  b->d_cursor, b->d_start, b->d_ncount, b->d_perm, b->d_rank, b->d_wpos4, b->d_wstart, b->d_wcount,
                   b->d_dstate, b->d_tag[0], b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -468,7 +468,7 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
     }
     hipGraphExec_t ex = nullptr;
     int key = 0;
-    HMD_TRY(get_graph(b, graph_chunk, K, b->timing, &ex, &key));
+    HMD_TRY(get_graph(b, graph_chunk, K, false, &ex, &key));
     while (steps - k >= graph_chunk) {
       if (b->timing) {
         hipEvent_t e0 = b->ev[0], e1 = b->ev[1];
@@ -480,8 +480,6 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
         HMD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
         b->graph_ms += ms;
         b->graph_steps += graph_chunk;
-        std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> gm = b->graph_marks[key];
-        HMD_TRY(harvest(b, gm));
       } else {
         HMD_HIP(ctx, hipGraphLaunch(ex, s));
       }
@@ -494,7 +492,7 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
   // finish the last step: sample it with the Berendsen factor applied
   const int nt = int(b->ntot);
   hipLaunchKernelGGL(k_integrate<2>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
-                     state_ref(b, b->cur), b->d_f4, b->d_key, b->d_count, b->acc, b->d_dstate, K);
+                     state_ref(b, b->cur), b->d_f4, b->d_key, b->d_count, b->d_rank, b->acc, b->d_dstate, K);
   if (b->done > b->P.n_equil) {
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate + 2, b->done);
     b->sampled_upto = b->done;

@@ -60,7 +60,8 @@ __global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __res
                                                    const uint16_t* __restrict__ atom_sim,
                                                    StateRef st, const float4* __restrict__ f4,
                                                    uint32_t* __restrict__ key, uint32_t* __restrict__ count,
-                                                   Acc acc, const int64_t* __restrict__ dstate, StepConst K) {
+                                                   uint32_t* __restrict__ rank, Acc acc,
+                                                   const int64_t* __restrict__ dstate, StepConst K) {
   __shared__ double lds_vx[BIN_LDS];
   __shared__ double lds_cnt[BIN_LDS];
   __shared__ int lds_bin_base;
@@ -145,34 +146,60 @@ __global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __res
         }
       }
     }
-    if (MODE == 2 || !valid) return;
-    if (i == D->a0) {
+    if (MODE == 2) return;
+    if (valid && i == D->a0) {
       const int p = int((n + 1) & 1);
       acc.vc2[p][s] = 0.0;
       acc.pe[p][s] = 0.0;
       acc.ke[p][s] = 0.0;
     }
     // First half-kick with the force of the previous step, drift, wrap.
-    const float4 f = f4[i];
-    v[0] += K.hdt * (double(f.x) + D->g);
-    v[1] += K.hdt * double(f.y);
-    v[2] += K.hdt * double(f.z);
-    r[0] = wrap_periodic(r[0] + K.dt * v[0], D->Lx);
-    r[1] = r[1] + K.dt * v[1];
-    r[2] = wrap_periodic(r[2] + K.dt * v[2], D->Lz);
-    st.x[i] = r[0]; st.y[i] = r[1]; st.z[i] = r[2];
-    st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
-    const bool bad = !(r[1] > 0.0 && r[1] < D->h) || !(r[0] >= 0.0 && r[0] < D->Lx) ||
-                     !(r[2] >= 0.0 && r[2] < D->Lz) || !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
-    if (bad) atomicOr(&acc.status[s], 1);
+    const float4 f = valid ? f4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) {
+      v[0] += K.hdt * (double(f.x) + D->g);
+      v[1] += K.hdt * double(f.y);
+      v[2] += K.hdt * double(f.z);
+      r[0] = wrap_periodic(r[0] + K.dt * v[0], D->Lx);
+      r[1] = r[1] + K.dt * v[1];
+      r[2] = wrap_periodic(r[2] + K.dt * v[2], D->Lz);
+    }
+    if (valid) {
+      st.x[i] = r[0]; st.y[i] = r[1]; st.z[i] = r[2];
+      st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
+      const bool bad = !(r[1] > 0.0 && r[1] < D->h) || !(r[0] >= 0.0 && r[0] < D->Lx) ||
+                       !(r[2] >= 0.0 && r[2] < D->Lz) || !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
+      if (bad) atomicOr(&acc.status[s], 1);
+    }
   }
-  if (!valid) return;
-  const int cx = dcell(r[0], D->inv_x, D->nx);
-  const int cy = dcell(r[1], D->inv_y, D->ny);
-  const int cz = dcell(r[2], D->inv_z, D->nz);
-  const uint32_t c = uint32_t(D->c0 + (cz * D->ny + cy) * D->nx + cx);
-  key[i] = c;
-  atomicAdd(&count[c], 1u);
+  uint32_t c = 0;
+  if (valid) {
+    const int cx = dcell(r[0], D->inv_x, D->nx);
+    const int cy = dcell(r[1], D->inv_y, D->ny);
+    const int cz = dcell(r[2], D->inv_z, D->nz);
+    c = uint32_t(D->c0 + (cz * D->ny + cy) * D->nx + cx);
+    key[i] = c;
+  }
+  // Arrival rank inside the cell: lanes of a wave with the same key take one
+  // atomic together (sorted neighbours share keys, so a wave has few keys).
+  const int lane = threadIdx.x & (WAVE - 1);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  bool todo = valid;
+  uint32_t rk = 0;
+  while (__any(todo)) {
+    const unsigned long long pm = __ballot(todo);
+    const int leader = __ffsll(pm) - 1;
+    const uint32_t ck = __shfl(c, leader);
+    const bool mine = todo && c == ck;
+    const unsigned long long m = __ballot(mine);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&count[ck], uint32_t(__popcll(m)));
+    base = __shfl(base, leader);
+    if (mine) {
+      rk = base + uint32_t(__popcll(m & lt));
+      todo = false;
+    }
+  }
+  if (valid) rank[i] = rk;
 }
 
 // ---------------------------------------------------------------------------
@@ -231,14 +258,13 @@ __global__ __launch_bounds__(1024) void k_scan(const SimDev* __restrict__ sims, 
 }
 
 // scatter: counting-sort placement of every slot index into its cell's range
-// (arrival order inside a cell is fixed by the reorder kernel).
+// at its arrival rank (the order inside a cell is fixed by the reorder kernel).
 __global__ __launch_bounds__(256) void k_scatter(int ntot, const uint32_t* __restrict__ key,
-                                                 const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
-                                                 uint32_t* __restrict__ perm) {
+                                                 const uint32_t* __restrict__ start,
+                                                 const uint32_t* __restrict__ rank, uint32_t* __restrict__ perm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ntot) return;
-  const uint32_t c = key[i];
-  perm[start[c] + atomicAdd(&cursor[c], 1u)] = uint32_t(i);
+  perm[start[key[i]] + rank[i]] = uint32_t(i);
 }
 
 // reorder: inside each cell, the atom from old slot p goes to position
@@ -397,11 +423,11 @@ __global__ __launch_bounds__(256) void k_force(int ntot, const SimDev* __restric
 }
 
 template __global__ void k_integrate<0>(int, const SimDev*, const uint16_t*, StateRef, const float4*, uint32_t*,
-                                        uint32_t*, Acc, const int64_t*, StepConst);
+                                        uint32_t*, uint32_t*, Acc, const int64_t*, StepConst);
 template __global__ void k_integrate<1>(int, const SimDev*, const uint16_t*, StateRef, const float4*, uint32_t*,
-                                        uint32_t*, Acc, const int64_t*, StepConst);
+                                        uint32_t*, uint32_t*, Acc, const int64_t*, StepConst);
 template __global__ void k_integrate<2>(int, const SimDev*, const uint16_t*, StateRef, const float4*, uint32_t*,
-                                        uint32_t*, Acc, const int64_t*, StepConst);
+                                        uint32_t*, uint32_t*, Acc, const int64_t*, StepConst);
 template __global__ void k_force<0>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
                                     const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
                                     StateRef, Acc, int64_t*, StepConst);
