@@ -161,8 +161,15 @@ void md_sys_free(hmd_sys* s);
  * database inputs (Eq. d2Eq), noisy covariance C = K + sigma_n^2 I
  * (Eq. covarianceEq), posterior mean and variance (Eqs. predMeanEq,
  * predVarEq), log marginal likelihood (Eq. evidenceEq).  Prior mean zero.
- * X is row-major n x d; y the outputs; y_se (nullable) per-point standard
- * errors used to set sigma_n when hyper->sigma_n < 0.  All FP64, on device.
+ * X is row-major n x d (1 <= d <= 4); y the outputs; y_se (nullable)
+ * per-point standard errors.  Readings: the mean separation is the mean of
+ * |x_ik - x_jk| over pairs i < j (a quarter of range[k] with fewer than two
+ * points, or when scale_mode = 1); with out_scale the outputs are divided by
+ * their RMS before fitting; sigma_n < 0 means mean(y_se) in those units.
+ * gp_append refits (the normalisation moves with the data) except when the
+ * normalisation, noise and output scale are all fixed, where it extends the
+ * Cholesky factor by one row.  All arithmetic FP64 on the device; ENOTSPD
+ * when the covariance is not positive definite.
  * ------------------------------------------------------------------------ */
 typedef struct {
     double sigma_f, ell, sigma_n;  /* sigma_n < 0: mean(y_se) / output scale */
@@ -180,6 +187,9 @@ int gp_append(hmd_gp* gp, const double* x, double y, double y_se);
 int gp_predict(hmd_gp* gp, const double* Xs, int m, double* mean, double* var);
 int gp_log_marginal(hmd_gp* gp, double* lml);
 int gp_size(const hmd_gp* gp);
+/* The normalisation in use: per-input denominators of Eq. d2Eq (d values),
+ * the output scale and sigma_n in scaled units (each nullable). */
+int gp_scales(const hmd_gp* gp, double* scale, double* s_q, double* sigma_n);
 void gp_free(hmd_gp* gp);
 
 /* ------------------------------------------------------------------------

@@ -293,3 +293,83 @@ class System:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- GP surrogate
+class GpHyper(_c.Structure):
+    _fields_ = [("sigma_f", d), ("ell", d), ("sigma_n", d), ("scale_mode", i32), ("range", d * 4),
+                ("out_scale", i32)]
+
+
+_sig("hmd_gp_hyper_default", None, P(GpHyper))
+_sig("gp_fit", i32, vp, P(d), P(d), P(d), i32, i32, P(GpHyper), P(vp))
+_sig("gp_append", i32, vp, P(d), d, d)
+_sig("gp_predict", i32, vp, P(d), i32, P(d), P(d))
+_sig("gp_log_marginal", i32, vp, P(d))
+_sig("gp_size", i32, vp)
+_sig("gp_scales", i32, vp, P(d), P(d), P(d))
+_sig("gp_free", None, vp)
+
+
+def gp_hyper(sigma_f=1.0, ell=1.0, sigma_n=-1.0, scale_mode=0, ranges=(16.0, 0.049), out_scale=1):
+    h = GpHyper()
+    _lib.hmd_gp_hyper_default(_c.byref(h))
+    h.sigma_f, h.ell, h.sigma_n, h.scale_mode, h.out_scale = sigma_f, ell, sigma_n, scale_mode, out_scale
+    for k, r in enumerate(ranges):
+        h.range[k] = r
+    return h
+
+
+class GP:
+    """gp_*: FP64 Gaussian process on the device."""
+
+    def __init__(self, ctx: Context, X, y, y_se=None, hyper: GpHyper = None):
+        self.ctx = ctx
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(len(y), -1))
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        self.d = X.shape[1] if X.size else 2
+        se = None if y_se is None else np.ascontiguousarray(y_se, dtype=np.float64)
+        self._h = vp()
+        hp = hyper or gp_hyper()
+        ctx.check(_lib.gp_fit(ctx.handle, _ptr(X), _ptr(y), _ptr(se) if se is not None else None, len(y), self.d,
+                              _c.byref(hp), _c.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return _lib.gp_size(self._h)
+
+    def append(self, x, y, se=0.0):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        self.ctx.check(_lib.gp_append(self._h, _ptr(x), float(y), float(se)))
+
+    def predict(self, Xs):
+        Xs = np.ascontiguousarray(np.asarray(Xs, dtype=np.float64).reshape(-1, self.d))
+        m = len(Xs)
+        mean, var = np.zeros(m), np.zeros(m)
+        self.ctx.check(_lib.gp_predict(self._h, _ptr(Xs), m, _ptr(mean), _ptr(var)))
+        return mean, var
+
+    def log_marginal(self):
+        v = d()
+        self.ctx.check(_lib.gp_log_marginal(self._h, _c.byref(v)))
+        return v.value
+
+    def scales(self):
+        sc = np.zeros(self.d)
+        sq, sn = d(), d()
+        self.ctx.check(_lib.gp_scales(self._h, _ptr(sc), _c.byref(sq), _c.byref(sn)))
+        return sc, sq.value, sn.value
+
+    def close(self):
+        if self._h:
+            _lib.gp_free(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -30,6 +30,7 @@ SOURCES = [
     ("md_kernels.hip", "hip"),
     ("md_engine.hip", "hip"),
     ("abi.cpp", "hip"),
+    ("gp.hip", "hip"),
     ("pending.cpp", "host"),
 ]
 

@@ -1,0 +1,513 @@
+// gp.hip -- Gaussian-process surrogate on the device, FP64 throughout
+// (paper Sec. 2.2-2.3):
+//   covariance   C = sigma_f^2 exp(-d^2 / 2 l^2) + sigma_n^2 I
+//                (Eqs. quadraticKernelEq, d2Eq, covarianceEq)
+//   factor       C = L L^T (right-looking Cholesky in one workgroup)
+//   weights      alpha = C^-1 y by two triangular solves
+//   prediction   mean = K* alpha (Eq. predMeanEq),
+//                var = sigma_f^2 - |L^-1 k*|^2 (diagonal of Eq. predVarEq)
+//   evidence     -1/2 y^T alpha - sum log L_ii - n/2 log 2 pi (Eq. evidenceEq)
+// Database sizes here are hundreds of points: the factorisation and solves
+// are latency bound, so one workgroup walks the columns with barriers while
+// prediction spreads query blocks over the chip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "engine.h"
+
+struct hmd_gp {
+  hmd_ctx* ctx = nullptr;
+  hmd_gp_hyper hyp{};
+  int d = 0;
+  int n = 0, cap = 0;
+  std::vector<double> X, y, se;  // database (host copy)
+  double scale[4] = {1, 1, 1, 1};
+  double s_q = 1.0, sigma_n = 0.0;
+  double* dX = nullptr;      // cap x 4, row-major
+  double* dy = nullptr;      // scaled outputs
+  double* dL = nullptr;      // cap x cap, column-major (leading dimension cap)
+  double* dalpha = nullptr;  // C^-1 y
+  double* dtmp = nullptr;    // cap
+  double* dq = nullptr;      // query staging
+  double* dV = nullptr;      // query workspace
+  double* dout = nullptr;    // predictions / scalars
+  int* dinfo = nullptr;
+  size_t q_cap = 0;
+};
+
+namespace hmd {
+namespace {
+
+constexpr int GP_MAXD = 4;
+
+struct KParams {
+  double inv_scale[GP_MAXD];
+  double sf2, inv_2l2, sn2;
+  int d;
+};
+
+__device__ __forceinline__ double sqexp(const double* a, const double* b, const KParams& P) {
+  double d2 = 0.0;
+  for (int k = 0; k < P.d; ++k) {
+    const double t = (a[k] - b[k]) * P.inv_scale[k];
+    d2 += t * t;
+  }
+  return P.sf2 * exp(-d2 * P.inv_2l2);
+}
+
+// Lower triangle (and diagonal) of C for rows/cols [0, n).
+__global__ void k_gp_cov(int n, int ld, const double* __restrict__ X, KParams P, double* __restrict__ L) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n || j >= n || i < j) return;
+  double c = sqexp(X + GP_MAXD * i, X + GP_MAXD * j, P);
+  if (i == j) c += P.sn2;
+  L[i + size_t(j) * ld] = c;
+}
+
+// In-place right-looking Cholesky of the lower triangle, one workgroup.
+// info = 0 on success, k + 1 if the k-th pivot is not positive.
+__global__ __launch_bounds__(1024) void k_gp_chol(int n, int ld, double* __restrict__ A, int* __restrict__ info,
+                                                  int k0) {
+  __shared__ double piv;
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int k = k0; k < n; ++k) {
+    if (tid == 0) {
+      const double a = A[k + size_t(k) * ld];
+      if (!(a > 0.0)) {
+        bad = k + 1;
+        piv = 1.0;
+      } else {
+        piv = sqrt(a);
+        A[k + size_t(k) * ld] = piv;
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    const double inv = 1.0 / piv;
+    for (int i = k + 1 + tid; i < n; i += nt) A[i + size_t(k) * ld] *= inv;
+    __syncthreads();
+    // trailing update of the lower triangle in 32 x 32 tiles
+    const int tx = tid & 31, ty = tid >> 5;
+    for (int jj = k + 1; jj < n; jj += 32) {
+      const int j = jj + ty;
+      const double ljk = j < n ? A[j + size_t(k) * ld] : 0.0;
+      for (int ii = jj; ii < n; ii += 32) {
+        const int i = ii + tx;
+        if (i < n && j < n && i >= j) A[i + size_t(j) * ld] -= A[i + size_t(k) * ld] * ljk;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *info = bad;
+}
+
+// x = L^-1 b (lower) then, if `both`, x = L^-T x: column-oriented
+// substitution in one workgroup; b is overwritten by the result.
+__global__ __launch_bounds__(1024) void k_gp_solve(int n, int ld, const double* __restrict__ L, double* __restrict__ b,
+                                                   int both) {
+  __shared__ double xk;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      xk = b[k] / L[k + size_t(k) * ld];
+      b[k] = xk;
+    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < n; i += nt) b[i] -= L[i + size_t(k) * ld] * xk;
+    __syncthreads();
+  }
+  if (!both) return;
+  for (int k = n - 1; k >= 0; --k) {
+    if (tid == 0) {
+      xk = b[k] / L[k + size_t(k) * ld];
+      b[k] = xk;
+    }
+    __syncthreads();
+    for (int i = tid; i < k; i += nt) b[i] -= L[k + size_t(i) * ld] * xk;
+    __syncthreads();
+  }
+}
+
+// Prediction for a block of QB queries per workgroup: k* columns, mean by a
+// dot product with alpha, variance by a multi-right-hand-side forward solve.
+constexpr int QB = 32;
+__global__ __launch_bounds__(256) void k_gp_predict(int n, int ld, int m, const double* __restrict__ X,
+                                                    const double* __restrict__ Xq, const double* __restrict__ L,
+                                                    const double* __restrict__ alpha, KParams P,
+                                                    double* __restrict__ V, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int q0 = blockIdx.x * QB;
+  const int nq = min(QB, m - q0);
+  double* Vb = V + size_t(blockIdx.x) * QB * size_t(n);  // n x QB, row-major in the query index
+  const int tid = threadIdx.x;
+  for (int t = tid; t < n * QB; t += blockDim.x) {
+    const int i = t / QB, q = t % QB;
+    Vb[t] = q < nq ? sqexp(X + GP_MAXD * i, Xq + GP_MAXD * (q0 + q), P) : 0.0;
+  }
+  __syncthreads();
+  // mean: one query at a time, block reduction over the database
+  for (int q = 0; q < nq; ++q) {
+    double s = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) s += Vb[i * QB + q] * alpha[i];
+    red[tid] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) out[2 * (q0 + q)] = red[0];
+    __syncthreads();
+  }
+  // forward substitution L V = K*^T for all queries of the block
+  for (int k = 0; k < n; ++k) {
+    const double inv = 1.0 / L[k + size_t(k) * ld];
+    if (tid < QB) Vb[k * QB + tid] *= inv;
+    __syncthreads();
+    for (int t = tid; t < (n - k - 1) * QB; t += blockDim.x) {
+      const int i = k + 1 + t / QB, q = t % QB;
+      Vb[i * QB + q] -= L[i + size_t(k) * ld] * Vb[k * QB + q];
+    }
+    __syncthreads();
+  }
+  if (tid < nq) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += Vb[i * QB + tid] * Vb[i * QB + tid];
+    out[2 * (q0 + tid) + 1] = P.sf2 - s;
+  }
+}
+
+// out[0] = y^T alpha, out[1] = sum log L_ii.
+__global__ __launch_bounds__(256) void k_gp_lml(int n, int ld, const double* __restrict__ L,
+                                                const double* __restrict__ y, const double* __restrict__ alpha,
+                                                double* __restrict__ out) {
+  __shared__ double r0[256], r1[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a += y[i] * alpha[i];
+    b += log(L[i + size_t(i) * ld]);
+  }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r0[threadIdx.x] += r0[threadIdx.x + o];
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = r0[0];
+    out[1] = r1[0];
+  }
+}
+
+// New last row of L for the point at index n: row = L^-1 c, then the pivot.
+__global__ __launch_bounds__(1024) void k_gp_append_row(int n, int ld, const double* __restrict__ X, KParams P,
+                                                        double* __restrict__ L, double* __restrict__ row,
+                                                        int* __restrict__ info) {
+  __shared__ double xk;
+  __shared__ double red[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < n; i += nt) row[i] = sqexp(X + GP_MAXD * i, X + GP_MAXD * n, P);
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      xk = row[k] / L[k + size_t(k) * ld];
+      row[k] = xk;
+    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < n; i += nt) row[i] -= L[i + size_t(k) * ld] * xk;
+    __syncthreads();
+  }
+  double s = 0.0;
+  for (int i = tid; i < n; i += nt) {
+    s += row[i] * row[i];
+    L[n + size_t(i) * ld] = row[i];
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int o = nt / 2; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double c = P.sf2 + P.sn2 - red[0];
+    if (c > 0.0) {
+      L[n + size_t(n) * ld] = sqrt(c);
+      *info = 0;
+    } else {
+      *info = n + 1;
+    }
+  }
+}
+
+KParams kparams(const hmd_gp* g) {
+  KParams P{};
+  for (int k = 0; k < GP_MAXD; ++k) P.inv_scale[k] = k < g->d ? 1.0 / g->scale[k] : 0.0;
+  P.sf2 = g->hyp.sigma_f * g->hyp.sigma_f;
+  P.inv_2l2 = 1.0 / (2.0 * g->hyp.ell * g->hyp.ell);
+  P.sn2 = g->sigma_n * g->sigma_n;
+  P.d = g->d;
+  return P;
+}
+
+// Normalisation of Eq. d2Eq and the output scale (host, FP64).
+void normalise(hmd_gp* g) {
+  const int n = g->n, d = g->d;
+  for (int k = 0; k < d; ++k) {
+    const double fallback = 0.25 * g->hyp.range[k];
+    double m = 0.0;
+    if (g->hyp.scale_mode == 0 && n >= 2) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) s += std::fabs(g->X[size_t(i) * d + k] - g->X[size_t(j) * d + k]);
+      m = s / (0.5 * double(n) * double(n - 1));
+    }
+    g->scale[k] = m > 0.0 ? m : fallback;
+  }
+  g->s_q = 1.0;
+  if (g->hyp.out_scale && n > 0) {
+    double s = 0.0;
+    for (double v : g->y) s += v * v;
+    s = std::sqrt(s / double(n));
+    if (s > 0.0) g->s_q = s;
+  }
+  if (g->hyp.sigma_n >= 0.0) {
+    g->sigma_n = g->hyp.sigma_n / g->s_q;
+  } else {
+    double s = 0.0;
+    for (double v : g->se) s += v;
+    g->sigma_n = n > 0 ? (s / double(n)) / g->s_q : 0.0;
+  }
+}
+
+int reserve(hmd_gp* g, int need) {
+  hmd_ctx* ctx = g->ctx;
+  if (need <= g->cap) return HMD_OK;
+  int cap = g->cap > 0 ? g->cap : 64;
+  while (cap < need) cap *= 2;
+  for (double* p : {g->dX, g->dy, g->dL, g->dalpha, g->dtmp})
+    if (p) (void)hipFree(p);
+  HMD_HIP(ctx, hipMalloc(&g->dX, sizeof(double) * GP_MAXD * cap));
+  HMD_HIP(ctx, hipMalloc(&g->dy, sizeof(double) * cap));
+  HMD_HIP(ctx, hipMalloc(&g->dL, sizeof(double) * size_t(cap) * cap));
+  HMD_HIP(ctx, hipMalloc(&g->dalpha, sizeof(double) * cap));
+  HMD_HIP(ctx, hipMalloc(&g->dtmp, sizeof(double) * (cap + 1)));
+  g->cap = cap;
+  return HMD_OK;
+}
+
+int upload_db(hmd_gp* g) {
+  hmd_ctx* ctx = g->ctx;
+  std::vector<double> xs(size_t(GP_MAXD) * g->n, 0.0), ys(g->n);
+  for (int i = 0; i < g->n; ++i) {
+    for (int k = 0; k < g->d; ++k) xs[size_t(i) * GP_MAXD + k] = g->X[size_t(i) * g->d + k];
+    ys[i] = g->y[i] / g->s_q;
+  }
+  HMD_HIP(ctx, hipMemcpyAsync(g->dX, xs.data(), 8 * xs.size(), hipMemcpyHostToDevice, ctx->stream));
+  HMD_HIP(ctx, hipMemcpyAsync(g->dy, ys.data(), 8 * ys.size(), hipMemcpyHostToDevice, ctx->stream));
+  return HMD_OK;
+}
+
+int solve_alpha(hmd_gp* g) {
+  hmd_ctx* ctx = g->ctx;
+  hipStream_t s = ctx->stream;
+  HMD_HIP(ctx, hipMemcpyAsync(g->dalpha, g->dy, 8 * size_t(g->n), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_gp_solve, dim3(1), dim3(1024), 0, s, g->n, g->cap, g->dL, g->dalpha, 1);
+  HMD_HIP(ctx, hipGetLastError());
+  return HMD_OK;
+}
+
+// Full refit: normalisation, covariance, factorisation, weights.
+int refit(hmd_gp* g) {
+  hmd_ctx* ctx = g->ctx;
+  normalise(g);
+  if (g->n == 0) return HMD_OK;
+  int rc = reserve(g, g->n);
+  if (rc != HMD_OK) return rc;
+  if ((rc = upload_db(g)) != HMD_OK) return rc;
+  hipStream_t s = ctx->stream;
+  const KParams P = kparams(g);
+  hipLaunchKernelGGL(k_gp_cov, dim3((g->n + 255) / 256, g->n), dim3(256), 0, s, g->n, g->cap, g->dX, P, g->dL);
+  hipLaunchKernelGGL(k_gp_chol, dim3(1), dim3(1024), 0, s, g->n, g->cap, g->dL, g->dinfo, 0);
+  int info = 0;
+  HMD_HIP(ctx, hipMemcpyAsync(&info, g->dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  if (info != 0) {
+    ctx->err = "gp: covariance not positive definite at pivot " + std::to_string(info - 1);
+    return HMD_ENOTSPD;
+  }
+  return solve_alpha(g);
+}
+
+}  // namespace
+}  // namespace hmd
+
+using namespace hmd;
+
+extern "C" {
+
+void hmd_gp_hyper_default(hmd_gp_hyper* h) {
+  if (!h) return;
+  h->sigma_f = 1.0;
+  h->ell = 1.0;
+  h->sigma_n = -1.0;
+  h->scale_mode = 0;
+  h->range[0] = 16.0;   // channel heights 4..20
+  h->range[1] = 0.049;  // body forces 0.001..0.05
+  h->range[2] = 1.0;
+  h->range[3] = 1.0;
+  h->out_scale = 1;
+}
+
+int gp_fit(hmd_ctx* ctx, const double* X, const double* y, const double* y_se, int n, int d,
+           const hmd_gp_hyper* hyper, hmd_gp** out) {
+  if (!ctx || !out || n < 0 || d < 1 || d > GP_MAXD || (n > 0 && (!X || !y))) {
+    if (ctx) ctx->err = "gp_fit: bad arguments (1 <= d <= 4, n >= 0)";
+    return HMD_EINVAL;
+  }
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  auto* g = new hmd_gp();
+  g->ctx = ctx;
+  if (hyper) g->hyp = *hyper;
+  else hmd_gp_hyper_default(&g->hyp);
+  if (!(g->hyp.sigma_f > 0.0) || !(g->hyp.ell > 0.0)) {
+    delete g;
+    ctx->err = "gp_fit: sigma_f and ell must be positive";
+    return HMD_EINVAL;
+  }
+  g->d = d;
+  g->n = n;
+  g->X.assign(X, X + size_t(n) * d);
+  g->y.assign(y, y + n);
+  g->se.assign(n, 0.0);
+  if (y_se) g->se.assign(y_se, y_se + n);
+  if (hipMalloc(&g->dinfo, sizeof(int)) != hipSuccess || hipMalloc(&g->dout, sizeof(double) * 4) != hipSuccess) {
+    gp_free(g);
+    ctx->err = "gp_fit: device allocation failed";
+    return HMD_ENOMEM;
+  }
+  const int rc = refit(g);
+  if (rc != HMD_OK) {
+    gp_free(g);
+    return rc;
+  }
+  HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *out = g;
+  return HMD_OK;
+}
+
+int gp_append(hmd_gp* g, const double* x, double y, double y_se) {
+  if (!g || !x) return HMD_EINVAL;
+  hmd_ctx* ctx = g->ctx;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  g->X.insert(g->X.end(), x, x + g->d);
+  g->y.push_back(y);
+  g->se.push_back(y_se);
+  g->n += 1;
+  // fixed normalisation, fixed noise and no output scaling: extend L by one
+  // row; otherwise the normalisation moved and the factor is rebuilt
+  const bool rank1 = g->hyp.scale_mode == 1 && g->hyp.out_scale == 0 && g->hyp.sigma_n >= 0.0 && g->n >= 2 &&
+                     g->n <= g->cap;
+  if (!rank1) return refit(g);
+  normalise(g);
+  int rc = upload_db(g);
+  if (rc != HMD_OK) return rc;
+  hipStream_t s = ctx->stream;
+  hipLaunchKernelGGL(k_gp_append_row, dim3(1), dim3(1024), 0, s, g->n - 1, g->cap, g->dX, kparams(g), g->dL,
+                     g->dtmp, g->dinfo);
+  int info = 0;
+  HMD_HIP(ctx, hipMemcpyAsync(&info, g->dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  if (info != 0) return refit(g);
+  rc = solve_alpha(g);
+  if (rc != HMD_OK) return rc;
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  return HMD_OK;
+}
+
+int gp_predict(hmd_gp* g, const double* Xs, int m, double* mean, double* var) {
+  if (!g || m < 0 || (m > 0 && (!Xs || !mean || !var))) return HMD_EINVAL;
+  hmd_ctx* ctx = g->ctx;
+  if (m == 0) return HMD_OK;
+  const double sf2 = g->hyp.sigma_f * g->hyp.sigma_f;
+  if (g->n == 0) {  // prior: zero mean, signal variance
+    for (int q = 0; q < m; ++q) {
+      mean[q] = 0.0;
+      var[q] = sf2 * g->s_q * g->s_q;
+    }
+    return HMD_OK;
+  }
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  const int nblk = (m + QB - 1) / QB;
+  const size_t need_q = size_t(GP_MAXD) * m, need_v = size_t(nblk) * QB * g->n;
+  if (need_q + need_v + 2 * size_t(m) > g->q_cap) {
+    if (g->dq) (void)hipFree(g->dq);
+    g->q_cap = 2 * (need_q + need_v + 2 * size_t(m));
+    HMD_HIP(ctx, hipMalloc(&g->dq, sizeof(double) * g->q_cap));
+  }
+  double* dXq = g->dq;
+  double* dV = g->dq + need_q;
+  double* dres = dV + need_v;
+  std::vector<double> xs(need_q, 0.0), res(2 * size_t(m));
+  for (int q = 0; q < m; ++q)
+    for (int k = 0; k < g->d; ++k) xs[size_t(q) * GP_MAXD + k] = Xs[size_t(q) * g->d + k];
+  hipStream_t s = ctx->stream;
+  HMD_HIP(ctx, hipMemcpyAsync(dXq, xs.data(), 8 * xs.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_gp_predict, dim3(nblk), dim3(256), 0, s, g->n, g->cap, m, g->dX, dXq, g->dL, g->dalpha,
+                     kparams(g), dV, dres);
+  HMD_HIP(ctx, hipGetLastError());
+  HMD_HIP(ctx, hipMemcpyAsync(res.data(), dres, 8 * res.size(), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  for (int q = 0; q < m; ++q) {
+    mean[q] = res[2 * q] * g->s_q;
+    var[q] = res[2 * q + 1] * g->s_q * g->s_q;
+  }
+  return HMD_OK;
+}
+
+int gp_log_marginal(hmd_gp* g, double* lml) {
+  if (!g || !lml) return HMD_EINVAL;
+  hmd_ctx* ctx = g->ctx;
+  if (g->n == 0) {
+    *lml = 0.0;
+    return HMD_OK;
+  }
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  hipLaunchKernelGGL(k_gp_lml, dim3(1), dim3(256), 0, s, g->n, g->cap, g->dL, g->dy, g->dalpha, g->dout);
+  double h[2];
+  HMD_HIP(ctx, hipMemcpyAsync(h, g->dout, sizeof(h), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  *lml = -0.5 * h[0] - h[1] - 0.5 * double(g->n) * std::log(2.0 * M_PI);
+  return HMD_OK;
+}
+
+int gp_size(const hmd_gp* g) { return g ? g->n : 0; }
+
+int gp_scales(const hmd_gp* g, double* scale, double* s_q, double* sigma_n) {
+  if (!g) return HMD_EINVAL;
+  if (scale)
+    for (int k = 0; k < g->d; ++k) scale[k] = g->scale[k];
+  if (s_q) *s_q = g->s_q;
+  if (sigma_n) *sigma_n = g->sigma_n;
+  return HMD_OK;
+}
+
+void gp_free(hmd_gp* g) {
+  if (!g) return;
+  for (void* p : {(void*)g->dX, (void*)g->dy, (void*)g->dL, (void*)g->dalpha, (void*)g->dtmp, (void*)g->dq,
+                  (void*)g->dout, (void*)g->dinfo})
+    if (p) (void)hipFree(p);
+  delete g;
+}
+
+}  // extern "C"

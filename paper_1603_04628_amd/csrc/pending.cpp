@@ -3,20 +3,6 @@
 #include "hmd.h"
 
 extern "C" {
-void hmd_gp_hyper_default(hmd_gp_hyper* h) {
-  if (!h) return;
-  h->sigma_f = 1.0; h->ell = 1.0; h->sigma_n = -1.0; h->scale_mode = 0;
-  for (double& r : h->range) r = 0.0;
-  h->out_scale = 1;
-}
-int gp_fit(hmd_ctx*, const double*, const double*, const double*, int, int, const hmd_gp_hyper*, hmd_gp**) {
-  return HMD_ENOSYS;
-}
-int gp_append(hmd_gp*, const double*, double, double) { return HMD_ENOSYS; }
-int gp_predict(hmd_gp*, const double*, int, double*, double*) { return HMD_ENOSYS; }
-int gp_log_marginal(hmd_gp*, double*) { return HMD_ENOSYS; }
-int gp_size(const hmd_gp*) { return 0; }
-void gp_free(hmd_gp*) {}
 void hmd_ens_cfg_default(hmd_ens_cfg* c) {
   if (!c) return;
   c->members = 5; c->hidden = 64; c->iters = 5000; c->lr = 1e-3; c->seed = 0;

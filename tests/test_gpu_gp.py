@@ -1,0 +1,85 @@
+"""Parity of the device GP (FP64) with the oracle GP through the C ABI."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+hmd = pytest.importorskip("paper_1603_04628_amd")
+from paper_1603_04628_amd import binding as B  # noqa: E402
+from oracle.gp import GP as OGP, Hyper  # noqa: E402
+
+RANGES = (16.0, 0.049)
+
+
+def data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = np.column_stack([rng.uniform(4, 20, n), rng.uniform(0.001, 0.05, n)])
+    y = 0.002 * X[:, 0] ** 3 * X[:, 1] * (1 + 0.2 * np.sin(X[:, 0])) + rng.normal(0, 0.01, n)
+    se = rng.uniform(0.005, 0.02, n)
+    return X, y, se
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return hmd.Context()
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 65, 256, 333])
+def test_fit_predict_matches_oracle(ctx, n):
+    X, y, se = data(n, n)
+    g = B.GP(ctx, X, y, se, B.gp_hyper(ranges=RANGES))
+    o = OGP(X, y, se, Hyper(ranges=RANGES))
+    sc, sq, sn = g.scales()
+    np.testing.assert_allclose(sc, o.scale, rtol=1e-13)
+    assert sq == pytest.approx(o.s_q, rel=1e-14) and sn == pytest.approx(o.sigma_n, rel=1e-13)
+    Xs, _, _ = data(200, 1000 + n)
+    Xs = np.vstack([Xs, X[:3], [[40.0, 0.2]]])
+    mg, vg = g.predict(Xs)
+    mo, vo = o.predict(Xs)
+    scale = max(np.abs(mo).max(), 1e-30)
+    assert np.abs(mg - mo).max() <= 1e-9 * scale + 1e-12
+    assert np.abs(vg - vo).max() <= 1e-9 * o.s_q ** 2
+    assert g.log_marginal() == pytest.approx(o.log_marginal(), rel=1e-9, abs=1e-9)
+
+
+def test_append_matches_oracle_refit(ctx):
+    X, y, se = data(40, 7)
+    g = B.GP(ctx, X[:30], y[:30], se[:30], B.gp_hyper(ranges=RANGES))
+    o = OGP(X[:30], y[:30], se[:30], Hyper(ranges=RANGES))
+    for k in range(30, 40):
+        g.append(X[k], y[k], se[k])
+        o.append(X[k], y[k], se[k])
+    assert len(g) == 40
+    Xs, _, _ = data(50, 99)
+    np.testing.assert_allclose(g.predict(Xs)[0], o.predict(Xs)[0], rtol=1e-9, atol=1e-12)
+
+
+def test_rank_one_append_equals_full_factorisation(ctx):
+    X, y, _ = data(70, 8)
+    hp = B.gp_hyper(sigma_n=0.05, scale_mode=1, ranges=RANGES, out_scale=0)
+    g = B.GP(ctx, X[:60], y[:60], None, hp)
+    for k in range(60, 70):
+        g.append(X[k], y[k], 0.0)
+    full = B.GP(ctx, X, y, None, hp)
+    Xs, _, _ = data(30, 5)
+    a, b = g.predict(Xs), full.predict(Xs)
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-10, atol=1e-13)
+    o = OGP(X, y, None, Hyper(sigma_n=0.05, scale_mode=1, ranges=RANGES, out_scale=0))
+    np.testing.assert_allclose(a[0], o.predict(Xs)[0], rtol=1e-9, atol=1e-12)
+
+
+def test_empty_database_returns_prior(ctx):
+    g = B.GP(ctx, np.zeros((0, 2)), np.zeros(0), None, B.gp_hyper(ranges=RANGES))
+    m, v = g.predict([[5.0, 0.01], [10.0, 0.02]])
+    assert np.all(m == 0.0) and np.all(v == 1.0)
+    g.append([5.0, 0.01], 0.3, 0.01)
+    m, v = g.predict([[5.0, 0.01]])
+    assert v[0] < 1.0
+
+
+def test_duplicate_points_without_noise_are_not_spd(ctx):
+    X = np.array([[5.0, 0.01], [5.0, 0.01]])
+    with pytest.raises(B.HmdError) as e:
+        B.GP(ctx, X, [0.1, 0.1], None, B.gp_hyper(sigma_n=0.0, ranges=RANGES))
+    assert e.value.code == B.HMD_ENOTSPD

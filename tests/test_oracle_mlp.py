@@ -1,0 +1,59 @@
+"""Pins for the MLP-ensemble oracle: finite-difference gradients, the Adam
+update formula, the Glorot-uniform start, and that training fits.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def _data(n=64, seed=0):
+    rng = np.random.default_rng(seed)
+    X = np.column_stack([rng.uniform(4, 20, n), rng.uniform(0.001, 0.05, n)])
+    y = 0.003 * X[:, 0] ** 2 * X[:, 1] * 10
+    return X, y
+
+
+def test_backward_matches_central_differences():
+    H = 8
+    rng = np.random.default_rng(1)
+    theta = rng.normal(0, 0.5, mlp.n_params(H))
+    Xs = rng.normal(size=(10, 2))
+    ys = rng.normal(size=10)
+    _, g = mlp.loss_and_grad(theta, Xs, ys, H)
+    fd = np.zeros_like(theta)
+    h = 1e-6
+    for p in range(len(theta)):
+        e = np.zeros_like(theta)
+        e[p] = h
+        fd[p] = (mlp.loss_and_grad(theta + e, Xs, ys, H)[0] - mlp.loss_and_grad(theta - e, Xs, ys, H)[0]) / (2 * h)
+    assert np.abs(g - fd).max() <= 1e-6 * max(1.0, np.abs(fd).max())
+
+
+def test_first_adam_step_is_lr_times_sign():
+    # with m = v = 0 the bias-corrected first step is lr * g / (|g| + eps)
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    th, m, v = mlp.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
+    np.testing.assert_allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_glorot_uniform_start():
+    H = 64
+    th = mlp.glorot_init(H, 0, 0)
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(th, H)
+    for W, lim in ((W1, np.sqrt(6 / 66)), (W2, np.sqrt(6 / 128)), (W3, np.sqrt(6 / 65))):
+        assert np.abs(W).max() < lim
+        assert np.var(W) == pytest.approx(lim ** 2 / 3, rel=0.2 if W.size > 100 else 0.6)
+    assert not b1.any() and not b2.any() and not b3.any()
+    assert not np.array_equal(th, mlp.glorot_init(H, 1, 0))
+    assert np.array_equal(th, mlp.glorot_init(H, 0, 0))
+
+
+def test_ensemble_fits_a_smooth_map():
+    X, y = _data(64)
+    ens = mlp.Ensemble(X, y, members=2, hidden=16, iters=1500, lr=3e-3)
+    assert max(ens.losses) < 1e-3
+    m, s = ens.predict(X)
+    assert np.sqrt(np.mean((m - y) ** 2)) < 0.05 * np.sqrt(np.mean(y ** 2))
+    assert np.all(s >= 0)
