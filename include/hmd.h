@@ -194,9 +194,15 @@ void gp_free(hmd_gp* gp);
 
 /* ------------------------------------------------------------------------
  * MLP deep ensemble (a learned surrogate beside the GP; not in the paper):
- * `members` nets of 2 -> hidden -> hidden -> 1 with tanh, FP32, trained
- * full-batch with Adam on standardised inputs and scaled outputs by the
- * library's own forward/backward kernels.
+ * `members` nets of 2 -> hidden -> hidden -> 1 with tanh (hidden <= 64),
+ * FP32 weights and accumulation, trained full-batch on the mean squared
+ * error with Adam (beta 0.9/0.999, eps 1e-8) by the library's own
+ * forward/backward kernels.  Inputs are standardised by the training mean
+ * and standard deviation, outputs divided by their RMS; weights start
+ * Glorot-uniform from Philox4x32-10 (key = seed, counter (p div 4, member,
+ * 2, 0), word p mod 4 for flat parameter p), biases at zero.  Flat parameter
+ * order: W1[hidden x 2], b1, W2[hidden x hidden], b2, W3[1 x hidden], b3.
+ * X is row-major n x 2.
  * ------------------------------------------------------------------------ */
 typedef struct { int members, hidden, iters; double lr; uint64_t seed; } hmd_ens_cfg;
 
@@ -210,6 +216,7 @@ int ens_loss(const hmd_ens* e, double* loss);
  * (test hook): grad receives the flattened parameter gradient. */
 int ens_grad_init(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg,
                   int member, double* params, double* grad, int* n_params);
+int ens_members(const hmd_ens* e);
 void ens_free(hmd_ens* e);
 
 /* ------------------------------------------------------------------------

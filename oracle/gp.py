@@ -67,7 +67,8 @@ def kernel(A: np.ndarray, B: np.ndarray, scale: np.ndarray, sigma_f: float, ell:
 class GP:
     def __init__(self, X, y, y_se=None, hyper: Optional[Hyper] = None):
         self.h = hyper or Hyper()
-        self.X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
+        X = np.asarray(X, dtype=np.float64)
+        self.X = X.reshape(len(y), X.shape[-1] if X.ndim == 2 else -1)
         self.y = np.asarray(y, dtype=np.float64).copy()
         self.se = np.zeros_like(self.y) if y_se is None else np.asarray(y_se, dtype=np.float64).copy()
         self._fit()

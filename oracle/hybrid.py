@@ -1,0 +1,134 @@
+"""Hybrid macro-march oracle (Alg. 1 of the paper), FP64 numpy.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Per macro step (Alg. 1, time-evolution loop):
+  1. pressure from the density (here a linear equation of state
+     p = p_out + c2 (rho - rho_ref), a reading standing in for the pressure GP);
+  2. pressure gradient by central differences (Alg. 1, p' = dp/ds), ghost
+     values p_in(t) before the first and p_out after the last section;
+  3. body force per section, Eq. momentumEq: g = F_ext/m - (1/rho) dp/ds
+     (F_ext = 0: the flow is driven by the oscillating inlet pressure);
+  4. surrogate mean and standard deviation at (h, g) (Eqs. predMeanEq,
+     predVarEq for the GP);
+  5. sections whose standard deviation exceeds max(tau_rel |mean|, tau_abs)
+     take the flux from the micro-solver and are added to the database
+     (Alg. 1 MD branch; tau_abs alone is the paper's absolute threshold
+     sigma_t, tau_rel alone a relative one); every `audit_every`-th surrogate
+     answer is also checked against the micro-solver;
+  6. mass conservation, Eq. continuityEq per unit span:
+     d(rho h)/dt = -(q'_{i+1/2} - q'_{i-1/2}) / ds with face fluxes the mean
+     of the two neighbouring sections and the boundary faces carrying the
+     boundary section's own flux.
+The flagged sections of one step are solved together (one batch) and the
+database grows after the step, where Alg. 1 walks the sections one by one.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class HybridCfg:
+    n_sections: int = 200
+    h0: float = 10.0
+    amp: float = 0.5
+    L: float = 2000.0
+    dt_macro: float = 0.02
+    rho_ref: float = 0.8
+    p_out: float = 0.0
+    dp_mean: float = 10.0
+    dp_amp: float = 0.3
+    period: float = 250.0     # in macro steps
+    c2: float = 200.0
+    tau_rel: float = 0.05
+    tau_abs: float = 0.0      # absolute threshold sigma_t of Sec. 2.2 (0: off)
+    audit_every: int = 0
+
+
+class Hybrid:
+    """micro(h, g) -> (q, se) arrays; surrogate has predict(X) -> (mean, var)
+    and append(x, y, se).  `var_is_std` selects whether predict's second
+    output is a standard deviation (ensemble) or a variance (GP)."""
+
+    def __init__(self, cfg: HybridCfg, surrogate, micro, var_is_std=False, rho0=None):
+        self.c = cfg
+        n = cfg.n_sections
+        self.ds = cfg.L / n
+        self.s = (np.arange(n) + 0.5) * self.ds
+        self.h = cfg.h0 * (1.0 + cfg.amp * np.cos(2.0 * np.pi * self.s / cfg.L))
+        self.rho = np.full(n, cfg.rho_ref) if rho0 is None else np.asarray(rho0, dtype=np.float64).copy()
+        self.sur = surrogate
+        self.micro = micro
+        self.var_is_std = var_is_std
+        self.step_no = 0
+        self.md_calls = 0
+        self.audited = 0
+        self.audit_pass = 0
+        self.answers = 0
+        self.q = np.zeros(n)
+        self.q_std = np.zeros(n)
+        self.from_md = np.zeros(n, dtype=bool)
+
+    def p_in(self, t_steps):
+        c = self.c
+        return c.p_out + c.dp_mean * (1.0 + c.dp_amp * np.sin(2.0 * np.pi * t_steps / c.period))
+
+    def forces(self):
+        c = self.c
+        p = c.p_out + c.c2 * (self.rho - c.rho_ref)
+        pl = np.concatenate([[self.p_in(self.step_no)], p[:-1]])
+        pr = np.concatenate([p[1:], [c.p_out]])
+        dpds = (pr - pl) / (2.0 * self.ds)
+        return -dpds / self.rho
+
+    def step(self):
+        c = self.c
+        g = self.forces()
+        X = np.column_stack([self.h, g])
+        mean, second = self.sur.predict(X)
+        std = second if self.var_is_std else np.sqrt(np.maximum(second, 0.0))
+        flag = std > np.maximum(c.tau_rel * np.abs(mean), c.tau_abs)
+        audit = np.zeros_like(flag)
+        if c.audit_every > 0:
+            for i in np.nonzero(~flag)[0]:
+                self.answers += 1
+                if self.answers % c.audit_every == 0:
+                    audit[i] = True
+        run = flag | audit
+        q = mean.copy()
+        if run.any():
+            idx = np.nonzero(run)[0]
+            qm, se = self.micro(self.h[idx], g[idx])
+            self.md_calls += len(idx)
+            for k, i in enumerate(idx):
+                if flag[i]:
+                    q[i] = qm[k]
+                else:
+                    self.audited += 1
+                    self.audit_pass += int(abs(mean[i] - qm[k]) <= 2.0 * se[k])
+            for k, i in enumerate(idx):
+                if flag[i]:
+                    self.sur.append(X[i], qm[k], se[k])
+        self.q, self.q_std, self.from_md = q, std, flag
+        face = 0.5 * (q[:-1] + q[1:])
+        flux = np.concatenate([[q[0]], face, [q[-1]]])
+        m = self.rho * self.h - c.dt_macro * (flux[1:] - flux[:-1]) / self.ds
+        self.rho = m / self.h
+        self.step_no += 1
+
+    def mass(self):
+        return float((self.rho * self.h).sum() * self.ds)
+
+
+def poiseuille_flux(h, g, rho=0.8, eta=2.0, slip=0.0):
+    """Continuum flux per unit span of a planar channel with Navier slip:
+    q' = rho^2 g h^3 (1 + 6 b / h) / (12 eta)."""
+    h = np.asarray(h, dtype=np.float64)
+    return rho * rho * np.asarray(g) * h ** 3 * (1.0 + 6.0 * slip / h) / (12.0 * eta)
+
+
+def lubrication_integral(h0, amp, L, n=200000):
+    """int_0^L h(s)^-3 ds for h = h0 (1 + amp cos(2 pi s / L)) (midpoint rule)."""
+    s = (np.arange(n) + 0.5) * L / n
+    return float(np.sum((h0 * (1 + amp * np.cos(2 * np.pi * s / L))) ** -3) * L / n)

@@ -373,3 +373,72 @@ class GP:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- MLP ensemble
+class EnsCfg(_c.Structure):
+    _fields_ = [("members", i32), ("hidden", i32), ("iters", i32), ("lr", d), ("seed", u64)]
+
+
+_sig("hmd_ens_cfg_default", None, P(EnsCfg))
+_sig("ens_fit", i32, vp, P(d), P(d), i32, P(EnsCfg), P(vp))
+_sig("ens_predict", i32, vp, P(d), i32, P(d), P(d))
+_sig("ens_loss", i32, vp, P(d))
+_sig("ens_grad_init", i32, vp, P(d), P(d), i32, P(EnsCfg), i32, P(d), P(d), P(i32))
+_sig("ens_members", i32, vp)
+_sig("ens_free", None, vp)
+
+
+def ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3, seed=0):
+    return EnsCfg(members, hidden, iters, lr, seed)
+
+
+class Ensemble:
+    """ens_*: MLP deep ensemble trained and evaluated on the device."""
+
+    def __init__(self, ctx: Context, X, y, cfg: EnsCfg = None):
+        self.ctx = ctx
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 2)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        self.cfg = cfg or ens_cfg()
+        self._h = vp()
+        ctx.check(_lib.ens_fit(ctx.handle, _ptr(X), _ptr(y), len(y), _c.byref(self.cfg), _c.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def predict(self, Xs):
+        Xs = np.ascontiguousarray(Xs, dtype=np.float64).reshape(-1, 2)
+        m = len(Xs)
+        mean, std = np.zeros(m), np.zeros(m)
+        self.ctx.check(_lib.ens_predict(self._h, _ptr(Xs), m, _ptr(mean), _ptr(std)))
+        return mean, std
+
+    def losses(self):
+        out = np.zeros(self.cfg.members)
+        self.ctx.check(_lib.ens_loss(self._h, _ptr(out)))
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.ens_free(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ens_grad_init(ctx: Context, X, y, cfg: EnsCfg, member: int):
+    """(initial parameters, FP32 gradient of the MSE at them) for one member."""
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 2)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    P_ = cfg.hidden * cfg.hidden + 5 * cfg.hidden + 1
+    th, g = np.zeros(P_), np.zeros(P_)
+    n = i32()
+    ctx.check(_lib.ens_grad_init(ctx.handle, _ptr(X), _ptr(y), len(y), _c.byref(cfg), member, _ptr(th), _ptr(g),
+                                 _c.byref(n)))
+    return th, g

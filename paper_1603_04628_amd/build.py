@@ -31,6 +31,7 @@ SOURCES = [
     ("md_engine.hip", "hip"),
     ("abi.cpp", "hip"),
     ("gp.hip", "hip"),
+    ("ens.hip", "hip"),
     ("pending.cpp", "host"),
 ]
 

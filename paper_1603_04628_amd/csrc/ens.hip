@@ -1,0 +1,440 @@
+// ens.hip -- MLP deep ensemble on the device (a learned surrogate beside the
+// paper's GP): members of 2 -> H -> H -> 1 tanh networks, FP32 weights and
+// accumulation, trained full-batch on the mean squared error with Adam.
+//
+// Training runs every iteration of every member in one launch: one workgroup
+// per member keeps its parameters in LDS, each thread owns a fixed slice of
+// the parameters (their gradient sums and Adam moments stay in registers),
+// and the batch streams through LDS in chunks of CHUNK samples (forward,
+// back-propagation, per-parameter gradient sums).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "engine.h"
+
+struct hmd_ens {
+  hmd_ctx* ctx = nullptr;
+  hmd_ens_cfg cfg{};
+  int P = 0;                 // parameters per member
+  double mu[2] = {0, 0}, sd[2] = {1, 1}, s_q = 1.0;
+  float* dparams = nullptr;  // members x P
+  std::vector<double> loss;  // final training loss per member
+};
+
+namespace hmd {
+namespace {
+
+constexpr int ENS_TPB = 256;
+constexpr int CHUNK = 32;
+constexpr int MAXH = 64;
+constexpr int MAXOWN = (MAXH * MAXH + 5 * MAXH + 1 + ENS_TPB - 1) / ENS_TPB;
+
+inline int nparams(int H) { return H * H + 5 * H + 1; }
+
+// Which tensor a flat parameter index belongs to, and its (row, col).
+struct Slot {
+  int kind, o, i;  // kind: 0 W1, 1 b1, 2 W2, 3 b2, 4 W3, 5 b3, -1 none
+};
+
+__device__ __forceinline__ Slot decode(int p, int H) {
+  Slot s{-1, 0, 0};
+  if (p < 2 * H) s = Slot{0, p / 2, p % 2};
+  else if (p < 3 * H) s = Slot{1, p - 2 * H, 0};
+  else if (p < 3 * H + H * H) s = Slot{2, (p - 3 * H) / H, (p - 3 * H) % H};
+  else if (p < 4 * H + H * H) s = Slot{3, p - 3 * H - H * H, 0};
+  else if (p < 5 * H + H * H) s = Slot{4, p - 4 * H - H * H, 0};
+  else if (p == 5 * H + H * H) s = Slot{5, 0, 0};
+  return s;
+}
+
+// mode 0: train `iters` Adam steps and write the parameters back;
+// mode 1: write the gradient at the given parameters (no update).
+__global__ __launch_bounds__(ENS_TPB) void k_ens_train(int N, int H, int iters, float lr, const float* __restrict__ Xs,
+                                                       const float* __restrict__ ys, float* __restrict__ params,
+                                                       float* __restrict__ grad_out, float* __restrict__ loss_out,
+                                                       int mode) {
+  extern __shared__ float lds[];
+  const int P = H * H + 5 * H + 1;
+  float* th = lds;                   // P
+  float* x = th + P;                 // CHUNK x 2
+  float* h1 = x + 2 * CHUNK;         // CHUNK x H
+  float* h2 = h1 + CHUNK * H;        // CHUNK x H
+  float* dz2 = h2 + CHUNK * H;       // CHUNK x H
+  float* dz1 = dz2 + CHUNK * H;      // CHUNK x H
+  float* dout = dz1 + CHUNK * H;     // CHUNK
+  float* red = dout + CHUNK;         // ENS_TPB
+  float* W1 = th;
+  float* b1 = W1 + 2 * H;
+  float* W2 = b1 + H;
+  float* b2 = W2 + H * H;
+  float* W3 = b2 + H;
+  float* b3 = W3 + H;
+
+  const int tid = threadIdx.x;
+  float* my = params + size_t(blockIdx.x) * P;
+  for (int p = tid; p < P; p += ENS_TPB) th[p] = my[p];
+  float g[MAXOWN], m[MAXOWN], v[MAXOWN];
+  Slot sl[MAXOWN];
+#pragma unroll
+  for (int k = 0; k < MAXOWN; ++k) {
+    g[k] = m[k] = v[k] = 0.f;
+    sl[k] = decode(tid + k * ENS_TPB, H);
+  }
+  __syncthreads();
+  const float invN = 1.0f / float(N);
+  double b1t = 1.0, b2t = 1.0;
+  const int total = mode == 1 ? 1 : iters;
+  float last_loss = 0.f;
+  for (int it = 1; it <= total; ++it) {
+#pragma unroll
+    for (int k = 0; k < MAXOWN; ++k) g[k] = 0.f;
+    float lsum = 0.f;
+    for (int c0 = 0; c0 < N; c0 += CHUNK) {
+      const int nc = min(CHUNK, N - c0);
+      for (int e = tid; e < 2 * nc; e += ENS_TPB) x[e] = Xs[2 * c0 + e];
+      __syncthreads();
+      for (int e = tid; e < nc * H; e += ENS_TPB) {
+        const int s = e / H, o = e % H;
+        h1[e] = tanhf(W1[2 * o] * x[2 * s] + W1[2 * o + 1] * x[2 * s + 1] + b1[o]);
+      }
+      __syncthreads();
+      for (int e = tid; e < nc * H; e += ENS_TPB) {
+        const int s = e / H, o = e % H;
+        float a = b2[o];
+        const float* w = W2 + o * H;
+        const float* hh = h1 + s * H;
+        for (int i = 0; i < H; ++i) a += w[i] * hh[i];
+        h2[e] = tanhf(a);
+      }
+      __syncthreads();
+      if (tid < nc) {
+        float a = b3[0];
+        const float* hh = h2 + tid * H;
+        for (int o = 0; o < H; ++o) a += W3[o] * hh[o];
+        const float r = a - ys[c0 + tid];
+        lsum += r * r;
+        dout[tid] = 2.0f * r * invN;
+      }
+      __syncthreads();
+      for (int e = tid; e < nc * H; e += ENS_TPB) {
+        const int s = e / H, o = e % H;
+        const float t = h2[e];
+        dz2[e] = dout[s] * W3[o] * (1.0f - t * t);
+      }
+      __syncthreads();
+      for (int e = tid; e < nc * H; e += ENS_TPB) {
+        const int s = e / H, i = e % H;
+        float a = 0.f;
+        const float* dz = dz2 + s * H;
+        for (int o = 0; o < H; ++o) a += dz[o] * W2[o * H + i];
+        const float t = h1[e];
+        dz1[e] = a * (1.0f - t * t);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < MAXOWN; ++k) {
+        const Slot q = sl[k];
+        float a = 0.f;
+        switch (q.kind) {
+          case 0: for (int s = 0; s < nc; ++s) a += dz1[s * H + q.o] * x[2 * s + q.i]; break;
+          case 1: for (int s = 0; s < nc; ++s) a += dz1[s * H + q.o]; break;
+          case 2: for (int s = 0; s < nc; ++s) a += dz2[s * H + q.o] * h1[s * H + q.i]; break;
+          case 3: for (int s = 0; s < nc; ++s) a += dz2[s * H + q.o]; break;
+          case 4: for (int s = 0; s < nc; ++s) a += dout[s] * h2[s * H + q.o]; break;
+          case 5: for (int s = 0; s < nc; ++s) a += dout[s]; break;
+          default: break;
+        }
+        g[k] += a;
+      }
+      __syncthreads();
+    }
+    // loss of this iteration (before its update)
+    red[tid] = lsum;
+    __syncthreads();
+    for (int o = ENS_TPB / 2; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    last_loss = red[0] * invN;
+    __syncthreads();
+    if (mode == 1) break;
+    // Adam (Kingma & Ba 2015), beta = (0.9, 0.999), eps = 1e-8
+    b1t *= 0.9;
+    b2t *= 0.999;
+    const float c1 = float(1.0 / (1.0 - b1t)), c2 = float(1.0 / (1.0 - b2t));
+#pragma unroll
+    for (int k = 0; k < MAXOWN; ++k) {
+      const int p = tid + k * ENS_TPB;
+      if (p < P) {
+        m[k] = 0.9f * m[k] + 0.1f * g[k];
+        v[k] = 0.999f * v[k] + 0.001f * g[k] * g[k];
+        th[p] -= lr * (m[k] * c1) / (sqrtf(v[k] * c2) + 1e-8f);
+      }
+    }
+    __syncthreads();
+  }
+  if (mode == 1) {
+#pragma unroll
+    for (int k = 0; k < MAXOWN; ++k) {
+      const int p = tid + k * ENS_TPB;
+      if (p < P) grad_out[size_t(blockIdx.x) * P + p] = g[k];
+    }
+  } else {
+    for (int p = tid; p < P; p += ENS_TPB) my[p] = th[p];
+  }
+  if (tid == 0) loss_out[blockIdx.x] = last_loss;
+}
+
+// One thread per query: every member's output (standardised inputs in,
+// scaled output out), then the ensemble mean and sample standard deviation.
+__global__ __launch_bounds__(128) void k_ens_predict(int m, int members, int H, const float* __restrict__ params,
+                                                     const double* __restrict__ Xq, double mu0, double mu1,
+                                                     double sd0, double sd1, double s_q, double* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const int P = H * H + 5 * H + 1;
+  const float x0 = float((Xq[2 * q] - mu0) / sd0), x1 = float((Xq[2 * q + 1] - mu1) / sd1);
+  double sum = 0.0, sum2 = 0.0;
+  for (int k = 0; k < members; ++k) {
+    const float* th = params + size_t(k) * P;
+    const float* W1 = th;
+    const float* b1 = W1 + 2 * H;
+    const float* W2 = b1 + H;
+    const float* b2 = W2 + H * H;
+    const float* W3 = b2 + H;
+    const float b3 = W3[H];
+    float h1[MAXH];
+    for (int o = 0; o < H; ++o) h1[o] = tanhf(W1[2 * o] * x0 + W1[2 * o + 1] * x1 + b1[o]);
+    float y = b3;
+    for (int o = 0; o < H; ++o) {
+      float a = b2[o];
+      const float* w = W2 + o * H;
+      for (int i = 0; i < H; ++i) a += w[i] * h1[i];
+      y += W3[o] * tanhf(a);
+    }
+    const double yo = double(y) * s_q;
+    sum += yo;
+    sum2 += yo * yo;
+  }
+  const double mean = sum / members;
+  const double var = members > 1 ? (sum2 - members * mean * mean) / (members - 1) : 0.0;
+  out[2 * q] = mean;
+  out[2 * q + 1] = sqrt(var > 0.0 ? var : 0.0);
+}
+
+size_t train_lds_bytes(int H) {
+  return sizeof(float) * (size_t(nparams(H)) + 2 * CHUNK + 4 * size_t(CHUNK) * H + CHUNK + ENS_TPB);
+}
+
+// Glorot-uniform start of one member: Philox4x32-10 keyed by the seed, word
+// p mod 4 of counter (p div 4, member, 2, 0); biases zero.
+void glorot(int H, int member, uint64_t seed, float* out) {
+  const int P = nparams(H);
+  const uint32_t key[2] = {uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32)};
+  std::vector<double> u(P);
+  for (int j = 0; 4 * j < P; ++j) {
+    const uint32_t ctr[4] = {uint32_t(j), uint32_t(member), 2u, 0u};
+    uint32_t r[4];
+    philox4x32_10(ctr, key, r);
+    for (int w = 0; w < 4 && 4 * j + w < P; ++w) u[4 * j + w] = (double(r[w]) + 0.5) / 4294967296.0;
+  }
+  for (int p = 0; p < P; ++p) out[p] = 0.f;
+  const double l1 = std::sqrt(6.0 / (2.0 + H)), l2 = std::sqrt(6.0 / (2.0 * H)), l3 = std::sqrt(6.0 / (H + 1.0));
+  for (int p = 0; p < 2 * H; ++p) out[p] = float(l1 * (2.0 * u[p] - 1.0));
+  for (int p = 3 * H; p < 3 * H + H * H; ++p) out[p] = float(l2 * (2.0 * u[p] - 1.0));
+  for (int p = 4 * H + H * H; p < 5 * H + H * H; ++p) out[p] = float(l3 * (2.0 * u[p] - 1.0));
+}
+
+int check_cfg(hmd_ctx* ctx, const hmd_ens_cfg& c, int n) {
+  if (c.members < 1 || c.members > 64 || c.hidden < 1 || c.hidden > MAXH || c.iters < 0 || !(c.lr > 0.0) || n < 1) {
+    ctx->err = "ens: 1..64 members, 1..64 hidden units, iters >= 0, lr > 0, n >= 1";
+    return HMD_EINVAL;
+  }
+  return HMD_OK;
+}
+
+// Standardise inputs and scale outputs (host, FP64), upload as FP32.
+int stage_data(hmd_ens* e, const double* X, const double* y, int n, float** dX, float** dy) {
+  hmd_ctx* ctx = e->ctx;
+  for (int k = 0; k < 2; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += X[2 * i + k];
+    e->mu[k] = s / n;
+    double v = 0.0;
+    for (int i = 0; i < n; ++i) v += (X[2 * i + k] - e->mu[k]) * (X[2 * i + k] - e->mu[k]);
+    e->sd[k] = std::sqrt(v / n);
+    if (!(e->sd[k] > 0.0)) e->sd[k] = 1.0;
+  }
+  double s2 = 0.0;
+  for (int i = 0; i < n; ++i) s2 += y[i] * y[i];
+  e->s_q = std::sqrt(s2 / n);
+  if (!(e->s_q > 0.0)) e->s_q = 1.0;
+  std::vector<float> xs(2 * size_t(n)), ys(n);
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < 2; ++k) xs[2 * i + k] = float((X[2 * i + k] - e->mu[k]) / e->sd[k]);
+    ys[i] = float(y[i] / e->s_q);
+  }
+  HMD_HIP(ctx, hipMalloc(dX, sizeof(float) * xs.size()));
+  HMD_HIP(ctx, hipMalloc(dy, sizeof(float) * ys.size()));
+  HMD_HIP(ctx, hipMemcpyAsync(*dX, xs.data(), sizeof(float) * xs.size(), hipMemcpyHostToDevice, ctx->stream));
+  HMD_HIP(ctx, hipMemcpyAsync(*dy, ys.data(), sizeof(float) * ys.size(), hipMemcpyHostToDevice, ctx->stream));
+  return HMD_OK;
+}
+
+int run_train(hmd_ens* e, int n, const float* dX, const float* dy, int mode, float* dgrad) {
+  hmd_ctx* ctx = e->ctx;
+  const hmd_ens_cfg& c = e->cfg;
+  const size_t lds = train_lds_bytes(c.hidden);
+  float* dloss = nullptr;
+  HMD_HIP(ctx, hipMalloc(&dloss, sizeof(float) * c.members));
+  hipLaunchKernelGGL(k_ens_train, dim3(c.members), dim3(ENS_TPB), lds, ctx->stream, n, c.hidden, c.iters,
+                     float(c.lr), dX, dy, e->dparams, dgrad, dloss, mode);
+  hipError_t err = hipGetLastError();
+  std::vector<float> loss(c.members);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(loss.data(), dloss, sizeof(float) * c.members, hipMemcpyDeviceToHost, ctx->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(dloss);
+  if (err != hipSuccess) {
+    ctx->err = std::string("ens training: ") + hipGetErrorString(err);
+    return HMD_EDEVICE;
+  }
+  e->loss.assign(loss.begin(), loss.end());
+  return HMD_OK;
+}
+
+int init_params(hmd_ens* e) {
+  hmd_ctx* ctx = e->ctx;
+  const hmd_ens_cfg& c = e->cfg;
+  e->P = nparams(c.hidden);
+  std::vector<float> h(size_t(c.members) * e->P);
+  for (int k = 0; k < c.members; ++k) glorot(c.hidden, k, c.seed, h.data() + size_t(k) * e->P);
+  HMD_HIP(ctx, hipMalloc(&e->dparams, sizeof(float) * h.size()));
+  HMD_HIP(ctx, hipMemcpyAsync(e->dparams, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, ctx->stream));
+  return HMD_OK;
+}
+
+}  // namespace
+}  // namespace hmd
+
+using namespace hmd;
+
+extern "C" {
+
+void hmd_ens_cfg_default(hmd_ens_cfg* c) {
+  if (!c) return;
+  c->members = 5;
+  c->hidden = 64;
+  c->iters = 5000;
+  c->lr = 1e-3;
+  c->seed = 0;
+}
+
+int ens_fit(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg, hmd_ens** out) {
+  if (!ctx || !X || !y || !out) return HMD_EINVAL;
+  hmd_ens_cfg c;
+  if (cfg) c = *cfg;
+  else hmd_ens_cfg_default(&c);
+  int rc = check_cfg(ctx, c, n);
+  if (rc != HMD_OK) return rc;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  auto* e = new hmd_ens();
+  e->ctx = ctx;
+  e->cfg = c;
+  float *dX = nullptr, *dy = nullptr;
+  if ((rc = init_params(e)) == HMD_OK && (rc = stage_data(e, X, y, n, &dX, &dy)) == HMD_OK)
+    rc = run_train(e, n, dX, dy, 0, nullptr);
+  if (dX) (void)hipFree(dX);
+  if (dy) (void)hipFree(dy);
+  if (rc != HMD_OK) {
+    ens_free(e);
+    return rc;
+  }
+  *out = e;
+  return HMD_OK;
+}
+
+int ens_predict(hmd_ens* e, const double* Xs, int m, double* mean, double* std) {
+  if (!e || m < 0 || (m > 0 && (!Xs || !mean || !std))) return HMD_EINVAL;
+  if (m == 0) return HMD_OK;
+  hmd_ctx* ctx = e->ctx;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  double *dq = nullptr, *dout = nullptr;
+  HMD_HIP(ctx, hipMalloc(&dq, sizeof(double) * 2 * m));
+  hipError_t err = hipMalloc(&dout, sizeof(double) * 2 * m);
+  std::vector<double> res(2 * size_t(m));
+  if (err == hipSuccess) err = hipMemcpyAsync(dq, Xs, sizeof(double) * 2 * m, hipMemcpyHostToDevice, ctx->stream);
+  if (err == hipSuccess) {
+    hipLaunchKernelGGL(k_ens_predict, dim3((m + 127) / 128), dim3(128), 0, ctx->stream, m, e->cfg.members,
+                       e->cfg.hidden, e->dparams, dq, e->mu[0], e->mu[1], e->sd[0], e->sd[1], e->s_q, dout);
+    err = hipGetLastError();
+  }
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(res.data(), dout, sizeof(double) * res.size(), hipMemcpyDeviceToHost, ctx->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(dq);
+  if (dout) (void)hipFree(dout);
+  if (err != hipSuccess) {
+    ctx->err = std::string("ens_predict: ") + hipGetErrorString(err);
+    return HMD_EDEVICE;
+  }
+  for (int q = 0; q < m; ++q) {
+    mean[q] = res[2 * q];
+    std[q] = res[2 * q + 1];
+  }
+  return HMD_OK;
+}
+
+int ens_loss(const hmd_ens* e, double* loss) {
+  if (!e || !loss) return HMD_EINVAL;
+  for (size_t k = 0; k < e->loss.size(); ++k) loss[k] = e->loss[k];
+  return HMD_OK;
+}
+
+int ens_grad_init(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg, int member,
+                  double* params, double* grad, int* n_params) {
+  if (!ctx || !X || !y) return HMD_EINVAL;
+  hmd_ens_cfg c;
+  if (cfg) c = *cfg;
+  else hmd_ens_cfg_default(&c);
+  int rc = check_cfg(ctx, c, n);
+  if (rc != HMD_OK) return rc;
+  if (member < 0 || member >= c.members) return HMD_EINVAL;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  hmd_ens e;
+  e.ctx = ctx;
+  e.cfg = c;
+  float *dX = nullptr, *dy = nullptr, *dg = nullptr;
+  if ((rc = init_params(&e)) == HMD_OK && (rc = stage_data(&e, X, y, n, &dX, &dy)) == HMD_OK) {
+    if (hipMalloc(&dg, sizeof(float) * size_t(c.members) * e.P) != hipSuccess) rc = HMD_ENOMEM;
+    else rc = run_train(&e, n, dX, dy, 1, dg);
+  }
+  if (rc == HMD_OK) {
+    std::vector<float> hp(e.P), hg(e.P);
+    if (hipMemcpy(hp.data(), e.dparams + size_t(member) * e.P, sizeof(float) * e.P, hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(hg.data(), dg + size_t(member) * e.P, sizeof(float) * e.P, hipMemcpyDeviceToHost) != hipSuccess)
+      rc = HMD_EDEVICE;
+    for (int p = 0; p < e.P; ++p) {
+      if (params) params[p] = hp[p];
+      if (grad) grad[p] = hg[p];
+    }
+    if (n_params) *n_params = e.P;
+  }
+  for (void* p : {(void*)dX, (void*)dy, (void*)dg, (void*)e.dparams})
+    if (p) (void)hipFree(p);
+  return rc;
+}
+
+int ens_members(const hmd_ens* e) { return e ? e->cfg.members : 0; }
+
+void ens_free(hmd_ens* e) {
+  if (!e) return;
+  if (e->dparams) (void)hipFree(e->dparams);
+  delete e;
+}
+
+}  // extern "C"

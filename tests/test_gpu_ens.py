@@ -1,0 +1,68 @@
+"""Parity of the device MLP ensemble (FP32) with the FP64 oracle: identical
+start, gradients within 1e-4 relative, trained predictions close."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+hmd = pytest.importorskip("paper_1603_04628_amd")
+from paper_1603_04628_amd import binding as B  # noqa: E402
+from oracle import mlp  # noqa: E402
+
+
+def data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = np.column_stack([rng.uniform(4, 20, n), rng.uniform(0.001, 0.05, n)])
+    y = 0.004 * X[:, 0] ** 2 * X[:, 1] * (1 + 0.1 * np.cos(X[:, 0])) + rng.normal(0, 0.003, n)
+    return X, y
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return hmd.Context()
+
+
+def _oracle_scaled(X, y):
+    mu, sd = X.mean(0), X.std(0)
+    return (X - mu) / sd, y / np.sqrt(np.mean(y ** 2))
+
+
+@pytest.mark.parametrize("n,hidden", [(256, 64), (37, 64), (100, 16)])
+def test_initial_parameters_and_gradients(ctx, n, hidden):
+    X, y = data(n, n)
+    cfg = B.ens_cfg(members=3, hidden=hidden, iters=1)
+    Xs, ys = _oracle_scaled(X, y)
+    for k in range(3):
+        th_g, g_g = B.ens_grad_init(ctx, X, y, cfg, k)
+        th_o = mlp.glorot_init(hidden, k, 0)
+        assert np.array_equal(th_g, th_o.astype(np.float32).astype(np.float64))
+        _, g_o = mlp.loss_and_grad(th_o, Xs, ys, hidden)
+        assert np.linalg.norm(g_g - g_o) <= 1e-4 * np.linalg.norm(g_o)
+
+
+def test_trained_ensemble_tracks_oracle(ctx):
+    X, y = data(256, 3)
+    cfg = B.ens_cfg(members=5, hidden=64, iters=1500, lr=1e-3)
+    e = B.Ensemble(ctx, X, y, cfg)
+    o = mlp.Ensemble(X, y, members=5, hidden=64, iters=1500, lr=1e-3)
+    np.testing.assert_allclose(e.losses(), o.losses, rtol=0.05, atol=1e-6)
+    Xq, yq = data(200, 4)
+    mg, sg = e.predict(Xq)
+    mo, so = o.predict(Xq)
+    rms = np.sqrt(np.mean(y ** 2))
+    assert np.abs(mg - mo).max() <= 0.01 * rms
+    assert np.abs(sg - so).max() <= 0.01 * rms
+    assert np.sqrt(np.mean((mg - yq) ** 2)) < 0.1 * rms
+
+
+def test_single_member_has_zero_spread(ctx):
+    X, y = data(64, 5)
+    e = B.Ensemble(ctx, X, y, B.ens_cfg(members=1, hidden=8, iters=10))
+    _, s = e.predict(X[:5])
+    assert np.all(s == 0.0)
+
+
+def test_bad_configuration_rejected(ctx):
+    X, y = data(16, 6)
+    with pytest.raises(B.HmdError):
+        B.Ensemble(ctx, X, y, B.ens_cfg(hidden=65))

@@ -1,0 +1,100 @@
+"""Pins for the hybrid macro-march oracle (Alg. 1, Eqs. continuityEq and
+momentumEq): conservation, threshold limits, Reynolds-lubrication steady
+state, closed-form lubrication integral.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle.gp import GP, Hyper
+from oracle.hybrid import Hybrid, HybridCfg, lubrication_integral, poiseuille_flux
+
+
+class Exact:
+    """A surrogate that knows the continuum law exactly (zero spread)."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+
+    def predict(self, X):
+        return poiseuille_flux(X[:, 0], X[:, 1], **self.kw), np.zeros(len(X))
+
+    def append(self, x, y, se):
+        raise AssertionError("an exact surrogate never falls back")
+
+
+def micro(h, g):
+    q = poiseuille_flux(h, g)
+    return q, np.full(len(q), 1e-3)
+
+
+def test_lubrication_integral_closed_form():
+    # int (1 + a cos t)^-3 over a period = 2 pi (2 + a^2) / (2 (1 - a^2)^(5/2))
+    a = 0.5
+    closed = (2 + a * a) / (2 * (1 - a * a) ** 2.5)
+    assert closed == pytest.approx(2.3094, abs=1e-4)
+    assert lubrication_integral(10.0, a, 2000.0) == pytest.approx(closed * 2000.0 / 1000.0, rel=1e-9)
+
+
+def test_mass_changes_only_by_boundary_fluxes():
+    cfg = HybridCfg(n_sections=50, L=500.0, dt_macro=0.01, tau_rel=1e9)
+    hy = Hybrid(cfg, Exact(), micro, var_is_std=True)
+    for _ in range(20):
+        m0 = hy.mass()
+        hy.step()
+        q = hy.q
+        assert hy.mass() - m0 == pytest.approx(cfg.dt_macro * (q[0] - q[-1]), abs=1e-11 * m0)
+
+
+def test_threshold_above_signal_gives_zero_flow_without_md():
+    # empty database and an absolute threshold above sigma_f (Sec. 3.2): the
+    # prior mean (zero) answers every query and no micro-solve runs
+    cfg = HybridCfg(n_sections=20, L=200.0, dt_macro=0.01, tau_rel=0.0, tau_abs=1.01)
+    hy = Hybrid(cfg, GP(np.zeros((0, 2)), np.zeros(0), None, Hyper()), micro)
+    for _ in range(5):
+        hy.step()
+    assert hy.md_calls == 0 and np.all(hy.q == 0.0)
+
+
+def test_zero_threshold_calls_md_everywhere():
+    cfg = HybridCfg(n_sections=10, L=100.0, dt_macro=0.001, tau_rel=0.0)
+    gp = GP(np.zeros((0, 2)), np.zeros(0), None, Hyper())
+    hy = Hybrid(cfg, gp, micro)
+    for _ in range(3):
+        hy.step()
+    assert hy.md_calls == 30 and np.all(hy.from_md)
+
+
+def _steady_flux(n, L=400.0, h0=10.0, dp=2.0, eta=2.0):
+    cfg = HybridCfg(n_sections=n, L=L, h0=h0, amp=0.5, dp_mean=dp, dp_amp=0.0, c2=2000.0, tau_rel=1e9)
+    # explicit stability: D = c2 rho h^2 / (12 eta) at the widest section
+    D = cfg.c2 * 0.8 * (1.5 * h0) ** 2 / (12 * eta)
+    cfg.dt_macro = 0.4 * (L / n) ** 2 / D
+    hy = Hybrid(cfg, Exact(eta=eta), micro, var_is_std=True)
+    for _ in range(int(30000 * (n / 40) ** 2)):
+        hy.step()
+    return hy.q
+
+
+def test_steady_state_is_reynolds_lubrication():
+    # constant inlet pressure: the march settles to a uniform flux, which
+    # converges at first order in the section spacing to the lubrication
+    # result Q = rho dp / (12 eta int h^-3 ds)
+    q20, q40 = _steady_flux(20), _steady_flux(40)
+    # collocated central differences carry a slowly decaying odd-even mode
+    assert np.std(q40) < 1e-4 * np.mean(q40)
+    Q = 0.8 * 2.0 / (12 * 2.0 * lubrication_integral(10.0, 0.5, 400.0))
+    assert np.mean(q40) == pytest.approx(Q, rel=0.05)
+    assert 2 * np.mean(q40) - np.mean(q20) == pytest.approx(Q, rel=0.005)
+
+
+def test_relative_threshold_rule():
+    class Stub:
+        def predict(self, X):
+            return np.array([1.0, -1.0, 0.0, 2.0]), np.array([0.04, 0.06, 0.0, 0.09]) ** 2
+
+        def append(self, x, y, se):
+            pass
+
+    cfg = HybridCfg(n_sections=4, L=40.0, dt_macro=1e-4, tau_rel=0.05)
+    hy = Hybrid(cfg, Stub(), micro)
+    hy.step()
+    assert hy.from_md.tolist() == [False, True, False, False]
