@@ -74,8 +74,9 @@ void hmd_md_params_default(hmd_md_params* p);
 int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ctx** out);
 void hmd_destroy(hmd_ctx* ctx);
 const char* hmd_last_error(const hmd_ctx* ctx);
-/* Replace the MD parameters used by later calls on this context. */
+/* Replace (or read) the MD parameters used by later calls on this context. */
 int hmd_set_params(hmd_ctx* ctx, const hmd_md_params* params);
+int hmd_get_params(const hmd_ctx* ctx, hmd_md_params* params);
 
 /* ------------------------------------------------------------------------
  * The micro-solve.  A job is one NEMD channel (Sec. 2.1, quasi-steady
@@ -217,36 +218,66 @@ int ens_loss(const hmd_ens* e, double* loss);
 int ens_grad_init(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg,
                   int member, double* params, double* grad, int* n_params);
 int ens_members(const hmd_ens* e);
+/* Online learning: add one training point (kept on the host), and retrain
+ * every member from its initial weights on the whole training set. */
+int ens_append(hmd_ens* e, const double* x, double y);
+int ens_refit(hmd_ens* e);
+int ens_size(const hmd_ens* e);
 void ens_free(hmd_ens* e);
 
 /* ------------------------------------------------------------------------
- * Hybrid macro solve (Alg. 1): 1-D unsteady mass conservation
- * (Eq. continuityEq) on n_sections cross-sections of a channel
- * h(s) = h0 (1 + amp cos(2 pi s / L)); pressure from a linear equation of
- * state p = p_out + c2 (rho - rho_ref); per section the body force of
- * Eq. momentumEq; flux from the surrogate, or from batched MD when the
- * surrogate's standard deviation exceeds tau_rel * |mean|; MD results are
- * appended to the surrogate's database.
+ * Hybrid macro solve (Alg. 1).  Sections i = 0..n-1 at s_i = (i + 1/2) ds,
+ * ds = L / n, of a channel h(s) = h0 (1 + amp cos(2 pi s / L)).  Per macro
+ * step (t = step count):
+ *   p_i = p_out + c2 (rho_i - rho_ref)            (linear equation of state)
+ *   dp/ds_i = (p_{i+1} - p_{i-1}) / (2 ds), ghosts p_{-1} = p_in(t),
+ *             p_n = p_out, p_in(t) = p_out + dp_mean (1 + dp_amp sin(2 pi t / period))
+ *   g_i = -(1/rho_i) dp/ds_i                      (Eq. momentumEq, F_ext = 0)
+ *   surrogate mean and standard deviation at (h_i, g_i); the section falls
+ *   back to the micro-solver when std > max(tau_rel |mean|, tau_abs)
+ *   (tau_abs alone is the paper's absolute sigma_t); fallback results join
+ *   the surrogate's database (the GP refits at once, the ensemble every
+ *   refit_every new points); every audit_every-th surrogate answer is also
+ *   run and counted as passing when |mean - q_MD| <= 2 SE_MD
+ *   rho_i h_i -= dt_macro (q_{i+1/2} - q_{i-1/2}) / ds  (Eq. continuityEq per
+ *   unit span; faces average the neighbours, boundary faces carry the
+ *   boundary section's flux)
+ * All sections that fall back in one step run as one MD batch.  The MD
+ * protocol is the context's parameters (box, n_equil) with md_sample
+ * sampling steps; seeds count up from `seed`.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int n_sections;
     double h0, amp, L, dt_macro, rho_ref, p_out, dp_mean, dp_amp, period, c2;
-    double tau_rel;
-    int surrogate;    /* 0: GP, 1: MLP ensemble */
-    int audit_every;  /* every k-th surrogate answer is re-run with MD (0: off) */
-    int64_t md_sample;/* sampling steps of each fallback MD run */
-    int refit_every;  /* ensemble: retrain after this many new MD points */
+    double tau_rel, tau_abs;
+    int surrogate;     /* 0: GP, 1: MLP ensemble */
+    int audit_every;   /* every k-th surrogate answer is re-run with MD (0: off) */
+    int64_t md_sample; /* sampling steps of each fallback MD run */
+    int refit_every;   /* ensemble: retrain after this many new MD points */
+    uint64_t seed;     /* first MD seed */
 } hmd_hybrid_cfg;
 typedef struct {
-    int64_t steps, md_calls, audited, audit_pass, queries;
-    double wall_s, md_wall_s, md_atom_steps;
+    int64_t steps, md_calls, audited, audit_pass, queries, md_failed;
+    double wall_s, md_wall_s, md_atom_steps, surrogate_wall_s;
 } hmd_hybrid_stats;
 
+/* A replacement micro-solver: given n (h, g) pairs, write the mean flux and
+ * its standard error; return 0 on success.  Used instead of batched MD when
+ * set (coupling another solver, or a known law in tests). */
+typedef int (*hmd_micro_fn)(void* user, int n, const double* h, const double* g, double* q, double* se);
+
 void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c);
+/* Exactly one of gp / ens matches cfg->surrogate; the hybrid borrows it
+ * (the caller frees it after hybrid_free).  rho starts at rho_ref. */
 int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out);
+int hybrid_set_micro(hmd_hybrid* hy, hmd_micro_fn fn, void* user);
+/* Overwrite the density of every section (n_sections doubles). */
+int hybrid_set_rho(hmd_hybrid* hy, const double* rho);
+/* One macro step; out (nullable) receives the cumulative statistics. */
 int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out);
-/* rho, q, q_std (n_sections doubles), from_md (n_sections bytes). */
-int hybrid_get(hmd_hybrid* hy, double* rho, double* q, double* q_std, uint8_t* from_md);
+/* rho, q, q_std, g (n_sections doubles), from_md (n_sections bytes); each
+ * nullable. */
+int hybrid_get(hmd_hybrid* hy, double* rho, double* q, double* q_std, double* g, uint8_t* from_md);
 void hybrid_free(hmd_hybrid* hy);
 
 #ifdef __cplusplus

@@ -32,7 +32,7 @@ SOURCES = [
     ("abi.cpp", "hip"),
     ("gp.hip", "hip"),
     ("ens.hip", "hip"),
-    ("pending.cpp", "host"),
+    ("hybrid.cpp", "host"),
 ]
 
 

@@ -83,6 +83,12 @@ void hmd_destroy(hmd_ctx* ctx) {
 
 const char* hmd_last_error(const hmd_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+int hmd_get_params(const hmd_ctx* ctx, hmd_md_params* params) {
+  if (!ctx || !params) return HMD_EINVAL;
+  *params = ctx->params;
+  return HMD_OK;
+}
+
 int hmd_set_params(hmd_ctx* ctx, const hmd_md_params* params) {
   if (!ctx || !params) return HMD_EINVAL;
   ctx->params = *params;

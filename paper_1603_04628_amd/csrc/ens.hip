@@ -22,6 +22,7 @@ struct hmd_ens {
   double mu[2] = {0, 0}, sd[2] = {1, 1}, s_q = 1.0;
   float* dparams = nullptr;  // members x P
   std::vector<double> loss;  // final training loss per member
+  std::vector<double> X, y;  // training set (host copy, for refits)
 };
 
 namespace hmd {
@@ -344,11 +345,9 @@ int ens_fit(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens
   auto* e = new hmd_ens();
   e->ctx = ctx;
   e->cfg = c;
-  float *dX = nullptr, *dy = nullptr;
-  if ((rc = init_params(e)) == HMD_OK && (rc = stage_data(e, X, y, n, &dX, &dy)) == HMD_OK)
-    rc = run_train(e, n, dX, dy, 0, nullptr);
-  if (dX) (void)hipFree(dX);
-  if (dy) (void)hipFree(dy);
+  e->X.assign(X, X + 2 * size_t(n));
+  e->y.assign(y, y + n);
+  rc = ens_refit(e);
   if (rc != HMD_OK) {
     ens_free(e);
     return rc;
@@ -356,6 +355,35 @@ int ens_fit(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens
   *out = e;
   return HMD_OK;
 }
+
+int ens_append(hmd_ens* e, const double* x, double y) {
+  if (!e || !x) return HMD_EINVAL;
+  e->X.push_back(x[0]);
+  e->X.push_back(x[1]);
+  e->y.push_back(y);
+  return HMD_OK;
+}
+
+int ens_refit(hmd_ens* e) {
+  if (!e) return HMD_EINVAL;
+  hmd_ctx* ctx = e->ctx;
+  const int n = int(e->y.size());
+  int rc = check_cfg(ctx, e->cfg, n);
+  if (rc != HMD_OK) return rc;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  if (e->dparams) {
+    (void)hipFree(e->dparams);
+    e->dparams = nullptr;
+  }
+  float *dX = nullptr, *dy = nullptr;
+  if ((rc = init_params(e)) == HMD_OK && (rc = stage_data(e, e->X.data(), e->y.data(), n, &dX, &dy)) == HMD_OK)
+    rc = run_train(e, n, dX, dy, 0, nullptr);
+  if (dX) (void)hipFree(dX);
+  if (dy) (void)hipFree(dy);
+  return rc;
+}
+
+int ens_size(const hmd_ens* e) { return e ? int(e->y.size()) : 0; }
 
 int ens_predict(hmd_ens* e, const double* Xs, int m, double* mean, double* std) {
   if (!e || m < 0 || (m > 0 && (!Xs || !mean || !std))) return HMD_EINVAL;

@@ -1,0 +1,261 @@
+// hybrid.cpp -- the macro march of the hybrid scheme (paper Alg. 1): 1-D
+// mass conservation over the channel sections, body force from the pressure
+// gradient, flux from the surrogate (device GP or MLP ensemble) or, where the
+// surrogate is too uncertain, from one batched MD launch for every such
+// section; new MD results grow the surrogate's database.
+//
+// Host code (the section arrays are a few hundred doubles); built without
+// floating-point contraction so the march rounds as written.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hmd.h"
+
+struct hmd_ctx;  // opaque here
+
+struct hmd_hybrid {
+  hmd_ctx* ctx = nullptr;
+  hmd_hybrid_cfg cfg{};
+  hmd_gp* gp = nullptr;
+  hmd_ens* ens = nullptr;
+  hmd_micro_fn micro = nullptr;
+  void* micro_user = nullptr;
+  double ds = 0.0;
+  std::vector<double> h, rho, q, q_std, g;
+  std::vector<uint8_t> from_md;
+  int64_t step_no = 0, answers = 0, pending_refit = 0;
+  uint64_t next_seed = 0;
+  hmd_hybrid_stats st{};
+};
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586;
+
+using clock_t_ = std::chrono::steady_clock;
+
+double seconds_since(clock_t_::time_point t0) {
+  return std::chrono::duration<double>(clock_t_::now() - t0).count();
+}
+
+// Fluxes for the listed sections from the micro-solver (callback or batched MD).
+int solve_micro(hmd_hybrid* hy, const std::vector<int>& idx, std::vector<double>& qm, std::vector<double>& se,
+                std::vector<int>& ok) {
+  const int n = int(idx.size());
+  qm.assign(n, 0.0);
+  se.assign(n, 0.0);
+  ok.assign(n, 1);
+  std::vector<double> hh(n), gg(n);
+  for (int k = 0; k < n; ++k) {
+    hh[k] = hy->h[idx[k]];
+    gg[k] = hy->g[idx[k]];
+  }
+  const auto t0 = clock_t_::now();
+  if (hy->micro) {
+    const int rc = hy->micro(hy->micro_user, n, hh.data(), gg.data(), qm.data(), se.data());
+    hy->st.md_wall_s += seconds_since(t0);
+    return rc == 0 ? HMD_OK : HMD_EINVAL;
+  }
+  std::vector<hmd_md_job> jobs(n);
+  for (int k = 0; k < n; ++k) jobs[k] = hmd_md_job{hh[k], gg[k], hy->next_seed++, hy->cfg.md_sample};
+  std::vector<hmd_md_result> res(n);
+  const int rc = md_flux_batch(hy->ctx, jobs.data(), n, res.data());
+  hy->st.md_wall_s += seconds_since(t0);
+  if (rc != HMD_OK) return rc;
+  hmd_md_params P;
+  hmd_get_params(hy->ctx, &P);
+  for (int k = 0; k < n; ++k) {
+    qm[k] = res[k].flux;
+    se[k] = res[k].flux_se;
+    ok[k] = res[k].status == HMD_OK;
+    hy->st.md_failed += ok[k] ? 0 : 1;
+    hy->st.md_atom_steps += double(res[k].n_fluid) * double(P.n_equil + hy->cfg.md_sample);
+  }
+  return HMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c) {
+  if (!c) return;
+  c->n_sections = 200;
+  c->h0 = 10.0;
+  c->amp = 0.5;
+  c->L = 2000.0;
+  c->dt_macro = 0.02;
+  c->rho_ref = 0.8;
+  c->p_out = 0.0;
+  c->dp_mean = 10.0;
+  c->dp_amp = 0.3;
+  c->period = 250.0;
+  c->c2 = 200.0;
+  c->tau_rel = 0.05;
+  c->tau_abs = 0.0;
+  c->surrogate = 0;
+  c->audit_every = 0;
+  c->md_sample = 4000;
+  c->refit_every = 16;
+  c->seed = 1000000;
+}
+
+int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out) {
+  if (!ctx || !cfg || !out) return HMD_EINVAL;
+  const hmd_hybrid_cfg& c = *cfg;
+  if (c.n_sections < 2 || !(c.L > 0.0) || !(c.h0 > 0.0) || !(c.dt_macro > 0.0) || !(c.rho_ref > 0.0) ||
+      c.tau_rel < 0.0 || c.tau_abs < 0.0 || (c.surrogate == 0 && !gp) || (c.surrogate == 1 && !ens) ||
+      c.surrogate < 0 || c.surrogate > 1 || c.md_sample < 0 || c.refit_every < 1 || !(c.period > 0.0))
+    return HMD_EINVAL;
+  auto* hy = new hmd_hybrid();
+  hy->ctx = ctx;
+  hy->cfg = c;
+  hy->gp = gp;
+  hy->ens = ens;
+  hy->next_seed = c.seed;
+  const int n = c.n_sections;
+  hy->ds = c.L / double(n);
+  hy->h.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const double s = (double(i) + 0.5) * hy->ds;
+    hy->h[i] = c.h0 * (1.0 + c.amp * std::cos(kTwoPi * s / c.L));
+  }
+  hy->rho.assign(n, c.rho_ref);
+  hy->q.assign(n, 0.0);
+  hy->q_std.assign(n, 0.0);
+  hy->g.assign(n, 0.0);
+  hy->from_md.assign(n, 0);
+  *out = hy;
+  return HMD_OK;
+}
+
+int hybrid_set_micro(hmd_hybrid* hy, hmd_micro_fn fn, void* user) {
+  if (!hy) return HMD_EINVAL;
+  hy->micro = fn;
+  hy->micro_user = user;
+  return HMD_OK;
+}
+
+int hybrid_set_rho(hmd_hybrid* hy, const double* rho) {
+  if (!hy || !rho) return HMD_EINVAL;
+  for (int i = 0; i < hy->cfg.n_sections; ++i)
+    if (!(rho[i] > 0.0)) return HMD_EINVAL;
+  hy->rho.assign(rho, rho + hy->cfg.n_sections);
+  return HMD_OK;
+}
+
+int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
+  if (!hy) return HMD_EINVAL;
+  const auto t0 = clock_t_::now();
+  const hmd_hybrid_cfg& c = hy->cfg;
+  const int n = c.n_sections;
+  // pressure, central-difference gradient with ghost pressures, body force
+  std::vector<double> p(n);
+  for (int i = 0; i < n; ++i) p[i] = c.p_out + c.c2 * (hy->rho[i] - c.rho_ref);
+  const double p_in = c.p_out + c.dp_mean * (1.0 + c.dp_amp * std::sin(kTwoPi * double(hy->step_no) / c.period));
+  for (int i = 0; i < n; ++i) {
+    const double pl = i > 0 ? p[i - 1] : p_in;
+    const double pr = i < n - 1 ? p[i + 1] : c.p_out;
+    const double dpds = (pr - pl) / (2.0 * hy->ds);
+    hy->g[i] = -dpds / hy->rho[i];
+  }
+  // surrogate query for every section
+  std::vector<double> X(2 * size_t(n)), mean(n), second(n), sd(n);
+  for (int i = 0; i < n; ++i) {
+    X[2 * i] = hy->h[i];
+    X[2 * i + 1] = hy->g[i];
+  }
+  const auto ts = clock_t_::now();
+  int rc = c.surrogate == 0 ? gp_predict(hy->gp, X.data(), n, mean.data(), second.data())
+                            : ens_predict(hy->ens, X.data(), n, mean.data(), second.data());
+  hy->st.surrogate_wall_s += seconds_since(ts);
+  if (rc != HMD_OK) return rc;
+  for (int i = 0; i < n; ++i) sd[i] = c.surrogate == 0 ? std::sqrt(second[i] > 0.0 ? second[i] : 0.0) : second[i];
+  hy->st.queries += n;
+  // threshold test and audits
+  std::vector<int> run;
+  std::vector<uint8_t> flag(n, 0), audit(n, 0);
+  for (int i = 0; i < n; ++i) {
+    const double thr = std::fmax(c.tau_rel * std::fabs(mean[i]), c.tau_abs);
+    flag[i] = sd[i] > thr;
+  }
+  for (int i = 0; i < n; ++i)
+    if (!flag[i] && c.audit_every > 0) {
+      hy->answers += 1;
+      if (hy->answers % c.audit_every == 0) audit[i] = 1;
+    }
+  for (int i = 0; i < n; ++i)
+    if (flag[i] || audit[i]) run.push_back(i);
+  std::vector<double> qv(mean);
+  if (!run.empty()) {
+    std::vector<double> qm, se;
+    std::vector<int> ok;
+    rc = solve_micro(hy, run, qm, se, ok);
+    if (rc != HMD_OK) return rc;
+    hy->st.md_calls += int64_t(run.size());
+    for (size_t k = 0; k < run.size(); ++k) {
+      const int i = run[k];
+      if (flag[i]) {
+        qv[i] = qm[k];
+      } else {
+        hy->st.audited += 1;
+        hy->st.audit_pass += std::fabs(mean[i] - qm[k]) <= 2.0 * se[k] ? 1 : 0;
+      }
+    }
+    // database growth (runs that failed to converge are left out, Sec. 3.2)
+    const auto tg = clock_t_::now();
+    for (size_t k = 0; k < run.size(); ++k) {
+      const int i = run[k];
+      if (!flag[i] || !ok[k]) continue;
+      const double x[2] = {hy->h[i], hy->g[i]};
+      if (c.surrogate == 0) {
+        rc = gp_append(hy->gp, x, qm[k], se[k]);
+      } else {
+        rc = ens_append(hy->ens, x, qm[k]);
+        hy->pending_refit += 1;
+      }
+      if (rc != HMD_OK) return rc;
+    }
+    if (c.surrogate == 1 && hy->pending_refit >= c.refit_every) {
+      rc = ens_refit(hy->ens);
+      if (rc != HMD_OK) return rc;
+      hy->pending_refit = 0;
+    }
+    hy->st.surrogate_wall_s += seconds_since(tg);
+  }
+  // conservative update of rho h
+  std::vector<double> flux(n + 1);
+  flux[0] = qv[0];
+  flux[n] = qv[n - 1];
+  for (int i = 0; i + 1 < n; ++i) flux[i + 1] = 0.5 * (qv[i] + qv[i + 1]);
+  for (int i = 0; i < n; ++i) {
+    const double m = hy->rho[i] * hy->h[i] - c.dt_macro * (flux[i + 1] - flux[i]) / hy->ds;
+    hy->rho[i] = m / hy->h[i];
+  }
+  hy->q = qv;
+  hy->q_std = sd;
+  hy->from_md = flag;
+  hy->step_no += 1;
+  hy->st.steps = hy->step_no;
+  hy->st.wall_s += seconds_since(t0);
+  if (out) *out = hy->st;
+  return HMD_OK;
+}
+
+int hybrid_get(hmd_hybrid* hy, double* rho, double* q, double* q_std, double* g, uint8_t* from_md) {
+  if (!hy) return HMD_EINVAL;
+  const size_t n = size_t(hy->cfg.n_sections);
+  if (rho) std::memcpy(rho, hy->rho.data(), 8 * n);
+  if (q) std::memcpy(q, hy->q.data(), 8 * n);
+  if (q_std) std::memcpy(q_std, hy->q_std.data(), 8 * n);
+  if (g) std::memcpy(g, hy->g.data(), 8 * n);
+  if (from_md) std::memcpy(from_md, hy->from_md.data(), n);
+  return HMD_OK;
+}
+
+void hybrid_free(hmd_hybrid* hy) { delete hy; }
+
+}  // extern "C"

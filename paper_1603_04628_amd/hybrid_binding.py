@@ -1,0 +1,102 @@
+"""ctypes binding of the hybrid macro march (hybrid_* in include/hmd.h)."""
+import ctypes as _c
+
+import numpy as np
+
+from .binding import Context, HmdError, _lib, _ptr, _sig, d, i32, i64, u64, u8, vp
+
+P = _c.POINTER
+
+
+class HybridCfg(_c.Structure):
+    _fields_ = [("n_sections", i32), ("h0", d), ("amp", d), ("L", d), ("dt_macro", d), ("rho_ref", d),
+                ("p_out", d), ("dp_mean", d), ("dp_amp", d), ("period", d), ("c2", d), ("tau_rel", d),
+                ("tau_abs", d), ("surrogate", i32), ("audit_every", i32), ("md_sample", i64),
+                ("refit_every", i32), ("seed", u64)]
+
+
+class HybridStats(_c.Structure):
+    _fields_ = [("steps", i64), ("md_calls", i64), ("audited", i64), ("audit_pass", i64), ("queries", i64),
+                ("md_failed", i64), ("wall_s", d), ("md_wall_s", d), ("md_atom_steps", d),
+                ("surrogate_wall_s", d)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+MICRO_FN = _c.CFUNCTYPE(i32, vp, i32, P(d), P(d), P(d), P(d))
+
+_sig("hmd_hybrid_cfg_default", None, P(HybridCfg))
+_sig("hybrid_create", i32, vp, P(HybridCfg), vp, vp, P(vp))
+_sig("hybrid_set_micro", i32, vp, MICRO_FN, vp)
+_sig("hybrid_set_rho", i32, vp, P(d))
+_sig("hybrid_step", i32, vp, P(HybridStats))
+_sig("hybrid_get", i32, vp, P(d), P(d), P(d), P(d), P(u8))
+_sig("hybrid_free", None, vp)
+
+
+def hybrid_cfg(**kw):
+    c = HybridCfg()
+    _lib.hmd_hybrid_cfg_default(_c.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+class Hybrid:
+    """hybrid_*: macro march with the device GP or ensemble as surrogate.
+
+    `micro`, when given, is a Python callable (h, g) -> (q, se) used instead
+    of batched MD (kept alive by this object)."""
+
+    def __init__(self, ctx: Context, cfg: HybridCfg, gp=None, ens=None, micro=None):
+        self.ctx = ctx
+        self.cfg = cfg
+        self.n = cfg.n_sections
+        self._h = vp()
+        ctx.check(_lib.hybrid_create(ctx.handle, _c.byref(cfg), gp.handle if gp is not None else None,
+                                     ens.handle if ens is not None else None, _c.byref(self._h)))
+        self._keep = (gp, ens)
+        self._cb = None
+        if micro is not None:
+            def cb(user, n, h, g, q, se):
+                try:
+                    hh = np.ctypeslib.as_array(h, (n,)).copy()
+                    gg = np.ctypeslib.as_array(g, (n,)).copy()
+                    qq, ss = micro(hh, gg)
+                    np.ctypeslib.as_array(q, (n,))[:] = qq
+                    np.ctypeslib.as_array(se, (n,))[:] = ss
+                    return 0
+                except Exception:
+                    return 1
+            self._cb = MICRO_FN(cb)
+            ctx.check(_lib.hybrid_set_micro(self._h, self._cb, None))
+
+    def set_rho(self, rho):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        self.ctx.check(_lib.hybrid_set_rho(self._h, _ptr(rho)))
+
+    def step(self):
+        st = HybridStats()
+        self.ctx.check(_lib.hybrid_step(self._h, _c.byref(st)))
+        return st.as_dict()
+
+    def get(self):
+        rho, q, qs, g = (np.zeros(self.n) for _ in range(4))
+        fm = np.zeros(self.n, dtype=np.uint8)
+        self.ctx.check(_lib.hybrid_get(self._h, _ptr(rho), _ptr(q), _ptr(qs), _ptr(g), _ptr(fm, u8)))
+        return {"rho": rho, "q": q, "q_std": qs, "g": g, "from_md": fm.astype(bool)}
+
+    def close(self):
+        if self._h:
+            _lib.hybrid_free(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Hybrid", "HybridCfg", "HybridStats", "hybrid_cfg", "HmdError"]

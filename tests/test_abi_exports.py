@@ -14,6 +14,7 @@ LIB = os.path.join(ROOT, "paper_1603_04628_amd", "libhmd.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = "\n".join(line for line in text.splitlines() if not line.lstrip().startswith("typedef"))
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([a-z][a-z0-9_]*)\s*\(", text, flags=re.M)
     return sorted(set(names))
 

@@ -1,0 +1,85 @@
+"""The library's hybrid march (C ABI, device GP / ensemble) against the
+oracle march with the same micro-solver law, and a run with real batched MD."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+hmd = pytest.importorskip("paper_1603_04628_amd")
+from paper_1603_04628_amd import binding as B  # noqa: E402
+from paper_1603_04628_amd import hybrid_binding as HB  # noqa: E402
+from oracle.gp import GP as OGP, Hyper  # noqa: E402
+from oracle.hybrid import Hybrid as OHybrid, HybridCfg as OCfg, poiseuille_flux  # noqa: E402
+
+
+def law(h, g):
+    # a known micro-solver: continuum flux with a small slip length and an
+    # h-dependent standard error (the same function feeds both marches)
+    q = poiseuille_flux(h, g, eta=2.0, slip=0.5)
+    return q, 0.002 + 1e-4 * np.asarray(h)
+
+
+CFG = dict(n_sections=24, h0=10.0, amp=0.5, L=240.0, dt_macro=0.002, rho_ref=0.8, p_out=0.0, dp_mean=3.0,
+           dp_amp=0.3, period=20.0, c2=200.0, tau_rel=0.05, tau_abs=0.0, audit_every=7)
+
+
+def test_gp_march_matches_oracle():
+    ctx = hmd.Context()
+    X0 = np.array([[6.0, 0.01], [12.0, 0.02]])
+    y0, se0 = law(X0[:, 0], X0[:, 1])
+    g = B.GP(ctx, X0, y0, se0, B.gp_hyper(ranges=(16.0, 0.049)))
+    hy = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=0, **CFG), gp=g, micro=law)
+    og = OGP(X0, y0, se0, Hyper(ranges=(16.0, 0.049)))
+    oh = OHybrid(OCfg(**CFG), og, law)
+    for step in range(25):
+        st = hy.step()
+        oh.step()
+        r = hy.get()
+        assert np.array_equal(r["from_md"], oh.from_md), step
+        np.testing.assert_allclose(r["rho"], oh.rho, rtol=1e-11)
+        np.testing.assert_allclose(r["q"], oh.q, rtol=1e-8, atol=1e-12)
+    assert st["md_calls"] == oh.md_calls and st["audited"] == oh.audited and st["audit_pass"] == oh.audit_pass
+    assert st["md_calls"] > 0 and len(g) == 2 + oh.md_calls - oh.audited
+
+
+def test_ensemble_march_thresholds():
+    ctx = hmd.Context()
+    rng = np.random.default_rng(0)
+    X0 = np.column_stack([rng.uniform(4, 16, 64), rng.uniform(0.001, 0.05, 64)])
+    y0, _ = law(X0[:, 0], X0[:, 1])
+    e = B.Ensemble(ctx, X0, y0, B.ens_cfg(members=3, hidden=16, iters=300, lr=3e-3))
+    cfg = dict(CFG)
+    cfg["tau_rel"] = 0.02
+    hy = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=1, refit_every=4, **cfg), ens=e, micro=law)
+    for _ in range(4):
+        hy.step()
+        r = hy.get()
+        keep = ~r["from_md"]
+        # sections answered by the ensemble passed the relative threshold
+        assert np.all(r["q_std"][keep] <= 0.02 * np.abs(r["q"][keep]))
+        # sections that fell back carry the micro-solver's flux
+        np.testing.assert_allclose(r["q"][~keep], law(hy_h(cfg)[~keep], r["g"][~keep])[0], rtol=1e-12)
+    st = hy.step()
+    assert st["queries"] == 5 * 24
+
+
+def hy_h(cfg):
+    n, L = cfg["n_sections"], cfg["L"]
+    s = (np.arange(n) + 0.5) * L / n
+    return cfg["h0"] * (1.0 + cfg["amp"] * np.cos(2.0 * np.pi * s / L))
+
+
+def test_march_with_batched_md_fallback():
+    params = hmd.Params(Lx_nom=12.0, Lz_nom=12.0, n_equil=200)
+    ctx = hmd.Context(params)
+    g = B.GP(ctx, np.zeros((0, 2)), np.zeros(0), None, B.gp_hyper(ranges=(16.0, 0.049)))
+    cfg = HB.hybrid_cfg(surrogate=0, n_sections=6, L=60.0, h0=10.0, dt_macro=1e-3, dp_mean=1.0, md_sample=400,
+                        tau_rel=0.5)
+    hy = HB.Hybrid(ctx, cfg, gp=g)
+    st = hy.step()
+    assert st["md_calls"] == 6  # empty database: every section falls back
+    assert st["md_atom_steps"] > 0 and st["md_wall_s"] > 0
+    r = hy.get()
+    assert np.all(np.isfinite(r["q"])) and np.all(r["from_md"])
+    st = hy.step()
+    assert st["steps"] == 2 and np.all(np.isfinite(hy.get()["rho"]))
