@@ -64,6 +64,14 @@ typedef struct {
     int n_blocks;
     int64_t n_fluid;
     double delta;
+    /* Implementation choices (results agree to the force tolerance):
+     * force_path 0: cell list rebuilt every step, forces over the 27
+     * neighbouring cells; 1: Verlet pair list (cut-off rc + skin) rebuilt
+     * from the cell list whenever an atom has moved skin/2 since the last
+     * build; -1: the library's tuned choice.  cell_w: minimum cell width
+     * (0: rc, or rc + skin for the pair list). */
+    int force_path;
+    double skin, cell_w;
 } hmd_md_params;
 
 void hmd_md_params_default(hmd_md_params* p);
@@ -127,6 +135,17 @@ int md_batch_kernel_ms(const hmd_batch* b, const char* kernel, double* ms, int64
  * atom of the full neighbour sum) and wall-fluid pairs.  Runs one extra
  * force evaluation (forces unchanged). */
 int md_batch_pair_count(hmd_batch* b, int64_t* fluid_pairs, int64_t* wall_pairs);
+/* The implementation choices in use: force path (0 cell, 1 pair list),
+ * pair-list skin, threads per block, pair-list capacity per atom. */
+int md_batch_config(const hmd_batch* b, int* path, double* skin, int* tpb, int* list_cap);
+
+/* Autotuner: times `probe_steps` steps (after a warm-up of a quarter of
+ * that) of these jobs for each candidate (force path, skin, threads per
+ * block), and keeps the fastest for later batches of the same workload
+ * signature on this context (force_path -1).  table (nullable, 4 doubles per
+ * candidate: path, skin, threads per block, ms per step); n_rows receives the
+ * number of candidates. */
+int md_autotune(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int probe_steps, double* table, int* n_rows);
 void md_batch_free(hmd_batch* b);
 
 /* ------------------------------------------------------------------------
@@ -154,6 +173,11 @@ int md_run(hmd_sys* s, int64_t steps, int thermostat_on, double* energy_trace);
  * params.bin_dy from y = 0, the sum of v_x and the atom count (ceil(h/bin_dy)
  * doubles each). */
 int md_sys_profile(hmd_sys* s, double* mvx, double* cnt);
+/* Pair path only: the Verlet lists of the last build, per atom id, as sorted
+ * neighbour ids (fluid ids, or N_f + wall index for wall atoms); counts has
+ * n_fluid entries, idx up to cap entries, total receives the entry count. */
+int md_neighbor_lists(hmd_sys* s, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total);
+int md_sys_config(hmd_sys* s, int* path, double* skin, int* tpb, int* list_cap);
 void md_sys_free(hmd_sys* s);
 
 /* ------------------------------------------------------------------------

@@ -26,7 +26,7 @@ class OraParams(ctypes.Structure):
         ("dt", ctypes.c_double), ("tau_T", ctypes.c_double),
         ("Lx_nom", ctypes.c_double), ("Lz_nom", ctypes.c_double),
         ("bin_dy", ctypes.c_double), ("n_equil", ctypes.c_int64), ("n_blocks", ctypes.c_int),
-        ("n_fluid", ctypes.c_int64), ("delta", ctypes.c_double),
+        ("n_fluid", ctypes.c_int64), ("delta", ctypes.c_double), ("cell_w", ctypes.c_double),
     ]
 
 
@@ -50,6 +50,7 @@ class Params:
     n_blocks: int = 20
     n_fluid: int = 0
     delta: float = 1.0
+    cell_w: float = 0.0
 
     def to_c(self) -> OraParams:
         return OraParams(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -172,6 +173,19 @@ class System:
         f = np.zeros((self.n_fluid, 3))
         pe = lib().ora_forces_cells(self._h, _ptr(f))
         return f, pe
+
+    def neighbors(self, rl):
+        """Per fluid atom, the sorted fluid ids and (N_f + wall id) within rl."""
+        L = lib()
+        L.ora_neighbors.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int), ctypes.c_int64]
+        L.ora_neighbors.restype = ctypes.c_int64
+        counts = np.zeros(self.n_fluid, dtype=np.int32)
+        tot = L.ora_neighbors(self._h, rl, _ptr(counts, ctypes.c_int), ctypes.POINTER(ctypes.c_int)(), 0)
+        idx = np.zeros(max(tot, 1), dtype=np.int32)
+        L.ora_neighbors(self._h, rl, _ptr(counts, ctypes.c_int), _ptr(idx, ctypes.c_int), tot)
+        starts = np.concatenate([[0], np.cumsum(counts)])
+        return [idx[starts[i]:starts[i + 1]] for i in range(self.n_fluid)]
 
     def cells(self):
         nx, ny, nz = self.ncell

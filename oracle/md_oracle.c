@@ -90,6 +90,7 @@ typedef struct {
     int n_blocks;       /* blocks for the standard error */
     int64_t n_fluid;    /* 0: round(rho*Lx*Lz*h) */
     double delta;       /* gap between wall plane and the first lattice plane */
+    double cell_w;      /* minimum cell width; 0 means rc */
 } ora_params;
 
 typedef struct {
@@ -130,6 +131,7 @@ void ora_default_params(ora_params *P)
     P->bin_dy = 0.25;
     P->n_equil = 0; P->n_blocks = 20; P->n_fluid = 0;
     P->delta = 1.0;
+    P->cell_w = 0.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -292,9 +294,10 @@ static int cell_axis(double x, double inv, int n)
 static void setup_cells(ora_sys *S)
 {
     const ora_params *P = &S->P;
-    S->ncx = (int)floor(S->Lx / P->rc);
-    S->ncz = (int)floor(S->Lz / P->rc);
-    S->ncy = (int)floor(S->h / P->rc);
+    double wmin = P->cell_w > P->rc ? P->cell_w : P->rc;
+    S->ncx = (int)floor(S->Lx / wmin);
+    S->ncz = (int)floor(S->Lz / wmin);
+    S->ncy = (int)floor(S->h / wmin);
     if (S->ncy < 1) S->ncy = 1;
     S->inv_wx = (double)S->ncx / S->Lx;
     S->inv_wy = (double)S->ncy / S->h;
@@ -737,4 +740,33 @@ int ora_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* Neighbour sets for a pair-list cut-off rl (brute force): for fluid atom i
+ * (id order) the fluid atoms j != i and wall atoms w (reported as N_f + w)
+ * with squared minimum-image distance below rl^2, in ascending index order.
+ * counts[i] receives the set sizes; idx (nullable, capacity cap) the
+ * concatenated sets.  Returns the total number of entries. */
+int64_t ora_neighbors(const ora_sys *S, double rl, int *counts, int *idx, int64_t cap)
+{
+    double rl2 = rl * rl;
+    int64_t tot = 0;
+    for (int64_t i = 0; i < S->nf; ++i) {
+        int c = 0;
+        for (int64_t j = 0; j < S->nf + S->nw; ++j) {
+            if (j == i) continue;
+            const double *pj = j < S->nf ? &S->x[3 * j] : &S->xw[3 * (j - S->nf)];
+            double dx = min_image(S->x[3 * i] - pj[0], S->Lx);
+            double dy = S->x[3 * i + 1] - pj[1];
+            double dz = min_image(S->x[3 * i + 2] - pj[2], S->Lz);
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rl2) {
+                if (idx && tot < cap) idx[tot] = (int)j;
+                ++tot;
+                ++c;
+            }
+        }
+        counts[i] = c;
+    }
+    return tot;
 }

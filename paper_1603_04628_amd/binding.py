@@ -31,7 +31,7 @@ class MdParams(_c.Structure):
     _fields_ = [("rho", d), ("T0", d), ("rc", d), ("eps_wf", d), ("sigma_wf", d), ("rho_wall", d),
                 ("wall_layers", i32), ("thermo_axis", i32), ("dt", d), ("tau_T", d), ("Lx_nom", d),
                 ("Lz_nom", d), ("bin_dy", d), ("n_equil", i64), ("n_blocks", i32), ("n_fluid", i64),
-                ("delta", d)]
+                ("delta", d), ("force_path", i32), ("skin", d), ("cell_w", d)]
 
 
 class MdJob(_c.Structure):
@@ -74,6 +74,27 @@ _sig("md_cell_lists", i32, vp, P(u32), P(u32), P(u32))
 _sig("md_run", i32, vp, i64, i32, P(d))
 _sig("md_sys_profile", i32, vp, P(d), P(d))
 _sig("md_sys_free", None, vp)
+_sig("md_neighbor_lists", i32, vp, P(u32), P(u32), i64, P(i64))
+_sig("md_sys_config", i32, vp, P(i32), P(d), P(i32), P(i32))
+_sig("md_batch_config", i32, vp, P(i32), P(d), P(i32), P(i32))
+_sig("md_autotune", i32, vp, P(MdJob), i32, i32, P(d), P(i32))
+
+
+def md_autotune(ctx, jobs, probe_steps=200):
+    """Time every candidate configuration on these jobs; the fastest is kept
+    for later batches of the same workload.  Returns rows of
+    (path, skin, threads per block, ms per step)."""
+    arr = _jobs(jobs)
+    table = np.zeros(4 * 32)
+    n = i32()
+    ctx.check(_lib.md_autotune(ctx.handle, arr, len(jobs), int(probe_steps), _ptr(table), _c.byref(n)))
+    return table[:4 * n.value].reshape(-1, 4)
+
+
+def _config(fn, h):
+    path, skin, tpb, cap = i32(), d(), i32(), i32()
+    fn(h, _c.byref(path), _c.byref(skin), _c.byref(tpb), _c.byref(cap))
+    return {"path": path.value, "skin": skin.value, "tpb": tpb.value, "list_cap": cap.value}
 
 
 def lib():
@@ -110,6 +131,9 @@ class Params:
     n_blocks: int = 20
     n_fluid: int = 0
     delta: float = 1.0
+    force_path: int = -1
+    skin: float = 0.3
+    cell_w: float = 0.0
 
     def to_c(self):
         return MdParams(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -218,6 +242,9 @@ class Batch:
         self.ctx.check(_lib.md_batch_pair_count(self._h, _c.byref(ff), _c.byref(wf)))
         return ff.value, wf.value
 
+    def config(self):
+        return _config(_lib.md_batch_config, self._h)
+
     def close(self):
         if self._h:
             _lib.md_batch_free(self._h)
@@ -276,6 +303,19 @@ class System:
         self.ctx.check(_lib.md_run(self._h, int(steps), 1 if thermostat else 0,
                                    _ptr(trace) if energy else None))
         return trace
+
+    def config(self):
+        return _config(_lib.md_sys_config, self._h)
+
+    def neighbors(self):
+        """Pair path: per atom id, sorted neighbour ids (N_f + w for wall w)."""
+        counts = np.zeros(self.n_fluid, dtype=np.uint32)
+        tot = i64()
+        self.ctx.check(_lib.md_neighbor_lists(self._h, _ptr(counts, u32), None, 0, _c.byref(tot)))
+        idx = np.zeros(max(tot.value, 1), dtype=np.uint32)
+        self.ctx.check(_lib.md_neighbor_lists(self._h, _ptr(counts, u32), _ptr(idx, u32), tot.value, _c.byref(tot)))
+        starts = np.concatenate([[0], np.cumsum(counts.astype(np.int64))])
+        return [idx[starts[i]:starts[i + 1]] for i in range(self.n_fluid)]
 
     def profile(self):
         nb = int(np.ceil(self.h / self.ctx.params.bin_dy))

@@ -30,6 +30,7 @@ SOURCES = [
     ("md_kernels.hip", "hip"),
     ("md_engine.hip", "hip"),
     ("abi.cpp", "hip"),
+    ("tune.cpp", "hip"),
     ("gp.hip", "hip"),
     ("ens.hip", "hip"),
     ("hybrid.cpp", "host"),

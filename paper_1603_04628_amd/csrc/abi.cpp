@@ -40,6 +40,7 @@ void hmd_md_params_default(hmd_md_params* p) {
   p->dt = 0.005; p->tau_T = 0.1;
   p->Lx_nom = 12.0; p->Lz_nom = 12.0; p->bin_dy = 0.25;
   p->n_equil = 0; p->n_blocks = 20; p->n_fluid = 0; p->delta = 1.0;
+  p->force_path = -1; p->skin = 0.3; p->cell_w = 0.0;
 }
 
 int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ctx** out) {
@@ -127,7 +128,7 @@ int md_batch_set_timing(hmd_batch* b, int on) {
 
 int md_batch_kernel_ms(const hmd_batch* b, const char* kernel, double* ms, int64_t* launches) {
   if (!b || !kernel || !ms) return HMD_EINVAL;
-  static const char* names[hmd::K_COUNT] = {"integrate", "scan", "scatter", "reorder", "force"};
+  static const char* names[hmd::K_COUNT] = {"integrate", "scan", "scatter", "reorder", "force", "keys", "list"};
   if (std::strcmp(kernel, "graph_step") == 0) {
     *ms = b->graph_steps ? b->graph_ms / double(b->graph_steps) : 0.0;
     if (launches) *launches = b->graph_steps;
@@ -248,6 +249,16 @@ int md_run(hmd_sys* s, int64_t steps, int thermostat_on, double* energy_trace) {
 int md_sys_profile(hmd_sys* s, double* mvx, double* cnt) {
   if (!s) return HMD_EINVAL;
   return guarded(s->b->ctx, [&] { return hmd::batch_profile(s->b, 0, mvx, cnt); });
+}
+
+int md_neighbor_lists(hmd_sys* s, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total) {
+  if (!s) return HMD_EINVAL;
+  return guarded(s->b->ctx, [&] { return hmd::batch_neighbors(s->b, 0, counts, idx, cap, total); });
+}
+
+int md_sys_config(hmd_sys* s, int* path, double* skin, int* tpb, int* list_cap) {
+  if (!s) return HMD_EINVAL;
+  return md_batch_config(s->b, path, skin, tpb, list_cap);
 }
 
 void md_sys_free(hmd_sys* s) {

@@ -17,7 +17,8 @@ struct hmd_ctx {
   bool own_stream = false;
   hmd_md_params params{};
   std::string err;
-  int force_variant = -1;  // -1: pick per batch; otherwise a fixed force kernel variant
+  // tuned choices keyed by a workload signature (see tune.hip)
+  std::map<std::string, std::vector<double>> tuned;
 };
 
 namespace hmd {
@@ -32,6 +33,12 @@ namespace hmd {
     }                                                                                   \
   } while (0)
 
+#define HMD_TRY(expr)              \
+  do {                             \
+    int rc_ = (expr);              \
+    if (rc_ != HMD_OK) return rc_; \
+  } while (0)
+
 // Per-system constants read by every kernel (device copy, one per system).
 struct SimDev {
   double Lx, Lz, h;
@@ -41,19 +48,23 @@ struct SimDev {
   double inv_area;             // 1 / (Lx Lz)
   double inv_bin;              // 1 / bin width
   double inv_nf;               // 1 / N_f
-  float fwx, fwy, fwz, fpad;   // FP32 cell widths (neighbour-cell shifts)
+  double fix_x, fix_y, fix_z;  // fixed-point scales (2^32 per extent)
+  double y_lo;                 // fixed-point origin in y
+  float unit_x, unit_y, unit_z;  // length of one fixed-point unit
+  float fwx, fwy, fwz;         // FP32 cell widths (neighbour-cell shifts)
   int nx, ny, nz;
   int a0, nf;                  // fluid slots [a0, a0 + nf)
   int c0, ncell;               // global fluid cells [c0, c0 + ncell)
   int wc0;                     // wall columns [wc0, wc0 + 2 nx nz)
+  int w0;                      // wall atoms [w0, w0 + nw) of the wall arrays
   int nbins, bin0;             // profile bins [bin0, bin0 + nbins)
-  int pad;
 };
 
 // Step constants passed by value.
 struct StepConst {
   double dt, hdt, dt_tau, T0;
-  float rc2, eps_wf, sig2_wf, ush_ff, ush_wf;
+  int64_t n_equil;
+  float rc2, eps_wf, sig2_wf, ush_ff, ush_wf, half_skin2;
   int axis;        // thermostatted velocity component
   int nb, B, r;    // SE blocks, block length, samples dropped at the front
   int thermo_on;   // thermostat active in this run
@@ -74,7 +85,7 @@ struct Acc {
   unsigned long long* pairs;  // [2] in-cutoff fluid-fluid (ordered) and wall-fluid pairs
 };
 
-enum Kern { K_INTEGRATE = 0, K_SCAN, K_SCATTER, K_REORDER, K_FORCE, K_COUNT };
+enum Kern { K_INTEGRATE = 0, K_SCAN, K_SCATTER, K_REORDER, K_FORCE, K_KEYS, K_LIST, K_COUNT };
 
 }  // namespace hmd
 
@@ -83,42 +94,50 @@ struct hmd_batch {
   hmd_md_params P{};
   int S = 0;
   int64_t n_sample = 0;
+  int path = 1;           // 0 cell path, 1 pair path
+  int tpb = 256;          // threads per block of the per-slot kernels
+  double skin = 0.3;
+  int list_cap = 0, list_ld = 0;
   std::vector<hmd::HostSystem> host;  // geometry (atom arrays released after upload)
+  std::vector<int> wall_id;           // wall slot (column order) -> wall id within its system
   std::vector<hmd::SimDev> sims;
   int64_t ntot = 0, ncell = 0, nwall = 0, nwcell = 0, nbins = 0;
-  int force_variant = 0;
 
   // device buffers
   hmd::SimDev* d_sims = nullptr;
   uint16_t* d_atom_sim = nullptr;   // slot -> system
   uint16_t* d_cell_sim = nullptr;   // global fluid cell -> system
-  double* d_state[2][6] = {};       // x y z vx vy vz, ping-pong
+  double* d_state[2][6] = {};       // x y z vx vy vz: current copy and reorder target
   int* d_tag[2] = {};               // atom id within its system
   float4* d_f4 = nullptr;           // force (w: potential energy) per slot
-  float4* d_pos4 = nullptr;         // cell-relative FP32 position (w: local cell id bits)
+  float4* d_pos4 = nullptr;         // cell path: cell-relative FP32 position (w: local cell id bits)
+  int4* d_pfix = nullptr;           // pair path: fixed-point positions, fluid slots then wall atoms
+  int4* d_pbuild = nullptr;         // pair path: positions at the last list build
+  uint32_t* d_slot_cell = nullptr;  // pair path: cell of each slot at the last build
+  uint32_t* d_list = nullptr;       // pair path: list_cap x list_ld entries
+  uint32_t* d_nlist = nullptr;
+  int* d_flag = nullptr;            // [2] rebuild flags by step parity, [2] list overflow
   uint32_t* d_key = nullptr;        // global cell of each slot
   uint32_t* d_count = nullptr;      // atomic counters per cell
-  uint32_t* d_cursor = nullptr;     // scatter cursors per cell
+  uint32_t* d_rank = nullptr;       // arrival rank of each slot inside its new cell
   uint32_t* d_start = nullptr;      // first slot of each cell
   uint32_t* d_ncount = nullptr;     // atoms per cell after the sort
   uint32_t* d_perm = nullptr;       // scatter target -> source slot
-  uint32_t* d_rank = nullptr;       // arrival rank of each slot inside its new cell
   float4* d_wpos4 = nullptr;        // wall atoms, column order, column-relative
   uint32_t* d_wstart = nullptr;
   uint32_t* d_wcount = nullptr;
-  int64_t* d_dstate = nullptr;      // done, n_equil, sampled_upto, lambda pending
+  int64_t* d_dstate = nullptr;      // [0] steps done at a graph's start, [3] Berendsen factor pending
   hmd::Acc acc{};
   double* d_accbuf = nullptr;
   int* d_status = nullptr;
 
-  int cur = 0;  // which state buffer is current
-  int64_t done = 0, sampled_upto = 0;
+  int cur = 0;  // cell path: which state copy is current (pair path: always 0)
+  int64_t done = 0;
   bool pending = false;
   bool thermo_on = true;
 
-  std::map<int, hipGraphExec_t> graphs;  // chunk length -> executable graph
+  std::map<int, hipGraphExec_t> graphs;  // key -> executable graph
   std::map<int, hipGraph_t> graph_defs;
-  std::map<int, std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>> graph_marks;
 
   bool timing = false;
   std::vector<hipEvent_t> ev;             // event pool for timing
@@ -133,8 +152,6 @@ struct hmd_sys {
 };
 
 namespace hmd {
-struct StepConst;
-void launch_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K);
 int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out);
 int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, double* energy_trace);
 int batch_results(hmd_batch* b, hmd_md_result* out);
@@ -145,4 +162,7 @@ int batch_forces(hmd_batch* b, int sim, float* f, double* pe);
 int batch_cells(hmd_batch* b, int sim, uint32_t* cell_of, uint32_t* counts, uint32_t* order);
 int batch_profile(hmd_batch* b, int sim, double* mvx, double* cnt);
 int batch_pairs(hmd_batch* b, int64_t* ff, int64_t* wf);
+int batch_neighbors(hmd_batch* b, int sim, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total);
+// Resolved implementation choices for a batch of these jobs on this context.
+void choose_path(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int* path, double* skin, int* tpb);
 }  // namespace hmd

@@ -15,9 +15,9 @@ namespace hmd {
 
 namespace {
 
-constexpr int TPB = 256;
+constexpr double kTwo32 = 4294967296.0;
 
-inline int blocks_for(int64_t n) { return int((n + TPB - 1) / TPB); }
+inline int blocks_for(int64_t n, int tpb) { return int((n + tpb - 1) / tpb); }
 
 StateRef state_ref(hmd_batch* b, int which) {
   double** s = b->d_state[which];
@@ -31,6 +31,7 @@ StepConst step_const(const hmd_batch* b, bool thermostat, bool energy) {
   K.hdt = 0.5 * P.dt;
   K.dt_tau = P.dt / P.tau_T;
   K.T0 = P.T0;
+  K.n_equil = P.n_equil;
   K.rc2 = float(P.rc * P.rc);
   K.eps_wf = float(P.eps_wf);
   K.sig2_wf = float(P.sigma_wf * P.sigma_wf);
@@ -38,6 +39,7 @@ StepConst step_const(const hmd_batch* b, bool thermostat, bool energy) {
   K.ush_ff = float(4.0 * (ir6 * ir6 - ir6));
   const double sw6 = std::pow(P.sigma_wf / P.rc, 6.0);
   K.ush_wf = float(4.0 * P.eps_wf * (sw6 * sw6 - sw6));
+  K.half_skin2 = float(0.25 * b->skin * b->skin);
   K.axis = P.thermo_axis;
   K.nb = P.n_blocks;
   if (b->n_sample > 0) {
@@ -59,11 +61,11 @@ int dalloc(hmd_ctx* ctx, T** p, int64_t n) {
   return HMD_OK;
 }
 
-#define HMD_TRY(expr)            \
-  do {                           \
-    int rc_ = (expr);            \
-    if (rc_ != HMD_OK) return rc_; \
-  } while (0)
+uint32_t fix_axis_host(double v, double scale) {
+  double t = v * scale;
+  t = t < 0.0 ? 0.0 : (t > 4294967295.0 ? 4294967295.0 : t);
+  return uint32_t(t);
+}
 
 // Launches of one kind, optionally bracketed by timing events.
 struct Launcher {
@@ -84,61 +86,118 @@ struct Launcher {
   }
 };
 
-// One velocity-Verlet step over the whole batch (five launches).
-void enqueue_step(hmd_batch* b, Launcher& L, const StepConst& K) {
+// Counting sort of the current state by cell (flag null: unconditional).
+void enqueue_sort(hmd_batch* b, Launcher& L, const StepConst& K, const int* flag, StepRef R) {
   hipStream_t s = L.s;
-  const int nt = int(b->ntot);
-  const int src = b->cur, dst = 1 - b->cur;
-  L.begin(K_INTEGRATE);
-  hipLaunchKernelGGL(k_integrate<1>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
-                     state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->d_rank, b->acc, b->d_dstate, K);
+  const int nt = int(b->ntot), tpb = b->tpb, nb = blocks_for(nt, tpb);
+  if (b->path == 0) {
+    const int src = b->cur, dst = 1 - b->cur;
+    if (!flag && R.base == nullptr && R.k < 0) {  // keys for a sort outside a time step
+      hipLaunchKernelGGL((k_integrate<0, 0>), dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_atom_sim,
+                         state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->d_rank, b->d_pfix, b->d_pbuild,
+                         b->d_flag, b->acc, b->d_dstate, StepRef{nullptr, 0}, K);
+    }
+    L.begin(K_SCAN);
+    hipLaunchKernelGGL(k_scan, dim3(b->S), dim3(1024), 0, s, b->d_sims, b->d_count, b->d_start, b->d_ncount,
+                       nullptr, R);
+    L.end();
+    L.begin(K_SCATTER);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(tpb), 0, s, nt, b->d_key, b->d_start, b->d_rank, b->d_perm,
+                       nullptr, R);
+    L.end();
+    L.begin(K_REORDER);
+    hipLaunchKernelGGL(k_reorder<0>, dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_cell_sim, b->d_key,
+                       b->d_start, b->d_ncount, b->d_perm, state_ref(b, src), state_ref(b, dst), b->d_tag[src],
+                       b->d_tag[dst], b->d_pos4, b->d_pfix, b->d_pbuild, b->d_slot_cell, nullptr, R);
+    L.end();
+    b->cur = dst;
+    return;
+  }
+  L.begin(K_KEYS);
+  hipLaunchKernelGGL(k_keys, dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_atom_sim, state_ref(b, 0), b->d_key,
+                     b->d_count, b->d_rank, flag, R);
   L.end();
   L.begin(K_SCAN);
-  hipLaunchKernelGGL(k_scan, dim3(b->S), dim3(1024), 0, s, b->d_sims, b->d_count, b->d_cursor, b->d_start,
-                     b->d_ncount, b->d_dstate, 1);
+  hipLaunchKernelGGL(k_scan, dim3(b->S), dim3(1024), 0, s, b->d_sims, b->d_count, b->d_start, b->d_ncount, flag,
+                     R);
   L.end();
   L.begin(K_SCATTER);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_key, b->d_start, b->d_rank,
-                     b->d_perm);
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(tpb), 0, s, nt, b->d_key, b->d_start, b->d_rank, b->d_perm, flag,
+                     R);
   L.end();
   L.begin(K_REORDER);
-  hipLaunchKernelGGL(k_reorder, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_cell_sim, b->d_key,
-                     b->d_start, b->d_ncount, b->d_perm, state_ref(b, src), state_ref(b, dst), b->d_tag[src],
-                     b->d_tag[dst], b->d_pos4);
+  hipLaunchKernelGGL(k_reorder<1>, dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_cell_sim, b->d_key, b->d_start,
+                     b->d_ncount, b->d_perm, state_ref(b, 0), state_ref(b, 1), b->d_tag[0], b->d_tag[1],
+                     b->d_pos4, b->d_pfix, b->d_pbuild, b->d_slot_cell, flag, R);
   L.end();
-  b->cur = dst;  // the force kernel kicks the reordered state
+  const float rl2 = float((b->P.rc + b->skin) * (b->P.rc + b->skin));
+  L.begin(K_LIST);
+  hipLaunchKernelGGL(k_build_list, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->list_cap, b->d_sims,
+                     b->d_atom_sim, b->d_slot_cell, b->d_pfix, b->d_start, b->d_ncount, b->d_wstart, b->d_wcount,
+                     b->d_list, b->d_nlist, state_ref(b, 1), state_ref(b, 0), b->d_tag[1], b->d_tag[0],
+                     b->d_flag + 2, flag, R, rl2);
+  L.end();
+}
+
+void enqueue_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K, StepRef R) {
+  const int nt = int(b->ntot), tpb = b->tpb, nb = blocks_for(nt, tpb);
+  const int src = b->cur;
+  if (b->path == 0) {
+    if (mode == 0)
+      hipLaunchKernelGGL(k_force_cell<0>, dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_atom_sim, b->d_pos4,
+                         b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
+                         b->acc, b->d_dstate, R, K);
+    else
+      hipLaunchKernelGGL(k_force_cell<1>, dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_atom_sim, b->d_pos4,
+                         b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
+                         b->acc, b->d_dstate, R, K);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL(k_force_list<0>, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims, b->d_atom_sim,
+                         b->d_pfix, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
+    else
+      hipLaunchKernelGGL(k_force_list<1>, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims, b->d_atom_sim,
+                         b->d_pfix, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
+  }
+}
+
+// One velocity-Verlet step over the whole batch.
+void enqueue_step(hmd_batch* b, Launcher& L, const StepConst& K, StepRef R) {
+  hipStream_t s = L.s;
+  const int nt = int(b->ntot), tpb = b->tpb, nb = blocks_for(nt, tpb);
+  L.begin(K_INTEGRATE);
+  if (b->path == 0)
+    hipLaunchKernelGGL((k_integrate<1, 0>), dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_atom_sim,
+                       state_ref(b, b->cur), b->d_f4, b->d_key, b->d_count, b->d_rank, b->d_pfix, b->d_pbuild,
+                       b->d_flag, b->acc, b->d_dstate, R, K);
+  else
+    hipLaunchKernelGGL((k_integrate<1, 1>), dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_atom_sim,
+                       state_ref(b, 0), b->d_f4, b->d_key, b->d_count, b->d_rank, b->d_pfix, b->d_pbuild, b->d_flag,
+                       b->acc, b->d_dstate, R, K);
+  L.end();
+  enqueue_sort(b, L, K, b->path == 0 ? nullptr : b->d_flag, R);
   L.begin(K_FORCE);
-  launch_force(b, s, 1, K);
+  enqueue_force(b, s, 1, K, R);
   L.end();
 }
 
-// Sort the current positions into cells (no time step).
-void enqueue_sort(hmd_batch* b, hipStream_t s, const StepConst& K) {
-  const int nt = int(b->ntot);
-  const int src = b->cur, dst = 1 - b->cur;
-  hipLaunchKernelGGL(k_integrate<0>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
-                     state_ref(b, src), b->d_f4, b->d_key, b->d_count, b->d_rank, b->acc, b->d_dstate, K);
-  hipLaunchKernelGGL(k_scan, dim3(b->S), dim3(1024), 0, s, b->d_sims, b->d_count, b->d_cursor, b->d_start,
-                     b->d_ncount, b->d_dstate, 0);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_key, b->d_start, b->d_rank,
-                     b->d_perm);
-  hipLaunchKernelGGL(k_reorder, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_cell_sim, b->d_key,
-                     b->d_start, b->d_ncount, b->d_perm, state_ref(b, src), state_ref(b, dst), b->d_tag[src],
-                     b->d_tag[dst], b->d_pos4);
-  b->cur = dst;
+// Unconditional sort of the current positions (creation, new state).
+void sort_now(hmd_batch* b, const StepConst& K) {
+  Launcher L{b, b->ctx->stream, nullptr, 0};
+  enqueue_sort(b, L, K, nullptr, StepRef{nullptr, -1});
 }
 
-// Forces for the current sorted positions; potential energy sums go to
-// acc.pe[done & 1] (cleared first).
+// Forces for the current positions; potential energy and pair counts go to
+// acc.pe[(done + 1) & 1] and acc.pairs (cleared first).
 int forces_now(hmd_batch* b, bool energy) {
   hmd_ctx* ctx = b->ctx;
   hipStream_t s = ctx->stream;
   StepConst K = step_const(b, b->thermo_on, energy);
-  const int p = int(b->done & 1);
+  const int p = int((b->done + 1) & 1);
   HMD_HIP(ctx, hipMemsetAsync(b->acc.pe[p], 0, sizeof(double) * b->S, s));
   HMD_HIP(ctx, hipMemsetAsync(b->acc.ke[p], 0, sizeof(double) * b->S, s));
   HMD_HIP(ctx, hipMemsetAsync(b->acc.pairs, 0, 2 * sizeof(unsigned long long), s));
-  launch_force(b, s, 0, K);
+  enqueue_force(b, s, 0, K, StepRef{nullptr, b->done});
   HMD_HIP(ctx, hipGetLastError());
   return HMD_OK;
 }
@@ -150,25 +209,68 @@ void release_graphs(hmd_batch* b) {
   b->graph_defs.clear();
 }
 
-int graph_key(int chunk, bool thermostat) { return chunk * 2 + (thermostat ? 1 : 0); }
+int ensure_events(hmd_batch* b, size_t n) {
+  while (b->ev.size() < n) {
+    hipEvent_t e;
+    HMD_HIP(b->ctx, hipEventCreate(&e));
+    b->ev.push_back(e);
+  }
+  return HMD_OK;
+}
+
+int harvest(hmd_batch* b, std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>& marks) {
+  if (marks.empty()) return HMD_OK;
+  HMD_HIP(b->ctx, hipEventSynchronize(marks.back().second.second));
+  for (auto& m : marks) {
+    float ms = 0.f;
+    HMD_HIP(b->ctx, hipEventElapsedTime(&ms, m.second.first, m.second.second));
+    b->kern_ms[m.first] += ms;
+    b->kern_n[m.first] += 1;
+  }
+  marks.clear();
+  return HMD_OK;
+}
+
+// Executable graph of `chunk` steps; its step indices are read from
+// d_dstate[0], which its last node advances by `chunk`.
+int get_graph(hmd_batch* b, int chunk, const StepConst& K, hipGraphExec_t* out) {
+  const int key = chunk * 2 + (K.thermo_on ? 1 : 0);
+  auto it = b->graphs.find(key);
+  if (it != b->graphs.end()) {
+    *out = it->second;
+    return HMD_OK;
+  }
+  hmd_ctx* ctx = b->ctx;
+  hipStream_t s = ctx->stream;
+  const int cur0 = b->cur;
+  Launcher L{b, s, nullptr, 0};
+  HMD_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < chunk; ++k) enqueue_step(b, L, K, StepRef{b->d_dstate, k});
+  hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, s, b->d_dstate, int64_t(chunk));
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  b->cur = cur0;  // capture did not execute anything
+  if (e != hipSuccess) {
+    ctx->err = std::string("graph capture: ") + hipGetErrorString(e);
+    return HMD_EDEVICE;
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    ctx->err = std::string("graph instantiate: ") + hipGetErrorString(e);
+    return HMD_EDEVICE;
+  }
+  b->graph_defs[key] = g;
+  b->graphs[key] = ex;
+  *out = ex;
+  return HMD_OK;
+}
 
 }  // namespace
 
-void launch_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K) {
-  const int nt = int(b->ntot);
-  const int src = b->cur;
-  if (mode == 0)
-    hipLaunchKernelGGL(k_force<0>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim, b->d_pos4,
-                       b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
-                       b->acc, b->d_dstate, K);
-  else
-    hipLaunchKernelGGL(k_force<1>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim, b->d_pos4,
-                       b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
-                       b->acc, b->d_dstate, K);
-}
-
 int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
-  if (!ctx || !out || (n > 0 && !jobs) || n < 1 || n > 65535) {
+  if (!ctx || !out || !jobs || n < 1 || n > 65535) {
     if (ctx) ctx->err = "md batch: need 1..65535 jobs";
     return HMD_EINVAL;
   }
@@ -185,9 +287,11 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
       delete b;
       return HMD_EINVAL;
     }
+  choose_path(ctx, jobs, n, &b->path, &b->skin, &b->tpb);
+  const double wmin = std::max(b->path == 1 ? b->P.rc + b->skin : b->P.rc, b->P.cell_w);
   b->host.resize(n);
   for (int k = 0; k < n; ++k) {
-    int rc = build_system(b->P, jobs[k].h, jobs[k].g, jobs[k].seed, b->host[k], ctx->err);
+    int rc = build_system(b->P, jobs[k].h, jobs[k].g, jobs[k].seed, wmin, b->host[k], ctx->err);
     if (rc != HMD_OK) {
       delete b;
       return rc;
@@ -196,6 +300,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   // flattened layout
   b->sims.resize(n);
   int64_t a0 = 0, c0 = 0, wc0 = 0, bin0 = 0, w0 = 0;
+  const double half = 0.5 * std::cbrt(4.0 / b->P.rho_wall);
   for (int k = 0; k < n; ++k) {
     const HostSystem& H = b->host[k];
     SimDev& D = b->sims[k];
@@ -207,11 +312,20 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     D.inv_area = 1.0 / (H.Lx * H.Lz);
     D.inv_bin = 1.0 / b->P.bin_dy;
     D.inv_nf = 1.0 / double(H.nf);
+    const double margin = double(b->P.wall_layers) * half + 1.0;  // beyond the outermost wall layer
+    D.y_lo = -margin;
+    D.fix_x = kTwo32 / H.Lx;
+    D.fix_y = kTwo32 / (H.h + 2.0 * margin);
+    D.fix_z = kTwo32 / H.Lz;
+    D.unit_x = float(H.Lx / kTwo32);
+    D.unit_y = float((H.h + 2.0 * margin) / kTwo32);
+    D.unit_z = float(H.Lz / kTwo32);
     D.fwx = float(H.wx); D.fwy = float(H.wy); D.fwz = float(H.wz);
     D.nx = H.nx; D.ny = H.ny; D.nz = H.nz;
     D.a0 = int(a0); D.nf = int(H.nf);
     D.c0 = int(c0); D.ncell = H.nx * H.ny * H.nz;
     D.wc0 = int(wc0);
+    D.w0 = int(w0);
     D.nbins = H.nbins; D.bin0 = int(bin0);
     a0 += H.nf;
     c0 += D.ncell;
@@ -219,12 +333,19 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     bin0 += H.nbins;
     w0 += H.nw;
   }
-  if (a0 >= (int64_t(1) << 31) || c0 >= (int64_t(1) << 31)) {
+  if (a0 + w0 >= (int64_t(1) << 31) || c0 >= (int64_t(1) << 31)) {
     ctx->err = "md batch: too many atoms or cells for one batch";
     delete b;
     return HMD_EINVAL;
   }
   b->ntot = a0; b->ncell = c0; b->nwcell = wc0; b->nbins = bin0; b->nwall = w0;
+  // pair-list capacity: neighbours within rc + skin at twice the fluid density
+  // plus a wall half-space, rounded up to a multiple of 32
+  const double rl = b->P.rc + b->skin;
+  const double est = 2.0 * std::max(b->P.rho, 0.8) * 4.18879 * rl * rl * rl +
+                     2.0 * b->P.rho_wall * 2.0944 * rl * rl * rl;
+  b->list_cap = b->path == 1 ? int(32 * std::ceil(est / 32.0)) : 0;
+  b->list_ld = int(64 * ((b->ntot + 63) / 64));
 
   int rc = HMD_OK;
   auto fail = [&](int code) {
@@ -233,14 +354,22 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   };
   if ((rc = dalloc(ctx, &b->d_sims, n)) || (rc = dalloc(ctx, &b->d_atom_sim, b->ntot)) ||
       (rc = dalloc(ctx, &b->d_cell_sim, b->ncell)) || (rc = dalloc(ctx, &b->d_f4, b->ntot)) ||
-      (rc = dalloc(ctx, &b->d_pos4, b->ntot)) || (rc = dalloc(ctx, &b->d_key, b->ntot)) ||
-      (rc = dalloc(ctx, &b->d_count, b->ncell)) || (rc = dalloc(ctx, &b->d_cursor, b->ncell)) ||
-      (rc = dalloc(ctx, &b->d_start, b->ncell)) || (rc = dalloc(ctx, &b->d_ncount, b->ncell)) ||
-      (rc = dalloc(ctx, &b->d_perm, b->ntot)) || (rc = dalloc(ctx, &b->d_rank, b->ntot)) || (rc = dalloc(ctx, &b->d_wpos4, b->nwall)) ||
-      (rc = dalloc(ctx, &b->d_wstart, b->nwcell)) || (rc = dalloc(ctx, &b->d_wcount, b->nwcell)) ||
-      (rc = dalloc(ctx, &b->d_dstate, 4)) || (rc = dalloc(ctx, &b->d_tag[0], b->ntot)) ||
-      (rc = dalloc(ctx, &b->d_tag[1], b->ntot)))
+      (rc = dalloc(ctx, &b->d_key, b->ntot)) || (rc = dalloc(ctx, &b->d_count, b->ncell)) ||
+      (rc = dalloc(ctx, &b->d_rank, b->ntot)) || (rc = dalloc(ctx, &b->d_start, b->ncell)) ||
+      (rc = dalloc(ctx, &b->d_ncount, b->ncell)) || (rc = dalloc(ctx, &b->d_perm, b->ntot)) ||
+      (rc = dalloc(ctx, &b->d_wpos4, b->nwall)) || (rc = dalloc(ctx, &b->d_wstart, b->nwcell)) ||
+      (rc = dalloc(ctx, &b->d_wcount, b->nwcell)) || (rc = dalloc(ctx, &b->d_dstate, 4)) ||
+      (rc = dalloc(ctx, &b->d_tag[0], b->ntot)) || (rc = dalloc(ctx, &b->d_tag[1], b->ntot)) ||
+      (rc = dalloc(ctx, &b->d_flag, 4)))
     return fail(rc);
+  if (b->path == 0) {
+    if ((rc = dalloc(ctx, &b->d_pos4, b->ntot))) return fail(rc);
+  } else {
+    if ((rc = dalloc(ctx, &b->d_pfix, b->ntot + b->nwall)) || (rc = dalloc(ctx, &b->d_pbuild, b->ntot)) ||
+        (rc = dalloc(ctx, &b->d_slot_cell, b->ntot)) || (rc = dalloc(ctx, &b->d_nlist, b->ntot)) ||
+        (rc = dalloc(ctx, &b->d_list, int64_t(b->list_cap) * b->list_ld)))
+      return fail(rc);
+  }
   for (int w = 0; w < 2; ++w)
     for (int a = 0; a < 6; ++a)
       if ((rc = dalloc(ctx, &b->d_state[w][a], b->ntot))) return fail(rc);
@@ -265,8 +394,9 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   std::vector<int> tag(b->ntot);
   std::vector<uint16_t> atom_sim(b->ntot), cell_sim(b->ncell);
   std::vector<float4> wpos(std::max<int64_t>(b->nwall, 1));
+  std::vector<int4> wfix(std::max<int64_t>(b->nwall, 1));
   std::vector<uint32_t> wstart(b->nwcell), wcount(b->nwcell, 0);
-  int64_t wbase = 0;
+  b->wall_id.assign(std::max<int64_t>(b->nwall, 1), 0);
   for (int k = 0; k < n; ++k) {
     HostSystem& H = b->host[k];
     const SimDev& D = b->sims[k];
@@ -290,7 +420,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
       wkey[w] = (slab * H.nz + cz) * H.nx + cx;
       wcount[D.wc0 + wkey[w]]++;
     }
-    uint32_t acc0 = uint32_t(wbase);
+    uint32_t acc0 = uint32_t(D.w0);
     for (int c = 0; c < ncol; ++c) {
       wstart[D.wc0 + c] = acc0;
       acc0 += wcount[D.wc0 + c];
@@ -299,12 +429,15 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     for (int64_t w = 0; w < H.nw; ++w) {
       const int c = wkey[w];
       const uint32_t slot = wstart[D.wc0 + c] + fill[c]++;
+      b->wall_id[slot] = int(w);
       const int cx = c % H.nx, cz = (c / H.nx) % H.nz, slab = c / (H.nx * H.nz);
       const double oy = slab == 0 ? -H.wy : double(H.ny) * H.wy;
-      wpos[slot] = make_float4(float(H.xw[3 * w] - double(cx) * H.wx), float(H.xw[3 * w + 1] - oy),
-                               float(H.xw[3 * w + 2] - double(cz) * H.wz), 0.0f);
+      const double* p = &H.xw[3 * w];
+      wpos[slot] = make_float4(float(p[0] - double(cx) * H.wx), float(p[1] - oy), float(p[2] - double(cz) * H.wz),
+                               0.0f);
+      wfix[slot] = make_int4(int(fix_axis_host(p[0], D.fix_x)), int(fix_axis_host(p[1] - D.y_lo, D.fix_y)),
+                             int(fix_axis_host(p[2], D.fix_z)), 0);
     }
-    wbase += H.nw;
     // the big host arrays are no longer needed
     H.x.clear(); H.x.shrink_to_fit();
     H.v.clear(); H.v.shrink_to_fit();
@@ -322,15 +455,16 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
       (rc = up(b->d_wstart, wstart.data(), 4 * b->nwcell)) ||
       (rc = up(b->d_wcount, wcount.data(), 4 * b->nwcell)) || (rc = up(b->d_dstate, dstate, sizeof(dstate))))
     return fail(rc);
+  if (b->path == 1 && (rc = up(b->d_pfix + b->ntot, wfix.data(), sizeof(int4) * b->nwall))) return fail(rc);
   for (int a = 0; a < 6; ++a)
     if ((rc = up(b->d_state[0][a], hs[a].data(), 8 * b->ntot))) return fail(rc);
   HMD_HIP(ctx, hipMemsetAsync(b->d_accbuf, 0, sizeof(double) * nacc, s));
   HMD_HIP(ctx, hipMemsetAsync(b->d_status, 0, sizeof(int) * n, s));
   HMD_HIP(ctx, hipMemsetAsync(b->d_count, 0, 4 * b->ncell, s));
-  HMD_HIP(ctx, hipMemsetAsync(b->d_cursor, 0, 4 * b->ncell, s));
+  HMD_HIP(ctx, hipMemsetAsync(b->d_flag, 0, 4 * sizeof(int), s));
   b->cur = 0;
   StepConst K = step_const(b, true, true);
-  enqueue_sort(b, s, K);
+  sort_now(b, K);
   if ((rc = forces_now(b, true))) return fail(rc);
   HMD_HIP(ctx, hipStreamSynchronize(s));
   HMD_HIP(ctx, hipGetLastError());
@@ -342,9 +476,10 @@ void batch_free(hmd_batch* b) {
   if (!b) return;
   release_graphs(b);
   for (auto e : b->ev) (void)hipEventDestroy(e);
-  void* ptrs[] = {b->d_sims, b->d_atom_sim, b->d_cell_sim, b->d_f4, b->d_pos4, b->d_key, b->d_count,
-                  b->d_cursor, b->d_start, b->d_ncount, b->d_perm, b->d_rank, b->d_wpos4, b->d_wstart, b->d_wcount,
-                  b->d_dstate, b->d_tag[0], b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs};
+  void* ptrs[] = {b->d_sims, b->d_atom_sim, b->d_cell_sim, b->d_f4, b->d_pos4, b->d_pfix, b->d_pbuild,
+                  b->d_slot_cell, b->d_list, b->d_nlist, b->d_flag, b->d_key, b->d_count, b->d_rank, b->d_start,
+                  b->d_ncount, b->d_perm, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_dstate, b->d_tag[0],
+                  b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int w = 0; w < 2; ++w)
@@ -352,73 +487,6 @@ void batch_free(hmd_batch* b) {
       if (b->d_state[w][a]) (void)hipFree(b->d_state[w][a]);
   delete b;
 }
-
-namespace {
-
-int ensure_events(hmd_batch* b, size_t n) {
-  while (b->ev.size() < n) {
-    hipEvent_t e;
-    HMD_HIP(b->ctx, hipEventCreate(&e));
-    b->ev.push_back(e);
-  }
-  return HMD_OK;
-}
-
-int harvest(hmd_batch* b, std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>& marks) {
-  if (marks.empty()) return HMD_OK;
-  HMD_HIP(b->ctx, hipEventSynchronize(marks.back().second.second));
-  for (auto& m : marks) {
-    float ms = 0.f;
-    HMD_HIP(b->ctx, hipEventElapsedTime(&ms, m.second.first, m.second.second));
-    b->kern_ms[m.first] += ms;
-    b->kern_n[m.first] += 1;
-  }
-  marks.clear();
-  return HMD_OK;
-}
-
-// Executable graph of `chunk` steps.  With `timed`, every kernel of the
-// chunk is bracketed by captured event-record nodes whose pairs are kept in
-// b->graph_marks[key] (events past the direct-launch pool).
-int get_graph(hmd_batch* b, int chunk, const StepConst& K, bool timed, hipGraphExec_t* out, int* key_out) {
-  const int key = graph_key(chunk, K.thermo_on != 0) + (timed ? (1 << 24) : 0);
-  *key_out = key;
-  auto it = b->graphs.find(key);
-  if (it != b->graphs.end()) {
-    *out = it->second;
-    return HMD_OK;
-  }
-  hmd_ctx* ctx = b->ctx;
-  hipStream_t s = ctx->stream;
-  const int cur0 = b->cur;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
-  const size_t base = size_t(2 * K_COUNT) * 64;
-  if (timed) HMD_TRY(ensure_events(b, base + size_t(2 * K_COUNT) * chunk));
-  Launcher L{b, s, timed ? &marks : nullptr, int(base)};
-  HMD_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < chunk; ++k) enqueue_step(b, L, K);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(s, &g);
-  b->cur = cur0;  // capture did not execute anything
-  if (e != hipSuccess) {
-    ctx->err = std::string("graph capture: ") + hipGetErrorString(e);
-    return HMD_EDEVICE;
-  }
-  hipGraphExec_t ex = nullptr;
-  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    (void)hipGraphDestroy(g);
-    ctx->err = std::string("graph instantiate: ") + hipGetErrorString(e);
-    return HMD_EDEVICE;
-  }
-  b->graph_defs[key] = g;
-  b->graphs[key] = ex;
-  b->graph_marks[key] = marks;
-  *out = ex;
-  return HMD_OK;
-}
-
-}  // namespace
 
 int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, double* energy_trace) {
   hmd_ctx* ctx = b->ctx;
@@ -432,16 +500,15 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
   const bool energy = energy_trace != nullptr;
   const StepConst K = step_const(b, thermostat, energy);
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
-  const int per_sync = 64;
-  if (b->timing) HMD_TRY(ensure_events(b, size_t(2 * K_COUNT) * per_sync));
-  Launcher L{b, s, b->timing ? &marks : nullptr, 0};
+  const int per_sync = 32;
+  if (b->timing) HMD_TRY(ensure_events(b, size_t(2 * K_COUNT) * per_sync + 2));
+  Launcher L{b, s, b->timing ? &marks : nullptr, 2};
 
   auto direct_step = [&](int64_t k) -> int {
-    enqueue_step(b, L, K);
+    enqueue_step(b, L, K, StepRef{nullptr, b->done});
     if (energy) {
       HMD_HIP(ctx, hipStreamSynchronize(s));
-      const int64_t n = b->done + 1;
-      const int p = int(n & 1);
+      const int p = int((b->done + 1) & 1);
       double pe = 0, ke = 0, vc2 = 0;
       HMD_HIP(ctx, hipMemcpy(&pe, b->acc.pe[p], sizeof(double), hipMemcpyDeviceToHost));
       HMD_HIP(ctx, hipMemcpy(&ke, b->acc.ke[p], sizeof(double), hipMemcpyDeviceToHost));
@@ -452,9 +519,9 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
       energy_trace[k] = (0.5 * (ke + (lam2 - 1.0) * vc2) + pe) / nf;
     }
     b->done += 1;
-    if (b->timing && int(marks.size()) >= per_sync * K_COUNT) {
+    if (b->timing && int(marks.size()) >= per_sync * (K_COUNT - 1)) {
       HMD_TRY(harvest(b, marks));
-      L.next_ev = 0;
+      L.next_ev = 2;
     }
     return HMD_OK;
   };
@@ -464,11 +531,11 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
     if (b->cur != 0) HMD_TRY(direct_step(k++));
     if (b->timing) {
       HMD_TRY(harvest(b, marks));
-      L.next_ev = 0;
+      L.next_ev = 2;
     }
     hipGraphExec_t ex = nullptr;
-    int key = 0;
-    HMD_TRY(get_graph(b, graph_chunk, K, false, &ex, &key));
+    HMD_TRY(get_graph(b, graph_chunk, K, &ex));
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate, b->done);
     while (steps - k >= graph_chunk) {
       if (b->timing) {
         hipEvent_t e0 = b->ev[0], e1 = b->ev[1];
@@ -489,15 +556,7 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
   }
   while (k < steps) HMD_TRY(direct_step(k++));
   if (b->timing) HMD_TRY(harvest(b, marks));
-  // finish the last step: sample it with the Berendsen factor applied
-  const int nt = int(b->ntot);
-  hipLaunchKernelGGL(k_integrate<2>, dim3(blocks_for(nt)), dim3(TPB), 0, s, nt, b->d_sims, b->d_atom_sim,
-                     state_ref(b, b->cur), b->d_f4, b->d_key, b->d_count, b->d_rank, b->acc, b->d_dstate, K);
-  if (b->done > b->P.n_equil) {
-    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate + 2, b->done);
-    b->sampled_upto = b->done;
-  }
-  b->pending = thermostat;
+  b->pending = thermostat && b->done > 0;
   HMD_HIP(ctx, hipGetLastError());
   HMD_HIP(ctx, hipStreamSynchronize(s));
   return HMD_OK;
@@ -510,11 +569,13 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
   const int n = b->S, nb = b->P.n_blocks;
   std::vector<double> blocks(size_t(n) * nb), tsum(3 * size_t(n)), pe(n);
   std::vector<int> status(n);
+  int flags[4] = {0, 0, 0, 0};
   hipStream_t s = ctx->stream;
   HMD_HIP(ctx, hipMemcpyAsync(blocks.data(), b->acc.blocks, 8 * blocks.size(), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(tsum.data(), b->acc.tsum, 8 * tsum.size(), hipMemcpyDeviceToHost, s));
-  HMD_HIP(ctx, hipMemcpyAsync(pe.data(), b->acc.pe[b->done & 1], 8 * size_t(n), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(pe.data(), b->acc.pe[(b->done + 1) & 1], 8 * size_t(n), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(status.data(), b->d_status, 4 * size_t(n), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(flags, b->d_flag, sizeof(flags), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
   const int64_t used = b->n_sample > 0 ? (b->n_sample / nb) * nb : 0;
   const int64_t sampled = std::max<int64_t>(0, std::min(b->done - b->P.n_equil, used));
@@ -524,7 +585,8 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
     const SimDev& D = b->sims[k];
     R.n_fluid = D.nf;
     R.pe = pe[k] * D.inv_nf;
-    int st = (status[k] & 1) ? HMD_EUNSTABLE : HMD_OK;
+    // an overflowing pair list drops interactions: every result is suspect
+    int st = (status[k] & 1) || flags[2] > 0 ? HMD_EUNSTABLE : HMD_OK;
     if (b->n_sample > 0 && sampled == used) {
       const double B = double(b->n_sample / nb);
       std::vector<double> bm(nb);
@@ -553,11 +615,12 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
     }
     R.status = st;
   }
+  if (flags[2] > 0) ctx->err = "pair list overflow: " + std::to_string(flags[2]) + " > capacity";
   return HMD_OK;
 }
 
 // ---------------------------------------------------------------------------
-// single-system hooks (batch of one or more; `sim` selects the system)
+// single-system hooks (`sim` selects the system of the batch)
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -622,7 +685,7 @@ int batch_set_state(hmd_batch* b, int sim, const double* x, const double* v) {
   hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate + 3, int64_t(0));
   b->pending = false;
   StepConst K = step_const(b, b->thermo_on, true);
-  enqueue_sort(b, s, K);
+  sort_now(b, K);
   HMD_TRY(forces_now(b, true));
   HMD_HIP(ctx, hipStreamSynchronize(s));
   return HMD_OK;
@@ -638,7 +701,7 @@ int batch_forces(hmd_batch* b, int sim, float* f, double* pe) {
   HMD_HIP(ctx, hipMemcpyAsync(f4.data(), b->d_f4, sizeof(float4) * b->ntot, hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(tag.data(), b->d_tag[b->cur], 4 * b->ntot, hipMemcpyDeviceToHost, s));
   double pes = 0.0;
-  HMD_HIP(ctx, hipMemcpyAsync(&pes, b->acc.pe[b->done & 1] + sim, 8, hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(&pes, b->acc.pe[(b->done + 1) & 1] + sim, 8, hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
   const SimDev& D = b->sims[sim];
   for (int i = 0; i < D.nf; ++i) {
@@ -657,23 +720,71 @@ int batch_forces(hmd_batch* b, int sim, float* f, double* pe) {
 int batch_cells(hmd_batch* b, int sim, uint32_t* cell_of, uint32_t* counts, uint32_t* order) {
   hmd_ctx* ctx = b->ctx;
   if (sim < 0 || sim >= b->S) return HMD_EINVAL;
-  std::vector<float4> p4(b->ntot);
-  std::vector<int> tag(b->ntot);
   const SimDev& D = b->sims[sim];
-  std::vector<uint32_t> nc(D.ncell);
+  std::vector<int> tag(b->ntot);
+  std::vector<uint32_t> nc(D.ncell), cell(b->ntot);
   hipStream_t s = ctx->stream;
-  HMD_HIP(ctx, hipMemcpyAsync(p4.data(), b->d_pos4, sizeof(float4) * b->ntot, hipMemcpyDeviceToHost, s));
+  if (b->path == 0) {
+    std::vector<float4> p4(b->ntot);
+    HMD_HIP(ctx, hipMemcpyAsync(p4.data(), b->d_pos4, sizeof(float4) * b->ntot, hipMemcpyDeviceToHost, s));
+    HMD_HIP(ctx, hipStreamSynchronize(s));
+    for (int64_t g = 0; g < b->ntot; ++g) {
+      int lc;
+      std::memcpy(&lc, &p4[g].w, 4);
+      cell[g] = uint32_t(lc);
+    }
+  } else {
+    HMD_HIP(ctx, hipMemcpyAsync(cell.data(), b->d_slot_cell, 4 * b->ntot, hipMemcpyDeviceToHost, s));
+    HMD_HIP(ctx, hipStreamSynchronize(s));
+    for (int64_t g = 0; g < b->ntot; ++g) cell[g] -= uint32_t(D.c0);
+  }
   HMD_HIP(ctx, hipMemcpyAsync(tag.data(), b->d_tag[b->cur], 4 * b->ntot, hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(nc.data(), b->d_ncount + D.c0, 4 * size_t(D.ncell), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
   for (int i = 0; i < D.nf; ++i) {
     const int64_t g = D.a0 + i;
-    int lc;
-    std::memcpy(&lc, &p4[g].w, 4);
-    if (cell_of) cell_of[tag[g]] = uint32_t(lc);
+    if (cell_of) cell_of[tag[g]] = cell[g];
     if (order) order[i] = uint32_t(tag[g]);
   }
   if (counts) std::memcpy(counts, nc.data(), 4 * size_t(D.ncell));
+  return HMD_OK;
+}
+
+int batch_neighbors(hmd_batch* b, int sim, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total) {
+  hmd_ctx* ctx = b->ctx;
+  if (sim < 0 || sim >= b->S || b->path != 1) return HMD_EINVAL;
+  const SimDev& D = b->sims[sim];
+  std::vector<uint32_t> nl(b->ntot), list(size_t(b->list_cap) * b->list_ld);
+  std::vector<int> tag(b->ntot);
+  hipStream_t s = ctx->stream;
+  HMD_HIP(ctx, hipMemcpyAsync(nl.data(), b->d_nlist, 4 * b->ntot, hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(list.data(), b->d_list, 4 * list.size(), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(tag.data(), b->d_tag[0], 4 * b->ntot, hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  // per atom id: neighbour ids (fluid ids, or N_f + wall index of the system)
+  std::vector<std::vector<uint32_t>> per(D.nf);
+  int64_t tot = 0;
+  for (int i = 0; i < D.nf; ++i) {
+    const int64_t g = D.a0 + i;
+    auto& v = per[tag[g]];
+    for (uint32_t k = 0; k < nl[g]; ++k) {
+      const uint32_t j = list[size_t(k) * b->list_ld + g];
+      v.push_back(j < uint32_t(b->ntot) ? uint32_t(tag[j])
+                                        : uint32_t(D.nf) + uint32_t(b->wall_id[j - uint32_t(b->ntot)]));
+    }
+    tot += int64_t(v.size());
+  }
+  int64_t w = 0;
+  for (int id = 0; id < D.nf; ++id) {
+    auto& v = per[id];
+    std::sort(v.begin(), v.end());
+    if (counts) counts[id] = uint32_t(v.size());
+    for (uint32_t j : v) {
+      if (idx && w < cap) idx[w] = j;
+      ++w;
+    }
+  }
+  if (total) *total = tot;
   return HMD_OK;
 }
 

