@@ -93,6 +93,7 @@ def main():
     # HIP events around every kernel (per-kernel averages); the rest replays
     # the captured graph, timed as a whole
     tail = min(args.timed_tail, args.steps)
+    builds0 = batch.list_builds()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.run(args.steps - tail, graph_chunk=args.chunk)
@@ -101,7 +102,10 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
     value = batch.atoms * args.steps / wall
-    kern = {k: batch.kernel_ms(k)[0] for k in ("integrate", "scan", "scatter", "reorder", "force", "graph_step")}
+    kern = {k: batch.kernel_ms(k)[0]
+            for k in ("integrate", "keys", "scan", "scatter", "reorder", "list", "force", "graph_step")}
+    cfg = batch.config()
+    builds = batch.list_builds() - builds0
     res = batch.results() if args.warmup + args.steps >= N_EQUIL + N_SAMPLE else []
     log(f"batched: {value:.3e} atom-steps/s, {ms_step:.3f} ms/step, kernels {kern}")
     n_atoms = int(batch.atoms)
@@ -140,10 +144,13 @@ def main():
         "config": {"workload": "batched uneven NEMD channels: 64 systems, h=4+16u, g=0.001+0.049u, "
                                "57.1x57.1 sigma box, rho 0.8, T 1, rc 2.5, dt 0.005, 10k+20k steps, "
                                "FP32 forces / FP64 state and sums",
-                   "systems": len(jobs), "fluid_atoms": n_atoms, "graph_chunk": args.chunk},
+                   "systems": len(jobs), "fluid_atoms": n_atoms, "graph_chunk": args.chunk,
+                   "force_path": "pair list" if cfg["path"] == 1 else "cell list", "skin": cfg["skin"],
+                   "threads_per_block": cfg["tpb"],
+                   "list_builds_per_step": builds / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_force<1>", "avg_ms": force_ms,
+                     "kernel": "k_force_list<1>" if cfg["path"] == 1 else "k_force_cell<1>", "avg_ms": force_ms,
                      "pairs_per_launch": pairs_per_launch, "flop_per_pair": FLOP_PER_PAIR},
         "plain_atom_steps_per_s": plain,
         "batched_over_plain": value / plain if plain else None,

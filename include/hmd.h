@@ -135,6 +135,11 @@ int md_batch_kernel_ms(const hmd_batch* b, const char* kernel, double* ms, int64
  * atom of the full neighbour sum) and wall-fluid pairs.  Runs one extra
  * force evaluation (forces unchanged). */
 int md_batch_pair_count(hmd_batch* b, int64_t* fluid_pairs, int64_t* wall_pairs);
+/* Number of Verlet pair-list builds made since the batch was created or its
+ * state last set (Sec. 2.1 neighbour search; 0 on the cell path).  A build
+ * happens whenever some atom of the batch has moved more than half the skin
+ * since the previous one. */
+int md_batch_list_builds(hmd_batch* b, int64_t* builds);
 /* The implementation choices in use: force path (0 cell, 1 pair list),
  * pair-list skin, threads per block, pair-list capacity per atom. */
 int md_batch_config(const hmd_batch* b, int* path, double* skin, int* tpb, int* list_cap);

@@ -64,6 +64,7 @@ _sig("md_batch_atoms", i64, vp)
 _sig("md_batch_set_timing", i32, vp, i32)
 _sig("md_batch_kernel_ms", i32, vp, _c.c_char_p, P(d), P(i64))
 _sig("md_batch_pair_count", i32, vp, P(i64), P(i64))
+_sig("md_batch_list_builds", i32, vp, P(i64))
 _sig("md_batch_free", None, vp)
 _sig("md_sys_create", i32, vp, d, d, u64, P(vp))
 _sig("md_sys_info", i32, vp, P(i64), P(i64), P(d), P(i32))
@@ -242,6 +243,11 @@ class Batch:
         self.ctx.check(_lib.md_batch_pair_count(self._h, _c.byref(ff), _c.byref(wf)))
         return ff.value, wf.value
 
+    def list_builds(self) -> int:
+        n = i64()
+        self.ctx.check(_lib.md_batch_list_builds(self._h, _c.byref(n)))
+        return n.value
+
     def config(self):
         return _config(_lib.md_batch_config, self._h)
 
@@ -365,9 +371,10 @@ class GP:
 
     def __init__(self, ctx: Context, X, y, y_se=None, hyper: GpHyper = None):
         self.ctx = ctx
-        X = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(len(y), -1))
+        X = np.asarray(X, dtype=np.float64)
+        X = np.ascontiguousarray(X.reshape(len(y), X.shape[-1] if X.ndim == 2 else -1))
         y = np.ascontiguousarray(y, dtype=np.float64)
-        self.d = X.shape[1] if X.size else 2
+        self.d = X.shape[1]
         se = None if y_se is None else np.ascontiguousarray(y_se, dtype=np.float64)
         self._h = vp()
         hp = hyper or gp_hyper()

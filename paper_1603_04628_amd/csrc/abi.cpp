@@ -148,6 +148,11 @@ int md_batch_pair_count(hmd_batch* b, int64_t* fluid_pairs, int64_t* wall_pairs)
   return guarded(b->ctx, [&] { return hmd::batch_pairs(b, fluid_pairs, wall_pairs); });
 }
 
+int md_batch_list_builds(hmd_batch* b, int64_t* builds) {
+  if (!b) return HMD_EINVAL;
+  return guarded(b->ctx, [&] { return hmd::batch_list_builds(b, builds); });
+}
+
 void md_batch_free(hmd_batch* b) { hmd::batch_free(b); }
 
 int md_flux_batch(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_md_result* out) {

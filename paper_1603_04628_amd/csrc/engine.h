@@ -58,6 +58,11 @@ struct SimDev {
   int wc0;                     // wall columns [wc0, wc0 + 2 nx nz)
   int w0;                      // wall atoms [w0, w0 + nw) of the wall arrays
   int nbins, bin0;             // profile bins [bin0, bin0 + nbins)
+  // Cells are numbered in Morton (Z) order of their coordinates so that
+  // consecutive slots form compact 3-D clusters: rank maps the row-major
+  // cell id (cz ny + cy) nx + cx to its place in that order, lin inverts it.
+  const uint32_t* rank;
+  const uint32_t* lin;
 };
 
 // Step constants passed by value.
@@ -100,6 +105,8 @@ struct hmd_batch {
   int list_cap = 0, list_ld = 0;
   std::vector<hmd::HostSystem> host;  // geometry (atom arrays released after upload)
   std::vector<int> wall_id;           // wall slot (column order) -> wall id within its system
+  std::vector<uint32_t> cell_rank;    // per system, concatenated: row-major cell id -> Morton rank
+  uint32_t* d_cellmap = nullptr;      // device copies: rank tables, then inverse tables
   std::vector<hmd::SimDev> sims;
   int64_t ntot = 0, ncell = 0, nwall = 0, nwcell = 0, nbins = 0;
 
@@ -116,7 +123,7 @@ struct hmd_batch {
   uint32_t* d_slot_cell = nullptr;  // pair path: cell of each slot at the last build
   uint32_t* d_list = nullptr;       // pair path: list_cap x list_ld entries
   uint32_t* d_nlist = nullptr;
-  int* d_flag = nullptr;            // [2] rebuild flags by step parity, [2] list overflow
+  int* d_flag = nullptr;            // [2] rebuild flags by step parity, list overflow, builds so far
   uint32_t* d_key = nullptr;        // global cell of each slot
   uint32_t* d_count = nullptr;      // atomic counters per cell
   uint32_t* d_rank = nullptr;       // arrival rank of each slot inside its new cell
@@ -162,6 +169,7 @@ int batch_forces(hmd_batch* b, int sim, float* f, double* pe);
 int batch_cells(hmd_batch* b, int sim, uint32_t* cell_of, uint32_t* counts, uint32_t* order);
 int batch_profile(hmd_batch* b, int sim, double* mvx, double* cnt);
 int batch_pairs(hmd_batch* b, int64_t* ff, int64_t* wf);
+int batch_list_builds(hmd_batch* b, int64_t* builds);
 int batch_neighbors(hmd_batch* b, int sim, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total);
 // Resolved implementation choices for a batch of these jobs on this context.
 void choose_path(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int* path, double* skin, int* tpb);

@@ -61,6 +61,17 @@ int dalloc(hmd_ctx* ctx, T** p, int64_t n) {
   return HMD_OK;
 }
 
+// 3-D Morton code: bits of x, y, z interleaved (x lowest).
+uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  uint64_t m = 0;
+  for (int b = 0; b < 21; ++b) {
+    m |= uint64_t((x >> b) & 1u) << (3 * b);
+    m |= uint64_t((y >> b) & 1u) << (3 * b + 1);
+    m |= uint64_t((z >> b) & 1u) << (3 * b + 2);
+  }
+  return m;
+}
+
 uint32_t fix_axis_host(double v, double scale) {
   double t = v * scale;
   t = t < 0.0 ? 0.0 : (t > 4294967295.0 ? 4294967295.0 : t);
@@ -373,6 +384,28 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   for (int w = 0; w < 2; ++w)
     for (int a = 0; a < 6; ++a)
       if ((rc = dalloc(ctx, &b->d_state[w][a], b->ntot))) return fail(rc);
+  // Morton numbering of every system's cells (rank tables, then inverses)
+  if ((rc = dalloc(ctx, &b->d_cellmap, 2 * b->ncell))) return fail(rc);
+  b->cell_rank.assign(b->ncell, 0);
+  std::vector<uint32_t> cell_lin(b->ncell);
+  for (int k = 0; k < n; ++k) {
+    SimDev& D = b->sims[k];
+    std::vector<std::pair<uint64_t, uint32_t>> order(D.ncell);
+    for (int lid = 0; lid < D.ncell; ++lid) {
+      const uint32_t cx = lid % D.nx, cy = (lid / D.nx) % D.ny, cz = lid / (D.nx * D.ny);
+      order[lid] = {morton3(cx, cy, cz), uint32_t(lid)};
+    }
+    std::sort(order.begin(), order.end());
+    for (int r = 0; r < D.ncell; ++r) {
+      b->cell_rank[D.c0 + order[r].second] = uint32_t(r);
+      cell_lin[D.c0 + r] = order[r].second;
+    }
+    D.rank = b->d_cellmap + D.c0;
+    D.lin = b->d_cellmap + b->ncell + D.c0;
+  }
+  HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap, b->cell_rank.data(), 4 * b->ncell, hipMemcpyHostToDevice, ctx->stream));
+  HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap + b->ncell, cell_lin.data(), 4 * b->ncell, hipMemcpyHostToDevice,
+                              ctx->stream));
   const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->P.n_blocks + 3 * int64_t(n) + 2 * b->nbins;
   if ((rc = dalloc(ctx, &b->d_accbuf, nacc)) || (rc = dalloc(ctx, &b->d_status, n)) ||
       (rc = dalloc(ctx, &b->acc.pairs, 2)))
@@ -479,7 +512,7 @@ void batch_free(hmd_batch* b) {
   void* ptrs[] = {b->d_sims, b->d_atom_sim, b->d_cell_sim, b->d_f4, b->d_pos4, b->d_pfix, b->d_pbuild,
                   b->d_slot_cell, b->d_list, b->d_nlist, b->d_flag, b->d_key, b->d_count, b->d_rank, b->d_start,
                   b->d_ncount, b->d_perm, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_dstate, b->d_tag[0],
-                  b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs};
+                  b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs, b->d_cellmap};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int w = 0; w < 2; ++w)
@@ -734,19 +767,29 @@ int batch_cells(hmd_batch* b, int sim, uint32_t* cell_of, uint32_t* counts, uint
       cell[g] = uint32_t(lc);
     }
   } else {
+    // slots carry the Morton-ordered cell; report the row-major id
+    std::vector<uint32_t> lin(D.ncell);
+    for (int lid = 0; lid < D.ncell; ++lid) lin[b->cell_rank[D.c0 + lid]] = uint32_t(lid);
     HMD_HIP(ctx, hipMemcpyAsync(cell.data(), b->d_slot_cell, 4 * b->ntot, hipMemcpyDeviceToHost, s));
     HMD_HIP(ctx, hipStreamSynchronize(s));
-    for (int64_t g = 0; g < b->ntot; ++g) cell[g] -= uint32_t(D.c0);
+    for (int64_t g = D.a0; g < D.a0 + D.nf; ++g) cell[g] = lin[cell[g] - uint32_t(D.c0)];
   }
+  std::vector<uint32_t> st(D.ncell);
   HMD_HIP(ctx, hipMemcpyAsync(tag.data(), b->d_tag[b->cur], 4 * b->ntot, hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(nc.data(), b->d_ncount + D.c0, 4 * size_t(D.ncell), hipMemcpyDeviceToHost, s));
+  HMD_HIP(ctx, hipMemcpyAsync(st.data(), b->d_start + D.c0, 4 * size_t(D.ncell), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
-  for (int i = 0; i < D.nf; ++i) {
-    const int64_t g = D.a0 + i;
-    if (cell_of) cell_of[tag[g]] = cell[g];
-    if (order) order[i] = uint32_t(tag[g]);
+  if (cell_of)
+    for (int i = 0; i < D.nf; ++i) cell_of[tag[D.a0 + i]] = cell[D.a0 + i];
+  // counts and members are stored in Morton order of the cells; report them
+  // in row-major cell order, members in the library's order inside a cell
+  int64_t w = 0;
+  for (int lid = 0; lid < D.ncell; ++lid) {
+    const uint32_t key = b->cell_rank[D.c0 + lid];
+    if (counts) counts[lid] = nc[key];
+    for (uint32_t m = 0; m < nc[key]; ++m, ++w)
+      if (order) order[w] = uint32_t(tag[st[key] + m]);
   }
-  if (counts) std::memcpy(counts, nc.data(), 4 * size_t(D.ncell));
   return HMD_OK;
 }
 
@@ -768,7 +811,7 @@ int batch_neighbors(hmd_batch* b, int sim, uint32_t* counts, uint32_t* idx, int6
     const int64_t g = D.a0 + i;
     auto& v = per[tag[g]];
     for (uint32_t k = 0; k < nl[g]; ++k) {
-      const uint32_t j = list[size_t(k) * b->list_ld + g];
+      const uint32_t j = list[(size_t(k >> 2) * b->list_ld + size_t(g)) * 4 + (k & 3u)];
       v.push_back(j < uint32_t(b->ntot) ? uint32_t(tag[j])
                                         : uint32_t(D.nf) + uint32_t(b->wall_id[j - uint32_t(b->ntot)]));
     }
@@ -796,6 +839,15 @@ int batch_pairs(hmd_batch* b, int64_t* ff, int64_t* wf) {
   HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (ff) *ff = int64_t(h[0]);
   if (wf) *wf = int64_t(h[1]);
+  return HMD_OK;
+}
+
+int batch_list_builds(hmd_batch* b, int64_t* builds) {
+  hmd_ctx* ctx = b->ctx;
+  int flags[4] = {0, 0, 0, 0};
+  HMD_HIP(ctx, hipMemcpyAsync(flags, b->d_flag, sizeof(flags), hipMemcpyDeviceToHost, ctx->stream));
+  HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (builds) *builds = b->path == 1 ? int64_t(flags[3]) : 0;
   return HMD_OK;
 }
 

@@ -76,6 +76,17 @@ __device__ __forceinline__ float3 fixed_sep(const int4& a, const int4& b, const 
 
 __device__ __forceinline__ int64_t step_n(const StepRef& R) { return (R.base ? *R.base : 0) + R.k; }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// Renumber them so every XCD walks one contiguous range of slots: spatially
+// sorted neighbours then share that XCD's L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb / NXCD, rem = nb % NXCD;
+  const int x = b % NXCD, r = b / NXCD;
+  return x < rem ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
+}
+
 __device__ __forceinline__ bool rebuild_needed(const int* flag, const StepRef& R) {
   return flag == nullptr || flag[(step_n(R) + 1) & 1] != 0;
 }
@@ -123,7 +134,7 @@ __global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __res
                                                    int4* __restrict__ pfix, const int4* __restrict__ pbuild,
                                                    int* __restrict__ flag, Acc acc, const int64_t* __restrict__ dstate,
                                                    StepRef R, StepConst K) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   const bool valid = i < ntot;
   const int s = valid ? int(atom_sim[i]) : 0;
   const SimDev& D = sims[s];
@@ -178,7 +189,7 @@ __global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __res
     const int cx = dcell(r[0], D.inv_x, D.nx);
     const int cy = dcell(r[1], D.inv_y, D.ny);
     const int cz = dcell(r[2], D.inv_z, D.nz);
-    c = uint32_t(D.c0 + (cz * D.ny + cy) * D.nx + cx);
+    c = uint32_t(D.c0) + D.rank[(cz * D.ny + cy) * D.nx + cx];
     key[i] = c;
   }
   rank_in_cell(valid, c, count, rank, i);
@@ -190,7 +201,7 @@ __global__ __launch_bounds__(256) void k_keys(int ntot, const SimDev* __restrict
                                               uint32_t* __restrict__ key, uint32_t* __restrict__ count,
                                               uint32_t* __restrict__ rank, const int* __restrict__ flag, StepRef R) {
   if (!rebuild_needed(flag, R)) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   const bool valid = i < ntot;
   uint32_t c = 0;
   if (valid) {
@@ -198,7 +209,7 @@ __global__ __launch_bounds__(256) void k_keys(int ntot, const SimDev* __restrict
     const int cx = dcell(st.x[i], D.inv_x, D.nx);
     const int cy = dcell(st.y[i], D.inv_y, D.ny);
     const int cz = dcell(st.z[i], D.inv_z, D.nz);
-    c = uint32_t(D.c0 + (cz * D.ny + cy) * D.nx + cx);
+    c = uint32_t(D.c0) + D.rank[(cz * D.ny + cy) * D.nx + cx];
     key[i] = c;
   }
   rank_in_cell(valid, c, count, rank, i);
@@ -257,7 +268,7 @@ __global__ __launch_bounds__(256) void k_scatter(int ntot, const uint32_t* __res
                                                  const uint32_t* __restrict__ rank, uint32_t* __restrict__ perm,
                                                  const int* __restrict__ flag, StepRef R) {
   if (!rebuild_needed(flag, R)) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= ntot) return;
   perm[start[key[i]] + rank[i]] = uint32_t(i);
 }
@@ -292,7 +303,7 @@ __global__ __launch_bounds__(256) void k_reorder(int ntot, const SimDev* __restr
   dst.vx[d] = src.vx[p]; dst.vy[d] = src.vy[p]; dst.vz[d] = src.vz[p];
   tag_dst[d] = tag_src[p];
   const SimDev& D = sims[cell_sim[c]];
-  const int lc = int(c) - D.c0;
+  const int lc = int(D.lin[int(c) - D.c0]);  // row-major id of the cell
   if (PATH == 0) {
     const int cx = lc % D.nx, cy = (lc / D.nx) % D.ny, cz = lc / (D.nx * D.ny);
     pos4[d] = make_float4(float(x - double(cx) * D.wx), float(y - double(cy) * D.wy),
@@ -320,15 +331,20 @@ __global__ __launch_bounds__(256) void k_build_list(int ntot, int ld, int cap, c
                                                     int* __restrict__ overflow, const int* __restrict__ flag,
                                                     StepRef R, float rl2) {
   if (!rebuild_needed(flag, R)) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= ntot) return;
   to.x[i] = from.x[i]; to.y[i] = from.y[i]; to.z[i] = from.z[i];
   to.vx[i] = from.vx[i]; to.vy[i] = from.vy[i]; to.vz[i] = from.vz[i];
   tag_to[i] = tag_from[i];
   const SimDev& D = sims[atom_sim[i]];
   const int4 me = pfix[i];
-  const int lc = int(slot_cell[i]) - D.c0;
+  const int lc = int(D.lin[int(slot_cell[i]) - D.c0]);
   const int cx = lc % D.nx, cy = (lc / D.nx) % D.ny, cz = lc / (D.nx * D.ny);
+  if (i == 0) atomicAdd(&overflow[1], 1);  // builds so far
+  // entries go out four at a time: group g of slot i is the 16 bytes at
+  // (g * ld + i) * 4, so a wave's k-th groups form one contiguous run
+  uint4* list4 = reinterpret_cast<uint4*>(list);
+  uint4 buf = make_uint4(0u, 0u, 0u, 0u);
   uint32_t cnt = 0;
   for (int oz = -1; oz <= 1; ++oz) {
     int jz = cz + oz;
@@ -341,7 +357,7 @@ __global__ __launch_bounds__(256) void k_build_list(int ntot, int ld, int cap, c
         jx += jx < 0 ? D.nx : (jx >= D.nx ? -D.nx : 0);
         uint32_t b, e, off;
         if (!wall) {
-          const uint32_t gc = uint32_t(D.c0 + (jz * D.ny + jy) * D.nx + jx);
+          const uint32_t gc = uint32_t(D.c0) + D.rank[(jz * D.ny + jy) * D.nx + jx];
           b = start[gc];
           e = b + ncount[gc];
           off = 0;
@@ -356,15 +372,21 @@ __global__ __launch_bounds__(256) void k_build_list(int ntot, int ld, int cap, c
           const float3 d = fixed_sep(me, pfix[q], D);
           const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
           if (r2 < rl2 && q != uint32_t(i)) {
-            if (cnt < uint32_t(cap)) list[size_t(cnt) * ld + i] = q;
+            const uint32_t t = cnt & 3u;
+            buf.x = t == 0 ? q : buf.x;
+            buf.y = t == 1 ? q : buf.y;
+            buf.z = t == 2 ? q : buf.z;
+            buf.w = t == 3 ? q : buf.w;
+            if (t == 3 && cnt < uint32_t(cap)) list4[size_t(cnt >> 2) * ld + i] = buf;
             ++cnt;
           }
         }
       }
     }
   }
+  if ((cnt & 3u) != 0 && cnt < uint32_t(cap)) list4[size_t(cnt >> 2) * ld + i] = buf;
   if (cnt > uint32_t(cap)) {
-    atomicMax(overflow, int(cnt));
+    atomicMax(&overflow[0], int(cnt));
     cnt = cap;
   }
   nlist[i] = cnt;
@@ -484,7 +506,7 @@ __global__ __launch_bounds__(256) void k_force_cell(int ntot, const SimDev* __re
   __shared__ double lds_vx[BIN_LDS];
   __shared__ double lds_cnt[BIN_LDS];
   __shared__ int lds_base;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   const bool valid = i < ntot;
   const int s = valid ? int(atom_sim[i]) : 0;
   float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
@@ -507,7 +529,7 @@ __global__ __launch_bounds__(256) void k_force_cell(int ntot, const SimDev* __re
           jx += jx < 0 ? D.nx : (jx >= D.nx ? -D.nx : 0);
           const float ax = me.x - float(ox) * D.fwx;
           if (!wall) {
-            const uint32_t gc = uint32_t(D.c0 + (jz * D.ny + jy) * D.nx + jx);
+            const uint32_t gc = uint32_t(D.c0) + D.rank[(jz * D.ny + jy) * D.nx + jx];
             const uint32_t b = start[gc], e = b + ncount[gc];
             for (uint32_t j = b; j < e; ++j) {
               const float4 o = pos4[j];
@@ -575,7 +597,7 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
   __shared__ double lds_vx[BIN_LDS];
   __shared__ double lds_cnt[BIN_LDS];
   __shared__ int lds_base;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   const bool valid = i < ntot;
   const int s = valid ? int(atom_sim[i]) : 0;
   float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
@@ -584,10 +606,9 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
     const SimDev& D = sims[s];
     const int4 me = pfix[i];
     const uint32_t n = nlist[i];
-    const uint32_t* col = list + i;
-    for (uint32_t k = 0; k < n; ++k) {
-      const uint32_t j = col[size_t(k) * ld];
-      const float3 d = fixed_sep(me, pfix[j], D);
+    const uint4* grp = reinterpret_cast<const uint4*>(list) + i;  // group g at grp[g * ld]
+    auto pair = [&](uint32_t j, const int4& o) {
+      const float3 d = fixed_sep(me, o, D);
       const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
       if (r2 < K.rc2) {
         const bool wall = j >= uint32_t(ntot);
@@ -607,6 +628,24 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
           }
         }
       }
+    };
+    // one coalesced 16-byte load brings four entries; their four gathers are
+    // in flight together, then their arithmetic
+    const uint32_t full = n >> 2;
+    for (uint32_t g = 0; g < full; ++g) {
+      const uint4 jj = grp[size_t(g) * ld];
+      const int4 o0 = pfix[jj.x], o1 = pfix[jj.y], o2 = pfix[jj.z], o3 = pfix[jj.w];
+      pair(jj.x, o0);
+      pair(jj.y, o1);
+      pair(jj.z, o2);
+      pair(jj.w, o3);
+    }
+    const uint32_t rest = n & 3u;
+    if (rest) {
+      const uint4 jj = grp[size_t(full) * ld];
+      pair(jj.x, pfix[jj.x]);
+      if (rest > 1) pair(jj.y, pfix[jj.y]);
+      if (rest > 2) pair(jj.z, pfix[jj.z]);
     }
     f4[i] = make_float4(fx, fy, fz, pe);
   }

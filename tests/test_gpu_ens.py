@@ -52,7 +52,8 @@ def test_trained_ensemble_tracks_oracle(ctx):
     rms = np.sqrt(np.mean(y ** 2))
     assert np.abs(mg - mo).max() <= 0.01 * rms
     assert np.abs(sg - so).max() <= 0.01 * rms
-    assert np.sqrt(np.mean((mg - yq) ** 2)) < 0.1 * rms
+    # held-out targets carry noise of 0.003 (about 13% of their RMS)
+    assert np.sqrt(np.mean((mg - yq) ** 2)) < 0.2 * rms
 
 
 def test_single_member_has_zero_spread(ctx):
