@@ -58,6 +58,36 @@ def cpu_baseline(budget_s: float):
                       f"in {dt:.1f} s, FP64, OpenMP over atoms"}
 
 
+def copy_calibration(mib: int):
+    """A plain device copy of known size (mib MiB read, mib MiB written),
+    three times: what a hardware byte counter reads for it calibrates the
+    same counter on the force kernel."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copied {mib} MiB three times")
+
+
+def summarize_pmc(path: str, kernel: str):
+    """Mean per-dispatch value of each counter in a rocprofv3 counter
+    collection CSV, over the dispatches whose kernel name contains `kernel`."""
+    import csv
+    sums, counts = {}, {}
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if kernel not in row["Kernel_Name"]:
+                continue
+            k = row["Counter_Name"]
+            sums[k] = sums.get(k, 0.0) + float(row["Counter_Value"])
+            counts[k] = counts.get(k, 0) + 1
+    for k in sorted(sums):
+        print(f"{kernel}\t{k}\tdispatches={counts[k]}\tmean={sums[k] / counts[k]:.6g}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,7 +99,18 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--summarize-pmc", default="", metavar="CSV",
+                    help="only print per-dispatch counter means of --kernel from a rocprofv3 CSV")
+    ap.add_argument("--kernel", default="k_force_list")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.kernel)
+        return
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (independent micro-solves "
               "would shard by bin-packing systems across GPUs with no communication during MD)", file=sys.stderr)
@@ -150,7 +191,7 @@ def main():
                    "list_builds_per_step": builds / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_force_list<1>" if cfg["path"] == 1 else "k_force_cell<1>", "avg_ms": force_ms,
+                     "kernel": "k_force_list<1, 0>" if cfg["path"] == 1 else "k_force_cell<1>", "avg_ms": force_ms,
                      "pairs_per_launch": pairs_per_launch, "flop_per_pair": FLOP_PER_PAIR},
         "plain_atom_steps_per_s": plain,
         "batched_over_plain": value / plain if plain else None,

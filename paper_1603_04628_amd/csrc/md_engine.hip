@@ -163,12 +163,10 @@ void enqueue_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K, St
                          b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
                          b->acc, b->d_dstate, R, K);
   } else {
-    if (mode == 0)
-      hipLaunchKernelGGL(k_force_list<0>, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims, b->d_atom_sim,
-                         b->d_pfix, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
-    else
-      hipLaunchKernelGGL(k_force_list<1>, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims, b->d_atom_sim,
-                         b->d_pfix, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
+    auto* kern = mode == 0 ? (K.energy_on ? k_force_list<0, 1> : k_force_list<0, 0>)
+                           : (K.energy_on ? k_force_list<1, 1> : k_force_list<1, 0>);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims, b->d_atom_sim, b->d_pfix,
+                       b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
   }
 }
 

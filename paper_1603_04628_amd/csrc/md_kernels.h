@@ -46,7 +46,7 @@ __global__ void k_force_cell(int ntot, const SimDev* sims, const uint16_t* atom_
                              const uint32_t* start, const uint32_t* ncount, const float4* wpos4,
                              const uint32_t* wstart, const uint32_t* wcount, float4* f4, StateRef st, Acc acc,
                              int64_t* dstate, StepRef R, StepConst K);
-template <int MODE>
+template <int MODE, int ENERGY>
 __global__ void k_force_list(int ntot, int ld, const SimDev* sims, const uint16_t* atom_sim, const int4* pfix,
                              const uint32_t* list, const uint32_t* nlist, float4* f4, StateRef st, Acc acc,
                              int64_t* dstate, StepRef R, StepConst K);

@@ -146,14 +146,17 @@ __global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __res
   if (MODE == 1) {
     const int64_t n = step_n(R);  // steps completed before this one
     if (valid && dstate[3] != 0) {
-      const double Tc = acc.vc2[n & 1][s] * D.inv_nf;
-      v[K.axis] *= sqrt(1.0 + K.dt_tau * (K.T0 / Tc - 1.0));
+      const double Tc = ((n & 1) ? acc.vc2[1] : acc.vc2[0])[s] * D.inv_nf;
+      const double lam = sqrt(1.0 + K.dt_tau * (K.T0 / Tc - 1.0));
+      v[0] *= K.axis == 0 ? lam : 1.0;
+      v[1] *= K.axis == 1 ? lam : 1.0;
+      v[2] *= K.axis == 2 ? lam : 1.0;
     }
     if (valid && i == D.a0) {
       const int p = int((n + 1) & 1);
-      acc.vc2[p][s] = 0.0;
-      acc.pe[p][s] = 0.0;
-      acc.ke[p][s] = 0.0;
+      (p ? acc.vc2[1] : acc.vc2[0])[s] = 0.0;
+      (p ? acc.pe[1] : acc.pe[0])[s] = 0.0;
+      (p ? acc.ke[1] : acc.ke[0])[s] = 0.0;
     }
     if (PATH == 1 && i == 0 && flag) flag[n & 1] = 0;
     if (valid) {
@@ -404,28 +407,36 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   const int64_t nstep = step_n(R) + 1;
   const int p = int(nstep & 1);
   double vc2 = 0.0, ke = 0.0, pes = valid ? double(pe) : 0.0;
-  double v[3] = {0, 0, 0};
+  // scalars, not an array indexed by the run-time axis (that would live in
+  // private memory)
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
   if (MODE == 1 && valid) {
     const SimDev& D = sims[s];
-    v[0] = st.vx[i] + K.hdt * (double(fx) + D.g);
-    v[1] = st.vy[i] + K.hdt * double(fy);
-    v[2] = st.vz[i] + K.hdt * double(fz);
-    st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
-    vc2 = v[K.axis] * v[K.axis];
-    ke = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    v0 = st.vx[i] + K.hdt * (double(fx) + D.g);
+    v1 = st.vy[i] + K.hdt * double(fy);
+    v2 = st.vz[i] + K.hdt * double(fz);
+    st.vx[i] = v0; st.vy[i] = v1; st.vz[i] = v2;
+    const double vc = K.axis == 0 ? v0 : (K.axis == 1 ? v1 : v2);
+    vc2 = vc * vc;
+    ke = v0 * v0 + v1 * v1 + v2 * v2;
   }
   if (MODE == 1 || K.energy_on) {
+    // parity-selected accumulators picked by value (indexing the by-value
+    // pointer arrays with p would copy them to private memory)
+    double* const acc_vc2 = p ? acc.vc2[1] : acc.vc2[0];
+    double* const acc_ke = p ? acc.ke[1] : acc.ke[0];
+    double* const acc_pe = p ? acc.pe[1] : acc.pe[0];
     if (wave_uniform(valid ? s : -1)) {
       vc2 = wave_sum(vc2);
       if (K.energy_on) { ke = wave_sum(ke); pes = wave_sum(pes); }
       const int sw = __shfl(s, 0);
       if ((threadIdx.x & (WAVE - 1)) == 0) {
-        if (MODE == 1) atomicAdd(&acc.vc2[p][sw], vc2);
-        if (K.energy_on) { atomicAdd(&acc.ke[p][sw], ke); atomicAdd(&acc.pe[p][sw], pes); }
+        if (MODE == 1) atomicAdd(&acc_vc2[sw], vc2);
+        if (K.energy_on) { atomicAdd(&acc_ke[sw], ke); atomicAdd(&acc_pe[sw], pes); }
       }
     } else if (valid) {
-      if (MODE == 1) atomicAdd(&acc.vc2[p][s], vc2);
-      if (K.energy_on) { atomicAdd(&acc.ke[p][s], ke); atomicAdd(&acc.pe[p][s], pes); }
+      if (MODE == 1) atomicAdd(&acc_vc2[s], vc2);
+      if (K.energy_on) { atomicAdd(&acc_ke[s], ke); atomicAdd(&acc_pe[s], pes); }
     }
   }
   if (MODE != 1) return;
@@ -436,22 +447,27 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   const int64_t b = (ns - K.r) / K.B;
   if (b >= K.nb) return;
   const double a = K.thermo_on ? K.dt_tau : 0.0;
-  double q[4] = {v[0], v[0] * v[0], v[1] * v[1], v[2] * v[2]};
-  if (valid) q[1 + K.axis] = (1.0 - a) * q[1 + K.axis] + a * K.T0;
-  if (!valid) q[0] = q[1] = q[2] = q[3] = 0.0;
+  double q0 = v0, q1 = v0 * v0, q2 = v1 * v1, q3 = v2 * v2;
+  if (K.axis == 0) q1 = (1.0 - a) * q1 + a * K.T0;
+  else if (K.axis == 1) q2 = (1.0 - a) * q2 + a * K.T0;
+  else q3 = (1.0 - a) * q3 + a * K.T0;
+  if (!valid) q0 = q1 = q2 = q3 = 0.0;
   if (wave_uniform(valid ? s : -1)) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = wave_sum(q[k]);
+    q0 = wave_sum(q0); q1 = wave_sum(q1); q2 = wave_sum(q2); q3 = wave_sum(q3);
     const int sw = __shfl(s, 0);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
       const SimDev& Dw = sims[sw];
-      atomicAdd(&acc.blocks[int64_t(sw) * K.nb + b], q[0] * Dw.inv_area);
-      for (int k = 0; k < 3; ++k) atomicAdd(&acc.tsum[3 * sw + k], q[1 + k] * Dw.inv_nf);
+      atomicAdd(&acc.blocks[int64_t(sw) * K.nb + b], q0 * Dw.inv_area);
+      atomicAdd(&acc.tsum[3 * sw + 0], q1 * Dw.inv_nf);
+      atomicAdd(&acc.tsum[3 * sw + 1], q2 * Dw.inv_nf);
+      atomicAdd(&acc.tsum[3 * sw + 2], q3 * Dw.inv_nf);
     }
   } else if (valid) {
     const SimDev& D = sims[s];
-    atomicAdd(&acc.blocks[int64_t(s) * K.nb + b], q[0] * D.inv_area);
-    for (int k = 0; k < 3; ++k) atomicAdd(&acc.tsum[3 * s + k], q[1 + k] * D.inv_nf);
+    atomicAdd(&acc.blocks[int64_t(s) * K.nb + b], q0 * D.inv_area);
+    atomicAdd(&acc.tsum[3 * s + 0], q1 * D.inv_nf);
+    atomicAdd(&acc.tsum[3 * s + 1], q2 * D.inv_nf);
+    atomicAdd(&acc.tsum[3 * s + 2], q3 * D.inv_nf);
   }
   if (!K.bins_on) return;
   // wall-normal profile: aggregate in LDS relative to the block's lowest bin
@@ -471,10 +487,10 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   if (gb >= 0) {
     const int o = gb - base;
     if (o < BIN_LDS) {
-      atomicAdd(&lds_vx[o], v[0]);
+      atomicAdd(&lds_vx[o], v0);
       atomicAdd(&lds_cnt[o], 1.0);
     } else {
-      atomicAdd(&acc.binvx[gb], v[0]);
+      atomicAdd(&acc.binvx[gb], v0);
       atomicAdd(&acc.bincnt[gb], 1.0);
     }
   }
@@ -587,7 +603,7 @@ __global__ __launch_bounds__(256) void k_force_cell(int ntot, const SimDev* __re
 // slot's Verlet list (entries >= ntot are wall atoms), FP32 from fixed-point
 // separations.
 // ---------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, int ENERGY>
 __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimDev* __restrict__ sims,
                                                     const uint16_t* __restrict__ atom_sim,
                                                     const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
@@ -607,49 +623,50 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
     const int4 me = pfix[i];
     const uint32_t n = nlist[i];
     const uint4* grp = reinterpret_cast<const uint4*>(list) + i;  // group g at grp[g * ld]
+    // Shifted LJ (Eq. LJ) for one list entry; entries past the cut-off add
+    // zero through a select rather than a branch.
     auto pair = [&](uint32_t j, const int4& o) {
       const float3 d = fixed_sep(me, o, D);
       const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-      if (r2 < K.rc2) {
-        const bool wall = j >= uint32_t(ntot);
-        const float ri2 = 1.0f / r2;
-        const float s2 = wall ? K.sig2_wf * ri2 : ri2;
-        const float s6 = s2 * s2 * s2;
-        const float eps24 = wall ? 24.0f * K.eps_wf : 24.0f;
-        const float fr = eps24 * s6 * (2.0f * s6 - 1.0f) * ri2;
-        fx += fr * d.x; fy += fr * d.y; fz += fr * d.z;
-        if (K.energy_on) {
-          if (wall) {
-            pe += 4.0f * K.eps_wf * s6 * (s6 - 1.0f) - K.ush_wf;
-            ++nwf;
-          } else {
-            pe += 0.5f * (4.0f * s6 * (s6 - 1.0f) - K.ush_ff);
-            ++nff;
-          }
-        }
+      const bool in = r2 < K.rc2;
+      const bool wall = j >= uint32_t(ntot);
+      const float ri2 = __builtin_amdgcn_rcpf(r2);  // 1 ulp
+      const float s2 = wall ? K.sig2_wf * ri2 : ri2;
+      const float s6 = s2 * s2 * s2;
+      const float eps24 = wall ? 24.0f * K.eps_wf : 24.0f;
+      const float fr = in ? eps24 * s6 * (2.0f * s6 - 1.0f) * ri2 : 0.0f;
+      fx += fr * d.x; fy += fr * d.y; fz += fr * d.z;
+      if (ENERGY) {
+        const float u = wall ? 4.0f * K.eps_wf * s6 * (s6 - 1.0f) - K.ush_wf
+                             : 0.5f * (4.0f * s6 * (s6 - 1.0f) - K.ush_ff);
+        pe += in ? u : 0.0f;
+        nwf += (in && wall) ? 1u : 0u;
+        nff += (in && !wall) ? 1u : 0u;
       }
     };
-    // one coalesced 16-byte load brings four entries; their four gathers are
-    // in flight together, then their arithmetic
-    const uint32_t full = n >> 2;
+    // One coalesced 16-byte load brings four entries.  The next group's load
+    // is issued before this group's arithmetic so that its latency overlaps
+    // the four position gathers and the pair terms.
+    const uint32_t full = n >> 2, rest = n & 3u, ngrp = (n + 3u) >> 2;
+    uint4 jj = ngrp ? grp[0] : make_uint4(0u, 0u, 0u, 0u);
     for (uint32_t g = 0; g < full; ++g) {
-      const uint4 jj = grp[size_t(g) * ld];
       const int4 o0 = pfix[jj.x], o1 = pfix[jj.y], o2 = pfix[jj.z], o3 = pfix[jj.w];
+      const uint32_t gn = g + 1 < ngrp ? g + 1 : g;
+      const uint4 jn = grp[size_t(gn) * ld];
       pair(jj.x, o0);
       pair(jj.y, o1);
       pair(jj.z, o2);
       pair(jj.w, o3);
+      jj = jn;
     }
-    const uint32_t rest = n & 3u;
-    if (rest) {
-      const uint4 jj = grp[size_t(full) * ld];
+    if (rest) {  // jj holds the partial last group
       pair(jj.x, pfix[jj.x]);
       if (rest > 1) pair(jj.y, pfix[jj.y]);
       if (rest > 2) pair(jj.z, pfix[jj.z]);
     }
     f4[i] = make_float4(fx, fy, fz, pe);
   }
-  if (K.energy_on) {
+  if (ENERGY) {
     const unsigned long long a = wave_sum((unsigned long long)nff), w = wave_sum((unsigned long long)nwf);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
       atomicAdd(&acc.pairs[0], a);
@@ -683,9 +700,14 @@ template __global__ void k_force_cell<0>(int, const SimDev*, const uint16_t*, co
 template __global__ void k_force_cell<1>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
                                          const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
                                          StateRef, Acc, int64_t*, StepRef, StepConst);
-template __global__ void k_force_list<0>(int, int, const SimDev*, const uint16_t*, const int4*, const uint32_t*,
-                                         const uint32_t*, float4*, StateRef, Acc, int64_t*, StepRef, StepConst);
-template __global__ void k_force_list<1>(int, int, const SimDev*, const uint16_t*, const int4*, const uint32_t*,
-                                         const uint32_t*, float4*, StateRef, Acc, int64_t*, StepRef, StepConst);
+#define HMD_FORCE_LIST(M, E)                                                                          \
+  template __global__ void k_force_list<M, E>(int, int, const SimDev*, const uint16_t*, const int4*,          \
+                                              const uint32_t*, const uint32_t*, float4*, StateRef, Acc,       \
+                                              int64_t*, StepRef, StepConst);
+HMD_FORCE_LIST(0, 0)
+HMD_FORCE_LIST(0, 1)
+HMD_FORCE_LIST(1, 0)
+HMD_FORCE_LIST(1, 1)
+#undef HMD_FORCE_LIST
 
 }  // namespace hmd
