@@ -99,6 +99,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--skin", type=float, default=0.3, help="pair-list skin (sigma)")
+    ap.add_argument("--force-path", type=int, default=-1, help="0 cell lists, 1 pair lists, -1 library choice")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate configurations first (outside the timed region) and use the fastest")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--summarize-pmc", default="", metavar="CSV",
@@ -121,8 +125,13 @@ def main():
     import paper_1603_04628_amd as hmd
 
     jobs = workloads.batch_jobs(64)
-    params = hmd.Params(n_equil=N_EQUIL, **workloads.batch_box())
+    params = hmd.Params(n_equil=N_EQUIL, skin=args.skin, force_path=args.force_path, **workloads.batch_box())
     ctx = hmd.Context(params)
+    tune_table = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tune_table = hmd.md_autotune(ctx, [(j.h, j.g, j.seed, N_SAMPLE) for j in jobs], probe_steps=200)
+        log(f"autotune in {time.perf_counter() - t0:.1f} s: {tune_table.tolist()}")
     t0 = time.perf_counter()
     batch = hmd.Batch(ctx, [(j.h, j.g, j.seed, N_SAMPLE) for j in jobs])
     log(f"batch set up in {time.perf_counter() - t0:.1f} s: {batch.atoms} fluid atoms")
