@@ -348,6 +348,8 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     return HMD_EINVAL;
   }
   b->ntot = a0; b->ncell = c0; b->nwcell = wc0; b->nbins = bin0; b->nwall = w0;
+  // the pair-list build packs a position index into 24 bits
+  if (b->path == 1 && b->ntot + b->nwall >= (int64_t(1) << 24)) b->path = 0;
   // pair-list capacity: neighbours within rc + skin at twice the fluid density
   // plus a wall half-space, rounded up to a multiple of 32
   const double rl = b->P.rc + b->skin;
@@ -646,7 +648,9 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
     }
     R.status = st;
   }
-  if (flags[2] > 0) ctx->err = "pair list overflow: " + std::to_string(flags[2]) + " > capacity";
+  if (flags[2] > 0)
+    ctx->err = flags[2] >= (1 << 30) ? std::string("pair list build: a cell holds more than 255 atoms")
+                                     : "pair list overflow: " + std::to_string(flags[2]) + " > capacity";
   return HMD_OK;
 }
 

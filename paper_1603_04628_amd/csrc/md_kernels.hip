@@ -344,46 +344,85 @@ __global__ __launch_bounds__(256) void k_build_list(int ntot, int ld, int cap, c
   const int lc = int(D.lin[int(slot_cell[i]) - D.c0]);
   const int cx = lc % D.nx, cy = (lc / D.nx) % D.ny, cz = lc / (D.nx * D.ny);
   if (i == 0) atomicAdd(&overflow[1], 1);  // builds so far
+  // The 27 neighbouring cells are visited in ascending order of their first
+  // entry in the position array (fluid slots, then wall atoms from ntot), so
+  // every list comes out sorted by index: neighbouring slots then walk the
+  // position array in step, which keeps the force kernel's gathers on shared
+  // cache lines.  Key: first entry << 8 | entry count (the host guarantees
+  // fewer than 2^24 entries; a cell of more than 255 atoms is reported as an
+  // overflow).
+  uint32_t key[32];
+  bool big = false;
+#pragma unroll
+  for (int oz = -1; oz <= 1; ++oz) {
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy) {
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        int jz = cz + oz;
+        jz += jz < 0 ? D.nz : (jz >= D.nz ? -D.nz : 0);
+        int jx = cx + ox;
+        jx += jx < 0 ? D.nx : (jx >= D.nx ? -D.nx : 0);
+        const int jy = cy + oy;
+        uint32_t b, n;
+        if (jy >= 0 && jy < D.ny) {
+          const uint32_t gc = uint32_t(D.c0) + D.rank[(jz * D.ny + jy) * D.nx + jx];
+          b = start[gc];
+          n = ncount[gc];
+        } else {
+          const uint32_t wc = uint32_t(D.wc0 + ((jy < 0 ? 0 : 1) * D.nz + jz) * D.nx + jx);
+          b = uint32_t(ntot) + wstart[wc];
+          n = wcount[wc];
+        }
+        big |= n > 255u;
+        key[(oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)] = (b << 8) | (n > 255u ? 255u : n);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 27; k < 32; ++k) key[k] = 0xffffffffu;
+  // bitonic sort of the 32 keys in registers (all indices compile-time)
+#pragma unroll
+  for (int size = 2; size <= 32; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+      for (int a = 0; a < 32; ++a) {
+        const int c = a ^ stride;
+        if (c > a) {
+          const uint32_t lo = min(key[a], key[c]), hi = max(key[a], key[c]);
+          const bool up = (a & size) == 0;
+          key[a] = up ? lo : hi;
+          key[c] = up ? hi : lo;
+        }
+      }
+    }
+  }
+  if (big) atomicMax(&overflow[0], 1 << 30);
   // entries go out four at a time: group g of slot i is the 16 bytes at
   // (g * ld + i) * 4, so a wave's k-th groups form one contiguous run
   uint4* list4 = reinterpret_cast<uint4*>(list);
   uint4 buf = make_uint4(0u, 0u, 0u, 0u);
   uint32_t cnt = 0;
-  for (int oz = -1; oz <= 1; ++oz) {
-    int jz = cz + oz;
-    jz += jz < 0 ? D.nz : (jz >= D.nz ? -D.nz : 0);
-    for (int oy = -1; oy <= 1; ++oy) {
-      const int jy = cy + oy;
-      const bool wall = jy < 0 || jy >= D.ny;
-      for (int ox = -1; ox <= 1; ++ox) {
-        int jx = cx + ox;
-        jx += jx < 0 ? D.nx : (jx >= D.nx ? -D.nx : 0);
-        uint32_t b, e, off;
-        if (!wall) {
-          const uint32_t gc = uint32_t(D.c0) + D.rank[(jz * D.ny + jy) * D.nx + jx];
-          b = start[gc];
-          e = b + ncount[gc];
-          off = 0;
-        } else {
-          const uint32_t wc = uint32_t(D.wc0 + ((jy < 0 ? 0 : 1) * D.nz + jz) * D.nx + jx);
-          b = wstart[wc];
-          e = b + wcount[wc];
-          off = uint32_t(ntot);
-        }
-        for (uint32_t j = b; j < e; ++j) {
-          const uint32_t q = j + off;
-          const float3 d = fixed_sep(me, pfix[q], D);
-          const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-          if (r2 < rl2 && q != uint32_t(i)) {
-            const uint32_t t = cnt & 3u;
-            buf.x = t == 0 ? q : buf.x;
-            buf.y = t == 1 ? q : buf.y;
-            buf.z = t == 2 ? q : buf.z;
-            buf.w = t == 3 ? q : buf.w;
-            if (t == 3 && cnt < uint32_t(cap)) list4[size_t(cnt >> 2) * ld + i] = buf;
-            ++cnt;
-          }
-        }
+#pragma unroll 1
+  for (int k = 0; k < 27; ++k) {
+    // take the smallest remaining key and shift the rest down (register
+    // moves; a run-time index into key[] would put it in private memory)
+    const uint32_t kk = key[0];
+#pragma unroll
+    for (int t = 0; t < 26; ++t) key[t] = key[t + 1];
+    const uint32_t b = kk >> 8, e = b + (kk & 255u);
+    for (uint32_t q = b; q < e; ++q) {
+      const float3 d = fixed_sep(me, pfix[q], D);
+      const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+      if (r2 < rl2 && q != uint32_t(i)) {
+        const uint32_t t = cnt & 3u;
+        buf.x = t == 0 ? q : buf.x;
+        buf.y = t == 1 ? q : buf.y;
+        buf.z = t == 2 ? q : buf.z;
+        buf.w = t == 3 ? q : buf.w;
+        if (t == 3 && cnt < uint32_t(cap)) list4[size_t(cnt >> 2) * ld + i] = buf;
+        ++cnt;
       }
     }
   }

@@ -156,23 +156,32 @@ def test_thermostat_holds_target():
     assert r["T"][1] == pytest.approx(1.0, abs=0.01)
 
 
+FLUX_PARAMS = dict(n_equil=3000, rho=0.6, **SMALL_L)
+FLUX_SEEDS = list(range(7, 19))
+
+
+@pytest.fixture(scope="module")
+def oracle_flux():
+    return [omd.md_flux(6.0, 0.1, s, 8000, omd.Params(**FLUX_PARAMS)) for s in FLUX_SEEDS]
+
+
 @pytest.mark.parametrize("path", PATHS)
-def test_flux_matches_oracle_within_standard_errors(path):
-    # liquid channel (rho = 0.6 over the wall gap), independent runs per seed
-    params = dict(n_equil=3000, rho=0.6, **SMALL_L)
-    ctx = hmd.Context(hmd.Params(force_path=path, **params))
-    seeds = [7, 8, 9]
-    gres = hmd.md_flux_batch(ctx, [(6.0, 0.1, s, 8000) for s in seeds])
-    ores = [omd.md_flux(6.0, 0.1, s, 8000, omd.Params(**params)) for s in seeds]
+def test_flux_matches_oracle_within_standard_errors(path, oracle_flux):
+    # liquid channel (rho = 0.6 over the wall gap), one independent run per
+    # seed on each side.  The error of each mean comes from the spread over
+    # seeds: the 20-block standard error of a single run underestimates it
+    # when the flux stays correlated longer than a block.
+    ctx = hmd.Context(hmd.Params(force_path=path, **FLUX_PARAMS))
+    gres = hmd.md_flux_batch(ctx, [(6.0, 0.1, s, 8000) for s in FLUX_SEEDS])
     dg = np.array([r["flux"] for r in gres])
-    do = np.array([r["flux"] for r in ores])
-    se = np.hypot([r["flux_se"] for r in gres], [r["flux_se"] for r in ores])
-    z = (dg.mean() - do.mean()) / (np.sqrt((se ** 2).sum()) / len(seeds))
-    print("flux gpu", dg, "oracle", do, "z", z)
+    do = np.array([r["flux"] for r in oracle_flux])
+    n = len(FLUX_SEEDS)
+    t = (dg.mean() - do.mean()) / np.sqrt(dg.var(ddof=1) / n + do.var(ddof=1) / n)
+    print("flux gpu", dg, "oracle", do, "t", t)
     assert all(r["status"] == 0 for r in gres)
-    assert abs(z) <= 3.0
+    assert abs(t) <= 3.5  # two-sided p < 0.003 at 22 degrees of freedom
     # temperatures are reported with the step's Berendsen factor applied
-    for r, o in zip(gres, ores):
+    for r, o in zip(gres, oracle_flux):
         assert r["T"][1] == pytest.approx(o["T"][1], abs=0.01)
 
 
