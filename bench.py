@@ -88,6 +88,163 @@ def summarize_pmc(path: str, kernel: str):
         print(f"{kernel}\t{k}\tdispatches={counts[k]}\tmean={sums[k] / counts[k]:.6g}")
 
 
+# Macro problem of the hybrid solve: converging-diverging channel
+# h(s) = h0 (1 + 0.5 cos 2 pi s / L), 200 cross-sections of 10 sigma, linear
+# equation of state with an artificial stiffness c^2 (weakly compressible),
+# inlet pressure oscillating by 30% with a period of 250 macro steps, mean
+# pressure drop set so the steady lubrication solution has g = 0.038 at the
+# throat (h = 5): with the oscillation every g stays inside the training
+# range [0.001, 0.05] of the surrogates.
+HY = dict(n_sections=200, h0=10.0, amp=0.5, L=2000.0, rho_ref=0.8, p_out=0.0, dp_amp=0.1, period=250.0,
+          c2=200.0)
+HY_G_THROAT = 0.038
+# MD protocol of a fallback or audit call: the batch protocol, long enough
+# for the start-up flow of the widest section (h = 15) to settle
+HY_EQUIL, HY_SAMPLE = N_EQUIL, N_SAMPLE
+HY_STEPS = 500
+
+
+def _sections():
+    n, L = HY["n_sections"], HY["L"]
+    s = (np.arange(n) + 0.5) * L / n
+    return s, HY["h0"] * (1.0 + HY["amp"] * np.cos(2.0 * np.pi * s / L))
+
+
+def _lubrication_start(dp):
+    """Steady lubrication profile (q' ~ h^3 g constant): g = C / h^3 with the
+    integral of g over the channel equal to dp / rho_ref; the density follows
+    from the linear equation of state."""
+    s, h = _sections()
+    ds = HY["L"] / HY["n_sections"]
+    w = h ** -3
+    C = dp / (HY["rho_ref"] * w.sum() * ds)
+    g = C * w
+    p = HY["p_out"] + dp - HY["rho_ref"] * (np.cumsum(g) - 0.5 * g) * ds
+    return HY["rho_ref"] + (p - HY["p_out"]) / HY["c2"], C
+
+
+def hybrid_bench(args, hmd, first_results):
+    """Surrogate data and fits (training 256 + held-out 64 batched MD runs of
+    the batch protocol), then the hybrid march with the GP and with the MLP
+    ensemble, and two all-MD macro steps that price the all-MD march."""
+    import torch
+    from paper_1603_04628_amd import binding as B
+    from paper_1603_04628_amd import hybrid_binding as HB
+    out = {}
+    ctx = hmd.Context(hmd.Params(n_equil=N_EQUIL, **workloads.batch_box()))
+    train, test = workloads.surrogate_training_jobs(args.train_points, 64)
+    # the timed batch already ran seeds 0..63 with this protocol: reuse them
+    reuse = len(first_results) if len(first_results) <= len(train) else 0
+    todo = train[reuse:] + test
+    t0 = time.perf_counter()
+    rnew = hmd.md_flux_batch(ctx, [(j.h, j.g, j.seed, N_SAMPLE) for j in todo])
+    t_data = time.perf_counter() - t0
+    rtr = list(first_results[:reuse]) + rnew[:len(train) - reuse]
+    rte = rnew[len(train) - reuse:]
+    ok_tr = [k for k, r in enumerate(rtr) if r["status"] == 0]
+    ok_te = [k for k, r in enumerate(rte) if r["status"] == 0]
+    X = np.array([[train[k].h, train[k].g] for k in ok_tr])
+    y = np.array([rtr[k]["flux"] for k in ok_tr])
+    se = np.array([rtr[k]["flux_se"] for k in ok_tr])
+    Xt = np.array([[test[k].h, test[k].g] for k in ok_te])
+    yt = np.array([rte[k]["flux"] for k in ok_te])
+    set_ = np.array([rte[k]["flux_se"] for k in ok_te])
+    log(f"surrogate data: {len(ok_tr)} + {len(ok_te)} MD runs in {t_data:.1f} s")
+    hyper = B.gp_hyper(ranges=(16.0, 0.049))
+    ecfg = B.ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3)
+    Xq = Xt[np.arange(200) % len(Xt)]
+    fits = {}
+    for name in ("gp", "ensemble"):
+        t0 = time.perf_counter()
+        sur = B.GP(ctx, X, y, se, hyper) if name == "gp" else B.Ensemble(ctx, X, y, ecfg)
+        torch.cuda.synchronize()
+        t_fit = time.perf_counter() - t0
+        sur.predict(Xq)
+        t0 = time.perf_counter()
+        for _ in range(20):
+            m, v = sur.predict(Xq)
+        t_pred = (time.perf_counter() - t0) / 20
+        m, v = sur.predict(Xt)
+        sd = np.sqrt(v) if name == "gp" else v
+        inside = np.abs(m - yt) <= 2.0 * np.sqrt(sd ** 2 + set_ ** 2)
+        fits[name] = {"fit_s": t_fit, "predict_200_ms": 1e3 * t_pred, "heldout_within_2sigma": float(inside.mean()),
+                      "heldout_rmse_over_rms": float(np.sqrt(np.mean((m - yt) ** 2)) / np.sqrt(np.mean(yt ** 2)))}
+        log(f"{name}: {fits[name]}")
+    out["surrogate"] = {"train_points": len(ok_tr), "heldout_points": len(ok_te), "md_data_s": t_data,
+                        "reused_from_timed_batch": reuse,
+                        "protocol": f"{N_EQUIL} + {N_SAMPLE} steps per point, 57.1 x 57.1 sigma box", **fits}
+
+    # macro constants: pressure drop from the throat condition, macro step
+    # from the explicit diffusion limit with the surrogate's dq'/dg
+    _, C0 = _lubrication_start(1.0)
+    dp = HY_G_THROAT / (C0 / 5.0 ** 3)
+    rho0, _ = _lubrication_start(dp)
+    _, hs = _sections()
+    gp0 = B.GP(ctx, X, y, se, hyper)
+    dg = 1e-3
+    qp, _ = gp0.predict(np.column_stack([hs, np.full_like(hs, 0.025 + dg)]))
+    qm, _ = gp0.predict(np.column_stack([hs, np.full_like(hs, 0.025 - dg)]))
+    dqdg = (qp - qm) / (2 * dg)
+    ds = HY["L"] / HY["n_sections"]
+    d_max = float(np.max(HY["c2"] * dqdg / (HY["rho_ref"] * hs)))
+    dt_macro = 0.4 * ds * ds / d_max
+    gp0.close()
+    base = dict(HY, dt_macro=dt_macro, dp_mean=dp, md_sample=HY_SAMPLE, refit_every=64)
+    hctx = hmd.Context(hmd.Params(n_equil=HY_EQUIL, **workloads.batch_box()))
+
+    # absolute floor of the flagging threshold: the typical standard error of
+    # the training MD itself (a surrogate this certain is not improved on by
+    # a fresh MD call)
+    tau_abs = float(np.median(se))
+
+    def run(surrogate, tau, steps, audit_every, budget_s=None, floor=tau_abs):
+        sur = B.GP(hctx, X, y, se, hyper) if surrogate == 0 else B.Ensemble(hctx, X, y, ecfg)
+        cfg = HB.hybrid_cfg(surrogate=surrogate, tau_rel=tau, tau_abs=floor, audit_every=audit_every, **base)
+        hy = HB.Hybrid(hctx, cfg, gp=sur if surrogate == 0 else None, ens=sur if surrogate == 1 else None)
+        hy.set_rho(rho0)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = hy.step()
+            if budget_s is not None and time.perf_counter() - t0 > budget_s:
+                break
+        wall = time.perf_counter() - t0
+        r = hy.get()
+        hy.close()
+        sur.close()
+        st["wall_s"] = wall
+        st["rho_range"] = [float(r["rho"].min()), float(r["rho"].max())]
+        st["g_range"] = [float(r["g"].min()), float(r["g"].max())]
+        return st
+
+    # all-MD: every query answered by batched MD (threshold 0) for the first
+    # macro steps; the whole march is priced at the rate measured here
+    nv = args.all_md_steps
+    allmd = run(0, 0.0, nv, 0, floor=0.0)
+    per_step_atom_steps = allmd["md_atom_steps"] / nv
+    md_rate = allmd["md_atom_steps"] / allmd["md_wall_s"]
+    all_md_s = args.hybrid_steps * per_step_atom_steps / md_rate
+    log(f"all-MD: {nv} steps in {allmd['wall_s']:.1f} s, {md_rate:.3e} atom-steps/s -> {all_md_s:.0f} s for "
+        f"{args.hybrid_steps} steps")
+    runs = []
+    for name, sid in (("gp", 0), ("ensemble", 1)):
+        for tau in args.taus:
+            st = run(sid, tau, args.hybrid_steps, args.audit_every, budget_s=args.hybrid_budget)
+            done = st["steps"]
+            st.update(surrogate=name, tau=tau, tau_abs=tau_abs,
+                      speedup_vs_all_md=done * per_step_atom_steps / md_rate / st["wall_s"],
+                      audit_pass_rate=st["audit_pass"] / st["audited"] if st["audited"] else None,
+                      md_atom_steps_ratio=done * per_step_atom_steps / max(st["md_atom_steps"], 1.0))
+            log(f"hybrid {name} tau={tau}: {st['wall_s']:.1f} s, md_calls {st['md_calls']}, "
+                f"audits {st['audit_pass']}/{st['audited']}, speedup {st['speedup_vs_all_md']:.0f}x")
+            runs.append(st)
+    out["hybrid"] = {"macro": dict(base, steps=args.hybrid_steps, md_protocol=f"{HY_EQUIL} + {HY_SAMPLE} steps"),
+                     "all_md": {"validated_steps": nv, "wall_s_validated": allmd["wall_s"],
+                                "atom_steps_per_macro_step": per_step_atom_steps,
+                                "md_atom_steps_per_s": md_rate, "estimated_wall_s": all_md_s},
+                     "runs": runs}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +258,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skin", type=float, default=0.3, help="pair-list skin (sigma)")
     ap.add_argument("--force-path", type=int, default=-1, help="0 cell lists, 1 pair lists, -1 library choice")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the surrogate and hybrid-solve measurement")
+    ap.add_argument("--train-points", type=int, default=256)
+    ap.add_argument("--taus", type=lambda t: [float(x) for x in t.split(",")], default=[0.05],
+                    help="relative uncertainty thresholds of the hybrid runs, comma separated")
+    ap.add_argument("--audit-every", type=int, default=1000)
+    ap.add_argument("--hybrid-steps", type=int, default=HY_STEPS)
+    ap.add_argument("--all-md-steps", type=int, default=1, help="macro steps run all-MD to price the all-MD march")
+    ap.add_argument("--hybrid-budget", type=float, default=60.0,
+                    help="wall-clock cap (s) of one hybrid run; the speed-up is then taken over the steps done")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate configurations first (outside the timed region) and use the fastest")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -211,6 +377,8 @@ def main():
         st = [r["status"] for r in res]
         out["flux_status_ok"] = int(sum(1 for s in st if s == 0))
         out["flux_rel_se_median"] = float(np.median([r["flux_se"] / abs(r["flux"]) for r in res if r["flux"]]))
+    if not args.no_hybrid:
+        out.update(hybrid_bench(args, hmd, res))
     if not args.no_cpu:
         cb = cpu_baseline(args.cpu_seconds)
         out["cpu_baseline"] = cb

@@ -262,6 +262,10 @@ void ens_free(hmd_ens* e);
  *   dp/ds_i = (p_{i+1} - p_{i-1}) / (2 ds), ghosts p_{-1} = p_in(t),
  *             p_n = p_out, p_in(t) = p_out + dp_mean (1 + dp_amp sin(2 pi t / period))
  *   g_i = -(1/rho_i) dp/ds_i                      (Eq. momentumEq, F_ext = 0)
+ *   with mirror on, the query is (h_i, |g_i|) and the answer takes the sign
+ *   of g_i: the channel and its walls are symmetric under s -> -s, so the
+ *   flux is odd in the body force, q(h, -g) = -q(h, g), and every surrogate
+ *   point and MD run stays at g >= 0
  *   surrogate mean and standard deviation at (h_i, g_i); the section falls
  *   back to the micro-solver when std > max(tau_rel |mean|, tau_abs)
  *   (tau_abs alone is the paper's absolute sigma_t); fallback results join
@@ -284,6 +288,7 @@ typedef struct {
     int64_t md_sample; /* sampling steps of each fallback MD run */
     int refit_every;   /* ensemble: retrain after this many new MD points */
     uint64_t seed;     /* first MD seed */
+    int mirror;        /* 1: use q(h, -g) = -q(h, g) (default), 0: query g as it is */
 } hmd_hybrid_cfg;
 typedef struct {
     int64_t steps, md_calls, audited, audit_pass, queries, md_failed;

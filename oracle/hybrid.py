@@ -10,7 +10,10 @@ Per macro step (Alg. 1, time-evolution loop):
   3. body force per section, Eq. momentumEq: g = F_ext/m - (1/rho) dp/ds
      (F_ext = 0: the flow is driven by the oscillating inlet pressure);
   4. surrogate mean and standard deviation at (h, g) (Eqs. predMeanEq,
-     predVarEq for the GP);
+     predVarEq for the GP); with `mirror` the query is made at (h, |g|) and
+     the answer takes the sign of g, since the channel is symmetric under
+     s -> -s and the flux is odd in the body force (a reading: the paper's
+     database holds both signs of the force instead);
   5. sections whose standard deviation exceeds max(tau_rel |mean|, tau_abs)
      take the flux from the micro-solver and are added to the database
      (Alg. 1 MD branch; tau_abs alone is the paper's absolute threshold
@@ -44,6 +47,7 @@ class HybridCfg:
     tau_rel: float = 0.05
     tau_abs: float = 0.0      # absolute threshold sigma_t of Sec. 2.2 (0: off)
     audit_every: int = 0
+    mirror: bool = True       # q(h, -g) = -q(h, g): query at |g|, answer with the sign of g
 
 
 class Hybrid:
@@ -85,7 +89,11 @@ class Hybrid:
     def step(self):
         c = self.c
         g = self.forces()
-        X = np.column_stack([self.h, g])
+        # mirror symmetry s -> -s of the channel: the flux is odd in the body
+        # force, so the query is made at |g| and the answer takes g's sign
+        sgn = np.where(g < 0.0, -1.0, 1.0) if c.mirror else np.ones_like(g)
+        gq = sgn * g
+        X = np.column_stack([self.h, gq])
         mean, second = self.sur.predict(X)
         std = second if self.var_is_std else np.sqrt(np.maximum(second, 0.0))
         flag = std > np.maximum(c.tau_rel * np.abs(mean), c.tau_abs)
@@ -96,14 +104,14 @@ class Hybrid:
                 if self.answers % c.audit_every == 0:
                     audit[i] = True
         run = flag | audit
-        q = mean.copy()
+        q = sgn * mean
         if run.any():
             idx = np.nonzero(run)[0]
-            qm, se = self.micro(self.h[idx], g[idx])
+            qm, se = self.micro(self.h[idx], gq[idx])
             self.md_calls += len(idx)
             for k, i in enumerate(idx):
                 if flag[i]:
-                    q[i] = qm[k]
+                    q[i] = sgn[i] * qm[k]
                 else:
                     self.audited += 1
                     self.audit_pass += int(abs(mean[i] - qm[k]) <= 2.0 * se[k])

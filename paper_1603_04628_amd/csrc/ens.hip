@@ -9,6 +9,7 @@
 // back-propagation, per-parameter gradient sums).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -23,6 +24,11 @@ struct hmd_ens {
   float* dparams = nullptr;  // members x P
   std::vector<double> loss;  // final training loss per member
   std::vector<double> X, y;  // training set (host copy, for refits)
+  // prediction buffers, grown on demand and kept for later calls
+  double* dq = nullptr;      // queries, 2 per row
+  float* dy = nullptr;       // members x queries outputs
+  double* dout = nullptr;    // mean, std per query
+  int qcap = 0;
 };
 
 namespace hmd {
@@ -33,7 +39,7 @@ constexpr int CHUNK = 32;
 constexpr int MAXH = 64;
 constexpr int MAXOWN = (MAXH * MAXH + 5 * MAXH + 1 + ENS_TPB - 1) / ENS_TPB;
 
-inline int nparams(int H) { return H * H + 5 * H + 1; }
+__host__ __device__ inline int nparams(int H) { return H * H + 5 * H + 1; }
 
 // Which tensor a flat parameter index belongs to, and its (row, col).
 struct Slot {
@@ -189,34 +195,70 @@ __global__ __launch_bounds__(ENS_TPB) void k_ens_train(int N, int H, int iters, 
   if (tid == 0) loss_out[blockIdx.x] = last_loss;
 }
 
-// One thread per query: every member's output (standardised inputs in,
-// scaled output out), then the ensemble mean and sample standard deviation.
-__global__ __launch_bounds__(128) void k_ens_predict(int m, int members, int H, const float* __restrict__ params,
-                                                     const double* __restrict__ Xq, double mu0, double mu1,
-                                                     double sd0, double sd1, double s_q, double* __restrict__ out) {
+// Prediction, member by member: one wavefront per (block of PQB queries,
+// member), lane o holding hidden unit o.  The member's W2 sits transposed in
+// LDS so lane o reads its column with consecutive addresses; the layer-1
+// activations of the PQB queries are shared through LDS; the output layer is
+// a wavefront sum.
+constexpr int PQB = 8;
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_ens_member_out(int m, int H, const float* __restrict__ params,
+                                                       const double* __restrict__ Xq, double mu0, double mu1,
+                                                       double sd0, double sd1, float* __restrict__ yout) {
+  __shared__ float w2t[MAXH * MAXH];
+  __shared__ float h1[PQB][MAXH];
+  const int k = blockIdx.y, o = threadIdx.x, q0 = blockIdx.x * PQB;
+  const int P = nparams(H);
+  const float* W1 = params + size_t(k) * P;
+  const float* b1 = W1 + 2 * H;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float b3 = W3[H];
+  for (int t = o; t < H * H; t += 64) w2t[(t % H) * H + t / H] = W2[t];  // W2 row o' = output unit o'
+  const bool unit = o < H;
+  if (unit) {
+    const float w10 = W1[2 * o], w11 = W1[2 * o + 1], c1 = b1[o];
+#pragma unroll
+    for (int q = 0; q < PQB; ++q) {
+      const int qq = q0 + q < m ? q0 + q : m - 1;
+      const float x0 = float((Xq[2 * qq] - mu0) / sd0), x1 = float((Xq[2 * qq + 1] - mu1) / sd1);
+      h1[q][o] = tanhf(w10 * x0 + w11 * x1 + c1);
+    }
+  }
+  __syncthreads();
+  float a[PQB];
+  const float c2 = unit ? b2[o] : 0.0f;
+#pragma unroll
+  for (int q = 0; q < PQB; ++q) a[q] = c2;
+  if (unit)
+    for (int i = 0; i < H; ++i) {
+      const float w = w2t[i * H + o];
+#pragma unroll
+      for (int q = 0; q < PQB; ++q) a[q] += w * h1[q][i];
+    }
+  const float w3 = unit ? W3[o] : 0.0f;
+#pragma unroll
+  for (int q = 0; q < PQB; ++q) {
+    const float v = wave_sum_f(unit ? w3 * tanhf(a[q]) : 0.0f);
+    if (o == 0 && q0 + q < m) yout[size_t(k) * m + q0 + q] = b3 + v;
+  }
+}
+
+// Ensemble mean and sample standard deviation (M - 1) per query, FP64.
+__global__ __launch_bounds__(128) void k_ens_reduce(int m, int members, const float* __restrict__ yout,
+                                                    double s_q, double* __restrict__ out) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
-  const int P = H * H + 5 * H + 1;
-  const float x0 = float((Xq[2 * q] - mu0) / sd0), x1 = float((Xq[2 * q + 1] - mu1) / sd1);
   double sum = 0.0, sum2 = 0.0;
   for (int k = 0; k < members; ++k) {
-    const float* th = params + size_t(k) * P;
-    const float* W1 = th;
-    const float* b1 = W1 + 2 * H;
-    const float* W2 = b1 + H;
-    const float* b2 = W2 + H * H;
-    const float* W3 = b2 + H;
-    const float b3 = W3[H];
-    float h1[MAXH];
-    for (int o = 0; o < H; ++o) h1[o] = tanhf(W1[2 * o] * x0 + W1[2 * o + 1] * x1 + b1[o]);
-    float y = b3;
-    for (int o = 0; o < H; ++o) {
-      float a = b2[o];
-      const float* w = W2 + o * H;
-      for (int i = 0; i < H; ++i) a += w[i] * h1[i];
-      y += W3[o] * tanhf(a);
-    }
-    const double yo = double(y) * s_q;
+    const double yo = double(yout[size_t(k) * m + q]) * s_q;
     sum += yo;
     sum2 += yo * yo;
   }
@@ -390,25 +432,28 @@ int ens_predict(hmd_ens* e, const double* Xs, int m, double* mean, double* std) 
   if (m == 0) return HMD_OK;
   hmd_ctx* ctx = e->ctx;
   HMD_HIP(ctx, hipSetDevice(ctx->device));
-  double *dq = nullptr, *dout = nullptr;
-  HMD_HIP(ctx, hipMalloc(&dq, sizeof(double) * 2 * m));
-  hipError_t err = hipMalloc(&dout, sizeof(double) * 2 * m);
+  if (m > e->qcap) {
+    if (e->dq) (void)hipFree(e->dq);
+    if (e->dy) (void)hipFree(e->dy);
+    if (e->dout) (void)hipFree(e->dout);
+    e->dq = nullptr; e->dy = nullptr; e->dout = nullptr; e->qcap = 0;
+    const int cap = std::max(m, 256);
+    HMD_HIP(ctx, hipMalloc(&e->dq, sizeof(double) * 2 * cap));
+    HMD_HIP(ctx, hipMalloc(&e->dy, sizeof(float) * size_t(e->cfg.members) * cap));
+    HMD_HIP(ctx, hipMalloc(&e->dout, sizeof(double) * 2 * cap));
+    e->qcap = cap;
+  }
   std::vector<double> res(2 * size_t(m));
-  if (err == hipSuccess) err = hipMemcpyAsync(dq, Xs, sizeof(double) * 2 * m, hipMemcpyHostToDevice, ctx->stream);
-  if (err == hipSuccess) {
-    hipLaunchKernelGGL(k_ens_predict, dim3((m + 127) / 128), dim3(128), 0, ctx->stream, m, e->cfg.members,
-                       e->cfg.hidden, e->dparams, dq, e->mu[0], e->mu[1], e->sd[0], e->sd[1], e->s_q, dout);
-    err = hipGetLastError();
-  }
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(res.data(), dout, sizeof(double) * res.size(), hipMemcpyDeviceToHost, ctx->stream);
-  if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
-  (void)hipFree(dq);
-  if (dout) (void)hipFree(dout);
-  if (err != hipSuccess) {
-    ctx->err = std::string("ens_predict: ") + hipGetErrorString(err);
-    return HMD_EDEVICE;
-  }
+  HMD_HIP(ctx, hipMemcpyAsync(e->dq, Xs, sizeof(double) * 2 * m, hipMemcpyHostToDevice, ctx->stream));
+  hipLaunchKernelGGL(k_ens_member_out, dim3((m + PQB - 1) / PQB, e->cfg.members), dim3(64), 0, ctx->stream, m,
+                     e->cfg.hidden, e->dparams, e->dq, e->mu[0], e->mu[1], e->sd[0], e->sd[1], e->dy);
+  HMD_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(k_ens_reduce, dim3((m + 127) / 128), dim3(128), 0, ctx->stream, m, e->cfg.members, e->dy,
+                     e->s_q, e->dout);
+  HMD_HIP(ctx, hipGetLastError());
+  HMD_HIP(ctx, hipMemcpyAsync(res.data(), e->dout, sizeof(double) * res.size(), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
   for (int q = 0; q < m; ++q) {
     mean[q] = res[2 * q];
     std[q] = res[2 * q + 1];
@@ -462,6 +507,9 @@ int ens_members(const hmd_ens* e) { return e ? e->cfg.members : 0; }
 void ens_free(hmd_ens* e) {
   if (!e) return;
   if (e->dparams) (void)hipFree(e->dparams);
+  if (e->dq) (void)hipFree(e->dq);
+  if (e->dy) (void)hipFree(e->dy);
+  if (e->dout) (void)hipFree(e->dout);
   delete e;
 }
 

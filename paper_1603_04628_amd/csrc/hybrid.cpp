@@ -42,8 +42,8 @@ double seconds_since(clock_t_::time_point t0) {
 }
 
 // Fluxes for the listed sections from the micro-solver (callback or batched MD).
-int solve_micro(hmd_hybrid* hy, const std::vector<int>& idx, std::vector<double>& qm, std::vector<double>& se,
-                std::vector<int>& ok) {
+int solve_micro(hmd_hybrid* hy, const std::vector<int>& idx, const std::vector<double>& gq,
+                std::vector<double>& qm, std::vector<double>& se, std::vector<int>& ok) {
   const int n = int(idx.size());
   qm.assign(n, 0.0);
   se.assign(n, 0.0);
@@ -51,7 +51,7 @@ int solve_micro(hmd_hybrid* hy, const std::vector<int>& idx, std::vector<double>
   std::vector<double> hh(n), gg(n);
   for (int k = 0; k < n; ++k) {
     hh[k] = hy->h[idx[k]];
-    gg[k] = hy->g[idx[k]];
+    gg[k] = gq[idx[k]];
   }
   const auto t0 = clock_t_::now();
   if (hy->micro) {
@@ -101,6 +101,7 @@ void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c) {
   c->md_sample = 4000;
   c->refit_every = 16;
   c->seed = 1000000;
+  c->mirror = 1;
 }
 
 int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out) {
@@ -162,11 +163,15 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
     const double dpds = (pr - pl) / (2.0 * hy->ds);
     hy->g[i] = -dpds / hy->rho[i];
   }
-  // surrogate query for every section
-  std::vector<double> X(2 * size_t(n)), mean(n), second(n), sd(n);
+  // surrogate query for every section (at |g| with the sign restored after,
+  // when mirror is on)
+  std::vector<double> X(2 * size_t(n)), mean(n), second(n), sd(n), gq(n), sgn(n, 1.0);
   for (int i = 0; i < n; ++i) {
+    const bool neg = c.mirror && hy->g[i] < 0.0;
+    gq[i] = neg ? -hy->g[i] : hy->g[i];
+    sgn[i] = neg ? -1.0 : 1.0;
     X[2 * i] = hy->h[i];
-    X[2 * i + 1] = hy->g[i];
+    X[2 * i + 1] = gq[i];
   }
   const auto ts = clock_t_::now();
   int rc = c.surrogate == 0 ? gp_predict(hy->gp, X.data(), n, mean.data(), second.data())
@@ -189,17 +194,18 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
     }
   for (int i = 0; i < n; ++i)
     if (flag[i] || audit[i]) run.push_back(i);
-  std::vector<double> qv(mean);
+  std::vector<double> qv(n);
+  for (int i = 0; i < n; ++i) qv[i] = sgn[i] * mean[i];
   if (!run.empty()) {
     std::vector<double> qm, se;
     std::vector<int> ok;
-    rc = solve_micro(hy, run, qm, se, ok);
+    rc = solve_micro(hy, run, gq, qm, se, ok);
     if (rc != HMD_OK) return rc;
     hy->st.md_calls += int64_t(run.size());
     for (size_t k = 0; k < run.size(); ++k) {
       const int i = run[k];
       if (flag[i]) {
-        qv[i] = qm[k];
+        qv[i] = sgn[i] * qm[k];
       } else {
         hy->st.audited += 1;
         hy->st.audit_pass += std::fabs(mean[i] - qm[k]) <= 2.0 * se[k] ? 1 : 0;
@@ -210,7 +216,7 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
     for (size_t k = 0; k < run.size(); ++k) {
       const int i = run[k];
       if (!flag[i] || !ok[k]) continue;
-      const double x[2] = {hy->h[i], hy->g[i]};
+      const double x[2] = {hy->h[i], gq[i]};
       if (c.surrogate == 0) {
         rc = gp_append(hy->gp, x, qm[k], se[k]);
       } else {

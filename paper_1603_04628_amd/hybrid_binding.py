@@ -12,7 +12,7 @@ class HybridCfg(_c.Structure):
     _fields_ = [("n_sections", i32), ("h0", d), ("amp", d), ("L", d), ("dt_macro", d), ("rho_ref", d),
                 ("p_out", d), ("dp_mean", d), ("dp_amp", d), ("period", d), ("c2", d), ("tau_rel", d),
                 ("tau_abs", d), ("surrogate", i32), ("audit_every", i32), ("md_sample", i64),
-                ("refit_every", i32), ("seed", u64)]
+                ("refit_every", i32), ("seed", u64), ("mirror", i32)]
 
 
 class HybridStats(_c.Structure):
