@@ -293,6 +293,9 @@ typedef struct {
 typedef struct {
     int64_t steps, md_calls, audited, audit_pass, queries, md_failed;
     double wall_s, md_wall_s, md_atom_steps, surrogate_wall_s;
+    /* audits run apart from the fallback batch: their time and atom-steps
+     * (included in wall_s, excluded from md_wall_s and md_atom_steps) */
+    double audit_wall_s, audit_atom_steps;
 } hmd_hybrid_stats;
 
 /* A replacement micro-solver: given n (h, g) pairs, write the mean flux and

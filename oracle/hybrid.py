@@ -108,7 +108,7 @@ class Hybrid:
         if run.any():
             idx = np.nonzero(run)[0]
             qm, se = self.micro(self.h[idx], gq[idx])
-            self.md_calls += len(idx)
+            self.md_calls += int(flag.sum())  # audits are counted apart
             for k, i in enumerate(idx):
                 if flag[i]:
                     q[i] = sgn[i] * qm[k]

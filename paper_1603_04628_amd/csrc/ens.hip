@@ -65,13 +65,16 @@ __global__ __launch_bounds__(ENS_TPB) void k_ens_train(int N, int H, int iters, 
                                                        int mode) {
   extern __shared__ float lds[];
   const int P = H * H + 5 * H + 1;
+  // activation rows are padded to H + 1 floats so that lanes walking
+  // different rows at the same column hit different LDS banks
+  const int HP = H + 1;
   float* th = lds;                   // P
   float* x = th + P;                 // CHUNK x 2
-  float* h1 = x + 2 * CHUNK;         // CHUNK x H
-  float* h2 = h1 + CHUNK * H;        // CHUNK x H
-  float* dz2 = h2 + CHUNK * H;       // CHUNK x H
-  float* dz1 = dz2 + CHUNK * H;      // CHUNK x H
-  float* dout = dz1 + CHUNK * H;     // CHUNK
+  float* h1 = x + 2 * CHUNK;         // CHUNK x HP
+  float* h2 = h1 + CHUNK * HP;       // CHUNK x HP
+  float* dz2 = h2 + CHUNK * HP;      // CHUNK x HP
+  float* dz1 = dz2 + CHUNK * HP;     // CHUNK x HP
+  float* dout = dz1 + CHUNK * HP;    // CHUNK
   float* red = dout + CHUNK;         // ENS_TPB
   float* W1 = th;
   float* b1 = W1 + 2 * H;
@@ -105,21 +108,23 @@ __global__ __launch_bounds__(ENS_TPB) void k_ens_train(int N, int H, int iters, 
       __syncthreads();
       for (int e = tid; e < nc * H; e += ENS_TPB) {
         const int s = e / H, o = e % H;
-        h1[e] = tanhf(W1[2 * o] * x[2 * s] + W1[2 * o + 1] * x[2 * s + 1] + b1[o]);
+        h1[s * HP + o] = tanhf(W1[2 * o] * x[2 * s] + W1[2 * o + 1] * x[2 * s + 1] + b1[o]);
       }
       __syncthreads();
+      // lanes run over points (same output unit): the W2 row is a broadcast
+      // and the padded activation rows spread over the banks
       for (int e = tid; e < nc * H; e += ENS_TPB) {
-        const int s = e / H, o = e % H;
+        const int s = e % nc, o = e / nc;
         float a = b2[o];
         const float* w = W2 + o * H;
-        const float* hh = h1 + s * H;
+        const float* hh = h1 + s * HP;
         for (int i = 0; i < H; ++i) a += w[i] * hh[i];
-        h2[e] = tanhf(a);
+        h2[s * HP + o] = tanhf(a);
       }
       __syncthreads();
       if (tid < nc) {
         float a = b3[0];
-        const float* hh = h2 + tid * H;
+        const float* hh = h2 + tid * HP;
         for (int o = 0; o < H; ++o) a += W3[o] * hh[o];
         const float r = a - ys[c0 + tid];
         lsum += r * r;
@@ -128,17 +133,17 @@ __global__ __launch_bounds__(ENS_TPB) void k_ens_train(int N, int H, int iters, 
       __syncthreads();
       for (int e = tid; e < nc * H; e += ENS_TPB) {
         const int s = e / H, o = e % H;
-        const float t = h2[e];
-        dz2[e] = dout[s] * W3[o] * (1.0f - t * t);
+        const float t = h2[s * HP + o];
+        dz2[s * HP + o] = dout[s] * W3[o] * (1.0f - t * t);
       }
       __syncthreads();
       for (int e = tid; e < nc * H; e += ENS_TPB) {
         const int s = e / H, i = e % H;
         float a = 0.f;
-        const float* dz = dz2 + s * H;
+        const float* dz = dz2 + s * HP;
         for (int o = 0; o < H; ++o) a += dz[o] * W2[o * H + i];
-        const float t = h1[e];
-        dz1[e] = a * (1.0f - t * t);
+        const float t = h1[s * HP + i];
+        dz1[s * HP + i] = a * (1.0f - t * t);
       }
       __syncthreads();
 #pragma unroll
@@ -146,11 +151,11 @@ __global__ __launch_bounds__(ENS_TPB) void k_ens_train(int N, int H, int iters, 
         const Slot q = sl[k];
         float a = 0.f;
         switch (q.kind) {
-          case 0: for (int s = 0; s < nc; ++s) a += dz1[s * H + q.o] * x[2 * s + q.i]; break;
-          case 1: for (int s = 0; s < nc; ++s) a += dz1[s * H + q.o]; break;
-          case 2: for (int s = 0; s < nc; ++s) a += dz2[s * H + q.o] * h1[s * H + q.i]; break;
-          case 3: for (int s = 0; s < nc; ++s) a += dz2[s * H + q.o]; break;
-          case 4: for (int s = 0; s < nc; ++s) a += dout[s] * h2[s * H + q.o]; break;
+          case 0: for (int s = 0; s < nc; ++s) a += dz1[s * HP + q.o] * x[2 * s + q.i]; break;
+          case 1: for (int s = 0; s < nc; ++s) a += dz1[s * HP + q.o]; break;
+          case 2: for (int s = 0; s < nc; ++s) a += dz2[s * HP + q.o] * h1[s * HP + q.i]; break;
+          case 3: for (int s = 0; s < nc; ++s) a += dz2[s * HP + q.o]; break;
+          case 4: for (int s = 0; s < nc; ++s) a += dout[s] * h2[s * HP + q.o]; break;
           case 5: for (int s = 0; s < nc; ++s) a += dout[s]; break;
           default: break;
         }
@@ -269,7 +274,7 @@ __global__ __launch_bounds__(128) void k_ens_reduce(int m, int members, const fl
 }
 
 size_t train_lds_bytes(int H) {
-  return sizeof(float) * (size_t(nparams(H)) + 2 * CHUNK + 4 * size_t(CHUNK) * H + CHUNK + ENS_TPB);
+  return sizeof(float) * (size_t(nparams(H)) + 2 * CHUNK + 4 * size_t(CHUNK) * (H + 1) + CHUNK + ENS_TPB);
 }
 
 // Glorot-uniform start of one member: Philox4x32-10 keyed by the seed, word

@@ -18,7 +18,7 @@ class HybridCfg(_c.Structure):
 class HybridStats(_c.Structure):
     _fields_ = [("steps", i64), ("md_calls", i64), ("audited", i64), ("audit_pass", i64), ("queries", i64),
                 ("md_failed", i64), ("wall_s", d), ("md_wall_s", d), ("md_atom_steps", d),
-                ("surrogate_wall_s", d)]
+                ("surrogate_wall_s", d), ("audit_wall_s", d), ("audit_atom_steps", d)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
