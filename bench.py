@@ -199,7 +199,8 @@ def hybrid_bench(args, hmd, first_results):
 
     def run(surrogate, tau, steps, audit_every, budget_s=None, floor=tau_abs):
         sur = B.GP(hctx, X, y, se, hyper) if surrogate == 0 else B.Ensemble(hctx, X, y, ecfg)
-        cfg = HB.hybrid_cfg(surrogate=surrogate, tau_rel=tau, tau_abs=floor, audit_every=audit_every, **base)
+        cfg = HB.hybrid_cfg(surrogate=surrogate, tau_rel=tau, tau_abs=floor, audit_every=audit_every,
+                            audit_batch=64, **base)
         hy = HB.Hybrid(hctx, cfg, gp=sur if surrogate == 0 else None, ens=sur if surrogate == 1 else None)
         hy.set_rho(rho0)
         t0 = time.perf_counter()
@@ -207,6 +208,7 @@ def hybrid_bench(args, hmd, first_results):
             st = hy.step()
             if budget_s is not None and time.perf_counter() - t0 > budget_s:
                 break
+        st = hy.flush_audits()
         wall = time.perf_counter() - t0
         r = hy.get()
         hy.close()

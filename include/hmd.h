@@ -289,6 +289,8 @@ typedef struct {
     int refit_every;   /* ensemble: retrain after this many new MD points */
     uint64_t seed;     /* first MD seed */
     int mirror;        /* 1: use q(h, -g) = -q(h, g) (default), 0: query g as it is */
+    int audit_batch;   /* audits wait until this many are pending, then run as one
+                          MD batch (0: in the step that drew them) */
 } hmd_hybrid_cfg;
 typedef struct {
     int64_t steps, md_calls, audited, audit_pass, queries, md_failed;
@@ -304,6 +306,8 @@ typedef struct {
 typedef int (*hmd_micro_fn)(void* user, int n, const double* h, const double* g, double* q, double* se);
 
 void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c);
+/* Runs the audits still pending (audit_batch > 0) and returns the stats. */
+int hybrid_flush_audits(hmd_hybrid* hy, hmd_hybrid_stats* out);
 /* Exactly one of gp / ens matches cfg->surrogate; the hybrid borrows it
  * (the caller frees it after hybrid_free).  rho starts at rho_ref. */
 int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out);

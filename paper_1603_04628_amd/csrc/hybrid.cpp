@@ -6,6 +6,7 @@
 //
 // Host code (the section arrays are a few hundred doubles); built without
 // floating-point contraction so the march rounds as written.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -29,6 +30,8 @@ struct hmd_hybrid {
   int64_t step_no = 0, answers = 0, pending_refit = 0;
   uint64_t next_seed = 0;
   hmd_hybrid_stats st{};
+  // audits waiting for their batch: (h, |g|) and the surrogate's answer
+  std::vector<double> audit_h, audit_g, audit_mean;
 };
 
 namespace {
@@ -42,19 +45,14 @@ double seconds_since(clock_t_::time_point t0) {
 }
 
 // Fluxes for the listed sections from the micro-solver (callback or batched MD).
-int solve_micro(hmd_hybrid* hy, const std::vector<int>& idx, const std::vector<double>& gq,
-                std::vector<double>& qm, std::vector<double>& se, std::vector<int>& ok, bool audit) {
+int solve_micro(hmd_hybrid* hy, std::vector<double> hh, std::vector<double> gg, std::vector<double>& qm,
+                std::vector<double>& se, std::vector<int>& ok, bool audit) {
   double& wall = audit ? hy->st.audit_wall_s : hy->st.md_wall_s;
   double& atom_steps = audit ? hy->st.audit_atom_steps : hy->st.md_atom_steps;
-  const int n = int(idx.size());
+  const int n = int(hh.size());
   qm.assign(n, 0.0);
   se.assign(n, 0.0);
   ok.assign(n, 1);
-  std::vector<double> hh(n), gg(n);
-  for (int k = 0; k < n; ++k) {
-    hh[k] = hy->h[idx[k]];
-    gg[k] = gq[idx[k]];
-  }
   const auto t0 = clock_t_::now();
   if (hy->micro) {
     const int rc = hy->micro(hy->micro_user, n, hh.data(), gg.data(), qm.data(), se.data());
@@ -76,6 +74,24 @@ int solve_micro(hmd_hybrid* hy, const std::vector<int>& idx, const std::vector<d
     hy->st.md_failed += ok[k] || audit ? 0 : 1;
     atom_steps += double(res[k].n_fluid) * double(P.n_equil + hy->cfg.md_sample);
   }
+  return HMD_OK;
+}
+
+// Runs the pending audits as one batch and scores them.
+int flush_audits(hmd_hybrid* hy) {
+  if (hy->audit_h.empty()) return HMD_OK;
+  std::vector<double> qm, se;
+  std::vector<int> ok;
+  const int rc = solve_micro(hy, hy->audit_h, hy->audit_g, qm, se, ok, true);
+  if (rc != HMD_OK) return rc;
+  for (size_t k = 0; k < qm.size(); ++k) {
+    if (!ok[k]) continue;
+    hy->st.audited += 1;
+    hy->st.audit_pass += std::fabs(hy->audit_mean[k] - qm[k]) <= 2.0 * se[k] ? 1 : 0;
+  }
+  hy->audit_h.clear();
+  hy->audit_g.clear();
+  hy->audit_mean.clear();
   return HMD_OK;
 }
 
@@ -104,6 +120,7 @@ void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c) {
   c->refit_every = 16;
   c->seed = 1000000;
   c->mirror = 1;
+  c->audit_batch = 0;
 }
 
 int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out) {
@@ -201,9 +218,13 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   std::vector<int> fl, au;
   for (int i : run) (flag[i] ? fl : au).push_back(i);
   if (!fl.empty()) {
-    std::vector<double> qm, se;
+    std::vector<double> qm, se, hh, gg;
     std::vector<int> ok;
-    rc = solve_micro(hy, fl, gq, qm, se, ok, false);
+    for (int i : fl) {
+      hh.push_back(hy->h[i]);
+      gg.push_back(gq[i]);
+    }
+    rc = solve_micro(hy, hh, gg, qm, se, ok, false);
     if (rc != HMD_OK) return rc;
     hy->st.md_calls += int64_t(fl.size());
     for (size_t k = 0; k < fl.size(); ++k) qv[fl[k]] = sgn[fl[k]] * qm[k];
@@ -228,17 +249,16 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
     }
     hy->st.surrogate_wall_s += seconds_since(tg);
   }
-  // audits run as a batch of their own, timed apart from the method
-  if (!au.empty()) {
-    std::vector<double> qm, se;
-    std::vector<int> ok;
-    rc = solve_micro(hy, au, gq, qm, se, ok, true);
+  // audits do not feed back into the march: they wait and run as batches of
+  // their own (audit_batch at a time, 0: at once), timed apart from the method
+  for (int i : au) {
+    hy->audit_h.push_back(hy->h[i]);
+    hy->audit_g.push_back(gq[i]);
+    hy->audit_mean.push_back(mean[i]);
+  }
+  if (!hy->audit_h.empty() && int(hy->audit_h.size()) >= std::max(c.audit_batch, 1)) {
+    rc = flush_audits(hy);
     if (rc != HMD_OK) return rc;
-    for (size_t k = 0; k < au.size(); ++k) {
-      if (!ok[k]) continue;
-      hy->st.audited += 1;
-      hy->st.audit_pass += std::fabs(mean[au[k]] - qm[k]) <= 2.0 * se[k] ? 1 : 0;
-    }
   }
   // conservative update of rho h
   std::vector<double> flux(n + 1);
@@ -268,6 +288,15 @@ int hybrid_get(hmd_hybrid* hy, double* rho, double* q, double* q_std, double* g,
   if (g) std::memcpy(g, hy->g.data(), 8 * n);
   if (from_md) std::memcpy(from_md, hy->from_md.data(), n);
   return HMD_OK;
+}
+
+int hybrid_flush_audits(hmd_hybrid* hy, hmd_hybrid_stats* out) {
+  if (!hy) return HMD_EINVAL;
+  const auto t0 = clock_t_::now();
+  const int rc = flush_audits(hy);
+  hy->st.wall_s += seconds_since(t0);
+  if (out) *out = hy->st;
+  return rc;
 }
 
 void hybrid_free(hmd_hybrid* hy) { delete hy; }

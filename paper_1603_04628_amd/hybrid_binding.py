@@ -12,7 +12,7 @@ class HybridCfg(_c.Structure):
     _fields_ = [("n_sections", i32), ("h0", d), ("amp", d), ("L", d), ("dt_macro", d), ("rho_ref", d),
                 ("p_out", d), ("dp_mean", d), ("dp_amp", d), ("period", d), ("c2", d), ("tau_rel", d),
                 ("tau_abs", d), ("surrogate", i32), ("audit_every", i32), ("md_sample", i64),
-                ("refit_every", i32), ("seed", u64), ("mirror", i32)]
+                ("refit_every", i32), ("seed", u64), ("mirror", i32), ("audit_batch", i32)]
 
 
 class HybridStats(_c.Structure):
@@ -32,6 +32,7 @@ _sig("hybrid_set_micro", i32, vp, MICRO_FN, vp)
 _sig("hybrid_set_rho", i32, vp, P(d))
 _sig("hybrid_step", i32, vp, P(HybridStats))
 _sig("hybrid_get", i32, vp, P(d), P(d), P(d), P(d), P(u8))
+_sig("hybrid_flush_audits", i32, vp, P(HybridStats))
 _sig("hybrid_free", None, vp)
 
 
@@ -79,6 +80,11 @@ class Hybrid:
     def step(self):
         st = HybridStats()
         self.ctx.check(_lib.hybrid_step(self._h, _c.byref(st)))
+        return st.as_dict()
+
+    def flush_audits(self):
+        st = HybridStats()
+        self.ctx.check(_lib.hybrid_flush_audits(self._h, _c.byref(st)))
         return st.as_dict()
 
     def get(self):

@@ -83,3 +83,19 @@ def test_march_with_batched_md_fallback():
     assert np.all(np.isfinite(r["q"])) and np.all(r["from_md"])
     st = hy.step()
     assert st["steps"] == 2 and np.all(np.isfinite(hy.get()["rho"]))
+
+
+def test_deferred_audits_score_like_immediate_ones():
+    ctx = hmd.Context()
+    X0 = np.array([[6.0, 0.01], [12.0, 0.02], [9.0, 0.03]])
+    y0, se0 = law(X0[:, 0], X0[:, 1])
+    out = []
+    for batch in (0, 5):
+        g = B.GP(ctx, X0, y0, se0, B.gp_hyper(ranges=(16.0, 0.049)))
+        hy = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=0, audit_batch=batch, **CFG), gp=g, micro=law)
+        for _ in range(12):
+            hy.step()
+        st = hy.flush_audits()
+        out.append((st["audited"], st["audit_pass"], st["md_calls"], hy.get()["rho"]))
+    assert out[0][:3] == out[1][:3] and out[0][0] > 5
+    np.testing.assert_array_equal(out[0][3], out[1][3])
