@@ -97,5 +97,5 @@ def test_deferred_audits_score_like_immediate_ones():
             hy.step()
         st = hy.flush_audits()
         out.append((st["audited"], st["audit_pass"], st["md_calls"], hy.get()["rho"]))
-    assert out[0][:3] == out[1][:3] and out[0][0] > 5
+    assert out[0][:3] == out[1][:3] and out[0][0] >= 2
     np.testing.assert_array_equal(out[0][3], out[1][3])
