@@ -112,6 +112,12 @@ int md_flux(hmd_ctx* ctx, double h, double g, uint64_t seed, int64_t steps, doub
  * per-job results, each with its own status; the call returns HMD_OK unless
  * the batch as a whole could not run. */
 int md_flux_batch(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_md_result* out);
+/* Device-pointer form (interop with a framework's tensors): jobs stay on the
+ * host (the geometry is built there); flux, SE and status of each job land in
+ * the device arrays d_flux[n], d_se[n], d_status[n] through copies on
+ * `stream` (NULL: the context's stream), complete when the call returns. */
+int md_flux_batch_dev(hmd_ctx* ctx, const hmd_md_job* jobs, int n, double* d_flux, double* d_se, int* d_status,
+                      void* stream);
 
 /* Staged form of md_flux_batch, for timing the step loop alone: create sets
  * up and uploads every system; run advances all systems by `steps` steps
@@ -215,6 +221,12 @@ int gp_fit(hmd_ctx* ctx, const double* X, const double* y, const double* y_se, i
 int gp_append(hmd_gp* gp, const double* x, double y, double y_se);
 /* mean[m], var[m] (latent posterior variance, output units^2). */
 int gp_predict(hmd_gp* gp, const double* Xs, int m, double* mean, double* var);
+/* Device-pointer form (Eqs. predMeanEq, predVarEq): dXs is m x d row-major in
+ * device memory, dmean[m] and dvar[m] are device arrays; the kernels are
+ * queued on `stream` (NULL: the context's stream) and the call returns
+ * without waiting.  The GP's scratch is shared by its calls: calls on
+ * different streams must not overlap. */
+int gp_predict_dev(hmd_gp* gp, const double* dXs, int m, double* dmean, double* dvar, void* stream);
 int gp_log_marginal(hmd_gp* gp, double* lml);
 int gp_size(const hmd_gp* gp);
 /* The normalisation in use: per-input denominators of Eq. d2Eq (d values),
@@ -240,6 +252,11 @@ void hmd_ens_cfg_default(hmd_ens_cfg* c);
 int ens_fit(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg, hmd_ens** out);
 /* mean[m], std[m] (sample standard deviation over members). */
 int ens_predict(hmd_ens* e, const double* Xs, int m, double* mean, double* std);
+/* Device-pointer form: dXs is m x 2 row-major in device memory, dmean[m] and
+ * dstd[m] device arrays; queued on `stream` (NULL: the context's stream)
+ * without waiting.  Scratch is shared by the ensemble's calls, as for
+ * gp_predict_dev. */
+int ens_predict_dev(hmd_ens* e, const double* dXs, int m, double* dmean, double* dstd, void* stream);
 /* Final training loss per member (MSE on scaled outputs), members values. */
 int ens_loss(const hmd_ens* e, double* loss);
 /* Gradients of the MSE loss of member `k` for its initial parameters

@@ -8,6 +8,6 @@ package fails if the library is not built.
 """
 from . import binding  # noqa: F401  (raises ImportError when libhmd.so is missing)
 from .binding import (Batch, Context, HmdError, Params, System, md_autotune,  # noqa: F401
-                      md_flux, md_flux_batch)
+                      md_flux, md_flux_batch, md_flux_batch_dev)
 from .binding import GP, Ensemble, ens_cfg, gp_hyper  # noqa: F401,E402
 from .hybrid_binding import Hybrid, hybrid_cfg  # noqa: F401,E402

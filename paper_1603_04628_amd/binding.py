@@ -57,6 +57,7 @@ _sig("hmd_last_error", _c.c_char_p, vp)
 _sig("hmd_set_params", i32, vp, P(MdParams))
 _sig("md_flux", i32, vp, d, d, u64, i64, P(d), P(d))
 _sig("md_flux_batch", i32, vp, P(MdJob), i32, P(MdResult))
+_sig("md_flux_batch_dev", i32, vp, P(MdJob), i32, vp, vp, vp, vp)
 _sig("md_batch_create", i32, vp, P(MdJob), i32, P(vp))
 _sig("md_batch_run", i32, vp, i64, i32)
 _sig("md_batch_results", i32, vp, P(MdResult))
@@ -209,6 +210,34 @@ def md_flux_batch(ctx: Context, jobs: Sequence) -> List[dict]:
     return [_result_dict(r) for r in out]
 
 
+def _torch_stream():
+    import torch
+    return vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t, cols=None):
+    """A contiguous float64 CUDA tensor (device pointers for the *_dev calls)."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise HmdError(HMD_EINVAL, "expected a CUDA tensor")
+    t = t.to(torch.float64).contiguous()
+    return t if cols is None else t.reshape(-1, cols)
+
+
+def md_flux_batch_dev(ctx: Context, jobs: Sequence):
+    """md_flux_batch with results in device tensors (flux, se, status) on the
+    current torch stream."""
+    import torch
+    arr = _jobs(jobs)
+    n = len(jobs)
+    f = torch.empty(n, dtype=torch.float64, device="cuda")
+    se = torch.empty_like(f)
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.check(_lib.md_flux_batch_dev(ctx.handle, arr, n, vp(f.data_ptr()), vp(se.data_ptr()), vp(st.data_ptr()),
+                                     _torch_stream()))
+    return f, se, st
+
+
 class Batch:
     """Staged batch (md_batch_*): create, run, results, per-kernel timing."""
 
@@ -351,6 +380,7 @@ _sig("hmd_gp_hyper_default", None, P(GpHyper))
 _sig("gp_fit", i32, vp, P(d), P(d), P(d), i32, i32, P(GpHyper), P(vp))
 _sig("gp_append", i32, vp, P(d), d, d)
 _sig("gp_predict", i32, vp, P(d), i32, P(d), P(d))
+_sig("gp_predict_dev", i32, vp, vp, i32, vp, vp, vp)
 _sig("gp_log_marginal", i32, vp, P(d))
 _sig("gp_size", i32, vp)
 _sig("gp_scales", i32, vp, P(d), P(d), P(d))
@@ -399,6 +429,17 @@ class GP:
         self.ctx.check(_lib.gp_predict(self._h, _ptr(Xs), m, _ptr(mean), _ptr(var)))
         return mean, var
 
+    def predict_dev(self, Xs):
+        """Queries and results as CUDA tensors, on the current torch stream."""
+        import torch
+        Xs = _dev_f64(Xs, self.d)
+        m = Xs.shape[0]
+        mean = torch.empty(m, dtype=torch.float64, device=Xs.device)
+        var = torch.empty_like(mean)
+        self.ctx.check(_lib.gp_predict_dev(self._h, vp(Xs.data_ptr()), m, vp(mean.data_ptr()),
+                                           vp(var.data_ptr()), _torch_stream()))
+        return mean, var
+
     def log_marginal(self):
         v = d()
         self.ctx.check(_lib.gp_log_marginal(self._h, _c.byref(v)))
@@ -430,6 +471,7 @@ class EnsCfg(_c.Structure):
 _sig("hmd_ens_cfg_default", None, P(EnsCfg))
 _sig("ens_fit", i32, vp, P(d), P(d), i32, P(EnsCfg), P(vp))
 _sig("ens_predict", i32, vp, P(d), i32, P(d), P(d))
+_sig("ens_predict_dev", i32, vp, vp, i32, vp, vp, vp)
 _sig("ens_loss", i32, vp, P(d))
 _sig("ens_grad_init", i32, vp, P(d), P(d), i32, P(EnsCfg), i32, P(d), P(d), P(i32))
 _sig("ens_members", i32, vp)
@@ -460,6 +502,17 @@ class Ensemble:
         m = len(Xs)
         mean, std = np.zeros(m), np.zeros(m)
         self.ctx.check(_lib.ens_predict(self._h, _ptr(Xs), m, _ptr(mean), _ptr(std)))
+        return mean, std
+
+    def predict_dev(self, Xs):
+        """Queries and results as CUDA tensors, on the current torch stream."""
+        import torch
+        Xs = _dev_f64(Xs, 2)
+        m = Xs.shape[0]
+        mean = torch.empty(m, dtype=torch.float64, device=Xs.device)
+        std = torch.empty_like(mean)
+        self.ctx.check(_lib.ens_predict_dev(self._h, vp(Xs.data_ptr()), m, vp(mean.data_ptr()),
+                                            vp(std.data_ptr()), _torch_stream()))
         return mean, std
 
     def losses(self):

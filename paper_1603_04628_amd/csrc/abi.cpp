@@ -187,6 +187,30 @@ int md_flux_batch(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_md_result* ou
   });
 }
 
+int md_flux_batch_dev(hmd_ctx* ctx, const hmd_md_job* jobs, int n, double* d_flux, double* d_se, int* d_status,
+                      void* stream) {
+  if (!ctx || !jobs || n < 1 || !d_flux || !d_se || !d_status) {
+    if (ctx) ctx->err = "md_flux_batch_dev: null argument or n < 1";
+    return HMD_EINVAL;
+  }
+  std::vector<hmd_md_result> res(n);
+  int rc = md_flux_batch(ctx, jobs, n, res.data());
+  if (rc != HMD_OK) return rc;
+  std::vector<double> f(n), se(n);
+  std::vector<int> st(n);
+  for (int k = 0; k < n; ++k) {
+    f[k] = res[k].flux;
+    se[k] = res[k].flux_se;
+    st[k] = res[k].status;
+  }
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  HMD_HIP(ctx, hipMemcpyAsync(d_flux, f.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  HMD_HIP(ctx, hipMemcpyAsync(d_se, se.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  HMD_HIP(ctx, hipMemcpyAsync(d_status, st.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  HMD_HIP(ctx, hipStreamSynchronize(s));  // the host staging arrays end here
+  return HMD_OK;
+}
+
 int md_flux(hmd_ctx* ctx, double h, double g, uint64_t seed, int64_t steps, double* flux, double* se) {
   if (!ctx) return HMD_EINVAL;
   hmd_md_job job{h, g, seed, steps};

@@ -258,7 +258,8 @@ __global__ __launch_bounds__(64) void k_ens_member_out(int m, int H, const float
 
 // Ensemble mean and sample standard deviation (M - 1) per query, FP64.
 __global__ __launch_bounds__(128) void k_ens_reduce(int m, int members, const float* __restrict__ yout,
-                                                    double s_q, double* __restrict__ out) {
+                                                    double s_q, double* __restrict__ mean_out,
+                                                    double* __restrict__ std_out) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
   double sum = 0.0, sum2 = 0.0;
@@ -269,8 +270,8 @@ __global__ __launch_bounds__(128) void k_ens_reduce(int m, int members, const fl
   }
   const double mean = sum / members;
   const double var = members > 1 ? (sum2 - members * mean * mean) / (members - 1) : 0.0;
-  out[2 * q] = mean;
-  out[2 * q + 1] = sqrt(var > 0.0 ? var : 0.0);
+  mean_out[q] = mean;
+  std_out[q] = sqrt(var > 0.0 ? var : 0.0);
 }
 
 size_t train_lds_bytes(int H) {
@@ -448,21 +449,48 @@ int ens_predict(hmd_ens* e, const double* Xs, int m, double* mean, double* std) 
     HMD_HIP(ctx, hipMalloc(&e->dout, sizeof(double) * 2 * cap));
     e->qcap = cap;
   }
-  std::vector<double> res(2 * size_t(m));
+  std::vector<double> res(2 * size_t(m));  // means, then standard deviations
   HMD_HIP(ctx, hipMemcpyAsync(e->dq, Xs, sizeof(double) * 2 * m, hipMemcpyHostToDevice, ctx->stream));
   hipLaunchKernelGGL(k_ens_member_out, dim3((m + PQB - 1) / PQB, e->cfg.members), dim3(64), 0, ctx->stream, m,
                      e->cfg.hidden, e->dparams, e->dq, e->mu[0], e->mu[1], e->sd[0], e->sd[1], e->dy);
   HMD_HIP(ctx, hipGetLastError());
   hipLaunchKernelGGL(k_ens_reduce, dim3((m + 127) / 128), dim3(128), 0, ctx->stream, m, e->cfg.members, e->dy,
-                     e->s_q, e->dout);
+                     e->s_q, e->dout, e->dout + m);
   HMD_HIP(ctx, hipGetLastError());
   HMD_HIP(ctx, hipMemcpyAsync(res.data(), e->dout, sizeof(double) * res.size(), hipMemcpyDeviceToHost,
                               ctx->stream));
   HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
   for (int q = 0; q < m; ++q) {
-    mean[q] = res[2 * q];
-    std[q] = res[2 * q + 1];
+    mean[q] = res[q];
+    std[q] = res[size_t(m) + q];
   }
+  return HMD_OK;
+}
+
+int ens_predict_dev(hmd_ens* e, const double* dXs, int m, double* dmean, double* dstd, void* stream) {
+  if (!e || m < 0 || (m > 0 && (!dXs || !dmean || !dstd))) return HMD_EINVAL;
+  if (m == 0) return HMD_OK;
+  hmd_ctx* ctx = e->ctx;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  if (m > e->qcap) {
+    HMD_HIP(ctx, hipStreamSynchronize(s));  // the old scratch may still be read
+    if (e->dq) (void)hipFree(e->dq);
+    if (e->dy) (void)hipFree(e->dy);
+    if (e->dout) (void)hipFree(e->dout);
+    e->dq = nullptr; e->dy = nullptr; e->dout = nullptr; e->qcap = 0;
+    const int cap = std::max(m, 256);
+    HMD_HIP(ctx, hipMalloc(&e->dq, sizeof(double) * 2 * cap));
+    HMD_HIP(ctx, hipMalloc(&e->dy, sizeof(float) * size_t(e->cfg.members) * cap));
+    HMD_HIP(ctx, hipMalloc(&e->dout, sizeof(double) * 2 * cap));
+    e->qcap = cap;
+  }
+  hipLaunchKernelGGL(k_ens_member_out, dim3((m + PQB - 1) / PQB, e->cfg.members), dim3(64), 0, s, m,
+                     e->cfg.hidden, e->dparams, dXs, e->mu[0], e->mu[1], e->sd[0], e->sd[1], e->dy);
+  HMD_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(k_ens_reduce, dim3((m + 127) / 128), dim3(128), 0, s, m, e->cfg.members, e->dy, e->s_q,
+                     dmean, dstd);
+  HMD_HIP(ctx, hipGetLastError());
   return HMD_OK;
 }
 

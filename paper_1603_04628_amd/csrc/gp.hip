@@ -12,6 +12,7 @@
 // prediction spreads query blocks over the chip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -137,6 +138,23 @@ __global__ __launch_bounds__(1024) void k_gp_solve(int n, int ld, const double* 
 
 // Prediction for a block of QB queries per workgroup: k* columns, mean by a
 // dot product with alpha, variance by a multi-right-hand-side forward solve.
+// Device-pointer interop: queries row-major with d columns -> the padded
+// layout of the predict kernel; results (scaled back to output units) into
+// separate mean and variance arrays.
+__global__ void k_gp_pack(int m, int d, const double* __restrict__ src, double* __restrict__ dst) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  for (int k = 0; k < GP_MAXD; ++k) dst[size_t(q) * GP_MAXD + k] = k < d ? src[size_t(q) * d + k] : 0.0;
+}
+
+__global__ void k_gp_unpack(int m, int have_data, const double* __restrict__ res, double s_q, double sf2,
+                            double* __restrict__ mean, double* __restrict__ var) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  mean[q] = have_data ? res[2 * q] * s_q : 0.0;
+  var[q] = (have_data ? res[2 * q + 1] : sf2) * s_q * s_q;
+}
+
 constexpr int QB = 32;
 __global__ __launch_bounds__(256) void k_gp_predict(int n, int ld, int m, const double* __restrict__ X,
                                                     const double* __restrict__ Xq, const double* __restrict__ L,
@@ -471,6 +489,37 @@ int gp_predict(hmd_gp* g, const double* Xs, int m, double* mean, double* var) {
     mean[q] = res[2 * q] * g->s_q;
     var[q] = res[2 * q + 1] * g->s_q * g->s_q;
   }
+  return HMD_OK;
+}
+
+int gp_predict_dev(hmd_gp* g, const double* dXs, int m, double* dmean, double* dvar, void* stream) {
+  if (!g || m < 0 || (m > 0 && (!dXs || !dmean || !dvar))) return HMD_EINVAL;
+  hmd_ctx* ctx = g->ctx;
+  if (m == 0) return HMD_OK;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  const double sf2 = g->hyp.sigma_f * g->hyp.sigma_f;
+  const int nblk = (m + QB - 1) / QB;
+  const size_t need_q = size_t(GP_MAXD) * m, need_v = size_t(nblk) * QB * std::max(g->n, 1);
+  if (need_q + need_v + 2 * size_t(m) > g->q_cap) {
+    HMD_HIP(ctx, hipStreamSynchronize(s));  // the old scratch may still be read
+    if (g->dq) (void)hipFree(g->dq);
+    g->q_cap = 2 * (need_q + need_v + 2 * size_t(m));
+    HMD_HIP(ctx, hipMalloc(&g->dq, sizeof(double) * g->q_cap));
+  }
+  double* dXq = g->dq;
+  double* dV = g->dq + need_q;
+  double* dres = dV + need_v;
+  hipLaunchKernelGGL(k_gp_pack, dim3((m + 255) / 256), dim3(256), 0, s, m, g->d, dXs, dXq);
+  HMD_HIP(ctx, hipGetLastError());
+  if (g->n > 0) {
+    hipLaunchKernelGGL(k_gp_predict, dim3(nblk), dim3(256), 0, s, g->n, g->cap, m, g->dX, dXq, g->dL, g->dalpha,
+                       kparams(g), dV, dres);
+    HMD_HIP(ctx, hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_gp_unpack, dim3((m + 255) / 256), dim3(256), 0, s, m, g->n > 0 ? 1 : 0, dres, g->s_q, sf2,
+                     dmean, dvar);
+  HMD_HIP(ctx, hipGetLastError());
   return HMD_OK;
 }
 
