@@ -22,6 +22,26 @@ if not os.path.exists(LIBPATH):
     raise ImportError(f"{LIBPATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
 
 _c = ctypes
+
+
+def _share_torch_hip_runtime():
+    """Load PyTorch's bundled HIP runtime first, when there is one.  It has
+    the same soname as ROCm's, so libhmd.so then binds to it and a process
+    that also uses torch holds one runtime: device pointers and streams pass
+    between the two, and torch's synchronisation covers the library's work."""
+    try:
+        import importlib.util
+        spec = importlib.util.find_spec("torch")
+    except (ImportError, ValueError):
+        return
+    if spec is None or not spec.submodule_search_locations:
+        return
+    path = os.path.join(list(spec.submodule_search_locations)[0], "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        _c.CDLL(path, mode=_c.RTLD_GLOBAL)
+
+
+_share_torch_hip_runtime()
 _lib = _c.CDLL(LIBPATH)
 P = _c.POINTER
 d, i32, i64, u64, u32, u8, vp = _c.c_double, _c.c_int, _c.c_int64, _c.c_uint64, _c.c_uint32, _c.c_uint8, _c.c_void_p
