@@ -35,6 +35,29 @@ FLOP_PER_PAIR = 21
 N_EQUIL, N_SAMPLE = 10000, 20000
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "force_list_batch64_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1603_04628_amd", "csrc", "md_kernels.hip")
+
+
+def committed_counters():
+    """Per-launch HBM traffic and counter FLOPs of the force kernel from the
+    committed rocprofv3 summary, or None when the kernel source has changed
+    since those counters were taken."""
+    import hashlib
+    try:
+        vals = {}
+        for line in open(COUNTERS):
+            if ":" in line and not line.startswith(("|", "#", "`")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if vals.get("source_sha256") != sha:
+        return None
+    return {"traffic": float(vals["traffic_bytes_per_launch"]), "flop": float(vals["counter_flop_per_launch"])}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -349,6 +372,7 @@ def main():
 
     force_ms = kern["force"]
     achieved = pairs_per_launch * FLOP_PER_PAIR / (force_ms * 1e-3) / 1e12
+    cnt = committed_counters() if cfg["path"] == 1 else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -370,7 +394,8 @@ def main():
                    "threads_per_block": cfg["tpb"],
                    "list_builds_per_step": builds / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None,
+                     "frac": achieved / PEAK_FP32, "traffic": cnt["traffic"] if cnt else None,
+                     "counter_tflops": cnt["flop"] / (force_ms * 1e-3) / 1e12 if cnt else None,
                      "kernel": "k_force_list<1, 0>" if cfg["path"] == 1 else "k_force_cell<1>", "avg_ms": force_ms,
                      "pairs_per_launch": pairs_per_launch, "flop_per_pair": FLOP_PER_PAIR},
         "plain_atom_steps_per_s": plain,
