@@ -297,3 +297,34 @@ def test_neighbor_sets_symmetric_and_nested(small_equilibrated):
     # every in-cutoff neighbour contributes to the force: the pair count matches
     # the brute-force energy's pair count implied by a cut-off just above 0
     assert sum(len(a) for a in inner) < sum(len(a) for a in nb)
+
+
+@pytest.mark.slow
+def test_wide_channel_core_is_poiseuille():
+    # h = 20 sigma, body force g: away from the wall layers the streaming
+    # velocity follows the continuum solution u(y) = (rho g / 2 eta) y (h' - y)
+    # up to an offset: a parabola, symmetric about the mid-plane, whose
+    # curvature gives a shear viscosity in the range of the LJ liquid near
+    # rho = 0.8, T = 1 (about 2 in reduced units)
+    p = md.Params(Lx_nom=12.0, Lz_nom=12.0, n_equil=12000, thermo_axis=2)
+    g = 0.02
+    s = md.System(20.0, g, 3, p)
+    s.run(24000)
+    mvx, cnt = s.profile()
+    y = (np.arange(len(mvx)) + 0.5) * p.bin_dy
+    u = mvx / np.maximum(cnt, 1.0)
+    core = (y > 4.0) & (y < 16.0)
+    rho_core = cnt[core].sum() / cnt.sum() * s.n_fluid / (s.Lx * s.Lz * core.sum() * p.bin_dy)
+    A = np.column_stack([np.ones(core.sum()), y[core], y[core] ** 2])
+    c, *_ = np.linalg.lstsq(A, u[core], rcond=None)
+    fit = A @ c
+    r2 = 1.0 - np.sum((u[core] - fit) ** 2) / np.sum((u[core] - u[core].mean()) ** 2)
+    assert r2 >= 0.9
+    assert c[2] < 0.0
+    assert abs(-c[1] / (2.0 * c[2]) - 10.0) < 1.0  # vertex at the mid-plane
+    eta = -rho_core * g / (2.0 * c[2])
+    assert 1.5 < eta < 3.0
+    # the profile integrates to the measured mass flow rate per unit span
+    r = s.result()
+    q_profile = np.sum(mvx) / (s.Lx * s.Lz) / (24000 - 12000)
+    assert q_profile == pytest.approx(r["flux"], rel=0.02)
