@@ -33,16 +33,18 @@ PEAK_FP32 = 157.3
 # r^2 5, 1/r^2 1, r^-6 2, force factor 4, accumulation 6.
 FLOP_PER_PAIR = 21
 N_EQUIL, N_SAMPLE = 10000, 20000
+PATH_NAMES = {0: "cell list", 1: "pair list", 2: "pair list, LDS-staged tiles"}
+FORCE_KERNELS = {0: "k_force_cell<1>", 1: "k_force_list<1, 0", 2: "k_force_tiles<1, 0"}
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "force_list_batch64_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1603_04628_amd", "csrc", "md_kernels.hip")
 
 
-def committed_counters():
+def committed_counters(kernel):
     """Per-launch HBM traffic and counter FLOPs of the force kernel from the
-    committed rocprofv3 summary, or None when the kernel source has changed
-    since those counters were taken."""
+    committed rocprofv3 summary, or None when that summary covers another
+    kernel or the kernel source has changed since the counters were taken."""
     import hashlib
     try:
         vals = {}
@@ -53,7 +55,7 @@ def committed_counters():
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except OSError:
         return None
-    if vals.get("source_sha256") != sha:
+    if vals.get("source_sha256") != sha or vals.get("kernel") != kernel:
         return None
     return {"traffic": float(vals["traffic_bytes_per_launch"]), "flop": float(vals["counter_flop_per_launch"])}
 
@@ -372,7 +374,7 @@ def main():
 
     force_ms = kern["force"]
     achieved = pairs_per_launch * FLOP_PER_PAIR / (force_ms * 1e-3) / 1e12
-    cnt = committed_counters() if cfg["path"] == 1 else None
+    cnt = committed_counters(FORCE_KERNELS[cfg["path"]])
     out = {
         "metric": METRIC,
         "value": value,
@@ -390,13 +392,13 @@ def main():
                                "57.1x57.1 sigma box, rho 0.8, T 1, rc 2.5, dt 0.005, 10k+20k steps, "
                                "FP32 forces / FP64 state and sums",
                    "systems": len(jobs), "fluid_atoms": n_atoms, "graph_chunk": args.chunk,
-                   "force_path": "pair list" if cfg["path"] == 1 else "cell list", "skin": cfg["skin"],
+                   "force_path": PATH_NAMES[cfg["path"]], "skin": cfg["skin"],
                    "threads_per_block": cfg["tpb"],
                    "list_builds_per_step": builds / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": cnt["traffic"] if cnt else None,
                      "counter_tflops": cnt["flop"] / (force_ms * 1e-3) / 1e12 if cnt else None,
-                     "kernel": "k_force_list<1, 0>" if cfg["path"] == 1 else "k_force_cell<1>", "avg_ms": force_ms,
+                     "kernel": FORCE_KERNELS[cfg["path"]], "avg_ms": force_ms,
                      "pairs_per_launch": pairs_per_launch, "flop_per_pair": FLOP_PER_PAIR},
         "plain_atom_steps_per_s": plain,
         "batched_over_plain": value / plain if plain else None,

@@ -68,8 +68,10 @@ typedef struct {
      * force_path 0: cell list rebuilt every step, forces over the 27
      * neighbouring cells; 1: Verlet pair list (cut-off rc + skin) rebuilt
      * from the cell list whenever an atom has moved skin/2 since the last
-     * build; -1: the library's tuned choice.  cell_w: minimum cell width
-     * (0: rc, or rc + skin for the pair list). */
+     * build; 2: the same lists for workgroups that each own a tile of whole
+     * cell columns and read their neighbours' positions from LDS (16-bit
+     * list entries); -1: the library's tuned choice.  cell_w: minimum cell
+     * width (0: rc, or rc + skin for the pair lists). */
     int force_path;
     double skin, cell_w;
 } hmd_md_params;

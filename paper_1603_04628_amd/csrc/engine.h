@@ -51,6 +51,7 @@ struct SimDev {
   double fix_x, fix_y, fix_z;  // fixed-point scales (2^32 per extent)
   double y_lo;                 // fixed-point origin in y
   float unit_x, unit_y, unit_z;  // length of one fixed-point unit
+  float inv_u, inv_u2;         // 1 / unit_x and its square (same unit on every axis: uniform scale)
   float fwx, fwy, fwz;         // FP32 cell widths (neighbour-cell shifts)
   int nx, ny, nz;
   int a0, nf;                  // fluid slots [a0, a0 + nf)
@@ -103,6 +104,7 @@ struct hmd_batch {
   int tpb = 256;          // threads per block of the per-slot kernels
   double skin = 0.3;
   int list_cap = 0, list_ld = 0;
+  bool uniform = false;   // one fixed-point unit on all axes in every system
   std::vector<hmd::HostSystem> host;  // geometry (atom arrays released after upload)
   std::vector<int> wall_id;           // wall slot (column order) -> wall id within its system
   std::vector<uint32_t> cell_rank;    // per system, concatenated: row-major cell id -> Morton rank
@@ -122,6 +124,9 @@ struct hmd_batch {
   int4* d_pbuild = nullptr;         // pair path: positions at the last list build
   uint32_t* d_slot_cell = nullptr;  // pair path: cell of each slot at the last build
   uint32_t* d_list = nullptr;       // pair path: list_cap x list_ld entries
+  int4* d_tiles = nullptr;          // tiled path: (system, z slab, first column, columns) per workgroup
+  uint8_t* d_tilemode = nullptr;    // tiled path: 0 LDS indices, 1 position indices (LDS too small)
+  int ntiles = 0, stage_cap = 0;    // tiles; LDS capacity in atoms
   uint32_t* d_nlist = nullptr;
   int* d_flag = nullptr;            // [2] rebuild flags by step parity, list overflow, builds so far
   uint32_t* d_key = nullptr;        // global cell of each slot

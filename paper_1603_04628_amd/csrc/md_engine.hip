@@ -97,6 +97,24 @@ struct Launcher {
   }
 };
 
+// Pair-list build (after a reorder into `from`: the build copies the state
+// back into `to`; from == to copies nothing).
+void launch_build(hmd_batch* b, hipStream_t s, const int* flag, StepRef R, StateRef from, StateRef to,
+                  const int* tag_from, int* tag_to, int global_out) {
+  const int nt = int(b->ntot), tpb = b->tpb, nb = blocks_for(nt, tpb);
+  const float rl2 = float((b->P.rc + b->skin) * (b->P.rc + b->skin));
+  if (b->path == 2) {
+    hipLaunchKernelGGL(k_build_tiles, dim3(b->ntiles), dim3(TILE_THREADS), size_t(12) * b->stage_cap, s, nt,
+                       b->list_ld, b->list_cap, b->stage_cap, b->d_tiles, b->d_sims, b->d_slot_cell, b->d_pfix,
+                       b->d_start, b->d_ncount, b->d_wstart, b->d_wcount, b->d_list, b->d_nlist, b->d_tilemode,
+                       from, to, tag_from, tag_to, b->d_flag + 2, flag, R, rl2, global_out);
+    return;
+  }
+  hipLaunchKernelGGL(k_build_list, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->list_cap, b->d_sims,
+                     b->d_atom_sim, b->d_slot_cell, b->d_pfix, b->d_start, b->d_ncount, b->d_wstart, b->d_wcount,
+                     b->d_list, b->d_nlist, from, to, tag_from, tag_to, b->d_flag + 2, flag, R, rl2);
+}
+
 // Counting sort of the current state by cell (flag null: unconditional).
 void enqueue_sort(hmd_batch* b, Launcher& L, const StepConst& K, const int* flag, StepRef R) {
   hipStream_t s = L.s;
@@ -141,12 +159,8 @@ void enqueue_sort(hmd_batch* b, Launcher& L, const StepConst& K, const int* flag
                      b->d_ncount, b->d_perm, state_ref(b, 0), state_ref(b, 1), b->d_tag[0], b->d_tag[1],
                      b->d_pos4, b->d_pfix, b->d_pbuild, b->d_slot_cell, flag, R);
   L.end();
-  const float rl2 = float((b->P.rc + b->skin) * (b->P.rc + b->skin));
   L.begin(K_LIST);
-  hipLaunchKernelGGL(k_build_list, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->list_cap, b->d_sims,
-                     b->d_atom_sim, b->d_slot_cell, b->d_pfix, b->d_start, b->d_ncount, b->d_wstart, b->d_wcount,
-                     b->d_list, b->d_nlist, state_ref(b, 1), state_ref(b, 0), b->d_tag[1], b->d_tag[0],
-                     b->d_flag + 2, flag, R, rl2);
+  launch_build(b, s, flag, R, state_ref(b, 1), state_ref(b, 0), b->d_tag[1], b->d_tag[0], 0);
   L.end();
 }
 
@@ -162,9 +176,20 @@ void enqueue_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K, St
       hipLaunchKernelGGL(k_force_cell<1>, dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_atom_sim, b->d_pos4,
                          b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
                          b->acc, b->d_dstate, R, K);
+  } else if (b->path == 2) {
+    auto* kern = b->uniform ? (mode == 0 ? (K.energy_on ? k_force_tiles<0, 1, 1> : k_force_tiles<0, 0, 1>)
+                                         : (K.energy_on ? k_force_tiles<1, 1, 1> : k_force_tiles<1, 0, 1>))
+                            : (mode == 0 ? (K.energy_on ? k_force_tiles<0, 1, 0> : k_force_tiles<0, 0, 0>)
+                                         : (K.energy_on ? k_force_tiles<1, 1, 0> : k_force_tiles<1, 0, 0>));
+    hipLaunchKernelGGL(kern, dim3(b->ntiles), dim3(TILE_THREADS), size_t(12) * b->stage_cap, s, nt, b->list_ld,
+                       b->stage_cap, b->d_tiles, b->d_tilemode, b->d_sims, b->d_pfix, b->d_start, b->d_ncount,
+                       b->d_wstart, b->d_wcount, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc,
+                       b->d_dstate, R, K);
   } else {
-    auto* kern = mode == 0 ? (K.energy_on ? k_force_list<0, 1> : k_force_list<0, 0>)
-                           : (K.energy_on ? k_force_list<1, 1> : k_force_list<1, 0>);
+    auto* kern = b->uniform ? (mode == 0 ? (K.energy_on ? k_force_list<0, 1, 1> : k_force_list<0, 0, 1>)
+                                         : (K.energy_on ? k_force_list<1, 1, 1> : k_force_list<1, 0, 1>))
+                            : (mode == 0 ? (K.energy_on ? k_force_list<0, 1, 0> : k_force_list<0, 0, 0>)
+                                         : (K.energy_on ? k_force_list<1, 1, 0> : k_force_list<1, 0, 0>));
     hipLaunchKernelGGL(kern, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims, b->d_atom_sim, b->d_pfix,
                        b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
   }
@@ -278,6 +303,48 @@ int get_graph(hmd_batch* b, int chunk, const StepConst& K, hipGraphExec_t* out) 
 
 }  // namespace
 
+// Tiles of the tiled path: per system and z slab, runs of whole columns
+// sized so that a tile holds about one to two workgroups of atoms and its
+// staged neighbourhood fits the LDS capacity.
+int make_tiles(hmd_batch* b) {
+  hmd_ctx* ctx = b->ctx;
+  constexpr int kStageCap = 4096;  // atoms (x, y, z fixed point: 48 KiB)
+  b->stage_cap = kStageCap;
+  std::vector<int4> tiles;
+  for (int k = 0; k < b->S; ++k) {
+    const SimDev& D = b->sims[k];
+    const HostSystem& H = b->host[k];
+    const double per_col = double(D.nf) / double(D.nx * D.nz);
+    const double wall_col = double(H.nw) / double(2 * D.nx * D.nz);
+    int best = 1;
+    double best_use = -1.0;
+    for (int nc = 1; nc <= D.nx; ++nc) {
+      const double atoms = nc * per_col;
+      const double staged = 3.0 * std::min(nc + 2, D.nx) * (per_col + 2.0 * wall_col);
+      if (staged > 0.75 * kStageCap && nc > 1) break;
+      const double passes = std::ceil(atoms / TILE_THREADS);
+      const double use = atoms / (passes * TILE_THREADS);
+      if (use > best_use + 0.02) {
+        best_use = use;
+        best = nc;
+      }
+    }
+    const int ntx = (D.nx + best - 1) / best;
+    for (int z = 0; z < D.nz; ++z)
+      for (int t = 0; t < ntx; ++t) {  // columns split as evenly as possible
+        const int x0 = int(int64_t(t) * D.nx / ntx), x1 = int(int64_t(t + 1) * D.nx / ntx);
+        tiles.push_back(make_int4(k, z, x0, x1 - x0));
+      }
+  }
+  b->ntiles = int(tiles.size());
+  HMD_TRY(dalloc(ctx, &b->d_tiles, b->ntiles));
+  HMD_TRY(dalloc(ctx, &b->d_tilemode, b->ntiles));
+  HMD_HIP(ctx, hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice,
+                              ctx->stream));
+  HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return HMD_OK;
+}
+
 int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   if (!ctx || !out || !jobs || n < 1 || n > 65535) {
     if (ctx) ctx->err = "md batch: need 1..65535 jobs";
@@ -297,7 +364,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
       return HMD_EINVAL;
     }
   choose_path(ctx, jobs, n, &b->path, &b->skin, &b->tpb);
-  const double wmin = std::max(b->path == 1 ? b->P.rc + b->skin : b->P.rc, b->P.cell_w);
+  const double wmin = std::max(b->path >= 1 ? b->P.rc + b->skin : b->P.rc, b->P.cell_w);
   b->host.resize(n);
   for (int k = 0; k < n; ++k) {
     int rc = build_system(b->P, jobs[k].h, jobs[k].g, jobs[k].seed, wmin, b->host[k], ctx->err);
@@ -324,11 +391,16 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     const double margin = double(b->P.wall_layers) * half + 1.0;  // beyond the outermost wall layer
     D.y_lo = -margin;
     D.fix_x = kTwo32 / H.Lx;
-    D.fix_y = kTwo32 / (H.h + 2.0 * margin);
     D.fix_z = kTwo32 / H.Lz;
+    // y takes the x unit when the wall span fits in 2^32 of them (then, with
+    // Lx = Lz, one unit serves every axis)
+    const double span_y = H.h + 2.0 * margin;
+    D.fix_y = span_y < H.Lx ? D.fix_x : kTwo32 / span_y;
     D.unit_x = float(H.Lx / kTwo32);
-    D.unit_y = float((H.h + 2.0 * margin) / kTwo32);
+    D.unit_y = float(1.0 / D.fix_y);
     D.unit_z = float(H.Lz / kTwo32);
+    D.inv_u = float(D.fix_x);
+    D.inv_u2 = float(D.fix_x * D.fix_x);
     D.fwx = float(H.wx); D.fwy = float(H.wy); D.fwz = float(H.wz);
     D.nx = H.nx; D.ny = H.ny; D.nz = H.nz;
     D.a0 = int(a0); D.nf = int(H.nf);
@@ -348,14 +420,18 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     return HMD_EINVAL;
   }
   b->ntot = a0; b->ncell = c0; b->nwcell = wc0; b->nbins = bin0; b->nwall = w0;
+  b->uniform = true;
+  for (const SimDev& D : b->sims)
+    b->uniform = b->uniform && D.fix_x == D.fix_y && D.fix_x == D.fix_z;
   // the pair-list build packs a position index into 24 bits
   if (b->path == 1 && b->ntot + b->nwall >= (int64_t(1) << 24)) b->path = 0;
+  if (b->path == 2 && b->P.wall_layers < 1) b->path = 1;
   // pair-list capacity: neighbours within rc + skin at twice the fluid density
   // plus a wall half-space, rounded up to a multiple of 32
   const double rl = b->P.rc + b->skin;
   const double est = 2.0 * std::max(b->P.rho, 0.8) * 4.18879 * rl * rl * rl +
                      2.0 * b->P.rho_wall * 2.0944 * rl * rl * rl;
-  b->list_cap = b->path == 1 ? int(32 * std::ceil(est / 32.0)) : 0;
+  b->list_cap = b->path >= 1 ? int(32 * std::ceil(est / 32.0)) : 0;
   b->list_ld = int(64 * ((b->ntot + 63) / 64));
 
   int rc = HMD_OK;
@@ -384,7 +460,8 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   for (int w = 0; w < 2; ++w)
     for (int a = 0; a < 6; ++a)
       if ((rc = dalloc(ctx, &b->d_state[w][a], b->ntot))) return fail(rc);
-  // Morton numbering of every system's cells (rank tables, then inverses)
+  // cell numbering of every system (rank tables, then inverses): Morton
+  // order, or slab order (z, x, y) for the tiled path
   if ((rc = dalloc(ctx, &b->d_cellmap, 2 * b->ncell))) return fail(rc);
   b->cell_rank.assign(b->ncell, 0);
   std::vector<uint32_t> cell_lin(b->ncell);
@@ -393,7 +470,8 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     std::vector<std::pair<uint64_t, uint32_t>> order(D.ncell);
     for (int lid = 0; lid < D.ncell; ++lid) {
       const uint32_t cx = lid % D.nx, cy = (lid / D.nx) % D.ny, cz = lid / (D.nx * D.ny);
-      order[lid] = {morton3(cx, cy, cz), uint32_t(lid)};
+      const uint64_t key = b->path == 2 ? (uint64_t(cz) * D.nx + cx) * D.ny + cy : morton3(cx, cy, cz);
+      order[lid] = {key, uint32_t(lid)};
     }
     std::sort(order.begin(), order.end());
     for (int r = 0; r < D.ncell; ++r) {
@@ -403,6 +481,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     D.rank = b->d_cellmap + D.c0;
     D.lin = b->d_cellmap + b->ncell + D.c0;
   }
+  if (b->path == 2 && (rc = make_tiles(b))) return fail(rc);
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap, b->cell_rank.data(), 4 * b->ncell, hipMemcpyHostToDevice, ctx->stream));
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap + b->ncell, cell_lin.data(), 4 * b->ncell, hipMemcpyHostToDevice,
                               ctx->stream));
@@ -488,7 +567,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
       (rc = up(b->d_wstart, wstart.data(), 4 * b->nwcell)) ||
       (rc = up(b->d_wcount, wcount.data(), 4 * b->nwcell)) || (rc = up(b->d_dstate, dstate, sizeof(dstate))))
     return fail(rc);
-  if (b->path == 1 && (rc = up(b->d_pfix + b->ntot, wfix.data(), sizeof(int4) * b->nwall))) return fail(rc);
+  if (b->path >= 1 && (rc = up(b->d_pfix + b->ntot, wfix.data(), sizeof(int4) * b->nwall))) return fail(rc);
   for (int a = 0; a < 6; ++a)
     if ((rc = up(b->d_state[0][a], hs[a].data(), 8 * b->ntot))) return fail(rc);
   HMD_HIP(ctx, hipMemsetAsync(b->d_accbuf, 0, sizeof(double) * nacc, s));
@@ -512,7 +591,8 @@ void batch_free(hmd_batch* b) {
   void* ptrs[] = {b->d_sims, b->d_atom_sim, b->d_cell_sim, b->d_f4, b->d_pos4, b->d_pfix, b->d_pbuild,
                   b->d_slot_cell, b->d_list, b->d_nlist, b->d_flag, b->d_key, b->d_count, b->d_rank, b->d_start,
                   b->d_ncount, b->d_perm, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_dstate, b->d_tag[0],
-                  b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs, b->d_cellmap};
+                  b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs, b->d_cellmap, b->d_tiles,
+                  b->d_tilemode};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int w = 0; w < 2; ++w)
@@ -797,14 +877,22 @@ int batch_cells(hmd_batch* b, int sim, uint32_t* cell_of, uint32_t* counts, uint
 
 int batch_neighbors(hmd_batch* b, int sim, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total) {
   hmd_ctx* ctx = b->ctx;
-  if (sim < 0 || sim >= b->S || b->path != 1) return HMD_EINVAL;
+  if (sim < 0 || sim >= b->S || b->path == 0) return HMD_EINVAL;
   const SimDev& D = b->sims[sim];
   std::vector<uint32_t> nl(b->ntot), list(size_t(b->list_cap) * b->list_ld);
   std::vector<int> tag(b->ntot);
   hipStream_t s = ctx->stream;
+  // tiled lists hold LDS indices: rebuild them with position indices to read
+  // them out, then rebuild them as they were
+  if (b->path == 2)
+    launch_build(b, s, nullptr, StepRef{nullptr, -1}, state_ref(b, 0), state_ref(b, 0), b->d_tag[0],
+                 b->d_tag[0], 1);
   HMD_HIP(ctx, hipMemcpyAsync(nl.data(), b->d_nlist, 4 * b->ntot, hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(list.data(), b->d_list, 4 * list.size(), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(tag.data(), b->d_tag[0], 4 * b->ntot, hipMemcpyDeviceToHost, s));
+  if (b->path == 2)
+    launch_build(b, s, nullptr, StepRef{nullptr, -1}, state_ref(b, 0), state_ref(b, 0), b->d_tag[0],
+                 b->d_tag[0], 0);
   HMD_HIP(ctx, hipStreamSynchronize(s));
   // per atom id: neighbour ids (fluid ids, or N_f + wall index of the system)
   std::vector<std::vector<uint32_t>> per(D.nf);
@@ -849,7 +937,7 @@ int batch_list_builds(hmd_batch* b, int64_t* builds) {
   int flags[4] = {0, 0, 0, 0};
   HMD_HIP(ctx, hipMemcpyAsync(flags, b->d_flag, sizeof(flags), hipMemcpyDeviceToHost, ctx->stream));
   HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (builds) *builds = b->path == 1 ? int64_t(flags[3]) : 0;
+  if (builds) *builds = b->path >= 1 ? int64_t(flags[3]) : 0;
   return HMD_OK;
 }
 

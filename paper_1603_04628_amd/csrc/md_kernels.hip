@@ -637,12 +637,58 @@ __global__ __launch_bounds__(256) void k_force_cell(int ntot, const SimDev* __re
   finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, lds_vx, lds_cnt, &lds_base);
 }
 
+// Shifted LJ (Eq. LJ) for one list entry from a fixed-point separation,
+// accumulated into f (and pe, pair counts with ENERGY); entries past the
+// cut-off add zero through a select.  UNI: one fixed-point unit u on every
+// axis, so the separation stays in units -- r^2 compares with rc^2 / u^2,
+// sigma^2 / r^2 takes 1 / u^2, and f carries a factor u removed once per
+// atom by the caller (multiply by inv_u).
+struct PairConst {
+  float rc2, s2_ff, s2_wf, eps24_wf, eps4_wf, ush_ff, ush_wf;
+};
+
+template <int UNI>
+__device__ __forceinline__ PairConst pair_const(const StepConst& K, const SimDev& D) {
+  PairConst c;
+  c.rc2 = UNI ? K.rc2 * D.inv_u2 : K.rc2;
+  c.s2_ff = UNI ? D.inv_u2 : 1.0f;
+  c.s2_wf = UNI ? K.sig2_wf * D.inv_u2 : K.sig2_wf;
+  c.eps24_wf = 24.0f * K.eps_wf;
+  c.eps4_wf = 4.0f * K.eps_wf;
+  c.ush_ff = K.ush_ff;
+  c.ush_wf = K.ush_wf;
+  return c;
+}
+
+template <int ENERGY, int UNI>
+__device__ __forceinline__ void lj_term(int dx, int dy, int dz, bool wall, const PairConst& c, const SimDev& D,
+                                        float& fx, float& fy, float& fz, float& pe, uint32_t& nff,
+                                        uint32_t& nwf) {
+  const float ax = UNI ? float(dx) : float(dx) * D.unit_x;
+  const float ay = UNI ? float(dy) : float(dy) * D.unit_y;
+  const float az = UNI ? float(dz) : float(dz) * D.unit_z;
+  const float r2 = ax * ax + ay * ay + az * az;
+  const bool in = r2 < c.rc2;
+  const float ri2 = __builtin_amdgcn_rcpf(r2);  // 1 ulp
+  const float s2 = (wall ? c.s2_wf : c.s2_ff) * ri2;
+  const float s6 = s2 * s2 * s2;
+  const float eps24 = wall ? c.eps24_wf : 24.0f;
+  const float fr = in ? eps24 * s6 * (2.0f * s6 - 1.0f) * ri2 : 0.0f;
+  fx += fr * ax; fy += fr * ay; fz += fr * az;
+  if (ENERGY) {
+    const float u = wall ? c.eps4_wf * s6 * (s6 - 1.0f) - c.ush_wf : 0.5f * (4.0f * s6 * (s6 - 1.0f) - c.ush_ff);
+    pe += in ? u : 0.0f;
+    nwf += (in && wall) ? 1u : 0u;
+    nff += (in && !wall) ? 1u : 0u;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pair-path force (one thread per slot): the same shifted LJ sum over the
 // slot's Verlet list (entries >= ntot are wall atoms), FP32 from fixed-point
 // separations.
 // ---------------------------------------------------------------------------
-template <int MODE, int ENERGY>
+template <int MODE, int ENERGY, int UNI>
 __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimDev* __restrict__ sims,
                                                     const uint16_t* __restrict__ atom_sim,
                                                     const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
@@ -662,26 +708,11 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
     const int4 me = pfix[i];
     const uint32_t n = nlist[i];
     const uint4* grp = reinterpret_cast<const uint4*>(list) + i;  // group g at grp[g * ld]
-    // Shifted LJ (Eq. LJ) for one list entry; entries past the cut-off add
-    // zero through a select rather than a branch.
+    const PairConst pc = pair_const<UNI>(K, D);
     auto pair = [&](uint32_t j, const int4& o) {
-      const float3 d = fixed_sep(me, o, D);
-      const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-      const bool in = r2 < K.rc2;
-      const bool wall = j >= uint32_t(ntot);
-      const float ri2 = __builtin_amdgcn_rcpf(r2);  // 1 ulp
-      const float s2 = wall ? K.sig2_wf * ri2 : ri2;
-      const float s6 = s2 * s2 * s2;
-      const float eps24 = wall ? 24.0f * K.eps_wf : 24.0f;
-      const float fr = in ? eps24 * s6 * (2.0f * s6 - 1.0f) * ri2 : 0.0f;
-      fx += fr * d.x; fy += fr * d.y; fz += fr * d.z;
-      if (ENERGY) {
-        const float u = wall ? 4.0f * K.eps_wf * s6 * (s6 - 1.0f) - K.ush_wf
-                             : 0.5f * (4.0f * s6 * (s6 - 1.0f) - K.ush_ff);
-        pe += in ? u : 0.0f;
-        nwf += (in && wall) ? 1u : 0u;
-        nff += (in && !wall) ? 1u : 0u;
-      }
+      lj_term<ENERGY, UNI>(int(uint32_t(me.x) - uint32_t(o.x)), int(uint32_t(me.y) - uint32_t(o.y)),
+                           int(uint32_t(me.z) - uint32_t(o.z)), j >= uint32_t(ntot), pc, D, fx, fy, fz, pe, nff,
+                           nwf);
     };
     // One coalesced 16-byte load brings four entries.  The next group's load
     // is issued before this group's arithmetic so that its latency overlaps
@@ -703,6 +734,7 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
       if (rest > 1) pair(jj.y, pfix[jj.y]);
       if (rest > 2) pair(jj.z, pfix[jj.z]);
     }
+    if (UNI) { fx *= D.inv_u; fy *= D.inv_u; fz *= D.inv_u; }
     f4[i] = make_float4(fx, fy, fz, pe);
   }
   if (ENERGY) {
@@ -713,6 +745,316 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
     }
   }
   finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, lds_vx, lds_cnt, &lds_base);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled pair path.  Cells are numbered slab by slab ((z nx + x) ny + y), so a
+// tile -- ncol whole columns of one z slab -- owns one contiguous slot range,
+// and everything its atoms can reach lies in three slabs (z - 1, z, z + 1)
+// over columns x0 - 1 .. x0 + ncol: per slab one contiguous range of fluid
+// slots and one of wall atoms per wall (two of each where the columns wrap
+// around x).  A workgroup copies those ranges into LDS (fluid ranges first,
+// then walls) and its lists hold 16-bit LDS indices, so the force loop reads
+// neighbour positions from LDS instead of gathering them from memory.  A
+// tile whose ranges exceed the LDS capacity keeps 32-bit position indices
+// and gathers from memory instead.
+// ---------------------------------------------------------------------------
+constexpr int TILE_TPB = 256;
+constexpr int TILE_RUNS = 18;  // kind (fluid, lower wall, upper wall) x 3 slabs x 2 pieces
+
+struct TileStage {
+  uint32_t gb[TILE_RUNS];       // first entry of each range in the position array
+  uint32_t off[TILE_RUNS + 1];  // LDS offset of each range (prefix sums)
+  int pa[2], pb[2], npieces;    // column pieces of the x range
+  int s, z, x0, ncol;
+  uint32_t home0, home1;        // home slots
+};
+
+// Column pieces of x0 - 1 .. x0 + ncol with periodic wrap (one piece covers
+// the whole row when the range would meet itself).
+__device__ __forceinline__ void tile_pieces(int x0, int ncol, int nx, int* pa, int* pb, int* np) {
+  if (ncol + 2 >= nx) {
+    pa[0] = 0; pb[0] = nx - 1; *np = 1;
+    return;
+  }
+  const int xa = x0 - 1, xb = x0 + ncol;
+  if (xa < 0) {
+    pa[0] = xa + nx; pb[0] = nx - 1; pa[1] = 0; pb[1] = xb; *np = 2;
+  } else if (xb >= nx) {
+    pa[0] = xa; pb[0] = nx - 1; pa[1] = 0; pb[1] = xb - nx; *np = 2;
+  } else {
+    pa[0] = xa; pb[0] = xb; *np = 1;
+  }
+}
+
+// Fills the range table of tile t (all threads; ends with a barrier).
+__device__ __forceinline__ void tile_ranges(const int4& tile, int ntot, const SimDev* __restrict__ sims,
+                                            const uint32_t* __restrict__ start,
+                                            const uint32_t* __restrict__ ncount,
+                                            const uint32_t* __restrict__ wstart,
+                                            const uint32_t* __restrict__ wcount, TileStage& T) {
+  __shared__ uint32_t len[TILE_RUNS];
+  const int tid = threadIdx.x;
+  const SimDev& D = sims[tile.x];
+  if (tid == 0) {
+    T.s = tile.x; T.z = tile.y; T.x0 = tile.z; T.ncol = tile.w;
+    tile_pieces(tile.z, tile.w, D.nx, T.pa, T.pb, &T.npieces);
+    const uint32_t c_first = uint32_t(D.c0 + (tile.y * D.nx + tile.z) * D.ny);
+    const uint32_t c_last = c_first + uint32_t(tile.w * D.ny) - 1u;
+    T.home0 = start[c_first];
+    T.home1 = start[c_last] + ncount[c_last];
+  }
+  __syncthreads();
+  if (tid < TILE_RUNS) {
+    const int kind = tid / 6, dz = (tid / 2) % 3 - 1, piece = tid & 1;
+    uint32_t gb = 0, n = 0;
+    if (piece < T.npieces) {
+      int zz = T.z + dz;
+      zz += zz < 0 ? D.nz : (zz >= D.nz ? -D.nz : 0);
+      const int a = T.pa[piece], b = T.pb[piece];
+      if (kind == 0) {
+        const uint32_t c1 = uint32_t(D.c0 + (zz * D.nx + a) * D.ny);
+        const uint32_t c2 = uint32_t(D.c0 + (zz * D.nx + b) * D.ny + D.ny - 1);
+        gb = start[c1];
+        n = start[c2] + ncount[c2] - gb;
+      } else {
+        const uint32_t w1 = uint32_t(D.wc0 + ((kind - 1) * D.nz + zz) * D.nx + a);
+        const uint32_t w2 = uint32_t(D.wc0 + ((kind - 1) * D.nz + zz) * D.nx + b);
+        gb = uint32_t(ntot) + wstart[w1];
+        n = wstart[w2] + wcount[w2] - wstart[w1];
+      }
+    }
+    T.gb[tid] = gb;
+    len[tid] = n;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int r = 0; r < TILE_RUNS; ++r) {
+      T.off[r] = acc;
+      acc += len[r];
+    }
+    T.off[TILE_RUNS] = acc;
+  }
+  __syncthreads();
+}
+
+// Copies the tile's ranges into LDS (structure of arrays; caller checks the
+// capacity first).
+__device__ __forceinline__ void tile_stage(const TileStage& T, const int4* __restrict__ pfix, int* lx, int* ly,
+                                           int* lz) {
+  for (int r = 0; r < TILE_RUNS; ++r) {  // range by range: contiguous loads, no search
+    const uint32_t o = T.off[r], n = T.off[r + 1] - o, g = T.gb[r];
+    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+      const int4 p = pfix[g + k];
+      lx[o + k] = p.x; ly[o + k] = p.y; lz[o + k] = p.z;
+    }
+  }
+  __syncthreads();
+}
+
+// Verlet lists of a tile's atoms (rebuild steps only).  Also completes the
+// reorder (state copy back) for the tile's slots.  global_out writes 32-bit
+// position indices (the layout of k_build_list) for every tile.
+__global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
+    int ntot, int ld, int cap, int stage_cap, const int4* __restrict__ tiles, const SimDev* __restrict__ sims,
+    const uint32_t* __restrict__ slot_cell, const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
+    const uint32_t* __restrict__ ncount, const uint32_t* __restrict__ wstart, const uint32_t* __restrict__ wcount,
+    uint32_t* __restrict__ list, uint32_t* __restrict__ nlist, uint8_t* __restrict__ tilemode, StateRef from,
+    StateRef to, const int* __restrict__ tag_from, int* __restrict__ tag_to, int* __restrict__ overflow,
+    const int* __restrict__ flag, StepRef R, float rl2, int global_out) {
+  if (!rebuild_needed(flag, R)) return;
+  extern __shared__ int lds_pos[];
+  __shared__ TileStage T;
+  const int t = xcd_block();
+  tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
+  const uint32_t total = T.off[TILE_RUNS];
+  const bool local = !global_out && total <= uint32_t(stage_cap);
+  int* lx = lds_pos;
+  int* ly = lx + stage_cap;
+  int* lz = ly + stage_cap;
+  if (local) tile_stage(T, pfix, lx, ly, lz);
+  if (threadIdx.x == 0) tilemode[t] = local ? 0 : 1;
+  if (t == 0 && threadIdx.x == 0) atomicAdd(&overflow[1], 1);  // builds so far
+  const SimDev& D = sims[T.s];
+  const bool copy = from.x != to.x;  // a rebuild outside the step sequence copies nothing
+  for (uint32_t i = T.home0 + threadIdx.x; i < T.home1; i += blockDim.x) {
+    if (copy) {
+      to.x[i] = from.x[i]; to.y[i] = from.y[i]; to.z[i] = from.z[i];
+      to.vx[i] = from.vx[i]; to.vy[i] = from.vy[i]; to.vz[i] = from.vz[i];
+      tag_to[i] = tag_from[i];
+    }
+    const int4 me = pfix[i];
+    const int r0 = int(slot_cell[i]) - D.c0;  // (z nx + x) ny + y
+    const int cy = r0 % D.ny, cx = (r0 / D.ny) % D.nx, cz = r0 / (D.ny * D.nx);
+    uint32_t cnt = 0;
+    uint16_t* list16 = reinterpret_cast<uint16_t*>(list);
+    // entry c of slot i: 16-bit at ((c / 8) ld + i) 8 + c % 8 (LDS index),
+    // 32-bit at ((c / 4) ld + i) 4 + c % 4 (position index)
+    auto put16 = [&](bool hit, uint32_t k) {
+      if (hit && cnt < uint32_t(cap)) list16[(size_t(cnt >> 3) * ld + i) * 8 + (cnt & 7u)] = uint16_t(k);
+      cnt += hit ? 1u : 0u;
+    };
+    auto put32 = [&](bool hit, uint32_t q) {
+      if (hit && cnt < uint32_t(cap)) list[(size_t(cnt >> 2) * ld + i) * 4 + (cnt & 3u)] = q;
+      cnt += hit ? 1u : 0u;
+    };
+    for (int dz = -1; dz <= 1; ++dz) {
+      int jz = cz + dz;
+      jz += jz < 0 ? D.nz : (jz >= D.nz ? -D.nz : 0);
+      for (int dx = -1; dx <= 1; ++dx) {
+        int jx = cx + dx;
+        jx += jx < 0 ? D.nx : (jx >= D.nx ? -D.nx : 0);
+        const int piece = (T.npieces == 1 || (jx >= T.pa[0] && jx <= T.pb[0])) ? 0 : 1;
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int jy = cy + dy;
+          const int kind = jy < 0 ? 1 : (jy >= D.ny ? 2 : 0);
+          uint32_t cb, cn;
+          if (kind == 0) {
+            const uint32_t gc = uint32_t(D.c0 + (jz * D.nx + jx) * D.ny + jy);
+            cb = start[gc];
+            cn = ncount[gc];
+          } else {
+            const uint32_t wc = uint32_t(D.wc0 + ((kind - 1) * D.nz + jz) * D.nx + jx);
+            cb = uint32_t(ntot) + wstart[wc];
+            cn = wcount[wc];
+          }
+          const int run = kind * 6 + (dz + 1) * 2 + piece;
+          const uint32_t base = T.off[run] + (cb - T.gb[run]);
+          const uint32_t self = i - cb;  // candidate index of the atom itself (if in this cell)
+          if (local) {
+            // four candidates per pass: their LDS reads are in flight together
+            uint32_t m = 0;
+            for (; m + 4 <= cn; m += 4) {
+              float r2[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const uint32_t k = base + m + u;
+                const float3 d = fixed_sep(me, make_int4(lx[k], ly[k], lz[k], 0), D);
+                r2[u] = d.x * d.x + d.y * d.y + d.z * d.z;
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) put16(r2[u] < rl2 && m + u != self, base + m + u);
+            }
+            for (; m < cn; ++m) {
+              const uint32_t k = base + m;
+              const float3 d = fixed_sep(me, make_int4(lx[k], ly[k], lz[k], 0), D);
+              put16(d.x * d.x + d.y * d.y + d.z * d.z < rl2 && m != self, k);
+            }
+          } else {
+            for (uint32_t m = 0; m < cn; ++m) {
+              const float3 d = fixed_sep(me, pfix[cb + m], D);
+              put32(d.x * d.x + d.y * d.y + d.z * d.z < rl2 && m != self, cb + m);
+            }
+          }
+        }
+      }
+    }
+    if (cnt > uint32_t(cap)) {
+      atomicMax(&overflow[0], int(cnt));
+      cnt = cap;
+    }
+    nlist[i] = cnt;
+  }
+}
+
+// Forces of a tile's atoms from their lists, neighbour positions read from
+// LDS (or gathered, for a tile built with 32-bit indices), then the second
+// half-kick and the sample of the step.
+template <int MODE, int ENERGY, int UNI>
+__global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
+    int ntot, int ld, int stage_cap, const int4* __restrict__ tiles, const uint8_t* __restrict__ tilemode,
+    const SimDev* __restrict__ sims, const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
+    const uint32_t* __restrict__ ncount, const uint32_t* __restrict__ wstart, const uint32_t* __restrict__ wcount,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ nlist, float4* __restrict__ f4, StateRef st,
+    Acc acc, int64_t* __restrict__ dstate, StepRef R, StepConst K) {
+  extern __shared__ int lds_pos[];
+  __shared__ TileStage T;
+  __shared__ double lds_vx[BIN_LDS];
+  __shared__ double lds_cnt[BIN_LDS];
+  __shared__ int lds_base;
+  const int t = xcd_block();
+  tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
+  const bool local = tilemode[t] == 0;
+  int* lx = lds_pos;
+  int* ly = lx + stage_cap;
+  int* lz = ly + stage_cap;
+  if (local) tile_stage(T, pfix, lx, ly, lz);
+  const uint32_t first_wall = local ? T.off[6] : uint32_t(ntot);  // walls come after the fluid ranges
+  const int s = T.s;
+  const SimDev& D = sims[s];
+  const uint32_t n_home = T.home1 - T.home0;
+  for (uint32_t base = 0; base < n_home; base += blockDim.x) {
+    const uint32_t i = T.home0 + base + threadIdx.x;
+    const bool valid = base + threadIdx.x < n_home;
+    float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
+    uint32_t nff = 0, nwf = 0;
+    if (valid) {
+      const int4 me = pfix[i];
+      const uint32_t n = nlist[i];
+      const uint4* grp = reinterpret_cast<const uint4*>(list) + i;
+      const PairConst pc = pair_const<UNI>(K, D);
+      auto pair = [&](uint32_t j, int ox, int oy, int oz) {
+        lj_term<ENERGY, UNI>(int(uint32_t(me.x) - uint32_t(ox)), int(uint32_t(me.y) - uint32_t(oy)),
+                             int(uint32_t(me.z) - uint32_t(oz)), j >= first_wall, pc, D, fx, fy, fz, pe, nff,
+                             nwf);
+      };
+      if (local) {
+        // eight 16-bit LDS indices per 16-byte group; the next group is
+        // requested before this one's arithmetic
+        const uint32_t full = n >> 3, rest = n & 7u, ngrp = (n + 7u) >> 3;
+        uint4 jj = ngrp ? grp[0] : make_uint4(0u, 0u, 0u, 0u);
+        auto two = [&](uint32_t w) {
+          const uint32_t k0 = w & 0xffffu, k1 = w >> 16;
+          pair(k0, lx[k0], ly[k0], lz[k0]);
+          pair(k1, lx[k1], ly[k1], lz[k1]);
+        };
+        for (uint32_t g = 0; g < full; ++g) {
+          const uint32_t gn = g + 1 < ngrp ? g + 1 : g;
+          const uint4 jn = grp[size_t(gn) * ld];
+          two(jj.x); two(jj.y); two(jj.z); two(jj.w);
+          jj = jn;
+        }
+        if (rest) {  // jj holds the partial last group
+          const uint32_t w[4] = {jj.x, jj.y, jj.z, jj.w};
+#pragma unroll
+          for (int e = 0; e < 7; ++e)
+            if (uint32_t(e) < rest) {
+              const uint32_t k = (w[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+              pair(k, lx[k], ly[k], lz[k]);
+            }
+        }
+      } else {
+        const uint32_t full = n >> 2, rest = n & 3u;
+        for (uint32_t g = 0; g < full; ++g) {
+          const uint4 jj = grp[size_t(g) * ld];
+          const int4 o0 = pfix[jj.x], o1 = pfix[jj.y], o2 = pfix[jj.z], o3 = pfix[jj.w];
+          pair(jj.x, o0.x, o0.y, o0.z);
+          pair(jj.y, o1.x, o1.y, o1.z);
+          pair(jj.z, o2.x, o2.y, o2.z);
+          pair(jj.w, o3.x, o3.y, o3.z);
+        }
+        if (rest) {
+          const uint4 jj = grp[size_t(full) * ld];
+          const int4 o0 = pfix[jj.x];
+          pair(jj.x, o0.x, o0.y, o0.z);
+          if (rest > 1) { const int4 o1 = pfix[jj.y]; pair(jj.y, o1.x, o1.y, o1.z); }
+          if (rest > 2) { const int4 o2 = pfix[jj.z]; pair(jj.z, o2.x, o2.y, o2.z); }
+        }
+      }
+      if (UNI) { fx *= D.inv_u; fy *= D.inv_u; fz *= D.inv_u; }
+      f4[i] = make_float4(fx, fy, fz, pe);
+    }
+    if (ENERGY) {
+      const unsigned long long a = wave_sum((unsigned long long)nff), w = wave_sum((unsigned long long)nwf);
+      if ((threadIdx.x & (WAVE - 1)) == 0) {
+        atomicAdd(&acc.pairs[0], a);
+        atomicAdd(&acc.pairs[1], w);
+      }
+    }
+    finish_force<MODE>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, lds_vx, lds_cnt,
+                       &lds_base);
+  }
 }
 
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
@@ -739,14 +1081,33 @@ template __global__ void k_force_cell<0>(int, const SimDev*, const uint16_t*, co
 template __global__ void k_force_cell<1>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
                                          const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
                                          StateRef, Acc, int64_t*, StepRef, StepConst);
-#define HMD_FORCE_LIST(M, E)                                                                          \
-  template __global__ void k_force_list<M, E>(int, int, const SimDev*, const uint16_t*, const int4*,          \
+#define HMD_FORCE_TILES(M, E, U)                                                                       \
+  template __global__ void k_force_tiles<M, E, U>(int, int, int, const int4*, const uint8_t*, const SimDev*,     \
+                                               const int4*, const uint32_t*, const uint32_t*, const uint32_t*, \
+                                               const uint32_t*, const uint32_t*, const uint32_t*, float4*,     \
+                                               StateRef, Acc, int64_t*, StepRef, StepConst);
+HMD_FORCE_TILES(0, 0, 0)
+HMD_FORCE_TILES(0, 1, 0)
+HMD_FORCE_TILES(1, 0, 0)
+HMD_FORCE_TILES(1, 1, 0)
+HMD_FORCE_TILES(0, 0, 1)
+HMD_FORCE_TILES(0, 1, 1)
+HMD_FORCE_TILES(1, 0, 1)
+HMD_FORCE_TILES(1, 1, 1)
+#undef HMD_FORCE_TILES
+
+#define HMD_FORCE_LIST(M, E, U)                                                                       \
+  template __global__ void k_force_list<M, E, U>(int, int, const SimDev*, const uint16_t*, const int4*,          \
                                               const uint32_t*, const uint32_t*, float4*, StateRef, Acc,       \
                                               int64_t*, StepRef, StepConst);
-HMD_FORCE_LIST(0, 0)
-HMD_FORCE_LIST(0, 1)
-HMD_FORCE_LIST(1, 0)
-HMD_FORCE_LIST(1, 1)
+HMD_FORCE_LIST(0, 0, 0)
+HMD_FORCE_LIST(0, 1, 0)
+HMD_FORCE_LIST(1, 0, 0)
+HMD_FORCE_LIST(1, 1, 0)
+HMD_FORCE_LIST(0, 0, 1)
+HMD_FORCE_LIST(0, 1, 1)
+HMD_FORCE_LIST(1, 0, 1)
+HMD_FORCE_LIST(1, 1, 1)
 #undef HMD_FORCE_LIST
 
 }  // namespace hmd

@@ -34,10 +34,10 @@ std::string signature(const hmd_ctx* ctx, const hmd_md_job* jobs, int n) {
 
 void choose_path(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int* path, double* skin, int* tpb) {
   const hmd_md_params& P = ctx->params;
-  *path = 1;
+  *path = 2;  // LDS-staged tiles unless tuned or asked otherwise
   *skin = P.skin > 0.0 ? P.skin : 0.3;
   *tpb = 256;
-  if (P.force_path == 0 || P.force_path == 1) {
+  if (P.force_path >= 0 && P.force_path <= 2) {
     *path = P.force_path;
     return;
   }
@@ -64,7 +64,7 @@ int md_autotune(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int probe_steps, do
     int tpb;
   };
   std::vector<Cand> cands = {{0, 0.0, 128}, {0, 0.0, 256}, {1, 0.2, 256}, {1, 0.3, 128}, {1, 0.3, 256},
-                             {1, 0.4, 256}, {1, 0.5, 256}};
+                             {1, 0.4, 256}, {1, 0.5, 256}, {2, 0.3, 256}, {2, 0.4, 256}, {2, 0.5, 256}};
   const hmd_md_params saved = ctx->params;
   // probe without the sampling schedule: open-ended runs
   std::vector<hmd_md_job> probe(jobs, jobs + n);

@@ -20,12 +20,12 @@ SMALL_L = dict(Lx_nom=workloads.BOX_SMALL_LITERAL, Lz_nom=workloads.BOX_SMALL_LI
 SMALL = dict(Lx_nom=workloads.BOX_SMALL, Lz_nom=workloads.BOX_SMALL, n_fluid=2048)
 LARGE = dict(Lx_nom=workloads.BOX_LARGE, Lz_nom=workloads.BOX_LARGE)
 SKIN = 0.3
-PATHS = [0, 1]
+PATHS = [0, 1, 2]  # cell lists, pair lists, LDS-staged tiles of pair lists
 
 
 def _pair(h, g, seed, path=1, **params):
     ctx = hmd.Context(hmd.Params(force_path=path, skin=SKIN, **params))
-    cell_w = 2.5 + SKIN if path == 1 else 0.0
+    cell_w = 2.5 + SKIN if path >= 1 else 0.0
     return ctx, hmd.System(ctx, h, g, seed), omd.System(h, g, seed, omd.Params(cell_w=cell_w, **params))
 
 
@@ -63,9 +63,11 @@ def test_cell_membership_bit_exact(h, params, steps, path):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("h,params,steps", [(6.0, SMALL_L, 300), (4.0, SMALL_L, 100), (12.0, SMALL_L, 200)])
-def test_pair_lists_match_oracle_neighbour_sets(h, params, steps):
-    ctx, g_sys, o_sys = _pair(h, 0.02, 6, 1, **params)
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("h,params,steps", [(6.0, SMALL_L, 300), (4.0, SMALL_L, 100), (12.0, SMALL_L, 200),
+                                            (15.0, SMALL, 200)])
+def test_pair_lists_match_oracle_neighbour_sets(h, params, steps, path):
+    ctx, g_sys, o_sys = _pair(h, 0.02, 6, path, **params)
     o_sys.run(steps)
     xo, vo = o_sys.get_state()
     g_sys.set_state(xo, vo)
@@ -220,10 +222,11 @@ def test_paths_agree_on_a_trajectory():
         s = hmd.System(ctx, 6.0, 0.05, 12)
         s.run(60)
         out.append(s.get_state())
-    d = out[0][0] - out[1][0]
-    d[:, 0] -= s.Lx * np.round(d[:, 0] / s.Lx)
-    d[:, 2] -= s.Lz * np.round(d[:, 2] / s.Lz)
-    assert np.sqrt((d ** 2).mean()) < 1e-4
+    for other in out[1:]:
+        d = out[0][0] - other[0]
+        d[:, 0] -= s.Lx * np.round(d[:, 0] / s.Lx)
+        d[:, 2] -= s.Lz * np.round(d[:, 2] / s.Lz)
+        assert np.sqrt((d ** 2).mean()) < 1e-4
 
 
 def test_unstable_system_is_reported():
