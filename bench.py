@@ -285,7 +285,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--skin", type=float, default=0.3, help="pair-list skin (sigma)")
+    ap.add_argument("--skin", type=float, default=0.35, help="pair-list skin (sigma); 0.35 is the best of a 0.25-0.45 sweep on this workload")
     ap.add_argument("--force-path", type=int, default=-1, help="0 cell lists, 1 pair lists, -1 library choice")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the surrogate and hybrid-solve measurement")
     ap.add_argument("--train-points", type=int, default=256)

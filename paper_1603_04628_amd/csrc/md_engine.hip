@@ -104,7 +104,7 @@ void launch_build(hmd_batch* b, hipStream_t s, const int* flag, StepRef R, State
   const int nt = int(b->ntot), tpb = b->tpb, nb = blocks_for(nt, tpb);
   const float rl2 = float((b->P.rc + b->skin) * (b->P.rc + b->skin));
   if (b->path == 2) {
-    hipLaunchKernelGGL(k_build_tiles, dim3(b->ntiles), dim3(TILE_THREADS), size_t(12) * b->stage_cap, s, nt,
+    hipLaunchKernelGGL(k_build_tiles, dim3(b->ntiles), dim3(TILE_THREADS), 0, s, nt,
                        b->list_ld, b->list_cap, b->stage_cap, b->d_tiles, b->d_sims, b->d_slot_cell, b->d_pfix,
                        b->d_start, b->d_ncount, b->d_wstart, b->d_wcount, b->d_list, b->d_nlist, b->d_tilemode,
                        from, to, tag_from, tag_to, b->d_flag + 2, flag, R, rl2, global_out);
@@ -164,6 +164,25 @@ void enqueue_sort(hmd_batch* b, Launcher& L, const StepConst& K, const int* flag
   L.end();
 }
 
+// Pair-path force kernels by variant index ((mode 2 + energy) 2 + uniform
+// unit) 2 + wall parameters equal to the fluid's.
+#define HMD_V(K, M, E, U, W) &K<M, E, U, W>
+#define HMD_VARIANTS(K)                                                                                   \
+  HMD_V(K, 0, 0, 0, 0), HMD_V(K, 0, 0, 0, 1), HMD_V(K, 0, 0, 1, 0), HMD_V(K, 0, 0, 1, 1),               \
+      HMD_V(K, 0, 1, 0, 0), HMD_V(K, 0, 1, 0, 1), HMD_V(K, 0, 1, 1, 0), HMD_V(K, 0, 1, 1, 1),           \
+      HMD_V(K, 1, 0, 0, 0), HMD_V(K, 1, 0, 0, 1), HMD_V(K, 1, 0, 1, 0), HMD_V(K, 1, 0, 1, 1),           \
+      HMD_V(K, 1, 1, 0, 0), HMD_V(K, 1, 1, 0, 1), HMD_V(K, 1, 1, 1, 0), HMD_V(K, 1, 1, 1, 1)
+decltype(&k_force_tiles<0, 0, 0, 0>) force_tiles_variant(int v) {
+  static const decltype(&k_force_tiles<0, 0, 0, 0>) tab[16] = {HMD_VARIANTS(k_force_tiles)};
+  return tab[v];
+}
+decltype(&k_force_list<0, 0, 0, 0>) force_list_variant(int v) {
+  static const decltype(&k_force_list<0, 0, 0, 0>) tab[16] = {HMD_VARIANTS(k_force_list)};
+  return tab[v];
+}
+#undef HMD_VARIANTS
+#undef HMD_V
+
 void enqueue_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K, StepRef R) {
   const int nt = int(b->ntot), tpb = b->tpb, nb = blocks_for(nt, tpb);
   const int src = b->cur;
@@ -176,22 +195,18 @@ void enqueue_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K, St
       hipLaunchKernelGGL(k_force_cell<1>, dim3(nb), dim3(tpb), 0, s, nt, b->d_sims, b->d_atom_sim, b->d_pos4,
                          b->d_start, b->d_ncount, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_f4, state_ref(b, src),
                          b->acc, b->d_dstate, R, K);
-  } else if (b->path == 2) {
-    auto* kern = b->uniform ? (mode == 0 ? (K.energy_on ? k_force_tiles<0, 1, 1> : k_force_tiles<0, 0, 1>)
-                                         : (K.energy_on ? k_force_tiles<1, 1, 1> : k_force_tiles<1, 0, 1>))
-                            : (mode == 0 ? (K.energy_on ? k_force_tiles<0, 1, 0> : k_force_tiles<0, 0, 0>)
-                                         : (K.energy_on ? k_force_tiles<1, 1, 0> : k_force_tiles<1, 0, 0>));
-    hipLaunchKernelGGL(kern, dim3(b->ntiles), dim3(TILE_THREADS), size_t(12) * b->stage_cap, s, nt, b->list_ld,
-                       b->stage_cap, b->d_tiles, b->d_tilemode, b->d_sims, b->d_pfix, b->d_start, b->d_ncount,
-                       b->d_wstart, b->d_wcount, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc,
-                       b->d_dstate, R, K);
   } else {
-    auto* kern = b->uniform ? (mode == 0 ? (K.energy_on ? k_force_list<0, 1, 1> : k_force_list<0, 0, 1>)
-                                         : (K.energy_on ? k_force_list<1, 1, 1> : k_force_list<1, 0, 1>))
-                            : (mode == 0 ? (K.energy_on ? k_force_list<0, 1, 0> : k_force_list<0, 0, 0>)
-                                         : (K.energy_on ? k_force_list<1, 1, 0> : k_force_list<1, 0, 0>));
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims, b->d_atom_sim, b->d_pfix,
-                       b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
+    const int v = ((mode * 2 + (K.energy_on ? 1 : 0)) * 2 + (b->uniform ? 1 : 0)) * 2 + (b->walls_same ? 1 : 0);
+    if (b->path == 2) {
+      hipLaunchKernelGGL(force_tiles_variant(v), dim3(b->ntiles), dim3(TILE_THREADS), 0, s, nt, b->list_ld,
+                         b->stage_cap, b->d_tiles, b->d_tilemode, b->d_sims, b->d_pfix, b->d_start, b->d_ncount,
+                         b->d_wstart, b->d_wcount, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc,
+                         b->d_dstate, R, K);
+    } else {
+      hipLaunchKernelGGL(force_list_variant(v), dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims,
+                         b->d_atom_sim, b->d_pfix, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc,
+                         b->d_dstate, R, K);
+    }
   }
 }
 
@@ -308,7 +323,7 @@ int get_graph(hmd_batch* b, int chunk, const StepConst& K, hipGraphExec_t* out) 
 // staged neighbourhood fits the LDS capacity.
 int make_tiles(hmd_batch* b) {
   hmd_ctx* ctx = b->ctx;
-  constexpr int kStageCap = 4096;  // atoms (x, y, z fixed point: 48 KiB)
+  constexpr int kStageCap = TILE_STAGE;
   b->stage_cap = kStageCap;
   std::vector<int4> tiles;
   for (int k = 0; k < b->S; ++k) {
@@ -420,6 +435,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     return HMD_EINVAL;
   }
   b->ntot = a0; b->ncell = c0; b->nwcell = wc0; b->nbins = bin0; b->nwall = w0;
+  b->walls_same = b->P.eps_wf == 1.0 && b->P.sigma_wf == 1.0;
   b->uniform = true;
   for (const SimDev& D : b->sims)
     b->uniform = b->uniform && D.fix_x == D.fix_y && D.fix_x == D.fix_z;

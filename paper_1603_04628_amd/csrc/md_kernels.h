@@ -46,18 +46,21 @@ __global__ void k_force_cell(int ntot, const SimDev* sims, const uint16_t* atom_
                              const uint32_t* start, const uint32_t* ncount, const float4* wpos4,
                              const uint32_t* wstart, const uint32_t* wcount, float4* f4, StateRef st, Acc acc,
                              int64_t* dstate, StepRef R, StepConst K);
-template <int MODE, int ENERGY, int UNI>
+template <int MODE, int ENERGY, int UNI, int WS>
 __global__ void k_force_list(int ntot, int ld, const SimDev* sims, const uint16_t* atom_sim, const int4* pfix,
                              const uint32_t* list, const uint32_t* nlist, float4* f4, StateRef st, Acc acc,
                              int64_t* dstate, StepRef R, StepConst K);
 constexpr int TILE_THREADS = 256;  // threads per tile workgroup
+// LDS capacity of a tile in atoms (x, y, z fixed point: 48 KiB); a
+// compile-time size lets every LDS read carry its array offset as an immediate
+constexpr int TILE_STAGE = 4096;
 __global__ void k_build_tiles(int ntot, int ld, int cap, int stage_cap, const int4* tiles, const SimDev* sims,
                               const uint32_t* slot_cell, const int4* pfix, const uint32_t* start,
                               const uint32_t* ncount, const uint32_t* wstart, const uint32_t* wcount,
                               uint32_t* list, uint32_t* nlist, uint8_t* tilemode, StateRef from, StateRef to,
                               const int* tag_from, int* tag_to, int* overflow, const int* flag, StepRef R,
                               float rl2, int global_out);
-template <int MODE, int ENERGY, int UNI>
+template <int MODE, int ENERGY, int UNI, int WS>
 __global__ void k_force_tiles(int ntot, int ld, int stage_cap, const int4* tiles, const uint8_t* tilemode,
                               const SimDev* sims, const int4* pfix, const uint32_t* start, const uint32_t* ncount,
                               const uint32_t* wstart, const uint32_t* wcount, const uint32_t* list,

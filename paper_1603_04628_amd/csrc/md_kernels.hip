@@ -639,8 +639,8 @@ __global__ __launch_bounds__(256) void k_force_cell(int ntot, const SimDev* __re
 
 // Shifted LJ (Eq. LJ) for one list entry from a fixed-point separation,
 // accumulated into f (and pe, pair counts with ENERGY); entries past the
-// cut-off add zero through a select.  UNI: one fixed-point unit u on every
-// axis, so the separation stays in units -- r^2 compares with rc^2 / u^2,
+// cut-off add zero through a select.  WS: sigma_wf = eps_wf = 1.  UNI: one
+// fixed-point unit u on every axis, so the separation stays in units -- r^2 compares with rc^2 / u^2,
 // sigma^2 / r^2 takes 1 / u^2, and f carries a factor u removed once per
 // atom by the caller (multiply by inv_u).
 struct PairConst {
@@ -660,10 +660,12 @@ __device__ __forceinline__ PairConst pair_const(const StepConst& K, const SimDev
   return c;
 }
 
-template <int ENERGY, int UNI>
-__device__ __forceinline__ void lj_term(int dx, int dy, int dz, bool wall, const PairConst& c, const SimDev& D,
-                                        float& fx, float& fy, float& fz, float& pe, uint32_t& nff,
-                                        uint32_t& nwf) {
+template <int ENERGY, int UNI, int WS>
+__device__ __forceinline__ void lj_term(int dx, int dy, int dz, bool wall_atom, const PairConst& c,
+                                        const SimDev& D, float& fx, float& fy, float& fz, float& pe,
+                                        uint32_t& nff, uint32_t& nwf) {
+  // WS: wall-fluid parameters equal the fluid's, so forces need no wall test
+  const bool wall = (WS && !ENERGY) ? false : wall_atom;
   const float ax = UNI ? float(dx) : float(dx) * D.unit_x;
   const float ay = UNI ? float(dy) : float(dy) * D.unit_y;
   const float az = UNI ? float(dz) : float(dz) * D.unit_z;
@@ -688,7 +690,7 @@ __device__ __forceinline__ void lj_term(int dx, int dy, int dz, bool wall, const
 // slot's Verlet list (entries >= ntot are wall atoms), FP32 from fixed-point
 // separations.
 // ---------------------------------------------------------------------------
-template <int MODE, int ENERGY, int UNI>
+template <int MODE, int ENERGY, int UNI, int WS>
 __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimDev* __restrict__ sims,
                                                     const uint16_t* __restrict__ atom_sim,
                                                     const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
@@ -710,7 +712,7 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
     const uint4* grp = reinterpret_cast<const uint4*>(list) + i;  // group g at grp[g * ld]
     const PairConst pc = pair_const<UNI>(K, D);
     auto pair = [&](uint32_t j, const int4& o) {
-      lj_term<ENERGY, UNI>(int(uint32_t(me.x) - uint32_t(o.x)), int(uint32_t(me.y) - uint32_t(o.y)),
+      lj_term<ENERGY, UNI, WS>(int(uint32_t(me.x) - uint32_t(o.x)), int(uint32_t(me.y) - uint32_t(o.y)),
                            int(uint32_t(me.z) - uint32_t(o.z)), j >= uint32_t(ntot), pc, D, fx, fy, fz, pe, nff,
                            nwf);
     };
@@ -761,6 +763,7 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
 // ---------------------------------------------------------------------------
 constexpr int TILE_TPB = 256;
 constexpr int TILE_RUNS = 18;  // kind (fluid, lower wall, upper wall) x 3 slabs x 2 pieces
+
 
 struct TileStage {
   uint32_t gb[TILE_RUNS];       // first entry of each range in the position array
@@ -864,15 +867,12 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     StateRef to, const int* __restrict__ tag_from, int* __restrict__ tag_to, int* __restrict__ overflow,
     const int* __restrict__ flag, StepRef R, float rl2, int global_out) {
   if (!rebuild_needed(flag, R)) return;
-  extern __shared__ int lds_pos[];
+  __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
   __shared__ TileStage T;
   const int t = xcd_block();
   tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
   const uint32_t total = T.off[TILE_RUNS];
-  const bool local = !global_out && total <= uint32_t(stage_cap);
-  int* lx = lds_pos;
-  int* ly = lx + stage_cap;
-  int* lz = ly + stage_cap;
+  const bool local = !global_out && total <= uint32_t(TILE_STAGE);
   if (local) tile_stage(T, pfix, lx, ly, lz);
   if (threadIdx.x == 0) tilemode[t] = local ? 0 : 1;
   if (t == 0 && threadIdx.x == 0) atomicAdd(&overflow[1], 1);  // builds so far
@@ -961,14 +961,14 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
 // Forces of a tile's atoms from their lists, neighbour positions read from
 // LDS (or gathered, for a tile built with 32-bit indices), then the second
 // half-kick and the sample of the step.
-template <int MODE, int ENERGY, int UNI>
+template <int MODE, int ENERGY, int UNI, int WS>
 __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     int ntot, int ld, int stage_cap, const int4* __restrict__ tiles, const uint8_t* __restrict__ tilemode,
     const SimDev* __restrict__ sims, const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
     const uint32_t* __restrict__ ncount, const uint32_t* __restrict__ wstart, const uint32_t* __restrict__ wcount,
     const uint32_t* __restrict__ list, const uint32_t* __restrict__ nlist, float4* __restrict__ f4, StateRef st,
     Acc acc, int64_t* __restrict__ dstate, StepRef R, StepConst K) {
-  extern __shared__ int lds_pos[];
+  __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
   __shared__ TileStage T;
   __shared__ double lds_vx[BIN_LDS];
   __shared__ double lds_cnt[BIN_LDS];
@@ -976,9 +976,6 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
   const int t = xcd_block();
   tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
   const bool local = tilemode[t] == 0;
-  int* lx = lds_pos;
-  int* ly = lx + stage_cap;
-  int* lz = ly + stage_cap;
   if (local) tile_stage(T, pfix, lx, ly, lz);
   const uint32_t first_wall = local ? T.off[6] : uint32_t(ntot);  // walls come after the fluid ranges
   const int s = T.s;
@@ -995,7 +992,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
       const uint4* grp = reinterpret_cast<const uint4*>(list) + i;
       const PairConst pc = pair_const<UNI>(K, D);
       auto pair = [&](uint32_t j, int ox, int oy, int oz) {
-        lj_term<ENERGY, UNI>(int(uint32_t(me.x) - uint32_t(ox)), int(uint32_t(me.y) - uint32_t(oy)),
+        lj_term<ENERGY, UNI, WS>(int(uint32_t(me.x) - uint32_t(ox)), int(uint32_t(me.y) - uint32_t(oy)),
                              int(uint32_t(me.z) - uint32_t(oz)), j >= first_wall, pc, D, fx, fy, fz, pe, nff,
                              nwf);
       };
@@ -1081,33 +1078,23 @@ template __global__ void k_force_cell<0>(int, const SimDev*, const uint16_t*, co
 template __global__ void k_force_cell<1>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
                                          const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
                                          StateRef, Acc, int64_t*, StepRef, StepConst);
-#define HMD_FORCE_TILES(M, E, U)                                                                       \
-  template __global__ void k_force_tiles<M, E, U>(int, int, int, const int4*, const uint8_t*, const SimDev*,     \
-                                               const int4*, const uint32_t*, const uint32_t*, const uint32_t*, \
-                                               const uint32_t*, const uint32_t*, const uint32_t*, float4*,     \
-                                               StateRef, Acc, int64_t*, StepRef, StepConst);
-HMD_FORCE_TILES(0, 0, 0)
-HMD_FORCE_TILES(0, 1, 0)
-HMD_FORCE_TILES(1, 0, 0)
-HMD_FORCE_TILES(1, 1, 0)
-HMD_FORCE_TILES(0, 0, 1)
-HMD_FORCE_TILES(0, 1, 1)
-HMD_FORCE_TILES(1, 0, 1)
-HMD_FORCE_TILES(1, 1, 1)
+#define HMD_FORCE_TILES(M, E, U, W)                                                                    \
+  template __global__ void k_force_tiles<M, E, U, W>(int, int, int, const int4*, const uint8_t*,              \
+                                                     const SimDev*, const int4*, const uint32_t*,              \
+                                                     const uint32_t*, const uint32_t*, const uint32_t*,         \
+                                                     const uint32_t*, const uint32_t*, float4*, StateRef, Acc, \
+                                                     int64_t*, StepRef, StepConst);
+#define HMD_FORCE_LIST(M, E, U, W)                                                                     \
+  template __global__ void k_force_list<M, E, U, W>(int, int, const SimDev*, const uint16_t*, const int4*,    \
+                                                    const uint32_t*, const uint32_t*, float4*, StateRef, Acc,  \
+                                                    int64_t*, StepRef, StepConst);
+#define HMD_FORCE_BOTH(M, E, U, W) HMD_FORCE_TILES(M, E, U, W) HMD_FORCE_LIST(M, E, U, W)
+HMD_FORCE_BOTH(0, 0, 0, 0) HMD_FORCE_BOTH(0, 0, 0, 1) HMD_FORCE_BOTH(0, 0, 1, 0) HMD_FORCE_BOTH(0, 0, 1, 1)
+HMD_FORCE_BOTH(0, 1, 0, 0) HMD_FORCE_BOTH(0, 1, 0, 1) HMD_FORCE_BOTH(0, 1, 1, 0) HMD_FORCE_BOTH(0, 1, 1, 1)
+HMD_FORCE_BOTH(1, 0, 0, 0) HMD_FORCE_BOTH(1, 0, 0, 1) HMD_FORCE_BOTH(1, 0, 1, 0) HMD_FORCE_BOTH(1, 0, 1, 1)
+HMD_FORCE_BOTH(1, 1, 0, 0) HMD_FORCE_BOTH(1, 1, 0, 1) HMD_FORCE_BOTH(1, 1, 1, 0) HMD_FORCE_BOTH(1, 1, 1, 1)
+#undef HMD_FORCE_BOTH
 #undef HMD_FORCE_TILES
-
-#define HMD_FORCE_LIST(M, E, U)                                                                       \
-  template __global__ void k_force_list<M, E, U>(int, int, const SimDev*, const uint16_t*, const int4*,          \
-                                              const uint32_t*, const uint32_t*, float4*, StateRef, Acc,       \
-                                              int64_t*, StepRef, StepConst);
-HMD_FORCE_LIST(0, 0, 0)
-HMD_FORCE_LIST(0, 1, 0)
-HMD_FORCE_LIST(1, 0, 0)
-HMD_FORCE_LIST(1, 1, 0)
-HMD_FORCE_LIST(0, 0, 1)
-HMD_FORCE_LIST(0, 1, 1)
-HMD_FORCE_LIST(1, 0, 1)
-HMD_FORCE_LIST(1, 1, 1)
 #undef HMD_FORCE_LIST
 
 }  // namespace hmd
