@@ -34,7 +34,8 @@ PEAK_FP32 = 157.3
 FLOP_PER_PAIR = 21
 N_EQUIL, N_SAMPLE = 10000, 20000
 PATH_NAMES = {0: "cell list", 1: "pair list", 2: "pair list, LDS-staged tiles"}
-FORCE_KERNELS = {0: "k_force_cell<1>", 1: "k_force_list<1, 0", 2: "k_force_tiles<1, 0"}
+# force kernel of a sampling step on this workload (square box, wall parameters = fluid)
+FORCE_KERNELS = {0: "k_force_cell<1>", 1: "k_force_list<1, 0, 1, 1>", 2: "k_force_tiles<1, 0, 1, 1>"}
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "force_list_batch64_counters.md")
