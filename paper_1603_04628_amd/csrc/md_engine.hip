@@ -104,7 +104,8 @@ void launch_build(hmd_batch* b, hipStream_t s, const int* flag, StepRef R, State
   const int nt = int(b->ntot), tpb = b->tpb, nb = blocks_for(nt, tpb);
   const float rl2 = float((b->P.rc + b->skin) * (b->P.rc + b->skin));
   if (b->path == 2) {
-    hipLaunchKernelGGL(k_build_tiles, dim3(b->ntiles), dim3(TILE_THREADS), 0, s, nt,
+    hipLaunchKernelGGL(b->uniform ? k_build_tiles<1> : k_build_tiles<0>, dim3(b->ntiles), dim3(TILE_THREADS), 0,
+                       s, nt,
                        b->list_ld, b->list_cap, b->stage_cap, b->d_tiles, b->d_sims, b->d_slot_cell, b->d_pfix,
                        b->d_start, b->d_ncount, b->d_wstart, b->d_wcount, b->d_list, b->d_nlist, b->d_tilemode,
                        from, to, tag_from, tag_to, b->d_flag + 2, flag, R, rl2, global_out);

@@ -861,6 +861,7 @@ __device__ __forceinline__ void tile_stage(const TileStage& T, const int4* __res
 // Verlet lists of a tile's atoms (rebuild steps only).  Also completes the
 // reorder (state copy back) for the tile's slots.  global_out writes 32-bit
 // position indices (the layout of k_build_list) for every tile.
+template <int UNI>
 __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     int ntot, int ld, int cap, int stage_cap, const int4* __restrict__ tiles, const SimDev* __restrict__ sims,
     const uint32_t* __restrict__ slot_cell, const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
@@ -887,6 +888,14 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
       tag_to[i] = tag_from[i];
     }
     const int4 me = pfix[i];
+    // squared separation (in fixed-point units squared with UNI)
+    const float rl2u = UNI ? rl2 * D.inv_u2 : rl2;
+    auto sep2 = [&](int ox, int oy, int oz) {
+      const float ax = float(int(uint32_t(me.x) - uint32_t(ox))) * (UNI ? 1.0f : D.unit_x);
+      const float ay = float(int(uint32_t(me.y) - uint32_t(oy))) * (UNI ? 1.0f : D.unit_y);
+      const float az = float(int(uint32_t(me.z) - uint32_t(oz))) * (UNI ? 1.0f : D.unit_z);
+      return ax * ax + ay * ay + az * az;
+    };
     const int r0 = int(slot_cell[i]) - D.c0;  // (z nx + x) ny + y
     const int cy = r0 % D.ny, cx = (r0 / D.ny) % D.nx, cz = r0 / (D.ny * D.nx);
     uint32_t cnt = 0;
@@ -932,21 +941,19 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
                 const uint32_t k = base + m + u;
-                const float3 d = fixed_sep(me, make_int4(lx[k], ly[k], lz[k], 0), D);
-                r2[u] = d.x * d.x + d.y * d.y + d.z * d.z;
+                r2[u] = sep2(lx[k], ly[k], lz[k]);
               }
 #pragma unroll
-              for (int u = 0; u < 4; ++u) put16(r2[u] < rl2 && m + u != self, base + m + u);
+              for (int u = 0; u < 4; ++u) put16(r2[u] < rl2u && m + u != self, base + m + u);
             }
             for (; m < cn; ++m) {
               const uint32_t k = base + m;
-              const float3 d = fixed_sep(me, make_int4(lx[k], ly[k], lz[k], 0), D);
-              put16(d.x * d.x + d.y * d.y + d.z * d.z < rl2 && m != self, k);
+              put16(sep2(lx[k], ly[k], lz[k]) < rl2u && m != self, k);
             }
           } else {
             for (uint32_t m = 0; m < cn; ++m) {
-              const float3 d = fixed_sep(me, pfix[cb + m], D);
-              put32(d.x * d.x + d.y * d.y + d.z * d.z < rl2 && m != self, cb + m);
+              const int4 o = pfix[cb + m];
+              put32(sep2(o.x, o.y, o.z) < rl2u && m != self, cb + m);
             }
           }
         }
@@ -1080,6 +1087,15 @@ template __global__ void k_force_cell<0>(int, const SimDev*, const uint16_t*, co
 template __global__ void k_force_cell<1>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
                                          const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
                                          StateRef, Acc, int64_t*, StepRef, StepConst);
+template __global__ void k_build_tiles<0>(int, int, int, int, const int4*, const SimDev*, const uint32_t*,
+                                          const int4*, const uint32_t*, const uint32_t*, const uint32_t*,
+                                          const uint32_t*, uint32_t*, uint32_t*, uint8_t*, StateRef, StateRef,
+                                          const int*, int*, int*, const int*, StepRef, float, int);
+template __global__ void k_build_tiles<1>(int, int, int, int, const int4*, const SimDev*, const uint32_t*,
+                                          const int4*, const uint32_t*, const uint32_t*, const uint32_t*,
+                                          const uint32_t*, uint32_t*, uint32_t*, uint8_t*, StateRef, StateRef,
+                                          const int*, int*, int*, const int*, StepRef, float, int);
+
 #define HMD_FORCE_TILES(M, E, U, W)                                                                    \
   template __global__ void k_force_tiles<M, E, U, W>(int, int, int, const int4*, const uint8_t*,              \
                                                      const SimDev*, const int4*, const uint32_t*,              \
