@@ -70,8 +70,11 @@ typedef struct {
      * from the cell list whenever an atom has moved skin/2 since the last
      * build; 2: the same lists for workgroups that each own a tile of whole
      * cell columns and read their neighbours' positions from LDS (16-bit
-     * list entries); -1: the library's tuned choice.  cell_w: minimum cell
-     * width (0: rc, or rc + skin for the pair lists). */
+     * list entries); 3: path 2 with every tile on the position-index
+     * fallback that a tile takes when its neighbourhood exceeds the LDS
+     * capacity (for tests; reported as path 2); -1: the library's tuned
+     * choice.  cell_w: minimum cell width (0: rc, or rc + skin for the pair
+     * lists). */
     int force_path;
     double skin, cell_w;
 } hmd_md_params;

@@ -106,6 +106,7 @@ struct hmd_batch {
   int list_cap = 0, list_ld = 0;
   bool uniform = false;   // one fixed-point unit on all axes in every system
   bool walls_same = false;  // wall-fluid LJ parameters equal the fluid's
+  bool force_gather = false;  // tiled path: every tile on the gather fallback
   std::vector<hmd::HostSystem> host;  // geometry (atom arrays released after upload)
   std::vector<int> wall_id;           // wall slot (column order) -> wall id within its system
   std::vector<uint32_t> cell_rank;    // per system, concatenated: row-major cell id -> Morton rank

@@ -108,7 +108,8 @@ void launch_build(hmd_batch* b, hipStream_t s, const int* flag, StepRef R, State
                        s, nt,
                        b->list_ld, b->list_cap, b->stage_cap, b->d_tiles, b->d_sims, b->d_slot_cell, b->d_pfix,
                        b->d_start, b->d_ncount, b->d_wstart, b->d_wcount, b->d_list, b->d_nlist, b->d_tilemode,
-                       from, to, tag_from, tag_to, b->d_flag + 2, flag, R, rl2, global_out);
+                       from, to, tag_from, tag_to, b->d_flag + 2, flag, R, rl2,
+                       global_out || b->force_gather ? 1 : 0);
     return;
   }
   hipLaunchKernelGGL(k_build_list, dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->list_cap, b->d_sims,
@@ -380,6 +381,10 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
       return HMD_EINVAL;
     }
   choose_path(ctx, jobs, n, &b->path, &b->skin, &b->tpb);
+  if (b->path == 3) {  // the tiled path with every tile on its gather fallback
+    b->path = 2;
+    b->force_gather = true;
+  }
   const double wmin = std::max(b->path >= 1 ? b->P.rc + b->skin : b->P.rc, b->P.cell_w);
   b->host.resize(n);
   for (int k = 0; k < n; ++k) {

@@ -37,7 +37,7 @@ void choose_path(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int* path, double*
   *path = 2;  // LDS-staged tiles unless tuned or asked otherwise
   *skin = P.skin > 0.0 ? P.skin : 0.3;
   *tpb = 256;
-  if (P.force_path >= 0 && P.force_path <= 2) {
+  if (P.force_path >= 0 && P.force_path <= 3) {
     *path = P.force_path;
     return;
   }

@@ -20,7 +20,7 @@ SMALL_L = dict(Lx_nom=workloads.BOX_SMALL_LITERAL, Lz_nom=workloads.BOX_SMALL_LI
 SMALL = dict(Lx_nom=workloads.BOX_SMALL, Lz_nom=workloads.BOX_SMALL, n_fluid=2048)
 LARGE = dict(Lx_nom=workloads.BOX_LARGE, Lz_nom=workloads.BOX_LARGE)
 SKIN = 0.3
-PATHS = [0, 1, 2]  # cell lists, pair lists, LDS-staged tiles of pair lists
+PATHS = [0, 1, 2, 3]  # cell lists, pair lists, LDS-staged tiles, tiles on the gather fallback
 
 
 def _pair(h, g, seed, path=1, **params):
@@ -48,7 +48,7 @@ def test_initial_state_is_identical(h, params):
                                             (12.0, SMALL_L, 200)])
 def test_cell_membership_bit_exact(h, params, steps, path):
     ctx, g_sys, o_sys = _pair(h, 0.02, 5, path, **params)
-    assert g_sys.config()["path"] == path
+    assert g_sys.config()["path"] == min(path, 2)
     o_sys.run(steps)
     xo, vo = o_sys.get_state()
     g_sys.set_state(xo, vo)
@@ -63,7 +63,7 @@ def test_cell_membership_bit_exact(h, params, steps, path):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("h,params,steps", [(6.0, SMALL_L, 300), (4.0, SMALL_L, 100), (12.0, SMALL_L, 200),
                                             (15.0, SMALL, 200)])
 def test_pair_lists_match_oracle_neighbour_sets(h, params, steps, path):
