@@ -294,7 +294,7 @@ def main():
                     help="relative uncertainty thresholds of the hybrid runs, comma separated")
     ap.add_argument("--audit-every", type=int, default=1000)
     ap.add_argument("--hybrid-steps", type=int, default=HY_STEPS)
-    ap.add_argument("--refit-every", type=int, default=16, help="ensemble retrains after this many new MD points")
+    ap.add_argument("--refit-every", type=int, default=1, help="ensemble retrains after this many new MD points")
     ap.add_argument("--all-md-steps", type=int, default=1, help="macro steps run all-MD to price the all-MD march")
     ap.add_argument("--hybrid-budget", type=float, default=60.0,
                     help="wall-clock cap (s) of one hybrid run; the speed-up is then taken over the steps done")

@@ -37,7 +37,6 @@ namespace {
 constexpr int ENS_TPB = 256;
 constexpr int CHUNK = 32;
 constexpr int MAXH = 64;
-constexpr int MAXOWN = (MAXH * MAXH + 5 * MAXH + 1 + ENS_TPB - 1) / ENS_TPB;
 
 __host__ __device__ inline int nparams(int H) { return H * H + 5 * H + 1; }
 
@@ -57,12 +56,15 @@ __device__ __forceinline__ Slot decode(int p, int H) {
   return s;
 }
 
-// mode 0: train `iters` Adam steps and write the parameters back;
-// mode 1: write the gradient at the given parameters (no update).
-__global__ __launch_bounds__(ENS_TPB) void k_ens_train(int N, int H, int iters, float lr, const float* __restrict__ Xs,
-                                                       const float* __restrict__ ys, float* __restrict__ params,
-                                                       float* __restrict__ grad_out, float* __restrict__ loss_out,
-                                                       int mode) {
+// Training is split over (chunk of CHUNK points, member) workgroups so that
+// every iteration runs on many CUs: k_ens_chunk computes one chunk's forward
+// and backward pass and its share of the gradient and loss (MSE over all N
+// points: the 2/N and 1/N factors are applied here); k_ens_adam sums the
+// shares of each member and takes one Adam step.
+__global__ __launch_bounds__(ENS_TPB) void k_ens_chunk(int N, int H, const float* __restrict__ Xs,
+                                                       const float* __restrict__ ys,
+                                                       const float* __restrict__ params, float* __restrict__ gpart,
+                                                       float* __restrict__ lpart) {
   extern __shared__ float lds[];
   const int P = H * H + 5 * H + 1;
   // activation rows are padded to H + 1 floats so that lanes walking
@@ -83,122 +85,114 @@ __global__ __launch_bounds__(ENS_TPB) void k_ens_train(int N, int H, int iters, 
   float* W3 = b2 + H;
   float* b3 = W3 + H;
 
-  const int tid = threadIdx.x;
-  float* my = params + size_t(blockIdx.x) * P;
+  const int tid = threadIdx.x, member = blockIdx.y, chunk = blockIdx.x, nchunk = gridDim.x;
+  const float* my = params + size_t(member) * P;
   for (int p = tid; p < P; p += ENS_TPB) th[p] = my[p];
-  float g[MAXOWN], m[MAXOWN], v[MAXOWN];
-  Slot sl[MAXOWN];
-#pragma unroll
-  for (int k = 0; k < MAXOWN; ++k) {
-    g[k] = m[k] = v[k] = 0.f;
-    sl[k] = decode(tid + k * ENS_TPB, H);
-  }
+  const int c0 = chunk * CHUNK, nc = min(CHUNK, N - c0);
+  for (int e = tid; e < 2 * nc; e += ENS_TPB) x[e] = Xs[2 * c0 + e];
   __syncthreads();
   const float invN = 1.0f / float(N);
-  double b1t = 1.0, b2t = 1.0;
-  const int total = mode == 1 ? 1 : iters;
-  float last_loss = 0.f;
-  for (int it = 1; it <= total; ++it) {
-#pragma unroll
-    for (int k = 0; k < MAXOWN; ++k) g[k] = 0.f;
-    float lsum = 0.f;
-    for (int c0 = 0; c0 < N; c0 += CHUNK) {
-      const int nc = min(CHUNK, N - c0);
-      for (int e = tid; e < 2 * nc; e += ENS_TPB) x[e] = Xs[2 * c0 + e];
-      __syncthreads();
-      for (int e = tid; e < nc * H; e += ENS_TPB) {
-        const int s = e / H, o = e % H;
-        h1[s * HP + o] = tanhf(W1[2 * o] * x[2 * s] + W1[2 * o + 1] * x[2 * s + 1] + b1[o]);
-      }
-      __syncthreads();
-      // lanes run over points (same output unit): the W2 row is a broadcast
-      // and the padded activation rows spread over the banks
-      for (int e = tid; e < nc * H; e += ENS_TPB) {
-        const int s = e % nc, o = e / nc;
-        float a = b2[o];
-        const float* w = W2 + o * H;
-        const float* hh = h1 + s * HP;
-        for (int i = 0; i < H; ++i) a += w[i] * hh[i];
-        h2[s * HP + o] = tanhf(a);
-      }
-      __syncthreads();
-      if (tid < nc) {
-        float a = b3[0];
-        const float* hh = h2 + tid * HP;
-        for (int o = 0; o < H; ++o) a += W3[o] * hh[o];
-        const float r = a - ys[c0 + tid];
-        lsum += r * r;
-        dout[tid] = 2.0f * r * invN;
-      }
-      __syncthreads();
-      for (int e = tid; e < nc * H; e += ENS_TPB) {
-        const int s = e / H, o = e % H;
-        const float t = h2[s * HP + o];
-        dz2[s * HP + o] = dout[s] * W3[o] * (1.0f - t * t);
-      }
-      __syncthreads();
-      for (int e = tid; e < nc * H; e += ENS_TPB) {
-        const int s = e / H, i = e % H;
-        float a = 0.f;
-        const float* dz = dz2 + s * HP;
-        for (int o = 0; o < H; ++o) a += dz[o] * W2[o * H + i];
-        const float t = h1[s * HP + i];
-        dz1[s * HP + i] = a * (1.0f - t * t);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < MAXOWN; ++k) {
-        const Slot q = sl[k];
-        float a = 0.f;
-        switch (q.kind) {
-          case 0: for (int s = 0; s < nc; ++s) a += dz1[s * HP + q.o] * x[2 * s + q.i]; break;
-          case 1: for (int s = 0; s < nc; ++s) a += dz1[s * HP + q.o]; break;
-          case 2: for (int s = 0; s < nc; ++s) a += dz2[s * HP + q.o] * h1[s * HP + q.i]; break;
-          case 3: for (int s = 0; s < nc; ++s) a += dz2[s * HP + q.o]; break;
-          case 4: for (int s = 0; s < nc; ++s) a += dout[s] * h2[s * HP + q.o]; break;
-          case 5: for (int s = 0; s < nc; ++s) a += dout[s]; break;
-          default: break;
-        }
-        g[k] += a;
-      }
-      __syncthreads();
+  for (int e = tid; e < nc * H; e += ENS_TPB) {
+    const int s = e / H, o = e % H;
+    h1[s * HP + o] = tanhf(W1[2 * o] * x[2 * s] + W1[2 * o + 1] * x[2 * s + 1] + b1[o]);
+  }
+  __syncthreads();
+  // lanes run over points (same output unit): the W2 row is a broadcast and
+  // the padded activation rows spread over the banks
+  for (int e = tid; e < nc * H; e += ENS_TPB) {
+    const int s = e % nc, o = e / nc;
+    float a = b2[o];
+    const float* w = W2 + o * H;
+    const float* hh = h1 + s * HP;
+    for (int i = 0; i < H; ++i) a += w[i] * hh[i];
+    h2[s * HP + o] = tanhf(a);
+  }
+  __syncthreads();
+  float lsum = 0.f;
+  if (tid < nc) {
+    float a = b3[0];
+    const float* hh = h2 + tid * HP;
+    for (int o = 0; o < H; ++o) a += W3[o] * hh[o];
+    const float r = a - ys[c0 + tid];
+    lsum = r * r;
+    dout[tid] = 2.0f * r * invN;
+  }
+  __syncthreads();
+  for (int e = tid; e < nc * H; e += ENS_TPB) {
+    const int s = e / H, o = e % H;
+    const float t = h2[s * HP + o];
+    dz2[s * HP + o] = dout[s] * W3[o] * (1.0f - t * t);
+  }
+  __syncthreads();
+  for (int e = tid; e < nc * H; e += ENS_TPB) {
+    const int s = e / H, i = e % H;
+    float a = 0.f;
+    const float* dz = dz2 + s * HP;
+    for (int o = 0; o < H; ++o) a += dz[o] * W2[o * H + i];
+    const float t = h1[s * HP + i];
+    dz1[s * HP + i] = a * (1.0f - t * t);
+  }
+  __syncthreads();
+  float* gout = gpart + (size_t(member) * nchunk + chunk) * P;
+  for (int p = tid; p < P; p += ENS_TPB) {
+    const Slot q = decode(p, H);
+    float a = 0.f;
+    switch (q.kind) {
+      case 0: for (int s = 0; s < nc; ++s) a += dz1[s * HP + q.o] * x[2 * s + q.i]; break;
+      case 1: for (int s = 0; s < nc; ++s) a += dz1[s * HP + q.o]; break;
+      case 2: for (int s = 0; s < nc; ++s) a += dz2[s * HP + q.o] * h1[s * HP + q.i]; break;
+      case 3: for (int s = 0; s < nc; ++s) a += dz2[s * HP + q.o]; break;
+      case 4: for (int s = 0; s < nc; ++s) a += dout[s] * h2[s * HP + q.o]; break;
+      case 5: for (int s = 0; s < nc; ++s) a += dout[s]; break;
+      default: break;
     }
-    // loss of this iteration (before its update)
-    red[tid] = lsum;
-    __syncthreads();
-    for (int o = ENS_TPB / 2; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
-    last_loss = red[0] * invN;
-    __syncthreads();
-    if (mode == 1) break;
-    // Adam (Kingma & Ba 2015), beta = (0.9, 0.999), eps = 1e-8
-    b1t *= 0.9;
-    b2t *= 0.999;
-    const float c1 = float(1.0 / (1.0 - b1t)), c2 = float(1.0 / (1.0 - b2t));
-#pragma unroll
-    for (int k = 0; k < MAXOWN; ++k) {
-      const int p = tid + k * ENS_TPB;
-      if (p < P) {
-        m[k] = 0.9f * m[k] + 0.1f * g[k];
-        v[k] = 0.999f * v[k] + 0.001f * g[k] * g[k];
-        th[p] -= lr * (m[k] * c1) / (sqrtf(v[k] * c2) + 1e-8f);
-      }
-    }
+    gout[p] = a;
+  }
+  red[tid] = lsum;
+  __syncthreads();
+  for (int o = ENS_TPB / 2; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  if (mode == 1) {
-#pragma unroll
-    for (int k = 0; k < MAXOWN; ++k) {
-      const int p = tid + k * ENS_TPB;
-      if (p < P) grad_out[size_t(blockIdx.x) * P + p] = g[k];
-    }
-  } else {
-    for (int p = tid; p < P; p += ENS_TPB) my[p] = th[p];
-  }
-  if (tid == 0) loss_out[blockIdx.x] = last_loss;
+  if (tid == 0) lpart[size_t(member) * nchunk + chunk] = red[0] * invN;
 }
+
+// Per member: the gradient summed over chunks, then (unless grad_out is set,
+// which receives the gradient instead) one Adam step (Kingma & Ba 2015,
+// beta = (0.9, 0.999), eps = 1e-8).  Grid: (parameter blocks, members); the
+// step number is *tbase + k + 1.  loss_out receives the loss at the
+// parameters before the step.
+__global__ __launch_bounds__(ENS_TPB) void k_ens_adam(int P, int nchunk, const float* __restrict__ gpart,
+                                                      const float* __restrict__ lpart, float* __restrict__ params,
+                                                      float* __restrict__ mom, float* __restrict__ vel,
+                                                      const int* __restrict__ tbase, int k, float lr,
+                                                      float* __restrict__ loss_out, float* __restrict__ grad_out) {
+  const int member = blockIdx.y, p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) {
+    const float* gm = gpart + size_t(member) * nchunk * P;
+    float g = 0.f;
+    for (int c = 0; c < nchunk; ++c) g += gm[size_t(c) * P + p];
+    if (grad_out) {
+      grad_out[size_t(member) * P + p] = g;
+    } else {
+      const int t = *tbase + k + 1;
+      const float c1 = float(1.0 / (1.0 - pow(0.9, double(t)))), c2 = float(1.0 / (1.0 - pow(0.999, double(t))));
+      float* m = mom + size_t(member) * P;
+      float* v = vel + size_t(member) * P;
+      const float mk = 0.9f * m[p] + 0.1f * g, vk = 0.999f * v[p] + 0.001f * g * g;
+      m[p] = mk;
+      v[p] = vk;
+      params[size_t(member) * P + p] -= lr * (mk * c1) / (sqrtf(vk * c2) + 1e-8f);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    float l = 0.f;
+    for (int c = 0; c < nchunk; ++c) l += lpart[size_t(member) * nchunk + c];
+    loss_out[member] = l;
+  }
+}
+
+__global__ void k_ens_tick(int* tbase, int k) { *tbase += k; }
 
 // Prediction, member by member: one wavefront per (block of PQB queries,
 // member), lane o holding hidden unit o.  The member's W2 sits transposed in
@@ -337,16 +331,55 @@ int run_train(hmd_ens* e, int n, const float* dX, const float* dy, int mode, flo
   hmd_ctx* ctx = e->ctx;
   const hmd_ens_cfg& c = e->cfg;
   const size_t lds = train_lds_bytes(c.hidden);
-  float* dloss = nullptr;
-  HMD_HIP(ctx, hipMalloc(&dloss, sizeof(float) * c.members));
-  hipLaunchKernelGGL(k_ens_train, dim3(c.members), dim3(ENS_TPB), lds, ctx->stream, n, c.hidden, c.iters,
-                     float(c.lr), dX, dy, e->dparams, dgrad, dloss, mode);
-  hipError_t err = hipGetLastError();
-  std::vector<float> loss(c.members);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(loss.data(), dloss, sizeof(float) * c.members, hipMemcpyDeviceToHost, ctx->stream);
-  if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
-  (void)hipFree(dloss);
+  const int nchunk = (n + CHUNK - 1) / CHUNK, P = e->P, M = c.members;
+  float *gpart = nullptr, *lpart = nullptr, *mom = nullptr, *vel = nullptr, *dloss = nullptr;
+  int* tstep = nullptr;
+  hipError_t err = hipMalloc(&gpart, sizeof(float) * size_t(M) * nchunk * P);
+  if (err == hipSuccess) err = hipMalloc(&lpart, sizeof(float) * size_t(M) * nchunk);
+  if (err == hipSuccess) err = hipMalloc(&mom, sizeof(float) * size_t(M) * P);
+  if (err == hipSuccess) err = hipMalloc(&vel, sizeof(float) * size_t(M) * P);
+  if (err == hipSuccess) err = hipMalloc(&dloss, sizeof(float) * M);
+  if (err == hipSuccess) err = hipMalloc(&tstep, sizeof(int) * M);
+  hipStream_t s = ctx->stream;
+  if (err == hipSuccess) err = hipMemsetAsync(mom, 0, sizeof(float) * size_t(M) * P, s);
+  if (err == hipSuccess) err = hipMemsetAsync(vel, 0, sizeof(float) * size_t(M) * P, s);
+  if (err == hipSuccess) err = hipMemsetAsync(tstep, 0, sizeof(int) * M, s);
+  const int iters = mode == 1 ? 1 : c.iters;
+  const dim3 agrid((P + ENS_TPB - 1) / ENS_TPB, M);
+  auto iteration = [&](int k) {
+    hipLaunchKernelGGL(k_ens_chunk, dim3(nchunk, M), dim3(ENS_TPB), lds, s, n, c.hidden, dX, dy, e->dparams,
+                       gpart, lpart);
+    hipLaunchKernelGGL(k_ens_adam, agrid, dim3(ENS_TPB), 0, s, P, nchunk, gpart, lpart, e->dparams, mom, vel,
+                       tstep, k, float(c.lr), dloss, mode == 1 ? dgrad : nullptr);
+  };
+  // iterations in captured blocks of kBlock (a graph replay per block), the
+  // remainder as direct launches; the step counter advances once per block
+  constexpr int kBlock = 100;
+  const int nblock = iters / kBlock;
+  if (err == hipSuccess && nblock > 0) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    err = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+      for (int k = 0; k < kBlock; ++k) iteration(k);
+      hipLaunchKernelGGL(k_ens_tick, dim3(1), dim3(1), 0, s, tstep, kBlock);
+      err = hipStreamEndCapture(s, &g);
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    for (int r = 0; r < nblock && err == hipSuccess; ++r) err = hipGraphLaunch(ge, s);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  for (int k = 0; k < iters - nblock * kBlock && err == hipSuccess; ++k) {
+    iteration(k);
+    err = hipGetLastError();
+  }
+  std::vector<float> loss(M, 0.f);
+  if (err == hipSuccess && iters > 0)
+    err = hipMemcpyAsync(loss.data(), dloss, sizeof(float) * M, hipMemcpyDeviceToHost, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  for (void* p : {(void*)gpart, (void*)lpart, (void*)mom, (void*)vel, (void*)dloss, (void*)tstep})
+    if (p) (void)hipFree(p);
   if (err != hipSuccess) {
     ctx->err = std::string("ens training: ") + hipGetErrorString(err);
     return HMD_EDEVICE;
