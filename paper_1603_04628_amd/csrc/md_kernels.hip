@@ -438,11 +438,23 @@ __global__ __launch_bounds__(256) void k_build_list(int ntot, int ld, int cap, c
 // and the sample of the completed step (flux, temperatures, wall-normal
 // profile).  Temperatures are stored with the Berendsen factor of this step
 // applied: lambda^2 T_c = T_c + a (T0 - T_c), a = dt / tau.
-template <int MODE>
+// Whether step R + 1 is a sampled step (flux, temperatures, profile).
+__device__ __forceinline__ bool sampled_step(const StepRef& R, const StepConst& K) {
+  const int64_t nstep = step_n(R) + 1;
+  const int64_t ns = nstep - K.n_equil - 1;
+  return nstep > K.n_equil && ns >= K.r && (ns - K.r) / K.B < K.nb;
+}
+
+// TB = 1: the caller owns per-system FP32 profile bins in LDS (tbin_vx,
+// tbin_cnt indexed from the system's first bin), cleared before and flushed
+// after all of its atoms, and all of its lanes belong to one system; TB = 0:
+// the bins are gathered here per call.
+template <int MODE, int TB = 0>
 __device__ __forceinline__ void finish_force(int i, bool valid, int s, const SimDev* __restrict__ sims, float fx,
                                              float fy, float fz, float pe, StateRef st, Acc acc,
                                              int64_t* __restrict__ dstate, const StepRef& R, const StepConst& K,
-                                             double* lds_vx, double* lds_cnt, int* lds_base) {
+                                             double* lds_vx, double* lds_cnt, int* lds_base,
+                                             float* tbin_vx = nullptr, float* tbin_cnt = nullptr) {
   const int64_t nstep = step_n(R) + 1;
   const int p = int(nstep & 1);
   double vc2 = 0.0, ke = 0.0, pes = valid ? double(pe) : 0.0;
@@ -465,7 +477,8 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
     double* const acc_vc2 = p ? acc.vc2[1] : acc.vc2[0];
     double* const acc_ke = p ? acc.ke[1] : acc.ke[0];
     double* const acc_pe = p ? acc.pe[1] : acc.pe[0];
-    if (wave_uniform(valid ? s : -1)) {
+    // a tile's atoms all belong to one system (invalid lanes add zero)
+    if (TB || wave_uniform(valid ? s : -1)) {
       vc2 = wave_sum(vc2);
       if (K.energy_on) { ke = wave_sum(ke); pes = wave_sum(pes); }
       const int sw = __shfl(s, 0);
@@ -491,7 +504,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   else if (K.axis == 1) q2 = (1.0 - a) * q2 + a * K.T0;
   else q3 = (1.0 - a) * q3 + a * K.T0;
   if (!valid) q0 = q1 = q2 = q3 = 0.0;
-  if (wave_uniform(valid ? s : -1)) {
+  if (TB || wave_uniform(valid ? s : -1)) {
     q0 = wave_sum(q0); q1 = wave_sum(q1); q2 = wave_sum(q2); q3 = wave_sum(q3);
     const int sw = __shfl(s, 0);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
@@ -516,7 +529,17 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
     int bb = int(floor(st.y[i] * D.inv_bin));
     bb = bb < 0 ? 0 : (bb >= D.nbins ? D.nbins - 1 : bb);
     gb = D.bin0 + bb;
+    if (TB) {
+      if (bb < BIN_LDS) {
+        atomicAdd(&tbin_vx[bb], float(v0));
+        atomicAdd(&tbin_cnt[bb], 1.0f);
+      } else {
+        atomicAdd(&acc.binvx[gb], v0);
+        atomicAdd(&acc.bincnt[gb], 1.0);
+      }
+    }
   }
+  if (TB) return;
   for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) { lds_vx[k] = 0.0; lds_cnt[k] = 0.0; }
   if (threadIdx.x == 0) *lds_base = 0x7fffffff;
   __syncthreads();
@@ -979,11 +1002,13 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     Acc acc, int64_t* __restrict__ dstate, StepRef R, StepConst K) {
   __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
   __shared__ TileStage T;
-  __shared__ double lds_vx[BIN_LDS];
-  __shared__ double lds_cnt[BIN_LDS];
-  __shared__ int lds_base;
+  __shared__ float tbin_vx[BIN_LDS];
+  __shared__ float tbin_cnt[BIN_LDS];
   const int t = xcd_block();
-  tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
+  const bool bins = MODE == 1 && K.bins_on && sampled_step(R, K);
+  if (bins)
+    for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) { tbin_vx[k] = 0.f; tbin_cnt[k] = 0.f; }
+  tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);  // ends with a barrier
   const bool local = tilemode[t] == 0;
   if (local) tile_stage(T, pfix, lx, ly, lz);
   const uint32_t first_wall = local ? T.off[6] : uint32_t(ntot);  // walls come after the fluid ranges
@@ -1058,8 +1083,17 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
         atomicAdd(&acc.pairs[1], w);
       }
     }
-    finish_force<MODE>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, lds_vx, lds_cnt,
-                       &lds_base);
+    finish_force<MODE, 1>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, nullptr, nullptr,
+                          nullptr, tbin_vx, tbin_cnt);
+  }
+  if (bins) {  // one flush of the tile's profile bins
+    __syncthreads();
+    const int nb = min(D.nbins, BIN_LDS);
+    for (int k = threadIdx.x; k < nb; k += blockDim.x)
+      if (tbin_cnt[k] != 0.f) {
+        atomicAdd(&acc.binvx[D.bin0 + k], double(tbin_vx[k]));
+        atomicAdd(&acc.bincnt[D.bin0 + k], double(tbin_cnt[k]));
+      }
   }
 }
 
