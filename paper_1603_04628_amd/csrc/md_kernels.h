@@ -54,6 +54,8 @@ constexpr int TILE_THREADS = 256;  // threads per tile workgroup
 // LDS capacity of a tile in atoms (x, y, z fixed point: 48 KiB); a
 // compile-time size lets every LDS read carry its array offset as an immediate
 constexpr int TILE_STAGE = 4096;
+// cells of a tile's neighbourhood listed in LDS by the list build
+constexpr int TILE_CTAB = 960;
 template <int UNI>
 __global__ void k_build_tiles(int ntot, int ld, int cap, int stage_cap, const int4* tiles, const SimDev* sims,
                               const uint32_t* slot_cell, const int4* pfix, const uint32_t* start,

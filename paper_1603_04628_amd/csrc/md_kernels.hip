@@ -895,6 +895,11 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
   if (!rebuild_needed(flag, R)) return;
   __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
   __shared__ TileStage T;
+  // LDS index of each neighbourhood cell's first atom (<< 8) and its count,
+  // by (slab, column offset, y + 1): the candidate loop then reads no cell
+  // tables from memory
+  __shared__ uint32_t ctab[TILE_CTAB];
+  __shared__ int tab_ok;
   const int t = xcd_block();
   tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
   const uint32_t total = T.off[TILE_RUNS];
@@ -903,6 +908,37 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
   if (threadIdx.x == 0) tilemode[t] = local ? 0 : 1;
   if (t == 0 && threadIdx.x == 0) atomicAdd(&overflow[1], 1);  // builds so far
   const SimDev& D = sims[T.s];
+  const bool whole = T.npieces == 1 && T.pa[0] == 0 && T.pb[0] == D.nx - 1;
+  const int ncolx = whole ? D.nx : T.ncol + 2, nyt = D.ny + 2;
+  bool use_tab = local && 3 * ncolx * nyt <= TILE_CTAB;
+  if (use_tab) {
+    if (threadIdx.x == 0) tab_ok = 1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * ncolx * nyt; e += blockDim.x) {
+      const int si = e / (ncolx * nyt), xi = (e / nyt) % ncolx, jy = e % nyt - 1;
+      int jz = T.z + si - 1;
+      jz += jz < 0 ? D.nz : (jz >= D.nz ? -D.nz : 0);
+      int jx = whole ? xi : T.x0 - 1 + xi;
+      jx += jx < 0 ? D.nx : (jx >= D.nx ? -D.nx : 0);
+      const int piece = (T.npieces == 1 || (jx >= T.pa[0] && jx <= T.pb[0])) ? 0 : 1;
+      const int kind = jy < 0 ? 1 : (jy >= D.ny ? 2 : 0);
+      uint32_t cb, cn;
+      if (kind == 0) {
+        const uint32_t gc = uint32_t(D.c0 + (jz * D.nx + jx) * D.ny + jy);
+        cb = start[gc];
+        cn = ncount[gc];
+      } else {
+        const uint32_t wc = uint32_t(D.wc0 + ((kind - 1) * D.nz + jz) * D.nx + jx);
+        cb = uint32_t(ntot) + wstart[wc];
+        cn = wcount[wc];
+      }
+      const int run = kind * 6 + si * 2 + piece;
+      if (cn > 255u) tab_ok = 0;
+      ctab[e] = ((T.off[run] + (cb - T.gb[run])) << 8) | (cn > 255u ? 255u : cn);
+    }
+    __syncthreads();
+    use_tab = tab_ok != 0;
+  }
   const bool copy = from.x != to.x;  // a rebuild outside the step sequence copies nothing
   for (uint32_t i = T.home0 + threadIdx.x; i < T.home1; i += blockDim.x) {
     if (copy) {
@@ -933,6 +969,36 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
       if (hit && cnt < uint32_t(cap)) list[(size_t(cnt >> 2) * ld + i) * 4 + (cnt & 3u)] = q;
       cnt += hit ? 1u : 0u;
     };
+    if (use_tab) {
+      // own LDS index, for the self test
+      const int xs = whole ? cx : cx - T.x0 + 1;
+      const uint32_t myk = (ctab[(ncolx + xs) * nyt + cy + 1] >> 8) + (i - start[slot_cell[i]]);
+      for (int dz = 0; dz < 3; ++dz)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int jx = cx + dx;
+          if (whole) jx += jx < 0 ? D.nx : (jx >= D.nx ? -D.nx : 0);
+          else jx -= T.x0 - 1;
+          const uint32_t* row = ctab + (dz * ncolx + jx) * nyt + cy;  // y offsets -1, 0, 1 -> row[0..2]
+          for (int dy = 0; dy < 3; ++dy) {
+            const uint32_t w = row[dy], base = w >> 8, cn = w & 255u;
+            uint32_t m = 0;
+            for (; m + 4 <= cn; m += 4) {
+              float r2[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const uint32_t k = base + m + u;
+                r2[u] = sep2(lx[k], ly[k], lz[k]);
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) put16(r2[u] < rl2u && base + m + u != myk, base + m + u);
+            }
+            for (; m < cn; ++m) {
+              const uint32_t k = base + m;
+              put16(sep2(lx[k], ly[k], lz[k]) < rl2u && k != myk, k);
+            }
+          }
+        }
+    } else
     for (int dz = -1; dz <= 1; ++dz) {
       int jz = cz + dz;
       jz += jz < 0 ? D.nz : (jz >= D.nz ? -D.nz : 0);
