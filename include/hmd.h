@@ -151,6 +151,12 @@ int md_batch_pair_count(hmd_batch* b, int64_t* fluid_pairs, int64_t* wall_pairs)
  * happens whenever some atom of the batch has moved more than half the skin
  * since the previous one. */
 int md_batch_list_builds(hmd_batch* b, int64_t* builds);
+/* One system of a batch, for checks at full batch size: its state (atom id
+ * order, n_fluid x 3 each; x and v may be null to ask for n_fluid only) and
+ * the forces at that state (recomputed, FP32, n_fluid x 3) with its
+ * potential energy. */
+int md_batch_get_state(hmd_batch* b, int sim, double* x, double* v, int64_t* n_fluid);
+int md_batch_forces(hmd_batch* b, int sim, float* f, double* pe);
 /* The implementation choices in use: force path (0 cell, 1 pair list),
  * pair-list skin, threads per block, pair-list capacity per atom. */
 int md_batch_config(const hmd_batch* b, int* path, double* skin, int* tpb, int* list_cap);

@@ -86,6 +86,8 @@ _sig("md_batch_set_timing", i32, vp, i32)
 _sig("md_batch_kernel_ms", i32, vp, _c.c_char_p, P(d), P(i64))
 _sig("md_batch_pair_count", i32, vp, P(i64), P(i64))
 _sig("md_batch_list_builds", i32, vp, P(i64))
+_sig("md_batch_get_state", i32, vp, i32, P(d), P(d), P(i64))
+_sig("md_batch_forces", i32, vp, i32, P(_c.c_float), P(d))
 _sig("md_batch_free", None, vp)
 _sig("md_sys_create", i32, vp, d, d, u64, P(vp))
 _sig("md_sys_info", i32, vp, P(i64), P(i64), P(d), P(i32))
@@ -291,6 +293,23 @@ class Batch:
         ff, wf = i64(), i64()
         self.ctx.check(_lib.md_batch_pair_count(self._h, _c.byref(ff), _c.byref(wf)))
         return ff.value, wf.value
+
+    def n_fluid(self, sim: int) -> int:
+        n = i64()
+        self.ctx.check(_lib.md_batch_get_state(self._h, int(sim), None, None, _c.byref(n)))
+        return n.value
+
+    def get_state(self, sim: int):
+        n = self.n_fluid(sim)
+        x, v = np.zeros((n, 3)), np.zeros((n, 3))
+        self.ctx.check(_lib.md_batch_get_state(self._h, int(sim), _ptr(x), _ptr(v), None))
+        return x, v
+
+    def forces(self, sim: int):
+        f = np.zeros((self.n_fluid(sim), 3), dtype=np.float32)
+        pe = d()
+        self.ctx.check(_lib.md_batch_forces(self._h, int(sim), _ptr(f, _c.c_float), _c.byref(pe)))
+        return f, pe.value
 
     def list_builds(self) -> int:
         n = i64()

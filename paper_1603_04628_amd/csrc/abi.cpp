@@ -148,6 +148,18 @@ int md_batch_pair_count(hmd_batch* b, int64_t* fluid_pairs, int64_t* wall_pairs)
   return guarded(b->ctx, [&] { return hmd::batch_pairs(b, fluid_pairs, wall_pairs); });
 }
 
+int md_batch_get_state(hmd_batch* b, int sim, double* x, double* v, int64_t* n_fluid) {
+  if (!b || sim < 0 || sim >= b->S) return HMD_EINVAL;
+  if (n_fluid) *n_fluid = b->sims[sim].nf;
+  if (!x && !v) return HMD_OK;
+  return guarded(b->ctx, [&] { return hmd::batch_get_state(b, sim, x, v); });
+}
+
+int md_batch_forces(hmd_batch* b, int sim, float* f, double* pe) {
+  if (!b || sim < 0 || sim >= b->S) return HMD_EINVAL;
+  return guarded(b->ctx, [&] { return hmd::batch_forces(b, sim, f, pe); });
+}
+
 int md_batch_list_builds(hmd_batch* b, int64_t* builds) {
   if (!b) return HMD_EINVAL;
   return guarded(b->ctx, [&] { return hmd::batch_list_builds(b, builds); });

@@ -260,3 +260,27 @@ def test_autotuner_picks_a_configuration():
     best = table[np.argmin(table[:, 3])]
     cfg = b.config()
     assert cfg["path"] == int(best[0]) and cfg["tpb"] == int(best[2])
+
+
+def test_full_batch_forces_match_oracle():
+    # the 64-channel batch as the benchmark runs it (2,115,470 atoms, default
+    # path and skin, graph chunks of 100): after 300 steps, the forces of the
+    # thinnest, a middle and the thickest system at their device state match
+    # the oracle's from the same positions
+    params = dict(n_equil=10000, **workloads.batch_box())
+    ctx = hmd.Context(hmd.Params(skin=0.35, **params))
+    jobs = workloads.batch_jobs(64)
+    b = hmd.Batch(ctx, [(j.h, j.g, j.seed, 20000) for j in jobs])
+    assert b.atoms == 2115470
+    b.run(300, graph_chunk=100)
+    hs = [j.h for j in jobs]
+    for sim in sorted({int(np.argmin(hs)), 31, int(np.argmax(hs))}):
+        x, v = b.get_state(sim)
+        f, pe = b.forces(sim)
+        j = jobs[sim]
+        o = omd.System(j.h, j.g, j.seed, omd.Params(cell_w=2.5 + 0.35, **params))
+        o.set_state(x, v)
+        fo, peo = o.forces_cells()
+        assert np.all(np.isfinite(f))
+        assert _rel_rms(f, fo) <= 1e-5, sim
+        assert pe == pytest.approx(peo, rel=1e-5)
