@@ -797,6 +797,7 @@ struct TileStage {
   int s, z, x0, ncol;
   uint32_t home0, home1;        // home slots
 };
+static_assert(sizeof(TileStage) == TILE_REC * sizeof(uint32_t), "tile record layout");
 
 // Column pieces of x0 - 1 .. x0 + ncol with periodic wrap (one piece covers
 // the whole row when the range would meet itself).
@@ -868,16 +869,38 @@ __device__ __forceinline__ void tile_ranges(const int4& tile, int ntot, const Si
 }
 
 // Copies the tile's ranges into LDS (structure of arrays; caller checks the
-// capacity first).
+// capacity first).  One flat pass over every staged entry, each thread with
+// four loads in flight: range by range, each short range would cost a whole
+// memory latency of its own.
 __device__ __forceinline__ void tile_stage(const TileStage& T, const int4* __restrict__ pfix, int* lx, int* ly,
                                            int* lz) {
-  for (int r = 0; r < TILE_RUNS; ++r) {  // range by range: contiguous loads, no search
-    const uint32_t o = T.off[r], n = T.off[r + 1] - o, g = T.gb[r];
-    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
-      const int4 p = pfix[g + k];
-      lx[o + k] = p.x; ly[o + k] = p.y; lz[o + k] = p.z;
+  constexpr int U = 4;
+  const uint32_t total = T.off[TILE_RUNS];
+  for (uint32_t e0 = threadIdx.x; e0 < total; e0 += U * blockDim.x) {
+    int4 p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e = e0 + u * blockDim.x;
+      if (e < total) {
+        int r = 0;  // the range holding entry e (empty ranges share their start with the next)
+#pragma unroll
+        for (int q = 1; q < TILE_RUNS; ++q) r += e >= T.off[q] ? 1 : 0;
+        p[u] = pfix[T.gb[r] + (e - T.off[r])];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e = e0 + u * blockDim.x;
+      if (e < total) { lx[e] = p[u].x; ly[e] = p[u].y; lz[e] = p[u].z; }
     }
   }
+  __syncthreads();
+}
+
+// Range table of a tile as the last list build left it (the cell ranges only
+// change when the cells are rebuilt, and every rebuild runs the list build).
+__device__ __forceinline__ void tile_load(const uint32_t* __restrict__ rec, TileStage& T) {
+  if (threadIdx.x < TILE_REC) reinterpret_cast<uint32_t*>(&T)[threadIdx.x] = rec[threadIdx.x];
   __syncthreads();
 }
 
@@ -889,9 +912,10 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     int ntot, int ld, int cap, int stage_cap, const int4* __restrict__ tiles, const SimDev* __restrict__ sims,
     const uint32_t* __restrict__ slot_cell, const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
     const uint32_t* __restrict__ ncount, const uint32_t* __restrict__ wstart, const uint32_t* __restrict__ wcount,
-    uint32_t* __restrict__ list, uint32_t* __restrict__ nlist, uint8_t* __restrict__ tilemode, StateRef from,
-    StateRef to, const int* __restrict__ tag_from, int* __restrict__ tag_to, int* __restrict__ overflow,
-    const int* __restrict__ flag, StepRef R, float rl2, int global_out) {
+    uint32_t* __restrict__ list, uint32_t* __restrict__ nlist, uint8_t* __restrict__ tilemode,
+    uint32_t* __restrict__ tilerec, StateRef from, StateRef to, const int* __restrict__ tag_from,
+    int* __restrict__ tag_to, int* __restrict__ overflow, const int* __restrict__ flag, StepRef R, float rl2,
+    int global_out) {
   if (!rebuild_needed(flag, R)) return;
   __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
   __shared__ TileStage T;
@@ -902,6 +926,8 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
   __shared__ int tab_ok;
   const int t = xcd_block();
   tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
+  if (threadIdx.x < TILE_REC)  // for the force kernels until the next rebuild
+    tilerec[size_t(t) * TILE_REC + threadIdx.x] = reinterpret_cast<const uint32_t*>(&T)[threadIdx.x];
   const uint32_t total = T.off[TILE_RUNS];
   const bool local = !global_out && total <= uint32_t(TILE_STAGE);
   if (local) tile_stage(T, pfix, lx, ly, lz);
@@ -1061,11 +1087,10 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
 // half-kick and the sample of the step.
 template <int MODE, int ENERGY, int UNI, int WS>
 __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
-    int ntot, int ld, int stage_cap, const int4* __restrict__ tiles, const uint8_t* __restrict__ tilemode,
-    const SimDev* __restrict__ sims, const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
-    const uint32_t* __restrict__ ncount, const uint32_t* __restrict__ wstart, const uint32_t* __restrict__ wcount,
-    const uint32_t* __restrict__ list, const uint32_t* __restrict__ nlist, float4* __restrict__ f4, StateRef st,
-    Acc acc, int64_t* __restrict__ dstate, StepRef R, StepConst K) {
+    int ntot, int ld, int stage_cap, const uint32_t* __restrict__ tilerec, const uint8_t* __restrict__ tilemode,
+    const SimDev* __restrict__ sims, const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ nlist, float4* __restrict__ f4, StateRef st, Acc acc,
+    int64_t* __restrict__ dstate, StepRef R, StepConst K) {
   __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
   __shared__ TileStage T;
   __shared__ float tbin_vx[BIN_LDS];
@@ -1074,21 +1099,38 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
   const bool bins = MODE == 1 && K.bins_on && sampled_step(R, K);
   if (bins)
     for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) { tbin_vx[k] = 0.f; tbin_cnt[k] = 0.f; }
-  tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);  // ends with a barrier
   const bool local = tilemode[t] == 0;
+  tile_load(tilerec + size_t(t) * TILE_REC, T);  // ends with a barrier
+  const uint32_t n_home = T.home1 - T.home0;
+  // a pass's own positions, list lengths and first list groups are requested
+  // one step ahead: the first pass's during the staging, the next pass's
+  // during this one's arithmetic
+  int4 me_nx = make_int4(0, 0, 0, 0);
+  uint32_t n_nx = 0;
+  uint4 g_nx = make_uint4(0u, 0u, 0u, 0u);
+  auto fetch = [&](uint32_t base) {
+    const uint32_t i = T.home0 + base + threadIdx.x;
+    if (base + threadIdx.x < n_home) {
+      me_nx = pfix[i];
+      n_nx = nlist[i];
+      g_nx = reinterpret_cast<const uint4*>(list)[i];
+    }
+  };
+  fetch(0);
   if (local) tile_stage(T, pfix, lx, ly, lz);
   const uint32_t first_wall = local ? T.off[6] : uint32_t(ntot);  // walls come after the fluid ranges
   const int s = T.s;
   const SimDev& D = sims[s];
-  const uint32_t n_home = T.home1 - T.home0;
   for (uint32_t base = 0; base < n_home; base += blockDim.x) {
     const uint32_t i = T.home0 + base + threadIdx.x;
     const bool valid = base + threadIdx.x < n_home;
+    const int4 me = me_nx;
+    const uint32_t n = n_nx;
+    const uint4 g0 = g_nx;
+    if (base + blockDim.x < n_home) fetch(base + blockDim.x);
     float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
     uint32_t nff = 0, nwf = 0;
     if (valid) {
-      const int4 me = pfix[i];
-      const uint32_t n = nlist[i];
       const uint4* grp = reinterpret_cast<const uint4*>(list) + i;
       const PairConst pc = pair_const<UNI>(K, D);
       auto pair = [&](uint32_t j, int ox, int oy, int oz) {
@@ -1100,7 +1142,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
         // eight 16-bit LDS indices per 16-byte group; the next group is
         // requested before this one's arithmetic
         const uint32_t full = n >> 3, rest = n & 7u, ngrp = (n + 7u) >> 3;
-        uint4 jj = ngrp ? grp[0] : make_uint4(0u, 0u, 0u, 0u);
+        uint4 jj = g0;
         auto two = [&](uint32_t w) {
           const uint32_t k0 = w & 0xffffu, k1 = w >> 16;
           pair(k0, lx[k0], ly[k0], lz[k0]);
@@ -1189,19 +1231,18 @@ template __global__ void k_force_cell<1>(int, const SimDev*, const uint16_t*, co
                                          StateRef, Acc, int64_t*, StepRef, StepConst);
 template __global__ void k_build_tiles<0>(int, int, int, int, const int4*, const SimDev*, const uint32_t*,
                                           const int4*, const uint32_t*, const uint32_t*, const uint32_t*,
-                                          const uint32_t*, uint32_t*, uint32_t*, uint8_t*, StateRef, StateRef,
-                                          const int*, int*, int*, const int*, StepRef, float, int);
+                                          const uint32_t*, uint32_t*, uint32_t*, uint8_t*, uint32_t*, StateRef,
+                                          StateRef, const int*, int*, int*, const int*, StepRef, float, int);
 template __global__ void k_build_tiles<1>(int, int, int, int, const int4*, const SimDev*, const uint32_t*,
                                           const int4*, const uint32_t*, const uint32_t*, const uint32_t*,
-                                          const uint32_t*, uint32_t*, uint32_t*, uint8_t*, StateRef, StateRef,
-                                          const int*, int*, int*, const int*, StepRef, float, int);
+                                          const uint32_t*, uint32_t*, uint32_t*, uint8_t*, uint32_t*, StateRef,
+                                          StateRef, const int*, int*, int*, const int*, StepRef, float, int);
 
 #define HMD_FORCE_TILES(M, E, U, W)                                                                    \
-  template __global__ void k_force_tiles<M, E, U, W>(int, int, int, const int4*, const uint8_t*,              \
+  template __global__ void k_force_tiles<M, E, U, W>(int, int, int, const uint32_t*, const uint8_t*,          \
                                                      const SimDev*, const int4*, const uint32_t*,              \
-                                                     const uint32_t*, const uint32_t*, const uint32_t*,         \
-                                                     const uint32_t*, const uint32_t*, float4*, StateRef, Acc, \
-                                                     int64_t*, StepRef, StepConst);
+                                                     const uint32_t*, float4*, StateRef, Acc, int64_t*,        \
+                                                     StepRef, StepConst);
 #define HMD_FORCE_LIST(M, E, U, W)                                                                     \
   template __global__ void k_force_list<M, E, U, W>(int, int, const SimDev*, const uint16_t*, const int4*,    \
                                                     const uint32_t*, const uint32_t*, float4*, StateRef, Acc,  \
