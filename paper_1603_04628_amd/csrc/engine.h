@@ -127,8 +127,7 @@ struct hmd_batch {
   uint32_t* d_slot_cell = nullptr;  // pair path: cell of each slot at the last build
   uint32_t* d_list = nullptr;       // pair path: list_cap x list_ld entries
   int4* d_tiles = nullptr;          // tiled path: (system, z slab, first column, columns) per workgroup
-  uint8_t* d_tilemode = nullptr;    // tiled path: 0 LDS indices, 1 position indices (LDS too small)
-  uint32_t* d_tilerec = nullptr;    // tiled path: range table per tile, written by each list build
+  uint32_t* d_tilerec = nullptr;    // tiled path: range table and list mode per tile, written by each list build
   int ntiles = 0, stage_cap = 0;    // tiles; LDS capacity in atoms
   uint32_t* d_nlist = nullptr;
   int* d_flag = nullptr;            // [2] rebuild flags by step parity, list overflow, builds so far

@@ -439,8 +439,7 @@ __global__ __launch_bounds__(256) void k_build_list(int ntot, int ld, int cap, c
 // profile).  Temperatures are stored with the Berendsen factor of this step
 // applied: lambda^2 T_c = T_c + a (T0 - T_c), a = dt / tau.
 // Whether step R + 1 is a sampled step (flux, temperatures, profile).
-__device__ __forceinline__ bool sampled_step(const StepRef& R, const StepConst& K) {
-  const int64_t nstep = step_n(R) + 1;
+__device__ __forceinline__ bool sampled_step(int64_t nstep, const StepConst& K) {
   const int64_t ns = nstep - K.n_equil - 1;
   return nstep > K.n_equil && ns >= K.r && (ns - K.r) / K.B < K.nb;
 }
@@ -452,10 +451,10 @@ __device__ __forceinline__ bool sampled_step(const StepRef& R, const StepConst& 
 template <int MODE, int TB = 0>
 __device__ __forceinline__ void finish_force(int i, bool valid, int s, const SimDev* __restrict__ sims, float fx,
                                              float fy, float fz, float pe, StateRef st, Acc acc,
-                                             int64_t* __restrict__ dstate, const StepRef& R, const StepConst& K,
+                                             int64_t* __restrict__ dstate, int64_t nstep, const StepConst& K,
                                              double* lds_vx, double* lds_cnt, int* lds_base,
-                                             float* tbin_vx = nullptr, float* tbin_cnt = nullptr) {
-  const int64_t nstep = step_n(R) + 1;
+                                             float* tbin_vx = nullptr, float* tbin_cnt = nullptr,
+                                             const double3* vpre = nullptr) {
   const int p = int(nstep & 1);
   double vc2 = 0.0, ke = 0.0, pes = valid ? double(pe) : 0.0;
   // scalars, not an array indexed by the run-time axis (that would live in
@@ -463,9 +462,9 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
   if (MODE == 1 && valid) {
     const SimDev& D = sims[s];
-    v0 = st.vx[i] + K.hdt * (double(fx) + D.g);
-    v1 = st.vy[i] + K.hdt * double(fy);
-    v2 = st.vz[i] + K.hdt * double(fz);
+    v0 = (vpre ? vpre->x : st.vx[i]) + K.hdt * (double(fx) + D.g);
+    v1 = (vpre ? vpre->y : st.vy[i]) + K.hdt * double(fy);
+    v2 = (vpre ? vpre->z : st.vz[i]) + K.hdt * double(fz);
     st.vx[i] = v0; st.vy[i] = v1; st.vz[i] = v2;
     const double vc = K.axis == 0 ? v0 : (K.axis == 1 ? v1 : v2);
     vc2 = vc * vc;
@@ -481,7 +480,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
     if (TB || wave_uniform(valid ? s : -1)) {
       vc2 = wave_sum(vc2);
       if (K.energy_on) { ke = wave_sum(ke); pes = wave_sum(pes); }
-      const int sw = __shfl(s, 0);
+      const int sw = TB ? s : __shfl(s, 0);  // tiles: s is uniform already
       if ((threadIdx.x & (WAVE - 1)) == 0) {
         if (MODE == 1) atomicAdd(&acc_vc2[sw], vc2);
         if (K.energy_on) { atomicAdd(&acc_ke[sw], ke); atomicAdd(&acc_pe[sw], pes); }
@@ -506,7 +505,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   if (!valid) q0 = q1 = q2 = q3 = 0.0;
   if (TB || wave_uniform(valid ? s : -1)) {
     q0 = wave_sum(q0); q1 = wave_sum(q1); q2 = wave_sum(q2); q3 = wave_sum(q3);
-    const int sw = __shfl(s, 0);
+    const int sw = TB ? s : __shfl(s, 0);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
       const SimDev& Dw = sims[sw];
       atomicAdd(&acc.blocks[int64_t(sw) * K.nb + b], q0 * Dw.inv_area);
@@ -657,7 +656,8 @@ __global__ __launch_bounds__(256) void k_force_cell(int ntot, const SimDev* __re
       atomicAdd(&acc.pairs[1], w);
     }
   }
-  finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, lds_vx, lds_cnt, &lds_base);
+  finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, step_n(R) + 1, K, lds_vx, lds_cnt,
+                     &lds_base);
 }
 
 // Shifted LJ (Eq. LJ) for one list entry from a fixed-point separation,
@@ -771,7 +771,8 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
       atomicAdd(&acc.pairs[1], w);
     }
   }
-  finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, lds_vx, lds_cnt, &lds_base);
+  finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, step_n(R) + 1, K, lds_vx, lds_cnt,
+                     &lds_base);
 }
 
 // ---------------------------------------------------------------------------
@@ -796,6 +797,7 @@ struct TileStage {
   int pa[2], pb[2], npieces;    // column pieces of the x range
   int s, z, x0, ncol;
   uint32_t home0, home1;        // home slots
+  uint32_t mode;                // 0: lists of LDS indices; 1: of position indices (LDS too small)
 };
 static_assert(sizeof(TileStage) == TILE_REC * sizeof(uint32_t), "tile record layout");
 
@@ -912,8 +914,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     int ntot, int ld, int cap, int stage_cap, const int4* __restrict__ tiles, const SimDev* __restrict__ sims,
     const uint32_t* __restrict__ slot_cell, const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
     const uint32_t* __restrict__ ncount, const uint32_t* __restrict__ wstart, const uint32_t* __restrict__ wcount,
-    uint32_t* __restrict__ list, uint32_t* __restrict__ nlist, uint8_t* __restrict__ tilemode,
-    uint32_t* __restrict__ tilerec, StateRef from, StateRef to, const int* __restrict__ tag_from,
+    uint32_t* __restrict__ list, uint32_t* __restrict__ nlist, uint32_t* __restrict__ tilerec, StateRef from, StateRef to, const int* __restrict__ tag_from,
     int* __restrict__ tag_to, int* __restrict__ overflow, const int* __restrict__ flag, StepRef R, float rl2,
     int global_out) {
   if (!rebuild_needed(flag, R)) return;
@@ -926,12 +927,12 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
   __shared__ int tab_ok;
   const int t = xcd_block();
   tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
-  if (threadIdx.x < TILE_REC)  // for the force kernels until the next rebuild
-    tilerec[size_t(t) * TILE_REC + threadIdx.x] = reinterpret_cast<const uint32_t*>(&T)[threadIdx.x];
   const uint32_t total = T.off[TILE_RUNS];
   const bool local = !global_out && total <= uint32_t(TILE_STAGE);
+  if (threadIdx.x < TILE_REC)  // range table and mode, for the force kernels until the next rebuild
+    tilerec[size_t(t) * TILE_REC + threadIdx.x] =
+        threadIdx.x == TILE_REC - 1 ? (local ? 0u : 1u) : reinterpret_cast<const uint32_t*>(&T)[threadIdx.x];
   if (local) tile_stage(T, pfix, lx, ly, lz);
-  if (threadIdx.x == 0) tilemode[t] = local ? 0 : 1;
   if (t == 0 && threadIdx.x == 0) atomicAdd(&overflow[1], 1);  // builds so far
   const SimDev& D = sims[T.s];
   const bool whole = T.npieces == 1 && T.pa[0] == 0 && T.pb[0] == D.nx - 1;
@@ -1087,8 +1088,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
 // half-kick and the sample of the step.
 template <int MODE, int ENERGY, int UNI, int WS>
 __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
-    int ntot, int ld, int stage_cap, const uint32_t* __restrict__ tilerec, const uint8_t* __restrict__ tilemode,
-    const SimDev* __restrict__ sims, const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
+    int ntot, int ld, int stage_cap, const uint32_t* __restrict__ tilerec, const SimDev* __restrict__ sims, const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
     const uint32_t* __restrict__ nlist, float4* __restrict__ f4, StateRef st, Acc acc,
     int64_t* __restrict__ dstate, StepRef R, StepConst K) {
   __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
@@ -1096,37 +1096,41 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
   __shared__ float tbin_vx[BIN_LDS];
   __shared__ float tbin_cnt[BIN_LDS];
   const int t = xcd_block();
-  const bool bins = MODE == 1 && K.bins_on && sampled_step(R, K);
+  const int64_t nstep = step_n(R) + 1;  // the step this launch completes
+  const bool bins = MODE == 1 && K.bins_on && sampled_step(nstep, K);
   if (bins)
     for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) { tbin_vx[k] = 0.f; tbin_cnt[k] = 0.f; }
-  const bool local = tilemode[t] == 0;
   tile_load(tilerec + size_t(t) * TILE_REC, T);  // ends with a barrier
+  const bool local = T.mode == 0;
+  const int s = __builtin_amdgcn_readfirstlane(T.s);  // one system per tile
+  const SimDev& D = sims[s];
   const uint32_t n_home = T.home1 - T.home0;
-  // a pass's own positions, list lengths and first list groups are requested
-  // one step ahead: the first pass's during the staging, the next pass's
-  // during this one's arithmetic
+  // a pass's own positions, velocities, list lengths and first list groups
+  // are requested one step ahead: the first pass's during the staging, the
+  // next pass's during this one's arithmetic
   int4 me_nx = make_int4(0, 0, 0, 0);
   uint32_t n_nx = 0;
   uint4 g_nx = make_uint4(0u, 0u, 0u, 0u);
+  double3 v_nx = make_double3(0.0, 0.0, 0.0);
   auto fetch = [&](uint32_t base) {
     const uint32_t i = T.home0 + base + threadIdx.x;
     if (base + threadIdx.x < n_home) {
       me_nx = pfix[i];
       n_nx = nlist[i];
       g_nx = reinterpret_cast<const uint4*>(list)[i];
+      if (MODE == 1) v_nx = make_double3(st.vx[i], st.vy[i], st.vz[i]);
     }
   };
   fetch(0);
   if (local) tile_stage(T, pfix, lx, ly, lz);
   const uint32_t first_wall = local ? T.off[6] : uint32_t(ntot);  // walls come after the fluid ranges
-  const int s = T.s;
-  const SimDev& D = sims[s];
   for (uint32_t base = 0; base < n_home; base += blockDim.x) {
     const uint32_t i = T.home0 + base + threadIdx.x;
     const bool valid = base + threadIdx.x < n_home;
     const int4 me = me_nx;
     const uint32_t n = n_nx;
     const uint4 g0 = g_nx;
+    const double3 v = v_nx;
     if (base + blockDim.x < n_home) fetch(base + blockDim.x);
     float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
     uint32_t nff = 0, nwf = 0;
@@ -1191,8 +1195,8 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
         atomicAdd(&acc.pairs[1], w);
       }
     }
-    finish_force<MODE, 1>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, R, K, nullptr, nullptr,
-                          nullptr, tbin_vx, tbin_cnt);
+    finish_force<MODE, 1>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, nstep, K, nullptr, nullptr,
+                          nullptr, tbin_vx, tbin_cnt, &v);
   }
   if (bins) {  // one flush of the tile's profile bins
     __syncthreads();
@@ -1231,16 +1235,16 @@ template __global__ void k_force_cell<1>(int, const SimDev*, const uint16_t*, co
                                          StateRef, Acc, int64_t*, StepRef, StepConst);
 template __global__ void k_build_tiles<0>(int, int, int, int, const int4*, const SimDev*, const uint32_t*,
                                           const int4*, const uint32_t*, const uint32_t*, const uint32_t*,
-                                          const uint32_t*, uint32_t*, uint32_t*, uint8_t*, uint32_t*, StateRef,
-                                          StateRef, const int*, int*, int*, const int*, StepRef, float, int);
+                                          const uint32_t*, uint32_t*, uint32_t*, uint32_t*, StateRef, StateRef,
+                                          const int*, int*, int*, const int*, StepRef, float, int);
 template __global__ void k_build_tiles<1>(int, int, int, int, const int4*, const SimDev*, const uint32_t*,
                                           const int4*, const uint32_t*, const uint32_t*, const uint32_t*,
-                                          const uint32_t*, uint32_t*, uint32_t*, uint8_t*, uint32_t*, StateRef,
-                                          StateRef, const int*, int*, int*, const int*, StepRef, float, int);
+                                          const uint32_t*, uint32_t*, uint32_t*, uint32_t*, StateRef, StateRef,
+                                          const int*, int*, int*, const int*, StepRef, float, int);
 
 #define HMD_FORCE_TILES(M, E, U, W)                                                                    \
-  template __global__ void k_force_tiles<M, E, U, W>(int, int, int, const uint32_t*, const uint8_t*,          \
-                                                     const SimDev*, const int4*, const uint32_t*,              \
+  template __global__ void k_force_tiles<M, E, U, W>(int, int, int, const uint32_t*, const SimDev*,           \
+                                                     const int4*, const uint32_t*,                             \
                                                      const uint32_t*, float4*, StateRef, Acc, int64_t*,        \
                                                      StepRef, StepConst);
 #define HMD_FORCE_LIST(M, E, U, W)                                                                     \
