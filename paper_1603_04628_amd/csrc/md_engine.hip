@@ -337,7 +337,7 @@ int make_tiles(hmd_batch* b) {
     for (int nc = 1; nc <= D.nx; ++nc) {
       const double atoms = nc * per_col;
       const double staged = 3.0 * std::min(nc + 2, D.nx) * (per_col + 2.0 * wall_col);
-      if (staged > 0.75 * kStageCap && nc > 1) break;
+      if (staged > 0.9 * kStageCap && nc > 1) break;
       const double passes = std::ceil(atoms / TILE_THREADS);
       const double use = atoms / (passes * TILE_THREADS);
       if (use > best_use + 0.02) {

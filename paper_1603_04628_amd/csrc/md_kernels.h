@@ -51,11 +51,12 @@ __global__ void k_force_list(int ntot, int ld, const SimDev* sims, const uint16_
                              const uint32_t* list, const uint32_t* nlist, float4* f4, StateRef st, Acc acc,
                              int64_t* dstate, StepRef R, StepConst K);
 constexpr int TILE_THREADS = 256;  // threads per tile workgroup
-// LDS capacity of a tile in atoms (x, y, z fixed point: 48 KiB); a
+// LDS capacity of a tile in atoms (x, y, z fixed point: 36 KiB, so four
+// workgroups share a compute unit's 160 KiB); a
 // compile-time size lets every LDS read carry its array offset as an immediate
-constexpr int TILE_STAGE = 4096;
+constexpr int TILE_STAGE = 3072;
 // cells of a tile's neighbourhood listed in LDS by the list build
-constexpr int TILE_CTAB = 960;
+constexpr int TILE_CTAB = 768;
 // 32-bit words of a tile's range table, kept in memory from one list build
 // to the next
 constexpr int TILE_REC = 49;
