@@ -985,21 +985,44 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     const int r0 = int(slot_cell[i]) - D.c0;  // (z nx + x) ny + y
     const int cy = r0 % D.ny, cx = (r0 / D.ny) % D.nx, cz = r0 / (D.ny * D.nx);
     uint32_t cnt = 0;
-    uint16_t* list16 = reinterpret_cast<uint16_t*>(list);
     // entry c of slot i: 16-bit at ((c / 8) ld + i) 8 + c % 8 (LDS index),
-    // 32-bit at ((c / 4) ld + i) 4 + c % 4 (position index)
+    // 32-bit at ((c / 4) ld + i) 4 + c % 4 (position index).  The 16-bit
+    // store takes a 32-bit byte offset (the list is below 4 GiB) and a count
+    // clamped to the capacity (an overflowing list is reported below and
+    // never used), so a hit costs no 64-bit arithmetic and no capacity test.
+    char* const list_b = reinterpret_cast<char*>(list);
+    const uint32_t capm1 = uint32_t(cap) - 1u;
     auto put16 = [&](bool hit, uint32_t k) {
-      if (hit && cnt < uint32_t(cap)) list16[(size_t(cnt >> 3) * ld + i) * 8 + (cnt & 7u)] = uint16_t(k);
+      if (hit) {
+        const uint32_t c = min(cnt, capm1);
+        const uint32_t off = ((__umul24(c >> 3, uint32_t(ld)) + i) << 4) + ((c & 7u) << 1);
+        *reinterpret_cast<uint16_t*>(list_b + off) = uint16_t(k);
+      }
       cnt += hit ? 1u : 0u;
     };
     auto put32 = [&](bool hit, uint32_t q) {
       if (hit && cnt < uint32_t(cap)) list[(size_t(cnt >> 2) * ld + i) * 4 + (cnt & 3u)] = q;
       cnt += hit ? 1u : 0u;
     };
+    // candidates k in [a, b) of the LDS arrays, four LDS reads in flight
+    auto screen = [&](uint32_t a, uint32_t b, uint32_t myk) {
+      uint32_t k = a;
+      for (; k + 4 <= b; k += 4) {
+        float r2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r2[u] = sep2(lx[k + u], ly[k + u], lz[k + u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) put16(r2[u] < rl2u && k + u != myk, k + u);
+      }
+      for (; k < b; ++k) put16(sep2(lx[k], ly[k], lz[k]) < rl2u && k != myk, k);
+    };
     if (use_tab) {
       // own LDS index, for the self test
       const int xs = whole ? cx : cx - T.x0 + 1;
       const uint32_t myk = (ctab[(ncolx + xs) * nyt + cy + 1] >> 8) + (i - start[slot_cell[i]]);
+      // cell by cell: the lanes of a wave sit in neighbouring cells, so their
+      // k-th neighbour cells (a wall column for the first and last fluid
+      // cells) are screened side by side
       for (int dz = 0; dz < 3; ++dz)
         for (int dx = -1; dx <= 1; ++dx) {
           int jx = cx + dx;
@@ -1007,22 +1030,8 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
           else jx -= T.x0 - 1;
           const uint32_t* row = ctab + (dz * ncolx + jx) * nyt + cy;  // y offsets -1, 0, 1 -> row[0..2]
           for (int dy = 0; dy < 3; ++dy) {
-            const uint32_t w = row[dy], base = w >> 8, cn = w & 255u;
-            uint32_t m = 0;
-            for (; m + 4 <= cn; m += 4) {
-              float r2[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const uint32_t k = base + m + u;
-                r2[u] = sep2(lx[k], ly[k], lz[k]);
-              }
-#pragma unroll
-              for (int u = 0; u < 4; ++u) put16(r2[u] < rl2u && base + m + u != myk, base + m + u);
-            }
-            for (; m < cn; ++m) {
-              const uint32_t k = base + m;
-              put16(sep2(lx[k], ly[k], lz[k]) < rl2u && k != myk, k);
-            }
+            const uint32_t w = row[dy];
+            screen(w >> 8, (w >> 8) + (w & 255u), myk);
           }
         }
     } else
