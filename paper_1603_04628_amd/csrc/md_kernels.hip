@@ -899,6 +899,39 @@ __device__ __forceinline__ void tile_stage(const TileStage& T, const int4* __res
   __syncthreads();
 }
 
+// The same copy as FP32 offsets from a tile origin o (fixed-point units
+// scaled by sc per axis), for the list build's screening: |offset| stays
+// below half an extent, so the 32-bit difference is the unwrapped offset,
+// and its FP32 rounding (2^-24 relative) is far below the screening margin.
+__device__ __forceinline__ void tile_stage_rel(const TileStage& T, const int4* __restrict__ pfix, int* lx, int* ly,
+                                               int* lz, const int4& o, const float3& sc) {
+  constexpr int U = 4;
+  const uint32_t total = T.off[TILE_RUNS];
+  for (uint32_t e0 = threadIdx.x; e0 < total; e0 += U * blockDim.x) {
+    int4 p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e = e0 + u * blockDim.x;
+      if (e < total) {
+        int r = 0;
+#pragma unroll
+        for (int q = 1; q < TILE_RUNS; ++q) r += e >= T.off[q] ? 1 : 0;
+        p[u] = pfix[T.gb[r] + (e - T.off[r])];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e = e0 + u * blockDim.x;
+      if (e < total) {
+        lx[e] = __float_as_int(float(int(uint32_t(p[u].x) - uint32_t(o.x))) * sc.x);
+        ly[e] = __float_as_int(float(int(uint32_t(p[u].y) - uint32_t(o.y))) * sc.y);
+        lz[e] = __float_as_int(float(int(uint32_t(p[u].z) - uint32_t(o.z))) * sc.z);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Range table of a tile as the last list build left it (the cell ranges only
 // change when the cells are rebuilt, and every rebuild runs the list build).
 __device__ __forceinline__ void tile_load(const uint32_t* __restrict__ rec, TileStage& T) {
@@ -932,12 +965,28 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
   if (threadIdx.x < TILE_REC)  // range table and mode, for the force kernels until the next rebuild
     tilerec[size_t(t) * TILE_REC + threadIdx.x] =
         threadIdx.x == TILE_REC - 1 ? (local ? 0u : 1u) : reinterpret_cast<const uint32_t*>(&T)[threadIdx.x];
-  if (local) tile_stage(T, pfix, lx, ly, lz);
   if (t == 0 && threadIdx.x == 0) atomicAdd(&overflow[1], 1);  // builds so far
   const SimDev& D = sims[T.s];
   const bool whole = T.npieces == 1 && T.pa[0] == 0 && T.pb[0] == D.nx - 1;
   const int ncolx = whole ? D.nx : T.ncol + 2, nyt = D.ny + 2;
   bool use_tab = local && 3 * ncolx * nyt <= TILE_CTAB;
+  // Screening in FP32 offsets from the centre of the tile's neighbourhood
+  // (no integer conversion per candidate) where that neighbourhood spans
+  // less than an extent in x and z, so that no offset wraps.  Margin: offsets
+  // stay below 2^31 units, so each is within 2^7 units of exact and r^2 within
+  // ~1e-6 relative of exact; screening at (1 + 1e-5) r_l^2 keeps every pair
+  // inside r_l (the surplus pairs beyond r_l add nothing to the forces).
+  const bool flt = use_tab && !whole && D.nz >= 4;
+  int4 org = make_int4(0, 0, 0, 0);
+  float3 sc = make_float3(1.0f, 1.0f, 1.0f);
+  if (flt) {
+    const double xc = (double(T.x0 - 1) + 0.5 * double(T.ncol + 2)) * D.wx, zc = (double(T.z) + 0.5) * D.wz;
+    org = make_int4(int(fix_axis(xc, D.fix_x)), int(0x80000000u), int(fix_axis(zc, D.fix_z)), 0);
+    if (!UNI) sc = make_float3(D.unit_x, D.unit_y, D.unit_z);
+    tile_stage_rel(T, pfix, lx, ly, lz, org, sc);
+  } else if (local) {
+    tile_stage(T, pfix, lx, ly, lz);
+  }
   if (use_tab) {
     if (threadIdx.x == 0) tab_ok = 1;
     __syncthreads();
@@ -965,7 +1014,9 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     }
     __syncthreads();
     use_tab = tab_ok != 0;
+    if (flt && !use_tab) tile_stage(T, pfix, lx, ly, lz);  // the cell-by-cell loop reads fixed point
   }
+  const bool rel = flt && use_tab;
   const bool copy = from.x != to.x;  // a rebuild outside the step sequence copies nothing
   for (uint32_t i = T.home0 + threadIdx.x; i < T.home1; i += blockDim.x) {
     if (copy) {
@@ -976,6 +1027,14 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     const int4 me = pfix[i];
     // squared separation (in fixed-point units squared with UNI)
     const float rl2u = UNI ? rl2 * D.inv_u2 : rl2;
+    const float rl2r = rl2u * 1.00001f;
+    const float mx = float(int(uint32_t(me.x) - uint32_t(org.x))) * sc.x;
+    const float my = float(int(uint32_t(me.y) - uint32_t(org.y))) * sc.y;
+    const float mz = float(int(uint32_t(me.z) - uint32_t(org.z))) * sc.z;
+    auto sep2r = [&](int ox, int oy, int oz) {
+      const float ax = mx - __int_as_float(ox), ay = my - __int_as_float(oy), az = mz - __int_as_float(oz);
+      return ax * ax + ay * ay + az * az;
+    };
     auto sep2 = [&](int ox, int oy, int oz) {
       const float ax = float(int(uint32_t(me.x) - uint32_t(ox))) * (UNI ? 1.0f : D.unit_x);
       const float ay = float(int(uint32_t(me.y) - uint32_t(oy))) * (UNI ? 1.0f : D.unit_y);
@@ -1007,14 +1066,25 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     // candidates k in [a, b) of the LDS arrays, four LDS reads in flight
     auto screen = [&](uint32_t a, uint32_t b, uint32_t myk) {
       uint32_t k = a;
-      for (; k + 4 <= b; k += 4) {
-        float r2[4];
+      if (rel) {
+        for (; k + 4 <= b; k += 4) {
+          float r2[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r2[u] = sep2(lx[k + u], ly[k + u], lz[k + u]);
+          for (int u = 0; u < 4; ++u) r2[u] = sep2r(lx[k + u], ly[k + u], lz[k + u]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) put16(r2[u] < rl2u && k + u != myk, k + u);
+          for (int u = 0; u < 4; ++u) put16(r2[u] < rl2r && k + u != myk, k + u);
+        }
+        for (; k < b; ++k) put16(sep2r(lx[k], ly[k], lz[k]) < rl2r && k != myk, k);
+      } else {
+        for (; k + 4 <= b; k += 4) {
+          float r2[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) r2[u] = sep2(lx[k + u], ly[k + u], lz[k + u]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) put16(r2[u] < rl2u && k + u != myk, k + u);
+        }
+        for (; k < b; ++k) put16(sep2(lx[k], ly[k], lz[k]) < rl2u && k != myk, k);
       }
-      for (; k < b; ++k) put16(sep2(lx[k], ly[k], lz[k]) < rl2u && k != myk, k);
     };
     if (use_tab) {
       // own LDS index, for the self test
