@@ -961,7 +961,8 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
   const int t = xcd_block();
   tile_ranges(tiles[t], ntot, sims, start, ncount, wstart, wcount, T);
   const uint32_t total = T.off[TILE_RUNS];
-  const bool local = !global_out && total <= uint32_t(TILE_STAGE);
+  // one LDS slot beyond the staged atoms holds the padding entry's position
+  const bool local = !global_out && total < uint32_t(TILE_STAGE);
   if (threadIdx.x < TILE_REC)  // range table and mode, for the force kernels until the next rebuild
     tilerec[size_t(t) * TILE_REC + threadIdx.x] =
         threadIdx.x == TILE_REC - 1 ? (local ? 0u : 1u) : reinterpret_cast<const uint32_t*>(&T)[threadIdx.x];
@@ -1154,6 +1155,12 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
         }
       }
     }
+    // LDS lists are padded to whole groups of eight with the slot after the
+    // staged atoms, which the force kernels place half a box away in z (more
+    // than r_c from every atom of the slab): the force loop then needs no
+    // partial last group
+    if (local && D.nz >= 4)
+      while (cnt & 7u) put16(true, total);
     if (cnt > uint32_t(cap)) {
       atomicMax(&overflow[0], int(cnt));
       cnt = cap;
@@ -1201,7 +1208,15 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     }
   };
   fetch(0);
-  if (local) tile_stage(T, pfix, lx, ly, lz);
+  if (local) {
+    if (threadIdx.x == 0) {  // the padding slot: half a box from the slab's centre in z
+      const uint32_t pad = T.off[TILE_RUNS];
+      lx[pad] = 0;
+      ly[pad] = 0;
+      lz[pad] = int(fix_axis((double(T.z) + 0.5) * D.wz, D.fix_z) + 0x80000000u);
+    }
+    tile_stage(T, pfix, lx, ly, lz);
+  }
   const uint32_t first_wall = local ? T.off[6] : uint32_t(ntot);  // walls come after the fluid ranges
   for (uint32_t base = 0; base < n_home; base += blockDim.x) {
     const uint32_t i = T.home0 + base + threadIdx.x;
