@@ -448,13 +448,20 @@ __device__ __forceinline__ bool sampled_step(int64_t nstep, const StepConst& K) 
 // tbin_cnt indexed from the system's first bin), cleared before and flushed
 // after all of its atoms, and all of its lanes belong to one system; TB = 0:
 // the bins are gathered here per call.
+// Per-thread sums of a tile, reduced once per tile by the caller: thermostat
+// component, kinetic and potential energy, then the flux and the three
+// temperature components of a sampled step.
+struct TileSums {
+  double v[7];
+};
+
 template <int MODE, int TB = 0>
 __device__ __forceinline__ void finish_force(int i, bool valid, int s, const SimDev* __restrict__ sims, float fx,
                                              float fy, float fz, float pe, StateRef st, Acc acc,
                                              int64_t* __restrict__ dstate, int64_t nstep, const StepConst& K,
                                              double* lds_vx, double* lds_cnt, int* lds_base,
                                              float* tbin_vx = nullptr, float* tbin_cnt = nullptr,
-                                             const double3* vpre = nullptr) {
+                                             const double3* vpre = nullptr, TileSums* ts = nullptr) {
   const int p = int(nstep & 1);
   double vc2 = 0.0, ke = 0.0, pes = valid ? double(pe) : 0.0;
   // scalars, not an array indexed by the run-time axis (that would live in
@@ -476,8 +483,10 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
     double* const acc_vc2 = p ? acc.vc2[1] : acc.vc2[0];
     double* const acc_ke = p ? acc.ke[1] : acc.ke[0];
     double* const acc_pe = p ? acc.pe[1] : acc.pe[0];
-    // a tile's atoms all belong to one system (invalid lanes add zero)
-    if (TB || wave_uniform(valid ? s : -1)) {
+    if (TB) {  // the caller reduces over the tile
+      ts->v[0] += vc2;
+      if (K.energy_on) { ts->v[1] += ke; ts->v[2] += pes; }
+    } else if (wave_uniform(valid ? s : -1)) {
       vc2 = wave_sum(vc2);
       if (K.energy_on) { ke = wave_sum(ke); pes = wave_sum(pes); }
       const int sw = TB ? s : __shfl(s, 0);  // tiles: s is uniform already
@@ -503,7 +512,9 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   else if (K.axis == 1) q2 = (1.0 - a) * q2 + a * K.T0;
   else q3 = (1.0 - a) * q3 + a * K.T0;
   if (!valid) q0 = q1 = q2 = q3 = 0.0;
-  if (TB || wave_uniform(valid ? s : -1)) {
+  if (TB) {
+    ts->v[3] += q0; ts->v[4] += q1; ts->v[5] += q2; ts->v[6] += q3;
+  } else if (wave_uniform(valid ? s : -1)) {
     q0 = wave_sum(q0); q1 = wave_sum(q1); q2 = wave_sum(q2); q3 = wave_sum(q3);
     const int sw = TB ? s : __shfl(s, 0);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
@@ -1218,6 +1229,9 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     tile_stage(T, pfix, lx, ly, lz);
   }
   const uint32_t first_wall = local ? T.off[6] : uint32_t(ntot);  // walls come after the fluid ranges
+  TileSums sums;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) sums.v[q] = 0.0;
   for (uint32_t base = 0; base < n_home; base += blockDim.x) {
     const uint32_t i = T.home0 + base + threadIdx.x;
     const bool valid = base + threadIdx.x < n_home;
@@ -1290,7 +1304,40 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
       }
     }
     finish_force<MODE, 1>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, nstep, K, nullptr, nullptr,
-                          nullptr, tbin_vx, tbin_cnt, &v);
+                          nullptr, tbin_vx, tbin_cnt, &v, &sums);
+  }
+  // one atomic per sum and tile (per wave and pass they queue on a few
+  // addresses per system)
+  if (MODE == 1 || K.energy_on) {
+    __shared__ double red[TILE_TPB / WAVE][7];
+    const int64_t ns = nstep - K.n_equil - 1;
+    const bool sampled = MODE == 1 && nstep > K.n_equil && ns >= K.r && (ns - K.r) / K.B < K.nb;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const bool need = q == 0 ? MODE == 1 : (q < 3 ? K.energy_on != 0 : sampled);
+      if (need) {
+        const double w = wave_sum(sums.v[q]);
+        if (lane == 0) red[wave][q] = w;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+      const int q = threadIdx.x;
+      const bool need = q == 0 ? MODE == 1 : (q < 3 ? K.energy_on != 0 : sampled);
+      if (need) {
+        double tot = 0.0;
+        for (int w = 0; w < int(blockDim.x / WAVE); ++w) tot += red[w][q];
+        const int p = int(nstep & 1);
+        double* dst;
+        if (q == 0) dst = (p ? acc.vc2[1] : acc.vc2[0]) + s;
+        else if (q == 1) dst = (p ? acc.ke[1] : acc.ke[0]) + s;
+        else if (q == 2) dst = (p ? acc.pe[1] : acc.pe[0]) + s;
+        else if (q == 3) { dst = acc.blocks + int64_t(s) * K.nb + (ns - K.r) / K.B; tot *= D.inv_area; }
+        else { dst = acc.tsum + 3 * s + (q - 4); tot *= D.inv_nf; }
+        atomicAdd(dst, tot);
+      }
+    }
   }
   if (bins) {  // one flush of the tile's profile bins
     __syncthreads();
