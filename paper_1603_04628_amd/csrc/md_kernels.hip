@@ -461,7 +461,8 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
                                              int64_t* __restrict__ dstate, int64_t nstep, const StepConst& K,
                                              double* lds_vx, double* lds_cnt, int* lds_base,
                                              float* tbin_vx = nullptr, float* tbin_cnt = nullptr,
-                                             const double3* vpre = nullptr, TileSums* ts = nullptr) {
+                                             const double3* vpre = nullptr, TileSums* ts = nullptr,
+                                             const double* ypre = nullptr) {
   const int p = int(nstep & 1);
   double vc2 = 0.0, ke = 0.0, pes = valid ? double(pe) : 0.0;
   // scalars, not an array indexed by the run-time axis (that would live in
@@ -536,7 +537,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   int gb = -1;
   if (valid) {
     const SimDev& D = sims[s];
-    int bb = int(floor(st.y[i] * D.inv_bin));
+    int bb = int(floor((ypre ? *ypre : st.y[i]) * D.inv_bin));
     bb = bb < 0 ? 0 : (bb >= D.nbins ? D.nbins - 1 : bb);
     gb = D.bin0 + bb;
     if (TB) {
@@ -1303,8 +1304,11 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
         atomicAdd(&acc.pairs[1], w);
       }
     }
+    // wall-normal position for the profile bin, from the fixed-point copy
+    // (within one fixed-point unit of the FP64 one; no memory read)
+    const double yb = double(uint32_t(me.y)) / D.fix_y + D.y_lo;
     finish_force<MODE, 1>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, nstep, K, nullptr, nullptr,
-                          nullptr, tbin_vx, tbin_cnt, &v, &sums);
+                          nullptr, tbin_vx, tbin_cnt, &v, &sums, &yb);
   }
   // one atomic per sum and tile (per wave and pass they queue on a few
   // addresses per system)

@@ -187,6 +187,27 @@ def test_flux_matches_oracle_within_standard_errors(path, oracle_flux):
         assert r["T"][1] == pytest.approx(o["T"][1], abs=0.01)
 
 
+@pytest.mark.parametrize("path", PATHS)
+def test_profile_bins_match_oracle(path):
+    # Sec. 2.1: every sampled step also adds each atom's streamwise velocity
+    # and a count to the wall-normal bin of its height.  From one equilibrated
+    # state, ten sampled steps on each side differ only by FP32 force rounding:
+    # the counts agree exactly and the momentum sums far below one velocity.
+    pre = omd.System(6.0, 0.05, 7, omd.Params(**SMALL_L))
+    pre.run(300)
+    x, v = pre.get_state()
+    ctx, g_sys, o_sys = _pair(6.0, 0.05, 7, path, n_equil=0, **SMALL_L)
+    g_sys.set_state(x, v)
+    o_sys.set_state(x, v)
+    g_sys.run(10)
+    o_sys.run(10)
+    mvx, cnt = g_sys.profile()
+    mvo, cno = o_sys.profile()
+    assert cno.sum() == 10 * o_sys.n_fluid
+    assert np.array_equal(cnt, cno)
+    assert np.abs(mvx - mvo).max() <= 1e-6 * max(1.0, np.abs(mvo).max())
+
+
 def test_batch_equals_single_systems():
     p = hmd.Params(**SMALL_L)
     ctx = hmd.Context(p)
