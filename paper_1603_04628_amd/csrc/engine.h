@@ -59,6 +59,7 @@ struct SimDev {
   int wc0;                     // wall columns [wc0, wc0 + 2 nx nz)
   int w0;                      // wall atoms [w0, w0 + nw) of the wall arrays
   int nbins, bin0;             // profile bins [bin0, bin0 + nbins)
+  int sbin0;                   // slab bins [sbin0, sbin0 + nz nbins) of the tiled path
   // Cells are numbered in Morton (Z) order of their coordinates so that
   // consecutive slots form compact 3-D clusters: rank maps the row-major
   // cell id (cz ny + cy) nx + cx to its place in that order, lin inverts it.
@@ -87,6 +88,8 @@ struct Acc {
   double* tsum;     // [S * 3] sums of T_a over sampled steps
   double* binvx;    // [bins] sum v_x
   double* bincnt;   // [bins] counts
+  double* sbinvx;   // [slab bins] the tiled path's sums per z slab (fewer writers per address)
+  double* sbincnt;  // [slab bins] its counts
   int* status;      // [S] bit 0: unstable
   unsigned long long* pairs;  // [2] in-cutoff fluid-fluid (ordered) and wall-fluid pairs
 };
@@ -112,7 +115,7 @@ struct hmd_batch {
   std::vector<uint32_t> cell_rank;    // per system, concatenated: row-major cell id -> Morton rank
   uint32_t* d_cellmap = nullptr;      // device copies: rank tables, then inverse tables
   std::vector<hmd::SimDev> sims;
-  int64_t ntot = 0, ncell = 0, nwall = 0, nwcell = 0, nbins = 0;
+  int64_t ntot = 0, ncell = 0, nwall = 0, nwcell = 0, nbins = 0, nsbins = 0;
 
   // device buffers
   hmd::SimDev* d_sims = nullptr;

@@ -395,7 +395,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   }
   // flattened layout
   b->sims.resize(n);
-  int64_t a0 = 0, c0 = 0, wc0 = 0, bin0 = 0, w0 = 0;
+  int64_t a0 = 0, c0 = 0, wc0 = 0, bin0 = 0, w0 = 0, sbin0 = 0;
   const double half = 0.5 * std::cbrt(4.0 / b->P.rho_wall);
   for (int k = 0; k < n; ++k) {
     const HostSystem& H = b->host[k];
@@ -428,10 +428,12 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     D.wc0 = int(wc0);
     D.w0 = int(w0);
     D.nbins = H.nbins; D.bin0 = int(bin0);
+    D.sbin0 = int(sbin0);
     a0 += H.nf;
     c0 += D.ncell;
     wc0 += 2 * int64_t(H.nx) * H.nz;
     bin0 += H.nbins;
+    sbin0 += int64_t(H.nz) * H.nbins;
     w0 += H.nw;
   }
   if (a0 + w0 >= (int64_t(1) << 31) || c0 >= (int64_t(1) << 31)) {
@@ -440,6 +442,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     return HMD_EINVAL;
   }
   b->ntot = a0; b->ncell = c0; b->nwcell = wc0; b->nbins = bin0; b->nwall = w0;
+  b->nsbins = sbin0;
   b->walls_same = b->P.eps_wf == 1.0 && b->P.sigma_wf == 1.0;
   b->uniform = true;
   for (const SimDev& D : b->sims)
@@ -506,7 +509,8 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap, b->cell_rank.data(), 4 * b->ncell, hipMemcpyHostToDevice, ctx->stream));
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap + b->ncell, cell_lin.data(), 4 * b->ncell, hipMemcpyHostToDevice,
                               ctx->stream));
-  const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->P.n_blocks + 3 * int64_t(n) + 2 * b->nbins;
+  const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->P.n_blocks + 3 * int64_t(n) + 2 * b->nbins +
+                       2 * b->nsbins;
   if ((rc = dalloc(ctx, &b->d_accbuf, nacc)) || (rc = dalloc(ctx, &b->d_status, n)) ||
       (rc = dalloc(ctx, &b->acc.pairs, 2)))
     return fail(rc);
@@ -517,7 +521,9 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   b->acc.blocks = q; q += int64_t(n) * b->P.n_blocks;
   b->acc.tsum = q; q += 3 * int64_t(n);
   b->acc.binvx = q; q += b->nbins;
-  b->acc.bincnt = q;
+  b->acc.bincnt = q; q += b->nbins;
+  b->acc.sbinvx = q; q += b->nsbins;
+  b->acc.sbincnt = q;
   b->acc.status = b->d_status;
 
   hipStream_t s = ctx->stream;
@@ -966,8 +972,19 @@ int batch_profile(hmd_batch* b, int sim, double* mvx, double* cnt) {
   hmd_ctx* ctx = b->ctx;
   if (sim < 0 || sim >= b->S) return HMD_EINVAL;
   const SimDev& D = b->sims[sim];
-  if (mvx) HMD_HIP(ctx, hipMemcpy(mvx, b->acc.binvx + D.bin0, 8 * size_t(D.nbins), hipMemcpyDeviceToHost));
-  if (cnt) HMD_HIP(ctx, hipMemcpy(cnt, b->acc.bincnt + D.bin0, 8 * size_t(D.nbins), hipMemcpyDeviceToHost));
+  // per-system bins plus the tiled path's per-slab bins
+  std::vector<double> a(D.nbins), c(D.nbins), sa(size_t(D.nz) * D.nbins), sc(size_t(D.nz) * D.nbins);
+  HMD_HIP(ctx, hipMemcpy(a.data(), b->acc.binvx + D.bin0, 8 * a.size(), hipMemcpyDeviceToHost));
+  HMD_HIP(ctx, hipMemcpy(c.data(), b->acc.bincnt + D.bin0, 8 * c.size(), hipMemcpyDeviceToHost));
+  HMD_HIP(ctx, hipMemcpy(sa.data(), b->acc.sbinvx + D.sbin0, 8 * sa.size(), hipMemcpyDeviceToHost));
+  HMD_HIP(ctx, hipMemcpy(sc.data(), b->acc.sbincnt + D.sbin0, 8 * sc.size(), hipMemcpyDeviceToHost));
+  for (int z = 0; z < D.nz; ++z)
+    for (int k = 0; k < D.nbins; ++k) {
+      a[k] += sa[size_t(z) * D.nbins + k];
+      c[k] += sc[size_t(z) * D.nbins + k];
+    }
+  if (mvx) std::copy(a.begin(), a.end(), mvx);
+  if (cnt) std::copy(c.begin(), c.end(), cnt);
   return HMD_OK;
 }
 

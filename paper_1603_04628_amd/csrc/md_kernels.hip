@@ -444,6 +444,8 @@ __device__ __forceinline__ bool sampled_step(int64_t nstep, const StepConst& K) 
   return nstep > K.n_equil && ns >= K.r && (ns - K.r) / K.B < K.nb;
 }
 
+// vpre, ypre: the atom's velocity and its height in bin widths, when the
+// caller has them already.
 // TB = 1: the caller owns per-system FP32 profile bins in LDS (tbin_vx,
 // tbin_cnt indexed from the system's first bin), cleared before and flushed
 // after all of its atoms, and all of its lanes belong to one system; TB = 0:
@@ -462,7 +464,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
                                              double* lds_vx, double* lds_cnt, int* lds_base,
                                              float* tbin_vx = nullptr, float* tbin_cnt = nullptr,
                                              const double3* vpre = nullptr, TileSums* ts = nullptr,
-                                             const double* ypre = nullptr) {
+                                             const double* ypre = nullptr, int tb_sampled = 0) {
   const int p = int(nstep & 1);
   double vc2 = 0.0, ke = 0.0, pes = valid ? double(pe) : 0.0;
   // scalars, not an array indexed by the run-time axis (that would live in
@@ -503,10 +505,17 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   if (MODE != 1) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) dstate[3] = K.thermo_on;
   // sample of step nstep (mass flow rate per unit span, Sec. 2.1)
-  const int64_t ns = nstep - K.n_equil - 1;
-  if (nstep <= K.n_equil || ns < K.r) return;
-  const int64_t b = (ns - K.r) / K.B;
-  if (b >= K.nb) return;
+  // tiles: the caller decides once per launch whether the step is sampled
+  // (the block index needs a 64-bit division)
+  int64_t b = 0;
+  if (TB) {
+    if (!tb_sampled) return;
+  } else {
+    const int64_t ns = nstep - K.n_equil - 1;
+    if (nstep <= K.n_equil || ns < K.r) return;
+    b = (ns - K.r) / K.B;
+    if (b >= K.nb) return;
+  }
   const double a = K.thermo_on ? K.dt_tau : 0.0;
   double q0 = v0, q1 = v0 * v0, q2 = v1 * v1, q3 = v2 * v2;
   if (K.axis == 0) q1 = (1.0 - a) * q1 + a * K.T0;
@@ -537,7 +546,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   int gb = -1;
   if (valid) {
     const SimDev& D = sims[s];
-    int bb = int(floor((ypre ? *ypre : st.y[i]) * D.inv_bin));
+    int bb = int(floor(ypre ? *ypre : st.y[i] * D.inv_bin));
     bb = bb < 0 ? 0 : (bb >= D.nbins ? D.nbins - 1 : bb);
     gb = D.bin0 + bb;
     if (TB) {
@@ -1195,13 +1204,15 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
   __shared__ float tbin_cnt[BIN_LDS];
   const int t = xcd_block();
   const int64_t nstep = step_n(R) + 1;  // the step this launch completes
-  const bool bins = MODE == 1 && K.bins_on && sampled_step(nstep, K);
+  const bool sampled = MODE == 1 && sampled_step(nstep, K);
+  const bool bins = sampled && K.bins_on;
   if (bins)
     for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) { tbin_vx[k] = 0.f; tbin_cnt[k] = 0.f; }
   tile_load(tilerec + size_t(t) * TILE_REC, T);  // ends with a barrier
   const bool local = T.mode == 0;
   const int s = __builtin_amdgcn_readfirstlane(T.s);  // one system per tile
   const SimDev& D = sims[s];
+  const double bin_c1 = D.inv_bin / D.fix_y, bin_c0 = D.y_lo * D.inv_bin;  // fixed-point y -> bins
   const uint32_t n_home = T.home1 - T.home0;
   // a pass's own positions, velocities, list lengths and first list groups
   // are requested one step ahead: the first pass's during the staging, the
@@ -1304,18 +1315,17 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
         atomicAdd(&acc.pairs[1], w);
       }
     }
-    // wall-normal position for the profile bin, from the fixed-point copy
-    // (within one fixed-point unit of the FP64 one; no memory read)
-    const double yb = double(uint32_t(me.y)) / D.fix_y + D.y_lo;
+    // wall-normal position in bin widths, from the fixed-point copy (within
+    // one fixed-point unit of the FP64 one; no memory read)
+    const double yb = double(uint32_t(me.y)) * bin_c1 + bin_c0;
     finish_force<MODE, 1>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, nstep, K, nullptr, nullptr,
-                          nullptr, tbin_vx, tbin_cnt, &v, &sums, &yb);
+                          nullptr, tbin_vx, tbin_cnt, &v, &sums, &yb, sampled ? 1 : 0);
   }
   // one atomic per sum and tile (per wave and pass they queue on a few
   // addresses per system)
   if (MODE == 1 || K.energy_on) {
     __shared__ double red[TILE_TPB / WAVE][7];
     const int64_t ns = nstep - K.n_equil - 1;
-    const bool sampled = MODE == 1 && nstep > K.n_equil && ns >= K.r && (ns - K.r) / K.B < K.nb;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
@@ -1347,9 +1357,10 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     __syncthreads();
     const int nb = min(D.nbins, BIN_LDS);
     for (int k = threadIdx.x; k < nb; k += blockDim.x)
-      if (tbin_cnt[k] != 0.f) {
-        atomicAdd(&acc.binvx[D.bin0 + k], double(tbin_vx[k]));
-        atomicAdd(&acc.bincnt[D.bin0 + k], double(tbin_cnt[k]));
+      if (tbin_cnt[k] != 0.f) {  // per z slab: a few tiles write each address, not all of the system's
+        const int64_t sb = int64_t(D.sbin0) + int64_t(T.z) * D.nbins + k;
+        atomicAdd(&acc.sbinvx[sb], double(tbin_vx[k]));
+        atomicAdd(&acc.sbincnt[sb], double(tbin_cnt[k]));
       }
   }
 }
