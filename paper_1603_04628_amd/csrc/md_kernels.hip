@@ -1272,9 +1272,12 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
           pair(k0, lx[k0], ly[k0], lz[k0]);
           pair(k1, lx[k1], ly[k1], lz[k1]);
         };
+        // group g of slot i at byte (g ld + i) 16: a 32-bit offset from the
+        // list base (the list is below 4 GiB), no 64-bit address arithmetic
+        const char* const list_b = reinterpret_cast<const char*>(list);
         for (uint32_t g = 0; g < full; ++g) {
           const uint32_t gn = g + 1 < ngrp ? g + 1 : g;
-          const uint4 jn = grp[size_t(gn) * ld];
+          const uint4 jn = *reinterpret_cast<const uint4*>(list_b + ((__umul24(gn, uint32_t(ld)) + i) << 4));
           two(jj.x); two(jj.y); two(jj.z); two(jj.w);
           jj = jn;
         }
