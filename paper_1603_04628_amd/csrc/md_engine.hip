@@ -106,7 +106,7 @@ void launch_build(hmd_batch* b, hipStream_t s, const int* flag, StepRef R, State
   if (b->path == 2) {
     hipLaunchKernelGGL(b->uniform ? k_build_tiles<1> : k_build_tiles<0>, dim3(b->ntiles), dim3(TILE_THREADS), 0,
                        s, nt,
-                       b->list_ld, b->list_cap, b->stage_cap, b->d_tiles, b->d_sims, b->d_slot_cell, b->d_pfix,
+                       b->list_ld, b->list_cap, b->d_tiles, b->d_sims, b->d_slot_cell, b->d_pfix,
                        b->d_start, b->d_ncount, b->d_wstart, b->d_wcount, b->d_list, b->d_nlist,
                        b->d_tilerec, from, to, tag_from, tag_to, b->d_flag + 2, flag, R, rl2,
                        global_out || b->force_gather ? 1 : 0);
@@ -201,7 +201,7 @@ void enqueue_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K, St
     const int v = ((mode * 2 + (K.energy_on ? 1 : 0)) * 2 + (b->uniform ? 1 : 0)) * 2 + (b->walls_same ? 1 : 0);
     if (b->path == 2) {
       hipLaunchKernelGGL(force_tiles_variant(v), dim3(b->ntiles), dim3(TILE_THREADS), 0, s, nt, b->list_ld,
-                         b->stage_cap, b->d_tilerec, b->d_sims, b->d_pfix, b->d_list,
+                         b->d_tilerec, b->d_sims, b->d_pfix, b->d_list,
                          b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
     } else {
       hipLaunchKernelGGL(force_list_variant(v), dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims,

@@ -61,14 +61,16 @@ constexpr int TILE_CTAB = 768;
 // to the next
 constexpr int TILE_REC = 49;
 template <int UNI>
-__global__ void k_build_tiles(int ntot, int ld, int cap, int stage_cap, const int4* tiles, const SimDev* sims,
+__global__ void k_build_tiles(int ntot, int ld, int cap, const int4* tiles, const SimDev* sims,
                               const uint32_t* slot_cell, const int4* pfix, const uint32_t* start,
                               const uint32_t* ncount, const uint32_t* wstart, const uint32_t* wcount,
-                              uint32_t* list, uint32_t* nlist, uint32_t* tilerec, StateRef from, StateRef to, const int* tag_from, int* tag_to, int* overflow,
-                              const int* flag, StepRef R, float rl2, int global_out);
+                              uint32_t* list, uint32_t* nlist, uint32_t* tilerec, StateRef from, StateRef to,
+                              const int* tag_from, int* tag_to, int* overflow, const int* flag, StepRef R,
+                              float rl2, int global_out);
 template <int MODE, int ENERGY, int UNI, int WS>
-__global__ void k_force_tiles(int ntot, int ld, int stage_cap, const uint32_t* tilerec, const SimDev* sims, const int4* pfix, const uint32_t* list, const uint32_t* nlist,
-                              float4* f4, StateRef st, Acc acc, int64_t* dstate, StepRef R, StepConst K);
+__global__ void k_force_tiles(int ntot, int ld, const uint32_t* tilerec, const SimDev* sims, const int4* pfix,
+                              const uint32_t* list, const uint32_t* nlist, float4* f4, StateRef st, Acc acc,
+                              int64_t* dstate, StepRef R, StepConst K);
 __global__ void k_set_i64(int64_t* p, int64_t v);
 __global__ void k_add_i64(int64_t* p, int64_t v);
 __global__ void k_set_i32(int* p, int v);

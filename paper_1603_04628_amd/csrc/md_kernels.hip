@@ -965,10 +965,11 @@ __device__ __forceinline__ void tile_load(const uint32_t* __restrict__ rec, Tile
 // position indices (the layout of k_build_list) for every tile.
 template <int UNI>
 __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
-    int ntot, int ld, int cap, int stage_cap, const int4* __restrict__ tiles, const SimDev* __restrict__ sims,
+    int ntot, int ld, int cap, const int4* __restrict__ tiles, const SimDev* __restrict__ sims,
     const uint32_t* __restrict__ slot_cell, const int4* __restrict__ pfix, const uint32_t* __restrict__ start,
     const uint32_t* __restrict__ ncount, const uint32_t* __restrict__ wstart, const uint32_t* __restrict__ wcount,
-    uint32_t* __restrict__ list, uint32_t* __restrict__ nlist, uint32_t* __restrict__ tilerec, StateRef from, StateRef to, const int* __restrict__ tag_from,
+    uint32_t* __restrict__ list, uint32_t* __restrict__ nlist, uint32_t* __restrict__ tilerec, StateRef from,
+    StateRef to, const int* __restrict__ tag_from,
     int* __restrict__ tag_to, int* __restrict__ overflow, const int* __restrict__ flag, StepRef R, float rl2,
     int global_out) {
   if (!rebuild_needed(flag, R)) return;
@@ -1195,7 +1196,8 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
 // half-kick and the sample of the step.
 template <int MODE, int ENERGY, int UNI, int WS>
 __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
-    int ntot, int ld, int stage_cap, const uint32_t* __restrict__ tilerec, const SimDev* __restrict__ sims, const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
+    int ntot, int ld, const uint32_t* __restrict__ tilerec, const SimDev* __restrict__ sims,
+    const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
     const uint32_t* __restrict__ nlist, float4* __restrict__ f4, StateRef st, Acc acc,
     int64_t* __restrict__ dstate, StepRef R, StepConst K) {
   __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
@@ -1392,17 +1394,17 @@ template __global__ void k_force_cell<0>(int, const SimDev*, const uint16_t*, co
 template __global__ void k_force_cell<1>(int, const SimDev*, const uint16_t*, const float4*, const uint32_t*,
                                          const uint32_t*, const float4*, const uint32_t*, const uint32_t*, float4*,
                                          StateRef, Acc, int64_t*, StepRef, StepConst);
-template __global__ void k_build_tiles<0>(int, int, int, int, const int4*, const SimDev*, const uint32_t*,
+template __global__ void k_build_tiles<0>(int, int, int, const int4*, const SimDev*, const uint32_t*,
                                           const int4*, const uint32_t*, const uint32_t*, const uint32_t*,
                                           const uint32_t*, uint32_t*, uint32_t*, uint32_t*, StateRef, StateRef,
                                           const int*, int*, int*, const int*, StepRef, float, int);
-template __global__ void k_build_tiles<1>(int, int, int, int, const int4*, const SimDev*, const uint32_t*,
+template __global__ void k_build_tiles<1>(int, int, int, const int4*, const SimDev*, const uint32_t*,
                                           const int4*, const uint32_t*, const uint32_t*, const uint32_t*,
                                           const uint32_t*, uint32_t*, uint32_t*, uint32_t*, StateRef, StateRef,
                                           const int*, int*, int*, const int*, StepRef, float, int);
 
 #define HMD_FORCE_TILES(M, E, U, W)                                                                    \
-  template __global__ void k_force_tiles<M, E, U, W>(int, int, int, const uint32_t*, const SimDev*,           \
+  template __global__ void k_force_tiles<M, E, U, W>(int, int, const uint32_t*, const SimDev*,                \
                                                      const int4*, const uint32_t*,                             \
                                                      const uint32_t*, float4*, StateRef, Acc, int64_t*,        \
                                                      StepRef, StepConst);
