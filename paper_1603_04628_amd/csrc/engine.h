@@ -59,7 +59,6 @@ struct SimDev {
   int wc0;                     // wall columns [wc0, wc0 + 2 nx nz)
   int w0;                      // wall atoms [w0, w0 + nw) of the wall arrays
   int nbins, bin0;             // profile bins [bin0, bin0 + nbins)
-  int sbin0;                   // slab bins [sbin0, sbin0 + nz nbins) of the tiled path
   // Cells are numbered in Morton (Z) order of their coordinates so that
   // consecutive slots form compact 3-D clusters: rank maps the row-major
   // cell id (cz ny + cy) nx + cx to its place in that order, lin inverts it.
@@ -88,8 +87,8 @@ struct Acc {
   double* tsum;     // [S * 3] sums of T_a over sampled steps
   double* binvx;    // [bins] sum v_x
   double* bincnt;   // [bins] counts
-  double* sbinvx;   // [slab bins] the tiled path's sums per z slab (fewer writers per address)
-  double* sbincnt;  // [slab bins] its counts
+  double* tbins;    // [tiles * BIN_LDS * 2] the tiled path's bins: (sum v_x, count) per tile and bin,
+                    // each tile adding to its own (no atomics; summed per system when read)
   int* status;      // [S] bit 0: unstable
   unsigned long long* pairs;  // [2] in-cutoff fluid-fluid (ordered) and wall-fluid pairs
 };
@@ -115,7 +114,7 @@ struct hmd_batch {
   std::vector<uint32_t> cell_rank;    // per system, concatenated: row-major cell id -> Morton rank
   uint32_t* d_cellmap = nullptr;      // device copies: rank tables, then inverse tables
   std::vector<hmd::SimDev> sims;
-  int64_t ntot = 0, ncell = 0, nwall = 0, nwcell = 0, nbins = 0, nsbins = 0;
+  int64_t ntot = 0, ncell = 0, nwall = 0, nwcell = 0, nbins = 0;
 
   // device buffers
   hmd::SimDev* d_sims = nullptr;
@@ -131,6 +130,8 @@ struct hmd_batch {
   uint32_t* d_list = nullptr;       // pair path: list_cap x list_ld entries
   int4* d_tiles = nullptr;          // tiled path: (system, z slab, first column, columns) per workgroup
   uint32_t* d_tilerec = nullptr;    // tiled path: range table and list mode per tile, written by each list build
+  double* d_tbins = nullptr;        // tiled path: profile bins per tile (Acc::tbins)
+  std::vector<int> tile_first;      // tiled path: first tile of each system (S + 1 entries)
   int ntiles = 0, stage_cap = 0;    // tiles; LDS capacity in atoms
   uint32_t* d_nlist = nullptr;
   int* d_flag = nullptr;            // [2] rebuild flags by step parity, list overflow, builds so far

@@ -327,7 +327,9 @@ int make_tiles(hmd_batch* b) {
   constexpr int kStageCap = TILE_STAGE;
   b->stage_cap = kStageCap;
   std::vector<int4> tiles;
+  b->tile_first.assign(b->S + 1, 0);
   for (int k = 0; k < b->S; ++k) {
+    b->tile_first[k] = int(tiles.size());
     const SimDev& D = b->sims[k];
     const HostSystem& H = b->host[k];
     const double per_col = double(D.nf) / double(D.nx * D.nz);
@@ -353,6 +355,9 @@ int make_tiles(hmd_batch* b) {
       }
   }
   b->ntiles = int(tiles.size());
+  b->tile_first[b->S] = b->ntiles;
+  HMD_TRY(dalloc(ctx, &b->d_tbins, int64_t(b->ntiles) * BIN_LDS * 2));
+  HMD_HIP(ctx, hipMemsetAsync(b->d_tbins, 0, sizeof(double) * size_t(b->ntiles) * BIN_LDS * 2, ctx->stream));
   HMD_TRY(dalloc(ctx, &b->d_tiles, b->ntiles));
   HMD_TRY(dalloc(ctx, &b->d_tilerec, int64_t(b->ntiles) * TILE_REC));
   HMD_HIP(ctx, hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice,
@@ -395,7 +400,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   }
   // flattened layout
   b->sims.resize(n);
-  int64_t a0 = 0, c0 = 0, wc0 = 0, bin0 = 0, w0 = 0, sbin0 = 0;
+  int64_t a0 = 0, c0 = 0, wc0 = 0, bin0 = 0, w0 = 0;
   const double half = 0.5 * std::cbrt(4.0 / b->P.rho_wall);
   for (int k = 0; k < n; ++k) {
     const HostSystem& H = b->host[k];
@@ -428,12 +433,10 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     D.wc0 = int(wc0);
     D.w0 = int(w0);
     D.nbins = H.nbins; D.bin0 = int(bin0);
-    D.sbin0 = int(sbin0);
     a0 += H.nf;
     c0 += D.ncell;
     wc0 += 2 * int64_t(H.nx) * H.nz;
     bin0 += H.nbins;
-    sbin0 += int64_t(H.nz) * H.nbins;
     w0 += H.nw;
   }
   if (a0 + w0 >= (int64_t(1) << 31) || c0 >= (int64_t(1) << 31)) {
@@ -442,7 +445,6 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     return HMD_EINVAL;
   }
   b->ntot = a0; b->ncell = c0; b->nwcell = wc0; b->nbins = bin0; b->nwall = w0;
-  b->nsbins = sbin0;
   b->walls_same = b->P.eps_wf == 1.0 && b->P.sigma_wf == 1.0;
   b->uniform = true;
   for (const SimDev& D : b->sims)
@@ -509,8 +511,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap, b->cell_rank.data(), 4 * b->ncell, hipMemcpyHostToDevice, ctx->stream));
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap + b->ncell, cell_lin.data(), 4 * b->ncell, hipMemcpyHostToDevice,
                               ctx->stream));
-  const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->P.n_blocks + 3 * int64_t(n) + 2 * b->nbins +
-                       2 * b->nsbins;
+  const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->P.n_blocks + 3 * int64_t(n) + 2 * b->nbins;
   if ((rc = dalloc(ctx, &b->d_accbuf, nacc)) || (rc = dalloc(ctx, &b->d_status, n)) ||
       (rc = dalloc(ctx, &b->acc.pairs, 2)))
     return fail(rc);
@@ -521,9 +522,8 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   b->acc.blocks = q; q += int64_t(n) * b->P.n_blocks;
   b->acc.tsum = q; q += 3 * int64_t(n);
   b->acc.binvx = q; q += b->nbins;
-  b->acc.bincnt = q; q += b->nbins;
-  b->acc.sbinvx = q; q += b->nsbins;
-  b->acc.sbincnt = q;
+  b->acc.bincnt = q;
+  b->acc.tbins = b->d_tbins;
   b->acc.status = b->d_status;
 
   hipStream_t s = ctx->stream;
@@ -619,7 +619,7 @@ void batch_free(hmd_batch* b) {
                   b->d_slot_cell, b->d_list, b->d_nlist, b->d_flag, b->d_key, b->d_count, b->d_rank, b->d_start,
                   b->d_ncount, b->d_perm, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_dstate, b->d_tag[0],
                   b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs, b->d_cellmap, b->d_tiles,
-                  b->d_tilerec};
+                  b->d_tilerec, b->d_tbins};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int w = 0; w < 2; ++w)
@@ -972,17 +972,21 @@ int batch_profile(hmd_batch* b, int sim, double* mvx, double* cnt) {
   hmd_ctx* ctx = b->ctx;
   if (sim < 0 || sim >= b->S) return HMD_EINVAL;
   const SimDev& D = b->sims[sim];
-  // per-system bins plus the tiled path's per-slab bins
-  std::vector<double> a(D.nbins), c(D.nbins), sa(size_t(D.nz) * D.nbins), sc(size_t(D.nz) * D.nbins);
+  // per-system bins plus, on the tiled path, the system's per-tile bins
+  std::vector<double> a(D.nbins), c(D.nbins);
   HMD_HIP(ctx, hipMemcpy(a.data(), b->acc.binvx + D.bin0, 8 * a.size(), hipMemcpyDeviceToHost));
   HMD_HIP(ctx, hipMemcpy(c.data(), b->acc.bincnt + D.bin0, 8 * c.size(), hipMemcpyDeviceToHost));
-  HMD_HIP(ctx, hipMemcpy(sa.data(), b->acc.sbinvx + D.sbin0, 8 * sa.size(), hipMemcpyDeviceToHost));
-  HMD_HIP(ctx, hipMemcpy(sc.data(), b->acc.sbincnt + D.sbin0, 8 * sc.size(), hipMemcpyDeviceToHost));
-  for (int z = 0; z < D.nz; ++z)
-    for (int k = 0; k < D.nbins; ++k) {
-      a[k] += sa[size_t(z) * D.nbins + k];
-      c[k] += sc[size_t(z) * D.nbins + k];
-    }
+  if (b->d_tbins) {
+    const int t0 = b->tile_first[sim], t1 = b->tile_first[sim + 1];
+    std::vector<double> tb(size_t(t1 - t0) * BIN_LDS * 2);
+    HMD_HIP(ctx, hipMemcpy(tb.data(), b->d_tbins + size_t(t0) * BIN_LDS * 2, 8 * tb.size(), hipMemcpyDeviceToHost));
+    const int nb = std::min(D.nbins, BIN_LDS);
+    for (int t = 0; t < t1 - t0; ++t)
+      for (int k = 0; k < nb; ++k) {
+        a[k] += tb[(size_t(t) * BIN_LDS + k) * 2];
+        c[k] += tb[(size_t(t) * BIN_LDS + k) * 2 + 1];
+      }
+  }
   if (mvx) std::copy(a.begin(), a.end(), mvx);
   if (cnt) std::copy(c.begin(), c.end(), cnt);
   return HMD_OK;

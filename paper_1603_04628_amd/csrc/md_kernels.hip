@@ -444,10 +444,23 @@ __device__ __forceinline__ bool sampled_step(int64_t nstep, const StepConst& K) 
   return nstep > K.n_equil && ns >= K.r && (ns - K.r) / K.B < K.nb;
 }
 
+// One atom's contribution to a tile's profile bin as a single 64-bit word, so
+// that one integer LDS atomic adds both the streamwise velocity and the count
+// (two FP32 LDS atomics per atom cost ~15 us per sampled step on the batch):
+// count in the top 24 bits, v_x + TBIN_OFFSET in units of TBIN_UNIT below
+// (40 bits hold 512 atoms of |v_x| < TBIN_OFFSET; the unit is 2.4e-7).
+constexpr int TBIN_CNT_SHIFT = 40;
+constexpr double TBIN_OFFSET = 16.0;
+constexpr double TBIN_UNIT = 1.0 / 4194304.0;  // 2^-22
+__device__ __forceinline__ unsigned long long tbin_word(double vx) {
+  const double c = vx < -TBIN_OFFSET + 1e-3 ? -TBIN_OFFSET + 1e-3 : (vx > TBIN_OFFSET - 1e-3 ? TBIN_OFFSET - 1e-3 : vx);
+  return (1ull << TBIN_CNT_SHIFT) + (unsigned long long)((c + TBIN_OFFSET) * (1.0 / TBIN_UNIT) + 0.5);
+}
+
 // vpre, ypre: the atom's velocity and its height in bin widths, when the
 // caller has them already.
-// TB = 1: the caller owns per-system FP32 profile bins in LDS (tbin_vx,
-// tbin_cnt indexed from the system's first bin), cleared before and flushed
+// TB = 1: the caller owns per-system profile bins in LDS (tbin, indexed from
+// the system's first bin, packed as in tbin_word), cleared before and flushed
 // after all of its atoms, and all of its lanes belong to one system; TB = 0:
 // the bins are gathered here per call.
 // Per-thread sums of a tile, reduced once per tile by the caller: thermostat
@@ -462,7 +475,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
                                              float fy, float fz, float pe, StateRef st, Acc acc,
                                              int64_t* __restrict__ dstate, int64_t nstep, const StepConst& K,
                                              double* lds_vx, double* lds_cnt, int* lds_base,
-                                             float* tbin_vx = nullptr, float* tbin_cnt = nullptr,
+                                             unsigned long long* tbin = nullptr,
                                              const double3* vpre = nullptr, TileSums* ts = nullptr,
                                              const double* ypre = nullptr, int tb_sampled = 0) {
   const int p = int(nstep & 1);
@@ -551,8 +564,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
     gb = D.bin0 + bb;
     if (TB) {
       if (bb < BIN_LDS) {
-        atomicAdd(&tbin_vx[bb], float(v0));
-        atomicAdd(&tbin_cnt[bb], 1.0f);
+        atomicAdd(&tbin[bb], tbin_word(v0));
       } else {
         atomicAdd(&acc.binvx[gb], v0);
         atomicAdd(&acc.bincnt[gb], 1.0);
@@ -1202,14 +1214,13 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     int64_t* __restrict__ dstate, StepRef R, StepConst K) {
   __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
   __shared__ TileStage T;
-  __shared__ float tbin_vx[BIN_LDS];
-  __shared__ float tbin_cnt[BIN_LDS];
+  __shared__ unsigned long long tbin[BIN_LDS];
   const int t = xcd_block();
   const int64_t nstep = step_n(R) + 1;  // the step this launch completes
   const bool sampled = MODE == 1 && sampled_step(nstep, K);
   const bool bins = sampled && K.bins_on;
   if (bins)
-    for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) { tbin_vx[k] = 0.f; tbin_cnt[k] = 0.f; }
+    for (int k = threadIdx.x; k < BIN_LDS; k += blockDim.x) tbin[k] = 0ull;
   tile_load(tilerec + size_t(t) * TILE_REC, T);  // ends with a barrier
   const bool local = T.mode == 0;
   const int s = __builtin_amdgcn_readfirstlane(T.s);  // one system per tile
@@ -1324,7 +1335,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     // one fixed-point unit of the FP64 one; no memory read)
     const double yb = double(uint32_t(me.y)) * bin_c1 + bin_c0;
     finish_force<MODE, 1>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, nstep, K, nullptr, nullptr,
-                          nullptr, tbin_vx, tbin_cnt, &v, &sums, &yb, sampled ? 1 : 0);
+                          nullptr, tbin, &v, &sums, &yb, sampled ? 1 : 0);
   }
   // one atomic per sum and tile (per wave and pass they queue on a few
   // addresses per system)
@@ -1362,10 +1373,11 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     __syncthreads();
     const int nb = min(D.nbins, BIN_LDS);
     for (int k = threadIdx.x; k < nb; k += blockDim.x)
-      if (tbin_cnt[k] != 0.f) {  // per z slab: a few tiles write each address, not all of the system's
-        const int64_t sb = int64_t(D.sbin0) + int64_t(T.z) * D.nbins + k;
-        atomicAdd(&acc.sbinvx[sb], double(tbin_vx[k]));
-        atomicAdd(&acc.sbincnt[sb], double(tbin_cnt[k]));
+      if (tbin[k] != 0ull) {  // the tile's own FP64 accumulators: a plain add, no atomics
+        double* const tb = acc.tbins + (size_t(t) * BIN_LDS + k) * 2;
+        const double n = double(tbin[k] >> TBIN_CNT_SHIFT);
+        tb[0] += double(tbin[k] & ((1ull << TBIN_CNT_SHIFT) - 1ull)) * TBIN_UNIT - TBIN_OFFSET * n;
+        tb[1] += n;
       }
   }
 }
