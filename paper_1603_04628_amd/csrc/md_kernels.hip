@@ -298,8 +298,17 @@ __global__ __launch_bounds__(256) void k_reorder(int ntot, const SimDev* __restr
   const uint32_t p = perm[j];
   const uint32_t c = key[p];
   const uint32_t st = start[c], n = ncount[c];
-  uint32_t rank = 0;
-  for (uint32_t m = 0; m < n; ++m) rank += perm[st + m] < p ? 1u : 0u;
+  // eight of the cell's entries in flight at a time (one at a time, each
+  // waited for, made this loop the kernel's cost)
+  uint32_t rank = 0, m = 0;
+  for (; m + 8 <= n; m += 8) {
+    uint32_t e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = perm[st + m + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rank += e[u] < p ? 1u : 0u;
+  }
+  for (; m < n; ++m) rank += perm[st + m] < p ? 1u : 0u;
   const uint32_t d = st + rank;
   const double x = src.x[p], y = src.y[p], z = src.z[p];
   dst.x[d] = x; dst.y[d] = y; dst.z[d] = z;
