@@ -136,66 +136,74 @@ __global__ __launch_bounds__(256) void k_integrate(int ntot, const SimDev* __res
                                                    StepRef R, StepConst K) {
   const int i = xcd_block() * blockDim.x + threadIdx.x;
   const bool valid = i < ntot;
-  const int s = valid ? int(atom_sim[i]) : 0;
-  const SimDev& D = sims[s];
-  double r[3] = {0, 0, 0}, v[3] = {0, 0, 0};
-  if (valid) {
-    r[0] = st.x[i]; r[1] = st.y[i]; r[2] = st.z[i];
-    v[0] = st.vx[i]; v[1] = st.vy[i]; v[2] = st.vz[i];
-  }
-  if (MODE == 1) {
-    const int64_t n = step_n(R);  // steps completed before this one
-    if (valid && dstate[3] != 0) {
-      const double Tc = ((n & 1) ? acc.vc2[1] : acc.vc2[0])[s] * D.inv_nf;
-      const double lam = sqrt(1.0 + K.dt_tau * (K.T0 / Tc - 1.0));
-      v[0] *= K.axis == 0 ? lam : 1.0;
-      v[1] *= K.axis == 1 ? lam : 1.0;
-      v[2] *= K.axis == 2 ? lam : 1.0;
-    }
-    if (valid && i == D.a0) {
-      const int p = int((n + 1) & 1);
-      (p ? acc.vc2[1] : acc.vc2[0])[s] = 0.0;
-      (p ? acc.pe[1] : acc.pe[0])[s] = 0.0;
-      (p ? acc.ke[1] : acc.ke[0])[s] = 0.0;
-    }
-    if (PATH == 1 && i == 0 && flag) flag[n & 1] = 0;
+  // The step of one atom for system s.  A wavefront whose atoms all belong
+  // to one system (all but the few that straddle two) runs it with s in a
+  // scalar register, so the system's constants come from scalar loads, not
+  // one vector load per constant.
+  auto body = [&](const int s) {
+    const SimDev& D = sims[s];
+    double r[3] = {0, 0, 0}, v[3] = {0, 0, 0};
     if (valid) {
-      const float4 f = f4[i];
-      v[0] += K.hdt * (double(f.x) + D.g);
-      v[1] += K.hdt * double(f.y);
-      v[2] += K.hdt * double(f.z);
-      r[0] = wrap_periodic(r[0] + K.dt * v[0], D.Lx);
-      r[1] = r[1] + K.dt * v[1];
-      r[2] = wrap_periodic(r[2] + K.dt * v[2], D.Lz);
-      st.x[i] = r[0]; st.y[i] = r[1]; st.z[i] = r[2];
-      st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
-      const bool bad = !(r[1] > 0.0 && r[1] < D.h) || !(r[0] >= 0.0 && r[0] < D.Lx) ||
-                       !(r[2] >= 0.0 && r[2] < D.Lz) || !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
-      if (bad) atomicOr(&acc.status[s], 1);
+      r[0] = st.x[i]; r[1] = st.y[i]; r[2] = st.z[i];
+      v[0] = st.vx[i]; v[1] = st.vy[i]; v[2] = st.vz[i];
+    }
+    if (MODE == 1) {
+      const int64_t n = step_n(R);  // steps completed before this one
+      if (valid && dstate[3] != 0) {
+        const double Tc = ((n & 1) ? acc.vc2[1] : acc.vc2[0])[s] * D.inv_nf;
+        const double lam = sqrt(1.0 + K.dt_tau * (K.T0 / Tc - 1.0));
+        v[0] *= K.axis == 0 ? lam : 1.0;
+        v[1] *= K.axis == 1 ? lam : 1.0;
+        v[2] *= K.axis == 2 ? lam : 1.0;
+      }
+      if (valid && i == D.a0) {
+        const int p = int((n + 1) & 1);
+        (p ? acc.vc2[1] : acc.vc2[0])[s] = 0.0;
+        (p ? acc.pe[1] : acc.pe[0])[s] = 0.0;
+        (p ? acc.ke[1] : acc.ke[0])[s] = 0.0;
+      }
+      if (PATH == 1 && i == 0 && flag) flag[n & 1] = 0;
+      if (valid) {
+        const float4 f = f4[i];
+        v[0] += K.hdt * (double(f.x) + D.g);
+        v[1] += K.hdt * double(f.y);
+        v[2] += K.hdt * double(f.z);
+        r[0] = wrap_periodic(r[0] + K.dt * v[0], D.Lx);
+        r[1] = r[1] + K.dt * v[1];
+        r[2] = wrap_periodic(r[2] + K.dt * v[2], D.Lz);
+        st.x[i] = r[0]; st.y[i] = r[1]; st.z[i] = r[2];
+        st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
+        const bool bad = !(r[1] > 0.0 && r[1] < D.h) || !(r[0] >= 0.0 && r[0] < D.Lx) ||
+                         !(r[2] >= 0.0 && r[2] < D.Lz) || !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
+        if (bad) atomicOr(&acc.status[s], 1);
+      }
+      if (PATH == 1) {
+        if (valid) {
+          const int4 p = to_fixed(r[0], r[1], r[2], D);
+          pfix[i] = p;
+          const float3 dd = fixed_sep(p, pbuild[i], D);
+          if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > K.half_skin2) flag[(n + 1) & 1] = 1;
+        }
+        return;
+      }
     }
     if (PATH == 1) {
-      if (valid) {
-        const int4 p = to_fixed(r[0], r[1], r[2], D);
-        pfix[i] = p;
-        const float3 dd = fixed_sep(p, pbuild[i], D);
-        if (dd.x * dd.x + dd.y * dd.y + dd.z * dd.z > K.half_skin2) flag[(n + 1) & 1] = 1;
-      }
+      if (valid) pfix[i] = to_fixed(r[0], r[1], r[2], D);
       return;
     }
-  }
-  if (PATH == 1) {
-    if (valid) pfix[i] = to_fixed(r[0], r[1], r[2], D);
-    return;
-  }
-  uint32_t c = 0;
-  if (valid) {
-    const int cx = dcell(r[0], D.inv_x, D.nx);
-    const int cy = dcell(r[1], D.inv_y, D.ny);
-    const int cz = dcell(r[2], D.inv_z, D.nz);
-    c = uint32_t(D.c0) + D.rank[(cz * D.ny + cy) * D.nx + cx];
-    key[i] = c;
-  }
-  rank_in_cell(valid, c, count, rank, i);
+    uint32_t c = 0;
+    if (valid) {
+      const int cx = dcell(r[0], D.inv_x, D.nx);
+      const int cy = dcell(r[1], D.inv_y, D.ny);
+      const int cz = dcell(r[2], D.inv_z, D.nz);
+      c = uint32_t(D.c0) + D.rank[(cz * D.ny + cy) * D.nx + cx];
+      key[i] = c;
+    }
+    rank_in_cell(valid, c, count, rank, i);
+  };
+  const int sl = valid ? int(atom_sim[i]) : 0;
+  if (wave_uniform(valid ? sl : -1)) body(__builtin_amdgcn_readfirstlane(sl));
+  else body(sl);
 }
 
 // Pair path: cell keys of the current positions on rebuild steps.
