@@ -1018,7 +1018,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     tilerec[size_t(t) * TILE_REC + threadIdx.x] =
         threadIdx.x == TILE_REC - 1 ? (local ? 0u : 1u) : reinterpret_cast<const uint32_t*>(&T)[threadIdx.x];
   if (t == 0 && threadIdx.x == 0) atomicAdd(&overflow[1], 1);  // builds so far
-  const SimDev& D = sims[T.s];
+  const SimDev& D = sims[__builtin_amdgcn_readfirstlane(T.s)];  // one system per tile: scalar loads
   const bool whole = T.npieces == 1 && T.pa[0] == 0 && T.pb[0] == D.nx - 1;
   const int ncolx = whole ? D.nx : T.ncol + 2, nyt = D.ny + 2;
   bool use_tab = local && 3 * ncolx * nyt <= TILE_CTAB;
