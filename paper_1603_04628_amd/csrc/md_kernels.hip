@@ -116,6 +116,33 @@ __device__ __forceinline__ void rank_in_cell(bool valid, uint32_t c, uint32_t* _
   if (valid) rank[i] = rk;
 }
 
+// Arrival rank of each slot in its cell, a block at a time (blockDim <= 256,
+// all threads call it): the block counts its own atoms per cell in an LDS
+// table, then takes one global atomic per distinct cell -- all in parallel,
+// where the wavefront version takes one per cell in turn.
+__device__ __forceinline__ void rank_in_cell_block(bool valid, uint32_t c, uint32_t* __restrict__ count,
+                                                   uint32_t* __restrict__ rank, int i) {
+  constexpr uint32_t H = 256, EMPTY = 0xffffffffu;
+  __shared__ uint32_t hkey[H], hcnt[H], hbase[H];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t k = tid; k < H; k += blockDim.x) { hkey[k] = EMPTY; hcnt[k] = 0u; }
+  __syncthreads();
+  uint32_t h = c & (H - 1u), local = 0;
+  if (valid) {  // open addressing: at most blockDim distinct keys in H slots
+    for (;;) {
+      const uint32_t old = atomicCAS(&hkey[h], EMPTY, c);
+      if (old == EMPTY || old == c) break;
+      h = (h + 1u) & (H - 1u);
+    }
+    local = atomicAdd(&hcnt[h], 1u);
+  }
+  __syncthreads();
+  for (uint32_t k = tid; k < H; k += blockDim.x)
+    if (hkey[k] != EMPTY) hbase[k] = atomicAdd(&count[hkey[k]], hcnt[k]);
+  __syncthreads();
+  if (valid) rank[i] = hbase[h] + local;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -215,15 +242,22 @@ __global__ __launch_bounds__(256) void k_keys(int ntot, const SimDev* __restrict
   const int i = xcd_block() * blockDim.x + threadIdx.x;
   const bool valid = i < ntot;
   uint32_t c = 0;
-  if (valid) {
-    const SimDev& D = sims[atom_sim[i]];
+  auto cell_of = [&](const int s) {
+    const SimDev& D = sims[s];
     const int cx = dcell(st.x[i], D.inv_x, D.nx);
     const int cy = dcell(st.y[i], D.inv_y, D.ny);
     const int cz = dcell(st.z[i], D.inv_z, D.nz);
-    c = uint32_t(D.c0) + D.rank[(cz * D.ny + cy) * D.nx + cx];
-    key[i] = c;
+    return uint32_t(D.c0) + D.rank[(cz * D.ny + cy) * D.nx + cx];
+  };
+  const int sl = valid ? int(atom_sim[i]) : 0;
+  if (wave_uniform(valid ? sl : -1)) {  // one system: its constants through scalar loads
+    const int su = __builtin_amdgcn_readfirstlane(sl);
+    if (valid) c = cell_of(su);
+  } else if (valid) {
+    c = cell_of(sl);
   }
-  rank_in_cell(valid, c, count, rank, i);
+  if (valid) key[i] = c;
+  rank_in_cell_block(valid, c, count, rank, i);
 }
 
 // scan: one block per system; exclusive scan of the per-cell counts into
