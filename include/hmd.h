@@ -215,8 +215,10 @@ void md_sys_free(hmd_sys* s);
  * their RMS before fitting; sigma_n < 0 means mean(y_se) in those units.
  * gp_append refits (the normalisation moves with the data) except when the
  * normalisation, noise and output scale are all fixed, where it extends the
- * Cholesky factor by one row.  All arithmetic FP64 on the device; ENOTSPD
- * when the covariance is not positive definite.
+ * Cholesky factor by one row.  L^-1 is kept beside the factor (extended
+ * by a row on such an append) so that a query costs one triangular
+ * product.  At most 6144 points (EINVAL beyond).  All arithmetic FP64 on
+ * the device; ENOTSPD when the covariance is not positive definite.
  * ------------------------------------------------------------------------ */
 typedef struct {
     double sigma_f, ell, sigma_n;  /* sigma_n < 0: mean(y_se) / output scale */

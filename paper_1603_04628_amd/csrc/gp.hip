@@ -5,11 +5,13 @@
 //   factor       C = L L^T (right-looking Cholesky in one workgroup)
 //   weights      alpha = C^-1 y by two triangular solves
 //   prediction   mean = K* alpha (Eq. predMeanEq),
-//                var = sigma_f^2 - |L^-1 k*|^2 (diagonal of Eq. predVarEq)
+//                var = sigma_f^2 - |L^-1 k*|^2 (diagonal of Eq. predVarEq), with
+//                L^-1 formed once per factorisation so that a query is a
+//                parallel product, not a sequential solve
 //   evidence     -1/2 y^T alpha - sum log L_ii - n/2 log 2 pi (Eq. evidenceEq)
 // Database sizes here are hundreds of points: the factorisation and solves
 // are latency bound, so one workgroup walks the columns with barriers while
-// prediction spreads query blocks over the chip.
+// prediction gives each query a workgroup of its own.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,10 +32,10 @@ struct hmd_gp {
   double* dX = nullptr;      // cap x 4, row-major
   double* dy = nullptr;      // scaled outputs
   double* dL = nullptr;      // cap x cap, column-major (leading dimension cap)
+  double* dLi = nullptr;     // L^-1, same layout (lower triangle)
   double* dalpha = nullptr;  // C^-1 y
   double* dtmp = nullptr;    // cap
   double* dq = nullptr;      // query staging
-  double* dV = nullptr;      // query workspace
   double* dout = nullptr;    // predictions / scalars
   int* dinfo = nullptr;
   size_t q_cap = 0;
@@ -43,6 +45,7 @@ namespace hmd {
 namespace {
 
 constexpr int GP_MAXD = 4;
+constexpr int GP_MAXN = 6144;  // database points: k* and the substitution vectors fit one workgroup's LDS
 
 struct KParams {
   double inv_scale[GP_MAXD];
@@ -136,8 +139,6 @@ __global__ __launch_bounds__(1024) void k_gp_solve(int n, int ld, const double* 
   }
 }
 
-// Prediction for a block of QB queries per workgroup: k* columns, mean by a
-// dot product with alpha, variance by a multi-right-hand-side forward solve.
 // Device-pointer interop: queries row-major with d columns -> the padded
 // layout of the predict kernel; results (scaled back to output units) into
 // separate mean and variance arrays.
@@ -155,49 +156,86 @@ __global__ void k_gp_unpack(int m, int have_data, const double* __restrict__ res
   var[q] = (have_data ? res[2 * q + 1] : sf2) * s_q * s_q;
 }
 
-constexpr int QB = 32;
-__global__ __launch_bounds__(256) void k_gp_predict(int n, int ld, int m, const double* __restrict__ X,
-                                                    const double* __restrict__ Xq, const double* __restrict__ L,
+// Column j of L^-1 per workgroup: forward substitution of L x = e_j, whose
+// entries above j are zero. x lives in LDS (dynamic, n doubles); every
+// thread derives the pivot value itself, so one barrier per step suffices.
+__global__ __launch_bounds__(256) void k_gp_tri_inv(int n, int ld, const double* __restrict__ L,
+                                                    double* __restrict__ Li) {
+  extern __shared__ double x[];
+  const int j = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  for (int i = j + tid; i < n; i += nt) x[i] = i == j ? 1.0 : 0.0;
+  for (int k = j; k < n; ++k) {
+    __syncthreads();
+    const double xk = x[k] / L[k + size_t(k) * ld];
+    // the pivot slot is not rewritten in this step, the others only by their owner
+    for (int i = k + 1 + tid; i < n; i += nt) x[i] -= L[i + size_t(k) * ld] * xk;
+    if (tid == 0) Li[k + size_t(j) * ld] = xk;
+  }
+}
+
+// L grew by row r (its leading rows unchanged): row r of L^-1 is
+// -(1 / L_rr) sum_{j<=k<r} L_rk (L^-1)_kj for j < r, and 1 / L_rr on the
+// diagonal. One wavefront per column j; row r of L staged in LDS.
+__global__ __launch_bounds__(256) void k_gp_inv_append_row(int r, int ld, const double* __restrict__ L,
+                                                           double* __restrict__ Li) {
+  extern __shared__ double lr[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int k = tid; k < r; k += blockDim.x) lr[k] = L[r + size_t(k) * ld];
+  __syncthreads();
+  const double inv_d = 1.0 / L[r + size_t(r) * ld];
+  const int j = blockIdx.x * (blockDim.x / 64) + (tid >> 6);
+  if (j > r) return;
+  if (j == r) {
+    if (lane == 0) Li[r + size_t(r) * ld] = inv_d;
+    return;
+  }
+  const double* col = Li + size_t(j) * ld;
+  double t = 0.0;
+  for (int k = j + lane; k < r; k += 64) t += lr[k] * col[k];
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+  if (lane == 0) Li[r + size_t(j) * ld] = -t * inv_d;
+}
+
+// One query per workgroup: k* in LDS (dynamic, n doubles), mean = k* . alpha,
+// variance = sigma_f^2 - |L^-1 k*|^2, both by block reduction.
+__global__ __launch_bounds__(256) void k_gp_predict(int n, int ld, const double* __restrict__ X,
+                                                    const double* __restrict__ Xq, const double* __restrict__ Li,
                                                     const double* __restrict__ alpha, KParams P,
-                                                    double* __restrict__ V, double* __restrict__ out) {
-  __shared__ double red[256];
-  const int q0 = blockIdx.x * QB;
-  const int nq = min(QB, m - q0);
-  double* Vb = V + size_t(blockIdx.x) * QB * size_t(n);  // n x QB, row-major in the query index
-  const int tid = threadIdx.x;
-  for (int t = tid; t < n * QB; t += blockDim.x) {
-    const int i = t / QB, q = t % QB;
-    Vb[t] = q < nq ? sqexp(X + GP_MAXD * i, Xq + GP_MAXD * (q0 + q), P) : 0.0;
+                                                    double* __restrict__ out) {
+  extern __shared__ double ks[];
+  __shared__ double red[2][256];
+  const int q = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  double sm = 0.0, sv = 0.0;
+  for (int i = tid; i < n; i += nt) {
+    const double k = sqexp(X + GP_MAXD * i, Xq + GP_MAXD * q, P);
+    ks[i] = k;
+    sm += k * alpha[i];
   }
   __syncthreads();
-  // mean: one query at a time, block reduction over the database
-  for (int q = 0; q < nq; ++q) {
-    double s = 0.0;
-    for (int i = tid; i < n; i += blockDim.x) s += Vb[i * QB + q] * alpha[i];
-    red[tid] = s;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
+  for (int i = tid; i < n; i += nt) {  // row i of L^-1 k*: column-major reads are coalesced over i
+    double w0 = 0.0, w1 = 0.0;
+    int j = 0;
+    for (; j + 1 <= i; j += 2) {
+      w0 += Li[i + size_t(j) * ld] * ks[j];
+      w1 += Li[i + size_t(j + 1) * ld] * ks[j + 1];
     }
-    if (tid == 0) out[2 * (q0 + q)] = red[0];
-    __syncthreads();
+    if (j == i) w0 += Li[i + size_t(j) * ld] * ks[j];
+    const double w = w0 + w1;
+    sv += w * w;
   }
-  // forward substitution L V = K*^T for all queries of the block
-  for (int k = 0; k < n; ++k) {
-    const double inv = 1.0 / L[k + size_t(k) * ld];
-    if (tid < QB) Vb[k * QB + tid] *= inv;
-    __syncthreads();
-    for (int t = tid; t < (n - k - 1) * QB; t += blockDim.x) {
-      const int i = k + 1 + t / QB, q = t % QB;
-      Vb[i * QB + q] -= L[i + size_t(k) * ld] * Vb[k * QB + q];
+  red[0][tid] = sm;
+  red[1][tid] = sv;
+  __syncthreads();
+  for (int o = nt / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      red[0][tid] += red[0][tid + o];
+      red[1][tid] += red[1][tid + o];
     }
     __syncthreads();
   }
-  if (tid < nq) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += Vb[i * QB + tid] * Vb[i * QB + tid];
-    out[2 * (q0 + tid) + 1] = P.sf2 - s;
+  if (tid == 0) {
+    out[2 * q] = red[0][0];
+    out[2 * q + 1] = P.sf2 - red[1][0];
   }
 }
 
@@ -312,11 +350,12 @@ int reserve(hmd_gp* g, int need) {
   if (need <= g->cap) return HMD_OK;
   int cap = g->cap > 0 ? g->cap : 64;
   while (cap < need) cap *= 2;
-  for (double* p : {g->dX, g->dy, g->dL, g->dalpha, g->dtmp})
+  for (double* p : {g->dX, g->dy, g->dL, g->dLi, g->dalpha, g->dtmp})
     if (p) (void)hipFree(p);
   HMD_HIP(ctx, hipMalloc(&g->dX, sizeof(double) * GP_MAXD * cap));
   HMD_HIP(ctx, hipMalloc(&g->dy, sizeof(double) * cap));
   HMD_HIP(ctx, hipMalloc(&g->dL, sizeof(double) * size_t(cap) * cap));
+  HMD_HIP(ctx, hipMalloc(&g->dLi, sizeof(double) * size_t(cap) * cap));
   HMD_HIP(ctx, hipMalloc(&g->dalpha, sizeof(double) * cap));
   HMD_HIP(ctx, hipMalloc(&g->dtmp, sizeof(double) * (cap + 1)));
   g->cap = cap;
@@ -335,11 +374,19 @@ int upload_db(hmd_gp* g) {
   return HMD_OK;
 }
 
-int solve_alpha(hmd_gp* g) {
+int solve_alpha(hmd_gp* g, bool grown_by_row) {
   hmd_ctx* ctx = g->ctx;
   hipStream_t s = ctx->stream;
   HMD_HIP(ctx, hipMemcpyAsync(g->dalpha, g->dy, 8 * size_t(g->n), hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_gp_solve, dim3(1), dim3(1024), 0, s, g->n, g->cap, g->dL, g->dalpha, 1);
+  HMD_HIP(ctx, hipGetLastError());
+  // L^-1 follows the factor: extended by its new row, or formed anew
+  const size_t lds = sizeof(double) * size_t(g->n);
+  if (grown_by_row)
+    hipLaunchKernelGGL(k_gp_inv_append_row, dim3((g->n + 3) / 4), dim3(256), lds, s, g->n - 1, g->cap, g->dL,
+                       g->dLi);
+  else
+    hipLaunchKernelGGL(k_gp_tri_inv, dim3(g->n), dim3(256), lds, s, g->n, g->cap, g->dL, g->dLi);
   HMD_HIP(ctx, hipGetLastError());
   return HMD_OK;
 }
@@ -363,7 +410,7 @@ int refit(hmd_gp* g) {
     ctx->err = "gp: covariance not positive definite at pivot " + std::to_string(info - 1);
     return HMD_ENOTSPD;
   }
-  return solve_alpha(g);
+  return solve_alpha(g, false);
 }
 
 }  // namespace
@@ -388,8 +435,8 @@ void hmd_gp_hyper_default(hmd_gp_hyper* h) {
 
 int gp_fit(hmd_ctx* ctx, const double* X, const double* y, const double* y_se, int n, int d,
            const hmd_gp_hyper* hyper, hmd_gp** out) {
-  if (!ctx || !out || n < 0 || d < 1 || d > GP_MAXD || (n > 0 && (!X || !y))) {
-    if (ctx) ctx->err = "gp_fit: bad arguments (1 <= d <= 4, n >= 0)";
+  if (!ctx || !out || n < 0 || n > GP_MAXN || d < 1 || d > GP_MAXD || (n > 0 && (!X || !y))) {
+    if (ctx) ctx->err = "gp_fit: bad arguments (1 <= d <= 4, 0 <= n <= 6144)";
     return HMD_EINVAL;
   }
   HMD_HIP(ctx, hipSetDevice(ctx->device));
@@ -426,6 +473,10 @@ int gp_fit(hmd_ctx* ctx, const double* X, const double* y, const double* y_se, i
 int gp_append(hmd_gp* g, const double* x, double y, double y_se) {
   if (!g || !x) return HMD_EINVAL;
   hmd_ctx* ctx = g->ctx;
+  if (g->n >= GP_MAXN) {
+    ctx->err = "gp_append: the database holds at most 6144 points";
+    return HMD_EINVAL;
+  }
   HMD_HIP(ctx, hipSetDevice(ctx->device));
   g->X.insert(g->X.end(), x, x + g->d);
   g->y.push_back(y);
@@ -446,7 +497,7 @@ int gp_append(hmd_gp* g, const double* x, double y, double y_se) {
   HMD_HIP(ctx, hipMemcpyAsync(&info, g->dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
   if (info != 0) return refit(g);
-  rc = solve_alpha(g);
+  rc = solve_alpha(g, true);
   if (rc != HMD_OK) return rc;
   HMD_HIP(ctx, hipStreamSynchronize(s));
   return HMD_OK;
@@ -465,23 +516,21 @@ int gp_predict(hmd_gp* g, const double* Xs, int m, double* mean, double* var) {
     return HMD_OK;
   }
   HMD_HIP(ctx, hipSetDevice(ctx->device));
-  const int nblk = (m + QB - 1) / QB;
-  const size_t need_q = size_t(GP_MAXD) * m, need_v = size_t(nblk) * QB * g->n;
-  if (need_q + need_v + 2 * size_t(m) > g->q_cap) {
+  const size_t need_q = size_t(GP_MAXD) * m;
+  if (need_q + 2 * size_t(m) > g->q_cap) {
     if (g->dq) (void)hipFree(g->dq);
-    g->q_cap = 2 * (need_q + need_v + 2 * size_t(m));
+    g->q_cap = 2 * (need_q + 2 * size_t(m));
     HMD_HIP(ctx, hipMalloc(&g->dq, sizeof(double) * g->q_cap));
   }
   double* dXq = g->dq;
-  double* dV = g->dq + need_q;
-  double* dres = dV + need_v;
+  double* dres = g->dq + need_q;
   std::vector<double> xs(need_q, 0.0), res(2 * size_t(m));
   for (int q = 0; q < m; ++q)
     for (int k = 0; k < g->d; ++k) xs[size_t(q) * GP_MAXD + k] = Xs[size_t(q) * g->d + k];
   hipStream_t s = ctx->stream;
   HMD_HIP(ctx, hipMemcpyAsync(dXq, xs.data(), 8 * xs.size(), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_gp_predict, dim3(nblk), dim3(256), 0, s, g->n, g->cap, m, g->dX, dXq, g->dL, g->dalpha,
-                     kparams(g), dV, dres);
+  hipLaunchKernelGGL(k_gp_predict, dim3(m), dim3(256), sizeof(double) * size_t(g->n), s, g->n, g->cap, g->dX, dXq,
+                     g->dLi, g->dalpha, kparams(g), dres);
   HMD_HIP(ctx, hipGetLastError());
   HMD_HIP(ctx, hipMemcpyAsync(res.data(), dres, 8 * res.size(), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
@@ -499,22 +548,20 @@ int gp_predict_dev(hmd_gp* g, const double* dXs, int m, double* dmean, double* d
   HMD_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
   const double sf2 = g->hyp.sigma_f * g->hyp.sigma_f;
-  const int nblk = (m + QB - 1) / QB;
-  const size_t need_q = size_t(GP_MAXD) * m, need_v = size_t(nblk) * QB * std::max(g->n, 1);
-  if (need_q + need_v + 2 * size_t(m) > g->q_cap) {
+  const size_t need_q = size_t(GP_MAXD) * m;
+  if (need_q + 2 * size_t(m) > g->q_cap) {
     HMD_HIP(ctx, hipStreamSynchronize(s));  // the old scratch may still be read
     if (g->dq) (void)hipFree(g->dq);
-    g->q_cap = 2 * (need_q + need_v + 2 * size_t(m));
+    g->q_cap = 2 * (need_q + 2 * size_t(m));
     HMD_HIP(ctx, hipMalloc(&g->dq, sizeof(double) * g->q_cap));
   }
   double* dXq = g->dq;
-  double* dV = g->dq + need_q;
-  double* dres = dV + need_v;
+  double* dres = g->dq + need_q;
   hipLaunchKernelGGL(k_gp_pack, dim3((m + 255) / 256), dim3(256), 0, s, m, g->d, dXs, dXq);
   HMD_HIP(ctx, hipGetLastError());
   if (g->n > 0) {
-    hipLaunchKernelGGL(k_gp_predict, dim3(nblk), dim3(256), 0, s, g->n, g->cap, m, g->dX, dXq, g->dL, g->dalpha,
-                       kparams(g), dV, dres);
+    hipLaunchKernelGGL(k_gp_predict, dim3(m), dim3(256), sizeof(double) * size_t(g->n), s, g->n, g->cap, g->dX,
+                       dXq, g->dLi, g->dalpha, kparams(g), dres);
     HMD_HIP(ctx, hipGetLastError());
   }
   hipLaunchKernelGGL(k_gp_unpack, dim3((m + 255) / 256), dim3(256), 0, s, m, g->n > 0 ? 1 : 0, dres, g->s_q, sf2,
@@ -553,7 +600,8 @@ int gp_scales(const hmd_gp* g, double* scale, double* s_q, double* sigma_n) {
 
 void gp_free(hmd_gp* g) {
   if (!g) return;
-  for (void* p : {(void*)g->dX, (void*)g->dy, (void*)g->dL, (void*)g->dalpha, (void*)g->dtmp, (void*)g->dq,
+  for (void* p : {(void*)g->dX, (void*)g->dy, (void*)g->dL, (void*)g->dLi, (void*)g->dalpha, (void*)g->dtmp,
+                  (void*)g->dq,
                   (void*)g->dout, (void*)g->dinfo})
     if (p) (void)hipFree(p);
   delete g;

@@ -83,3 +83,24 @@ def test_duplicate_points_without_noise_are_not_spd(ctx):
     with pytest.raises(B.HmdError) as e:
         B.GP(ctx, X, [0.1, 0.1], None, B.gp_hyper(sigma_n=0.0, ranges=RANGES))
     assert e.value.code == B.HMD_ENOTSPD
+
+
+def test_database_size_limit(ctx):
+    X = np.column_stack([np.linspace(4, 20, 6145), np.full(6145, 0.01)])
+    with pytest.raises(B.HmdError) as e:
+        B.GP(ctx, X, np.zeros(6145), None, B.gp_hyper(ranges=RANGES))
+    assert e.value.code == B.HMD_EINVAL
+
+
+def test_long_rank_one_append_chain(ctx):
+    """L^-1 extended row by row over many appends stays equal to a fresh inverse."""
+    X, y, _ = data(300, 11)
+    hp = B.gp_hyper(sigma_n=0.05, scale_mode=1, ranges=RANGES, out_scale=0)
+    g = B.GP(ctx, X[:2], y[:2], None, hp)
+    for k in range(2, 300):
+        g.append(X[k], y[k], 0.0)
+    full = B.GP(ctx, X, y, None, hp)
+    Xs, _, _ = data(64, 12)
+    a, b = g.predict(Xs), full.predict(Xs)
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-9, atol=1e-12)
