@@ -17,6 +17,7 @@
 // Step n (1-based) is identified as base + k with base read from device
 // memory (graph replays) or zero (direct launches).
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "engine.h"
 #include "md_kernels.h"
@@ -1131,26 +1132,41 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     const int cy = r0 % D.ny, cx = (r0 / D.ny) % D.nx, cz = r0 / (D.ny * D.nx);
     uint32_t cnt = 0;
     // entry c of slot i: 16-bit at ((c / 8) ld + i) 8 + c % 8 (LDS index),
-    // 32-bit at ((c / 4) ld + i) 4 + c % 4 (position index).  The 16-bit
-    // store takes a 32-bit byte offset (the list is below 4 GiB) and a count
-    // clamped to the capacity (an overflowing list is reported below and
-    // never used), so a hit costs no 64-bit arithmetic and no capacity test.
+    // 32-bit at ((c / 4) ld + i) 4 + c % 4 (position index).  16-bit entries
+    // gather in a register group (g0..g3, shifted down one entry per hit, the
+    // newest on top) that goes out as one 16-byte store when it holds eight:
+    // the lanes of a wave then write whole, adjacent groups instead of one
+    // scattered 16-bit store per hit.  Byte offsets are 32-bit (the list is
+    // below 4 GiB); the group index is clamped to cap / 8, a spill group in
+    // the half of the capacity that 16-bit entries leave unused (an
+    // overflowing list is reported below and never used).
     char* const list_b = reinterpret_cast<char*>(list);
-    const uint32_t capm1 = uint32_t(cap) - 1u;
+    uint32_t g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+    auto push16 = [&](uint32_t k) {
+      g0 = __builtin_amdgcn_alignbit(g1, g0, 16);
+      g1 = __builtin_amdgcn_alignbit(g2, g1, 16);
+      g2 = __builtin_amdgcn_alignbit(g3, g2, 16);
+      g3 = __builtin_amdgcn_alignbit(k, g3, 16);
+    };
+    auto store_group = [&](uint32_t g) {
+      g = min(g, uint32_t(cap) >> 3);
+      *reinterpret_cast<uint4*>(list_b + ((__umul24(g, uint32_t(ld)) + i) << 4)) = make_uint4(g0, g1, g2, g3);
+    };
     auto put16 = [&](bool hit, uint32_t k) {
       if (hit) {
-        const uint32_t c = min(cnt, capm1);
-        const uint32_t off = ((__umul24(c >> 3, uint32_t(ld)) + i) << 4) + ((c & 7u) << 1);
-        *reinterpret_cast<uint16_t*>(list_b + off) = uint16_t(k);
+        push16(k);
+        ++cnt;
+        if ((cnt & 7u) == 0u) store_group((cnt - 1u) >> 3);
       }
-      cnt += hit ? 1u : 0u;
     };
     auto put32 = [&](bool hit, uint32_t q) {
       if (hit && cnt < uint32_t(cap)) list[(size_t(cnt >> 2) * ld + i) * 4 + (cnt & 3u)] = q;
       cnt += hit ? 1u : 0u;
     };
-    // candidates k in [a, b) of the LDS arrays, four LDS reads in flight
-    auto screen = [&](uint32_t a, uint32_t b, uint32_t myk) {
+    // candidates k in [a, b) of the LDS arrays, four LDS reads in flight;
+    // only the atom's own cell (SELF) holds the atom itself
+    auto screen = [&](auto self_cell, uint32_t a, uint32_t b, uint32_t myk) {
+      constexpr bool SELF = decltype(self_cell)::value;
       uint32_t k = a;
       if (rel) {
         for (; k + 4 <= b; k += 4) {
@@ -1158,18 +1174,18 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
 #pragma unroll
           for (int u = 0; u < 4; ++u) r2[u] = sep2r(lx[k + u], ly[k + u], lz[k + u]);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) put16(r2[u] < rl2r && k + u != myk, k + u);
+          for (int u = 0; u < 4; ++u) put16(r2[u] < rl2r && (!SELF || k + u != myk), k + u);
         }
-        for (; k < b; ++k) put16(sep2r(lx[k], ly[k], lz[k]) < rl2r && k != myk, k);
+        for (; k < b; ++k) put16(sep2r(lx[k], ly[k], lz[k]) < rl2r && (!SELF || k != myk), k);
       } else {
         for (; k + 4 <= b; k += 4) {
           float r2[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) r2[u] = sep2(lx[k + u], ly[k + u], lz[k + u]);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) put16(r2[u] < rl2u && k + u != myk, k + u);
+          for (int u = 0; u < 4; ++u) put16(r2[u] < rl2u && (!SELF || k + u != myk), k + u);
         }
-        for (; k < b; ++k) put16(sep2(lx[k], ly[k], lz[k]) < rl2u && k != myk, k);
+        for (; k < b; ++k) put16(sep2(lx[k], ly[k], lz[k]) < rl2u && (!SELF || k != myk), k);
       }
     };
     if (use_tab) {
@@ -1187,7 +1203,10 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
           const uint32_t* row = ctab + (dz * ncolx + jx) * nyt + cy;  // y offsets -1, 0, 1 -> row[0..2]
           for (int dy = 0; dy < 3; ++dy) {
             const uint32_t w = row[dy];
-            screen(w >> 8, (w >> 8) + (w & 255u), myk);
+            if (dz == 1 && dx == 0 && dy == 1)
+              screen(std::true_type{}, w >> 8, (w >> 8) + (w & 255u), myk);
+            else
+              screen(std::false_type{}, w >> 8, (w >> 8) + (w & 255u), myk);
           }
         }
     } else
@@ -1244,8 +1263,12 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     // staged atoms, which the force kernels place half a box away in z (more
     // than r_c from every atom of the slab): the force loop then needs no
     // partial last group
-    if (local && D.nz >= 4)
+    if (local && D.nz >= 4) {
       while (cnt & 7u) put16(true, total);
+    } else if (local && (cnt & 7u)) {  // the partial last group, moved down to entry 0
+      for (uint32_t e = cnt & 7u; e < 8u; ++e) push16(0u);
+      store_group(cnt >> 3);
+    }
     if (cnt > uint32_t(cap)) {
       atomicMax(&overflow[0], int(cnt));
       cnt = cap;
