@@ -955,33 +955,61 @@ __device__ __forceinline__ void tile_ranges(const int4& tile, int ntot, const Si
   __syncthreads();
 }
 
-// Copies the tile's ranges into LDS (structure of arrays; caller checks the
-// capacity first).  One flat pass over every staged entry, each thread with
-// four loads in flight: range by range, each short range would cost a whole
-// memory latency of its own.
-__device__ __forceinline__ void tile_stage(const TileStage& T, const int4* __restrict__ pfix, int* lx, int* ly,
-                                           int* lz) {
+// Copies the tile's ranges into LDS in one flat pass over every staged
+// entry, each thread with four loads in flight (range by range, each short
+// range would cost a whole memory latency of its own); put(e, p) stores
+// entry e.  The range of entry e is the r with off[r] <= e < off[r + 1] (an
+// empty range shares its start with the next; the last such r is taken).  A
+// wavefront handles 64 consecutive entries at a time, so a ballot over the
+// lanes that hold the range starts counts the starts at or before its first
+// entry, and only the few starts inside those 64 are compared lane by lane.
+// All threads of the block call it (the ballots need whole wavefronts).
+template <class Put>
+__device__ __forceinline__ void tile_stage_core(const TileStage& T, const int4* __restrict__ pfix, Put put) {
   constexpr int U = 4;
   const uint32_t total = T.off[TILE_RUNS];
-  for (uint32_t e0 = threadIdx.x; e0 < total; e0 += U * blockDim.x) {
+  const uint32_t lane = threadIdx.x & (WAVE - 1);
+  const uint32_t start_q = (lane >= 1 && lane < uint32_t(TILE_RUNS)) ? T.off[lane] : 0xffffffffu;
+  // source of the last entry, read in place of entries past the end so that
+  // every load is issued unconditionally and in bounds
+  const int r_last = __popcll(__ballot(start_q < total));
+  const uint32_t last_src = total ? T.gb[r_last] + (total - 1u - T.off[r_last]) : 0u;
+  for (uint32_t w0 = threadIdx.x - lane; w0 < total; w0 += U * blockDim.x) {  // uniform per wavefront
+    uint32_t src[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t ew = w0 + u * blockDim.x, e = ew + lane;
+      int r = __popcll(__ballot(start_q <= ew));
+      unsigned long long m = __ballot(start_q > ew && start_q < ew + WAVE);
+      while (m) {
+        const int q = __builtin_ctzll(m);
+        m &= m - 1ull;
+        r += e >= uint32_t(__builtin_amdgcn_readlane(int(start_q), q)) ? 1 : 0;
+      }
+      src[u] = T.gb[r] + (e - T.off[r]);
+    }
+    // the loads go out together
     int4 p[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t e = e0 + u * blockDim.x;
-      if (e < total) {
-        int r = 0;  // the range holding entry e (empty ranges share their start with the next)
-#pragma unroll
-        for (int q = 1; q < TILE_RUNS; ++q) r += e >= T.off[q] ? 1 : 0;
-        p[u] = pfix[T.gb[r] + (e - T.off[r])];
-      }
+      const uint32_t e = w0 + u * blockDim.x + lane;
+      p[u] = pfix[e < total ? src[u] : last_src];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t e = e0 + u * blockDim.x;
-      if (e < total) { lx[e] = p[u].x; ly[e] = p[u].y; lz[e] = p[u].z; }
+      const uint32_t e = w0 + u * blockDim.x + lane;
+      if (e < total) put(e, p[u]);
     }
   }
   __syncthreads();
+}
+
+// Fixed-point copy (structure of arrays; the caller checks the capacity).
+__device__ __forceinline__ void tile_stage(const TileStage& T, const int4* __restrict__ pfix, int* lx, int* ly,
+                                           int* lz) {
+  tile_stage_core(T, pfix, [&](uint32_t e, const int4& q) {
+    lx[e] = q.x; ly[e] = q.y; lz[e] = q.z;
+  });
 }
 
 // The same copy as FP32 offsets from a tile origin o (fixed-point units
@@ -990,31 +1018,11 @@ __device__ __forceinline__ void tile_stage(const TileStage& T, const int4* __res
 // and its FP32 rounding (2^-24 relative) is far below the screening margin.
 __device__ __forceinline__ void tile_stage_rel(const TileStage& T, const int4* __restrict__ pfix, int* lx, int* ly,
                                                int* lz, const int4& o, const float3& sc) {
-  constexpr int U = 4;
-  const uint32_t total = T.off[TILE_RUNS];
-  for (uint32_t e0 = threadIdx.x; e0 < total; e0 += U * blockDim.x) {
-    int4 p[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t e = e0 + u * blockDim.x;
-      if (e < total) {
-        int r = 0;
-#pragma unroll
-        for (int q = 1; q < TILE_RUNS; ++q) r += e >= T.off[q] ? 1 : 0;
-        p[u] = pfix[T.gb[r] + (e - T.off[r])];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t e = e0 + u * blockDim.x;
-      if (e < total) {
-        lx[e] = __float_as_int(float(int(uint32_t(p[u].x) - uint32_t(o.x))) * sc.x);
-        ly[e] = __float_as_int(float(int(uint32_t(p[u].y) - uint32_t(o.y))) * sc.y);
-        lz[e] = __float_as_int(float(int(uint32_t(p[u].z) - uint32_t(o.z))) * sc.z);
-      }
-    }
-  }
-  __syncthreads();
+  tile_stage_core(T, pfix, [&](uint32_t e, const int4& q) {
+    lx[e] = __float_as_int(float(int(uint32_t(q.x) - uint32_t(o.x))) * sc.x);
+    ly[e] = __float_as_int(float(int(uint32_t(q.y) - uint32_t(o.y))) * sc.y);
+    lz[e] = __float_as_int(float(int(uint32_t(q.z) - uint32_t(o.z))) * sc.z);
+  });
 }
 
 // Range table of a tile as the last list build left it (the cell ranges only
