@@ -486,7 +486,15 @@ int gp_append(hmd_gp* g, const double* x, double y, double y_se) {
   // row; otherwise the normalisation moved and the factor is rebuilt
   const bool rank1 = g->hyp.scale_mode == 1 && g->hyp.out_scale == 0 && g->hyp.sigma_n >= 0.0 && g->n >= 2 &&
                      g->n <= g->cap;
-  if (!rank1) return refit(g);
+  // returns with the factor, weights and L^-1 complete, so that a following
+  // prediction on any stream sees them
+  auto full_refit = [&]() -> int {
+    const int r = refit(g);
+    if (r != HMD_OK) return r;
+    HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return HMD_OK;
+  };
+  if (!rank1) return full_refit();
   normalise(g);
   int rc = upload_db(g);
   if (rc != HMD_OK) return rc;
@@ -496,7 +504,7 @@ int gp_append(hmd_gp* g, const double* x, double y, double y_se) {
   int info = 0;
   HMD_HIP(ctx, hipMemcpyAsync(&info, g->dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
-  if (info != 0) return refit(g);
+  if (info != 0) return full_refit();
   rc = solve_alpha(g, true);
   if (rc != HMD_OK) return rc;
   HMD_HIP(ctx, hipStreamSynchronize(s));
