@@ -292,7 +292,9 @@ def main():
     ap.add_argument("--train-points", type=int, default=256)
     ap.add_argument("--taus", type=lambda t: [float(x) for x in t.split(",")], default=[0.05],
                     help="relative uncertainty thresholds of the hybrid runs, comma separated")
-    ap.add_argument("--audit-every", type=int, default=1000)
+    ap.add_argument("--audit-every", type=int, default=1009,
+                    help="audit every k-th surrogate answer; a k coprime with the 200 sections makes successive "
+                         "audits visit different sections (k = 1000 audits one section only)")
     ap.add_argument("--hybrid-steps", type=int, default=HY_STEPS)
     ap.add_argument("--refit-every", type=int, default=1, help="ensemble retrains after this many new MD points")
     ap.add_argument("--all-md-steps", type=int, default=1, help="macro steps run all-MD to price the all-MD march")

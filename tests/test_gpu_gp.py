@@ -104,3 +104,18 @@ def test_long_rank_one_append_chain(ctx):
     a, b = g.predict(Xs), full.predict(Xs)
     np.testing.assert_allclose(a[0], b[0], rtol=1e-9, atol=1e-12)
     np.testing.assert_allclose(a[1], b[1], rtol=1e-9, atol=1e-12)
+
+
+def test_large_database_matches_oracle(ctx):
+    """2050 points (a ragged tail on every 256-thread loop and 32 x 32 tile),
+    fixed scales and noise so the covariance stays well conditioned."""
+    X, y, _ = data(2050, 21)
+    hp = B.gp_hyper(sigma_n=0.05, scale_mode=1, ranges=RANGES, out_scale=0)
+    g = B.GP(ctx, X, y, None, hp)
+    o = OGP(X, y, None, Hyper(sigma_n=0.05, scale_mode=1, ranges=RANGES, out_scale=0))
+    Xs, _, _ = data(300, 22)
+    mg, vg = g.predict(Xs)
+    mo, vo = o.predict(Xs)
+    assert np.abs(mg - mo).max() <= 1e-9 * np.abs(mo).max() + 1e-12
+    assert np.abs(vg - vo).max() <= 1e-9
+    assert g.log_marginal() == pytest.approx(o.log_marginal(), rel=1e-9, abs=1e-9)
