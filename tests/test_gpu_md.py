@@ -305,3 +305,26 @@ def test_full_batch_forces_match_oracle():
         assert np.all(np.isfinite(f))
         assert _rel_rms(f, fo) <= 1e-5, sim
         assert pe == pytest.approx(peo, rel=1e-5)
+
+
+def test_full_batch_sampled_outputs_hold_invariants():
+    # the 64-channel batch (2,115,470 atoms, default path and skin) through
+    # md_flux_batch with a shortened protocol: every channel finishes, the
+    # thermostatted component holds T0, the flux follows the body force
+    # (never significantly against it, clearly with it where g h^3 is
+    # largest), and J is the flux per unit height
+    params = dict(n_equil=1000, **workloads.batch_box())
+    ctx = hmd.Context(hmd.Params(skin=0.35, **params))
+    jobs = workloads.batch_jobs(64)
+    res = hmd.md_flux_batch(ctx, [(j.h, j.g, j.seed, 2000) for j in jobs])
+    assert sum(r["n_fluid"] for r in res) == 2115470
+    drive = np.array([j.g * j.h ** 3 for j in jobs])
+    strong = set(np.argsort(drive)[-16:].tolist())
+    for k, (j, r) in enumerate(zip(jobs, res)):
+        assert r["status"] == 0, k
+        assert r["T"][1] == pytest.approx(1.0, abs=0.02), k
+        assert np.isfinite(r["flux"]) and r["flux_se"] > 0.0, k
+        assert r["flux"] > -4.0 * r["flux_se"], k
+        if k in strong:
+            assert r["flux"] > 3.0 * r["flux_se"], k
+        assert r["jflux"] == pytest.approx(r["flux"] / j.h, rel=1e-12), k
