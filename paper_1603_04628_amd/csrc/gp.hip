@@ -2,15 +2,16 @@
 // (paper Sec. 2.2-2.3):
 //   covariance   C = sigma_f^2 exp(-d^2 / 2 l^2) + sigma_n^2 I
 //                (Eqs. quadraticKernelEq, d2Eq, covarianceEq)
-//   factor       C = L L^T (right-looking Cholesky in one workgroup)
+//   factor       C = L L^T (blocked right-looking Cholesky, panels of 32)
 //   weights      alpha = C^-1 y by two triangular solves
 //   prediction   mean = K* alpha (Eq. predMeanEq),
 //                var = sigma_f^2 - |L^-1 k*|^2 (diagonal of Eq. predVarEq), with
 //                L^-1 formed once per factorisation so that a query is a
 //                parallel product, not a sequential solve
 //   evidence     -1/2 y^T alpha - sum log L_ii - n/2 log 2 pi (Eq. evidenceEq)
-// Database sizes here are hundreds of points: the factorisation and solves
-// are latency bound, so one workgroup walks the columns with barriers while
+// Database sizes here are hundreds of points: the triangular solves are
+// latency bound, so one workgroup walks the columns with barriers; the
+// factorisation spreads each panel's update over many workgroups, and
 // prediction gives each query a workgroup of its own.
 #include <hip/hip_runtime.h>
 
@@ -72,44 +73,104 @@ __global__ void k_gp_cov(int n, int ld, const double* __restrict__ X, KParams P,
   L[i + size_t(j) * ld] = c;
 }
 
-// In-place right-looking Cholesky of the lower triangle, one workgroup.
-// info = 0 on success, k + 1 if the k-th pivot is not positive.
-__global__ __launch_bounds__(1024) void k_gp_chol(int n, int ld, double* __restrict__ A, int* __restrict__ info,
-                                                  int k0) {
-  __shared__ double piv;
+// In-place blocked right-looking Cholesky of the lower triangle, panels of
+// CB columns, three launches per panel: the diagonal block factored in LDS
+// by one workgroup, the rows below it solved against it (one row per
+// thread), and the trailing lower triangle updated in CB x CB tiles.
+// info = 0 on success, k + 1 if the k-th pivot is not positive; once set,
+// the remaining launches return at once.
+constexpr int CB = 32;
+
+__global__ __launch_bounds__(256) void k_chol_diag(int n, int ld, double* __restrict__ A, int* __restrict__ info,
+                                                   int k0) {
+  __shared__ double a[CB][CB + 1];
   __shared__ int bad;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, kb = min(CB, n - k0);
+  if (k0 > 0 && *info != 0) return;  // an earlier pivot failed (uniform)
   if (tid == 0) bad = 0;
+  for (int e = tid; e < kb * kb; e += blockDim.x) {
+    const int r = e / kb, c = e % kb;
+    a[r][c] = r >= c ? A[(k0 + r) + size_t(k0 + c) * ld] : 0.0;
+  }
   __syncthreads();
-  for (int k = k0; k < n; ++k) {
+  for (int c = 0; c < kb; ++c) {
     if (tid == 0) {
-      const double a = A[k + size_t(k) * ld];
-      if (!(a > 0.0)) {
-        bad = k + 1;
-        piv = 1.0;
-      } else {
-        piv = sqrt(a);
-        A[k + size_t(k) * ld] = piv;
-      }
+      const double d = a[c][c];
+      if (!(d > 0.0)) bad = k0 + c + 1;
+      else a[c][c] = sqrt(d);
     }
     __syncthreads();
     if (bad) break;
-    const double inv = 1.0 / piv;
-    for (int i = k + 1 + tid; i < n; i += nt) A[i + size_t(k) * ld] *= inv;
+    if (tid > c && tid < kb) a[tid][c] /= a[c][c];
     __syncthreads();
-    // trailing update of the lower triangle in 32 x 32 tiles
-    const int tx = tid & 31, ty = tid >> 5;
-    for (int jj = k + 1; jj < n; jj += 32) {
-      const int j = jj + ty;
-      const double ljk = j < n ? A[j + size_t(k) * ld] : 0.0;
-      for (int ii = jj; ii < n; ii += 32) {
-        const int i = ii + tx;
-        if (i < n && j < n && i >= j) A[i + size_t(j) * ld] -= A[i + size_t(k) * ld] * ljk;
-      }
+    for (int e = tid; e < kb * kb; e += blockDim.x) {
+      const int r = e / kb, q = e % kb;
+      if (q > c && r >= q) a[r][q] -= a[r][c] * a[q][c];
     }
     __syncthreads();
   }
+  for (int e = tid; e < kb * kb; e += blockDim.x) {
+    const int r = e / kb, c = e % kb;
+    if (r >= c) A[(k0 + r) + size_t(k0 + c) * ld] = a[r][c];
+  }
   if (tid == 0) *info = bad;
+}
+
+// Rows k0 + kb .. n - 1 of the panel: x L_kk^T = a, by forward substitution
+// along the row.
+__global__ __launch_bounds__(256) void k_chol_panel(int n, int ld, double* __restrict__ A,
+                                                    const int* __restrict__ info, int k0) {
+  __shared__ double l[CB][CB + 1];
+  if (*info != 0) return;
+  const int tid = threadIdx.x, kb = CB;  // a panel with rows below it is full width
+  for (int e = tid; e < kb * kb; e += blockDim.x) {
+    const int r = e / kb, c = e % kb;
+    l[r][c] = r >= c ? A[(k0 + r) + size_t(k0 + c) * ld] : 0.0;
+  }
+  __syncthreads();
+  const int i = k0 + kb + blockIdx.x * blockDim.x + tid;
+  if (i >= n) return;
+  double x[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    double t = A[i + size_t(k0 + c) * ld];
+#pragma unroll
+    for (int m = 0; m < c; ++m) t -= x[m] * l[c][m];
+    x[c] = t / l[c][c];
+    A[i + size_t(k0 + c) * ld] = x[c];
+  }
+}
+
+// Trailing update A_ij -= sum_c P_ic P_jc over the lower triangle from row
+// and column k0 + CB on, one CB x CB tile per workgroup (tiles numbered row
+// by row over the lower triangle of tiles).
+__global__ __launch_bounds__(256) void k_chol_update(int n, int ld, double* __restrict__ A,
+                                                     const int* __restrict__ info, int k0) {
+  __shared__ double pi[CB][CB + 1], pj[CB][CB + 1];
+  if (*info != 0) return;
+  const int t0 = k0 + CB, b = blockIdx.x;
+  int ti = int((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+  while (ti * (ti + 1) / 2 > b) --ti;
+  const int tj = b - ti * (ti + 1) / 2;
+  const int i0 = t0 + ti * CB, j0 = t0 + tj * CB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    const int r = e % CB, c = e / CB;
+    pi[r][c] = i0 + r < n ? A[(i0 + r) + size_t(k0 + c) * ld] : 0.0;
+    pj[r][c] = j0 + r < n ? A[(j0 + r) + size_t(k0 + c) * ld] : 0.0;
+  }
+  __syncthreads();
+  const int r = tid % CB;
+  for (int q = tid / CB; q < CB; q += blockDim.x / CB) {
+    const int i = i0 + r, j = j0 + q;
+    if (i < n && j <= i) {
+      double t = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < CB; ++c) t += pi[r][c] * pj[q][c];
+      A[i + size_t(j) * ld] -= t;
+    }
+  }
 }
 
 // x = L^-1 b (lower) then, if `both`, x = L^-T x: column-oriented
@@ -402,7 +463,17 @@ int refit(hmd_gp* g) {
   hipStream_t s = ctx->stream;
   const KParams P = kparams(g);
   hipLaunchKernelGGL(k_gp_cov, dim3((g->n + 255) / 256, g->n), dim3(256), 0, s, g->n, g->cap, g->dX, P, g->dL);
-  hipLaunchKernelGGL(k_gp_chol, dim3(1), dim3(1024), 0, s, g->n, g->cap, g->dL, g->dinfo, 0);
+  for (int k0 = 0; k0 < g->n; k0 += CB) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, g->n, g->cap, g->dL, g->dinfo, k0);
+    const int rest = g->n - k0 - CB;
+    if (rest > 0) {
+      const int nt = (rest + CB - 1) / CB;
+      hipLaunchKernelGGL(k_chol_panel, dim3((rest + 255) / 256), dim3(256), 0, s, g->n, g->cap, g->dL, g->dinfo, k0);
+      hipLaunchKernelGGL(k_chol_update, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, g->n, g->cap, g->dL, g->dinfo,
+                         k0);
+    }
+  }
+  HMD_HIP(ctx, hipGetLastError());
   int info = 0;
   HMD_HIP(ctx, hipMemcpyAsync(&info, g->dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
