@@ -119,3 +119,18 @@ def test_large_database_matches_oracle(ctx):
     assert np.abs(mg - mo).max() <= 1e-9 * np.abs(mo).max() + 1e-12
     assert np.abs(vg - vo).max() <= 1e-9
     assert g.log_marginal() == pytest.approx(o.log_marginal(), rel=1e-9, abs=1e-9)
+
+
+def test_database_at_the_size_limit_matches_oracle(ctx):
+    """6144 points, the largest database the device GP takes; noise 0.2 keeps
+    cond(C) below 1 + n / 0.2^2 ~ 1.5e5."""
+    X, y, _ = data(6144, 23)
+    hp = B.gp_hyper(sigma_n=0.2, scale_mode=1, ranges=RANGES, out_scale=0)
+    g = B.GP(ctx, X, y, None, hp)
+    assert len(g) == 6144
+    o = OGP(X, y, None, Hyper(sigma_n=0.2, scale_mode=1, ranges=RANGES, out_scale=0))
+    Xs, _, _ = data(64, 24)
+    mg, vg = g.predict(Xs)
+    mo, vo = o.predict(Xs)
+    assert np.abs(mg - mo).max() <= 1e-9 * np.abs(mo).max() + 1e-12
+    assert np.abs(vg - vo).max() <= 1e-9
