@@ -1045,7 +1045,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
     int* __restrict__ tag_to, int* __restrict__ overflow, const int* __restrict__ flag, StepRef R, float rl2,
     int global_out) {
   if (!rebuild_needed(flag, R)) return;
-  __shared__ int lx[TILE_STAGE], ly[TILE_STAGE], lz[TILE_STAGE];
+  __shared__ int lx[TILE_STAGE + 4], ly[TILE_STAGE + 4], lz[TILE_STAGE + 4];
   __shared__ TileStage T;
   // LDS index of each neighbourhood cell's first atom (<< 8) and its count,
   // by (slab, column offset, y + 1): the candidate loop then reads no cell
@@ -1177,14 +1177,15 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
       constexpr bool SELF = decltype(self_cell)::value;
       uint32_t k = a;
       if (rel) {
-        for (; k + 4 <= b; k += 4) {
+        // whole blocks of four, the last one masked (its reads past b stay
+        // inside the arrays, which hold four spare slots): no remainder loop
+        for (; k < b; k += 4) {
           float r2[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) r2[u] = sep2r(lx[k + u], ly[k + u], lz[k + u]);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) put16(r2[u] < rl2r && (!SELF || k + u != myk), k + u);
+          for (int u = 0; u < 4; ++u) put16(r2[u] < rl2r && k + u < b && (!SELF || k + u != myk), k + u);
         }
-        for (; k < b; ++k) put16(sep2r(lx[k], ly[k], lz[k]) < rl2r && (!SELF || k != myk), k);
       } else {
         for (; k + 4 <= b; k += 4) {
           float r2[4];
