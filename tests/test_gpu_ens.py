@@ -27,7 +27,7 @@ def _oracle_scaled(X, y):
     return (X - mu) / sd, y / np.sqrt(np.mean(y ** 2))
 
 
-@pytest.mark.parametrize("n,hidden", [(256, 64), (37, 64), (100, 16)])
+@pytest.mark.parametrize("n,hidden", [(256, 64), (37, 64), (100, 16), (2, 64), (1001, 64), (50, 1)])
 def test_initial_parameters_and_gradients(ctx, n, hidden):
     X, y = data(n, n)
     cfg = B.ens_cfg(members=3, hidden=hidden, iters=1)
