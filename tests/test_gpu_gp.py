@@ -134,3 +134,15 @@ def test_database_at_the_size_limit_matches_oracle(ctx):
     mo, vo = o.predict(Xs)
     assert np.abs(mg - mo).max() <= 1e-9 * np.abs(mo).max() + 1e-12
     assert np.abs(vg - vo).max() <= 1e-9
+
+
+def test_many_queries_match_oracle(ctx):
+    """4097 queries (one workgroup each, a ragged count) on a 256-point database."""
+    X, y, se = data(256, 31)
+    g = B.GP(ctx, X, y, se, B.gp_hyper(ranges=RANGES))
+    o = OGP(X, y, se, Hyper(ranges=RANGES))
+    Xs, _, _ = data(4097, 32)
+    mg, vg = g.predict(Xs)
+    mo, vo = o.predict(Xs)
+    assert np.abs(mg - mo).max() <= 1e-9 * np.abs(mo).max() + 1e-12
+    assert np.abs(vg - vo).max() <= 1e-9 * o.s_q ** 2
