@@ -99,3 +99,44 @@ def test_deferred_audits_score_like_immediate_ones():
         out.append((st["audited"], st["audit_pass"], st["md_calls"], hy.get()["rho"]))
     assert out[0][:3] == out[1][:3] and out[0][0] >= 2
     np.testing.assert_array_equal(out[0][3], out[1][3])
+
+
+def test_full_size_march_matches_oracle():
+    # the benchmark's channel (200 sections over 2000 sigma, inlet pressure
+    # oscillating by 10% with a period of 250 steps, mean drop set for
+    # g = 0.038 at the throat, steady lubrication start, macro step from the
+    # explicit diffusion limit), the known law as micro-solver and a sparse
+    # 36-point starting database (so that the fallback and the database
+    # growth run too): both marches agree step by step, and the mass changes
+    # only by the boundary fluxes
+    n, L, h0, amp = 200, 2000.0, 10.0, 0.5
+    ds = L / n
+    s = (np.arange(n) + 0.5) * ds
+    h = h0 * (1.0 + amp * np.cos(2.0 * np.pi * s / L))
+    w = h ** -3
+    C = 0.038 * 5.0 ** 3
+    dp = C * 0.8 * w.sum() * ds
+    g0 = C * w
+    rho0 = 0.8 + (dp - 0.8 * (np.cumsum(g0) - 0.5 * g0) * ds) / 200.0
+    dt = 0.4 * ds * ds / float(np.max(200.0 * law(h, 1.0)[0] / (0.8 * h)))
+    cfg = dict(n_sections=n, h0=h0, amp=amp, L=L, dt_macro=dt, rho_ref=0.8, p_out=0.0, dp_mean=dp, dp_amp=0.1,
+               period=250.0, c2=200.0, tau_rel=0.05, tau_abs=0.0, audit_every=1009)
+    hh, gg = np.meshgrid(np.linspace(4.0, 20.0, 6), np.linspace(0.001, 0.05, 6))
+    X0 = np.column_stack([hh.ravel(), gg.ravel()])
+    y0, se0 = law(X0[:, 0], X0[:, 1])
+    ctx = hmd.Context()
+    g = B.GP(ctx, X0, y0, se0, B.gp_hyper(ranges=(16.0, 0.049)))
+    hy = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=0, **cfg), gp=g, micro=law)
+    hy.set_rho(rho0)
+    oh = OHybrid(OCfg(**cfg), OGP(X0, y0, se0, Hyper(ranges=(16.0, 0.049))), law, rho0=rho0)
+    for step in range(40):
+        m0 = oh.mass()
+        st = hy.step()
+        oh.step()
+        r = hy.get()
+        assert np.array_equal(r["from_md"], oh.from_md), step
+        np.testing.assert_allclose(r["rho"], oh.rho, rtol=1e-11)
+        np.testing.assert_allclose(r["q"], oh.q, rtol=1e-8, atol=1e-12)
+        assert oh.mass() == pytest.approx(m0 - dt * (oh.q[-1] - oh.q[0]), rel=1e-12)
+    assert st["md_calls"] == oh.md_calls and st["audited"] == oh.audited and st["audit_pass"] == oh.audit_pass
+    assert oh.md_calls > 0 and len(g) == 36 + oh.md_calls
