@@ -309,14 +309,16 @@ def test_full_batch_forces_match_oracle():
 
 def test_full_batch_sampled_outputs_hold_invariants():
     # the 64-channel batch (2,115,470 atoms, default path and skin) through
-    # md_flux_batch with a shortened protocol: every channel finishes, the
+    # md_flux_batch with the benchmark's protocol (10k + 20k steps; a shorter
+    # one leaves the widest channels' start-up flow unsettled, which the
+    # library rightly reports as not stationary): every channel finishes, the
     # thermostatted component holds T0, the flux follows the body force
     # (never significantly against it, clearly with it where g h^3 is
     # largest), and J is the flux per unit height
-    params = dict(n_equil=1000, **workloads.batch_box())
+    params = dict(n_equil=10000, **workloads.batch_box())
     ctx = hmd.Context(hmd.Params(skin=0.35, **params))
     jobs = workloads.batch_jobs(64)
-    res = hmd.md_flux_batch(ctx, [(j.h, j.g, j.seed, 2000) for j in jobs])
+    res = hmd.md_flux_batch(ctx, [(j.h, j.g, j.seed, 20000) for j in jobs])
     assert sum(r["n_fluid"] for r in res) == 2115470
     drive = np.array([j.g * j.h ** 3 for j in jobs])
     strong = set(np.argsort(drive)[-16:].tolist())
