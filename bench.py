@@ -282,6 +282,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=100)
     ap.add_argument("--timed-tail", type=int, default=200)
+    ap.add_argument("--timed-head", type=int, default=200,
+                    help="timed steps run first as direct launches with per-kernel events (the tail's twin early in "
+                         "the run, so that per-kernel averages cover equilibrating and sampling steps)")
     ap.add_argument("--plain-sims", type=int, default=4)
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -337,22 +340,40 @@ def main():
     ff, wf = batch.pair_count()
     pairs_per_launch = ff + wf
     batch.run(args.warmup, graph_chunk=args.chunk)
-    batch.set_timing(True)
-    # the last `tail` steps of the timed region run as direct launches with
-    # HIP events around every kernel (per-kernel averages); the rest replays
-    # the captured graph, timed as a whole
+    # the first `head` and the last `tail` steps of the timed region run as
+    # direct launches with HIP events around every kernel; the rest replays
+    # the captured graph, timed as a whole.  Per-kernel averages weight the
+    # two windows by the equilibrating and sampling steps of the timed region
+    # (the sampled steps add the profile and flux work to the force kernel).
     tail = min(args.timed_tail, args.steps)
+    head = min(args.timed_head, args.steps - tail)
+    names = ("integrate", "keys", "scan", "scatter", "reorder", "list", "force")
     builds0 = batch.list_builds()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    batch.run(args.steps - tail, graph_chunk=args.chunk)
+    batch.set_timing(True)
+    batch.run(head, graph_chunk=0)
+    k_head = {k: batch.kernel_ms(k)[0] for k in names}
+    batch.set_timing(True)
+    batch.run(args.steps - tail - head, graph_chunk=args.chunk)
     batch.run(tail, graph_chunk=0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
     value = batch.atoms * args.steps / wall
-    kern = {k: batch.kernel_ms(k)[0]
-            for k in ("integrate", "keys", "scan", "scatter", "reorder", "list", "force", "graph_step")}
+    k_tail = {k: batch.kernel_ms(k)[0] for k in names}
+    n_eq = min(max(N_EQUIL - args.warmup, 0), args.steps)  # timed steps before sampling starts
+    windows = []  # (per-kernel averages, window lies in the equilibrating steps)
+    if head > 0:
+        windows.append((k_head, 0.5 * head < n_eq))
+    if args.steps - head > 0:  # direct launches after the head: the tail, or every step without graphs
+        t_lo = head if args.chunk == 0 else args.steps - tail
+        windows.append((k_tail, 0.5 * (t_lo + args.steps) < n_eq))
+    eq = [w for w, in_eq in windows if in_eq] or [w for w, _ in windows]
+    sa = [w for w, in_eq in windows if not in_eq] or [w for w, _ in windows]
+    kern = {k: float(n_eq * np.mean([w[k] for w in eq]) + (args.steps - n_eq) * np.mean([w[k] for w in sa]))
+            / args.steps for k in names}
+    kern["graph_step"] = batch.kernel_ms("graph_step")[0]
     cfg = batch.config()
     builds = batch.list_builds() - builds0
     res = batch.results() if args.warmup + args.steps >= N_EQUIL + N_SAMPLE else []
@@ -407,6 +428,7 @@ def main():
         "batched_over_plain": value / plain if plain else None,
         "plain_sample": f"first {args.plain_sims} systems alone, {args.plain_steps} steps each, direct launches",
         "kernel_ms": kern,
+        "kernel_ms_windows": {"first_steps": k_head, "last_steps": k_tail, "equilibrating_steps": n_eq},
     }
     if res:
         st = [r["status"] for r in res]
