@@ -956,7 +956,7 @@ __device__ __forceinline__ void tile_ranges(const int4& tile, int ntot, const Si
 }
 
 // Copies the tile's ranges into LDS in one flat pass over every staged
-// entry, each thread with four loads in flight (range by range, each short
+// entry, each thread with eight loads in flight (range by range, each short
 // range would cost a whole memory latency of its own); put(e, p) stores
 // entry e.  The range of entry e is the r with off[r] <= e < off[r + 1] (an
 // empty range shares its start with the next; the last such r is taken).  A
@@ -966,7 +966,7 @@ __device__ __forceinline__ void tile_ranges(const int4& tile, int ntot, const Si
 // All threads of the block call it (the ballots need whole wavefronts).
 template <class Put>
 __device__ __forceinline__ void tile_stage_core(const TileStage& T, const int4* __restrict__ pfix, Put put) {
-  constexpr int U = 4;
+  constexpr int U = 8;
   const uint32_t total = T.off[TILE_RUNS];
   const uint32_t lane = threadIdx.x & (WAVE - 1);
   const uint32_t start_q = (lane >= 1 && lane < uint32_t(TILE_RUNS)) ? T.off[lane] : 0xffffffffu;
