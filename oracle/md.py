@@ -14,6 +14,7 @@ from dataclasses import dataclass, fields
 import numpy as np
 
 from . import build as _build
+from . import stats as _stats
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -47,7 +48,7 @@ class Params:
     Lz_nom: float = 12.0
     bin_dy: float = 0.25
     n_equil: int = 0
-    n_blocks: int = 20
+    n_blocks: int = 0
     n_fluid: int = 0
     delta: float = 1.0
     cell_w: float = 0.0
@@ -220,11 +221,28 @@ class System:
         return mvx, cnt
 
     def result(self):
+        """Mean flux and its standard error over the sampled steps (Sec. 2.3:
+        from the raw time-instantaneous data).  n_blocks = 0: Geyer's initial
+        monotone sequence estimator over the per-step series, with the
+        non-convergence test on its two halves; n_blocks >= 2: the block rule
+        of the C oracle."""
         out = np.zeros(8)
         st = ctypes.c_int()
         lib().ora_result(self._h, _ptr(out), ctypes.byref(st))
+        status = st.value
+        if self.params.n_blocks == 0:
+            ser = self.series()
+            if len(ser) >= 2:
+                mean, se = _stats.geyer(ser)
+                m1, m2 = _stats.halves(ser)
+                out[0], out[1], out[2] = mean, se, mean / self.h
+                # non-convergence (reading of the critical-shear remark,
+                # Sec. 3.2): the two halves differ by more than 8 SE, or the
+                # spanwise temperature runs away
+                if status == 0 and (abs(m2 - m1) > 8.0 * se or out[5] > 1.5 * self.params.T0):
+                    status = -5
         return {"flux": out[0], "flux_se": out[1], "jflux": out[2], "T": out[3:6].copy(),
-                "pe": out[6], "lambda": out[7], "status": st.value, "n_fluid": self.n_fluid}
+                "pe": out[6], "lambda": out[7], "status": status, "n_fluid": self.n_fluid}
 
 
 def md_flux(h, g, seed, n_sample, params: Params = None):

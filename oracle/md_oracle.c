@@ -87,7 +87,8 @@ typedef struct {
     double Lx_nom, Lz_nom;  /* nominal periodic extents, snapped to the wall lattice */
     double bin_dy;      /* width of the wall-normal profile bins */
     int64_t n_equil;    /* steps before sampling starts */
-    int n_blocks;       /* blocks for the standard error */
+    int n_blocks;       /* 0: standard error left to the caller (correlated-series
+                           estimator over the series); >= 2: that many blocks */
     int64_t n_fluid;    /* 0: round(rho*Lx*Lz*h) */
     double delta;       /* gap between wall plane and the first lattice plane */
     double cell_w;      /* minimum cell width; 0 means rc */
@@ -129,7 +130,7 @@ void ora_default_params(ora_params *P)
     P->dt = 0.005; P->tau_T = 0.1;
     P->Lx_nom = 12.0; P->Lz_nom = 12.0;
     P->bin_dy = 0.25;
-    P->n_equil = 0; P->n_blocks = 20; P->n_fluid = 0;
+    P->n_equil = 0; P->n_blocks = 0; P->n_fluid = 0;
     P->delta = 1.0;
     P->cell_w = 0.0;
 }
@@ -495,7 +496,7 @@ double ora_forces_cells(ora_sys *S, double *f)
 /* ------------------------------------------------------------------------ */
 ora_sys *ora_create(const ora_params *P, double h, double g, uint64_t seed)
 {
-    if (!(h > 2.0 * P->delta) || !(P->rc > 0.0) || P->n_blocks < 2) return NULL;
+    if (!(h > 2.0 * P->delta) || !(P->rc > 0.0) || P->n_blocks < 0 || P->n_blocks == 1) return NULL;
     ora_sys *S = (ora_sys *)calloc(1, sizeof(ora_sys));
     S->P = *P;
     S->h = h; S->g = g; S->seed = seed;
@@ -713,19 +714,24 @@ void ora_result(const ora_sys *S, double out[8], int *status)
 {
     for (int k = 0; k < 8; ++k) out[k] = 0.0;
     int st = S->status;
-    double bs[4];
-    int64_t B = ora_block_stats(S->series, S->nsamp, S->P.n_blocks, bs);
-    if (B >= 1) {
-        out[0] = bs[0];
-        out[1] = bs[1];
-        out[2] = bs[0] / S->h;
+    if (S->nsamp >= 1)
         for (int a = 0; a < 3; ++a) out[3 + a] = S->Tsum[a] / (double)S->nsamp;
-        /* non-convergence (reading of the critical-shear remark, Sec. 3.2):
-         * first-half and second-half block means differ by more than 8 SE,
-         * or the spanwise temperature, which no thermostat touches, runs
-         * away (> 1.5 T0). */
-        if (st == 0 && (fabs(bs[3] - bs[2]) > 8.0 * bs[1] || out[5] > 1.5 * S->P.T0)) st = -5;
-    } else if (st == 0) {
+    if (S->P.n_blocks >= 2) {
+        double bs[4];
+        int64_t B = ora_block_stats(S->series, S->nsamp, S->P.n_blocks, bs);
+        if (B >= 1) {
+            out[0] = bs[0];
+            out[1] = bs[1];
+            out[2] = bs[0] / S->h;
+            /* non-convergence (reading of the critical-shear remark, Sec. 3.2):
+             * first-half and second-half block means differ by more than 8 SE,
+             * or the spanwise temperature, which no thermostat touches, runs
+             * away (> 1.5 T0). */
+            if (st == 0 && (fabs(bs[3] - bs[2]) > 8.0 * bs[1] || out[5] > 1.5 * S->P.T0)) st = -5;
+        } else if (st == 0) {
+            st = -1;
+        }
+    } else if (st == 0 && S->nsamp < 2) {
         st = -1;
     }
     out[6] = S->pe / (double)S->nf;
