@@ -28,6 +28,7 @@ class OraParams(ctypes.Structure):
         ("Lx_nom", ctypes.c_double), ("Lz_nom", ctypes.c_double),
         ("bin_dy", ctypes.c_double), ("n_equil", ctypes.c_int64), ("n_blocks", ctypes.c_int),
         ("n_fluid", ctypes.c_int64), ("delta", ctypes.c_double), ("cell_w", ctypes.c_double),
+        ("periodic_y", ctypes.c_int), ("g_sin", ctypes.c_double),
     ]
 
 
@@ -52,6 +53,8 @@ class Params:
     n_fluid: int = 0
     delta: float = 1.0
     cell_w: float = 0.0
+    periodic_y: int = 0      # 1: bulk box periodic in y with period h (no walls)
+    g_sin: float = 0.0       # extra body force g_sin sin(2 pi y / h) along x
 
     def to_c(self) -> OraParams:
         return OraParams(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -209,6 +212,42 @@ class System:
         out = np.zeros(n)
         if n:
             lib().ora_series(self._h, _ptr(out))
+        return out
+
+    def flow_diag(self):
+        """Sums over the sampled steps (see ora_flow_diag in md_oracle.c)."""
+        L = lib()
+        L.ora_flow_diag.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+        out = np.zeros(13)
+        L.ora_flow_diag(self._h, _ptr(out))
+        keys = ("disp", "wraps", "p_start", "p_now", "kick1", "kick2", "fwall_x", "fpair_x", "fwall_y_lo",
+                "fwall_y_hi", "virial", "virial_yy", "samples")
+        return dict(zip(keys, out.tolist()))
+
+    def force_diag(self):
+        """Wall forces on the fluid, total pair force and virial at the
+        current positions."""
+        L = lib()
+        L.ora_force_diag.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+        out = np.zeros(11)
+        L.ora_force_diag(self._h, _ptr(out))
+        return {"wall_lo": out[0:3].copy(), "wall_hi": out[3:6].copy(), "total": out[6:9].copy(),
+                "virial": out[9], "virial_yy": out[10]}
+
+    def wall_force_series(self):
+        L = lib()
+        L.ora_wall_force_series.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+        n = lib().ora_nsamples(self._h)
+        out = np.zeros(n)
+        if n:
+            L.ora_wall_force_series(self._h, _ptr(out))
+        return out
+
+    def displacements(self):
+        L = lib()
+        L.ora_displacements.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+        out = np.zeros(self.n_fluid)
+        L.ora_displacements(self._h, _ptr(out))
         return out
 
     def profile(self):

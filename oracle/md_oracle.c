@@ -92,6 +92,8 @@ typedef struct {
     int64_t n_fluid;    /* 0: round(rho*Lx*Lz*h) */
     double delta;       /* gap between wall plane and the first lattice plane */
     double cell_w;      /* minimum cell width; 0 means rc */
+    int periodic_y;     /* 1: bulk box, periodic in y with period h (needs wall_layers = 0) */
+    double g_sin;       /* amplitude of a body force g_sin sin(2 pi y / h) along x, added to g */
 } ora_params;
 
 typedef struct {
@@ -119,6 +121,19 @@ typedef struct {
     double Tsum[3];
     double lambda_last;
     int status;
+    /* pair-force diagnostics of the last force evaluation: sums over fluid
+     * atoms of the wall forces (lower wall: sites at y <= 0; upper: y > 0)
+     * and of all pair forces, the fluid-fluid virial sum_{i<j} r_ij . f_ij
+     * and its yy part */
+    double fw_lo[3], fw_hi[3], ftot[3], vir, vir_yy;
+    /* flow diagnostics over the sampled steps */
+    double *disp;           /* per atom: unwrapped x displacement */
+    int64_t wraps;          /* net crossings of the periodic plane x = 0 (+ along +x) */
+    double p_start;         /* sum v_x when sampling began */
+    double kick1, kick2;    /* sums of the x kick forces (pair + body) of the first
+                               and second half-kicks of sampled steps */
+    double fwx_sum, ftx_sum, fwy_lo_sum, fwy_hi_sum, vir_sum, viryy_sum;
+    double *fwx_series;     /* per sampled step: wall force on the fluid along x */
 } ora_sys;
 
 /* Stated defaults (readings of the paper, see the design notes). */
@@ -133,6 +148,8 @@ void ora_default_params(ora_params *P)
     P->n_equil = 0; P->n_blocks = 0; P->n_fluid = 0;
     P->delta = 1.0;
     P->cell_w = 0.0;
+    P->periodic_y = 0;
+    P->g_sin = 0.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -217,11 +234,41 @@ static int cmp_i64(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
+/* Bulk box (periodic in y): nl planes evenly over the period, spacing h/nl,
+ * the plane count chosen like the channel's (largest closest distance,
+ * counting the spacing across the periodic boundary). */
+static lattice_t choose_lattice_periodic(int64_t nf, double Lx, double Lz, double h)
+{
+    lattice_t best = {1, 1, 1, h, Lx, Lz};
+    double best_d = -1.0;
+    int nlmax = (int)floor(h / 0.5);
+    if (nlmax < 2) nlmax = 2;
+    for (int nl = 2; nl <= nlmax; nl += 2) {  /* even: the half-spacing shift alternates across the boundary */
+        double s = h / (double)nl;
+        int64_t per = (nf + nl - 1) / nl;
+        int mx = (int)ceil(sqrt((double)per * Lx / Lz));
+        if (mx < 1) mx = 1;
+        int mz = (int)((per + mx - 1) / mx);
+        if (mz < 1) mz = 1;
+        double ax = Lx / (double)mx, az = Lz / (double)mz;
+        double d = ax < az ? ax : az;
+        double inter = sqrt(0.25 * ax * ax + 0.25 * az * az + s * s);
+        if (inter < d) d = inter;
+        if (2.0 * s < d) d = 2.0 * s;
+        if (d > best_d) {
+            best_d = d;
+            best.nl = nl; best.mx = mx; best.mz = mz; best.s = s; best.ax = ax; best.az = az;
+        }
+    }
+    return best;
+}
+
 static void init_fluid(ora_sys *S)
 {
     const ora_params *P = &S->P;
     double D = S->h - 2.0 * P->delta;
-    lattice_t L = choose_lattice(S->nf, S->Lx, S->Lz, D);
+    lattice_t L = P->periodic_y ? choose_lattice_periodic(S->nf, S->Lx, S->Lz, S->h)
+                                : choose_lattice(S->nf, S->Lx, S->Lz, D);
     int64_t nsites = (int64_t)L.nl * L.mx * L.mz;
     int64_t *perm = (int64_t *)malloc(sizeof(int64_t) * nsites);
     for (int64_t i = 0; i < nsites; ++i) perm[i] = i;
@@ -241,7 +288,8 @@ static void init_fluid(ora_sys *S)
         int l = (int)(site / ((int64_t)L.mx * L.mz));
         double off = (l & 1) ? 0.5 : 0.0;
         S->x[3 * n + 0] = ((double)i + off) * L.ax;
-        S->x[3 * n + 1] = (L.nl > 1) ? P->delta + (double)l * L.s : 0.5 * S->h;
+        if (P->periodic_y) S->x[3 * n + 1] = ((double)l + 0.5) * L.s;
+        else S->x[3 * n + 1] = (L.nl > 1) ? P->delta + (double)l * L.s : 0.5 * S->h;
         S->x[3 * n + 2] = ((double)k + off) * L.az;
     }
     free(perm);
@@ -400,6 +448,7 @@ double ora_forces_brute(ora_sys *S, double *f)
             if (j == i) continue;
             double dx = min_image(S->x[3 * i] - S->x[3 * j], S->Lx);
             double dy = S->x[3 * i + 1] - S->x[3 * j + 1];
+            if (P->periodic_y) dy = min_image(dy, S->h);
             double dz = min_image(S->x[3 * i + 2] - S->x[3 * j + 2], S->Lz);
             double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < rc2) {
@@ -425,7 +474,9 @@ double ora_forces_brute(ora_sys *S, double *f)
     return pe;
 }
 
-/* Cell-list evaluation of exactly the same sum (27 neighbouring cells). */
+/* Cell-list evaluation of exactly the same sum (27 neighbouring cells).
+ * Also records the wall forces on the fluid, the total pair force and the
+ * fluid-fluid virial (diagnostics, per atom then summed in atom order). */
 double ora_forces_cells(ora_sys *S, double *f)
 {
     const ora_params *P = &S->P;
@@ -435,17 +486,21 @@ double ora_forces_cells(ora_sys *S, double *f)
     double ush_wf = lj_u(rc2, P->eps_wf, P->sigma_wf);
     int nx = S->ncx, ny = S->ncy, nz = S->ncz;
     int64_t ncol = (int64_t)nx * nz;
-    double *pe_atom = (double *)malloc(sizeof(double) * (S->nf > 0 ? S->nf : 1));
+    int64_t na = S->nf > 0 ? S->nf : 1;
+    double *pe_atom = (double *)malloc(sizeof(double) * na);
+    double *diag = (double *)malloc(sizeof(double) * 8 * na);  /* lo xyz, hi xyz, vir, vir_yy */
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < S->nf; ++i) {
         int c = S->cell_of[i];
         int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
         double xi = S->x[3 * i], yi = S->x[3 * i + 1], zi = S->x[3 * i + 2];
         double fx = 0.0, fy = 0.0, fz = 0.0, pei = 0.0;
+        double wl[3] = {0.0, 0.0, 0.0}, wh[3] = {0.0, 0.0, 0.0}, vir = 0.0, viryy = 0.0;
         for (int oz = -1; oz <= 1; ++oz) {
             int jz = (cz + oz + nz) % nz;
             for (int oy = -1; oy <= 1; ++oy) {
                 int jy = cy + oy;
+                if (P->periodic_y) jy = (jy + ny) % ny;
                 for (int ox = -1; ox <= 1; ++ox) {
                     int jx = (cx + ox + nx) % nx;
                     if (jy >= 0 && jy < ny) {
@@ -455,12 +510,15 @@ double ora_forces_cells(ora_sys *S, double *f)
                             if (j == i) continue;
                             double dx = min_image(xi - S->x[3 * j], S->Lx);
                             double dy = yi - S->x[3 * j + 1];
+                            if (P->periodic_y) dy = min_image(dy, S->h);
                             double dz = min_image(zi - S->x[3 * j + 2], S->Lz);
                             double r2 = dx * dx + dy * dy + dz * dz;
                             if (r2 < rc2) {
                                 double fr = lj_f_over_r(r2, 1.0, 1.0);
                                 fx += fr * dx; fy += fr * dy; fz += fr * dz;
                                 pei += 0.5 * (lj_u(r2, 1.0, 1.0) - ush_ff);
+                                vir += 0.5 * fr * r2;
+                                viryy += 0.5 * fr * dy * dy;
                             }
                         }
                     } else {
@@ -476,6 +534,8 @@ double ora_forces_cells(ora_sys *S, double *f)
                                 double fr = lj_f_over_r(r2, P->eps_wf, P->sigma_wf);
                                 fx += fr * dx; fy += fr * dy; fz += fr * dz;
                                 pei += lj_u(r2, P->eps_wf, P->sigma_wf) - ush_wf;
+                                double *acc = (S->xw[3 * w + 1] <= 0.0) ? wl : wh;
+                                acc[0] += fr * dx; acc[1] += fr * dy; acc[2] += fr * dz;
                             }
                         }
                     }
@@ -484,10 +544,28 @@ double ora_forces_cells(ora_sys *S, double *f)
         }
         f[3 * i] = fx; f[3 * i + 1] = fy; f[3 * i + 2] = fz;
         pe_atom[i] = pei;
+        double *dg = diag + 8 * i;
+        dg[0] = wl[0]; dg[1] = wl[1]; dg[2] = wl[2];
+        dg[3] = wh[0]; dg[4] = wh[1]; dg[5] = wh[2];
+        dg[6] = vir; dg[7] = viryy;
     }
     double pe = 0.0;
-    for (int64_t i = 0; i < S->nf; ++i) pe += pe_atom[i];
+    for (int a = 0; a < 3; ++a) { S->fw_lo[a] = 0.0; S->fw_hi[a] = 0.0; S->ftot[a] = 0.0; }
+    S->vir = 0.0;
+    S->vir_yy = 0.0;
+    for (int64_t i = 0; i < S->nf; ++i) {
+        pe += pe_atom[i];
+        const double *dg = diag + 8 * i;
+        for (int a = 0; a < 3; ++a) {
+            S->fw_lo[a] += dg[a];
+            S->fw_hi[a] += dg[3 + a];
+            S->ftot[a] += f[3 * i + a];
+        }
+        S->vir += dg[6];
+        S->vir_yy += dg[7];
+    }
     free(pe_atom);
+    free(diag);
     return pe;
 }
 
@@ -497,6 +575,7 @@ double ora_forces_cells(ora_sys *S, double *f)
 ora_sys *ora_create(const ora_params *P, double h, double g, uint64_t seed)
 {
     if (!(h > 2.0 * P->delta) || !(P->rc > 0.0) || P->n_blocks < 0 || P->n_blocks == 1) return NULL;
+    if (P->periodic_y && (P->wall_layers != 0 || h < 3.0 * (P->cell_w > P->rc ? P->cell_w : P->rc))) return NULL;
     ora_sys *S = (ora_sys *)calloc(1, sizeof(ora_sys));
     S->P = *P;
     S->h = h; S->g = g; S->seed = seed;
@@ -514,6 +593,8 @@ ora_sys *ora_create(const ora_params *P, double h, double g, uint64_t seed)
     S->bin_cnt = (double *)calloc((size_t)S->nbins, sizeof(double));
     S->series_cap = 1024;
     S->series = (double *)malloc(sizeof(double) * S->series_cap);
+    S->fwx_series = (double *)malloc(sizeof(double) * S->series_cap);
+    S->disp = (double *)calloc((size_t)(S->nf > 0 ? S->nf : 1), sizeof(double));
     S->pe = ora_forces_cells(S, S->f);
     S->lambda_last = 1.0;
     return S;
@@ -526,6 +607,7 @@ void ora_free(ora_sys *S)
     free(S->cell_of); free(S->fstart); free(S->fcount); free(S->forder);
     free(S->wstart); free(S->wcount); free(S->worder);
     free(S->series); free(S->bin_mvx); free(S->bin_cnt);
+    free(S->fwx_series); free(S->disp);
     free(S);
 }
 
@@ -605,9 +687,24 @@ static void sample(ora_sys *S)
     if (S->nsamp == S->series_cap) {
         S->series_cap *= 2;
         S->series = (double *)realloc(S->series, sizeof(double) * S->series_cap);
+        S->fwx_series = (double *)realloc(S->fwx_series, sizeof(double) * S->series_cap);
     }
+    S->fwx_series[S->nsamp] = S->fw_lo[0] + S->fw_hi[0];
     S->series[S->nsamp++] = sx / (S->Lx * S->Lz);
     for (int a = 0; a < 3; ++a) S->Tsum[a] += t[a] / (double)S->nf;
+    S->fwx_sum += S->fw_lo[0] + S->fw_hi[0];
+    S->ftx_sum += S->ftot[0];
+    S->fwy_lo_sum += S->fw_lo[1];
+    S->fwy_hi_sum += S->fw_hi[1];
+    S->vir_sum += S->vir;
+    S->viryy_sum += S->vir_yy;
+}
+
+/* x body force on an atom at height y: g + g_sin sin(2 pi y / h) */
+static double body_force(const ora_sys *S, double y)
+{
+    if (S->P.g_sin == 0.0) return S->g;
+    return S->g + S->P.g_sin * sin(6.283185307179586 * y / S->h);
 }
 
 /* energy_trace (nullable): total energy per fluid atom after each step. */
@@ -617,23 +714,42 @@ void ora_run(ora_sys *S, int64_t steps, int thermostat_on, double *energy_trace)
     double hdt = 0.5 * P->dt;
     int ax = P->thermo_axis;
     for (int64_t s = 0; s < steps; ++s) {
+        int sampled = S->step + 1 > P->n_equil;
+        if (sampled && S->nsamp == 0) {
+            double px = 0.0;
+            for (int64_t i = 0; i < S->nf; ++i) px += S->v[3 * i];
+            S->p_start = px;
+        }
+        double k1 = 0.0;
         for (int64_t i = 0; i < S->nf; ++i) {
-            S->v[3 * i + 0] += hdt * (S->f[3 * i + 0] + S->g);
+            double gx = body_force(S, S->x[3 * i + 1]);
+            k1 += S->f[3 * i + 0] + gx;
+            S->v[3 * i + 0] += hdt * (S->f[3 * i + 0] + gx);
             S->v[3 * i + 1] += hdt * S->f[3 * i + 1];
             S->v[3 * i + 2] += hdt * S->f[3 * i + 2];
-            S->x[3 * i + 0] = wrap(S->x[3 * i + 0] + P->dt * S->v[3 * i + 0], S->Lx);
+            double xr = S->x[3 * i + 0] + P->dt * S->v[3 * i + 0];
+            if (sampled) {
+                S->disp[i] += P->dt * S->v[3 * i + 0];
+                if (xr >= S->Lx) S->wraps += 1;
+                else if (xr < 0.0) S->wraps -= 1;
+            }
+            S->x[3 * i + 0] = wrap(xr, S->Lx);
             S->x[3 * i + 1] = S->x[3 * i + 1] + P->dt * S->v[3 * i + 1];
+            if (P->periodic_y) S->x[3 * i + 1] = wrap(S->x[3 * i + 1], S->h);
             S->x[3 * i + 2] = wrap(S->x[3 * i + 2] + P->dt * S->v[3 * i + 2], S->Lz);
         }
         S->pe = ora_forces_cells(S, S->f);
-        double ss = 0.0;
+        double ss = 0.0, k2 = 0.0;
         for (int64_t i = 0; i < S->nf; ++i) {
-            S->v[3 * i + 0] += hdt * (S->f[3 * i + 0] + S->g);
+            double gx = body_force(S, S->x[3 * i + 1]);
+            k2 += S->f[3 * i + 0] + gx;
+            S->v[3 * i + 0] += hdt * (S->f[3 * i + 0] + gx);
             S->v[3 * i + 1] += hdt * S->f[3 * i + 1];
             S->v[3 * i + 2] += hdt * S->f[3 * i + 2];
             double vc = S->v[3 * i + ax];
             ss += vc * vc;
         }
+        if (sampled) { S->kick1 += k1; S->kick2 += k2; }
         if (thermostat_on) {
             double Tc = ss / (double)S->nf;
             double lam = sqrt(1.0 + (P->dt / P->tau_T) * (P->T0 / Tc - 1.0));
@@ -648,15 +764,50 @@ void ora_run(ora_sys *S, int64_t steps, int thermostat_on, double *energy_trace)
             energy_trace[s] = (ke + S->pe) / (double)S->nf;
         }
         for (int64_t i = 0; i < S->nf; ++i) {
-            /* unstable: non-finite state, an atom outside the wall gap, or a
-             * periodic coordinate that one wrap could not bring back (a move
-             * longer than the box in one step) */
+            /* unstable: non-finite state, an atom outside the wall gap (the
+             * period in a bulk box), or a periodic coordinate that one wrap
+             * could not bring back (a move longer than the box in one step) */
             double X = S->x[3 * i], y = S->x[3 * i + 1], Z = S->x[3 * i + 2];
-            if (!(y > 0.0 && y < S->h) || !(X >= 0.0 && X < S->Lx) || !(Z >= 0.0 && Z < S->Lz) ||
+            int y_ok = P->periodic_y ? (y >= 0.0 && y < S->h) : (y > 0.0 && y < S->h);
+            if (!y_ok || !(X >= 0.0 && X < S->Lx) || !(Z >= 0.0 && Z < S->Lz) ||
                 !isfinite(S->v[3 * i]) || !isfinite(S->v[3 * i + 1]) || !isfinite(S->v[3 * i + 2]))
                 S->status = -4;
         }
     }
+}
+
+/* Flow and force diagnostics over the sampled steps (see ora_sys):
+ * out[0] sum of x displacements, [1] net crossings of x = 0, [2] sum v_x at
+ * sampling start, [3] sum v_x now, [4] [5] first / second half-kick force
+ * sums, [6] sum of the x wall force, [7] sum of the x total pair force,
+ * [8] [9] sums of the y force of the lower / upper wall, [10] [11] sums of
+ * the virial and its yy part, [12] samples. */
+void ora_flow_diag(const ora_sys *S, double out[13])
+{
+    double d = 0.0, px = 0.0;
+    for (int64_t i = 0; i < S->nf; ++i) { d += S->disp[i]; px += S->v[3 * i]; }
+    out[0] = d; out[1] = (double)S->wraps; out[2] = S->p_start; out[3] = px;
+    out[4] = S->kick1; out[5] = S->kick2; out[6] = S->fwx_sum; out[7] = S->ftx_sum;
+    out[8] = S->fwy_lo_sum; out[9] = S->fwy_hi_sum; out[10] = S->vir_sum; out[11] = S->viryy_sum;
+    out[12] = (double)S->nsamp;
+}
+
+void ora_wall_force_series(const ora_sys *S, double *out)
+{
+    memcpy(out, S->fwx_series, sizeof(double) * S->nsamp);
+}
+
+/* Per-atom x displacements over the sampled steps. */
+void ora_displacements(const ora_sys *S, double *out) { memcpy(out, S->disp, sizeof(double) * S->nf); }
+
+/* Pair-force diagnostics of the current positions: out[0..2] lower-wall
+ * force on the fluid, [3..5] upper-wall force, [6..8] total pair force,
+ * [9] fluid-fluid virial, [10] its yy part. */
+void ora_force_diag(const ora_sys *S, double out[11])
+{
+    for (int a = 0; a < 3; ++a) { out[a] = S->fw_lo[a]; out[3 + a] = S->fw_hi[a]; out[6 + a] = S->ftot[a]; }
+    out[9] = S->vir;
+    out[10] = S->vir_yy;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -57,3 +57,26 @@ def test_ensemble_fits_a_smooth_map():
     m, s = ens.predict(X)
     assert np.sqrt(np.mean((m - y) ** 2)) < 0.05 * np.sqrt(np.mean(y ** 2))
     assert np.all(s >= 0)
+
+
+def test_forward_of_a_hand_set_network():
+    # H = 2, input (0.5, -1), flat layout W1 [H x 2] (one row per hidden
+    # unit), b1, W2 [H x H], b2, W3 [1 x H], b3:
+    #   W1 = [[2, 1], [0, -3]], b1 = (0, -2):  z1 = (0, 1), h1 = (0, t), t = tanh 1
+    #   W2 = [[1, 2], [-1, 0.5]], b2 = (0.25, 0):  h2 = (tanh(2t + 1/4), tanh(t/2))
+    #   W3 = [3, -2], b3 = 0.1:  out = 3 tanh(2t + 1/4) - 2 tanh(t/2) + 0.1
+    # = 2.205074484369277.  A transposed W1 or W2, or a bias in the wrong
+    # slot, changes the value.
+    theta = np.array([2.0, 1.0, 0.0, -3.0, 0.0, -2.0,
+                      1.0, 2.0, -1.0, 0.5, 0.25, 0.0,
+                      3.0, -2.0, 0.1])
+    assert len(theta) == mlp.n_params(2)
+    out, (h1, h2) = mlp.forward(theta, np.array([[0.5, -1.0]]), 2)
+    assert out[0] == pytest.approx(2.205074484369277, abs=1e-14)
+    assert h1[0, 0] == 0.0 and h1[0, 1] == pytest.approx(0.7615941559557649, abs=1e-15)
+    # the ensemble applies the input standardisation and output scale around
+    # the same network: inputs (mu + sd x) and outputs s_q out
+    ens = mlp.Ensemble.__new__(mlp.Ensemble)
+    ens.H, ens.mu, ens.sd, ens.s_q, ens.thetas = 2, np.array([1.0, 2.0]), np.array([4.0, 0.5]), 3.0, [theta]
+    m = ens.member_predict(np.array([[1.0 + 4.0 * 0.5, 2.0 + 0.5 * -1.0]]))
+    assert m[0, 0] == pytest.approx(3.0 * 2.205074484369277, abs=1e-13)
