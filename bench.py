@@ -65,6 +65,46 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def advance(batch, n, chunk):
+    """n steps as graph replays of `chunk` steps, then one replay of the even
+    remainder and, for an odd n, one direct step."""
+    full = (n // chunk) * chunk
+    if full:
+        batch.run(full, graph_chunk=chunk)
+    rest = n - full
+    if rest >= 2:
+        batch.run(rest - rest % 2, graph_chunk=rest - rest % 2)
+    if rest % 2:
+        batch.run(1, graph_chunk=0)
+
+
+def timed_plan(steps, warmup, chunk):
+    """Which steps of the 10k + 20k protocol are timed.  The timed steps split
+    1 : 2 between equilibrating and sampling steps (the protocol's own
+    proportion); when they are fewer than the protocol, the rest of the
+    equilibration runs untimed between the two timed stretches.  Returns the
+    warm-up, the timed stretches, the untimed skip, the graph chunk and the
+    graph sizes to capture during the warm-up."""
+    total = N_EQUIL + N_SAMPLE
+    if warmup + steps >= total:
+        eq = max(0, N_EQUIL - warmup)
+    else:
+        eq = min(max(0, N_EQUIL - warmup), 2 * int(round(steps / 6.0)))
+    eq = min(eq, steps)
+    sa = steps - eq
+    skip = max(0, N_EQUIL - warmup - eq) if sa > 0 else 0
+    c = max(2, min(chunk, eq if eq >= 2 else chunk, sa if sa >= 2 else chunk))
+    c -= c % 2
+    sizes = set()
+    for n in (eq, sa):
+        if n >= c:
+            sizes.add(c)
+        rest = n % c
+        if rest >= 2:
+            sizes.add(rest - rest % 2)
+    return {"warmup": warmup, "eq": eq, "sa": sa, "skip": skip, "chunk": c, "chunks": sorted(sizes)}
+
+
 def cpu_baseline(budget_s: float):
     """The oracle as it stands on the host cores: one system of the batch
     (seed 0), timed for a bounded number of steps."""
@@ -281,11 +321,7 @@ def main():
     ap.add_argument("--steps", type=int, default=N_EQUIL + N_SAMPLE - 200)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=100)
-    ap.add_argument("--timed-tail", type=int, default=200)
-    ap.add_argument("--timed-head", type=int, default=200,
-                    help="timed steps run first as direct launches with per-kernel events (the tail's twin early in "
-                         "the run, so that per-kernel averages cover equilibrating and sampling steps)")
-    ap.add_argument("--plain-sims", type=int, default=4)
+    ap.add_argument("--plain-sims", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -339,51 +375,64 @@ def main():
     log(f"batch set up in {time.perf_counter() - t0:.1f} s: {batch.atoms} fluid atoms")
     ff, wf = batch.pair_count()
     pairs_per_launch = ff + wf
-    batch.run(args.warmup, graph_chunk=args.chunk)
-    # the first `head` and the last `tail` steps of the timed region run as
-    # direct launches with HIP events around every kernel; the rest replays
-    # the captured graph, timed as a whole.  Per-kernel averages weight the
-    # two windows by the equilibrating and sampling steps of the timed region
-    # (the sampled steps add the profile and flux work to the force kernel).
-    tail = min(args.timed_tail, args.steps)
-    head = min(args.timed_head, args.steps - tail)
+    plan = timed_plan(args.steps, args.warmup, args.chunk)
+    log(f"timed plan: {plan}")
     names = ("integrate", "keys", "scan", "scatter", "reorder", "list", "force")
-    builds0 = batch.list_builds()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.set_timing(True)
-    batch.run(head, graph_chunk=0)
-    k_head = {k: batch.kernel_ms(k)[0] for k in names}
-    batch.set_timing(True)
-    batch.run(args.steps - tail - head, graph_chunk=args.chunk)
-    batch.run(tail, graph_chunk=0)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # warm-up: capture the timed graphs (their first replays are warm-up
+    # steps), then the rest of the warm-up untimed
+    done = 0
+    for cs in plan["chunks"]:
+        batch.set_timing(True)
+        batch.run(cs, graph_chunk=cs)
+        done += cs
+    batch.set_timing(False)
+    if plan["warmup"] > done:
+        advance(batch, plan["warmup"] - done, args.chunk)
+        done = plan["warmup"]
+    warm_steps = done
+    builds = 0
+    wall, windows = 0.0, []
+    for phase, n_timed in (("equilibrating", plan["eq"]), ("sampling", plan["sa"])):
+        if n_timed > 0:
+            batch.set_timing(True)
+            b0 = batch.list_builds()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            advance(batch, n_timed, plan["chunk"])
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            builds += batch.list_builds() - b0
+            windows.append((phase, n_timed, {k: batch.kernel_ms(k) for k in names + ("graph_step",)}))
+            batch.set_timing(False)
+            done += n_timed
+        if phase == "equilibrating" and plan["sa"] > 0 and done < N_EQUIL:  # untimed: the rest of it
+            advance(batch, N_EQUIL - done, args.chunk)
+            done = N_EQUIL
     ms_step = 1e3 * wall / args.steps
     value = batch.atoms * args.steps / wall
-    k_tail = {k: batch.kernel_ms(k)[0] for k in names}
-    n_eq = min(max(N_EQUIL - args.warmup, 0), args.steps)  # timed steps before sampling starts
-    windows = []  # (per-kernel averages, window lies in the equilibrating steps)
-    if head > 0:
-        windows.append((k_head, 0.5 * head < n_eq))
-    if args.steps - head > 0:  # direct launches after the head: the tail, or every step without graphs
-        t_lo = head if args.chunk == 0 else args.steps - tail
-        windows.append((k_tail, 0.5 * (t_lo + args.steps) < n_eq))
-    eq = [w for w, in_eq in windows if in_eq] or [w for w, _ in windows]
-    sa = [w for w, in_eq in windows if not in_eq] or [w for w, _ in windows]
-    kern = {k: float(n_eq * np.mean([w[k] for w in eq]) + (args.steps - n_eq) * np.mean([w[k] for w in sa]))
-            / args.steps for k in names}
-    kern["graph_step"] = batch.kernel_ms("graph_step")[0]
+    # per-kernel averages (ms per launch, one launch of each per step) from the
+    # event nodes in the timed graph replays, weighted like the protocol: one
+    # third of the steps equilibrating, two thirds sampling
+    w_phase = {"equilibrating": N_EQUIL / (N_EQUIL + N_SAMPLE), "sampling": N_SAMPLE / (N_EQUIL + N_SAMPLE)}
+    present = [w for w in windows if w[1] > 0]
+    wsum = sum(w_phase[p] for p, _, _ in present)
+    kern = {k: float(sum(w_phase[p] * km[k][0] for p, _, km in present) / wsum) for k in names}
+    kern["graph_step"] = float(sum(w_phase[p] * km["graph_step"][0] for p, _, km in present) / wsum)
+    kern_windows = {p: {"timed_steps": n, "launches_timed": int(km["force"][1]),
+                        **{k: float(km[k][0]) for k in names + ("graph_step",)}} for p, n, km in windows}
     cfg = batch.config()
-    builds = batch.list_builds() - builds0
-    res = batch.results() if args.warmup + args.steps >= N_EQUIL + N_SAMPLE else []
+    if done < N_EQUIL + N_SAMPLE:  # finish the sampling window (untimed) for the flux results
+        advance(batch, N_EQUIL + N_SAMPLE - done, args.chunk)
+    res = batch.results()
     log(f"batched: {value:.3e} atom-steps/s, {ms_step:.3f} ms/step, kernels {kern}")
     n_atoms = int(batch.atoms)
     batch.close()
 
     # plain path: the same jobs one system at a time with direct launches
     plain_atoms, plain_time = 0, 0.0
-    for j in jobs[:args.plain_sims]:
+    stride = max(1, len(jobs) // max(1, args.plain_sims))
+    plain_jobs = jobs[::stride][:args.plain_sims]  # spread over the batch's heights
+    for j in plain_jobs:
         single = hmd.Batch(ctx, [(j.h, j.g, j.seed, N_SAMPLE)])
         single.run(50, graph_chunk=0)
         torch.cuda.synchronize()
@@ -405,7 +454,7 @@ def main():
         "unit": "atom-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": warm_steps,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -413,9 +462,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched uneven NEMD channels: 64 systems, h=4+16u, g=0.001+0.049u, "
-                               "57.1x57.1 sigma box, rho 0.8, T 1, rc 2.5, dt 0.005, 10k+20k steps, "
-                               "FP32 forces / FP64 state and sums",
-                   "systems": len(jobs), "fluid_atoms": n_atoms, "graph_chunk": args.chunk,
+                               "57.1x57.1 sigma box, rho 0.8, T 1, rc 2.5, dt 0.005, protocol 10k+20k steps, "
+                               f"FP32 forces / FP64 state and sums; timed: {plan['eq']} equilibrating + "
+                               f"{plan['sa']} sampling steps as graph replays of {plan['chunk']} steps"
+                               + (f" (the other equilibration steps untimed)" if plan['skip'] else ""),
+                   "systems": len(jobs), "fluid_atoms": n_atoms, "graph_chunk": plan["chunk"],
                    "force_path": PATH_NAMES[cfg["path"]], "skin": cfg["skin"],
                    "threads_per_block": cfg["tpb"],
                    "list_builds_per_step": builds / args.steps},
@@ -426,9 +477,11 @@ def main():
                      "pairs_per_launch": pairs_per_launch, "flop_per_pair": FLOP_PER_PAIR},
         "plain_atom_steps_per_s": plain,
         "batched_over_plain": value / plain if plain else None,
-        "plain_sample": f"first {args.plain_sims} systems alone, {args.plain_steps} steps each, direct launches",
+        "plain_sample": f"{len(plain_jobs)} systems of the batch (every {stride}th: h = "
+                        f"{', '.join(f'{j.h:.1f}' for j in plain_jobs)}), one at a time, {args.plain_steps} "
+                        "steps each, direct launches",
         "kernel_ms": kern,
-        "kernel_ms_windows": {"first_steps": k_head, "last_steps": k_tail, "equilibrating_steps": n_eq},
+        "kernel_ms_windows": kern_windows,
     }
     if res:
         st = [r["status"] for r in res]

@@ -53,7 +53,7 @@ typedef struct hmd_hybrid hmd_hybrid;
  * hmd_md_params_default() fills the stated defaults:
  *   rho 0.8, T0 1, rc 2.5, eps_wf 1, sigma_wf 1, rho_wall 1, wall_layers 4,
  *   thermo_axis 1 (y), dt 0.005, tau_T 0.1, Lx = Lz = 12 (nominal, snapped to
- *   whole wall cubes), bin_dy 0.25, n_equil 0, n_blocks 20, n_fluid 0
+ *   whole wall cubes), bin_dy 0.25, n_equil 0, n_blocks 0, n_fluid 0
  *   (= round(rho Lx Lz h)), delta 1 (first lattice plane above a wall).
  * ------------------------------------------------------------------------ */
 typedef struct {
@@ -61,6 +61,9 @@ typedef struct {
     int wall_layers, thermo_axis;
     double dt, tau_T, Lx_nom, Lz_nom, bin_dy;
     int64_t n_equil;
+    /* standard error of the sampled flux: 0 = Geyer's initial monotone
+     * sequence estimator over the per-step series (default); 2..1024 = the
+     * standard deviation of that many contiguous block means / sqrt(n) */
     int n_blocks;
     int64_t n_fluid;
     double delta;
@@ -98,8 +101,10 @@ int hmd_get_params(const hmd_ctx* ctx, hmd_md_params* params);
  * F_ext/m - (1/rho) dp/dx), Philox seed, number of sampling steps after
  * params.n_equil equilibration steps.
  * Result: mean mass flow rate per unit span q' = sum(m v_x)/(Lx Lz) over the
- * sampled steps, its standard error from params.n_blocks contiguous block
- * means (Sec. 2.3: noise from the instantaneous data), J = q'/h, the sampled
+ * sampled steps, its standard error from the per-step series (Sec. 2.3: the
+ * noise of a run is the standard deviation of its mean, from the raw
+ * time-instantaneous data; estimator per params.n_blocks, see
+ * md_series_stats), J = q'/h, the sampled
  * kinetic temperatures per component, the potential energy per atom at the
  * end, the fluid atom count and a per-job status (HMD_OK, HMD_EUNSTABLE,
  * HMD_ENOTCONV).
@@ -132,6 +137,17 @@ int md_flux_batch_dev(hmd_ctx* ctx, const hmd_md_job* jobs, int n, double* d_flu
 int md_batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out);
 int md_batch_run(hmd_batch* b, int64_t steps, int graph_chunk);
 int md_batch_results(hmd_batch* b, hmd_md_result* out);
+/* Set the state of one system of a batch (atom id order, n_fluid x 3
+ * doubles each), e.g. a warm start from a stored state; the forces are
+ * recomputed.  The step count and sampling schedule are unchanged. */
+int md_batch_set_state(hmd_batch* b, int sim, const double* x, const double* v);
+/* The sampled flux series q'(t) of one system (Sec. 2.1 flow rate per step):
+ * *n receives its length, q (nullable, *n doubles) the values.  One entry
+ * per sampled step while n_sample <= 65536; beyond, each entry is the mean
+ * of B = ceil(n_sample / 65536) consecutive steps (the first n_sample mod B
+ * sampled steps are left out).  Entries past the steps run so far read 0.
+ * EINVAL for a batch created with n_sample = 0. */
+int md_batch_series(hmd_batch* b, int sim, double* q, int64_t* n);
 /* Fluid atoms summed over the batch (for atom-step rates). */
 int64_t md_batch_atoms(const hmd_batch* b);
 /* Average duration in ms of each kernel over the md_batch_run calls made
@@ -169,6 +185,33 @@ int md_batch_config(const hmd_batch* b, int* path, double* skin, int* tpb, int* 
  * number of candidates. */
 int md_autotune(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int probe_steps, double* table, int* n_rows);
 void md_batch_free(hmd_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Mean and standard error of sampled series (Sec. 2.3: the noise level of an
+ * MD run is the standard deviation of its mean output, estimated from the
+ * raw time-instantaneous data).  x holds S series of n samples each, row k
+ * at x + k ld (ld >= n).  n_blocks = 0: Geyer's initial monotone sequence
+ * estimator (Statistical Science 7 (1992) 473, Sec. 3.3): from the
+ * autocovariances gamma_t = (1/n) sum_{i<n-t} (x_i - mean)(x_{i+t} - mean),
+ * the pair sums gamma_2k + gamma_2k+1 are summed while positive, each
+ * replaced by the smallest so far, sigma^2 = -gamma_0 + 2 sum, SE =
+ * sqrt(sigma^2 / n) (gamma_0 / n when the sum is not positive).  n_blocks in
+ * 2..1024: the standard deviation of n_blocks contiguous block means over
+ * sqrt(n_blocks), a remainder of n mod n_blocks dropped from the front.
+ * out receives 4 doubles per series: mean, SE, mean of the first half,
+ * mean of the second half (of the block means for the block rule).
+ * EINVAL unless 1 <= S <= 65535, n >= 2, ld >= n and n >= n_blocks.  All
+ * arithmetic FP64 on the device; the host form copies x in and out back and
+ * returns when done.
+ * ------------------------------------------------------------------------ */
+int md_series_stats(hmd_ctx* ctx, const double* x, int S, int64_t n, int64_t ld, int n_blocks, double* out);
+/* Device-pointer form: d_x (S rows, stride ld) and d_out (4 S doubles) are
+ * device arrays; queued on `stream` (NULL: the context's stream) without
+ * waiting.  The autocovariances need S n doubles of scratch, which the
+ * context allocates on first use and keeps (growing it waits for the
+ * device); calls of one context on different streams must not overlap. */
+int md_series_stats_dev(hmd_ctx* ctx, const double* d_x, int S, int64_t n, int64_t ld, int n_blocks, double* d_out,
+                        void* stream);
 
 /* ------------------------------------------------------------------------
  * Single-system hooks (tests, checkpoint/restart).  Atom order in every

@@ -89,6 +89,10 @@ _sig("md_batch_list_builds", i32, vp, P(i64))
 _sig("md_batch_get_state", i32, vp, i32, P(d), P(d), P(i64))
 _sig("md_batch_forces", i32, vp, i32, P(_c.c_float), P(d))
 _sig("md_batch_free", None, vp)
+_sig("md_batch_set_state", i32, vp, i32, P(d), P(d))
+_sig("md_batch_series", i32, vp, i32, P(d), P(i64))
+_sig("md_series_stats", i32, vp, P(d), i32, i64, i64, i32, P(d))
+_sig("md_series_stats_dev", i32, vp, vp, i32, i64, i64, i32, vp, vp)
 _sig("md_sys_create", i32, vp, d, d, u64, P(vp))
 _sig("md_sys_info", i32, vp, P(i64), P(i64), P(d), P(i32))
 _sig("md_set_state", i32, vp, P(d), P(d))
@@ -152,7 +156,7 @@ class Params:
     Lz_nom: float = 12.0
     bin_dy: float = 0.25
     n_equil: int = 0
-    n_blocks: int = 20
+    n_blocks: int = 0
     n_fluid: int = 0
     delta: float = 1.0
     force_path: int = -1
@@ -260,6 +264,31 @@ def md_flux_batch_dev(ctx: Context, jobs: Sequence):
     return f, se, st
 
 
+def series_stats(ctx: Context, x, n_blocks: int = 0):
+    """Mean, standard error and half means of each row of x (S x n, or one
+    series of n): an (S, 4) array (a 4-vector for one series)."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    one = a.ndim == 1
+    a = a.reshape(1, -1) if one else a
+    S, n = a.shape
+    out = np.zeros((S, 4))
+    ctx.check(_lib.md_series_stats(ctx.handle, _ptr(a), S, n, n, int(n_blocks), _ptr(out)))
+    return out[0] if one else out
+
+
+def series_stats_dev(ctx: Context, x, n_blocks: int = 0):
+    """series_stats on a CUDA tensor (S x n): a (S, 4) float64 device tensor on
+    the current torch stream."""
+    import torch
+    t = _dev_f64(x)
+    t = t.reshape(1, -1) if t.dim() == 1 else t
+    S, n = t.shape
+    out = torch.empty((S, 4), dtype=torch.float64, device=t.device)
+    ctx.check(_lib.md_series_stats_dev(ctx.handle, vp(t.data_ptr()), S, n, n, int(n_blocks), vp(out.data_ptr()),
+                                       _torch_stream()))
+    return out
+
+
 class Batch:
     """Staged batch (md_batch_*): create, run, results, per-kernel timing."""
 
@@ -304,6 +333,22 @@ class Batch:
         x, v = np.zeros((n, 3)), np.zeros((n, 3))
         self.ctx.check(_lib.md_batch_get_state(self._h, int(sim), _ptr(x), _ptr(v), None))
         return x, v
+
+    def set_state(self, sim: int, x, v):
+        n = self.n_fluid(sim)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        if x.shape != (n, 3) or v.shape != (n, 3):
+            raise HmdError(HMD_EINVAL, f"state of system {sim} needs ({n}, 3) arrays")
+        self.ctx.check(_lib.md_batch_set_state(self._h, int(sim), _ptr(x), _ptr(v)))
+
+    def series(self, sim: int):
+        """The sampled flux series q'(t) of one system."""
+        n = i64()
+        self.ctx.check(_lib.md_batch_series(self._h, int(sim), None, _c.byref(n)))
+        q = np.zeros(n.value)
+        self.ctx.check(_lib.md_batch_series(self._h, int(sim), _ptr(q), _c.byref(n)))
+        return q
 
     def forces(self, sim: int):
         f = np.zeros((self.n_fluid(sim), 3), dtype=np.float32)

@@ -29,6 +29,7 @@ SOURCES = [
     ("md_setup.cpp", "host"),
     ("md_kernels.hip", "hip"),
     ("md_engine.hip", "hip"),
+    ("series.hip", "hip"),
     ("abi.cpp", "hip"),
     ("tune.cpp", "hip"),
     ("gp.hip", "hip"),

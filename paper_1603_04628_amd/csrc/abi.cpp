@@ -2,12 +2,14 @@
 // declarations and their contracts are in include/hmd.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <new>
 #include <vector>
 
 #include "engine.h"
+#include "series.h"
 
 namespace {
 
@@ -39,7 +41,7 @@ void hmd_md_params_default(hmd_md_params* p) {
   p->wall_layers = 4; p->thermo_axis = 1;
   p->dt = 0.005; p->tau_T = 0.1;
   p->Lx_nom = 12.0; p->Lz_nom = 12.0; p->bin_dy = 0.25;
-  p->n_equil = 0; p->n_blocks = 20; p->n_fluid = 0; p->delta = 1.0;
+  p->n_equil = 0; p->n_blocks = 0; p->n_fluid = 0; p->delta = 1.0;
   p->force_path = -1; p->skin = 0.3; p->cell_w = 0.0;
 }
 
@@ -75,10 +77,12 @@ int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ct
 
 void hmd_destroy(hmd_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->own_stream && ctx->stream) {
-    (void)hipSetDevice(ctx->device);
-    (void)hipStreamDestroy(ctx->stream);
+  (void)hipSetDevice(ctx->device);
+  if (ctx->d_series_scratch) {  // md_series_stats_dev may have used another stream
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->d_series_scratch);
   }
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -165,7 +169,71 @@ int md_batch_list_builds(hmd_batch* b, int64_t* builds) {
   return guarded(b->ctx, [&] { return hmd::batch_list_builds(b, builds); });
 }
 
+int md_batch_set_state(hmd_batch* b, int sim, const double* x, const double* v) {
+  if (!b || sim < 0 || sim >= b->S || !x || !v) return HMD_EINVAL;
+  return guarded(b->ctx, [&] { return hmd::batch_set_state(b, sim, x, v); });
+}
+
+int md_batch_series(hmd_batch* b, int sim, double* q, int64_t* n) {
+  if (!b) return HMD_EINVAL;
+  return guarded(b->ctx, [&] { return hmd::batch_series(b, sim, q, n); });
+}
+
 void md_batch_free(hmd_batch* b) { hmd::batch_free(b); }
+
+int md_series_stats(hmd_ctx* ctx, const double* x, int S, int64_t n, int64_t ld, int n_blocks, double* out) {
+  if (!ctx || !x || !out) return HMD_EINVAL;
+  HMD_TRY(hmd::series_stats_check(S, n, ld, n_blocks, ctx->err));
+  return guarded(ctx, [&]() -> int {
+    HMD_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    double *dx = nullptr, *dg = nullptr, *dout = nullptr;
+    auto release = [&] {
+      if (dx) (void)hipFree(dx);
+      if (dg) (void)hipFree(dg);
+      if (dout) (void)hipFree(dout);
+    };
+    const size_t nx = size_t(S) * size_t(ld), ng = n_blocks == 0 ? size_t(S) * size_t(n) : 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&dx), 8 * nx);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&dg), 8 * ng);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&dout), 8 * 4 * size_t(S));
+    if (e == hipSuccess) e = hipMemcpyAsync(dx, x, 8 * nx, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      hmd::series_stats_enqueue(s, dx, S, n, ld, 1.0, n_blocks, dg, dout);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 8 * 4 * size_t(S), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    release();
+    if (e != hipSuccess) {
+      ctx->err = std::string("md_series_stats: ") + hipGetErrorString(e);
+      return e == hipErrorOutOfMemory ? HMD_ENOMEM : HMD_EDEVICE;
+    }
+    return HMD_OK;
+  });
+}
+
+int md_series_stats_dev(hmd_ctx* ctx, const double* d_x, int S, int64_t n, int64_t ld, int n_blocks, double* d_out,
+                        void* stream) {
+  if (!ctx || !d_x || !d_out) return HMD_EINVAL;
+  HMD_TRY(hmd::series_stats_check(S, n, ld, n_blocks, ctx->err));
+  return guarded(ctx, [&]() -> int {
+    HMD_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    const int64_t need = n_blocks == 0 ? int64_t(S) * n : 1;
+    if (need > ctx->series_scratch_n) {  // grows; earlier work on the scratch must be done first
+      HMD_HIP(ctx, hipDeviceSynchronize());
+      if (ctx->d_series_scratch) HMD_HIP(ctx, hipFree(ctx->d_series_scratch));
+      ctx->d_series_scratch = nullptr;
+      ctx->series_scratch_n = 0;
+      HMD_HIP(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->d_series_scratch), 8 * size_t(need)));
+      ctx->series_scratch_n = need;
+    }
+    hmd::series_stats_enqueue(s, d_x, S, n, ld, 1.0, n_blocks, ctx->d_series_scratch, d_out);
+    HMD_HIP(ctx, hipGetLastError());
+    return HMD_OK;
+  });
+}
 
 int md_flux_batch(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_md_result* out) {
   if (!ctx || !jobs || !out || n < 1) {
@@ -176,8 +244,8 @@ int md_flux_batch(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_md_result* ou
     // one batch per distinct sampling length
     std::map<int64_t, std::vector<int>> groups;
     for (int k = 0; k < n; ++k) {
-      if (jobs[k].n_sample < ctx->params.n_blocks) {
-        ctx->err = "md_flux_batch: n_sample must be >= n_blocks";
+      if (jobs[k].n_sample < std::max(2, ctx->params.n_blocks)) {
+        ctx->err = "md_flux_batch: n_sample must be at least max(2, n_blocks)";
         return HMD_EINVAL;
       }
       groups[jobs[k].n_sample].push_back(k);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -17,8 +18,11 @@ struct hmd_ctx {
   bool own_stream = false;
   hmd_md_params params{};
   std::string err;
-  // tuned choices keyed by a workload signature (see tune.hip)
+  // tuned choices keyed by a workload signature (see tune.cpp)
   std::map<std::string, std::vector<double>> tuned;
+  // device scratch of md_series_stats_dev (autocovariances), grown on demand
+  double* d_series_scratch = nullptr;
+  int64_t series_scratch_n = 0;
 };
 
 namespace hmd {
@@ -83,7 +87,8 @@ struct Acc {
   double* vc2[2];   // sum v_c^2 after the second half-kick, by step parity
   double* pe[2];    // sum of per-atom potential energy, by step parity
   double* ke[2];    // sum |v|^2 after the second half-kick, by step parity
-  double* blocks;   // [S * nb] block sums of q'
+  double* blocks;   // [S * nb] the sampled q' series: entry k of a system holds the sum of
+                    // B consecutive steps' q' (B = 1 unless n_sample exceeds the series cap)
   double* tsum;     // [S * 3] sums of T_a over sampled steps
   double* binvx;    // [bins] sum v_x
   double* bincnt;   // [bins] counts
@@ -94,6 +99,8 @@ struct Acc {
 };
 
 enum Kern { K_INTEGRATE = 0, K_SCAN, K_SCATTER, K_REORDER, K_FORCE, K_KEYS, K_LIST, K_COUNT };
+constexpr int kStampedSteps = 5;  // steps per timed graph replay whose kernels are stamped
+constexpr int kMaxStamps = 64;     // stamps of one timed replay (kernels + 1 per stamped step, + 1)
 
 }  // namespace hmd
 
@@ -102,6 +109,12 @@ struct hmd_batch {
   hmd_md_params P{};
   int S = 0;
   int64_t n_sample = 0;
+  // sampled series per system: nser entries of ser_B steps each, the first
+  // ser_r sampled steps left out (ser_B = 1 and ser_r = 0 up to the cap)
+  int64_t nser = 1;
+  int ser_B = 1 << 30, ser_r = 0;
+  double* d_gam = nullptr;   // [S * nser] autocovariances (results)
+  double* d_sout = nullptr;  // [S * 4] mean, SE, half means (results)
   int path = 1;           // 0 cell path, 1 pair path
   int tpb = 256;          // threads per block of the per-slot kernels
   double skin = 0.3;
@@ -156,6 +169,11 @@ struct hmd_batch {
 
   std::map<int, hipGraphExec_t> graphs;  // key -> executable graph
   std::map<int, hipGraph_t> graph_defs;
+  // timed graphs: (kernel, stamp before, stamp after) of the stamped steps
+  std::map<int, std::vector<std::array<int, 3>>> graph_spans;
+  std::map<int, int> graph_nstamps;
+  unsigned long long* d_stamps = nullptr;  // [kMaxStamps] wall-clock stamps of a timed replay
+  double clock_khz = 0.0;                  // device wall-clock rate
 
   bool timing = false;
   std::vector<hipEvent_t> ev;             // event pool for timing
@@ -181,6 +199,7 @@ int batch_cells(hmd_batch* b, int sim, uint32_t* cell_of, uint32_t* counts, uint
 int batch_profile(hmd_batch* b, int sim, double* mvx, double* cnt);
 int batch_pairs(hmd_batch* b, int64_t* ff, int64_t* wf);
 int batch_list_builds(hmd_batch* b, int64_t* builds);
+int batch_series(hmd_batch* b, int sim, double* q, int64_t* n);
 int batch_neighbors(hmd_batch* b, int sim, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total);
 // Resolved implementation choices for a batch of these jobs on this context.
 void choose_path(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int* path, double* skin, int* tpb);

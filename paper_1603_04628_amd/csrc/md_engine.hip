@@ -4,12 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 
 #include "engine.h"
 #include "md_kernels.h"
+#include "series.h"
 
 namespace hmd {
 
@@ -41,14 +43,9 @@ StepConst step_const(const hmd_batch* b, bool thermostat, bool energy) {
   K.ush_wf = float(4.0 * P.eps_wf * (sw6 * sw6 - sw6));
   K.half_skin2 = float(0.25 * b->skin * b->skin);
   K.axis = P.thermo_axis;
-  K.nb = P.n_blocks;
-  if (b->n_sample > 0) {
-    K.B = int(b->n_sample / P.n_blocks);
-    K.r = int(b->n_sample - int64_t(K.B) * P.n_blocks);
-  } else {  // open-ended runs: every sample lands in block 0
-    K.B = 1 << 30;
-    K.r = 0;
-  }
+  K.nb = int(b->nser);
+  K.B = b->ser_B;
+  K.r = b->ser_r;
   K.thermo_on = thermostat ? 1 : 0;
   K.bins_on = 1;
   K.energy_on = energy ? 1 : 0;
@@ -78,20 +75,39 @@ uint32_t fix_axis_host(double v, double scale) {
   return uint32_t(t);
 }
 
-// Launches of one kind, optionally bracketed by timing events.
+// Launches of one kind, optionally timed.  Direct launches: HIP events
+// around each kernel (marks).  Captured graphs, where events cannot be timed:
+// stamp kernels writing the device wall clock into b->d_stamps, one before a
+// stamped step's first kernel and one after each of its kernels; spans
+// records (kernel, stamp before, stamp after).
 struct Launcher {
   hmd_batch* b;
   hipStream_t s;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* marks;  // null: untimed
   int next_ev = 0;
+  std::vector<std::array<int, 3>>* spans = nullptr;  // non-null: stamp mode
+  int next_stamp = 0, last_stamp = -1;
 
+  void stamp() {
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, b->d_stamps + next_stamp);
+    last_stamp = next_stamp++;
+  }
   void begin(int k) {
+    if (spans) {
+      if (last_stamp < 0) stamp();
+      spans->push_back({k, last_stamp, next_stamp});
+      return;
+    }
     if (!marks) return;
     hipEvent_t e0 = b->ev[next_ev++], e1 = b->ev[next_ev++];
     (void)hipEventRecord(e0, s);
     marks->push_back({k, {e0, e1}});
   }
   void end() {
+    if (spans) {
+      stamp();
+      return;
+    }
     if (!marks) return;
     (void)hipEventRecord(marks->back().second.second, s);
   }
@@ -257,6 +273,8 @@ void release_graphs(hmd_batch* b) {
   for (auto& kv : b->graph_defs) (void)hipGraphDestroy(kv.second);
   b->graphs.clear();
   b->graph_defs.clear();
+  b->graph_spans.clear();
+  b->graph_nstamps.clear();
 }
 
 int ensure_events(hmd_batch* b, size_t n) {
@@ -282,9 +300,12 @@ int harvest(hmd_batch* b, std::vector<std::pair<int, std::pair<hipEvent_t, hipEv
 }
 
 // Executable graph of `chunk` steps; its step indices are read from
-// d_dstate[0], which its last node advances by `chunk`.
+// d_dstate[0], which its last node advances by `chunk`.  With timing on, the
+// kernels of up to kStampedSteps evenly spaced steps (the last one among
+// them) are bracketed by stamp kernels, and one more stamp after the last
+// measures the gap of an empty interval.
 int get_graph(hmd_batch* b, int chunk, const StepConst& K, hipGraphExec_t* out) {
-  const int key = chunk * 2 + (K.thermo_on ? 1 : 0);
+  const int key = chunk * 4 + (K.thermo_on ? 1 : 0) + (b->timing ? 2 : 0);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;
@@ -293,9 +314,21 @@ int get_graph(hmd_batch* b, int chunk, const StepConst& K, hipGraphExec_t* out) 
   hmd_ctx* ctx = b->ctx;
   hipStream_t s = ctx->stream;
   const int cur0 = b->cur;
+  auto& spans = b->graph_spans[key];
+  spans.clear();
+  const int every = std::max(1, chunk / kStampedSteps);
   Launcher L{b, s, nullptr, 0};
   HMD_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < chunk; ++k) enqueue_step(b, L, K, StepRef{b->d_dstate, k});
+  for (int k = 0; k < chunk; ++k) {
+    const bool stamped = b->timing && (chunk - 1 - k) % every == 0 && (chunk - 1 - k) / every < kStampedSteps;
+    L.spans = stamped ? &spans : nullptr;
+    L.last_stamp = -1;
+    enqueue_step(b, L, K, StepRef{b->d_dstate, k});
+  }
+  if (b->timing) {  // calibration: an empty interval after the last stamp
+    L.spans = &spans;
+    L.stamp();
+  }
   hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, s, b->d_dstate, int64_t(chunk));
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
@@ -304,6 +337,7 @@ int get_graph(hmd_batch* b, int chunk, const StepConst& K, hipGraphExec_t* out) 
     ctx->err = std::string("graph capture: ") + hipGetErrorString(e);
     return HMD_EDEVICE;
   }
+  if (b->timing) b->graph_nstamps[key] = L.next_stamp;
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
@@ -377,13 +411,20 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   b->P = ctx->params;
   b->S = n;
   b->n_sample = jobs[0].n_sample;
+  const int64_t min_sample = std::max(2, b->P.n_blocks);
   for (int k = 0; k < n; ++k)
     if (jobs[k].n_sample != b->n_sample || jobs[k].n_sample < 0 ||
-        (jobs[k].n_sample > 0 && jobs[k].n_sample < b->P.n_blocks)) {
-      ctx->err = "md batch: every job needs the same n_sample (0 or >= n_blocks)";
+        (jobs[k].n_sample > 0 && jobs[k].n_sample < min_sample)) {
+      ctx->err = "md batch: every job needs the same n_sample (0, or at least max(2, n_blocks))";
       delete b;
       return HMD_EINVAL;
     }
+  if (b->n_sample > 0) {  // one series entry per sampled step up to the cap, then groups of B steps
+    const int64_t B = (b->n_sample + kSeriesCap - 1) / kSeriesCap;
+    b->ser_B = int(B);
+    b->nser = b->n_sample / B;
+    b->ser_r = int(b->n_sample - b->nser * B);
+  }
   choose_path(ctx, jobs, n, &b->path, &b->skin, &b->tpb);
   if (b->path == 3) {  // the tiled path with every tile on its gather fallback
     b->path = 2;
@@ -473,7 +514,8 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
       (rc = dalloc(ctx, &b->d_wpos4, b->nwall)) || (rc = dalloc(ctx, &b->d_wstart, b->nwcell)) ||
       (rc = dalloc(ctx, &b->d_wcount, b->nwcell)) || (rc = dalloc(ctx, &b->d_dstate, 4)) ||
       (rc = dalloc(ctx, &b->d_tag[0], b->ntot)) || (rc = dalloc(ctx, &b->d_tag[1], b->ntot)) ||
-      (rc = dalloc(ctx, &b->d_flag, 4)))
+      (rc = dalloc(ctx, &b->d_flag, 4)) ||
+      (rc = dalloc(ctx, &b->d_stamps, kMaxStamps)))
     return fail(rc);
   if (b->path == 0) {
     if ((rc = dalloc(ctx, &b->d_pos4, b->ntot))) return fail(rc);
@@ -511,15 +553,17 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap, b->cell_rank.data(), 4 * b->ncell, hipMemcpyHostToDevice, ctx->stream));
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap + b->ncell, cell_lin.data(), 4 * b->ncell, hipMemcpyHostToDevice,
                               ctx->stream));
-  const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->P.n_blocks + 3 * int64_t(n) + 2 * b->nbins;
+  const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->nser + 3 * int64_t(n) + 2 * b->nbins;
   if ((rc = dalloc(ctx, &b->d_accbuf, nacc)) || (rc = dalloc(ctx, &b->d_status, n)) ||
-      (rc = dalloc(ctx, &b->acc.pairs, 2)))
+      (rc = dalloc(ctx, &b->acc.pairs, 2)) || (rc = dalloc(ctx, &b->d_sout, 4 * int64_t(n))))
+    return fail(rc);
+  if (b->n_sample > 0 && b->P.n_blocks == 0 && (rc = dalloc(ctx, &b->d_gam, int64_t(n) * b->nser)))
     return fail(rc);
   double* q = b->d_accbuf;
   for (int p = 0; p < 2; ++p) { b->acc.vc2[p] = q; q += n; }
   for (int p = 0; p < 2; ++p) { b->acc.pe[p] = q; q += n; }
   for (int p = 0; p < 2; ++p) { b->acc.ke[p] = q; q += n; }
-  b->acc.blocks = q; q += int64_t(n) * b->P.n_blocks;
+  b->acc.blocks = q; q += int64_t(n) * b->nser;
   b->acc.tsum = q; q += 3 * int64_t(n);
   b->acc.binvx = q; q += b->nbins;
   b->acc.bincnt = q;
@@ -619,7 +663,7 @@ void batch_free(hmd_batch* b) {
                   b->d_slot_cell, b->d_list, b->d_nlist, b->d_flag, b->d_key, b->d_count, b->d_rank, b->d_start,
                   b->d_ncount, b->d_perm, b->d_wpos4, b->d_wstart, b->d_wcount, b->d_dstate, b->d_tag[0],
                   b->d_tag[1], b->d_accbuf, b->d_status, b->acc.pairs, b->d_cellmap, b->d_tiles,
-                  b->d_tilerec, b->d_tbins};
+                  b->d_tilerec, b->d_tbins, b->d_gam, b->d_sout, b->d_stamps};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int w = 0; w < 2; ++w)
@@ -675,6 +719,16 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
     }
     hipGraphExec_t ex = nullptr;
     HMD_TRY(get_graph(b, graph_chunk, K, &ex));
+    const int gkey = graph_chunk * 4 + (K.thermo_on ? 1 : 0) + (b->timing ? 2 : 0);
+    if (b->timing && b->clock_khz <= 0.0) {
+      int khz = 0;
+      HMD_HIP(ctx, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+      if (khz <= 0) {
+        ctx->err = "md run: the device reports no wall-clock rate for timed graph replays";
+        return HMD_EDEVICE;
+      }
+      b->clock_khz = double(khz);
+    }
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate, b->done);
     while (steps - k >= graph_chunk) {
       if (b->timing) {
@@ -687,6 +741,18 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
         HMD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
         b->graph_ms += ms;
         b->graph_steps += graph_chunk;
+        // the stamped steps of the replay: each kernel's time is the span
+        // between its stamps less the gap of the empty interval at the end
+        const auto& spans = b->graph_spans[gkey];
+        const int ns = b->graph_nstamps[gkey];
+        unsigned long long st[kMaxStamps];
+        HMD_HIP(ctx, hipMemcpy(st, b->d_stamps, sizeof(unsigned long long) * size_t(ns), hipMemcpyDeviceToHost));
+        const double gap = double(st[ns - 1] - st[ns - 2]);
+        for (const auto& sp : spans) {
+          const double ticks = std::max(0.0, double(st[sp[2]] - st[sp[1]]) - gap);
+          b->kern_ms[sp[0]] += ticks / b->clock_khz;
+          b->kern_n[sp[0]] += 1;
+        }
       } else {
         HMD_HIP(ctx, hipGraphLaunch(ex, s));
       }
@@ -706,19 +772,24 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
   hmd_ctx* ctx = b->ctx;
   HMD_HIP(ctx, hipSetDevice(ctx->device));
   HMD_TRY(forces_now(b, true));
-  const int n = b->S, nb = b->P.n_blocks;
-  std::vector<double> blocks(size_t(n) * nb), tsum(3 * size_t(n)), pe(n);
+  const int n = b->S;
+  // the sampling window is complete once every one of its n_sample steps ran
+  const bool complete = b->n_sample > 0 && b->done - b->P.n_equil >= b->n_sample;
+  hipStream_t s = ctx->stream;
+  if (complete)
+    series_stats_enqueue(s, b->acc.blocks, n, b->nser, b->nser, 1.0 / double(b->ser_B), b->P.n_blocks, b->d_gam,
+                         b->d_sout);
+  std::vector<double> sout(4 * size_t(n)), tsum(3 * size_t(n)), pe(n);
   std::vector<int> status(n);
   int flags[4] = {0, 0, 0, 0};
-  hipStream_t s = ctx->stream;
-  HMD_HIP(ctx, hipMemcpyAsync(blocks.data(), b->acc.blocks, 8 * blocks.size(), hipMemcpyDeviceToHost, s));
+  if (complete)
+    HMD_HIP(ctx, hipMemcpyAsync(sout.data(), b->d_sout, 8 * sout.size(), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(tsum.data(), b->acc.tsum, 8 * tsum.size(), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(pe.data(), b->acc.pe[(b->done + 1) & 1], 8 * size_t(n), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(status.data(), b->d_status, 4 * size_t(n), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipMemcpyAsync(flags, b->d_flag, sizeof(flags), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
-  const int64_t used = b->n_sample > 0 ? (b->n_sample / nb) * nb : 0;
-  const int64_t sampled = std::max<int64_t>(0, std::min(b->done - b->P.n_equil, used));
+  HMD_HIP(ctx, hipGetLastError());
   for (int k = 0; k < n; ++k) {
     hmd_md_result& R = out[k];
     std::memset(&R, 0, sizeof(R));
@@ -727,29 +798,17 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
     R.pe = pe[k] * D.inv_nf;
     // an overflowing pair list drops interactions: every result is suspect
     int st = (status[k] & 1) || flags[2] > 0 ? HMD_EUNSTABLE : HMD_OK;
-    if (b->n_sample > 0 && sampled == used) {
-      const double B = double(b->n_sample / nb);
-      std::vector<double> bm(nb);
-      double mean = 0.0;
-      for (int j = 0; j < nb; ++j) {
-        bm[j] = blocks[size_t(k) * nb + j] / B;
-        mean += bm[j];
-      }
-      mean /= double(nb);
-      double var = 0.0;
-      for (int j = 0; j < nb; ++j) var += (bm[j] - mean) * (bm[j] - mean);
-      var /= double(nb - 1);
-      R.flux = mean;
-      R.flux_se = std::sqrt(var / double(nb));
-      R.jflux = mean / D.h;
-      for (int a = 0; a < 3; ++a) R.T[a] = tsum[3 * k + a] / double(used);
-      const int h1 = nb / 2;
-      double m1 = 0.0, m2 = 0.0;
-      for (int j = 0; j < h1; ++j) m1 += bm[j];
-      for (int j = h1; j < nb; ++j) m2 += bm[j];
-      m1 /= double(h1);
-      m2 /= double(nb - h1);
-      if (st == HMD_OK && (std::fabs(m2 - m1) > 8.0 * R.flux_se || R.T[2] > 1.5 * b->P.T0)) st = HMD_ENOTCONV;
+    if (complete) {
+      const double* so = &sout[4 * size_t(k)];
+      R.flux = so[0];
+      R.flux_se = so[1];
+      R.jflux = so[0] / D.h;
+      // temperatures are summed over every sampled step
+      for (int a = 0; a < 3; ++a) R.T[a] = tsum[3 * k + a] / double(b->n_sample);
+      // non-convergence (critical shear, Sec. 3.2): the two halves of the
+      // series differ by more than 8 SE, or the spanwise temperature runs away
+      if (st == HMD_OK && (std::fabs(so[3] - so[2]) > 8.0 * R.flux_se || R.T[2] > 1.5 * b->P.T0))
+        st = HMD_ENOTCONV;
     } else if (st == HMD_OK) {
       st = HMD_EINVAL;  // sampling window not complete
     }
@@ -758,6 +817,22 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
   if (flags[2] > 0)
     ctx->err = flags[2] >= (1 << 30) ? std::string("pair list build: a cell holds more than 255 atoms")
                                      : "pair list overflow: " + std::to_string(flags[2]) + " > capacity";
+  return HMD_OK;
+}
+
+// The sampled q' series of one system: nser entries (each the mean of ser_B
+// consecutive sampled steps), as far as sampling has reached.
+int batch_series(hmd_batch* b, int sim, double* q, int64_t* n) {
+  hmd_ctx* ctx = b->ctx;
+  if (sim < 0 || sim >= b->S || b->n_sample <= 0) {
+    ctx->err = "md series: need a valid system of a batch with n_sample > 0";
+    return HMD_EINVAL;
+  }
+  if (n) *n = b->nser;
+  if (!q) return HMD_OK;
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  HMD_HIP(ctx, hipMemcpy(q, b->acc.blocks + int64_t(sim) * b->nser, 8 * size_t(b->nser), hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < b->nser; ++k) q[k] /= double(b->ser_B);
   return HMD_OK;
 }
 

@@ -71,6 +71,7 @@ template <int MODE, int ENERGY, int UNI, int WS>
 __global__ void k_force_tiles(int ntot, int ld, const uint32_t* tilerec, const SimDev* sims, const int4* pfix,
                               const uint32_t* list, const uint32_t* nlist, float4* f4, StateRef st, Acc acc,
                               int64_t* dstate, StepRef R, StepConst K);
+__global__ void k_stamp(unsigned long long* slot);
 __global__ void k_set_i64(int64_t* p, int64_t v);
 __global__ void k_add_i64(int64_t* p, int64_t v);
 __global__ void k_set_i32(int* p, int v);

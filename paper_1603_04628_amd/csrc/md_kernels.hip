@@ -1465,6 +1465,12 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
   }
 }
 
+// One timestamp of the device's constant-rate wall clock (timed graph
+// replays bracket each kernel of a step with these).
+__global__ void k_stamp(unsigned long long* slot) {
+  if (threadIdx.x == 0) *slot = (unsigned long long)wall_clock64();
+}
+
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
 __global__ void k_add_i64(int64_t* p, int64_t v) { *p += v; }
 __global__ void k_set_i32(int* p, int v) { *p = v; }

@@ -267,7 +267,7 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(hmd.HmdError):
         hmd.System(ctx, 1.0, 0.0, 0)  # h below twice the start gap
     with pytest.raises(hmd.HmdError):
-        hmd.md_flux_batch(ctx, [(6.0, 0.0, 0, 5)])  # fewer samples than blocks
+        hmd.md_flux_batch(ctx, [(6.0, 0.0, 0, 1)])  # one sample has no standard error
     with pytest.raises(hmd.HmdError):
         hmd.System(hmd.Context(hmd.Params(thermo_axis=0, **SMALL_L)), 6.0, 0.0, 0)  # thermostat on the flow
 
@@ -330,3 +330,25 @@ def test_full_batch_sampled_outputs_hold_invariants():
         if k in strong:
             assert r["flux"] > 3.0 * r["flux_se"], k
         assert r["jflux"] == pytest.approx(r["flux"] / j.h, rel=1e-12), k
+
+
+def test_timed_graph_replays_report_kernel_times():
+    # with timing on, each graph replay stamps the device clock around the
+    # kernels of five of its steps: every kernel gets a positive time and
+    # their sum stays within the replay's time per step
+    params = dict(n_equil=10000, **workloads.batch_box())
+    ctx = hmd.Context(hmd.Params(skin=0.35, **params))
+    jobs = workloads.batch_jobs(8)
+    b = hmd.Batch(ctx, [(j.h, j.g, j.seed, 20000) for j in jobs])
+    b.run(20, graph_chunk=20)
+    b.set_timing(True)
+    b.run(200, graph_chunk=20)
+    step_ms, nsteps = b.kernel_ms("graph_step")
+    assert nsteps == 200 and step_ms > 0.0
+    total = 0.0
+    for k in ("integrate", "keys", "scan", "scatter", "reorder", "list", "force"):
+        ms, n = b.kernel_ms(k)
+        assert n == 50 and ms > 0.0, k
+        total += ms
+    assert total <= 1.05 * step_ms
+    assert b.kernel_ms("force")[0] > 0.2 * step_ms

@@ -1,0 +1,156 @@
+"""Mean and standard error of sampled flux series on the device, against the
+oracle's estimator (Sec. 2.3: the noise of an MD run is the standard deviation
+of its mean, estimated from the raw time-instantaneous data), and the per-step
+flux series of the MD path against the oracle's from one identical state.
+
+Bars: the device statistics of a given series equal the oracle's to 1e-10
+relative (FP64 sums in another order); the per-step flux from identical states
+differs only by FP32 force rounding; the SE a run reports is the oracle's
+estimator applied to that run's own series.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+hmd = pytest.importorskip("paper_1603_04628_amd")
+from paper_1603_04628_amd import binding as B  # noqa: E402
+from oracle import md as omd  # noqa: E402
+from oracle import stats as ostats  # noqa: E402
+import workloads  # noqa: E402
+
+SMALL_L = dict(Lx_nom=workloads.BOX_SMALL_LITERAL, Lz_nom=workloads.BOX_SMALL_LITERAL)
+
+
+def _ar1(seed, phi, n):
+    rng = np.random.default_rng(seed)
+    e = rng.standard_normal(n)
+    x = np.empty(n)
+    x[0] = e[0] / np.sqrt(1.0 - phi * phi)
+    for t in range(1, n):
+        x[t] = phi * x[t - 1] + e[t]
+    return 0.3 + 0.01 * x
+
+
+@pytest.mark.parametrize("n", [2, 3, 257, 1000, 20000])
+def test_series_stats_match_oracle(n):
+    # four rows (iid, short and long correlation, anti-correlated) in one call;
+    # lengths below, at and across the 256-lag tiles, ragged tails included
+    ctx = hmd.Context(hmd.Params(**SMALL_L))
+    rows = np.stack([_ar1(1, 0.0, n), _ar1(2, 0.9, n), _ar1(3, 0.995, n), _ar1(4, -0.5, n)])
+    out = B.series_stats(ctx, rows)
+    for k, r in enumerate(rows):
+        m, se = ostats.geyer(r)
+        h1, h2 = ostats.halves(r)
+        assert out[k, 0] == pytest.approx(m, rel=1e-12)
+        assert out[k, 1] == pytest.approx(se, rel=1e-10), (k, out[k, 1], se)
+        assert out[k, 2] == pytest.approx(h1, rel=1e-12)
+        assert out[k, 3] == pytest.approx(h2, rel=1e-12)
+    if n >= 20:
+        outb = B.series_stats(ctx, rows, n_blocks=20)
+        for k, r in enumerate(rows):
+            m, se = ostats.blocks(r, 20)
+            assert outb[k, 0] == pytest.approx(m, rel=1e-12)
+            assert outb[k, 1] == pytest.approx(se, rel=1e-10)
+
+
+def test_series_stats_row_stride_and_dev_form():
+    import torch
+    ctx = hmd.Context(hmd.Params(**SMALL_L))
+    rows = np.stack([_ar1(7 + k, 0.8, 3001) for k in range(3)])
+    host = B.series_stats(ctx, rows)
+    dev = B.series_stats_dev(ctx, torch.from_numpy(rows).cuda())
+    torch.cuda.synchronize()
+    assert np.allclose(dev.cpu().numpy(), host, rtol=1e-14, atol=0)
+    # a larger call after a smaller one grows the context's scratch
+    big = np.stack([_ar1(20 + k, 0.95, 6000) for k in range(5)])
+    dev2 = B.series_stats_dev(ctx, torch.from_numpy(big).cuda())
+    torch.cuda.synchronize()
+    for k, r in enumerate(big):
+        assert dev2[k, 1].item() == pytest.approx(ostats.geyer(r)[1], rel=1e-10)
+
+
+def test_series_stats_rejects_bad_sizes():
+    ctx = hmd.Context(hmd.Params(**SMALL_L))
+    with pytest.raises(hmd.HmdError):
+        B.series_stats(ctx, np.zeros(1))
+    with pytest.raises(hmd.HmdError):
+        B.series_stats(ctx, np.zeros(10), n_blocks=20)
+    with pytest.raises(hmd.HmdError):
+        B.series_stats(ctx, np.zeros(10), n_blocks=1)
+
+
+@pytest.mark.parametrize("path", [0, 1, 2])
+def test_flux_series_from_identical_state(path):
+    # Sec. 2.1: every sampled step gives q' = sum(m v_x) / (Lx Lz).  From one
+    # equilibrated state, 60 sampled steps on each side differ only by FP32
+    # force rounding: each step's q' agrees far below the scale of the sum
+    # (sum |v_x| / (Lx Lz)), which pins the normalisation and the step index
+    pre = omd.System(6.0, 0.05, 7, omd.Params(**SMALL_L))
+    pre.run(300)
+    x, v = pre.get_state()
+    n = 60
+    params = dict(n_equil=0, **SMALL_L)
+    ora = omd.System(6.0, 0.05, 7, omd.Params(cell_w=2.8 if path else 0.0, **params))
+    ora.set_state(x, v)
+    ora.run(n)
+    qo = ora.series()
+    ctx = hmd.Context(hmd.Params(force_path=path, skin=0.3, **params))
+    b = hmd.Batch(ctx, [(6.0, 0.05, 7, n)])
+    b.set_state(0, x, v)
+    b.run(n, graph_chunk=20)
+    qg = b.series(0)
+    assert len(qg) == n == len(qo)
+    scale = np.abs(v[:, 0]).sum() / (ora.Lx * ora.Lz)
+    assert np.abs(qg - qo).max() <= 1e-6 * scale, np.abs(qg - qo).max() / scale
+    # the first step's q' follows from the given velocities and forces alone
+    assert abs(qg[0] - qo[0]) <= 1e-7 * scale
+    r = b.results()[0]
+    ro = ora.result()
+    assert r["status"] == 0 and ro["status"] == 0
+    assert r["flux"] == pytest.approx(ro["flux"], abs=1e-6 * scale)
+    assert r["T"][1] == pytest.approx(ro["T"][1], rel=1e-5)
+
+
+def test_results_se_is_the_oracle_estimator_of_the_run_series():
+    # the SE a run reports is Geyer's estimator of its own series, exactly
+    params = dict(n_equil=200, **SMALL_L)
+    ctx = hmd.Context(hmd.Params(**params))
+    jobs = [(6.0, 0.05, 3, 3000), (4.5, 0.02, 4, 3000), (9.0, 0.01, 5, 3000)]
+    b = hmd.Batch(ctx, jobs)
+    b.run(3200, graph_chunk=100)
+    res = b.results()
+    for k, r in enumerate(res):
+        q = b.series(k)
+        m, se = ostats.geyer(q)
+        h1, h2 = ostats.halves(q)
+        assert r["flux"] == pytest.approx(m, rel=1e-12)
+        assert r["flux_se"] == pytest.approx(se, rel=1e-9)
+        assert r["status"] in (0, -5)
+        if r["status"] == -5:
+            assert abs(h2 - h1) > 8.0 * se
+
+
+def test_incomplete_window_is_not_a_result():
+    # results before every sampling step has run carry HMD_EINVAL
+    ctx = hmd.Context(hmd.Params(n_equil=50, **SMALL_L))
+    b = hmd.Batch(ctx, [(6.0, 0.02, 1, 101)])
+    b.run(150, graph_chunk=0)  # one sampling step short
+    assert b.results()[0]["status"] == -1
+    b.run(1, graph_chunk=0)
+    assert b.results()[0]["status"] in (0, -5)
+
+
+def test_long_window_groups_steps():
+    # beyond 65,536 sampled steps each series entry is the mean of B steps
+    # (B = 2 here, one step in front left out): 70,001 steps -> 35,000 entries
+    ctx = hmd.Context(hmd.Params(n_equil=0, **SMALL_L))
+    b = hmd.Batch(ctx, [(6.0, 0.05, 2, 70001)])
+    b.run(70001, graph_chunk=100)
+    q = b.series(0)
+    assert len(q) == 35000
+    assert np.all(q != 0.0)
+    r = b.results()[0]
+    assert r["status"] in (0, -5)
+    assert r["flux"] == pytest.approx(q.mean(), rel=1e-12)
+    assert r["flux_se"] == pytest.approx(ostats.geyer(q)[1], rel=1e-9)
