@@ -212,6 +212,19 @@ int md_series_stats(hmd_ctx* ctx, const double* x, int S, int64_t n, int64_t ld,
  * device); calls of one context on different streams must not overlap. */
 int md_series_stats_dev(hmd_ctx* ctx, const double* d_x, int S, int64_t n, int64_t ld, int n_blocks, double* d_out,
                         void* stream);
+/* Allocation-free form of md_series_stats_dev, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid it): same arguments, results and kernels, but the
+ * autocovariance scratch is a fixed array of 2^21 doubles (16 MiB) in device
+ * memory, one per GPU, held until the process ends; this call allocates and
+ * frees nothing.  EINVAL when n_blocks = 0 and S n > 2^21 (the block rule
+ * needs no scratch).  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other contexts or threads) race
+ * and must be serialised by the caller.  Nothing in the scratch needs to
+ * start at zero (each call writes every entry it reads).  Queued on `stream`
+ * (NULL: the context's stream) without waiting. */
+int md_series_stats_noalloc(hmd_ctx* ctx, const double* d_x, int S, int64_t n, int64_t ld, int n_blocks,
+                            double* d_out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Single-system hooks (tests, checkpoint/restart).  Atom order in every

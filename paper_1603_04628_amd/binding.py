@@ -93,6 +93,7 @@ _sig("md_batch_set_state", i32, vp, i32, P(d), P(d))
 _sig("md_batch_series", i32, vp, i32, P(d), P(i64))
 _sig("md_series_stats", i32, vp, P(d), i32, i64, i64, i32, P(d))
 _sig("md_series_stats_dev", i32, vp, vp, i32, i64, i64, i32, vp, vp)
+_sig("md_series_stats_noalloc", i32, vp, vp, i32, i64, i64, i32, vp, vp)
 _sig("md_sys_create", i32, vp, d, d, u64, P(vp))
 _sig("md_sys_info", i32, vp, P(i64), P(i64), P(d), P(i32))
 _sig("md_set_state", i32, vp, P(d), P(d))
@@ -286,6 +287,23 @@ def series_stats_dev(ctx: Context, x, n_blocks: int = 0):
     out = torch.empty((S, 4), dtype=torch.float64, device=t.device)
     ctx.check(_lib.md_series_stats_dev(ctx.handle, vp(t.data_ptr()), S, n, n, int(n_blocks), vp(out.data_ptr()),
                                        _torch_stream()))
+    return out
+
+
+def series_stats_noalloc(ctx: Context, x, out, n_blocks: int = 0):
+    """md_series_stats_noalloc on CUDA tensors: x (S x n, float64, contiguous)
+    and a preallocated out (S x 4, float64); the call itself allocates
+    nothing on the device."""
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+        raise HmdError(HMD_EINVAL, "x must be a contiguous float64 CUDA tensor")
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()):
+        raise HmdError(HMD_EINVAL, "out must be a contiguous float64 CUDA tensor")
+    S, n = (1, x.shape[0]) if x.dim() == 1 else x.shape
+    if out.numel() < 4 * S:
+        raise HmdError(HMD_EINVAL, "out needs 4 doubles per series")
+    ctx.check(_lib.md_series_stats_noalloc(ctx.handle, vp(x.data_ptr()), S, n, n, int(n_blocks),
+                                           vp(out.data_ptr()), _torch_stream()))
     return out
 
 

@@ -62,6 +62,12 @@ int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ct
     delete ctx;
     return HMD_EDEVICE;
   }
+  // the device address of the allocation-free entry point's fixed scratch,
+  // looked up once per device
+  if (hmd::series_noalloc_init(device, ctx->err) != HMD_OK) {
+    delete ctx;
+    return HMD_EDEVICE;
+  }
   if (hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
   } else {

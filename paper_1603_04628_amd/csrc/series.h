@@ -13,6 +13,15 @@ constexpr int kSeriesMaxBlocks = 1024;  // block rule: at most this many blocks
 // sampled steps; beyond, each entry sums B consecutive steps)
 constexpr int64_t kSeriesCap = int64_t(1) << 16;
 
+// Fixed device scratch of the allocation-free form: 2^21 doubles (16 MiB)
+// per GPU, enough for the autocovariances of S series of n samples with
+// S n <= 2^21.
+constexpr int64_t kNoAllocScratchDoubles = int64_t(1) << 21;
+
+// Look up (once per device) the device address of the fixed scratch array;
+// called when a context is created on that device.
+int series_noalloc_init(int device, std::string& err);
+
 // HMD_OK, or HMD_EINVAL with a message for arguments the kernels cannot take.
 int series_stats_check(int S, int64_t n, int64_t ld, int n_blocks, std::string& err);
 // Queue the statistics of S rows (n samples, row stride ld, each sample times

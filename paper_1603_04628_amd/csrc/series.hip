@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "engine.h"
 #include "series.h"
@@ -178,4 +179,70 @@ void series_stats_enqueue(hipStream_t st, const double* d_x, int S, int64_t n, i
   hipLaunchKernelGGL(k_series_geyer, dim3((S + 63) / 64), dim3(64), 0, st, d_gam, n, n, S, d_out);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free form.  The autocovariance scratch lives in a fixed device
+// array, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// symbol): its device address is looked up once per device at context
+// creation and that address is what the kernels receive.
+// ---------------------------------------------------------------------------
+namespace {
+
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+int series_noalloc_init(int device, std::string& err) {
+  if (device < 0 || device >= kMaxDevices) {
+    err = "series scratch: device index out of range";
+    return HMD_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return HMD_OK;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) prev = device;
+  hipError_t e = hipSetDevice(device);
+  void* ptr = nullptr;
+  if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess || !ptr) {
+    err = std::string("series scratch: hipGetSymbolAddress: ") + hipGetErrorString(e);
+    return HMD_EDEVICE;
+  }
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return HMD_OK;
+}
+
+double* series_noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 }  // namespace hmd
+
+extern "C" int md_series_stats_noalloc(hmd_ctx* ctx, const double* d_x, int S, int64_t n, int64_t ld, int n_blocks,
+                                       double* d_out, void* stream) {
+  if (!ctx || !d_x || !d_out) return HMD_EINVAL;
+  HMD_TRY(hmd::series_stats_check(S, n, ld, n_blocks, ctx->err));
+  const int64_t need = n_blocks == 0 ? int64_t(S) * n : 0;
+  if (need > hmd::kNoAllocScratchDoubles) {
+    ctx->err = "md_series_stats_noalloc: S * n = " + std::to_string(need) + " exceeds the fixed scratch of " +
+               std::to_string(hmd::kNoAllocScratchDoubles) + " doubles";
+    return HMD_EINVAL;
+  }
+  double* sc = hmd::series_noalloc_scratch(ctx->device);
+  if (!sc) {
+    ctx->err = "md_series_stats_noalloc: no scratch address for this device (context not set up)";
+    return HMD_EDEVICE;
+  }
+  HMD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  hmd::series_stats_enqueue(s, d_x, S, n, ld, 1.0, n_blocks, sc, d_out);
+  HMD_HIP(ctx, hipGetLastError());
+  return HMD_OK;
+}
