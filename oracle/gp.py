@@ -23,6 +23,16 @@ Readings where the paper is silent (also listed in the design notes):
     mean per-point standard error in the same scaled units (Sec. 2.3 estimates
     sigma_n from the MD data rather than fitting it);
   - the variance compared with the threshold is the latent one (no sigma_n^2).
+Options beyond the paper's surrogate:
+  - noise_mode 1: heteroscedastic noise, each point's own (SE_i / s_q)^2 on
+    the diagonal of C in place of sigma_n^2 (Sec. 2.3 estimates the noise of
+    each run from its own data);
+  - kernel 1: the periodic kernel of App. B (Eq. periodicKernel) on a single
+    input t, K = sigma_f^2 exp(-2 sin^2(pi |t - t'| / T) / l^2), with no
+    input normalisation;
+  - optimize(): hyperparameters that maximise Eq. evidenceEq (Sec. 2.3, and
+    App. B for l and sigma_n of the periodic kernel), found by a library
+    optimiser over their logarithms.
 """
 from dataclasses import dataclass, field
 from typing import Optional, Sequence
@@ -39,6 +49,9 @@ class Hyper:
     scale_mode: int = 0            # 0 mean pairwise separation, 1 fixed ranges
     ranges: Sequence[float] = field(default_factory=lambda: (16.0, 0.049))
     out_scale: int = 1             # 1: divide outputs by their RMS
+    noise_mode: int = 0            # 0 uniform sigma_n, 1 per-point SE_i
+    kernel: int = 0                # 0 squared exponential, 1 periodic (App. B)
+    period: float = 1.0            # T of the periodic kernel
 
 
 def mean_separation(X: np.ndarray, ranges, mode: int) -> np.ndarray:
@@ -62,6 +75,12 @@ def kernel(A: np.ndarray, B: np.ndarray, scale: np.ndarray, sigma_f: float, ell:
     D = (A[:, None, :] - B[None, :, :]) / scale[None, None, :]
     d2 = (D ** 2).sum(-1)
     return sigma_f ** 2 * np.exp(-d2 / (2.0 * ell ** 2))
+
+
+def periodic_kernel(A: np.ndarray, B: np.ndarray, period: float, sigma_f: float, ell: float) -> np.ndarray:
+    """Eq. periodicKernel (App. B) on the first input."""
+    dt = np.abs(A[:, None, 0] - B[None, :, 0])
+    return sigma_f ** 2 * np.exp(-2.0 * np.sin(np.pi * dt / period) ** 2 / ell ** 2)
 
 
 class GP:
@@ -88,10 +107,17 @@ class GP:
             self.L = np.zeros((0, 0))
             self.alpha = np.zeros(0)
             return
-        C = kernel(self.X, self.X, self.scale, h.sigma_f, h.ell) + self.sigma_n ** 2 * np.eye(n)
+        noise = (self.se / self.s_q) ** 2 if h.noise_mode == 1 else np.full(n, self.sigma_n ** 2)
+        C = self._k(self.X, self.X) + np.diag(noise)
         self.L = np.linalg.cholesky(C)
         w = solve_triangular(self.L, self.ys, lower=True)
         self.alpha = solve_triangular(self.L.T, w, lower=False)
+
+    def _k(self, A, B):
+        h = self.h
+        if h.kernel == 1:
+            return periodic_kernel(A, B, h.period, h.sigma_f, h.ell)
+        return kernel(A, B, self.scale, h.sigma_f, h.ell)
 
     def append(self, x, y, se=0.0):
         """Alg. 1 database growth: append and update the covariance (the
@@ -107,7 +133,7 @@ class GP:
         sf2 = self.h.sigma_f ** 2
         if len(self.y) == 0:
             return np.zeros(len(Xs)), np.full(len(Xs), sf2 * self.s_q ** 2)
-        Ks = kernel(Xs, self.X, self.scale, self.h.sigma_f, self.h.ell)
+        Ks = self._k(Xs, self.X)
         mean = Ks @ self.alpha
         V = solve_triangular(self.L, Ks.T, lower=True)
         var = sf2 - (V ** 2).sum(0)
@@ -117,3 +143,35 @@ class GP:
         """Eq. evidenceEq on the scaled outputs."""
         n = len(self.y)
         return float(-0.5 * self.ys @ self.alpha - np.log(np.diag(self.L)).sum() - 0.5 * n * np.log(2 * np.pi))
+
+    def optimize(self, which=("sigma_f", "ell")):
+        """Maximise Eq. evidenceEq over the logarithms of the named
+        hyperparameters (sigma_n only with uniform noise; it is then held in
+        the scaled output units), then refit.  Returns the maximum."""
+        from scipy.optimize import minimize
+        names = list(which)
+        if "sigma_n" in names:
+            if self.h.noise_mode == 1:
+                raise ValueError("per-point noise has no sigma_n to optimise")
+            self.h.sigma_n = self.sigma_n * self.s_q  # hold it explicitly from here on
+
+        def set_theta(t):
+            for k, v in zip(names, np.exp(t)):
+                if k == "sigma_n":
+                    self.h.sigma_n = v * self.s_q
+                else:
+                    setattr(self.h, k, v)
+
+        def neg(t):
+            set_theta(t)
+            try:
+                self._fit()
+            except np.linalg.LinAlgError:
+                return 1e300
+            return -self.log_marginal()
+
+        t0 = np.log([self.sigma_n if k == "sigma_n" else getattr(self.h, k) for k in names])
+        r = minimize(neg, t0, method="Nelder-Mead", options={"xatol": 1e-10, "fatol": 1e-12, "maxiter": 4000})
+        set_theta(r.x)
+        self._fit()
+        return self.log_marginal()

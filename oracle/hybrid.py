@@ -25,10 +25,20 @@ Per macro step (Alg. 1, time-evolution loop):
      boundary section's own flux.
 The flagged sections of one step are solved together (one batch) and the
 database grows after the step, where Alg. 1 walks the sections one by one.
+
+With warm starts (Alg. 1 "find nearest prior input", "pseudoMD"), each
+flagged section's run starts from the recorded fallback run of the same
+height whose input is nearest (``startup.nearest_prior``; with the height
+fixed only the body force differs), else from the lattice, and equilibrates
+for the pseudoMD start-up of the 1-D channel flow (``startup.startup_time``),
+at least n_min_warm (n_min_cold from the lattice) steps; the step's batch
+equilibrates for the longest of them.
 """
 from dataclasses import dataclass
 
 import numpy as np
+
+from . import startup
 
 
 @dataclass
@@ -48,6 +58,13 @@ class HybridCfg:
     tau_abs: float = 0.0      # absolute threshold sigma_t of Sec. 2.2 (0: off)
     audit_every: int = 0
     mirror: bool = True       # q(h, -g) = -q(h, g): query at |g|, answer with the sign of g
+    warm_start: bool = False  # warm starts and pseudoMD start-up lengths
+    pseudo_nu: float = 2.5
+    pseudo_slip: float = 0.5
+    pseudo_tol: float = 0.01
+    n_min_warm: int = 1000
+    n_min_cold: int = 2000
+    md_dt: float = 0.005      # MD time step (start-up time -> steps)
 
 
 class Hybrid:
@@ -73,6 +90,10 @@ class Hybrid:
         self.q = np.zeros(n)
         self.q_std = np.zeros(n)
         self.from_md = np.zeros(n, dtype=bool)
+        self.warm = []            # (h, g) of the recorded fallback runs
+        self.plan_prior = np.full(n, -2)
+        self.plan_equil = np.zeros(n, dtype=np.int64)
+        self.plan_batch_equil = 0
 
     def p_in(self, t_steps):
         c = self.c
@@ -105,6 +126,20 @@ class Hybrid:
                     audit[i] = True
         run = flag | audit
         q = sgn * mean
+        self.plan_prior = np.full(len(g), -2)
+        self.plan_equil = np.zeros(len(g), dtype=np.int64)
+        self.plan_batch_equil = 0
+        if c.warm_start:
+            Xw = np.array(self.warm).reshape(-1, 2)
+            for i in np.nonzero(flag)[0]:
+                x_star = np.array([self.h[i], gq[i]])
+                prior = startup.nearest_prior(Xw, x_star, np.ones(2), np.ones(len(Xw), dtype=bool))
+                g_in = Xw[prior, 1] if prior >= 0 else 0.0
+                ts = startup.startup_time(self.h[i], g_in, gq[i], c.pseudo_nu, c.pseudo_slip, c.pseudo_tol)
+                ne = startup.startup_steps(ts, c.md_dt, c.n_min_warm if prior >= 0 else c.n_min_cold)
+                self.plan_prior[i] = prior
+                self.plan_equil[i] = ne
+                self.plan_batch_equil = max(self.plan_batch_equil, ne)
         if run.any():
             idx = np.nonzero(run)[0]
             qm, se = self.micro(self.h[idx], gq[idx])
@@ -118,6 +153,8 @@ class Hybrid:
             for k, i in enumerate(idx):
                 if flag[i]:
                     self.sur.append(X[i], qm[k], se[k])
+                    if c.warm_start:
+                        self.warm.append((self.h[i], gq[i]))
         self.q, self.q_std, self.from_md = q, std, flag
         face = 0.5 * (q[:-1] + q[1:])
         flux = np.concatenate([[q[0]], face, [q[-1]]])

@@ -104,3 +104,80 @@ def test_interpolation_is_more_certain_than_extrapolation():
     gp = GP(X, [0.1, 0.2, 0.3], [0.01] * 3)
     _, v = gp.predict([[6.0, 0.01], [30.0, 0.01]])
     assert v[0] < v[1]
+
+
+# ---------------------------------------------------------------- NEXT-4 options
+def test_heteroscedastic_noise_is_the_mvn_with_per_point_variances():
+    rng = np.random.default_rng(2)
+    X = rng.uniform(0, 4, (12, 2))
+    y = np.sin(X[:, 0]) + 0.1 * rng.standard_normal(12)
+    se = rng.uniform(0.01, 0.3, 12)
+    h = fixed(sigma_n=-1.0)
+    h.noise_mode = 1
+    gp = GP(X, y, se, h)
+    # Eq. covarianceEq with each point's own variance, built by a double loop
+    C = np.zeros((12, 12))
+    for i in range(12):
+        for j in range(12):
+            d2 = np.sum((X[i] - X[j]) ** 2)  # ranges 4 -> scale 1
+            C[i, j] = np.exp(-0.5 * d2) + (se[i] ** 2 if i == j else 0.0)
+    assert gp.log_marginal() == pytest.approx(multivariate_normal(np.zeros(12), C).logpdf(y), rel=1e-12)
+    # equal SEs reduce it to the uniform-noise GP
+    h2 = fixed(sigma_n=0.2)
+    gp_u = GP(X, y, None, h2)
+    h3 = fixed(sigma_n=-1.0)
+    h3.noise_mode = 1
+    gp_h = GP(X, y, np.full(12, 0.2), h3)
+    xs = rng.uniform(0, 4, (5, 2))
+    assert np.allclose(gp_u.predict(xs)[0], gp_h.predict(xs)[0], rtol=1e-12)
+    # a point with a huge standard error barely moves the posterior
+    se2 = np.full(13, 0.05)
+    se2[-1] = 1e4
+    X2 = np.vstack([X, [[2.0, 2.0]]])
+    y2 = np.append(y, 50.0)
+    h4 = fixed(sigma_n=-1.0)
+    h4.noise_mode = 1
+    gp_big = GP(X2, y2, se2, h4)
+    gp_ref = GP(X, y, se2[:12], h4)
+    assert np.abs(gp_big.predict(xs)[0] - gp_ref.predict(xs)[0]).max() < 1e-5
+
+
+def test_periodic_kernel_of_appendix_b():
+    T = 10.8
+    t = np.linspace(0.0, 30.0, 40)[:, None]
+    y = np.sin(2 * np.pi * t[:, 0] / T)
+    h = Hyper(sigma_f=1.0, ell=1.0, sigma_n=0.1, out_scale=0, kernel=1, period=T, ranges=(1.0,))
+    gp = GP(t, y, None, h)
+    K = gp._k(t, t)
+    # Eq. periodicKernel, written out: sigma_f^2 exp(-2 sin^2(pi dt / T) / l^2)
+    assert K[3, 17] == pytest.approx(np.exp(-2.0 * np.sin(np.pi * abs(t[3, 0] - t[17, 0]) / T) ** 2), rel=1e-14)
+    assert gp._k(np.array([[1.0]]), np.array([[1.0 + T]]))[0, 0] == pytest.approx(1.0, abs=1e-14)
+    # the posterior mean repeats with the period and follows the sine
+    q = np.linspace(5.0, 15.0, 7)[:, None]
+    m1, _ = gp.predict(q)
+    m2, _ = gp.predict(q + T)
+    assert np.allclose(m1, m2, atol=1e-3)
+    assert np.abs(m1 - np.sin(2 * np.pi * q[:, 0] / T)).max() < 0.1
+    C = K + 0.01 * np.eye(40)
+    assert gp.log_marginal() == pytest.approx(multivariate_normal(np.zeros(40), C).logpdf(y), rel=1e-12)
+
+
+@pytest.mark.parametrize("which", [("sigma_f", "ell"), ("ell", "sigma_n")])
+def test_optimised_hyperparameters_maximise_the_evidence(which):
+    rng = np.random.default_rng(8)
+    X = rng.uniform(0, 4, (30, 2))
+    y = np.sin(1.3 * X[:, 0]) * np.cos(0.7 * X[:, 1]) + 0.05 * rng.standard_normal(30)
+    gp = GP(X, y, np.full(30, 0.05), fixed(sigma_n=0.1))
+    best = gp.optimize(which)
+    assert best == pytest.approx(gp.log_marginal(), rel=1e-14)
+    theta = {"sigma_f": gp.h.sigma_f, "ell": gp.h.ell, "sigma_n": gp.h.sigma_n}
+    # no point of a grid around the optimum does better (a maximum), and the
+    # central differences of the evidence vanish there
+    for k in which:
+        for f in (0.9, 0.97, 1.03, 1.1):
+            g2 = GP(X, y, np.full(30, 0.05), fixed(**{**theta, k: theta[k] * f}))
+            assert g2.log_marginal() <= best + 1e-9
+        e = 1e-4
+        up = GP(X, y, None, fixed(**{**theta, k: theta[k] * (1 + e)})).log_marginal()
+        dn = GP(X, y, None, fixed(**{**theta, k: theta[k] * (1 - e)})).log_marginal()
+        assert abs(up - dn) / (2 * e) < 1e-4

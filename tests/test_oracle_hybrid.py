@@ -135,3 +135,30 @@ def test_mirror_is_exact_for_an_odd_micro_law():
     assert runs[True][3] >= 0.0
     np.testing.assert_allclose(runs[True][0], runs[False][0], rtol=1e-12)
     np.testing.assert_allclose(runs[True][1], runs[False][1], rtol=1e-10, atol=1e-14)
+
+
+def test_warm_start_plan_picks_nearest_same_height_run():
+    # the oracle march's plan: a section's first fallback starts from the
+    # lattice (n_min_cold at least); a later one from the recorded run of the
+    # same height with the nearest body force, for its pseudoMD start-up.
+    # Heights are compared exactly: the mirror sections i and n-1-i differ
+    # in the last bit of their cosine, so each section restarts from its own
+    # earlier runs
+    from oracle import startup
+    cfg = HybridCfg(n_sections=8, L=80.0, h0=10.0, dt_macro=0.002, dp_mean=3.0, dp_amp=0.3, period=6.0,
+                    tau_rel=1e-9, warm_start=True, n_min_warm=300, n_min_cold=2500)
+    gp = GP(np.zeros((0, 2)), np.zeros(0), None, Hyper(ranges=(16.0, 0.049)))
+    hy = Hybrid(cfg, gp, lambda h, g: (poiseuille_flux(h, g), 0.001 + 0.0 * h))
+    hy.step()
+    assert np.all(hy.plan_prior == -1) and np.all(hy.plan_equil >= 2500)
+    hy.step()
+    assert len(hy.warm) == 16
+    for i in range(8):
+        h_i, g_i = hy.warm[8 + i]  # this step's run of section i (all fell back, in order)
+        cands = [j for j in range(8) if hy.warm[j][0] == h_i]
+        assert len(cands) >= 1
+        best = min(cands, key=lambda j: (abs(hy.warm[j][1] - g_i), j))
+        assert hy.plan_prior[i] == best
+        ts = startup.startup_time(h_i, hy.warm[best][1], g_i, 2.5, 0.5, 0.01)
+        assert hy.plan_equil[i] == startup.startup_steps(ts, 0.005, 300)
+    assert hy.plan_batch_equil == hy.plan_equil.max()
