@@ -26,6 +26,13 @@ Per macro step (Alg. 1, time-evolution loop):
 The flagged sections of one step are solved together (one batch) and the
 database grows after the step, where Alg. 1 walks the sections one by one.
 
+Geometry 1 is the paper's benchmark channel (Sec. 2.1): periodic in s
+(the first section sits at inlet and outlet), sections at s_i = (i - 1) L / N
+(Eq. subsEq), h = a [cos(2 pi s / L) - 1] + h_1 (Eq. heightEq, with h_1 = h0
+and a = amp h0), driven by a uniform external force
+F_ext(t) = F_A sin(2 pi t / T) (Eq. extForcing1, t in macro steps); the
+pressure gradient and the face fluxes wrap around the ring.
+
 With warm starts (Alg. 1 "find nearest prior input", "pseudoMD"), each
 flagged section's run starts from the recorded fallback run of the same
 height whose input is nearest (``startup.nearest_prior``; with the height
@@ -65,6 +72,9 @@ class HybridCfg:
     n_min_warm: int = 1000
     n_min_cold: int = 2000
     md_dt: float = 0.005      # MD time step (start-up time -> steps)
+    geometry: int = 0         # 0 inlet/outlet channel, 1 the paper's periodic channel
+    f_amp: float = 0.0        # F_A / m of Eq. extForcing1 (geometry 1)
+    f_period: float = 250.0   # T of Eq. extForcing1, in macro steps
 
 
 class Hybrid:
@@ -76,8 +86,12 @@ class Hybrid:
         self.c = cfg
         n = cfg.n_sections
         self.ds = cfg.L / n
-        self.s = (np.arange(n) + 0.5) * self.ds
-        self.h = cfg.h0 * (1.0 + cfg.amp * np.cos(2.0 * np.pi * self.s / cfg.L))
+        if cfg.geometry == 1:
+            self.s = np.arange(n) * self.ds  # Eq. subsEq: s_i = (i - 1) L / N
+            self.h = cfg.amp * cfg.h0 * (np.cos(2.0 * np.pi * self.s / cfg.L) - 1.0) + cfg.h0  # Eq. heightEq
+        else:
+            self.s = (np.arange(n) + 0.5) * self.ds
+            self.h = cfg.h0 * (1.0 + cfg.amp * np.cos(2.0 * np.pi * self.s / cfg.L))
         self.rho = np.full(n, cfg.rho_ref) if rho0 is None else np.asarray(rho0, dtype=np.float64).copy()
         self.sur = surrogate
         self.micro = micro
@@ -99,13 +113,22 @@ class Hybrid:
         c = self.c
         return c.p_out + c.dp_mean * (1.0 + c.dp_amp * np.sin(2.0 * np.pi * t_steps / c.period))
 
+    def f_ext(self, t_steps):
+        """Eq. extForcing1 (geometry 1), per unit mass."""
+        c = self.c
+        return c.f_amp * np.sin(2.0 * np.pi * t_steps / c.f_period) if c.geometry == 1 else 0.0
+
     def forces(self):
+        """Eq. momentumEq per unit mass: F_ext/m - (1/rho) dp/ds."""
         c = self.c
         p = c.p_out + c.c2 * (self.rho - c.rho_ref)
-        pl = np.concatenate([[self.p_in(self.step_no)], p[:-1]])
-        pr = np.concatenate([p[1:], [c.p_out]])
+        if c.geometry == 1:
+            pl, pr = np.roll(p, 1), np.roll(p, -1)
+        else:
+            pl = np.concatenate([[self.p_in(self.step_no)], p[:-1]])
+            pr = np.concatenate([p[1:], [c.p_out]])
         dpds = (pr - pl) / (2.0 * self.ds)
-        return -dpds / self.rho
+        return self.f_ext(self.step_no) - dpds / self.rho
 
     def step(self):
         c = self.c
@@ -156,8 +179,12 @@ class Hybrid:
                     if c.warm_start:
                         self.warm.append((self.h[i], gq[i]))
         self.q, self.q_std, self.from_md = q, std, flag
-        face = 0.5 * (q[:-1] + q[1:])
-        flux = np.concatenate([[q[0]], face, [q[-1]]])
+        if c.geometry == 1:  # periodic faces: the last one closes the ring
+            face = 0.5 * (q + np.roll(q, -1))
+            flux = np.concatenate([[face[-1]], face])
+        else:
+            face = 0.5 * (q[:-1] + q[1:])
+            flux = np.concatenate([[q[0]], face, [q[-1]]])
         m = self.rho * self.h - c.dt_macro * (flux[1:] - flux[:-1]) / self.ds
         self.rho = m / self.h
         self.step_no += 1

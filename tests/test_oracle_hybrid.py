@@ -162,3 +162,50 @@ def test_warm_start_plan_picks_nearest_same_height_run():
         ts = startup.startup_time(h_i, hy.warm[best][1], g_i, 2.5, 0.5, 0.01)
         assert hy.plan_equil[i] == startup.startup_steps(ts, 0.005, 300)
     assert hy.plan_batch_equil == hy.plan_equil.max()
+
+
+# ---------------------------------------------------------------- the paper's periodic channel
+def _paper_cfg(n, **kw):
+    base = dict(n_sections=n, L=200.0, h0=10.0, amp=0.2, geometry=1, f_amp=0.03, f_period=4000.0,
+                dt_macro=0.05, c2=200.0, tau_rel=1e9)
+    base.update(kw)
+    return HybridCfg(**base)
+
+
+def test_paper_geometry_sections_and_heights():
+    # Eq. subsEq: s_i = (i - 1) L / N; Eq. heightEq: h = a (cos(2 pi s / L) - 1) + h_1
+    hy = Hybrid(_paper_cfg(5), Exact(), micro, var_is_std=True)
+    assert np.allclose(hy.s, [0.0, 40.0, 80.0, 120.0, 160.0])
+    a = 0.2 * 10.0
+    assert hy.h[0] == 10.0 and hy.h.min() == pytest.approx(10.0 - 2 * a * (1 - np.cos(np.pi * 0.8)) / 2, rel=1e-12)
+    assert np.allclose(hy.h, a * (np.cos(2 * np.pi * hy.s / 200.0) - 1.0) + 10.0, rtol=0, atol=1e-15)
+
+
+def test_periodic_channel_conserves_mass_exactly():
+    hy = Hybrid(_paper_cfg(40), Exact(), micro, var_is_std=True)
+    m0 = hy.mass()
+    for _ in range(300):
+        hy.step()
+    assert hy.mass() == pytest.approx(m0, rel=1e-13)
+    assert np.any(hy.q != 0.0)
+
+
+def test_periodic_channel_reaches_reynolds_lubrication_flow():
+    # near the peak of F_ext (quasi-steady: the forcing period is far longer
+    # than the pressure relaxation), the flow rate is uniform along the ring
+    # and equals Q = F L C / int h^-3 ds with q' = C h^3 g, C = rho^2 / (12 eta);
+    # int_0^L (b + a cos(2 pi s / L))^-3 ds = L (2 b^2 + a^2) / (2 (b^2 - a^2)^(5/2)), b = h_1 - a
+    n, L, h1, amp = 40, 200.0, 10.0, 0.2
+    a = amp * h1
+    C = 0.8 ** 2 / (12 * 2.0)
+    ds = L / n
+    dt = 0.4 * ds * ds / (200.0 * C * h1 ** 3 / (0.8 * h1))  # explicit diffusion limit at the widest section
+    cfg = _paper_cfg(n, dt_macro=dt, f_period=40000.0)
+    hy = Hybrid(cfg, Exact(), micro, var_is_std=True)
+    for _ in range(10000):  # F_ext at sin(pi/2): its peak
+        hy.step()
+    b = h1 - a
+    integral = L * (2 * b * b + a * a) / (2 * (b * b - a * a) ** 2.5)
+    Q = 0.03 * L * C / integral
+    assert np.abs(hy.q - Q).max() <= 0.002 * Q
+    assert hy.q.std() <= 0.001 * Q
