@@ -15,12 +15,15 @@ started from the steady profile of the prior input's body force g_in (rest:
 g_in = 0), u_g(y) = (g / 2 nu) [y (h - y) + b h].  The deviation from the
 new steady profile decays in the symmetric modes cos(k_n (y - h/2)) with
 cot(k_n h / 2) = b k_n; t_s is the first time at which the flow rate is
-within `tol` of its new steady value, |q(t) - q*| <= tol |q*|.
+within `tol` of its new steady value, relative to the larger of the two
+steady flow rates: |q(t) - q*| <= tol max(|q_in|, |q*|).
 
 Readings (where the paper is silent): the slip length b and kinematic
-viscosity nu are model constants; the tolerance is relative to the new
-steady flow rate; a run never equilibrates for less than a stated minimum
-(thermal relaxation; longer from the lattice than from a stored state).
+viscosity nu are model constants; the tolerance is relative to the larger of
+the old and new steady flow rates (a start-up between two nearly equal, or
+two nearly zero, flows is short); a run never equilibrates for less than a
+stated minimum (thermal relaxation; longer from the lattice than from a
+stored state).
 """
 import numpy as np
 
@@ -71,15 +74,16 @@ def deviation_modes(h, dg, nu, b, n_modes=200):
 
 
 def startup_time(h, g_in, g_new, nu, b, tol, n_modes=200):
-    """t_s: the first t >= 0 with |q(t) - q*| <= tol |q*| (bisection on the
-    modal sum, monotone after its first mode dominates)."""
+    """t_s: the first t >= 0 with |q(t) - q*| <= tol max(|q_in|, |q*|)
+    (bisection on the modal sum, monotone once its first mode dominates)."""
     q_new = flow_rate(h, g_new, nu, b)
+    q_in = flow_rate(h, g_in, nu, b)
     cw, rate = deviation_modes(h, g_in - g_new, nu, b, n_modes)
 
     def dev(t):
         return abs(float(np.sum(cw * np.exp(-rate * t))))
 
-    target = tol * abs(q_new)
+    target = tol * max(abs(q_in), abs(q_new))
     if dev(0.0) <= target:
         return 0.0
     hi = 1.0 / rate[0]

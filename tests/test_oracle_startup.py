@@ -41,10 +41,11 @@ def _fd_startup(h, g_in, g_new, nu, b, tol, M=100):
     y = (np.arange(M) + 0.5) * dy
     u = (g_in / (2 * nu)) * (y * (h - y) + b * h)
     q_new = su.flow_rate(h, g_new, nu, b)
+    scale = max(abs(q_new), abs(su.flow_rate(h, g_in, nu, b)))
     dt = 0.2 * dy * dy / nu
     f = (2 * b - dy) / (2 * b + dy)
     t = 0.0
-    while abs(u.sum() * dy - q_new) > tol * abs(q_new):
+    while abs(u.sum() * dy - q_new) > tol * scale:
         ul = np.concatenate([[f * u[0]], u[:-1]])
         ur = np.concatenate([u[1:], [f * u[-1]]])
         u = u + dt * (g_new + nu * (ul - 2 * u + ur) / (dy * dy))
@@ -67,6 +68,11 @@ def test_startup_time_scales_with_h_squared_and_vanishes_near_the_target():
     assert t2 == pytest.approx(4.0 * t1, rel=1e-9)
     # a prior within the tolerance needs no start-up
     assert su.startup_time(8.0, 0.02 * 1.005, 0.02, nu, 0.0, tol) == 0.0
+    # starting from rest, the tolerance is relative to the new flow alone
+    t_rest = su.startup_time(8.0, 0.0, 0.02, nu, 0.0, tol)
+    assert t_rest == pytest.approx(su.startup_time(8.0, 0.0, 0.002, nu, 0.0, tol), rel=1e-9)
+    # a start-up never takes longer than the one from rest to the larger flow
+    assert su.startup_time(8.0, 0.01, 0.012, nu, 0.0, tol) < su.startup_time(8.0, 0.0, 0.012, nu, 0.0, tol)
     # the closer the prior, the shorter the start-up
     assert su.startup_time(8.0, 0.018, 0.02, nu, 0.0, tol) < su.startup_time(8.0, 0.01, 0.02, nu, 0.0, tol)
     assert su.startup_steps(1.234, 0.005, 100) == 247
