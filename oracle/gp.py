@@ -147,7 +147,13 @@ class GP:
     def optimize(self, which=("sigma_f", "ell")):
         """Maximise Eq. evidenceEq over the logarithms of the named
         hyperparameters (sigma_n only with uniform noise; it is then held in
-        the scaled output units), then refit.  Returns the maximum."""
+        the scaled output units), then refit.  Returns the maximum.
+
+        The evidence can have several local maxima (the periodic kernel's in
+        ell does), and the paper asks for the maximising hyperparameters:
+        the search evaluates it on a grid of 17 points per hyperparameter over
+        two decades either side of the start, then refines by Nelder-Mead
+        from the best grid point and from the start, and keeps the larger."""
         from scipy.optimize import minimize
         names = list(which)
         if "sigma_n" in names:
@@ -171,7 +177,12 @@ class GP:
             return -self.log_marginal()
 
         t0 = np.log([self.sigma_n if k == "sigma_n" else getattr(self.h, k) for k in names])
-        r = minimize(neg, t0, method="Nelder-Mead", options={"xatol": 1e-10, "fatol": 1e-12, "maxiter": 4000})
+        axis = np.log(10.0) * np.linspace(-2.0, 2.0, 17)
+        grid = np.stack(np.meshgrid(*([axis] * len(names)), indexing="ij"), -1).reshape(-1, len(names))
+        tg = t0 + grid[int(np.argmin([neg(t0 + d) for d in grid]))]
+        opts = {"xatol": 1e-10, "fatol": 1e-12, "maxiter": 4000}
+        runs = [minimize(neg, t, method="Nelder-Mead", options=opts) for t in (tg, t0)]
+        r = min(runs, key=lambda q: q.fun)
         set_theta(r.x)
         self._fit()
         return self.log_marginal()

@@ -181,3 +181,25 @@ def test_optimised_hyperparameters_maximise_the_evidence(which):
         up = GP(X, y, None, fixed(**{**theta, k: theta[k] * (1 + e)})).log_marginal()
         dn = GP(X, y, None, fixed(**{**theta, k: theta[k] * (1 - e)})).log_marginal()
         assert abs(up - dn) / (2 * e) < 1e-4
+
+
+def test_optimised_evidence_is_the_global_maximum_of_a_multimodal_case():
+    # a noisy sine under the periodic kernel (App. B): the evidence in
+    # (ell, sigma_n) has more than one local maximum (a search from ell = 1
+    # alone stops near ell = 1.15).  The optimum is at least the evidence at
+    # every point of a fine brute-force grid over the region
+    rng = np.random.default_rng(11)
+    T = 10.8
+    X = np.sort(rng.uniform(0.0, 25.0, 60))[:, None]
+    y = np.sin(2 * np.pi * X[:, 0] / T) + 0.15 * rng.standard_normal(60)
+    hp = dict(sigma_n=0.3, out_scale=0, kernel=1, period=T, ranges=(1.0,))
+    gp = GP(X, y, None, Hyper(**hp))
+    best = gp.optimize(("ell", "sigma_n"))
+    brute = -np.inf
+    for ell in np.exp(np.linspace(np.log(0.3), np.log(6.0), 60)):
+        for sn in np.exp(np.linspace(np.log(0.05), np.log(0.5), 40)):
+            h = Hyper(**{**hp, "sigma_n": sn})
+            h.ell = ell
+            brute = max(brute, GP(X, y, None, h).log_marginal())
+    assert best >= brute - 1e-9
+    assert best > 14.4 and 1.8 < gp.h.ell < 2.6
