@@ -100,6 +100,7 @@ class Hybrid:
         self.md_calls = 0
         self.audited = 0
         self.audit_pass = 0
+        self.audit_pass_cal = 0   # passes of |mean - q_MD| <= 2 sqrt(std^2 + SE^2)
         self.answers = 0
         self.q = np.zeros(n)
         self.q_std = np.zeros(n)
@@ -173,6 +174,7 @@ class Hybrid:
                 else:
                     self.audited += 1
                     self.audit_pass += int(abs(mean[i] - qm[k]) <= 2.0 * se[k])
+                    self.audit_pass_cal += int(abs(mean[i] - qm[k]) <= 2.0 * np.sqrt(std[i] ** 2 + se[k] ** 2))
             for k, i in enumerate(idx):
                 if flag[i]:
                     self.sur.append(X[i], qm[k], se[k])
