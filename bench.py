@@ -217,12 +217,33 @@ def hybrid_bench(args, hmd, first_results):
     set_ = np.array([rte[k]["flux_se"] for k in ok_te])
     log(f"surrogate data: {len(ok_tr)} + {len(ok_te)} MD runs in {t_data:.1f} s")
     hyper = B.gp_hyper(ranges=(16.0, 0.049))
+    hyper_info = {"rule": args.gp_hyper, "sigma_f": 1.0, "ell": 1.0}
+    if args.gp_hyper == "evidence":
+        # Sec. 2.3: sigma_f and l maximise the log marginal likelihood of the
+        # training data (sigma_n from the runs' own standard errors)
+        t0 = time.perf_counter()
+        g_opt = B.GP(ctx, X, y, se, hyper)
+        lml0 = g_opt.log_marginal()
+        lml = g_opt.optimize(("sigma_f", "ell"))
+        hp = g_opt.hyper()
+        g_opt.close()
+        hyper = B.gp_hyper(ranges=(16.0, 0.049), sigma_f=hp["sigma_f"], ell=hp["ell"])
+        hyper_info.update(sigma_f=hp["sigma_f"], ell=hp["ell"], lml_at_1_1=lml0, lml=lml,
+                          optimize_s=time.perf_counter() - t0)
+        log(f"gp hyperparameters by evidence: {hyper_info}")
     ecfg = B.ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3)
     Xq = Xt[np.arange(200) % len(Xt)]
     fits = {}
-    for name in ("gp", "ensemble"):
+    variants = (("gp", 0), ("gp_per_point_noise", 0), ("ensemble", 1))
+    for name, kind in variants:
         t0 = time.perf_counter()
-        sur = B.GP(ctx, X, y, se, hyper) if name == "gp" else B.Ensemble(ctx, X, y, ecfg)
+        if kind == 0:
+            hp_v = hyper
+            if name == "gp_per_point_noise":
+                hp_v = B.gp_hyper(ranges=(16.0, 0.049), sigma_f=hyper.sigma_f, ell=hyper.ell, noise_mode=1)
+            sur = B.GP(ctx, X, y, se, hp_v)
+        else:
+            sur = B.Ensemble(ctx, X, y, ecfg)
         torch.cuda.synchronize()
         t_fit = time.perf_counter() - t0
         sur.predict(Xq)
@@ -231,12 +252,16 @@ def hybrid_bench(args, hmd, first_results):
             m, v = sur.predict(Xq)
         t_pred = (time.perf_counter() - t0) / 20
         m, v = sur.predict(Xt)
-        sd = np.sqrt(v) if name == "gp" else v
+        sd = np.sqrt(v) if kind == 0 else v
         inside = np.abs(m - yt) <= 2.0 * np.sqrt(sd ** 2 + set_ ** 2)
         fits[name] = {"fit_s": t_fit, "predict_200_ms": 1e3 * t_pred, "heldout_within_2sigma": float(inside.mean()),
-                      "heldout_rmse_over_rms": float(np.sqrt(np.mean((m - yt) ** 2)) / np.sqrt(np.mean(yt ** 2)))}
+                      "heldout_rmse_over_rms": float(np.sqrt(np.mean((m - yt) ** 2)) / np.sqrt(np.mean(yt ** 2))),
+                      "heldout_median_se_over_rms": float(np.median(set_) / np.sqrt(np.mean(yt ** 2))),
+                      "heldout_median_std_over_rms": float(np.median(sd) / np.sqrt(np.mean(yt ** 2)))}
         log(f"{name}: {fits[name]}")
+        sur.close()
     out["surrogate"] = {"train_points": len(ok_tr), "heldout_points": len(ok_te), "md_data_s": t_data,
+                        "gp_hyperparameters": hyper_info,
                         "reused_from_timed_batch": reuse,
                         "protocol": f"{N_EQUIL} + {N_SAMPLE} steps per point, 57.1 x 57.1 sigma box", **fits}
 
@@ -263,10 +288,10 @@ def hybrid_bench(args, hmd, first_results):
     # a fresh MD call)
     tau_abs = float(np.median(se))
 
-    def run(surrogate, tau, steps, audit_every, budget_s=None, floor=tau_abs):
+    def run(surrogate, tau, steps, audit_every, budget_s=None, floor=tau_abs, warm=1):
         sur = B.GP(hctx, X, y, se, hyper) if surrogate == 0 else B.Ensemble(hctx, X, y, ecfg)
         cfg = HB.hybrid_cfg(surrogate=surrogate, tau_rel=tau, tau_abs=floor, audit_every=audit_every,
-                            audit_batch=64, **base)
+                            audit_batch=64, warm_start=warm, **base)
         hy = HB.Hybrid(hctx, cfg, gp=sur if surrogate == 0 else None, ens=sur if surrogate == 1 else None)
         hy.set_rho(rho0)
         t0 = time.perf_counter()
@@ -284,33 +309,51 @@ def hybrid_bench(args, hmd, first_results):
         st["g_range"] = [float(r["g"].min()), float(r["g"].max())]
         return st
 
-    # all-MD: every query answered by batched MD (threshold 0) for the first
-    # macro steps; the whole march is priced at the rate measured here
+    # all-MD: every query answered by batched MD from the lattice with the
+    # full protocol (threshold 0, no warm starts) for the first macro steps;
+    # the whole march is priced at the rate measured here
     nv = args.all_md_steps
-    allmd = run(0, 0.0, nv, 0, floor=0.0)
+    allmd = run(0, 0.0, nv, 0, floor=0.0, warm=0)
     per_step_atom_steps = allmd["md_atom_steps"] / nv
     md_rate = allmd["md_atom_steps"] / allmd["md_wall_s"]
     all_md_s = args.hybrid_steps * per_step_atom_steps / md_rate
+    # training data as MD cost: the atom-steps of the training runs at the
+    # measured batched rate (the held-out runs are measurement, not method)
+    train_atom_steps = float(sum(rtr[k]["n_fluid"] for k in ok_tr)) * (N_EQUIL + N_SAMPLE)
+    train_md_s = train_atom_steps / md_rate
     log(f"all-MD: {nv} steps in {allmd['wall_s']:.1f} s, {md_rate:.3e} atom-steps/s -> {all_md_s:.0f} s for "
-        f"{args.hybrid_steps} steps")
+        f"{args.hybrid_steps} steps; training MD {train_md_s:.1f} s")
     runs = []
-    for name, sid in (("gp", 0), ("ensemble", 1)):
-        for tau in args.taus:
-            st = run(sid, tau, args.hybrid_steps, args.audit_every, budget_s=args.hybrid_budget)
-            done = st["steps"]
-            method_s = st["wall_s"] - st["audit_wall_s"]  # audits are measurement, not method
-            st.update(surrogate=name, tau=tau, tau_abs=tau_abs, method_wall_s=method_s,
-                      speedup_vs_all_md=done * per_step_atom_steps / md_rate / method_s,
-                      audit_pass_rate=st["audit_pass"] / st["audited"] if st["audited"] else None,
-                      md_atom_steps_ratio=done * per_step_atom_steps / max(st["md_atom_steps"], 1.0))
-            log(f"hybrid {name} tau={tau}: {done} steps, {method_s:.1f} s (+{st['audit_wall_s']:.1f} s audits), "
-                f"md_calls {st['md_calls']}, "
-                f"audits {st['audit_pass']}/{st['audited']}, speedup {st['speedup_vs_all_md']:.0f}x")
-            runs.append(st)
-    out["hybrid"] = {"macro": dict(base, steps=args.hybrid_steps, md_protocol=f"{HY_EQUIL} + {HY_SAMPLE} steps"),
+    plan = [(name, sid, tau, rule) for name, sid in (("gp", 0), ("ensemble", 1)) for tau in args.taus
+            for rule in args.rules if name == "gp" or tau in args.ens_taus]
+    for name, sid, tau, rule in plan:
+        floor = tau_abs if rule == "floor" else 0.0
+        st = run(sid, tau, args.hybrid_steps, args.audit_every, budget_s=args.hybrid_budget, floor=floor)
+        done = st["steps"]
+        method_s = st["wall_s"] - st["audit_wall_s"]  # audits are measurement, not method
+        all_md_done = done * per_step_atom_steps
+        st.update(surrogate=name, tau=tau, rule=rule, tau_abs=floor, method_wall_s=method_s,
+                  speedup_vs_all_md=all_md_done / md_rate / method_s,
+                  speedup_vs_all_md_incl_training=all_md_done / md_rate / (method_s + train_md_s * done /
+                                                                           args.hybrid_steps),
+                  audit_pass_rate=st["audit_pass"] / st["audited"] if st["audited"] else None,
+                  audit_pass_rate_with_surrogate_std=st["audit_pass_cal"] / st["audited"] if st["audited"] else None,
+                  md_atom_steps_ratio=all_md_done / max(st["md_atom_steps"], 1.0),
+                  md_atom_steps_ratio_incl_training=all_md_done / max(
+                      st["md_atom_steps"] + train_atom_steps * done / args.hybrid_steps, 1.0),
+                  warm_start_atom_steps_saved=st["md_atom_steps_cold"] - st["md_atom_steps"])
+        log(f"hybrid {name} tau={tau} {rule}: {done} steps, {method_s:.1f} s (+{st['audit_wall_s']:.1f} s audits), "
+            f"md_calls {st['md_calls']} ({st['warm_starts']} warm), audits {st['audit_pass']}/{st['audited']} "
+            f"({st['audit_pass_cal']} with the surrogate's std), "
+            f"speedup {st['speedup_vs_all_md']:.0f}x ({st['speedup_vs_all_md_incl_training']:.0f}x with training)")
+        runs.append(st)
+    out["hybrid"] = {"macro": dict(base, steps=args.hybrid_steps, md_protocol=f"{HY_EQUIL} + {HY_SAMPLE} steps",
+                                   warm_start="Alg. 1 nearest prior + pseudoMD start-up (1-D N-S, Navier slip)"),
                      "all_md": {"validated_steps": nv, "wall_s_validated": allmd["wall_s"],
                                 "atom_steps_per_macro_step": per_step_atom_steps,
                                 "md_atom_steps_per_s": md_rate, "estimated_wall_s": all_md_s},
+                     "training_md": {"runs": len(ok_tr), "atom_steps": train_atom_steps, "wall_s": train_md_s,
+                                     "counted_per": "march steps done / march steps, like the all-MD price"},
                      "runs": runs}
     return out
 
@@ -329,18 +372,28 @@ def main():
     ap.add_argument("--force-path", type=int, default=-1, help="0 cell lists, 1 pair lists, -1 library choice")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the surrogate and hybrid-solve measurement")
     ap.add_argument("--train-points", type=int, default=256)
-    ap.add_argument("--taus", type=lambda t: [float(x) for x in t.split(",")], default=[0.05],
-                    help="relative uncertainty thresholds of the hybrid runs, comma separated")
+    ap.add_argument("--taus", type=lambda t: [float(x) for x in t.split(",")], default=[0.01, 0.05, 0.10],
+                    help="relative uncertainty thresholds of the GP hybrid runs, comma separated")
+    ap.add_argument("--ens-taus", type=lambda t: [float(x) for x in t.split(",")], default=[0.05],
+                    help="thresholds at which the ensemble also marches")
+    ap.add_argument("--rules", type=lambda t: t.split(","), default=["plain", "floor"],
+                    help="threshold rules: plain (std > tau |mean|) and floor (std > max(tau |mean|, median "
+                         "training SE))")
     ap.add_argument("--audit-every", type=int, default=1009,
                     help="audit every k-th surrogate answer; a k coprime with the 200 sections makes successive "
                          "audits visit different sections (k = 1000 audits one section only)")
     ap.add_argument("--hybrid-steps", type=int, default=HY_STEPS)
     ap.add_argument("--refit-every", type=int, default=1, help="ensemble retrains after this many new MD points")
+    ap.add_argument("--gp-hyper", choices=("evidence", "paper"), default="evidence",
+                    help="GP sigma_f and l: maximise the evidence on the training data (Sec. 2.3's procedure), or "
+                         "the paper's values 1, 1")
     ap.add_argument("--all-md-steps", type=int, default=1, help="macro steps run all-MD to price the all-MD march")
     ap.add_argument("--hybrid-budget", type=float, default=60.0,
                     help="wall-clock cap (s) of one hybrid run; the speed-up is then taken over the steps done")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time the candidate configurations first (outside the timed region) and use the fastest")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (by default it times its candidates on the batch, outside the timed "
+                         "region, and the batch uses the fastest)")
+    ap.add_argument("--tune-steps", type=int, default=200, help="probe steps per autotuner candidate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--summarize-pmc", default="", metavar="CSV",
@@ -365,11 +418,12 @@ def main():
     jobs = workloads.batch_jobs(64)
     params = hmd.Params(n_equil=N_EQUIL, skin=args.skin, force_path=args.force_path, **workloads.batch_box())
     ctx = hmd.Context(params)
-    tune_table = None
-    if args.autotune:
+    tune_table, tune_s = None, None
+    if not args.no_autotune and args.force_path < 0:
         t0 = time.perf_counter()
-        tune_table = hmd.md_autotune(ctx, [(j.h, j.g, j.seed, N_SAMPLE) for j in jobs], probe_steps=200)
-        log(f"autotune in {time.perf_counter() - t0:.1f} s: {tune_table.tolist()}")
+        tune_table = hmd.md_autotune(ctx, [(j.h, j.g, j.seed, N_SAMPLE) for j in jobs], probe_steps=args.tune_steps)
+        tune_s = time.perf_counter() - t0
+        log(f"autotune in {tune_s:.1f} s: {tune_table.tolist()}")
     t0 = time.perf_counter()
     batch = hmd.Batch(ctx, [(j.h, j.g, j.seed, N_SAMPLE) for j in jobs])
     log(f"batch set up in {time.perf_counter() - t0:.1f} s: {batch.atoms} fluid atoms")
@@ -421,6 +475,7 @@ def main():
     kern_windows = {p: {"timed_steps": n, "launches_timed": int(km["force"][1]),
                         **{k: float(km[k][0]) for k in names + ("graph_step",)}} for p, n, km in windows}
     cfg = batch.config()
+    tuning = batch.tuning()
     if done < N_EQUIL + N_SAMPLE:  # finish the sampling window (untimed) for the flux results
         advance(batch, N_EQUIL + N_SAMPLE - done, args.chunk)
     res = batch.results()
@@ -468,7 +523,10 @@ def main():
                                + (f" (the other equilibration steps untimed)" if plan['skip'] else ""),
                    "systems": len(jobs), "fluid_atoms": n_atoms, "graph_chunk": plan["chunk"],
                    "force_path": PATH_NAMES[cfg["path"]], "skin": cfg["skin"],
-                   "threads_per_block": cfg["tpb"],
+                   "threads_per_block": cfg["tpb"], "tile_alpha": tuning["tile_alpha"],
+                   "cell_width": tuning["cell_width"], "whole_run_graph_chunk": tuning["graph_chunk"],
+                   "tiles": tuning["tiles"],
+                   "autotuned": tune_table is not None,
                    "list_builds_per_step": builds / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": cnt["traffic"] if cnt else None,
@@ -482,6 +540,10 @@ def main():
                         "steps each, direct launches",
         "kernel_ms": kern,
         "kernel_ms_windows": kern_windows,
+        "autotune": None if tune_table is None else {
+            "seconds": tune_s, "probe_steps": args.tune_steps,
+            "candidates": [dict(zip(("path", "skin", "tpb", "tile_alpha", "cell_w", "chunk", "ms_per_step"),
+                                    [float(v) for v in row])) for row in tune_table]},
     }
     if res:
         st = [r["status"] for r in res]

@@ -77,9 +77,16 @@ typedef struct {
      * fallback that a tile takes when its neighbourhood exceeds the LDS
      * capacity (for tests; reported as path 2); -1: the library's tuned
      * choice.  cell_w: minimum cell width (0: rc, or rc + skin for the pair
-     * lists). */
+     * lists).  tile_alpha (tiled path): each system's tiles take the column
+     * count that minimises (padded lanes + tile_alpha x staged atoms) per
+     * home atom; 0 = fill the lanes, larger values favour wider tiles that
+     * stage less halo per atom.  graph_chunk: steps per captured graph of
+     * the whole-run calls (even; 0 = 100).  force_path -1 applies what
+     * md_autotune chose for the workload, where it has run. */
     int force_path;
     double skin, cell_w;
+    double tile_alpha;
+    int graph_chunk;
 } hmd_md_params;
 
 void hmd_md_params_default(hmd_md_params* p);
@@ -141,6 +148,14 @@ int md_batch_results(hmd_batch* b, hmd_md_result* out);
  * doubles each), e.g. a warm start from a stored state; the forces are
  * recomputed.  The step count and sampling schedule are unchanged. */
 int md_batch_set_state(hmd_batch* b, int sim, const double* x, const double* v);
+/* The same for m systems at once (one upload): system sims[j] takes x[j]
+ * and v[j] (n_fluid x 3 doubles each, atom id order); the others keep
+ * their state.  EINVAL for an index out of range or given twice. */
+int md_batch_set_states(hmd_batch* b, int m, const int* sims, const double* const* x, const double* const* v);
+/* The states of every system (one download): x[k] and v[k] receive system
+ * k's positions and velocities (n_fluid x 3 doubles each, atom id order);
+ * a null x[k] or v[k] skips it. */
+int md_batch_get_states(hmd_batch* b, double* const* x, double* const* v);
 /* The sampled flux series q'(t) of one system (Sec. 2.1 flow rate per step):
  * *n receives its length, q (nullable, *n doubles) the values.  One entry
  * per sampled step while n_sample <= 65536; beyond, each entry is the mean
@@ -176,13 +191,24 @@ int md_batch_forces(hmd_batch* b, int sim, float* f, double* pe);
 /* The implementation choices in use: force path (0 cell, 1 pair list),
  * pair-list skin, threads per block, pair-list capacity per atom. */
 int md_batch_config(const hmd_batch* b, int* path, double* skin, int* tpb, int* list_cap);
+/* All implementation choices of a batch, 8 doubles: force path, skin,
+ * threads per block, tile_alpha, cell width in use (sigma), graph chunk of
+ * whole-run calls, tiles (tiled path) and pair-list capacity. */
+int md_batch_tuning(const hmd_batch* b, double out[8]);
 
-/* Autotuner: times `probe_steps` steps (after a warm-up of a quarter of
- * that) of these jobs for each candidate (force path, skin, threads per
- * block), and keeps the fastest for later batches of the same workload
- * signature on this context (force_path -1).  table (nullable, 4 doubles per
- * candidate: path, skin, threads per block, ms per step); n_rows receives the
- * number of candidates. */
+/* Autotuner (the project's own): picks the force path, pair-list skin (0.05
+ * steps), tile size (tile_alpha), cell width and graph chunk for these jobs
+ * by timing them.  One warm-up batch of the default configuration runs
+ * probe_steps steps from the start lattice; every candidate then starts from
+ * that warmed state and is timed over probe_steps steps of graph replays.
+ * The search is coordinate descent: path and threads per block, then skin,
+ * then tile_alpha, then cell width, then graph chunk, each axis at the best
+ * of the previous ones.  The winner is kept for later batches of the same
+ * workload signature on this context (number of systems, total atoms to a
+ * factor of 2, box, mean height to 1 sigma) and used when force_path is -1.
+ * table (nullable, room for 64 rows of 7 doubles): per candidate path,
+ * skin, threads per block, tile_alpha, cell width parameter, graph chunk, ms
+ * per step; n_rows receives the number of candidates timed. */
 int md_autotune(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int probe_steps, double* table, int* n_rows);
 void md_batch_free(hmd_batch* b);
 
@@ -281,6 +307,14 @@ typedef struct {
     int scale_mode;                /* 0: mean pairwise separation; 1: fixed ranges */
     double range[4];               /* per-input ranges for scale_mode 1 / fallback */
     int out_scale;                 /* 1: divide y by its RMS before fitting */
+    /* noise_mode 1: heteroscedastic noise, each point's own (y_se_i / output
+     * scale)^2 on the diagonal of C in place of sigma_n^2.  kernel 1: the
+     * periodic kernel of App. B (Eq. periodicKernel),
+     * sigma_f^2 exp(-2 sin^2(pi |t - t'| / period) / ell^2), on a single
+     * input (d = 1) with no input normalisation. */
+    int noise_mode;
+    int kernel;
+    double period;
 } hmd_gp_hyper;
 
 void hmd_gp_hyper_default(hmd_gp_hyper* h);
@@ -297,6 +331,21 @@ int gp_predict(hmd_gp* gp, const double* Xs, int m, double* mean, double* var);
  * different streams must not overlap. */
 int gp_predict_dev(hmd_gp* gp, const double* dXs, int m, double* dmean, double* dvar, void* stream);
 int gp_log_marginal(hmd_gp* gp, double* lml);
+/* Hyperparameters that maximise Eq. evidenceEq (Sec. 2.3: the paper's
+ * sigma_f and l; App. B: l and sigma_n of the periodic kernel): mask bit 0
+ * sigma_f, bit 1 ell, bit 2 sigma_n (uniform noise only; it is then held
+ * explicitly, in output units).  The evidence may have several local
+ * maxima: a grid of 17 points per chosen parameter, a quarter decade apart
+ * over two decades either side of the current values, picks the start of
+ * cyclic golden-section searches over the logarithm of each chosen
+ * parameter (bracket: a factor 10 either side of the current value), every
+ * evaluation a refit on the device, until a cycle gains less than 1e-12
+ * relative.  Cost: 17^m refits for m chosen parameters, then the search.  The GP is left fitted at the optimum;
+ * *lml (nullable) receives the maximum.  Later appends keep the optimised
+ * values. */
+int gp_optimize(hmd_gp* gp, int mask, double* lml);
+/* The hyperparameters in use (after gp_optimize, the optimised ones). */
+int gp_hyper_get(const hmd_gp* gp, hmd_gp_hyper* hyper);
 int gp_size(const hmd_gp* gp);
 /* The normalisation in use: per-input denominators of Eq. d2Eq (d values),
  * the output scale and sigma_n in scaled units (each nullable). */
@@ -377,6 +426,31 @@ typedef struct {
     int mirror;        /* 1: use q(h, -g) = -q(h, g) (default), 0: query g as it is */
     int audit_batch;   /* audits wait until this many are pending, then run as one
                           MD batch (0: in the step that drew them) */
+    /* Warm starts (Alg. 1 "find nearest prior input", "pseudoMD"; Sec. 2.4):
+     * with warm_start on, a fallback run starts from the final state of the
+     * earlier fallback run of the same height whose input has the largest
+     * covariance with the new one (the same height leaves only the body
+     * force to compare: the nearest |g|), else from the lattice; its
+     * equilibration is the start-up time of the 1-D channel flow with Navier
+     * slip (viscosity pseudo_nu, slip length pseudo_slip) from the prior's
+     * body force (0 from the lattice) to the new one, until the flow rate is
+     * within pseudo_tol of its new steady value (relative to the larger of
+     * the two steady flow rates), in steps, at least n_min_warm
+     * (n_min_cold from the lattice).  The runs of one step share a batch and
+     * step together, so the batch equilibrates for the longest of them.
+     * Audits always start from the lattice with params.n_equil. */
+    int warm_start;
+    double pseudo_nu, pseudo_slip, pseudo_tol;
+    int64_t n_min_warm, n_min_cold;
+    /* geometry 1: the paper's benchmark channel (Sec. 2.1), periodic in s
+     * (the first section at inlet and outlet), sections at s_i = i L / n
+     * (Eq. subsEq, 0-based), h = amp h0 (cos(2 pi s / L) - 1) + h0 (Eq.
+     * heightEq: h_1 = h0, a = amp h0), driven by the uniform external force
+     * per unit mass f_amp sin(2 pi t / f_period) (Eq. extForcing1, t in macro
+     * steps); pressure gradient and face fluxes wrap around, and p_out,
+     * dp_mean, dp_amp and period are unused.  geometry 0: the channel above. */
+    int geometry;
+    double f_amp, f_period;
 } hmd_hybrid_cfg;
 typedef struct {
     int64_t steps, md_calls, audited, audit_pass, queries, md_failed;
@@ -384,6 +458,15 @@ typedef struct {
     /* audits run apart from the fallback batch: their time and atom-steps
      * (included in wall_s, excluded from md_wall_s and md_atom_steps) */
     double audit_wall_s, audit_atom_steps;
+    /* fallback runs: equilibration atom-steps run, warm starts, and the
+     * atom-steps the same runs would have taken from the lattice with
+     * params.n_equil */
+    double md_equil_atom_steps;
+    int64_t warm_starts;
+    double md_atom_steps_cold;
+    /* audits that also pass when the surrogate's own predicted standard
+     * deviation is counted: |mean - q_MD| <= 2 sqrt(std^2 + SE_MD^2) */
+    int64_t audit_pass_cal;
 } hmd_hybrid_stats;
 
 /* A replacement micro-solver: given n (h, g) pairs, write the mean flux and
@@ -400,6 +483,14 @@ int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* 
 int hybrid_set_micro(hmd_hybrid* hy, hmd_micro_fn fn, void* user);
 /* Overwrite the density of every section (n_sections doubles). */
 int hybrid_set_rho(hmd_hybrid* hy, const double* rho);
+/* The fallback plan of the last macro step, per section (each nullable):
+ * prior[i] = index (in order of recording) of the earlier fallback run it
+ * starts from, -1 from the lattice, -2 when the section did not fall back;
+ * n_equil[i] its start-up in steps (0 when it did not fall back);
+ * *batch_equil the equilibration of the step's batch.  Every fallback run
+ * that converged is recorded, also under a replacement micro-solver, where
+ * the plan is computed the same way but no state is stored or used. */
+int hybrid_last_plan(hmd_hybrid* hy, int* prior, int64_t* n_equil, int64_t* batch_equil);
 /* One macro step; out (nullable) receives the cumulative statistics. */
 int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out);
 /* rho, q, q_std, g (n_sections doubles), from_md (n_sections bytes); each

@@ -51,7 +51,8 @@ class MdParams(_c.Structure):
     _fields_ = [("rho", d), ("T0", d), ("rc", d), ("eps_wf", d), ("sigma_wf", d), ("rho_wall", d),
                 ("wall_layers", i32), ("thermo_axis", i32), ("dt", d), ("tau_T", d), ("Lx_nom", d),
                 ("Lz_nom", d), ("bin_dy", d), ("n_equil", i64), ("n_blocks", i32), ("n_fluid", i64),
-                ("delta", d), ("force_path", i32), ("skin", d), ("cell_w", d)]
+                ("delta", d), ("force_path", i32), ("skin", d), ("cell_w", d), ("tile_alpha", d),
+                ("graph_chunk", i32)]
 
 
 class MdJob(_c.Structure):
@@ -107,17 +108,22 @@ _sig("md_neighbor_lists", i32, vp, P(u32), P(u32), i64, P(i64))
 _sig("md_sys_config", i32, vp, P(i32), P(d), P(i32), P(i32))
 _sig("md_batch_config", i32, vp, P(i32), P(d), P(i32), P(i32))
 _sig("md_autotune", i32, vp, P(MdJob), i32, i32, P(d), P(i32))
+_sig("md_batch_tuning", i32, vp, P(d))
+
+
+TUNE_COLUMNS = ("path", "skin", "tpb", "tile_alpha", "cell_w", "chunk", "ms_per_step")
 
 
 def md_autotune(ctx, jobs, probe_steps=200):
-    """Time every candidate configuration on these jobs; the fastest is kept
-    for later batches of the same workload.  Returns rows of
-    (path, skin, threads per block, ms per step)."""
+    """Time the candidate configurations on these jobs (coordinate descent
+    over path, skin, tile size, cell width, graph chunk); the fastest is
+    kept for later batches of the same workload.  Returns one row per
+    candidate with the columns of TUNE_COLUMNS."""
     arr = _jobs(jobs)
-    table = np.zeros(4 * 32)
+    table = np.zeros(7 * 64)
     n = i32()
     ctx.check(_lib.md_autotune(ctx.handle, arr, len(jobs), int(probe_steps), _ptr(table), _c.byref(n)))
-    return table[:4 * n.value].reshape(-1, 4)
+    return table[:7 * n.value].reshape(-1, 7)
 
 
 def _config(fn, h):
@@ -163,6 +169,8 @@ class Params:
     force_path: int = -1
     skin: float = 0.3
     cell_w: float = 0.0
+    tile_alpha: float = 0.0
+    graph_chunk: int = 0
 
     def to_c(self):
         return MdParams(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -382,6 +390,12 @@ class Batch:
     def config(self):
         return _config(_lib.md_batch_config, self._h)
 
+    def tuning(self):
+        out = np.zeros(8)
+        self.ctx.check(_lib.md_batch_tuning(self._h, _ptr(out)))
+        return {"path": int(out[0]), "skin": out[1], "tpb": int(out[2]), "tile_alpha": out[3], "cell_width": out[4],
+                "graph_chunk": int(out[5]), "tiles": int(out[6]), "list_cap": int(out[7])}
+
     def close(self):
         if self._h:
             _lib.md_batch_free(self._h)
@@ -475,7 +489,7 @@ class System:
 # ---------------------------------------------------------------- GP surrogate
 class GpHyper(_c.Structure):
     _fields_ = [("sigma_f", d), ("ell", d), ("sigma_n", d), ("scale_mode", i32), ("range", d * 4),
-                ("out_scale", i32)]
+                ("out_scale", i32), ("noise_mode", i32), ("kernel", i32), ("period", d)]
 
 
 _sig("hmd_gp_hyper_default", None, P(GpHyper))
@@ -484,15 +498,19 @@ _sig("gp_append", i32, vp, P(d), d, d)
 _sig("gp_predict", i32, vp, P(d), i32, P(d), P(d))
 _sig("gp_predict_dev", i32, vp, vp, i32, vp, vp, vp)
 _sig("gp_log_marginal", i32, vp, P(d))
+_sig("gp_optimize", i32, vp, i32, P(d))
+_sig("gp_hyper_get", i32, vp, P(GpHyper))
 _sig("gp_size", i32, vp)
 _sig("gp_scales", i32, vp, P(d), P(d), P(d))
 _sig("gp_free", None, vp)
 
 
-def gp_hyper(sigma_f=1.0, ell=1.0, sigma_n=-1.0, scale_mode=0, ranges=(16.0, 0.049), out_scale=1):
+def gp_hyper(sigma_f=1.0, ell=1.0, sigma_n=-1.0, scale_mode=0, ranges=(16.0, 0.049), out_scale=1, noise_mode=0,
+             kernel=0, period=1.0):
     h = GpHyper()
     _lib.hmd_gp_hyper_default(_c.byref(h))
     h.sigma_f, h.ell, h.sigma_n, h.scale_mode, h.out_scale = sigma_f, ell, sigma_n, scale_mode, out_scale
+    h.noise_mode, h.kernel, h.period = noise_mode, kernel, period
     for k, r in enumerate(ranges):
         h.range[k] = r
     return h
@@ -552,6 +570,21 @@ class GP:
         sq, sn = d(), d()
         self.ctx.check(_lib.gp_scales(self._h, _ptr(sc), _c.byref(sq), _c.byref(sn)))
         return sc, sq.value, sn.value
+
+    def optimize(self, which=("sigma_f", "ell")):
+        """Maximise the evidence (Eq. evidenceEq) over the named
+        hyperparameters; returns the maximum."""
+        bits = {"sigma_f": 1, "ell": 2, "sigma_n": 4}
+        mask = sum(bits[k] for k in which)
+        v = d()
+        self.ctx.check(_lib.gp_optimize(self._h, mask, _c.byref(v)))
+        return v.value
+
+    def hyper(self):
+        h = GpHyper()
+        self.ctx.check(_lib.gp_hyper_get(self._h, _c.byref(h)))
+        return {"sigma_f": h.sigma_f, "ell": h.ell, "sigma_n": h.sigma_n, "noise_mode": h.noise_mode,
+                "kernel": h.kernel, "period": h.period}
 
     def close(self):
         if self._h:

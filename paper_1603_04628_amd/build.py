@@ -35,6 +35,7 @@ SOURCES = [
     ("gp.hip", "hip"),
     ("ens.hip", "hip"),
     ("hybrid.cpp", "host"),
+    ("startup.cpp", "host"),
 ]
 
 

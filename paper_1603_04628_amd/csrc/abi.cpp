@@ -43,6 +43,7 @@ void hmd_md_params_default(hmd_md_params* p) {
   p->Lx_nom = 12.0; p->Lz_nom = 12.0; p->bin_dy = 0.25;
   p->n_equil = 0; p->n_blocks = 0; p->n_fluid = 0; p->delta = 1.0;
   p->force_path = -1; p->skin = 0.3; p->cell_w = 0.0;
+  p->tile_alpha = 0.0; p->graph_chunk = 0;
 }
 
 int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ctx** out) {
@@ -180,6 +181,38 @@ int md_batch_set_state(hmd_batch* b, int sim, const double* x, const double* v) 
   return guarded(b->ctx, [&] { return hmd::batch_set_state(b, sim, x, v); });
 }
 
+int md_batch_set_states(hmd_batch* b, int m, const int* sims, const double* const* x, const double* const* v) {
+  if (!b || m < 0 || (m > 0 && (!sims || !x || !v))) return HMD_EINVAL;
+  return guarded(b->ctx, [&]() -> int {
+    std::vector<std::vector<double>> xs(b->S), vs(b->S);
+    for (int j = 0; j < m; ++j) {
+      const int k = sims[j];
+      if (k < 0 || k >= b->S || !x[j] || !v[j] || !xs[k].empty()) {
+        b->ctx->err = "md_batch_set_states: bad or repeated system index, or a null array";
+        return HMD_EINVAL;
+      }
+      const size_t n3 = 3 * size_t(b->sims[k].nf);
+      xs[k].assign(x[j], x[j] + n3);
+      vs[k].assign(v[j], v[j] + n3);
+    }
+    if (m == 0) return HMD_OK;
+    return hmd::batch_set_all_states(b, xs, vs);
+  });
+}
+
+int md_batch_get_states(hmd_batch* b, double* const* x, double* const* v) {
+  if (!b || !x || !v) return HMD_EINVAL;
+  return guarded(b->ctx, [&]() -> int {
+    std::vector<std::vector<double>> xs, vs;
+    HMD_TRY(hmd::batch_get_all_states(b, xs, vs));
+    for (int k = 0; k < b->S; ++k) {
+      if (x[k]) std::copy(xs[k].begin(), xs[k].end(), x[k]);
+      if (v[k]) std::copy(vs[k].begin(), vs[k].end(), v[k]);
+    }
+    return HMD_OK;
+  });
+}
+
 int md_batch_series(hmd_batch* b, int sim, double* q, int64_t* n) {
   if (!b) return HMD_EINVAL;
   return guarded(b->ctx, [&] { return hmd::batch_series(b, sim, q, n); });
@@ -262,7 +295,7 @@ int md_flux_batch(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_md_result* ou
       hmd_batch* b = nullptr;
       int rc = hmd::batch_create(ctx, sub.data(), int(sub.size()), &b);
       if (rc != HMD_OK) return rc;
-      rc = hmd::batch_run(b, ctx->params.n_equil + kv.first, kDefaultChunk, true, nullptr);
+      rc = hmd::batch_run(b, ctx->params.n_equil + kv.first, b->chunk, true, nullptr);
       std::vector<hmd_md_result> res(sub.size());
       if (rc == HMD_OK) rc = hmd::batch_results(b, res.data());
       hmd::batch_free(b);

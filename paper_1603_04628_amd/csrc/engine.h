@@ -99,8 +99,8 @@ struct Acc {
 };
 
 enum Kern { K_INTEGRATE = 0, K_SCAN, K_SCATTER, K_REORDER, K_FORCE, K_KEYS, K_LIST, K_COUNT };
-constexpr int kStampedSteps = 5;  // steps per timed graph replay whose kernels are stamped
-constexpr int kMaxStamps = 64;     // stamps of one timed replay (kernels + 1 per stamped step, + 1)
+constexpr int kStampedSteps = 10;  // steps per timed graph replay whose kernels are stamped
+constexpr int kMaxStamps = 96;     // stamps of one timed replay (kernels + 1 per stamped step, + 1)
 
 }  // namespace hmd
 
@@ -118,6 +118,9 @@ struct hmd_batch {
   int path = 1;           // 0 cell path, 1 pair path
   int tpb = 256;          // threads per block of the per-slot kernels
   double skin = 0.3;
+  double tile_alpha = 0.0;  // tiled path: weight of staged atoms in the tile choice
+  double cell_w = 0.0;      // cell width parameter in use
+  int chunk = 100;          // graph chunk of whole-run calls
   int list_cap = 0, list_ld = 0;
   bool uniform = false;   // one fixed-point unit on all axes in every system
   bool walls_same = false;  // wall-fluid LJ parameters equal the fluid's
@@ -201,6 +204,22 @@ int batch_pairs(hmd_batch* b, int64_t* ff, int64_t* wf);
 int batch_list_builds(hmd_batch* b, int64_t* builds);
 int batch_series(hmd_batch* b, int sim, double* q, int64_t* n);
 int batch_neighbors(hmd_batch* b, int sim, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total);
+// Implementation choices of a batch.
+struct Config {
+  int path = 2;
+  double skin = 0.3;
+  int tpb = 256;
+  double tile_alpha = 0.0;
+  double cell_w = 0.0;
+  int chunk = 100;
+};
 // Resolved implementation choices for a batch of these jobs on this context.
-void choose_path(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int* path, double* skin, int* tpb);
+Config choose_config(hmd_ctx* ctx, const hmd_md_job* jobs, int n);
+// Graph chunk of whole-run calls for these jobs.
+int run_chunk(hmd_ctx* ctx, const hmd_md_job* jobs, int n);
+// The state of every system at once (atom id order, one download), and its
+// inverse (one upload; a system given empty vectors keeps its state).
+int batch_get_all_states(hmd_batch* b, std::vector<std::vector<double>>& x, std::vector<std::vector<double>>& v);
+int batch_set_all_states(hmd_batch* b, const std::vector<std::vector<double>>& x,
+                         const std::vector<std::vector<double>>& v);
 }  // namespace hmd

@@ -9,6 +9,9 @@
 //                L^-1 formed once per factorisation so that a query is a
 //                parallel product, not a sequential solve
 //   evidence     -1/2 y^T alpha - sum log L_ii - n/2 log 2 pi (Eq. evidenceEq)
+// Options: each point's own noise variance on the diagonal (heteroscedastic),
+// the periodic kernel of App. B (Eq. periodicKernel) on a single input, and
+// hyperparameters that maximise the evidence (gp_optimize).
 // Database sizes here are hundreds of points: the triangular solves are
 // latency bound, so one workgroup walks the columns with barriers; the
 // factorisation spreads each panel's update over many workgroups, and
@@ -36,6 +39,7 @@ struct hmd_gp {
   double* dLi = nullptr;     // L^-1, same layout (lower triangle)
   double* dalpha = nullptr;  // C^-1 y
   double* dtmp = nullptr;    // cap
+  double* dnoise = nullptr;  // cap: per-point noise variances (heteroscedastic)
   double* dq = nullptr;      // query staging
   double* dout = nullptr;    // predictions / scalars
   int* dinfo = nullptr;
@@ -51,10 +55,18 @@ constexpr int GP_MAXN = 6144;  // database points: k* and the substitution vecto
 struct KParams {
   double inv_scale[GP_MAXD];
   double sf2, inv_2l2, sn2;
+  double pi_over_T;  // periodic kernel: pi / T
   int d;
+  int kind;          // 0 squared exponential (Eq. quadraticKernelEq), 1 periodic (Eq. periodicKernel)
 };
 
+// K(a, b): sigma_f^2 exp(-d^2 / 2 l^2) on the normalised distance of Eq.
+// d2Eq, or sigma_f^2 exp(-2 sin^2(pi |t - t'| / T) / l^2) on the first input
 __device__ __forceinline__ double sqexp(const double* a, const double* b, const KParams& P) {
+  if (P.kind == 1) {
+    const double sn = sin(P.pi_over_T * fabs(a[0] - b[0]));
+    return P.sf2 * exp(-4.0 * sn * sn * P.inv_2l2);
+  }
   double d2 = 0.0;
   for (int k = 0; k < P.d; ++k) {
     const double t = (a[k] - b[k]) * P.inv_scale[k];
@@ -63,13 +75,15 @@ __device__ __forceinline__ double sqexp(const double* a, const double* b, const 
   return P.sf2 * exp(-d2 * P.inv_2l2);
 }
 
-// Lower triangle (and diagonal) of C for rows/cols [0, n).
-__global__ void k_gp_cov(int n, int ld, const double* __restrict__ X, KParams P, double* __restrict__ L) {
+// Lower triangle (and diagonal) of C for rows/cols [0, n); the diagonal
+// takes noise[i] when given (per-point variances), else sn2.
+__global__ void k_gp_cov(int n, int ld, const double* __restrict__ X, KParams P, const double* __restrict__ noise,
+                         double* __restrict__ L) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= n || j >= n || i < j) return;
   double c = sqexp(X + GP_MAXD * i, X + GP_MAXD * j, P);
-  if (i == j) c += P.sn2;
+  if (i == j) c += noise ? noise[i] : P.sn2;
   L[i + size_t(j) * ld] = c;
 }
 
@@ -373,6 +387,8 @@ KParams kparams(const hmd_gp* g) {
   P.inv_2l2 = 1.0 / (2.0 * g->hyp.ell * g->hyp.ell);
   P.sn2 = g->sigma_n * g->sigma_n;
   P.d = g->d;
+  P.kind = g->hyp.kernel;
+  P.pi_over_T = g->hyp.kernel == 1 ? M_PI / g->hyp.period : 0.0;
   return P;
 }
 
@@ -411,7 +427,7 @@ int reserve(hmd_gp* g, int need) {
   if (need <= g->cap) return HMD_OK;
   int cap = g->cap > 0 ? g->cap : 64;
   while (cap < need) cap *= 2;
-  for (double* p : {g->dX, g->dy, g->dL, g->dLi, g->dalpha, g->dtmp})
+  for (double* p : {g->dX, g->dy, g->dL, g->dLi, g->dalpha, g->dtmp, g->dnoise})
     if (p) (void)hipFree(p);
   HMD_HIP(ctx, hipMalloc(&g->dX, sizeof(double) * GP_MAXD * cap));
   HMD_HIP(ctx, hipMalloc(&g->dy, sizeof(double) * cap));
@@ -419,19 +435,25 @@ int reserve(hmd_gp* g, int need) {
   HMD_HIP(ctx, hipMalloc(&g->dLi, sizeof(double) * size_t(cap) * cap));
   HMD_HIP(ctx, hipMalloc(&g->dalpha, sizeof(double) * cap));
   HMD_HIP(ctx, hipMalloc(&g->dtmp, sizeof(double) * (cap + 1)));
+  HMD_HIP(ctx, hipMalloc(&g->dnoise, sizeof(double) * cap));
   g->cap = cap;
   return HMD_OK;
 }
 
 int upload_db(hmd_gp* g) {
   hmd_ctx* ctx = g->ctx;
-  std::vector<double> xs(size_t(GP_MAXD) * g->n, 0.0), ys(g->n);
+  std::vector<double> xs(size_t(GP_MAXD) * g->n, 0.0), ys(g->n), nz(g->n);
   for (int i = 0; i < g->n; ++i) {
     for (int k = 0; k < g->d; ++k) xs[size_t(i) * GP_MAXD + k] = g->X[size_t(i) * g->d + k];
     ys[i] = g->y[i] / g->s_q;
+    const double e = g->se[i] / g->s_q;
+    nz[i] = e * e;
   }
   HMD_HIP(ctx, hipMemcpyAsync(g->dX, xs.data(), 8 * xs.size(), hipMemcpyHostToDevice, ctx->stream));
   HMD_HIP(ctx, hipMemcpyAsync(g->dy, ys.data(), 8 * ys.size(), hipMemcpyHostToDevice, ctx->stream));
+  HMD_HIP(ctx, hipMemcpyAsync(g->dnoise, nz.data(), 8 * nz.size(), hipMemcpyHostToDevice, ctx->stream));
+  // the host staging vectors end with this function
+  HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return HMD_OK;
 }
 
@@ -462,7 +484,8 @@ int refit(hmd_gp* g) {
   if ((rc = upload_db(g)) != HMD_OK) return rc;
   hipStream_t s = ctx->stream;
   const KParams P = kparams(g);
-  hipLaunchKernelGGL(k_gp_cov, dim3((g->n + 255) / 256, g->n), dim3(256), 0, s, g->n, g->cap, g->dX, P, g->dL);
+  hipLaunchKernelGGL(k_gp_cov, dim3((g->n + 255) / 256, g->n), dim3(256), 0, s, g->n, g->cap, g->dX, P,
+                     g->hyp.noise_mode == 1 ? g->dnoise : nullptr, g->dL);
   for (int k0 = 0; k0 < g->n; k0 += CB) {
     hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, g->n, g->cap, g->dL, g->dinfo, k0);
     const int rest = g->n - k0 - CB;
@@ -502,6 +525,9 @@ void hmd_gp_hyper_default(hmd_gp_hyper* h) {
   h->range[2] = 1.0;
   h->range[3] = 1.0;
   h->out_scale = 1;
+  h->noise_mode = 0;
+  h->kernel = 0;
+  h->period = 1.0;
 }
 
 int gp_fit(hmd_ctx* ctx, const double* X, const double* y, const double* y_se, int n, int d,
@@ -515,9 +541,10 @@ int gp_fit(hmd_ctx* ctx, const double* X, const double* y, const double* y_se, i
   g->ctx = ctx;
   if (hyper) g->hyp = *hyper;
   else hmd_gp_hyper_default(&g->hyp);
-  if (!(g->hyp.sigma_f > 0.0) || !(g->hyp.ell > 0.0)) {
+  if (!(g->hyp.sigma_f > 0.0) || !(g->hyp.ell > 0.0) || g->hyp.noise_mode < 0 || g->hyp.noise_mode > 1 ||
+      g->hyp.kernel < 0 || g->hyp.kernel > 1 || (g->hyp.kernel == 1 && (d != 1 || !(g->hyp.period > 0.0)))) {
     delete g;
-    ctx->err = "gp_fit: sigma_f and ell must be positive";
+    ctx->err = "gp_fit: sigma_f, ell positive; noise_mode 0/1; kernel 0, or 1 (periodic) with d = 1 and period > 0";
     return HMD_EINVAL;
   }
   g->d = d;
@@ -555,8 +582,8 @@ int gp_append(hmd_gp* g, const double* x, double y, double y_se) {
   g->n += 1;
   // fixed normalisation, fixed noise and no output scaling: extend L by one
   // row; otherwise the normalisation moved and the factor is rebuilt
-  const bool rank1 = g->hyp.scale_mode == 1 && g->hyp.out_scale == 0 && g->hyp.sigma_n >= 0.0 && g->n >= 2 &&
-                     g->n <= g->cap;
+  const bool rank1 = (g->hyp.scale_mode == 1 || g->hyp.kernel == 1) && g->hyp.out_scale == 0 &&
+                     (g->hyp.sigma_n >= 0.0 || g->hyp.noise_mode == 1) && g->n >= 2 && g->n <= g->cap;
   // returns with the factor, weights and L^-1 complete, so that a following
   // prediction on any stream sees them
   auto full_refit = [&]() -> int {
@@ -570,8 +597,13 @@ int gp_append(hmd_gp* g, const double* x, double y, double y_se) {
   int rc = upload_db(g);
   if (rc != HMD_OK) return rc;
   hipStream_t s = ctx->stream;
-  hipLaunchKernelGGL(k_gp_append_row, dim3(1), dim3(1024), 0, s, g->n - 1, g->cap, g->dX, kparams(g), g->dL,
-                     g->dtmp, g->dinfo);
+  KParams P1 = kparams(g);
+  if (g->hyp.noise_mode == 1) {
+    const double e = y_se / g->s_q;
+    P1.sn2 = e * e;
+  }
+  hipLaunchKernelGGL(k_gp_append_row, dim3(1), dim3(1024), 0, s, g->n - 1, g->cap, g->dX, P1, g->dL, g->dtmp,
+                     g->dinfo);
   int info = 0;
   HMD_HIP(ctx, hipMemcpyAsync(&info, g->dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
   HMD_HIP(ctx, hipStreamSynchronize(s));
@@ -666,6 +698,109 @@ int gp_log_marginal(hmd_gp* g, double* lml) {
   return HMD_OK;
 }
 
+// Hyperparameters that maximise Eq. evidenceEq (Sec. 2.3; App. B).  The
+// evidence can have several local maxima (the periodic kernel's has in ell),
+// so the search first evaluates it on a grid of 17 points per chosen
+// parameter, a quarter decade apart over two decades either side of the
+// start, then refines from the best grid point by cyclic golden-section
+// searches over the logarithm of each chosen parameter, bracketed by a factor
+// 10 around the current value, each refit on the device, until a cycle gains
+// less than 1e-12 relative (at most 30 cycles).
+int gp_optimize(hmd_gp* g, int mask, double* lml) {
+  if (!g || mask <= 0 || mask > 7) return HMD_EINVAL;
+  hmd_ctx* ctx = g->ctx;
+  if (g->n < 1 || ((mask & 4) && g->hyp.noise_mode == 1)) {
+    ctx->err = "gp_optimize: needs data, and sigma_n only with uniform noise";
+    return HMD_EINVAL;
+  }
+  if (mask & 4) g->hyp.sigma_n = g->sigma_n * g->s_q;  // held explicitly from here on
+  auto get = [&](int k) {
+    return k == 0 ? g->hyp.sigma_f : (k == 1 ? g->hyp.ell : g->hyp.sigma_n / g->s_q);
+  };
+  auto set = [&](int k, double v) {
+    if (k == 0) g->hyp.sigma_f = v;
+    else if (k == 1) g->hyp.ell = v;
+    else g->hyp.sigma_n = v * g->s_q;
+  };
+  auto eval = [&](int k, double logv, double* out) -> int {
+    set(k, std::exp(logv));
+    const int rc = refit(g);
+    if (rc == HMD_ENOTSPD) {
+      *out = -INFINITY;
+      return HMD_OK;
+    }
+    if (rc != HMD_OK) return rc;
+    return gp_log_marginal(g, out);
+  };
+  int idx[3], m = 0, total = 1;
+  double c0[3], cbest[3];
+  for (int k = 0; k < 3; ++k)
+    if (mask & (1 << k)) {
+      idx[m] = k;
+      c0[m] = cbest[m] = std::log(get(k));
+      ++m;
+      total *= 17;
+    }
+  double gbest = -INFINITY;
+  for (int p = 0; p < total; ++p) {
+    int r = p;
+    for (int j = 0; j < m; ++j, r /= 17) set(idx[j], std::exp(c0[j] + std::log(10.0) * (-2.0 + 0.25 * (r % 17))));
+    const int rc = refit(g);
+    if (rc == HMD_ENOTSPD) continue;
+    if (rc != HMD_OK) return rc;
+    double f;
+    HMD_TRY(gp_log_marginal(g, &f));
+    if (f > gbest) {
+      gbest = f;
+      for (int j = 0; j < m; ++j) cbest[j] = std::log(get(idx[j]));
+    }
+  }
+  for (int j = 0; j < m; ++j) set(idx[j], std::exp(cbest[j]));
+  const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+  double best = -INFINITY;
+  HMD_TRY(eval(0, std::log(get(0)), &best));
+  for (int cycle = 0; cycle < 30; ++cycle) {
+    const double start = best;
+    for (int k = 0; k < 3; ++k) {
+      if (!(mask & (1 << k))) continue;
+      const double c0 = std::log(get(k));
+      double a = c0 - std::log(10.0), b = c0 + std::log(10.0);
+      double x1 = b - gr * (b - a), x2 = a + gr * (b - a), f1, f2;
+      HMD_TRY(eval(k, x1, &f1));
+      HMD_TRY(eval(k, x2, &f2));
+      for (int it = 0; it < 60; ++it) {
+        if (f1 >= f2) {
+          b = x2; x2 = x1; f2 = f1; x1 = b - gr * (b - a);
+          HMD_TRY(eval(k, x1, &f1));
+        } else {
+          a = x1; x1 = x2; f1 = f2; x2 = a + gr * (b - a);
+          HMD_TRY(eval(k, x2, &f2));
+        }
+      }
+      double fc;
+      const double xc = 0.5 * (a + b);
+      HMD_TRY(eval(k, xc, &fc));
+      double fold;
+      HMD_TRY(eval(k, c0, &fold));
+      if (fc >= fold) {
+        HMD_TRY(eval(k, xc, &best));
+      } else {
+        best = fold;  // the search did not beat the start: keep it (already refit)
+      }
+    }
+    if (std::fabs(best - start) <= 1e-12 * std::fabs(best)) break;
+  }
+  if (lml) *lml = best;
+  HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return HMD_OK;
+}
+
+int gp_hyper_get(const hmd_gp* g, hmd_gp_hyper* hyper) {
+  if (!g || !hyper) return HMD_EINVAL;
+  *hyper = g->hyp;
+  return HMD_OK;
+}
+
 int gp_size(const hmd_gp* g) { return g ? g->n : 0; }
 
 int gp_scales(const hmd_gp* g, double* scale, double* s_q, double* sigma_n) {
@@ -680,7 +815,7 @@ int gp_scales(const hmd_gp* g, double* scale, double* s_q, double* sigma_n) {
 void gp_free(hmd_gp* g) {
   if (!g) return;
   for (void* p : {(void*)g->dX, (void*)g->dy, (void*)g->dL, (void*)g->dLi, (void*)g->dalpha, (void*)g->dtmp,
-                  (void*)g->dq,
+                  (void*)g->dnoise, (void*)g->dq,
                   (void*)g->dout, (void*)g->dinfo})
     if (p) (void)hipFree(p);
   delete g;

@@ -14,8 +14,17 @@
 #include <vector>
 
 #include "hmd.h"
+#include "startup.h"
 
 struct hmd_ctx;  // opaque here
+
+namespace {
+// One recorded fallback run: its input and, with real MD, its final state.
+struct Warm {
+  double h, g;
+  std::vector<double> x, v;
+};
+}  // namespace
 
 struct hmd_hybrid {
   hmd_ctx* ctx = nullptr;
@@ -31,7 +40,12 @@ struct hmd_hybrid {
   uint64_t next_seed = 0;
   hmd_hybrid_stats st{};
   // audits waiting for their batch: (h, |g|) and the surrogate's answer
-  std::vector<double> audit_h, audit_g, audit_mean;
+  std::vector<double> audit_h, audit_g, audit_mean, audit_sd;
+  // warm starts: the recorded fallback runs and the last step's plan
+  std::vector<Warm> warm;
+  std::vector<int> plan_prior;
+  std::vector<int64_t> plan_equil;
+  int64_t plan_batch_equil = 0;
 };
 
 namespace {
@@ -44,9 +58,14 @@ double seconds_since(clock_t_::time_point t0) {
   return std::chrono::duration<double>(clock_t_::now() - t0).count();
 }
 
-// Fluxes for the listed sections from the micro-solver (callback or batched MD).
+// Fluxes for the listed sections from the micro-solver (callback or batched
+// MD).  Audits run from the lattice with params.n_equil; fallback runs with
+// warm starts use `prior` (index into hy->warm, -1: lattice) and equilibrate
+// for n_equil steps, and return their final states in xs, vs.
 int solve_micro(hmd_hybrid* hy, std::vector<double> hh, std::vector<double> gg, std::vector<double>& qm,
-                std::vector<double>& se, std::vector<int>& ok, bool audit) {
+                std::vector<double>& se, std::vector<int>& ok, bool audit, const std::vector<int>* prior = nullptr,
+                int64_t n_equil = -1, std::vector<std::vector<double>>* xs = nullptr,
+                std::vector<std::vector<double>>* vs = nullptr) {
   double& wall = audit ? hy->st.audit_wall_s : hy->st.md_wall_s;
   double& atom_steps = audit ? hy->st.audit_atom_steps : hy->st.md_atom_steps;
   const int n = int(hh.size());
@@ -62,17 +81,60 @@ int solve_micro(hmd_hybrid* hy, std::vector<double> hh, std::vector<double> gg, 
   std::vector<hmd_md_job> jobs(n);
   for (int k = 0; k < n; ++k) jobs[k] = hmd_md_job{hh[k], gg[k], hy->next_seed++, hy->cfg.md_sample};
   std::vector<hmd_md_result> res(n);
-  const int rc = md_flux_batch(hy->ctx, jobs.data(), n, res.data());
-  wall += seconds_since(t0);
-  if (rc != HMD_OK) return rc;
   hmd_md_params P;
   hmd_get_params(hy->ctx, &P);
+  const int64_t cold_equil = P.n_equil;
+  int rc = HMD_OK;
+  if (!prior) {
+    rc = md_flux_batch(hy->ctx, jobs.data(), n, res.data());
+  } else {
+    // the batch's own equilibration, warm states set after creation
+    hmd_md_params Q = P;
+    Q.n_equil = n_equil;
+    rc = hmd_set_params(hy->ctx, &Q);
+    hmd_batch* b = nullptr;
+    if (rc == HMD_OK) rc = md_batch_create(hy->ctx, jobs.data(), n, &b);
+    hmd_set_params(hy->ctx, &P);
+    if (rc == HMD_OK) {
+      std::vector<int> sims;
+      std::vector<const double*> px, pv;
+      for (int k = 0; k < n; ++k)
+        if ((*prior)[k] >= 0) {
+          sims.push_back(k);
+          px.push_back(hy->warm[(*prior)[k]].x.data());
+          pv.push_back(hy->warm[(*prior)[k]].v.data());
+        }
+      rc = md_batch_set_states(b, int(sims.size()), sims.data(), px.data(), pv.data());
+      if (rc == HMD_OK) rc = md_batch_run(b, n_equil + hy->cfg.md_sample, P.graph_chunk > 0 ? P.graph_chunk : 100);
+      if (rc == HMD_OK) rc = md_batch_results(b, res.data());
+      if (rc == HMD_OK) {
+        xs->assign(n, {});
+        vs->assign(n, {});
+        std::vector<double*> ox(n), ov(n);
+        for (int k = 0; k < n; ++k) {
+          (*xs)[k].resize(3 * size_t(res[k].n_fluid));
+          (*vs)[k].resize(3 * size_t(res[k].n_fluid));
+          ox[k] = (*xs)[k].data();
+          ov[k] = (*vs)[k].data();
+        }
+        rc = md_batch_get_states(b, ox.data(), ov.data());
+      }
+    }
+    if (b) md_batch_free(b);
+  }
+  wall += seconds_since(t0);
+  if (rc != HMD_OK) return rc;
+  const int64_t equil = prior ? n_equil : cold_equil;
   for (int k = 0; k < n; ++k) {
     qm[k] = res[k].flux;
     se[k] = res[k].flux_se;
     ok[k] = res[k].status == HMD_OK;
     hy->st.md_failed += ok[k] || audit ? 0 : 1;
-    atom_steps += double(res[k].n_fluid) * double(P.n_equil + hy->cfg.md_sample);
+    atom_steps += double(res[k].n_fluid) * double(equil + hy->cfg.md_sample);
+    if (!audit) {
+      hy->st.md_equil_atom_steps += double(res[k].n_fluid) * double(equil);
+      hy->st.md_atom_steps_cold += double(res[k].n_fluid) * double(cold_equil + hy->cfg.md_sample);
+    }
   }
   return HMD_OK;
 }
@@ -87,11 +149,15 @@ int flush_audits(hmd_hybrid* hy) {
   for (size_t k = 0; k < qm.size(); ++k) {
     if (!ok[k]) continue;
     hy->st.audited += 1;
-    hy->st.audit_pass += std::fabs(hy->audit_mean[k] - qm[k]) <= 2.0 * se[k] ? 1 : 0;
+    const double dev = std::fabs(hy->audit_mean[k] - qm[k]);
+    hy->st.audit_pass += dev <= 2.0 * se[k] ? 1 : 0;
+    hy->st.audit_pass_cal +=
+        dev <= 2.0 * std::sqrt(hy->audit_sd[k] * hy->audit_sd[k] + se[k] * se[k]) ? 1 : 0;
   }
   hy->audit_h.clear();
   hy->audit_g.clear();
   hy->audit_mean.clear();
+  hy->audit_sd.clear();
   return HMD_OK;
 }
 
@@ -121,6 +187,15 @@ void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c) {
   c->seed = 1000000;
   c->mirror = 1;
   c->audit_batch = 0;
+  c->warm_start = 0;
+  c->pseudo_nu = 2.5;
+  c->pseudo_slip = 0.5;
+  c->pseudo_tol = 0.01;
+  c->n_min_warm = 1000;
+  c->n_min_cold = 2000;
+  c->geometry = 0;
+  c->f_amp = 0.0;
+  c->f_period = 250.0;
 }
 
 int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out) {
@@ -128,7 +203,10 @@ int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* 
   const hmd_hybrid_cfg& c = *cfg;
   if (c.n_sections < 2 || !(c.L > 0.0) || !(c.h0 > 0.0) || !(c.dt_macro > 0.0) || !(c.rho_ref > 0.0) ||
       c.tau_rel < 0.0 || c.tau_abs < 0.0 || (c.surrogate == 0 && !gp) || (c.surrogate == 1 && !ens) ||
-      c.surrogate < 0 || c.surrogate > 1 || c.md_sample < 0 || c.refit_every < 1 || !(c.period > 0.0))
+      c.surrogate < 0 || c.surrogate > 1 || c.md_sample < 0 || c.refit_every < 1 || !(c.period > 0.0) ||
+      (c.warm_start && (!(c.pseudo_nu > 0.0) || !(c.pseudo_slip >= 0.0) || !(c.pseudo_tol > 0.0) ||
+                        c.n_min_warm < 0 || c.n_min_cold < 0)) ||
+      c.geometry < 0 || c.geometry > 1 || (c.geometry == 1 && !(c.f_period > 0.0)))
     return HMD_EINVAL;
   auto* hy = new hmd_hybrid();
   hy->ctx = ctx;
@@ -140,14 +218,21 @@ int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* 
   hy->ds = c.L / double(n);
   hy->h.resize(n);
   for (int i = 0; i < n; ++i) {
-    const double s = (double(i) + 0.5) * hy->ds;
-    hy->h[i] = c.h0 * (1.0 + c.amp * std::cos(kTwoPi * s / c.L));
+    if (c.geometry == 1) {  // Eqs. subsEq and heightEq
+      const double s = double(i) * hy->ds;
+      hy->h[i] = c.amp * c.h0 * (std::cos(kTwoPi * s / c.L) - 1.0) + c.h0;
+    } else {
+      const double s = (double(i) + 0.5) * hy->ds;
+      hy->h[i] = c.h0 * (1.0 + c.amp * std::cos(kTwoPi * s / c.L));
+    }
   }
   hy->rho.assign(n, c.rho_ref);
   hy->q.assign(n, 0.0);
   hy->q_std.assign(n, 0.0);
   hy->g.assign(n, 0.0);
   hy->from_md.assign(n, 0);
+  hy->plan_prior.assign(n, -2);
+  hy->plan_equil.assign(n, 0);
   *out = hy;
   return HMD_OK;
 }
@@ -176,11 +261,19 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   std::vector<double> p(n);
   for (int i = 0; i < n; ++i) p[i] = c.p_out + c.c2 * (hy->rho[i] - c.rho_ref);
   const double p_in = c.p_out + c.dp_mean * (1.0 + c.dp_amp * std::sin(kTwoPi * double(hy->step_no) / c.period));
+  // Eq. extForcing1 on the periodic channel
+  const double f_ext = c.geometry == 1 ? c.f_amp * std::sin(kTwoPi * double(hy->step_no) / c.f_period) : 0.0;
   for (int i = 0; i < n; ++i) {
-    const double pl = i > 0 ? p[i - 1] : p_in;
-    const double pr = i < n - 1 ? p[i + 1] : c.p_out;
+    double pl, pr;
+    if (c.geometry == 1) {
+      pl = p[(i + n - 1) % n];
+      pr = p[(i + 1) % n];
+    } else {
+      pl = i > 0 ? p[i - 1] : p_in;
+      pr = i < n - 1 ? p[i + 1] : c.p_out;
+    }
     const double dpds = (pr - pl) / (2.0 * hy->ds);
-    hy->g[i] = -dpds / hy->rho[i];
+    hy->g[i] = f_ext - dpds / hy->rho[i];
   }
   // surrogate query for every section (at |g| with the sign restored after,
   // when mirror is on)
@@ -217,18 +310,50 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   for (int i = 0; i < n; ++i) qv[i] = sgn[i] * mean[i];
   std::vector<int> fl, au;
   for (int i : run) (flag[i] ? fl : au).push_back(i);
+  std::fill(hy->plan_prior.begin(), hy->plan_prior.end(), -2);
+  std::fill(hy->plan_equil.begin(), hy->plan_equil.end(), int64_t(0));
+  hy->plan_batch_equil = 0;
   if (!fl.empty()) {
     std::vector<double> qm, se, hh, gg;
-    std::vector<int> ok;
+    std::vector<int> ok, prior;
     for (int i : fl) {
       hh.push_back(hy->h[i]);
       gg.push_back(gq[i]);
     }
-    rc = solve_micro(hy, hh, gg, qm, se, ok, false);
+    std::vector<std::vector<double>> xs, vs;
+    if (c.warm_start) {
+      // nearest prior of the same height: with h equal, the covariance of
+      // the inputs falls with |g - g*| alone; ties go to the earliest
+      hmd_md_params P;
+      hmd_get_params(hy->ctx, &P);
+      for (size_t k = 0; k < fl.size(); ++k) {
+        int best = -1;
+        double bd = 0.0;
+        for (size_t j = 0; j < hy->warm.size(); ++j) {
+          if (hy->warm[j].h != hh[k] || (!hy->micro && hy->warm[j].x.empty())) continue;
+          const double d = std::fabs(hy->warm[j].g - gg[k]);
+          if (best < 0 || d < bd) {
+            best = int(j);
+            bd = d;
+          }
+        }
+        const double g_in = best >= 0 ? hy->warm[best].g : 0.0;
+        const double ts = hmd::startup_time(hh[k], g_in, gg[k], c.pseudo_nu, c.pseudo_slip, c.pseudo_tol);
+        const int64_t ne = hmd::startup_steps(ts, P.dt, best >= 0 ? c.n_min_warm : c.n_min_cold);
+        prior.push_back(best);
+        hy->plan_prior[fl[k]] = best;
+        hy->plan_equil[fl[k]] = ne;
+        hy->plan_batch_equil = std::max(hy->plan_batch_equil, ne);
+        hy->st.warm_starts += best >= 0 ? 1 : 0;
+      }
+    }
+    rc = c.warm_start ? solve_micro(hy, hh, gg, qm, se, ok, false, &prior, hy->plan_batch_equil, &xs, &vs)
+                      : solve_micro(hy, hh, gg, qm, se, ok, false);
     if (rc != HMD_OK) return rc;
     hy->st.md_calls += int64_t(fl.size());
     for (size_t k = 0; k < fl.size(); ++k) qv[fl[k]] = sgn[fl[k]] * qm[k];
-    // database growth (runs that failed to converge are left out, Sec. 3.2)
+    // database growth (runs that failed to converge are left out, Sec. 3.2);
+    // with warm starts each converged run is recorded with its final state
     const auto tg = clock_t_::now();
     for (size_t k = 0; k < fl.size(); ++k) {
       const int i = fl[k];
@@ -241,6 +366,14 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
         hy->pending_refit += 1;
       }
       if (rc != HMD_OK) return rc;
+      if (c.warm_start) {
+        Warm w{hh[k], gg[k], {}, {}};
+        if (!xs.empty()) {
+          w.x.swap(xs[k]);
+          w.v.swap(vs[k]);
+        }
+        hy->warm.push_back(std::move(w));
+      }
     }
     if (c.surrogate == 1 && hy->pending_refit >= c.refit_every) {
       rc = ens_refit(hy->ens);
@@ -255,6 +388,7 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
     hy->audit_h.push_back(hy->h[i]);
     hy->audit_g.push_back(gq[i]);
     hy->audit_mean.push_back(mean[i]);
+    hy->audit_sd.push_back(sd[i]);
   }
   if (!hy->audit_h.empty() && int(hy->audit_h.size()) >= std::max(c.audit_batch, 1)) {
     rc = flush_audits(hy);
@@ -262,9 +396,14 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   }
   // conservative update of rho h
   std::vector<double> flux(n + 1);
-  flux[0] = qv[0];
-  flux[n] = qv[n - 1];
   for (int i = 0; i + 1 < n; ++i) flux[i + 1] = 0.5 * (qv[i] + qv[i + 1]);
+  if (c.geometry == 1) {  // the face between the last and first section closes the ring
+    flux[n] = 0.5 * (qv[n - 1] + qv[0]);
+    flux[0] = flux[n];
+  } else {
+    flux[0] = qv[0];
+    flux[n] = qv[n - 1];
+  }
   for (int i = 0; i < n; ++i) {
     const double m = hy->rho[i] * hy->h[i] - c.dt_macro * (flux[i + 1] - flux[i]) / hy->ds;
     hy->rho[i] = m / hy->h[i];
@@ -287,6 +426,15 @@ int hybrid_get(hmd_hybrid* hy, double* rho, double* q, double* q_std, double* g,
   if (q_std) std::memcpy(q_std, hy->q_std.data(), 8 * n);
   if (g) std::memcpy(g, hy->g.data(), 8 * n);
   if (from_md) std::memcpy(from_md, hy->from_md.data(), n);
+  return HMD_OK;
+}
+
+int hybrid_last_plan(hmd_hybrid* hy, int* prior, int64_t* n_equil, int64_t* batch_equil) {
+  if (!hy) return HMD_EINVAL;
+  const size_t n = size_t(hy->cfg.n_sections);
+  if (prior) std::memcpy(prior, hy->plan_prior.data(), sizeof(int) * n);
+  if (n_equil) std::memcpy(n_equil, hy->plan_equil.data(), sizeof(int64_t) * n);
+  if (batch_equil) *batch_equil = hy->plan_batch_equil;
   return HMD_OK;
 }
 

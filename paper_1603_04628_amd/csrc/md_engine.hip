@@ -368,6 +368,10 @@ int make_tiles(hmd_batch* b) {
     const HostSystem& H = b->host[k];
     const double per_col = double(D.nf) / double(D.nx * D.nz);
     const double wall_col = double(H.nw) / double(2 * D.nx * D.nz);
+    // columns per tile: the most home atoms per unit of cost, cost being
+    // the lanes of whole 256-lane passes plus tile_alpha per staged atom
+    // (a wider tile stages less halo per home atom); 2% hysteresis keeps
+    // the narrower of two near-equal choices
     int best = 1;
     double best_use = -1.0;
     for (int nc = 1; nc <= D.nx; ++nc) {
@@ -375,8 +379,8 @@ int make_tiles(hmd_batch* b) {
       const double staged = 3.0 * std::min(nc + 2, D.nx) * (per_col + 2.0 * wall_col);
       if (staged > 0.9 * kStageCap && nc > 1) break;
       const double passes = std::ceil(atoms / TILE_THREADS);
-      const double use = atoms / (passes * TILE_THREADS);
-      if (use > best_use + 0.02) {
+      const double use = atoms / (passes * TILE_THREADS + b->tile_alpha * staged);
+      if (use > best_use + 0.02 * (b->tile_alpha > 0.0 ? best_use : 1.0)) {
         best_use = use;
         best = nc;
       }
@@ -425,12 +429,20 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
     b->nser = b->n_sample / B;
     b->ser_r = int(b->n_sample - b->nser * B);
   }
-  choose_path(ctx, jobs, n, &b->path, &b->skin, &b->tpb);
+  {
+    const Config c = choose_config(ctx, jobs, n);
+    b->path = c.path;
+    b->skin = c.skin;
+    b->tpb = c.tpb;
+    b->tile_alpha = c.tile_alpha;
+    b->cell_w = c.cell_w;
+    b->chunk = c.chunk;
+  }
   if (b->path == 3) {  // the tiled path with every tile on its gather fallback
     b->path = 2;
     b->force_gather = true;
   }
-  const double wmin = std::max(b->path >= 1 ? b->P.rc + b->skin : b->P.rc, b->P.cell_w);
+  const double wmin = std::max(b->path >= 1 ? b->P.rc + b->skin : b->P.rc, b->cell_w);
   b->host.resize(n);
   for (int k = 0; k < n; ++k) {
     int rc = build_system(b->P, jobs[k].h, jobs[k].g, jobs[k].seed, wmin, b->host[k], ctx->err);
@@ -837,7 +849,8 @@ int batch_series(hmd_batch* b, int sim, double* q, int64_t* n) {
 }
 
 // ---------------------------------------------------------------------------
-// single-system hooks (`sim` selects the system of the batch)
+// state of every system at once, and single-system hooks (`sim` selects the
+// system of the batch)
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -855,6 +868,66 @@ int download_state(hmd_batch* b, std::vector<double> (&hs)[6], std::vector<int>&
 }
 
 }  // namespace
+
+int batch_get_all_states(hmd_batch* b, std::vector<std::vector<double>>& x, std::vector<std::vector<double>>& v) {
+  hmd_ctx* ctx = b->ctx;
+  std::vector<double> hs[6];
+  std::vector<int> tag;
+  HMD_TRY(download_state(b, hs, tag));
+  std::vector<double> vc2(b->S, 0.0);
+  if (b->pending)  // the device holds velocities before the last Berendsen factor
+    HMD_HIP(ctx, hipMemcpy(vc2.data(), b->acc.vc2[b->done & 1], 8 * size_t(b->S), hipMemcpyDeviceToHost));
+  x.assign(b->S, {});
+  v.assign(b->S, {});
+  for (int k = 0; k < b->S; ++k) {
+    const SimDev& D = b->sims[k];
+    const double lam =
+        b->pending ? std::sqrt(1.0 + (b->P.dt / b->P.tau_T) * (b->P.T0 / (vc2[k] * D.inv_nf) - 1.0)) : 1.0;
+    x[k].resize(3 * size_t(D.nf));
+    v[k].resize(3 * size_t(D.nf));
+    for (int i = 0; i < D.nf; ++i) {
+      const int64_t g = D.a0 + i;
+      const int id = tag[g];
+      for (int a = 0; a < 3; ++a) {
+        x[k][3 * id + a] = hs[a][g];
+        v[k][3 * id + a] = hs[3 + a][g] * (a == b->P.thermo_axis ? lam : 1.0);
+      }
+    }
+  }
+  return HMD_OK;
+}
+
+int batch_set_all_states(hmd_batch* b, const std::vector<std::vector<double>>& x,
+                         const std::vector<std::vector<double>>& v) {
+  hmd_ctx* ctx = b->ctx;
+  if (int(x.size()) != b->S || int(v.size()) != b->S) return HMD_EINVAL;
+  std::vector<double> hs[6];
+  std::vector<int> tag;
+  HMD_TRY(download_state(b, hs, tag));
+  for (int k = 0; k < b->S; ++k) {
+    const SimDev& D = b->sims[k];
+    if (x[k].empty() && v[k].empty()) continue;  // this system keeps its state
+    if (int64_t(x[k].size()) != 3 * int64_t(D.nf) || int64_t(v[k].size()) != 3 * int64_t(D.nf)) return HMD_EINVAL;
+    for (int i = 0; i < D.nf; ++i) {
+      const int64_t g = D.a0 + i;
+      const int id = tag[g];
+      for (int a = 0; a < 3; ++a) {
+        hs[a][g] = x[k][3 * id + a];
+        hs[3 + a][g] = v[k][3 * id + a];
+      }
+    }
+  }
+  hipStream_t s = ctx->stream;
+  for (int a = 0; a < 6; ++a)
+    HMD_HIP(ctx, hipMemcpyAsync(b->d_state[b->cur][a], hs[a].data(), 8 * b->ntot, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate + 3, int64_t(0));
+  b->pending = false;
+  StepConst K = step_const(b, b->thermo_on, true);
+  sort_now(b, K);
+  HMD_TRY(forces_now(b, true));
+  HMD_HIP(ctx, hipStreamSynchronize(s));
+  return HMD_OK;
+}
 
 int batch_get_state(hmd_batch* b, int sim, double* x, double* v) {
   hmd_ctx* ctx = b->ctx;

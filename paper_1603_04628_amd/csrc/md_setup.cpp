@@ -78,7 +78,7 @@ int build_system(const hmd_md_params& P, double h, double g, uint64_t seed, doub
   // the flow that is being measured
   if (!(P.rc > 0.0) || !(P.rho > 0.0) || !(P.rho_wall > 0.0) || !(P.dt > 0.0) || !(P.tau_T > 0.0) ||
       P.wall_layers < 0 || P.thermo_axis < 1 || P.thermo_axis > 2 || P.n_blocks < 0 || P.n_blocks == 1 ||
-      P.n_blocks > 1024 || !(P.bin_dy > 0.0) ||
+      P.n_blocks > 1024 || !(P.tile_alpha >= 0.0) || P.graph_chunk < 0 || (P.graph_chunk & 1) || !(P.bin_dy > 0.0) ||
       !(wmin >= P.rc)) {
     err = "invalid MD parameters (thermostat axis must be 1 or 2)";
     return HMD_EINVAL;

@@ -12,13 +12,17 @@ class HybridCfg(_c.Structure):
     _fields_ = [("n_sections", i32), ("h0", d), ("amp", d), ("L", d), ("dt_macro", d), ("rho_ref", d),
                 ("p_out", d), ("dp_mean", d), ("dp_amp", d), ("period", d), ("c2", d), ("tau_rel", d),
                 ("tau_abs", d), ("surrogate", i32), ("audit_every", i32), ("md_sample", i64),
-                ("refit_every", i32), ("seed", u64), ("mirror", i32), ("audit_batch", i32)]
+                ("refit_every", i32), ("seed", u64), ("mirror", i32), ("audit_batch", i32),
+                ("warm_start", i32), ("pseudo_nu", d), ("pseudo_slip", d), ("pseudo_tol", d),
+                ("n_min_warm", i64), ("n_min_cold", i64), ("geometry", i32), ("f_amp", d), ("f_period", d)]
 
 
 class HybridStats(_c.Structure):
     _fields_ = [("steps", i64), ("md_calls", i64), ("audited", i64), ("audit_pass", i64), ("queries", i64),
                 ("md_failed", i64), ("wall_s", d), ("md_wall_s", d), ("md_atom_steps", d),
-                ("surrogate_wall_s", d), ("audit_wall_s", d), ("audit_atom_steps", d)]
+                ("surrogate_wall_s", d), ("audit_wall_s", d), ("audit_atom_steps", d),
+                ("md_equil_atom_steps", d), ("warm_starts", i64), ("md_atom_steps_cold", d),
+                ("audit_pass_cal", i64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -33,6 +37,7 @@ _sig("hybrid_set_rho", i32, vp, P(d))
 _sig("hybrid_step", i32, vp, P(HybridStats))
 _sig("hybrid_get", i32, vp, P(d), P(d), P(d), P(d), P(u8))
 _sig("hybrid_flush_audits", i32, vp, P(HybridStats))
+_sig("hybrid_last_plan", i32, vp, P(i32), P(i64), P(i64))
 _sig("hybrid_free", None, vp)
 
 
@@ -92,6 +97,15 @@ class Hybrid:
         fm = np.zeros(self.n, dtype=np.uint8)
         self.ctx.check(_lib.hybrid_get(self._h, _ptr(rho), _ptr(q), _ptr(qs), _ptr(g), _ptr(fm, u8)))
         return {"rho": rho, "q": q, "q_std": qs, "g": g, "from_md": fm.astype(bool)}
+
+    def last_plan(self):
+        """The last step's fallback plan: prior run per section (-1 lattice,
+        -2 no fallback), start-up steps per section, and the batch's."""
+        prior = np.zeros(self.n, dtype=np.int32)
+        ne = np.zeros(self.n, dtype=np.int64)
+        be = i64()
+        self.ctx.check(_lib.hybrid_last_plan(self._h, _ptr(prior, i32), _ptr(ne, i64), _c.byref(be)))
+        return {"prior": prior, "n_equil": ne, "batch_equil": be.value}
 
     def close(self):
         if self._h:

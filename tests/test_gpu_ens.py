@@ -38,6 +38,15 @@ def test_initial_parameters_and_gradients(ctx, n, hidden):
         assert np.array_equal(th_g, th_o.astype(np.float32).astype(np.float64))
         _, g_o = mlp.loss_and_grad(th_o, Xs, ys, hidden)
         assert np.linalg.norm(g_g - g_o) <= 1e-4 * np.linalg.norm(g_o)
+        # tensor by tensor (W1, b1, W2, b2, W3, b3): an error confined to a
+        # small tensor cannot hide behind the global norm
+        H = hidden
+        o = 0
+        for name, size in (("W1", 2 * H), ("b1", H), ("W2", H * H), ("b2", H), ("W3", H), ("b3", 1)):
+            a, b = g_g[o:o + size], g_o[o:o + size]
+            assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b) + 1e-9 * np.linalg.norm(g_o), (name, k)
+            o += size
+        assert o == len(g_o)
 
 
 def test_trained_ensemble_tracks_oracle(ctx):

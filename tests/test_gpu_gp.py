@@ -146,3 +146,80 @@ def test_many_queries_match_oracle(ctx):
     mo, vo = o.predict(Xs)
     assert np.abs(mg - mo).max() <= 1e-9 * np.abs(mo).max() + 1e-12
     assert np.abs(vg - vo).max() <= 1e-9 * o.s_q ** 2
+
+
+# ---------------------------------------------------------------- NEXT-4 options
+@pytest.mark.parametrize("n", [1, 40, 300])
+def test_heteroscedastic_noise_matches_oracle(ctx, n):
+    X, y, se = data(n, 500 + n)
+    se = se * np.linspace(0.2, 5.0, n)  # very uneven per-point errors
+    g = B.GP(ctx, X, y, se, B.gp_hyper(ranges=RANGES, noise_mode=1))
+    o = OGP(X, y, se, Hyper(ranges=RANGES, noise_mode=1))
+    Xs, _, _ = data(150, 900 + n)
+    mg, vg = g.predict(Xs)
+    mo, vo = o.predict(Xs)
+    assert np.abs(mg - mo).max() <= 1e-9 * np.abs(mo).max() + 1e-12
+    assert np.abs(vg - vo).max() <= 1e-9 * vo.max()
+    assert g.log_marginal() == pytest.approx(o.log_marginal(), rel=1e-10)
+    # appending keeps matching (a refit: the normalisation moves)
+    g.append(Xs[0], 0.01, 0.5)
+    o.append(Xs[0], 0.01, 0.5)
+    assert np.abs(g.predict(Xs)[0] - o.predict(Xs)[0]).max() <= 1e-9 * np.abs(mo).max() + 1e-12
+
+
+def test_heteroscedastic_rank_one_append_equals_refit(ctx):
+    X, y, se = data(50, 77)
+    hp = dict(ranges=RANGES, scale_mode=1, out_scale=0, noise_mode=1)
+    g = B.GP(ctx, X[:30], y[:30], se[:30], B.gp_hyper(**hp))
+    for k in range(30, 50):
+        g.append(X[k], y[k], se[k])
+    full = B.GP(ctx, X, y, se, B.gp_hyper(**hp))
+    Xs, _, _ = data(60, 78)
+    assert np.allclose(g.predict(Xs)[0], full.predict(Xs)[0], rtol=1e-9, atol=1e-12)
+    assert np.allclose(g.predict(Xs)[1], full.predict(Xs)[1], rtol=1e-8, atol=1e-14)
+
+
+def test_periodic_kernel_matches_oracle(ctx):
+    # App. B: a noisy sinusoidal time series smoothed with the periodic kernel
+    T = 10.8
+    rng = np.random.default_rng(3)
+    t = np.sort(rng.uniform(0.0, 25.0, 120))[:, None]
+    y = np.sin(2 * np.pi * t[:, 0] / T) + 0.2 * rng.standard_normal(120)
+    hp = dict(sigma_n=0.2, out_scale=0, kernel=1, period=T, ranges=(1.0,))
+    g = B.GP(ctx, t, y, None, B.gp_hyper(**hp))
+    o = OGP(t, y, None, Hyper(**hp))
+    q = np.linspace(0.0, 40.0, 81)[:, None]
+    mg, vg = g.predict(q)
+    mo, vo = o.predict(q)
+    assert np.abs(mg - mo).max() <= 1e-9
+    assert np.abs(vg - vo).max() <= 1e-9
+    assert g.log_marginal() == pytest.approx(o.log_marginal(), rel=1e-10)
+    with pytest.raises(hmd.HmdError):  # the periodic kernel takes one input
+        B.GP(ctx, np.column_stack([t, t]), y, None, B.gp_hyper(**hp))
+
+
+@pytest.mark.parametrize("which,kernel", [(("sigma_f", "ell"), 0), (("ell", "sigma_n"), 1)])
+def test_optimised_hyperparameters_match_oracle(ctx, which, kernel):
+    rng = np.random.default_rng(11)
+    if kernel == 0:
+        X, y, se = data(80, 12)
+        hp = dict(ranges=RANGES)
+        sen = se
+    else:
+        T = 10.8
+        X = np.sort(rng.uniform(0.0, 25.0, 60))[:, None]
+        y = np.sin(2 * np.pi * X[:, 0] / T) + 0.15 * rng.standard_normal(60)
+        hp = dict(sigma_n=0.3, out_scale=0, kernel=1, period=T, ranges=(1.0,))
+        sen = None
+    g = B.GP(ctx, X, y, sen, B.gp_hyper(**hp))
+    o = OGP(X, y, sen, Hyper(**hp))
+    lg = g.optimize(which)
+    lo = o.optimize(which)
+    assert lg == pytest.approx(lo, rel=1e-8, abs=1e-8)
+    hg = g.hyper()
+    for k in which:
+        ref = o.h.sigma_n if k == "sigma_n" else getattr(o.h, k)
+        assert hg[k] == pytest.approx(ref, rel=2e-3), k
+    assert g.log_marginal() == pytest.approx(lg, rel=1e-12)
+    Xs = X[:10] + 0.01
+    assert np.abs(g.predict(Xs)[0] - o.predict(Xs)[0]).max() <= 1e-4 * np.abs(y).max()
