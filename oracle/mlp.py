@@ -13,6 +13,13 @@ counter (j, k, 2, 0), the parameter p taking word p mod 4 of counter
 j = p div 4, mapped to (0,1) as (r + 0.5) / 2^32; ensemble standard deviation
 with ddof = 1.
 
+Bootstrap option (the usual remedy for a deep ensemble whose members agree
+too readily): member k trains on N points drawn with replacement from the N
+training points; draw j is point (r N) >> 32 for the Philox word r of
+counter (j div 4, k, 3, 0), word j mod 4, same key.  Its loss is the mean
+squared error over that resample, i.e. (1/N) sum_i c_ki r_i^2 with c_ki the
+number of times point i was drawn.  Standardisation uses the whole set.
+
 Parameter layout of one member (flat, this order): W1 [H x 2] row-major
 (output-major), b1 [H], W2 [H x H], b2 [H], W3 [1 x H], b3 [1].
 """
@@ -55,6 +62,18 @@ def glorot_init(H: int, member: int, seed: int) -> np.ndarray:
     return theta
 
 
+def bootstrap_counts(N: int, member: int, seed: int) -> np.ndarray:
+    """Times each of the N points is drawn in member `member`'s resample."""
+    key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
+    c = np.zeros(N, dtype=np.int64)
+    for j in range((N + 3) // 4):
+        r = _md.philox4x32_10([j, member, 3, 0], key)
+        for w in range(4):
+            if 4 * j + w < N:
+                c[(int(r[w]) * N) >> 32] += 1
+    return c
+
+
 def forward(theta, Xs, H):
     W1, b1, W2, b2, W3, b3 = unpack(theta, H)
     h1 = np.tanh(Xs @ W1.T + b1)
@@ -63,14 +82,17 @@ def forward(theta, Xs, H):
     return out[:, 0], (h1, h2)
 
 
-def loss_and_grad(theta, Xs, ys, H):
-    """MSE loss and its gradient by hand-written back-propagation."""
+def loss_and_grad(theta, Xs, ys, H, w=None):
+    """MSE loss and its gradient by hand-written back-propagation; w (per
+    point, e.g. bootstrap counts) weights each squared residual, the mean
+    still taken over the N points."""
     W1, b1, W2, b2, W3, b3 = unpack(theta, H)
     out, (h1, h2) = forward(theta, Xs, H)
     N = len(ys)
     r = out - ys
-    loss = np.mean(r ** 2)
-    d_out = (2.0 / N) * r[:, None]                   # N x 1
+    wr = r if w is None else np.asarray(w, dtype=np.float64) * r
+    loss = np.mean(wr * r)
+    d_out = (2.0 / N) * wr[:, None]                  # N x 1
     gW3 = d_out.T @ h2
     gb3 = d_out.sum(0)
     dz2 = (d_out @ W3) * (1.0 - h2 ** 2)             # N x H
@@ -93,7 +115,7 @@ def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 class Ensemble:
-    def __init__(self, X, y, members=5, hidden=64, iters=5000, lr=1e-3, seed=0):
+    def __init__(self, X, y, members=5, hidden=64, iters=5000, lr=1e-3, seed=0, bootstrap=False):
         X = np.asarray(X, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
         self.H = hidden
@@ -107,11 +129,12 @@ class Ensemble:
         self.thetas, self.losses = [], []
         for k in range(members):
             th = glorot_init(hidden, k, seed)
+            w = bootstrap_counts(len(ys), k, seed).astype(np.float64) if bootstrap else None
             m = np.zeros_like(th)
             v = np.zeros_like(th)
             loss = None
             for t in range(1, iters + 1):
-                loss, g = loss_and_grad(th, Xs, ys, hidden)
+                loss, g = loss_and_grad(th, Xs, ys, hidden, w)
                 th, m, v = adam_step(th, g, m, v, t, lr)
             self.thetas.append(th)
             self.losses.append(loss)

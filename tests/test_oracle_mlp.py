@@ -3,6 +3,7 @@ update formula, the Glorot-uniform start, and that training fits.  CPU only."""
 import numpy as np
 import pytest
 
+from oracle import md as omd
 from oracle import mlp
 
 
@@ -80,3 +81,38 @@ def test_forward_of_a_hand_set_network():
     ens.H, ens.mu, ens.sd, ens.s_q, ens.thetas = 2, np.array([1.0, 2.0]), np.array([4.0, 0.5]), 3.0, [theta]
     m = ens.member_predict(np.array([[1.0 + 4.0 * 0.5, 2.0 + 0.5 * -1.0]]))
     assert m[0, 0] == pytest.approx(3.0 * 2.205074484369277, abs=1e-13)
+
+
+def test_bootstrap_weights_equal_an_explicit_resample():
+    # the weighted loss is the plain MSE over the resampled set itself: the
+    # drawn indices, read straight from the Philox words, give the same loss
+    # and gradient when the points are repeated explicitly
+    H, N, seed, member = 6, 37, 99, 3
+    rng = np.random.default_rng(2)
+    theta = rng.normal(0, 0.5, mlp.n_params(H))
+    Xs = rng.normal(size=(N, 2))
+    ys = rng.normal(size=N)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    idx = []
+    for j in range((N + 3) // 4):
+        r = omd.philox4x32_10([j, member, 3, 0], key)
+        idx += [(int(w) * N) >> 32 for w in r]
+    idx = np.array(idx[:N])
+    c = mlp.bootstrap_counts(N, member, seed)
+    assert c.sum() == N and np.array_equal(c, np.bincount(idx, minlength=N))
+    lw, gw = mlp.loss_and_grad(theta, Xs, ys, H, c)
+    lr, gr = mlp.loss_and_grad(theta, Xs[idx], ys[idx], H)
+    assert lw == pytest.approx(lr, rel=1e-12)
+    np.testing.assert_allclose(gw, gr, rtol=1e-10, atol=1e-14)
+
+
+def test_bootstrap_draws_are_uniform_and_members_differ():
+    # multinomial(N, 1/N): about 1 - 1/e of the points appear; the counts
+    # follow Poisson(1) in the large-N limit; members draw independently
+    N = 20000
+    c0, c1 = mlp.bootstrap_counts(N, 0, 5), mlp.bootstrap_counts(N, 1, 5)
+    assert (c0 > 0).mean() == pytest.approx(1.0 - np.exp(-1.0), abs=0.01)
+    for k in range(4):
+        p = np.exp(-1.0) / np.prod(np.arange(1, k + 1)) if k else np.exp(-1.0)
+        assert (c0 == k).mean() == pytest.approx(p, abs=0.01)
+    assert np.corrcoef(c0, c1)[0, 1] == pytest.approx(0.0, abs=0.03)
