@@ -3,8 +3,9 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 Per macro step (Alg. 1, time-evolution loop):
-  1. pressure from the density (here a linear equation of state
-     p = p_out + c2 (rho - rho_ref), a reading standing in for the pressure GP);
+  1. pressure from the density: a linear equation of state
+     p = p_out + c2 (rho - rho_ref) (eos = 0, a reading standing in for the
+     pressure GP), or the pressure surrogate p(h, rho) (eos = 1, below);
   2. pressure gradient by central differences (Alg. 1, p' = dp/ds), ghost
      values p_in(t) before the first and p_out after the last section;
   3. body force per section, Eq. momentumEq: g = F_ext/m - (1/rho) dp/ds
@@ -32,6 +33,19 @@ Geometry 1 is the paper's benchmark channel (Sec. 2.1): periodic in s
 and a = amp h0), driven by a uniform external force
 F_ext(t) = F_A sin(2 pi t / T) (Eq. extForcing1, t in macro steps); the
 pressure gradient and the face fluxes wrap around the ring.
+
+Pressure from a surrogate (eos = 1, Alg. 1 with the paper's full input
+set): step 1 takes the mean pressure p(h, rho) of each section from the
+pressure surrogate (Alg. 1 GPreg on C_p; inputs h and rho); the flux query
+is x* = (h, rho, F) (three inputs, F = g per unit mass); the micro-solver
+returns flux and pressure with their standard errors, the flux joins the flux
+database and the pressure joins the pressure database when its (h, rho) is
+not there yet.  The boundary pressures p_in(t) and p_out are then absolute.
+The pressure database comes from pre-simulations (``presimulate``): per
+distinct section height, runs at rest over a sweep of densities (the paper
+removes atoms progressively from one run; here each density is its own run,
+so that the sweep is one batch).  Warm starts are not combined with it (a
+stored state fits only a run of the same atom count).
 
 With warm starts (Alg. 1 "find nearest prior input", "pseudoMD"), each
 flagged section's run starts from the recorded fallback run of the same
@@ -75,14 +89,20 @@ class HybridCfg:
     geometry: int = 0         # 0 inlet/outlet channel, 1 the paper's periodic channel
     f_amp: float = 0.0        # F_A / m of Eq. extForcing1 (geometry 1)
     f_period: float = 250.0   # T of Eq. extForcing1, in macro steps
+    eos: int = 0              # 0 linear p = p_out + c2 (rho - rho_ref); 1 pressure surrogate p(h, rho)
 
 
 class Hybrid:
-    """micro(h, g) -> (q, se) arrays; surrogate has predict(X) -> (mean, var)
-    and append(x, y, se).  `var_is_std` selects whether predict's second
-    output is a standard deviation (ensemble) or a variance (GP)."""
+    """micro(h, g) -> (q, se) arrays (eos = 1: micro(h, rho, g) -> (q, se, p,
+    p_se)); surrogate has predict(X) -> (mean, var) and append(x, y, se),
+    with X rows (h, g) (eos = 1: (h, rho, g)); psur (eos = 1) is the
+    pressure surrogate over (h, rho), a GP with its inputs in .X.
+    `var_is_std` selects whether the flux surrogate's second output is a
+    standard deviation (ensemble) or a variance (GP)."""
 
-    def __init__(self, cfg: HybridCfg, surrogate, micro, var_is_std=False, rho0=None):
+    def __init__(self, cfg: HybridCfg, surrogate, micro, var_is_std=False, rho0=None, psur=None):
+        if cfg.eos == 1 and (psur is None or cfg.warm_start):
+            raise ValueError("eos = 1 needs a pressure surrogate and no warm starts")
         self.c = cfg
         n = cfg.n_sections
         self.ds = cfg.L / n
@@ -109,6 +129,11 @@ class Hybrid:
         self.plan_prior = np.full(n, -2)
         self.plan_equil = np.zeros(n, dtype=np.int64)
         self.plan_batch_equil = 0
+        self.psur = psur
+        self.p_db = set() if psur is None else {(float(a), float(b)) for a, b in np.asarray(psur.X)}
+        self.p_appends = 0
+        self.p = np.zeros(n)
+        self.p_std = np.zeros(n)
 
     def p_in(self, t_steps):
         c = self.c
@@ -119,10 +144,20 @@ class Hybrid:
         c = self.c
         return c.f_amp * np.sin(2.0 * np.pi * t_steps / c.f_period) if c.geometry == 1 else 0.0
 
+    def pressure(self):
+        """Section pressures: the linear law, or (eos = 1) the pressure
+        surrogate's mean at (h, rho) with its standard deviation."""
+        c = self.c
+        if c.eos == 1:
+            mean, var = self.psur.predict(np.column_stack([self.h, self.rho]))
+            return mean, np.sqrt(np.maximum(var, 0.0))
+        return c.p_out + c.c2 * (self.rho - c.rho_ref), np.zeros(len(self.rho))
+
     def forces(self):
         """Eq. momentumEq per unit mass: F_ext/m - (1/rho) dp/ds."""
         c = self.c
-        p = c.p_out + c.c2 * (self.rho - c.rho_ref)
+        p, self.p_std = self.pressure()
+        self.p = p
         if c.geometry == 1:
             pl, pr = np.roll(p, 1), np.roll(p, -1)
         else:
@@ -138,7 +173,7 @@ class Hybrid:
         # force, so the query is made at |g| and the answer takes g's sign
         sgn = np.where(g < 0.0, -1.0, 1.0) if c.mirror else np.ones_like(g)
         gq = sgn * g
-        X = np.column_stack([self.h, gq])
+        X = np.column_stack([self.h, self.rho, gq]) if c.eos == 1 else np.column_stack([self.h, gq])
         mean, second = self.sur.predict(X)
         std = second if self.var_is_std else np.sqrt(np.maximum(second, 0.0))
         flag = std > np.maximum(c.tau_rel * np.abs(mean), c.tau_abs)
@@ -166,7 +201,10 @@ class Hybrid:
                 self.plan_batch_equil = max(self.plan_batch_equil, ne)
         if run.any():
             idx = np.nonzero(run)[0]
-            qm, se = self.micro(self.h[idx], gq[idx])
+            if c.eos == 1:
+                qm, se, pm, pse = self.micro(self.h[idx], self.rho[idx], gq[idx])
+            else:
+                qm, se = self.micro(self.h[idx], gq[idx])
             self.md_calls += int(flag.sum())  # audits are counted apart
             for k, i in enumerate(idx):
                 if flag[i]:
@@ -180,6 +218,12 @@ class Hybrid:
                     self.sur.append(X[i], qm[k], se[k])
                     if c.warm_start:
                         self.warm.append((self.h[i], gq[i]))
+                    # Alg. 1: the run's pressure joins the pressure database
+                    # when its (h, rho) is not there yet
+                    if c.eos == 1 and (float(self.h[i]), float(self.rho[i])) not in self.p_db:
+                        self.psur.append(np.array([self.h[i], self.rho[i]]), pm[k], pse[k])
+                        self.p_db.add((float(self.h[i]), float(self.rho[i])))
+                        self.p_appends += 1
         self.q, self.q_std, self.from_md = q, std, flag
         if c.geometry == 1:  # periodic faces: the last one closes the ring
             face = 0.5 * (q + np.roll(q, -1))
@@ -193,6 +237,18 @@ class Hybrid:
 
     def mass(self):
         return float((self.rho * self.h).sum() * self.ds)
+
+
+def presimulate(micro_p, heights, rhos):
+    """Pressure database of the pre-simulations (Sec. 2.4): every distinct
+    height at every density of the sweep, the fluid at rest;
+    micro_p(h, rho) -> (p, p_se) arrays.  Returns (X_p rows (h, rho), p,
+    p_se)."""
+    hs = np.unique(np.asarray(heights, dtype=np.float64))
+    H, R = np.meshgrid(hs, np.asarray(rhos, dtype=np.float64), indexing="ij")
+    Xp = np.column_stack([H.ravel(), R.ravel()])
+    p, pse = micro_p(Xp[:, 0], Xp[:, 1])
+    return Xp, np.asarray(p, dtype=np.float64), np.asarray(pse, dtype=np.float64)
 
 
 def poiseuille_flux(h, g, rho=0.8, eta=2.0, slip=0.0):

@@ -243,6 +243,19 @@ class System:
             L.ora_wall_force_series(self._h, _ptr(out))
         return out
 
+    def pressure_series(self):
+        """Per sampled step: the normal pressure on the walls,
+        (F_lo,y - F_hi,y) / (2 Lx Lz), the mean of the two walls' normal
+        forces per unit area (the cross-section average of P_yy, by the yy
+        momentum balance; Alg. 1's pressure output of an MD run)."""
+        L = lib()
+        L.ora_pressure_series.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+        n = lib().ora_nsamples(self._h)
+        out = np.zeros(n)
+        if n:
+            L.ora_pressure_series(self._h, _ptr(out))
+        return out
+
     def displacements(self):
         L = lib()
         L.ora_displacements.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
@@ -280,8 +293,16 @@ class System:
                 # spanwise temperature runs away
                 if status == 0 and (abs(m2 - m1) > 8.0 * se or out[5] > 1.5 * self.params.T0):
                     status = -5
-        return {"flux": out[0], "flux_se": out[1], "jflux": out[2], "T": out[3:6].copy(),
-                "pe": out[6], "lambda": out[7], "status": status, "n_fluid": self.n_fluid}
+        res = {"flux": out[0], "flux_se": out[1], "jflux": out[2], "T": out[3:6].copy(),
+               "pe": out[6], "lambda": out[7], "status": status, "n_fluid": self.n_fluid}
+        # the run's pressure and its standard error (Geyer, over the per-step
+        # wall pressure)
+        pser = self.pressure_series()
+        if len(pser) >= 2:
+            res["p"], res["p_se"] = _stats.geyer(pser)
+        else:
+            res["p"], res["p_se"] = (float(pser[0]) if len(pser) else 0.0), 0.0
+        return res
 
 
 def md_flux(h, g, seed, n_sample, params: Params = None):

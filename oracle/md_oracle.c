@@ -134,6 +134,8 @@ typedef struct {
                                and second half-kicks of sampled steps */
     double fwx_sum, ftx_sum, fwy_lo_sum, fwy_hi_sum, vir_sum, viryy_sum;
     double *fwx_series;     /* per sampled step: wall force on the fluid along x */
+    double *pw_series;      /* per sampled step: normal pressure on the walls,
+                               (F_lo,y - F_hi,y) / (2 Lx Lz) */
 } ora_sys;
 
 /* Stated defaults (readings of the paper, see the design notes). */
@@ -594,6 +596,7 @@ ora_sys *ora_create(const ora_params *P, double h, double g, uint64_t seed)
     S->series_cap = 1024;
     S->series = (double *)malloc(sizeof(double) * S->series_cap);
     S->fwx_series = (double *)malloc(sizeof(double) * S->series_cap);
+    S->pw_series = (double *)malloc(sizeof(double) * S->series_cap);
     S->disp = (double *)calloc((size_t)(S->nf > 0 ? S->nf : 1), sizeof(double));
     S->pe = ora_forces_cells(S, S->f);
     S->lambda_last = 1.0;
@@ -607,7 +610,7 @@ void ora_free(ora_sys *S)
     free(S->cell_of); free(S->fstart); free(S->fcount); free(S->forder);
     free(S->wstart); free(S->wcount); free(S->worder);
     free(S->series); free(S->bin_mvx); free(S->bin_cnt);
-    free(S->fwx_series); free(S->disp);
+    free(S->fwx_series); free(S->pw_series); free(S->disp);
     free(S);
 }
 
@@ -688,8 +691,10 @@ static void sample(ora_sys *S)
         S->series_cap *= 2;
         S->series = (double *)realloc(S->series, sizeof(double) * S->series_cap);
         S->fwx_series = (double *)realloc(S->fwx_series, sizeof(double) * S->series_cap);
+        S->pw_series = (double *)realloc(S->pw_series, sizeof(double) * S->series_cap);
     }
     S->fwx_series[S->nsamp] = S->fw_lo[0] + S->fw_hi[0];
+    S->pw_series[S->nsamp] = 0.5 * (S->fw_lo[1] - S->fw_hi[1]) / (S->Lx * S->Lz);
     S->series[S->nsamp++] = sx / (S->Lx * S->Lz);
     for (int a = 0; a < 3; ++a) S->Tsum[a] += t[a] / (double)S->nf;
     S->fwx_sum += S->fw_lo[0] + S->fw_hi[0];
@@ -795,6 +800,14 @@ void ora_flow_diag(const ora_sys *S, double out[13])
 void ora_wall_force_series(const ora_sys *S, double *out)
 {
     memcpy(out, S->fwx_series, sizeof(double) * S->nsamp);
+}
+
+/* Per sampled step: the normal pressure the fluid exerts on the walls, the
+   mean of the two walls' normal forces per unit area (by the yy momentum
+   balance, the cross-section average of P_yy). */
+void ora_pressure_series(const ora_sys *S, double *out)
+{
+    memcpy(out, S->pw_series, sizeof(double) * S->nsamp);
 }
 
 /* Per-atom x displacements over the sampled steps. */

@@ -106,3 +106,19 @@ def test_walls_balance_the_body_force(driven_channel):
     d = s.flow_diag()
     assert d["fwall_y_lo"] > 0.0 and d["fwall_y_hi"] < 0.0
     assert d["fwall_y_lo"] == pytest.approx(-d["fwall_y_hi"], rel=0.05)
+
+
+def test_pressure_series_is_the_wall_normal_force_per_area():
+    # per sampled step the mean of the two walls' normal forces on the fluid
+    # per unit area; its mean is the summed wall forces over the samples, and
+    # the two walls push with equal and opposite mean force at rest
+    p = md.Params(n_equil=500, Lx_nom=12.0, Lz_nom=12.0)
+    s = md.System(7.0, 0.0, 4, p)
+    s.run(2500)
+    d = s.flow_diag()
+    ps = s.pressure_series()
+    assert len(ps) == 2000 == d["samples"]
+    assert ps.mean() == pytest.approx(0.5 * (d["fwall_y_lo"] - d["fwall_y_hi"]) / 2000 / (s.Lx * s.Lz), rel=1e-12)
+    r = s.result()
+    assert r["p"] == pytest.approx(ps.mean(), rel=1e-12) and 0.0 < r["p_se"] < 0.1 * r["p"]
+    assert d["fwall_y_lo"] == pytest.approx(-d["fwall_y_hi"], rel=0.05)

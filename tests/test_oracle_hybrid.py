@@ -209,3 +209,94 @@ def test_periodic_channel_reaches_reynolds_lubrication_flow():
     Q = 0.03 * L * C / integral
     assert np.abs(hy.q - Q).max() <= 0.002 * Q
     assert hy.q.std() <= 0.001 * Q
+
+
+# ---------------------------------------------------------------- pressure surrogate (eos = 1)
+class LinearP:
+    """A pressure surrogate that is the linear law itself (zero spread)."""
+
+    def __init__(self, X, c2=200.0, rho_ref=0.8, p_out=0.0):
+        self.X = np.asarray(X, dtype=np.float64)
+        self.c2, self.rho_ref, self.p_out = c2, rho_ref, p_out
+        self.appended = []
+
+    def predict(self, X):
+        return self.p_out + self.c2 * (X[:, 1] - self.rho_ref), np.zeros(len(X))
+
+    def append(self, x, y, se):
+        self.appended.append((float(x[0]), float(x[1]), float(y), float(se)))
+        self.X = np.vstack([self.X, np.asarray(x).reshape(1, -1)])
+
+
+class ThreeInput:
+    """A flux surrogate over (h, rho, g) that answers the 2-input law from
+    (h, g) and never falls back."""
+
+    def predict(self, X):
+        return poiseuille_flux(X[:, 0], X[:, 2]), np.zeros(len(X))
+
+    def append(self, x, y, se):
+        raise AssertionError("never falls back")
+
+
+def test_pressure_surrogate_of_the_linear_law_reproduces_the_linear_march():
+    # with p(h, rho) the linear law and a flux law that ignores rho, the
+    # eos = 1 march (Alg. 1 with the pressure GP and 3-input flux queries)
+    # equals the eos = 0 march to rounding: forces, query and sign plumbing
+    kw = dict(n_sections=30, L=300.0, dt_macro=0.004, dp_mean=2.0, dp_amp=0.5, period=20.0, tau_rel=1e9)
+    a = Hybrid(HybridCfg(**kw), Exact(), micro, var_is_std=True)
+    b = Hybrid(HybridCfg(eos=1, **kw), ThreeInput(), micro, psur=LinearP(np.zeros((0, 2))))
+    for _ in range(80):
+        a.step()
+        b.step()
+    np.testing.assert_allclose(b.rho, a.rho, rtol=1e-13)
+    np.testing.assert_allclose(b.q, a.q, rtol=1e-11, atol=1e-15)
+    b.forces()  # the pressures of the current densities
+    np.testing.assert_allclose(b.p, 200.0 * (b.rho - 0.8), rtol=1e-13, atol=1e-13)
+
+
+def test_fallback_pressures_join_the_pressure_database_once_per_input():
+    # Alg. 1: a fallback's pressure is appended when its (h, rho) is not in
+    # the pressure database; the pre-simulation inputs count as present
+    n = 6
+    cfg = HybridCfg(n_sections=n, L=60.0, dt_macro=1e-4, dp_mean=1.0, tau_rel=0.0, eos=1)
+    calls = []
+
+    def micro3(h, rho, g):
+        calls.append((h.copy(), rho.copy(), g.copy()))
+        q = poiseuille_flux(h, g, rho=rho)
+        return q, np.full(len(h), 1e-3), 1.5 + 0.0 * h, np.full(len(h), 0.01)
+
+    rho0 = np.linspace(0.81, 0.79, n)  # every (h, rho) distinct (mirrored heights can be equal)
+    hy0 = Hybrid(cfg, GP(np.zeros((0, 3)), np.zeros(0), None, Hyper(ranges=(16.0, 0.6, 0.049))), micro3,
+                 psur=LinearP(np.zeros((0, 2))), rho0=rho0)
+    pre = np.column_stack([hy0.h[:2], hy0.rho[:2]])  # two sections already in the pressure database
+    psur = LinearP(pre)
+    gp = GP(np.zeros((0, 3)), np.zeros(0), None, Hyper(ranges=(16.0, 0.6, 0.049)))
+    hy = Hybrid(cfg, gp, micro3, psur=psur, rho0=rho0)
+    hy.step()
+    assert len(calls) == 1 and len(calls[0][0]) == n  # threshold 0: every section ran
+    np.testing.assert_array_equal(calls[0][1], hy0.rho)  # queried at the sections' own densities
+    assert hy.p_appends == n - 2 and len(psur.appended) == n - 2
+    assert [(a, b) for a, b, _, _ in psur.appended] == [(float(h), float(r)) for h, r in zip(hy0.h[2:], hy0.rho[2:])]
+    assert len(gp.y) == n  # every fallback's flux joined the flux database (3 inputs)
+    assert gp.X.shape == (n, 3)
+    # a step whose (h, rho) inputs are all present appends no pressure
+    before = len(psur.appended)
+    hy.rho = hy0.rho.copy()  # back to the first step's densities
+    hy.step()
+    assert len(psur.appended) == before
+
+
+def test_presimulation_sweeps_every_distinct_height():
+    from oracle.hybrid import presimulate
+    seen = []
+
+    def micro_p(h, rho):
+        seen.append(len(h))
+        return 1.0 + 10.0 * (rho - 0.8) + 0.01 * h, np.full(len(h), 0.003)
+
+    Xp, p, pse = presimulate(micro_p, [10.0, 8.0, 10.0, 6.0], np.linspace(1.0, 0.5, 6))
+    assert seen == [18] and Xp.shape == (18, 2)
+    assert sorted(set(Xp[:, 0])) == [6.0, 8.0, 10.0]
+    np.testing.assert_allclose(p, 1.0 + 10.0 * (Xp[:, 1] - 0.8) + 0.01 * Xp[:, 0])
