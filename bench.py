@@ -9,8 +9,9 @@ the timed region; the timed region is the step loop (HIP-graph replays).
 
 Prints one JSON line: MD atom-steps/s of the batched path, the same jobs on
 the plain path (one system at a time, direct launches), the force kernel's
-roofline position from HIP-event timing captured inside the timed graph, and
-the CPU oracle on a bounded sample.
+roofline position from clock stamps around the kernels of the timed graph
+replays, the surrogates and the hybrid solve, and the CPU oracle on a bounded
+sample.
 """
 import argparse
 import json
@@ -67,7 +68,11 @@ def log(*a):
 
 def advance(batch, n, chunk):
     """n steps as graph replays of `chunk` steps, then one replay of the even
-    remainder and, for an odd n, one direct step."""
+    remainder and, for an odd n, one direct step (chunk 0: direct launches,
+    for counter runs)."""
+    if chunk == 0:
+        batch.run(n, graph_chunk=0)
+        return
     full = (n // chunk) * chunk
     if full:
         batch.run(full, graph_chunk=chunk)
@@ -93,6 +98,8 @@ def timed_plan(steps, warmup, chunk):
     eq = min(eq, steps)
     sa = steps - eq
     skip = max(0, N_EQUIL - warmup - eq) if sa > 0 else 0
+    if chunk == 0:  # direct launches: no graphs to capture
+        return {"warmup": warmup, "eq": eq, "sa": sa, "skip": skip, "chunk": 0, "chunks": []}
     c = max(2, min(chunk, eq if eq >= 2 else chunk, sa if sa >= 2 else chunk))
     c -= c % 2
     sizes = set()
@@ -157,7 +164,7 @@ def summarize_pmc(path: str, kernel: str):
 # Macro problem of the hybrid solve: converging-diverging channel
 # h(s) = h0 (1 + 0.5 cos 2 pi s / L), 200 cross-sections of 10 sigma, linear
 # equation of state with an artificial stiffness c^2 (weakly compressible),
-# inlet pressure oscillating by 30% with a period of 250 macro steps, mean
+# inlet pressure oscillating by 10% with a period of 250 macro steps, mean
 # pressure drop set so the steady lubrication solution has g = 0.038 at the
 # throat (h = 5): with the oscillation every g stays inside the training
 # range [0.001, 0.05] of the surrogates.
@@ -234,7 +241,9 @@ def hybrid_bench(args, hmd, first_results):
     ecfg = B.ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3)
     Xq = Xt[np.arange(200) % len(Xt)]
     fits = {}
-    variants = (("gp", 0), ("gp_per_point_noise", 0), ("ensemble", 1))
+    # the bootstrap ensemble: each member on its own resample of the data
+    ecfg_boot = B.ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3, bootstrap=1)
+    variants = (("gp", 0), ("gp_per_point_noise", 0), ("ensemble", 1), ("ensemble_bootstrap", 2))
     for name, kind in variants:
         t0 = time.perf_counter()
         if kind == 0:
@@ -243,7 +252,7 @@ def hybrid_bench(args, hmd, first_results):
                 hp_v = B.gp_hyper(ranges=(16.0, 0.049), sigma_f=hyper.sigma_f, ell=hyper.ell, noise_mode=1)
             sur = B.GP(ctx, X, y, se, hp_v)
         else:
-            sur = B.Ensemble(ctx, X, y, ecfg)
+            sur = B.Ensemble(ctx, X, y, ecfg if kind == 1 else ecfg_boot)
         torch.cuda.synchronize()
         t_fit = time.perf_counter() - t0
         sur.predict(Xq)
@@ -289,7 +298,10 @@ def hybrid_bench(args, hmd, first_results):
     tau_abs = float(np.median(se))
 
     def run(surrogate, tau, steps, audit_every, budget_s=None, floor=tau_abs, warm=1):
-        sur = B.GP(hctx, X, y, se, hyper) if surrogate == 0 else B.Ensemble(hctx, X, y, ecfg)
+        # surrogate 0: GP; 1: ensemble; 2: bootstrap ensemble (the march's kind 1)
+        sur = B.GP(hctx, X, y, se, hyper) if surrogate == 0 else B.Ensemble(hctx, X, y,
+                                                                            ecfg if surrogate == 1 else ecfg_boot)
+        surrogate = min(surrogate, 1)
         cfg = HB.hybrid_cfg(surrogate=surrogate, tau_rel=tau, tau_abs=floor, audit_every=audit_every,
                             audit_batch=64, warm_start=warm, **base)
         hy = HB.Hybrid(hctx, cfg, gp=sur if surrogate == 0 else None, ens=sur if surrogate == 1 else None)
@@ -324,7 +336,8 @@ def hybrid_bench(args, hmd, first_results):
     log(f"all-MD: {nv} steps in {allmd['wall_s']:.1f} s, {md_rate:.3e} atom-steps/s -> {all_md_s:.0f} s for "
         f"{args.hybrid_steps} steps; training MD {train_md_s:.1f} s")
     runs = []
-    plan = [(name, sid, tau, rule) for name, sid in (("gp", 0), ("ensemble", 1)) for tau in args.taus
+    plan = [(name, sid, tau, rule) for name, sid in (("gp", 0), ("ensemble", 1), ("ensemble_bootstrap", 2))
+            for tau in args.taus
             for rule in args.rules if name == "gp" or tau in args.ens_taus]
     for name, sid, tau, rule in plan:
         floor = tau_abs if rule == "floor" else 0.0
@@ -363,7 +376,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=N_EQUIL + N_SAMPLE - 200)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--chunk", type=int, default=100)
+    ap.add_argument("--chunk", type=int, default=100,
+                    help="steps per graph replay; 0: direct launches (for hardware-counter runs)")
     ap.add_argument("--plain-sims", type=int, default=8)
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -390,6 +404,8 @@ def main():
     ap.add_argument("--all-md-steps", type=int, default=1, help="macro steps run all-MD to price the all-MD march")
     ap.add_argument("--hybrid-budget", type=float, default=60.0,
                     help="wall-clock cap (s) of one hybrid run; the speed-up is then taken over the steps done")
+    ap.add_argument("--no-finish", action="store_true",
+                    help="stop after the timed steps (no flux results): for short profiled runs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (by default it times its candidates on the batch, outside the timed "
                          "region, and the batch uses the fastest)")
@@ -455,8 +471,18 @@ def main():
             advance(batch, n_timed, plan["chunk"])
             torch.cuda.synchronize()
             wall += time.perf_counter() - t0
-            builds += batch.list_builds() - b0
-            windows.append((phase, n_timed, {k: batch.kernel_ms(k) for k in names + ("graph_step",)}))
+            nb = batch.list_builds() - b0
+            builds += nb
+            km = {k: batch.kernel_ms(k) for k in names + ("graph_step", "list_rebuild", "list_idle")}
+            # the list build per step: its time on stamped rebuild and idle
+            # steps, weighted by this stretch's exact rebuild rate (the
+            # stamped steps hold too few rebuilds for a steady mean)
+            rate = nb / n_timed
+            if km["list_rebuild"][1] > 0 and km["list_idle"][1] > 0:
+                km["list_sampled"] = km["list"]
+                km["list"] = (rate * km["list_rebuild"][0] + (1.0 - rate) * km["list_idle"][0], km["list"][1])
+            km["rebuilds_per_step"] = (rate, nb)
+            windows.append((phase, n_timed, km))
             batch.set_timing(False)
             done += n_timed
         if phase == "equilibrating" and plan["sa"] > 0 and done < N_EQUIL:  # untimed: the rest of it
@@ -465,20 +491,22 @@ def main():
     ms_step = 1e3 * wall / args.steps
     value = batch.atoms * args.steps / wall
     # per-kernel averages (ms per launch, one launch of each per step) from the
-    # event nodes in the timed graph replays, weighted like the protocol: one
-    # third of the steps equilibrating, two thirds sampling
+    # clock stamps around each kernel of the stamped steps in the timed graph
+    # replays, weighted like the protocol: one third of the steps
+    # equilibrating, two thirds sampling
     w_phase = {"equilibrating": N_EQUIL / (N_EQUIL + N_SAMPLE), "sampling": N_SAMPLE / (N_EQUIL + N_SAMPLE)}
     present = [w for w in windows if w[1] > 0]
     wsum = sum(w_phase[p] for p, _, _ in present)
     kern = {k: float(sum(w_phase[p] * km[k][0] for p, _, km in present) / wsum) for k in names}
     kern["graph_step"] = float(sum(w_phase[p] * km["graph_step"][0] for p, _, km in present) / wsum)
     kern_windows = {p: {"timed_steps": n, "launches_timed": int(km["force"][1]),
-                        **{k: float(km[k][0]) for k in names + ("graph_step",)}} for p, n, km in windows}
+                        **{k: float(v[0]) for k, v in km.items()},
+                        "stamped_rebuild_steps": int(km["list_rebuild"][1])} for p, n, km in windows}
     cfg = batch.config()
     tuning = batch.tuning()
-    if done < N_EQUIL + N_SAMPLE:  # finish the sampling window (untimed) for the flux results
+    if done < N_EQUIL + N_SAMPLE and not args.no_finish:  # the rest of the sampling window (untimed): flux results
         advance(batch, N_EQUIL + N_SAMPLE - done, args.chunk)
-    res = batch.results()
+    res = batch.results() if not args.no_finish else []
     log(f"batched: {value:.3e} atom-steps/s, {ms_step:.3f} ms/step, kernels {kern}")
     n_atoms = int(batch.atoms)
     batch.close()
@@ -519,7 +547,8 @@ def main():
         "config": {"workload": "batched uneven NEMD channels: 64 systems, h=4+16u, g=0.001+0.049u, "
                                "57.1x57.1 sigma box, rho 0.8, T 1, rc 2.5, dt 0.005, protocol 10k+20k steps, "
                                f"FP32 forces / FP64 state and sums; timed: {plan['eq']} equilibrating + "
-                               f"{plan['sa']} sampling steps as graph replays of {plan['chunk']} steps"
+                               f"{plan['sa']} sampling steps as "
+                               + (f"graph replays of {plan['chunk']} steps" if plan['chunk'] else "direct launches")
                                + (f" (the other equilibration steps untimed)" if plan['skip'] else ""),
                    "systems": len(jobs), "fluid_atoms": n_atoms, "graph_chunk": plan["chunk"],
                    "force_path": PATH_NAMES[cfg["path"]], "skin": cfg["skin"],

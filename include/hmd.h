@@ -87,6 +87,14 @@ typedef struct {
     double skin, cell_w;
     double tile_alpha;
     int graph_chunk;
+    /* pressure 1: sampled steps also record the normal pressure the fluid
+     * exerts on the walls, (F_lo,y - F_hi,y) / (2 Lx Lz) (the cross-section
+     * average of P_yy, by the yy momentum balance; Alg. 1's pressure output
+     * of an MD run), into a per-step series beside the flux; results then
+     * carry p and p_se.  Pair paths only (force_path 0 is rejected); the
+     * force kernel of a sampled step then costs a few instructions more per
+     * pair.  0 (default): no pressure. */
+    int pressure;
 } hmd_md_params;
 
 void hmd_md_params_default(hmd_md_params* p);
@@ -116,8 +124,14 @@ int hmd_get_params(const hmd_ctx* ctx, hmd_md_params* params);
  * end, the fluid atom count and a per-job status (HMD_OK, HMD_EUNSTABLE,
  * HMD_ENOTCONV).
  * ------------------------------------------------------------------------ */
-typedef struct { double h, g; uint64_t seed; int64_t n_sample; } hmd_md_job;
-typedef struct { double flux, flux_se, jflux, T[3], pe; int64_t n_fluid; int status; } hmd_md_result;
+/* rho: fluid density of this job (atoms N_f = round(rho Lx Lz h)); <= 0
+ * takes params.rho. */
+typedef struct { double h, g; uint64_t seed; int64_t n_sample; double rho; } hmd_md_job;
+/* p, p_se: mean wall normal pressure and its standard error (same
+ * estimator as the flux) when params.pressure is on, else 0. */
+typedef struct {
+    double flux, flux_se, jflux, T[3], pe; int64_t n_fluid; int status; double p, p_se;
+} hmd_md_result;
 
 /* One job; flux and se receive q' and its standard error.  Returns the job's
  * status (a failed run returns HMD_EUNSTABLE / HMD_ENOTCONV with the values
@@ -163,13 +177,26 @@ int md_batch_get_states(hmd_batch* b, double* const* x, double* const* v);
  * sampled steps are left out).  Entries past the steps run so far read 0.
  * EINVAL for a batch created with n_sample = 0. */
 int md_batch_series(hmd_batch* b, int sim, double* q, int64_t* n);
+/* The sampled wall-pressure series of one system (params.pressure on), laid
+ * out as md_batch_series; EINVAL with pressure off. */
+int md_batch_pressure_series(hmd_batch* b, int sim, double* p, int64_t* n);
 /* Fluid atoms summed over the batch (for atom-step rates). */
 int64_t md_batch_atoms(const hmd_batch* b);
 /* Average duration in ms of each kernel over the md_batch_run calls made
- * since timing was switched on (HIP events on the batch's stream, captured
- * into the graph when graph_chunk > 0): names are "integrate", "scan",
- * "scatter", "reorder", "force"; "graph_step" gives the average time of one
- * step of graph replays. */
+ * since timing was switched on: names are "integrate", "keys", "scan",
+ * "scatter", "reorder", "list", "force"; "graph_step" gives the average time
+ * of one step of the stamped graph replays.  Direct launches are timed by
+ * HIP events on the batch's stream.  Graph replays (graph_chunk > 0): one
+ * replay in ten is a graph whose kernels of ten evenly spaced steps are
+ * bracketed by clock-stamp kernels (a kernel's time is the difference of its
+ * stamps less that of two adjacent stamps with nothing between them, at the
+ * device's wall-clock rate), timed by events and read back; the other
+ * replays run the plain graph without host synchronisation.  Stamped graph
+ * replays also give "list_rebuild" and "list_idle": the list build's mean
+ * time on stamped steps that rebuild the pair lists and on those that do
+ * not, so that a per-step figure can be weighted by the exact rebuild rate
+ * (md_batch_list_builds) rather than by the rebuilds that fell on stamped
+ * steps. */
 int md_batch_set_timing(hmd_batch* b, int on);
 int md_batch_kernel_ms(const hmd_batch* b, const char* kernel, double* ms, int64_t* launches);
 /* In-cutoff pairs at the current positions, summed over the batch:
@@ -346,6 +373,8 @@ int gp_log_marginal(hmd_gp* gp, double* lml);
 int gp_optimize(hmd_gp* gp, int mask, double* lml);
 /* The hyperparameters in use (after gp_optimize, the optimised ones). */
 int gp_hyper_get(const hmd_gp* gp, hmd_gp_hyper* hyper);
+/* The database inputs (n x d row-major into X, nullable) and *n, *d. */
+int gp_inputs(const hmd_gp* gp, double* X, int* n, int* d);
 int gp_size(const hmd_gp* gp);
 /* The normalisation in use: per-input denominators of Eq. d2Eq (d values),
  * the output scale and sigma_n in scaled units (each nullable). */
@@ -364,7 +393,12 @@ void gp_free(hmd_gp* gp);
  * order: W1[hidden x 2], b1, W2[hidden x hidden], b2, W3[1 x hidden], b3.
  * X is row-major n x 2.
  * ------------------------------------------------------------------------ */
-typedef struct { int members, hidden, iters; double lr; uint64_t seed; } hmd_ens_cfg;
+/* bootstrap 1: member k trains on a resample of the n points drawn with
+ * replacement (draw j is point (r n) >> 32 for the Philox4x32-10 word r of
+ * counter (j div 4, k, 3, 0), word j mod 4, key = seed): its loss weights
+ * each squared residual by the point's count; standardisation uses the
+ * whole set.  0: every member trains on the whole set. */
+typedef struct { int members, hidden, iters; double lr; uint64_t seed; int bootstrap; } hmd_ens_cfg;
 
 void hmd_ens_cfg_default(hmd_ens_cfg* c);
 int ens_fit(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg, hmd_ens** out);
@@ -451,6 +485,16 @@ typedef struct {
      * dp_mean, dp_amp and period are unused.  geometry 0: the channel above. */
     int geometry;
     double f_amp, f_period;
+    /* eos 1: the paper's full input set (Sec. 2.2; Alg. 1 with both GPs).
+     * The section pressure is the mean of a pressure GP p(h, rho) (attached
+     * with hybrid_set_pressure_gp, built from pre-simulations: md_flux_batch
+     * with params.pressure on, g = 0, over a density sweep per height)
+     * instead of the linear law; the flux GP takes three inputs (h, rho, |g|);
+     * every fallback runs at its section's density and also returns the
+     * wall pressure, which joins the pressure GP when that (h, rho) is not in
+     * it yet.  The boundary pressures p_out and p_in(t) are then absolute.
+     * Needs surrogate 0 and no warm starts.  eos 0: the linear law. */
+    int eos;
 } hmd_hybrid_cfg;
 typedef struct {
     int64_t steps, md_calls, audited, audit_pass, queries, md_failed;
@@ -467,12 +511,18 @@ typedef struct {
     /* audits that also pass when the surrogate's own predicted standard
      * deviation is counted: |mean - q_MD| <= 2 sqrt(std^2 + SE_MD^2) */
     int64_t audit_pass_cal;
+    /* eos 1: fallback pressures appended to the pressure GP */
+    int64_t p_appends;
 } hmd_hybrid_stats;
 
 /* A replacement micro-solver: given n (h, g) pairs, write the mean flux and
  * its standard error; return 0 on success.  Used instead of batched MD when
  * set (coupling another solver, or a known law in tests). */
 typedef int (*hmd_micro_fn)(void* user, int n, const double* h, const double* g, double* q, double* se);
+/* The same for eos 1: inputs (h, rho, g), outputs flux, its SE, wall
+ * pressure and its SE. */
+typedef int (*hmd_micro_p_fn)(void* user, int n, const double* h, const double* rho, const double* g, double* q,
+                              double* se, double* p, double* p_se);
 
 void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c);
 /* Runs the audits still pending (audit_batch > 0) and returns the stats. */
@@ -481,6 +531,13 @@ int hybrid_flush_audits(hmd_hybrid* hy, hmd_hybrid_stats* out);
  * (the caller frees it after hybrid_free).  rho starts at rho_ref. */
 int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out);
 int hybrid_set_micro(hmd_hybrid* hy, hmd_micro_fn fn, void* user);
+int hybrid_set_micro_p(hmd_hybrid* hy, hmd_micro_p_fn fn, void* user);
+/* eos 1: the pressure GP over (h, rho) (2 inputs), borrowed like the flux
+ * GP; its current inputs count as present for the append rule. */
+int hybrid_set_pressure_gp(hmd_hybrid* hy, hmd_gp* pgp);
+/* eos 1: the section pressures of the last step and their GP standard
+ * deviations (n_sections doubles each, nullable); eos 0: the linear law. */
+int hybrid_get_pressure(hmd_hybrid* hy, double* p, double* p_std);
 /* Overwrite the density of every section (n_sections doubles). */
 int hybrid_set_rho(hmd_hybrid* hy, const double* rho);
 /* The fallback plan of the last macro step, per section (each nullable):

@@ -52,16 +52,16 @@ class MdParams(_c.Structure):
                 ("wall_layers", i32), ("thermo_axis", i32), ("dt", d), ("tau_T", d), ("Lx_nom", d),
                 ("Lz_nom", d), ("bin_dy", d), ("n_equil", i64), ("n_blocks", i32), ("n_fluid", i64),
                 ("delta", d), ("force_path", i32), ("skin", d), ("cell_w", d), ("tile_alpha", d),
-                ("graph_chunk", i32)]
+                ("graph_chunk", i32), ("pressure", i32)]
 
 
 class MdJob(_c.Structure):
-    _fields_ = [("h", d), ("g", d), ("seed", u64), ("n_sample", i64)]
+    _fields_ = [("h", d), ("g", d), ("seed", u64), ("n_sample", i64), ("rho", d)]
 
 
 class MdResult(_c.Structure):
     _fields_ = [("flux", d), ("flux_se", d), ("jflux", d), ("T", d * 3), ("pe", d), ("n_fluid", i64),
-                ("status", i32)]
+                ("status", i32), ("p", d), ("p_se", d)]
 
 
 def _sig(name, res, *args):
@@ -92,6 +92,7 @@ _sig("md_batch_forces", i32, vp, i32, P(_c.c_float), P(d))
 _sig("md_batch_free", None, vp)
 _sig("md_batch_set_state", i32, vp, i32, P(d), P(d))
 _sig("md_batch_series", i32, vp, i32, P(d), P(i64))
+_sig("md_batch_pressure_series", i32, vp, i32, P(d), P(i64))
 _sig("md_series_stats", i32, vp, P(d), i32, i64, i64, i32, P(d))
 _sig("md_series_stats_dev", i32, vp, vp, i32, i64, i64, i32, vp, vp)
 _sig("md_series_stats_noalloc", i32, vp, vp, i32, i64, i64, i32, vp, vp)
@@ -171,6 +172,7 @@ class Params:
     cell_w: float = 0.0
     tile_alpha: float = 0.0
     graph_chunk: int = 0
+    pressure: int = 0
 
     def to_c(self):
         return MdParams(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -217,15 +219,17 @@ class Context:
 
 
 def _jobs(jobs) -> ctypes.Array:
+    """(h, g, seed, n_sample[, rho]) tuples; rho <= 0 or absent: the
+    context's density."""
     arr = (MdJob * len(jobs))()
     for k, j in enumerate(jobs):
-        arr[k] = MdJob(float(j[0]), float(j[1]), int(j[2]), int(j[3]))
+        arr[k] = MdJob(float(j[0]), float(j[1]), int(j[2]), int(j[3]), float(j[4]) if len(j) > 4 else 0.0)
     return arr
 
 
 def _result_dict(r: MdResult):
     return {"flux": r.flux, "flux_se": r.flux_se, "jflux": r.jflux, "T": np.array(list(r.T)), "pe": r.pe,
-            "n_fluid": r.n_fluid, "status": r.status}
+            "n_fluid": r.n_fluid, "status": r.status, "p": r.p, "p_se": r.p_se}
 
 
 def md_flux(ctx: Context, h, g, seed, steps):
@@ -375,6 +379,14 @@ class Batch:
         q = np.zeros(n.value)
         self.ctx.check(_lib.md_batch_series(self._h, int(sim), _ptr(q), _c.byref(n)))
         return q
+
+    def pressure_series(self, sim: int):
+        """The sampled wall-pressure series p(t) of one system (pressure on)."""
+        n = i64()
+        self.ctx.check(_lib.md_batch_pressure_series(self._h, int(sim), None, _c.byref(n)))
+        p = np.zeros(n.value)
+        self.ctx.check(_lib.md_batch_pressure_series(self._h, int(sim), _ptr(p), _c.byref(n)))
+        return p
 
     def forces(self, sim: int):
         f = np.zeros((self.n_fluid(sim), 3), dtype=np.float32)
@@ -600,7 +612,7 @@ class GP:
 
 # ---------------------------------------------------------------- MLP ensemble
 class EnsCfg(_c.Structure):
-    _fields_ = [("members", i32), ("hidden", i32), ("iters", i32), ("lr", d), ("seed", u64)]
+    _fields_ = [("members", i32), ("hidden", i32), ("iters", i32), ("lr", d), ("seed", u64), ("bootstrap", i32)]
 
 
 _sig("hmd_ens_cfg_default", None, P(EnsCfg))
@@ -613,8 +625,8 @@ _sig("ens_members", i32, vp)
 _sig("ens_free", None, vp)
 
 
-def ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3, seed=0):
-    return EnsCfg(members, hidden, iters, lr, seed)
+def ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3, seed=0, bootstrap=0):
+    return EnsCfg(members, hidden, iters, lr, seed, bootstrap)
 
 
 class Ensemble:

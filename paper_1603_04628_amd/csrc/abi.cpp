@@ -44,6 +44,7 @@ void hmd_md_params_default(hmd_md_params* p) {
   p->n_equil = 0; p->n_blocks = 0; p->n_fluid = 0; p->delta = 1.0;
   p->force_path = -1; p->skin = 0.3; p->cell_w = 0.0;
   p->tile_alpha = 0.0; p->graph_chunk = 0;
+  p->pressure = 0;
 }
 
 int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ctx** out) {
@@ -132,6 +133,10 @@ int md_batch_set_timing(hmd_batch* b, int on) {
     b->kern_ms[k] = 0.0;
     b->kern_n[k] = 0;
   }
+  for (int r = 0; r < 2; ++r) {
+    b->list_ms[r] = 0.0;
+    b->list_n[r] = 0;
+  }
   b->graph_ms = 0.0;
   b->graph_steps = 0;
   return HMD_OK;
@@ -145,6 +150,12 @@ int md_batch_kernel_ms(const hmd_batch* b, const char* kernel, double* ms, int64
     if (launches) *launches = b->graph_steps;
     return HMD_OK;
   }
+  for (int r = 0; r < 2; ++r)
+    if (std::strcmp(kernel, r ? "list_rebuild" : "list_idle") == 0) {
+      *ms = b->list_n[r] ? b->list_ms[r] / double(b->list_n[r]) : 0.0;
+      if (launches) *launches = b->list_n[r];
+      return HMD_OK;
+    }
   for (int k = 0; k < hmd::K_COUNT; ++k)
     if (std::strcmp(kernel, names[k]) == 0) {
       *ms = b->kern_n[k] ? b->kern_ms[k] / double(b->kern_n[k]) : 0.0;
@@ -215,7 +226,12 @@ int md_batch_get_states(hmd_batch* b, double* const* x, double* const* v) {
 
 int md_batch_series(hmd_batch* b, int sim, double* q, int64_t* n) {
   if (!b) return HMD_EINVAL;
-  return guarded(b->ctx, [&] { return hmd::batch_series(b, sim, q, n); });
+  return guarded(b->ctx, [&] { return hmd::batch_series(b, sim, q, n, 0); });
+}
+
+int md_batch_pressure_series(hmd_batch* b, int sim, double* p, int64_t* n) {
+  if (!b) return HMD_EINVAL;
+  return guarded(b->ctx, [&] { return hmd::batch_series(b, sim, p, n, 1); });
 }
 
 void md_batch_free(hmd_batch* b) { hmd::batch_free(b); }

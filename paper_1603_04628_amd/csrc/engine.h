@@ -80,6 +80,7 @@ struct StepConst {
   int thermo_on;   // thermostat active in this run
   int bins_on;     // accumulate the wall-normal profile
   int energy_on;   // accumulate potential and kinetic energy
+  int press_on;    // sampled steps also record the wall normal pressure
 };
 
 // Per-system FP64 accumulators (device).
@@ -89,6 +90,7 @@ struct Acc {
   double* ke[2];    // sum |v|^2 after the second half-kick, by step parity
   double* blocks;   // [S * nb] the sampled q' series: entry k of a system holds the sum of
                     // B consecutive steps' q' (B = 1 unless n_sample exceeds the series cap)
+  double* pblocks;  // [S * nb] the sampled wall-pressure series, laid out as blocks
   double* tsum;     // [S * 3] sums of T_a over sampled steps
   double* binvx;    // [bins] sum v_x
   double* bincnt;   // [bins] counts
@@ -99,7 +101,8 @@ struct Acc {
 };
 
 enum Kern { K_INTEGRATE = 0, K_SCAN, K_SCATTER, K_REORDER, K_FORCE, K_KEYS, K_LIST, K_COUNT };
-constexpr int kStampedSteps = 10;  // steps per timed graph replay whose kernels are stamped
+constexpr int kStampedSteps = 10;  // steps per stamped graph replay whose kernels are stamped
+constexpr int kStampEvery = 10;    // in timing mode, one replay in this many is the stamped graph
 constexpr int kMaxStamps = 96;     // stamps of one timed replay (kernels + 1 per stamped step, + 1)
 
 }  // namespace hmd
@@ -182,6 +185,8 @@ struct hmd_batch {
   std::vector<hipEvent_t> ev;             // event pool for timing
   double kern_ms[hmd::K_COUNT] = {};
   int64_t kern_n[hmd::K_COUNT] = {};
+  double list_ms[2] = {};   // stamped list-build time on steps without / with a rebuild
+  int64_t list_n[2] = {};
   double graph_ms = 0.0;     // timed graph replays
   int64_t graph_steps = 0;
 };
@@ -202,7 +207,7 @@ int batch_cells(hmd_batch* b, int sim, uint32_t* cell_of, uint32_t* counts, uint
 int batch_profile(hmd_batch* b, int sim, double* mvx, double* cnt);
 int batch_pairs(hmd_batch* b, int64_t* ff, int64_t* wf);
 int batch_list_builds(hmd_batch* b, int64_t* builds);
-int batch_series(hmd_batch* b, int sim, double* q, int64_t* n);
+int batch_series(hmd_batch* b, int sim, double* q, int64_t* n, int which);
 int batch_neighbors(hmd_batch* b, int sim, uint32_t* counts, uint32_t* idx, int64_t cap, int64_t* total);
 // Implementation choices of a batch.
 struct Config {

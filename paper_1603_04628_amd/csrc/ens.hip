@@ -59,10 +59,12 @@ __device__ __forceinline__ Slot decode(int p, int H) {
 // Training is split over (chunk of CHUNK points, member) workgroups so that
 // every iteration runs on many CUs: k_ens_chunk computes one chunk's forward
 // and backward pass and its share of the gradient and loss (MSE over all N
-// points: the 2/N and 1/N factors are applied here); k_ens_adam sums the
-// shares of each member and takes one Adam step.
+// points: the 2/N and 1/N factors are applied here; wts, when given, holds
+// each member's bootstrap count per point); k_ens_adam sums the shares of
+// each member and takes one Adam step.
 __global__ __launch_bounds__(ENS_TPB) void k_ens_chunk(int N, int H, const float* __restrict__ Xs,
                                                        const float* __restrict__ ys,
+                                                       const float* __restrict__ wts,
                                                        const float* __restrict__ params, float* __restrict__ gpart,
                                                        float* __restrict__ lpart) {
   extern __shared__ float lds[];
@@ -113,9 +115,12 @@ __global__ __launch_bounds__(ENS_TPB) void k_ens_chunk(int N, int H, const float
     float a = b3[0];
     const float* hh = h2 + tid * HP;
     for (int o = 0; o < H; ++o) a += W3[o] * hh[o];
+    // bootstrap: the point's count in this member's resample weights its
+    // squared residual (the mean still over N)
+    const float w = wts ? wts[size_t(member) * N + c0 + tid] : 1.0f;
     const float r = a - ys[c0 + tid];
-    lsum = r * r;
-    dout[tid] = 2.0f * r * invN;
+    lsum = w * r * r;
+    dout[tid] = 2.0f * w * r * invN;
   }
   __syncthreads();
   for (int e = tid; e < nc * H; e += ENS_TPB) {
@@ -291,16 +296,32 @@ void glorot(int H, int member, uint64_t seed, float* out) {
   for (int p = 4 * H + H * H; p < 5 * H + H * H; ++p) out[p] = float(l3 * (2.0 * u[p] - 1.0));
 }
 
+// Bootstrap resample of member `member` (counts per point): draw j takes
+// point (r n) >> 32 for the Philox word r of counter (j div 4, member, 3, 0),
+// word j mod 4, keyed by the seed.
+void bootstrap_counts(int n, int member, uint64_t seed, float* out) {
+  const uint32_t key[2] = {uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32)};
+  for (int i = 0; i < n; ++i) out[i] = 0.f;
+  for (int j = 0; 4 * j < n; ++j) {
+    const uint32_t ctr[4] = {uint32_t(j), uint32_t(member), 3u, 0u};
+    uint32_t r[4];
+    philox4x32_10(ctr, key, r);
+    for (int w = 0; w < 4 && 4 * j + w < n; ++w) out[(uint64_t(r[w]) * uint64_t(n)) >> 32] += 1.f;
+  }
+}
+
 int check_cfg(hmd_ctx* ctx, const hmd_ens_cfg& c, int n) {
-  if (c.members < 1 || c.members > 64 || c.hidden < 1 || c.hidden > MAXH || c.iters < 0 || !(c.lr > 0.0) || n < 1) {
-    ctx->err = "ens: 1..64 members, 1..64 hidden units, iters >= 0, lr > 0, n >= 1";
+  if (c.members < 1 || c.members > 64 || c.hidden < 1 || c.hidden > MAXH || c.iters < 0 || !(c.lr > 0.0) || n < 1 ||
+      c.bootstrap < 0 || c.bootstrap > 1) {
+    ctx->err = "ens: 1..64 members, 1..64 hidden units, iters >= 0, lr > 0, n >= 1, bootstrap 0 or 1";
     return HMD_EINVAL;
   }
   return HMD_OK;
 }
 
-// Standardise inputs and scale outputs (host, FP64), upload as FP32.
-int stage_data(hmd_ens* e, const double* X, const double* y, int n, float** dX, float** dy) {
+// Standardise inputs and scale outputs (host, FP64), upload as FP32; with
+// the bootstrap option also each member's counts (*dw, members x n).
+int stage_data(hmd_ens* e, const double* X, const double* y, int n, float** dX, float** dy, float** dw) {
   hmd_ctx* ctx = e->ctx;
   for (int k = 0; k < 2; ++k) {
     double s = 0.0;
@@ -324,10 +345,18 @@ int stage_data(hmd_ens* e, const double* X, const double* y, int n, float** dX, 
   HMD_HIP(ctx, hipMalloc(dy, sizeof(float) * ys.size()));
   HMD_HIP(ctx, hipMemcpyAsync(*dX, xs.data(), sizeof(float) * xs.size(), hipMemcpyHostToDevice, ctx->stream));
   HMD_HIP(ctx, hipMemcpyAsync(*dy, ys.data(), sizeof(float) * ys.size(), hipMemcpyHostToDevice, ctx->stream));
+  *dw = nullptr;
+  if (e->cfg.bootstrap) {
+    const int M = e->cfg.members;
+    std::vector<float> w(size_t(M) * n);
+    for (int k = 0; k < M; ++k) bootstrap_counts(n, k, e->cfg.seed, w.data() + size_t(k) * n);
+    HMD_HIP(ctx, hipMalloc(dw, sizeof(float) * w.size()));
+    HMD_HIP(ctx, hipMemcpy(*dw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice));
+  }
   return HMD_OK;
 }
 
-int run_train(hmd_ens* e, int n, const float* dX, const float* dy, int mode, float* dgrad) {
+int run_train(hmd_ens* e, int n, const float* dX, const float* dy, const float* dw, int mode, float* dgrad) {
   hmd_ctx* ctx = e->ctx;
   const hmd_ens_cfg& c = e->cfg;
   const size_t lds = train_lds_bytes(c.hidden);
@@ -347,7 +376,7 @@ int run_train(hmd_ens* e, int n, const float* dX, const float* dy, int mode, flo
   const int iters = mode == 1 ? 1 : c.iters;
   const dim3 agrid((P + ENS_TPB - 1) / ENS_TPB, M);
   auto iteration = [&](int k) {
-    hipLaunchKernelGGL(k_ens_chunk, dim3(nchunk, M), dim3(ENS_TPB), lds, s, n, c.hidden, dX, dy, e->dparams,
+    hipLaunchKernelGGL(k_ens_chunk, dim3(nchunk, M), dim3(ENS_TPB), lds, s, n, c.hidden, dX, dy, dw, e->dparams,
                        gpart, lpart);
     hipLaunchKernelGGL(k_ens_adam, agrid, dim3(ENS_TPB), 0, s, P, nchunk, gpart, lpart, e->dparams, mom, vel,
                        tstep, k, float(c.lr), dloss, mode == 1 ? dgrad : nullptr);
@@ -413,6 +442,7 @@ void hmd_ens_cfg_default(hmd_ens_cfg* c) {
   c->iters = 5000;
   c->lr = 1e-3;
   c->seed = 0;
+  c->bootstrap = 0;
 }
 
 int ens_fit(hmd_ctx* ctx, const double* X, const double* y, int n, const hmd_ens_cfg* cfg, hmd_ens** out) {
@@ -456,11 +486,11 @@ int ens_refit(hmd_ens* e) {
     (void)hipFree(e->dparams);
     e->dparams = nullptr;
   }
-  float *dX = nullptr, *dy = nullptr;
-  if ((rc = init_params(e)) == HMD_OK && (rc = stage_data(e, e->X.data(), e->y.data(), n, &dX, &dy)) == HMD_OK)
-    rc = run_train(e, n, dX, dy, 0, nullptr);
-  if (dX) (void)hipFree(dX);
-  if (dy) (void)hipFree(dy);
+  float *dX = nullptr, *dy = nullptr, *dw = nullptr;
+  if ((rc = init_params(e)) == HMD_OK && (rc = stage_data(e, e->X.data(), e->y.data(), n, &dX, &dy, &dw)) == HMD_OK)
+    rc = run_train(e, n, dX, dy, dw, 0, nullptr);
+  for (void* p : {(void*)dX, (void*)dy, (void*)dw})
+    if (p) (void)hipFree(p);
   return rc;
 }
 
@@ -546,10 +576,10 @@ int ens_grad_init(hmd_ctx* ctx, const double* X, const double* y, int n, const h
   hmd_ens e;
   e.ctx = ctx;
   e.cfg = c;
-  float *dX = nullptr, *dy = nullptr, *dg = nullptr;
-  if ((rc = init_params(&e)) == HMD_OK && (rc = stage_data(&e, X, y, n, &dX, &dy)) == HMD_OK) {
+  float *dX = nullptr, *dy = nullptr, *dg = nullptr, *dw = nullptr;
+  if ((rc = init_params(&e)) == HMD_OK && (rc = stage_data(&e, X, y, n, &dX, &dy, &dw)) == HMD_OK) {
     if (hipMalloc(&dg, sizeof(float) * size_t(c.members) * e.P) != hipSuccess) rc = HMD_ENOMEM;
-    else rc = run_train(&e, n, dX, dy, 1, dg);
+    else rc = run_train(&e, n, dX, dy, dw, 1, dg);
   }
   if (rc == HMD_OK) {
     std::vector<float> hp(e.P), hg(e.P);
@@ -563,7 +593,7 @@ int ens_grad_init(hmd_ctx* ctx, const double* X, const double* y, int n, const h
     }
     if (n_params) *n_params = e.P;
   }
-  for (void* p : {(void*)dX, (void*)dy, (void*)dg, (void*)e.dparams})
+  for (void* p : {(void*)dX, (void*)dy, (void*)dg, (void*)dw, (void*)e.dparams})
     if (p) (void)hipFree(p);
   return rc;
 }

@@ -803,6 +803,14 @@ int gp_hyper_get(const hmd_gp* g, hmd_gp_hyper* hyper) {
 
 int gp_size(const hmd_gp* g) { return g ? g->n : 0; }
 
+int gp_inputs(const hmd_gp* g, double* X, int* n, int* d) {
+  if (!g) return HMD_EINVAL;
+  if (n) *n = g->n;
+  if (d) *d = g->d;
+  if (X) std::copy(g->X.begin(), g->X.begin() + size_t(g->n) * g->d, X);
+  return HMD_OK;
+}
+
 int gp_scales(const hmd_gp* g, double* scale, double* s_q, double* sigma_n) {
   if (!g) return HMD_EINVAL;
   if (scale)

@@ -10,7 +10,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <set>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hmd.h"
@@ -33,14 +35,18 @@ struct hmd_hybrid {
   hmd_ens* ens = nullptr;
   hmd_micro_fn micro = nullptr;
   void* micro_user = nullptr;
+  hmd_micro_p_fn micro_p = nullptr;  // eos 1 replacement micro-solver
+  void* micro_p_user = nullptr;
+  hmd_gp* pgp = nullptr;             // eos 1: pressure GP over (h, rho)
+  std::set<std::pair<double, double>> p_db;  // eos 1: (h, rho) inputs in the pressure GP
   double ds = 0.0;
-  std::vector<double> h, rho, q, q_std, g;
+  std::vector<double> h, rho, q, q_std, g, p, p_std;
   std::vector<uint8_t> from_md;
   int64_t step_no = 0, answers = 0, pending_refit = 0;
   uint64_t next_seed = 0;
   hmd_hybrid_stats st{};
-  // audits waiting for their batch: (h, |g|) and the surrogate's answer
-  std::vector<double> audit_h, audit_g, audit_mean, audit_sd;
+  // audits waiting for their batch: (h, rho, |g|) and the surrogate's answer
+  std::vector<double> audit_h, audit_rho, audit_g, audit_mean, audit_sd;
   // warm starts: the recorded fallback runs and the last step's plan
   std::vector<Warm> warm;
   std::vector<int> plan_prior;
@@ -61,31 +67,50 @@ double seconds_since(clock_t_::time_point t0) {
 // Fluxes for the listed sections from the micro-solver (callback or batched
 // MD).  Audits run from the lattice with params.n_equil; fallback runs with
 // warm starts use `prior` (index into hy->warm, -1: lattice) and equilibrate
-// for n_equil steps, and return their final states in xs, vs.
+// for n_equil steps, and return their final states in xs, vs.  With eos 1
+// every run takes its section's density rr[k] and also returns the wall
+// pressure pm, its SE pse.
 int solve_micro(hmd_hybrid* hy, std::vector<double> hh, std::vector<double> gg, std::vector<double>& qm,
                 std::vector<double>& se, std::vector<int>& ok, bool audit, const std::vector<int>* prior = nullptr,
                 int64_t n_equil = -1, std::vector<std::vector<double>>* xs = nullptr,
-                std::vector<std::vector<double>>* vs = nullptr) {
+                std::vector<std::vector<double>>* vs = nullptr, const std::vector<double>* rr = nullptr,
+                std::vector<double>* pm = nullptr, std::vector<double>* pse = nullptr) {
   double& wall = audit ? hy->st.audit_wall_s : hy->st.md_wall_s;
   double& atom_steps = audit ? hy->st.audit_atom_steps : hy->st.md_atom_steps;
   const int n = int(hh.size());
+  const bool press = hy->cfg.eos == 1;
   qm.assign(n, 0.0);
   se.assign(n, 0.0);
   ok.assign(n, 1);
+  if (pm) pm->assign(n, 0.0);
+  if (pse) pse->assign(n, 0.0);
   const auto t0 = clock_t_::now();
-  if (hy->micro) {
+  if (press && hy->micro_p) {
+    const int rc = hy->micro_p(hy->micro_p_user, n, hh.data(), rr->data(), gg.data(), qm.data(), se.data(),
+                               pm->data(), pse->data());
+    wall += seconds_since(t0);
+    return rc == 0 ? HMD_OK : HMD_EINVAL;
+  }
+  if (!press && hy->micro) {
     const int rc = hy->micro(hy->micro_user, n, hh.data(), gg.data(), qm.data(), se.data());
     wall += seconds_since(t0);
     return rc == 0 ? HMD_OK : HMD_EINVAL;
   }
   std::vector<hmd_md_job> jobs(n);
-  for (int k = 0; k < n; ++k) jobs[k] = hmd_md_job{hh[k], gg[k], hy->next_seed++, hy->cfg.md_sample};
+  for (int k = 0; k < n; ++k)
+    jobs[k] = hmd_md_job{hh[k], gg[k], hy->next_seed++, hy->cfg.md_sample, press ? (*rr)[k] : 0.0};
   std::vector<hmd_md_result> res(n);
   hmd_md_params P;
   hmd_get_params(hy->ctx, &P);
   const int64_t cold_equil = P.n_equil;
   int rc = HMD_OK;
-  if (!prior) {
+  if (press) {  // the runs also record the wall pressure
+    hmd_md_params Q = P;
+    Q.pressure = 1;
+    rc = hmd_set_params(hy->ctx, &Q);
+    if (rc == HMD_OK) rc = md_flux_batch(hy->ctx, jobs.data(), n, res.data());
+    hmd_set_params(hy->ctx, &P);
+  } else if (!prior) {
     rc = md_flux_batch(hy->ctx, jobs.data(), n, res.data());
   } else {
     // the batch's own equilibration, warm states set after creation
@@ -128,6 +153,8 @@ int solve_micro(hmd_hybrid* hy, std::vector<double> hh, std::vector<double> gg, 
   for (int k = 0; k < n; ++k) {
     qm[k] = res[k].flux;
     se[k] = res[k].flux_se;
+    if (pm) (*pm)[k] = res[k].p;
+    if (pse) (*pse)[k] = res[k].p_se;
     ok[k] = res[k].status == HMD_OK;
     hy->st.md_failed += ok[k] || audit ? 0 : 1;
     atom_steps += double(res[k].n_fluid) * double(equil + hy->cfg.md_sample);
@@ -142,9 +169,10 @@ int solve_micro(hmd_hybrid* hy, std::vector<double> hh, std::vector<double> gg, 
 // Runs the pending audits as one batch and scores them.
 int flush_audits(hmd_hybrid* hy) {
   if (hy->audit_h.empty()) return HMD_OK;
-  std::vector<double> qm, se;
+  std::vector<double> qm, se, pm, pse;
   std::vector<int> ok;
-  const int rc = solve_micro(hy, hy->audit_h, hy->audit_g, qm, se, ok, true);
+  const int rc = solve_micro(hy, hy->audit_h, hy->audit_g, qm, se, ok, true, nullptr, -1, nullptr, nullptr,
+                             &hy->audit_rho, &pm, &pse);
   if (rc != HMD_OK) return rc;
   for (size_t k = 0; k < qm.size(); ++k) {
     if (!ok[k]) continue;
@@ -155,6 +183,7 @@ int flush_audits(hmd_hybrid* hy) {
         dev <= 2.0 * std::sqrt(hy->audit_sd[k] * hy->audit_sd[k] + se[k] * se[k]) ? 1 : 0;
   }
   hy->audit_h.clear();
+  hy->audit_rho.clear();
   hy->audit_g.clear();
   hy->audit_mean.clear();
   hy->audit_sd.clear();
@@ -196,6 +225,7 @@ void hmd_hybrid_cfg_default(hmd_hybrid_cfg* c) {
   c->geometry = 0;
   c->f_amp = 0.0;
   c->f_period = 250.0;
+  c->eos = 0;
 }
 
 int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* ens, hmd_hybrid** out) {
@@ -206,7 +236,8 @@ int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* 
       c.surrogate < 0 || c.surrogate > 1 || c.md_sample < 0 || c.refit_every < 1 || !(c.period > 0.0) ||
       (c.warm_start && (!(c.pseudo_nu > 0.0) || !(c.pseudo_slip >= 0.0) || !(c.pseudo_tol > 0.0) ||
                         c.n_min_warm < 0 || c.n_min_cold < 0)) ||
-      c.geometry < 0 || c.geometry > 1 || (c.geometry == 1 && !(c.f_period > 0.0)))
+      c.geometry < 0 || c.geometry > 1 || (c.geometry == 1 && !(c.f_period > 0.0)) || c.eos < 0 || c.eos > 1 ||
+      (c.eos == 1 && (c.surrogate != 0 || c.warm_start)))
     return HMD_EINVAL;
   auto* hy = new hmd_hybrid();
   hy->ctx = ctx;
@@ -230,6 +261,8 @@ int hybrid_create(hmd_ctx* ctx, const hmd_hybrid_cfg* cfg, hmd_gp* gp, hmd_ens* 
   hy->q.assign(n, 0.0);
   hy->q_std.assign(n, 0.0);
   hy->g.assign(n, 0.0);
+  hy->p.assign(n, 0.0);
+  hy->p_std.assign(n, 0.0);
   hy->from_md.assign(n, 0);
   hy->plan_prior.assign(n, -2);
   hy->plan_equil.assign(n, 0);
@@ -241,6 +274,36 @@ int hybrid_set_micro(hmd_hybrid* hy, hmd_micro_fn fn, void* user) {
   if (!hy) return HMD_EINVAL;
   hy->micro = fn;
   hy->micro_user = user;
+  return HMD_OK;
+}
+
+int hybrid_set_micro_p(hmd_hybrid* hy, hmd_micro_p_fn fn, void* user) {
+  if (!hy) return HMD_EINVAL;
+  hy->micro_p = fn;
+  hy->micro_p_user = user;
+  return HMD_OK;
+}
+
+int hybrid_set_pressure_gp(hmd_hybrid* hy, hmd_gp* pgp) {
+  if (!hy || !pgp) return HMD_EINVAL;
+  int n = 0, d = 0;
+  int rc = gp_inputs(pgp, nullptr, &n, &d);
+  if (rc != HMD_OK) return rc;
+  if (d != 2) return HMD_EINVAL;
+  std::vector<double> X(2 * size_t(n));
+  rc = gp_inputs(pgp, X.data(), nullptr, nullptr);
+  if (rc != HMD_OK) return rc;
+  hy->pgp = pgp;
+  hy->p_db.clear();
+  for (int k = 0; k < n; ++k) hy->p_db.insert({X[2 * size_t(k)], X[2 * size_t(k) + 1]});
+  return HMD_OK;
+}
+
+int hybrid_get_pressure(hmd_hybrid* hy, double* p, double* p_std) {
+  if (!hy) return HMD_EINVAL;
+  const int n = hy->cfg.n_sections;
+  if (p) std::copy(hy->p.begin(), hy->p.begin() + n, p);
+  if (p_std) std::copy(hy->p_std.begin(), hy->p_std.begin() + n, p_std);
   return HMD_OK;
 }
 
@@ -257,9 +320,29 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   const auto t0 = clock_t_::now();
   const hmd_hybrid_cfg& c = hy->cfg;
   const int n = c.n_sections;
-  // pressure, central-difference gradient with ghost pressures, body force
+  const bool press = c.eos == 1;
+  if (press && !hy->pgp) return HMD_EINVAL;  // eos 1 needs hybrid_set_pressure_gp first
+  // pressure (linear law, or eos 1: the pressure GP at (h, rho)),
+  // central-difference gradient with ghost pressures, body force
   std::vector<double> p(n);
-  for (int i = 0; i < n; ++i) p[i] = c.p_out + c.c2 * (hy->rho[i] - c.rho_ref);
+  if (press) {
+    std::vector<double> Xp(2 * size_t(n)), pv(n);
+    for (int i = 0; i < n; ++i) {
+      Xp[2 * i] = hy->h[i];
+      Xp[2 * i + 1] = hy->rho[i];
+    }
+    const auto tp = clock_t_::now();
+    const int rcp = gp_predict(hy->pgp, Xp.data(), n, p.data(), pv.data());
+    hy->st.surrogate_wall_s += seconds_since(tp);
+    if (rcp != HMD_OK) return rcp;
+    for (int i = 0; i < n; ++i) hy->p_std[i] = std::sqrt(pv[i] > 0.0 ? pv[i] : 0.0);
+  } else {
+    for (int i = 0; i < n; ++i) {
+      p[i] = c.p_out + c.c2 * (hy->rho[i] - c.rho_ref);
+      hy->p_std[i] = 0.0;
+    }
+  }
+  hy->p = p;
   const double p_in = c.p_out + c.dp_mean * (1.0 + c.dp_amp * std::sin(kTwoPi * double(hy->step_no) / c.period));
   // Eq. extForcing1 on the periodic channel
   const double f_ext = c.geometry == 1 ? c.f_amp * std::sin(kTwoPi * double(hy->step_no) / c.f_period) : 0.0;
@@ -277,13 +360,15 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   }
   // surrogate query for every section (at |g| with the sign restored after,
   // when mirror is on)
-  std::vector<double> X(2 * size_t(n)), mean(n), second(n), sd(n), gq(n), sgn(n, 1.0);
+  const int dx = press ? 3 : 2;  // flux inputs: (h, |g|), or (h, rho, |g|)
+  std::vector<double> X(dx * size_t(n)), mean(n), second(n), sd(n), gq(n), sgn(n, 1.0);
   for (int i = 0; i < n; ++i) {
     const bool neg = c.mirror && hy->g[i] < 0.0;
     gq[i] = neg ? -hy->g[i] : hy->g[i];
     sgn[i] = neg ? -1.0 : 1.0;
-    X[2 * i] = hy->h[i];
-    X[2 * i + 1] = gq[i];
+    X[dx * i] = hy->h[i];
+    if (press) X[dx * i + 1] = hy->rho[i];
+    X[dx * i + dx - 1] = gq[i];
   }
   const auto ts = clock_t_::now();
   int rc = c.surrogate == 0 ? gp_predict(hy->gp, X.data(), n, mean.data(), second.data())
@@ -314,11 +399,12 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   std::fill(hy->plan_equil.begin(), hy->plan_equil.end(), int64_t(0));
   hy->plan_batch_equil = 0;
   if (!fl.empty()) {
-    std::vector<double> qm, se, hh, gg;
+    std::vector<double> qm, se, hh, gg, rr, pm, pse;
     std::vector<int> ok, prior;
     for (int i : fl) {
       hh.push_back(hy->h[i]);
       gg.push_back(gq[i]);
+      rr.push_back(hy->rho[i]);
     }
     std::vector<std::vector<double>> xs, vs;
     if (c.warm_start) {
@@ -348,7 +434,7 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
       }
     }
     rc = c.warm_start ? solve_micro(hy, hh, gg, qm, se, ok, false, &prior, hy->plan_batch_equil, &xs, &vs)
-                      : solve_micro(hy, hh, gg, qm, se, ok, false);
+                      : solve_micro(hy, hh, gg, qm, se, ok, false, nullptr, -1, nullptr, nullptr, &rr, &pm, &pse);
     if (rc != HMD_OK) return rc;
     hy->st.md_calls += int64_t(fl.size());
     for (size_t k = 0; k < fl.size(); ++k) qv[fl[k]] = sgn[fl[k]] * qm[k];
@@ -358,9 +444,16 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
     for (size_t k = 0; k < fl.size(); ++k) {
       const int i = fl[k];
       if (!ok[k]) continue;
-      const double x[2] = {hy->h[i], gq[i]};
+      const double x[3] = {hy->h[i], press ? hy->rho[i] : gq[i], gq[i]};
       if (c.surrogate == 0) {
         rc = gp_append(hy->gp, x, qm[k], se[k]);
+        // Alg. 1: the run's pressure joins the pressure GP when its
+        // (h, rho) is not there yet
+        if (rc == HMD_OK && press && hy->p_db.insert({hy->h[i], hy->rho[i]}).second) {
+          const double xp[2] = {hy->h[i], hy->rho[i]};
+          rc = gp_append(hy->pgp, xp, pm[k], pse[k]);
+          hy->st.p_appends += 1;
+        }
       } else {
         rc = ens_append(hy->ens, x, qm[k]);
         hy->pending_refit += 1;
@@ -386,6 +479,7 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   // their own (audit_batch at a time, 0: at once), timed apart from the method
   for (int i : au) {
     hy->audit_h.push_back(hy->h[i]);
+    hy->audit_rho.push_back(hy->rho[i]);
     hy->audit_g.push_back(gq[i]);
     hy->audit_mean.push_back(mean[i]);
     hy->audit_sd.push_back(sd[i]);

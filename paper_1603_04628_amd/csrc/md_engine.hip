@@ -49,6 +49,7 @@ StepConst step_const(const hmd_batch* b, bool thermostat, bool energy) {
   K.thermo_on = thermostat ? 1 : 0;
   K.bins_on = 1;
   K.energy_on = energy ? 1 : 0;
+  K.press_on = P.pressure ? 1 : 0;
   return K;
 }
 
@@ -87,9 +88,11 @@ struct Launcher {
   int next_ev = 0;
   std::vector<std::array<int, 3>>* spans = nullptr;  // non-null: stamp mode
   int next_stamp = 0, last_stamp = -1;
+  const int* flag = nullptr;  // stamp mode: rebuild flags, recorded in each stamp's bit 63
+  StepRef R{nullptr, 0};      // stamp mode: the step being stamped
 
   void stamp() {
-    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, b->d_stamps + next_stamp);
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, b->d_stamps + next_stamp, flag, R);
     last_stamp = next_stamp++;
   }
   void begin(int k) {
@@ -183,23 +186,33 @@ void enqueue_sort(hmd_batch* b, Launcher& L, const StepConst& K, const int* flag
 }
 
 // Pair-path force kernels by variant index ((mode 2 + energy) 2 + uniform
-// unit) 2 + wall parameters equal to the fluid's.
-#define HMD_V(K, M, E, U, W) &K<M, E, U, W>
+// unit) 2 + wall parameters equal to the fluid's; sampling steps with the
+// wall pressure recorded take the PR table, indexed (energy 2 + uniform) 2 +
+// walls.
+#define HMD_V(K, M, E, U, W) &K<M, E, U, W, 0>
+#define HMD_VP(K, E, U, W) &K<1, E, U, W, 1>
+#define HMD_VARIANTS_PR(K)                                                                                  \
+  HMD_VP(K, 0, 0, 0), HMD_VP(K, 0, 0, 1), HMD_VP(K, 0, 1, 0), HMD_VP(K, 0, 1, 1), HMD_VP(K, 1, 0, 0),         \
+      HMD_VP(K, 1, 0, 1), HMD_VP(K, 1, 1, 0), HMD_VP(K, 1, 1, 1)
 #define HMD_VARIANTS(K)                                                                                   \
   HMD_V(K, 0, 0, 0, 0), HMD_V(K, 0, 0, 0, 1), HMD_V(K, 0, 0, 1, 0), HMD_V(K, 0, 0, 1, 1),               \
       HMD_V(K, 0, 1, 0, 0), HMD_V(K, 0, 1, 0, 1), HMD_V(K, 0, 1, 1, 0), HMD_V(K, 0, 1, 1, 1),           \
       HMD_V(K, 1, 0, 0, 0), HMD_V(K, 1, 0, 0, 1), HMD_V(K, 1, 0, 1, 0), HMD_V(K, 1, 0, 1, 1),           \
       HMD_V(K, 1, 1, 0, 0), HMD_V(K, 1, 1, 0, 1), HMD_V(K, 1, 1, 1, 0), HMD_V(K, 1, 1, 1, 1)
-decltype(&k_force_tiles<0, 0, 0, 0>) force_tiles_variant(int v) {
-  static const decltype(&k_force_tiles<0, 0, 0, 0>) tab[16] = {HMD_VARIANTS(k_force_tiles)};
-  return tab[v];
+decltype(&k_force_tiles<0, 0, 0, 0, 0>) force_tiles_variant(int v, bool pr) {
+  static const decltype(&k_force_tiles<0, 0, 0, 0, 0>) tab[16] = {HMD_VARIANTS(k_force_tiles)};
+  static const decltype(&k_force_tiles<0, 0, 0, 0, 0>) tab_pr[8] = {HMD_VARIANTS_PR(k_force_tiles)};
+  return pr ? tab_pr[v & 7] : tab[v];
 }
-decltype(&k_force_list<0, 0, 0, 0>) force_list_variant(int v) {
-  static const decltype(&k_force_list<0, 0, 0, 0>) tab[16] = {HMD_VARIANTS(k_force_list)};
-  return tab[v];
+decltype(&k_force_list<0, 0, 0, 0, 0>) force_list_variant(int v, bool pr) {
+  static const decltype(&k_force_list<0, 0, 0, 0, 0>) tab[16] = {HMD_VARIANTS(k_force_list)};
+  static const decltype(&k_force_list<0, 0, 0, 0, 0>) tab_pr[8] = {HMD_VARIANTS_PR(k_force_list)};
+  return pr ? tab_pr[v & 7] : tab[v];
 }
 #undef HMD_VARIANTS
+#undef HMD_VARIANTS_PR
 #undef HMD_V
+#undef HMD_VP
 
 void enqueue_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K, StepRef R) {
   const int nt = int(b->ntot), tpb = b->tpb, nb = blocks_for(nt, tpb);
@@ -215,12 +228,13 @@ void enqueue_force(hmd_batch* b, hipStream_t s, int mode, const StepConst& K, St
                          b->acc, b->d_dstate, R, K);
   } else {
     const int v = ((mode * 2 + (K.energy_on ? 1 : 0)) * 2 + (b->uniform ? 1 : 0)) * 2 + (b->walls_same ? 1 : 0);
+    const bool pr = mode == 1 && K.press_on;
     if (b->path == 2) {
-      hipLaunchKernelGGL(force_tiles_variant(v), dim3(b->ntiles), dim3(TILE_THREADS), 0, s, nt, b->list_ld,
+      hipLaunchKernelGGL(force_tiles_variant(v, pr), dim3(b->ntiles), dim3(TILE_THREADS), 0, s, nt, b->list_ld,
                          b->d_tilerec, b->d_sims, b->d_pfix, b->d_list,
                          b->d_nlist, b->d_f4, state_ref(b, 0), b->acc, b->d_dstate, R, K);
     } else {
-      hipLaunchKernelGGL(force_list_variant(v), dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims,
+      hipLaunchKernelGGL(force_list_variant(v, pr), dim3(nb), dim3(tpb), 0, s, nt, b->list_ld, b->d_sims,
                          b->d_atom_sim, b->d_pfix, b->d_list, b->d_nlist, b->d_f4, state_ref(b, 0), b->acc,
                          b->d_dstate, R, K);
     }
@@ -323,6 +337,8 @@ int get_graph(hmd_batch* b, int chunk, const StepConst& K, hipGraphExec_t* out) 
     const bool stamped = b->timing && (chunk - 1 - k) % every == 0 && (chunk - 1 - k) / every < kStampedSteps;
     L.spans = stamped ? &spans : nullptr;
     L.last_stamp = -1;
+    L.flag = b->path == 0 ? nullptr : b->d_flag;
+    L.R = StepRef{b->d_dstate, k};
     enqueue_step(b, L, K, StepRef{b->d_dstate, k});
   }
   if (b->timing) {  // calibration: an empty interval after the last stamp
@@ -445,7 +461,9 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   const double wmin = std::max(b->path >= 1 ? b->P.rc + b->skin : b->P.rc, b->cell_w);
   b->host.resize(n);
   for (int k = 0; k < n; ++k) {
-    int rc = build_system(b->P, jobs[k].h, jobs[k].g, jobs[k].seed, wmin, b->host[k], ctx->err);
+    hmd_md_params Pk = b->P;  // the job's own density, where it gives one
+    if (jobs[k].rho > 0.0) Pk.rho = jobs[k].rho;
+    int rc = build_system(Pk, jobs[k].h, jobs[k].g, jobs[k].seed, wmin, b->host[k], ctx->err);
     if (rc != HMD_OK) {
       delete b;
       return rc;
@@ -505,10 +523,17 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   // the pair-list build packs a position index into 24 bits
   if (b->path == 1 && b->ntot + b->nwall >= (int64_t(1) << 24)) b->path = 0;
   if (b->path == 2 && b->P.wall_layers < 1) b->path = 1;
+  if (b->P.pressure && b->path == 0) {
+    ctx->err = "md batch: the wall pressure needs a pair path (force_path 1 or 2)";
+    delete b;
+    return HMD_EINVAL;
+  }
   // pair-list capacity: neighbours within rc + skin at twice the fluid density
   // plus a wall half-space, rounded up to a multiple of 32
   const double rl = b->P.rc + b->skin;
-  const double est = 2.0 * std::max(b->P.rho, 0.8) * 4.18879 * rl * rl * rl +
+  double rho_max = b->P.rho;
+  for (int k = 0; k < n; ++k) rho_max = std::max(rho_max, jobs[k].rho);
+  const double est = 2.0 * std::max(rho_max, 0.8) * 4.18879 * rl * rl * rl +
                      2.0 * b->P.rho_wall * 2.0944 * rl * rl * rl;
   b->list_cap = b->path >= 1 ? int(32 * std::ceil(est / 32.0)) : 0;
   b->list_ld = int(64 * ((b->ntot + 63) / 64));
@@ -565,7 +590,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap, b->cell_rank.data(), 4 * b->ncell, hipMemcpyHostToDevice, ctx->stream));
   HMD_HIP(ctx, hipMemcpyAsync(b->d_cellmap + b->ncell, cell_lin.data(), 4 * b->ncell, hipMemcpyHostToDevice,
                               ctx->stream));
-  const int64_t nacc = 6 * int64_t(n) + int64_t(n) * b->nser + 3 * int64_t(n) + 2 * b->nbins;
+  const int64_t nacc = 6 * int64_t(n) + 2 * int64_t(n) * b->nser + 3 * int64_t(n) + 2 * b->nbins;
   if ((rc = dalloc(ctx, &b->d_accbuf, nacc)) || (rc = dalloc(ctx, &b->d_status, n)) ||
       (rc = dalloc(ctx, &b->acc.pairs, 2)) || (rc = dalloc(ctx, &b->d_sout, 4 * int64_t(n))))
     return fail(rc);
@@ -576,6 +601,7 @@ int batch_create(hmd_ctx* ctx, const hmd_md_job* jobs, int n, hmd_batch** out) {
   for (int p = 0; p < 2; ++p) { b->acc.pe[p] = q; q += n; }
   for (int p = 0; p < 2; ++p) { b->acc.ke[p] = q; q += n; }
   b->acc.blocks = q; q += int64_t(n) * b->nser;
+  b->acc.pblocks = q; q += int64_t(n) * b->nser;
   b->acc.tsum = q; q += 3 * int64_t(n);
   b->acc.binvx = q; q += b->nbins;
   b->acc.bincnt = q;
@@ -729,8 +755,17 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
       HMD_TRY(harvest(b, marks));
       L.next_ev = 2;
     }
-    hipGraphExec_t ex = nullptr;
+    // timing mode: one replay in kStampEvery is the stamped graph (timed
+    // by events, then its stamps read back); the others replay the plain
+    // graph with no host synchronisation, as outside timing mode
+    hipGraphExec_t ex = nullptr, ex_plain = nullptr;
     HMD_TRY(get_graph(b, graph_chunk, K, &ex));
+    if (b->timing) {
+      b->timing = false;
+      const int rc = get_graph(b, graph_chunk, K, &ex_plain);
+      b->timing = true;
+      HMD_TRY(rc);
+    }
     const int gkey = graph_chunk * 4 + (K.thermo_on ? 1 : 0) + (b->timing ? 2 : 0);
     if (b->timing && b->clock_khz <= 0.0) {
       int khz = 0;
@@ -742,8 +777,8 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
       b->clock_khz = double(khz);
     }
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, b->d_dstate, b->done);
-    while (steps - k >= graph_chunk) {
-      if (b->timing) {
+    for (int64_t rep = 0; steps - k >= graph_chunk; ++rep) {
+      if (b->timing && rep % kStampEvery == 0) {
         hipEvent_t e0 = b->ev[0], e1 = b->ev[1];
         HMD_HIP(ctx, hipEventRecord(e0, s));
         HMD_HIP(ctx, hipGraphLaunch(ex, s));
@@ -755,18 +790,26 @@ int batch_run(hmd_batch* b, int64_t steps, int graph_chunk, bool thermostat, dou
         b->graph_steps += graph_chunk;
         // the stamped steps of the replay: each kernel's time is the span
         // between its stamps less the gap of the empty interval at the end
+        // the list build's time is also kept apart for steps that rebuild
+        // and steps that do not (bit 63 of its opening stamp)
         const auto& spans = b->graph_spans[gkey];
         const int ns = b->graph_nstamps[gkey];
         unsigned long long st[kMaxStamps];
         HMD_HIP(ctx, hipMemcpy(st, b->d_stamps, sizeof(unsigned long long) * size_t(ns), hipMemcpyDeviceToHost));
-        const double gap = double(st[ns - 1] - st[ns - 2]);
+        constexpr unsigned long long kClock = ~(1ull << 63);
+        const double gap = double((st[ns - 1] & kClock) - (st[ns - 2] & kClock));
         for (const auto& sp : spans) {
-          const double ticks = std::max(0.0, double(st[sp[2]] - st[sp[1]]) - gap);
+          const double ticks = std::max(0.0, double((st[sp[2]] & kClock) - (st[sp[1]] & kClock)) - gap);
           b->kern_ms[sp[0]] += ticks / b->clock_khz;
           b->kern_n[sp[0]] += 1;
+          if (sp[0] == K_LIST) {
+            const int r = (st[sp[1]] >> 63) ? 1 : 0;
+            b->list_ms[r] += ticks / b->clock_khz;
+            b->list_n[r] += 1;
+          }
         }
       } else {
-        HMD_HIP(ctx, hipGraphLaunch(ex, s));
+        HMD_HIP(ctx, hipGraphLaunch(b->timing ? ex_plain : ex, s));
       }
       k += graph_chunk;
       b->done += graph_chunk;
@@ -788,10 +831,15 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
   // the sampling window is complete once every one of its n_sample steps ran
   const bool complete = b->n_sample > 0 && b->done - b->P.n_equil >= b->n_sample;
   hipStream_t s = ctx->stream;
+  std::vector<double> sout(4 * size_t(n)), pout(4 * size_t(n), 0.0), tsum(3 * size_t(n)), pe(n);
+  if (complete && b->P.pressure) {  // the pressure series first: d_sout is reused
+    series_stats_enqueue(s, b->acc.pblocks, n, b->nser, b->nser, 1.0 / double(b->ser_B), b->P.n_blocks,
+                         b->d_gam, b->d_sout);
+    HMD_HIP(ctx, hipMemcpyAsync(pout.data(), b->d_sout, 8 * pout.size(), hipMemcpyDeviceToHost, s));
+  }
   if (complete)
     series_stats_enqueue(s, b->acc.blocks, n, b->nser, b->nser, 1.0 / double(b->ser_B), b->P.n_blocks, b->d_gam,
                          b->d_sout);
-  std::vector<double> sout(4 * size_t(n)), tsum(3 * size_t(n)), pe(n);
   std::vector<int> status(n);
   int flags[4] = {0, 0, 0, 0};
   if (complete)
@@ -815,6 +863,10 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
       R.flux = so[0];
       R.flux_se = so[1];
       R.jflux = so[0] / D.h;
+      if (b->P.pressure) {
+        R.p = pout[4 * size_t(k)];
+        R.p_se = pout[4 * size_t(k) + 1];
+      }
       // temperatures are summed over every sampled step
       for (int a = 0; a < 3; ++a) R.T[a] = tsum[3 * k + a] / double(b->n_sample);
       // non-convergence (critical shear, Sec. 3.2): the two halves of the
@@ -834,16 +886,17 @@ int batch_results(hmd_batch* b, hmd_md_result* out) {
 
 // The sampled q' series of one system: nser entries (each the mean of ser_B
 // consecutive sampled steps), as far as sampling has reached.
-int batch_series(hmd_batch* b, int sim, double* q, int64_t* n) {
+int batch_series(hmd_batch* b, int sim, double* q, int64_t* n, int which) {
   hmd_ctx* ctx = b->ctx;
-  if (sim < 0 || sim >= b->S || b->n_sample <= 0) {
-    ctx->err = "md series: need a valid system of a batch with n_sample > 0";
+  if (sim < 0 || sim >= b->S || b->n_sample <= 0 || which < 0 || which > 1 || (which == 1 && !b->P.pressure)) {
+    ctx->err = "md series: need a valid system of a batch with n_sample > 0 (pressure series: pressure on)";
     return HMD_EINVAL;
   }
   if (n) *n = b->nser;
   if (!q) return HMD_OK;
   HMD_HIP(ctx, hipSetDevice(ctx->device));
-  HMD_HIP(ctx, hipMemcpy(q, b->acc.blocks + int64_t(sim) * b->nser, 8 * size_t(b->nser), hipMemcpyDeviceToHost));
+  const double* src = which ? b->acc.pblocks : b->acc.blocks;
+  HMD_HIP(ctx, hipMemcpy(q, src + int64_t(sim) * b->nser, 8 * size_t(b->nser), hipMemcpyDeviceToHost));
   for (int64_t k = 0; k < b->nser; ++k) q[k] /= double(b->ser_B);
   return HMD_OK;
 }

@@ -46,7 +46,7 @@ __global__ void k_force_cell(int ntot, const SimDev* sims, const uint16_t* atom_
                              const uint32_t* start, const uint32_t* ncount, const float4* wpos4,
                              const uint32_t* wstart, const uint32_t* wcount, float4* f4, StateRef st, Acc acc,
                              int64_t* dstate, StepRef R, StepConst K);
-template <int MODE, int ENERGY, int UNI, int WS>
+template <int MODE, int ENERGY, int UNI, int WS, int PR>
 __global__ void k_force_list(int ntot, int ld, const SimDev* sims, const uint16_t* atom_sim, const int4* pfix,
                              const uint32_t* list, const uint32_t* nlist, float4* f4, StateRef st, Acc acc,
                              int64_t* dstate, StepRef R, StepConst K);
@@ -67,11 +67,11 @@ __global__ void k_build_tiles(int ntot, int ld, int cap, const int4* tiles, cons
                               uint32_t* list, uint32_t* nlist, uint32_t* tilerec, StateRef from, StateRef to,
                               const int* tag_from, int* tag_to, int* overflow, const int* flag, StepRef R,
                               float rl2, int global_out);
-template <int MODE, int ENERGY, int UNI, int WS>
+template <int MODE, int ENERGY, int UNI, int WS, int PR>
 __global__ void k_force_tiles(int ntot, int ld, const uint32_t* tilerec, const SimDev* sims, const int4* pfix,
                               const uint32_t* list, const uint32_t* nlist, float4* f4, StateRef st, Acc acc,
                               int64_t* dstate, StepRef R, StepConst K);
-__global__ void k_stamp(unsigned long long* slot);
+__global__ void k_stamp(unsigned long long* slot, const int* flag, StepRef R);
 __global__ void k_set_i64(int64_t* p, int64_t v);
 __global__ void k_add_i64(int64_t* p, int64_t v);
 __global__ void k_set_i32(int* p, int v);

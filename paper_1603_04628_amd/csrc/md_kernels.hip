@@ -519,7 +519,7 @@ __device__ __forceinline__ unsigned long long tbin_word(double vx) {
 // component, kinetic and potential energy, then the flux and the three
 // temperature components of a sampled step.
 struct TileSums {
-  double v[7];
+  double v[8];
 };
 
 template <int MODE, int TB = 0>
@@ -529,7 +529,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
                                              double* lds_vx, double* lds_cnt, int* lds_base,
                                              unsigned long long* tbin = nullptr,
                                              const double3* vpre = nullptr, TileSums* ts = nullptr,
-                                             const double* ypre = nullptr, int tb_sampled = 0) {
+                                             const double* ypre = nullptr, int tb_sampled = 0, float pw = 0.0f) {
   const int p = int(nstep & 1);
   double vc2 = 0.0, ke = 0.0, pes = valid ? double(pe) : 0.0;
   // scalars, not an array indexed by the run-time axis (that would live in
@@ -586,11 +586,15 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
   if (K.axis == 0) q1 = (1.0 - a) * q1 + a * K.T0;
   else if (K.axis == 1) q2 = (1.0 - a) * q2 + a * K.T0;
   else q3 = (1.0 - a) * q3 + a * K.T0;
+  // the wall normal pressure of the step (with pressure on): the atom's
+  // share of (F_lo,y - F_hi,y) / 2, per unit area when added
+  double q4 = valid ? 0.5 * double(pw) : 0.0;
   if (!valid) q0 = q1 = q2 = q3 = 0.0;
   if (TB) {
-    ts->v[3] += q0; ts->v[4] += q1; ts->v[5] += q2; ts->v[6] += q3;
+    ts->v[3] += q0; ts->v[4] += q1; ts->v[5] += q2; ts->v[6] += q3; ts->v[7] += q4;
   } else if (wave_uniform(valid ? s : -1)) {
     q0 = wave_sum(q0); q1 = wave_sum(q1); q2 = wave_sum(q2); q3 = wave_sum(q3);
+    if (K.press_on) q4 = wave_sum(q4);
     const int sw = TB ? s : __shfl(s, 0);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
       const SimDev& Dw = sims[sw];
@@ -598,6 +602,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
       atomicAdd(&acc.tsum[3 * sw + 0], q1 * Dw.inv_nf);
       atomicAdd(&acc.tsum[3 * sw + 1], q2 * Dw.inv_nf);
       atomicAdd(&acc.tsum[3 * sw + 2], q3 * Dw.inv_nf);
+      if (K.press_on) atomicAdd(&acc.pblocks[int64_t(sw) * K.nb + b], q4 * Dw.inv_area);
     }
   } else if (valid) {
     const SimDev& D = sims[s];
@@ -605,6 +610,7 @@ __device__ __forceinline__ void finish_force(int i, bool valid, int s, const Sim
     atomicAdd(&acc.tsum[3 * s + 0], q1 * D.inv_nf);
     atomicAdd(&acc.tsum[3 * s + 1], q2 * D.inv_nf);
     atomicAdd(&acc.tsum[3 * s + 2], q3 * D.inv_nf);
+    if (K.press_on) atomicAdd(&acc.pblocks[int64_t(s) * K.nb + b], q4 * D.inv_area);
   }
   if (!K.bins_on) return;
   // wall-normal profile: aggregate in LDS relative to the block's lowest bin
@@ -768,10 +774,14 @@ __device__ __forceinline__ PairConst pair_const(const StepConst& K, const SimDev
   return c;
 }
 
-template <int ENERGY, int UNI, int WS>
+// PR: also the wall normal pressure term, f_r |dy| over wall pairs (every
+// lower-wall atom lies below every fluid atom and every upper-wall atom above,
+// so |dy| carries each wall's sign: the sum over wall pairs is
+// F_lo,y - F_hi,y, the normal forces of the two walls on the fluid).
+template <int ENERGY, int UNI, int WS, int PR = 0>
 __device__ __forceinline__ void lj_term(int dx, int dy, int dz, bool wall_atom, const PairConst& c,
                                         const SimDev& D, float& fx, float& fy, float& fz, float& pe,
-                                        uint32_t& nff, uint32_t& nwf) {
+                                        uint32_t& nff, uint32_t& nwf, float& pw) {
   // WS: wall-fluid parameters equal the fluid's, so forces need no wall test
   const bool wall = (WS && !ENERGY) ? false : wall_atom;
   const float ax = UNI ? float(dx) : float(dx) * D.unit_x;
@@ -787,6 +797,7 @@ __device__ __forceinline__ void lj_term(int dx, int dy, int dz, bool wall_atom, 
   const float eps48 = wall ? 2.0f * c.eps24_wf : 48.0f;
   const float fr = in ? s6 * (eps48 * s6 - eps24) * ri2 : 0.0f;
   fx += fr * ax; fy += fr * ay; fz += fr * az;
+  if (PR) pw += (wall_atom ? fr : 0.0f) * fabsf(ay);
   if (ENERGY) {
     const float u = wall ? c.eps4_wf * s6 * (s6 - 1.0f) - c.ush_wf : 0.5f * (4.0f * s6 * (s6 - 1.0f) - c.ush_ff);
     pe += in ? u : 0.0f;
@@ -800,7 +811,7 @@ __device__ __forceinline__ void lj_term(int dx, int dy, int dz, bool wall_atom, 
 // slot's Verlet list (entries >= ntot are wall atoms), FP32 from fixed-point
 // separations.
 // ---------------------------------------------------------------------------
-template <int MODE, int ENERGY, int UNI, int WS>
+template <int MODE, int ENERGY, int UNI, int WS, int PR>
 __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimDev* __restrict__ sims,
                                                     const uint16_t* __restrict__ atom_sim,
                                                     const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
@@ -813,7 +824,7 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
   const int i = xcd_block() * blockDim.x + threadIdx.x;
   const bool valid = i < ntot;
   const int s = valid ? int(atom_sim[i]) : 0;
-  float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
+  float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f, pw = 0.f;
   uint32_t nff = 0, nwf = 0;
   if (valid) {
     const SimDev& D = sims[s];
@@ -822,9 +833,9 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
     const uint4* grp = reinterpret_cast<const uint4*>(list) + i;  // group g at grp[g * ld]
     const PairConst pc = pair_const<UNI>(K, D);
     auto pair = [&](uint32_t j, const int4& o) {
-      lj_term<ENERGY, UNI, WS>(int(uint32_t(me.x) - uint32_t(o.x)), int(uint32_t(me.y) - uint32_t(o.y)),
-                           int(uint32_t(me.z) - uint32_t(o.z)), j >= uint32_t(ntot), pc, D, fx, fy, fz, pe, nff,
-                           nwf);
+      lj_term<ENERGY, UNI, WS, PR>(int(uint32_t(me.x) - uint32_t(o.x)), int(uint32_t(me.y) - uint32_t(o.y)),
+                                   int(uint32_t(me.z) - uint32_t(o.z)), j >= uint32_t(ntot), pc, D, fx, fy, fz,
+                                   pe, nff, nwf, pw);
     };
     // One coalesced 16-byte load brings four entries.  The next group's load
     // is issued before this group's arithmetic so that its latency overlaps
@@ -846,7 +857,7 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
       if (rest > 1) pair(jj.y, pfix[jj.y]);
       if (rest > 2) pair(jj.z, pfix[jj.z]);
     }
-    if (UNI) { fx *= D.inv_u; fy *= D.inv_u; fz *= D.inv_u; }
+    if (UNI) { fx *= D.inv_u; fy *= D.inv_u; fz *= D.inv_u; pw *= D.inv_u; }
     f4[i] = make_float4(fx, fy, fz, pe);
   }
   if (ENERGY) {
@@ -857,7 +868,7 @@ __global__ __launch_bounds__(256) void k_force_list(int ntot, int ld, const SimD
     }
   }
   finish_force<MODE>(i, valid, s, sims, fx, fy, fz, pe, st, acc, dstate, step_n(R) + 1, K, lds_vx, lds_cnt,
-                     &lds_base);
+                     &lds_base, nullptr, nullptr, nullptr, nullptr, 0, PR ? pw : 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -1289,7 +1300,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_build_tiles(
 // Forces of a tile's atoms from their lists, neighbour positions read from
 // LDS (or gathered, for a tile built with 32-bit indices), then the second
 // half-kick and the sample of the step.
-template <int MODE, int ENERGY, int UNI, int WS>
+template <int MODE, int ENERGY, int UNI, int WS, int PR>
 __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     int ntot, int ld, const uint32_t* __restrict__ tilerec, const SimDev* __restrict__ sims,
     const int4* __restrict__ pfix, const uint32_t* __restrict__ list,
@@ -1339,7 +1350,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
   const uint32_t first_wall = local ? T.off[6] : uint32_t(ntot);  // walls come after the fluid ranges
   TileSums sums;
 #pragma unroll
-  for (int q = 0; q < 7; ++q) sums.v[q] = 0.0;
+  for (int q = 0; q < 8; ++q) sums.v[q] = 0.0;
   for (uint32_t base = 0; base < n_home; base += blockDim.x) {
     const uint32_t i = T.home0 + base + threadIdx.x;
     const bool valid = base + threadIdx.x < n_home;
@@ -1348,15 +1359,15 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     const uint4 g0 = g_nx;
     const double3 v = v_nx;
     if (base + blockDim.x < n_home) fetch(base + blockDim.x);
-    float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f;
+    float fx = 0.f, fy = 0.f, fz = 0.f, pe = 0.f, pw = 0.f;
     uint32_t nff = 0, nwf = 0;
     if (valid) {
       const uint4* grp = reinterpret_cast<const uint4*>(list) + i;
       const PairConst pc = pair_const<UNI>(K, D);
       auto pair = [&](uint32_t j, int ox, int oy, int oz) {
-        lj_term<ENERGY, UNI, WS>(int(uint32_t(me.x) - uint32_t(ox)), int(uint32_t(me.y) - uint32_t(oy)),
-                             int(uint32_t(me.z) - uint32_t(oz)), j >= first_wall, pc, D, fx, fy, fz, pe, nff,
-                             nwf);
+        lj_term<ENERGY, UNI, WS, PR>(int(uint32_t(me.x) - uint32_t(ox)), int(uint32_t(me.y) - uint32_t(oy)),
+                                     int(uint32_t(me.z) - uint32_t(oz)), j >= first_wall, pc, D, fx, fy, fz, pe,
+                                     nff, nwf, pw);
       };
       if (local) {
         // eight 16-bit LDS indices per 16-byte group; the next group is
@@ -1404,7 +1415,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
           if (rest > 2) { const int4 o2 = pfix[jj.z]; pair(jj.z, o2.x, o2.y, o2.z); }
         }
       }
-      if (UNI) { fx *= D.inv_u; fy *= D.inv_u; fz *= D.inv_u; }
+      if (UNI) { fx *= D.inv_u; fy *= D.inv_u; fz *= D.inv_u; pw *= D.inv_u; }
       f4[i] = make_float4(fx, fy, fz, pe);
     }
     if (ENERGY) {
@@ -1418,26 +1429,27 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
     // one fixed-point unit of the FP64 one; no memory read)
     const double yb = double(uint32_t(me.y)) * bin_c1 + bin_c0;
     finish_force<MODE, 1>(int(i), valid, s, sims, fx, fy, fz, pe, st, acc, dstate, nstep, K, nullptr, nullptr,
-                          nullptr, tbin, &v, &sums, &yb, sampled ? 1 : 0);
+                          nullptr, tbin, &v, &sums, &yb, sampled ? 1 : 0, PR ? pw : 0.0f);
   }
   // one atomic per sum and tile (per wave and pass they queue on a few
   // addresses per system)
   if (MODE == 1 || K.energy_on) {
-    __shared__ double red[TILE_TPB / WAVE][7];
+    __shared__ double red[TILE_TPB / WAVE][8];
     const int64_t ns = nstep - K.n_equil - 1;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    // sums: 0 vc2, 1 ke, 2 pe, 3 q', 4-6 T components, 7 wall pressure
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      const bool need = q == 0 ? MODE == 1 : (q < 3 ? K.energy_on != 0 : sampled);
+    for (int q = 0; q < 8; ++q) {
+      const bool need = q == 0 ? MODE == 1 : (q < 3 ? K.energy_on != 0 : (q < 7 ? sampled : PR && sampled));
       if (need) {
         const double w = wave_sum(sums.v[q]);
         if (lane == 0) red[wave][q] = w;
       }
     }
     __syncthreads();
-    if (threadIdx.x < 7) {
+    if (threadIdx.x < 8) {
       const int q = threadIdx.x;
-      const bool need = q == 0 ? MODE == 1 : (q < 3 ? K.energy_on != 0 : sampled);
+      const bool need = q == 0 ? MODE == 1 : (q < 3 ? K.energy_on != 0 : (q < 7 ? sampled : PR && sampled));
       if (need) {
         double tot = 0.0;
         for (int w = 0; w < int(blockDim.x / WAVE); ++w) tot += red[w][q];
@@ -1447,6 +1459,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
         else if (q == 1) dst = (p ? acc.ke[1] : acc.ke[0]) + s;
         else if (q == 2) dst = (p ? acc.pe[1] : acc.pe[0]) + s;
         else if (q == 3) { dst = acc.blocks + int64_t(s) * K.nb + (ns - K.r) / K.B; tot *= D.inv_area; }
+        else if (q == 7) { dst = acc.pblocks + int64_t(s) * K.nb + (ns - K.r) / K.B; tot *= D.inv_area; }
         else { dst = acc.tsum + 3 * s + (q - 4); tot *= D.inv_nf; }
         atomicAdd(dst, tot);
       }
@@ -1467,8 +1480,11 @@ __global__ __launch_bounds__(TILE_TPB) void k_force_tiles(
 
 // One timestamp of the device's constant-rate wall clock (timed graph
 // replays bracket each kernel of a step with these).
-__global__ void k_stamp(unsigned long long* slot) {
-  if (threadIdx.x == 0) *slot = (unsigned long long)wall_clock64();
+// Device wall clock for per-kernel timing inside graphs; bit 63 carries
+// whether the step being stamped rebuilds its pair lists (flag non-null).
+__global__ void k_stamp(unsigned long long* slot, const int* flag, StepRef R) {
+  if (threadIdx.x == 0)
+    *slot = (unsigned long long)wall_clock64() | ((flag && rebuild_needed(flag, R)) ? (1ull << 63) : 0ull);
 }
 
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
@@ -1504,20 +1520,25 @@ template __global__ void k_build_tiles<1>(int, int, int, const int4*, const SimD
                                           const uint32_t*, uint32_t*, uint32_t*, uint32_t*, StateRef, StateRef,
                                           const int*, int*, int*, const int*, StepRef, float, int);
 
-#define HMD_FORCE_TILES(M, E, U, W)                                                                    \
-  template __global__ void k_force_tiles<M, E, U, W>(int, int, const uint32_t*, const SimDev*,                \
-                                                     const int4*, const uint32_t*,                             \
-                                                     const uint32_t*, float4*, StateRef, Acc, int64_t*,        \
-                                                     StepRef, StepConst);
-#define HMD_FORCE_LIST(M, E, U, W)                                                                     \
-  template __global__ void k_force_list<M, E, U, W>(int, int, const SimDev*, const uint16_t*, const int4*,    \
-                                                    const uint32_t*, const uint32_t*, float4*, StateRef, Acc,  \
-                                                    int64_t*, StepRef, StepConst);
-#define HMD_FORCE_BOTH(M, E, U, W) HMD_FORCE_TILES(M, E, U, W) HMD_FORCE_LIST(M, E, U, W)
+#define HMD_FORCE_TILES(M, E, U, W, PR)                                                                \
+  template __global__ void k_force_tiles<M, E, U, W, PR>(int, int, const uint32_t*, const SimDev*,            \
+                                                         const int4*, const uint32_t*,                         \
+                                                         const uint32_t*, float4*, StateRef, Acc, int64_t*,    \
+                                                         StepRef, StepConst);
+#define HMD_FORCE_LIST(M, E, U, W, PR)                                                                 \
+  template __global__ void k_force_list<M, E, U, W, PR>(int, int, const SimDev*, const uint16_t*, const int4*, \
+                                                        const uint32_t*, const uint32_t*, float4*, StateRef, Acc, \
+                                                        int64_t*, StepRef, StepConst);
+#define HMD_FORCE_BOTH(M, E, U, W) HMD_FORCE_TILES(M, E, U, W, 0) HMD_FORCE_LIST(M, E, U, W, 0)
 HMD_FORCE_BOTH(0, 0, 0, 0) HMD_FORCE_BOTH(0, 0, 0, 1) HMD_FORCE_BOTH(0, 0, 1, 0) HMD_FORCE_BOTH(0, 0, 1, 1)
 HMD_FORCE_BOTH(0, 1, 0, 0) HMD_FORCE_BOTH(0, 1, 0, 1) HMD_FORCE_BOTH(0, 1, 1, 0) HMD_FORCE_BOTH(0, 1, 1, 1)
 HMD_FORCE_BOTH(1, 0, 0, 0) HMD_FORCE_BOTH(1, 0, 0, 1) HMD_FORCE_BOTH(1, 0, 1, 0) HMD_FORCE_BOTH(1, 0, 1, 1)
 HMD_FORCE_BOTH(1, 1, 0, 0) HMD_FORCE_BOTH(1, 1, 0, 1) HMD_FORCE_BOTH(1, 1, 1, 0) HMD_FORCE_BOTH(1, 1, 1, 1)
+// sampling steps with the wall pressure recorded
+#define HMD_FORCE_PR(E, U, W) HMD_FORCE_TILES(1, E, U, W, 1) HMD_FORCE_LIST(1, E, U, W, 1)
+HMD_FORCE_PR(0, 0, 0) HMD_FORCE_PR(0, 0, 1) HMD_FORCE_PR(0, 1, 0) HMD_FORCE_PR(0, 1, 1)
+HMD_FORCE_PR(1, 0, 0) HMD_FORCE_PR(1, 0, 1) HMD_FORCE_PR(1, 1, 0) HMD_FORCE_PR(1, 1, 1)
+#undef HMD_FORCE_PR
 #undef HMD_FORCE_BOTH
 #undef HMD_FORCE_TILES
 #undef HMD_FORCE_LIST

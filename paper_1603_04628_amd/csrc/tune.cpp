@@ -169,6 +169,7 @@ int md_autotune(hmd_ctx* ctx, const hmd_md_job* jobs, int n, int probe_steps, do
     for (int path : {2, 1, 0})
       for (int tpb : {256, 128}) {
         if (path == 2 && tpb == 128) continue;
+        if (path == 0 && saved.pressure) continue;  // the wall pressure needs a pair path
         Config c = best;
         c.path = path;
         c.tpb = tpb;

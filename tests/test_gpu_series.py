@@ -154,3 +154,59 @@ def test_long_window_groups_steps():
     assert r["status"] in (0, -5)
     assert r["flux"] == pytest.approx(q.mean(), rel=1e-12)
     assert r["flux_se"] == pytest.approx(ostats.geyer(q)[1], rel=1e-9)
+
+
+@pytest.mark.parametrize("path", [1, 2, 3])
+def test_pressure_series_from_identical_state(path):
+    # Alg. 1's pressure output of a run: per sampled step the normal force of
+    # the walls on the fluid per unit area, (F_lo,y - F_hi,y) / (2 Lx Lz).
+    # From one equilibrated state both sides step 40 times; each step's
+    # pressure agrees to FP32-force rounding (the first step exactly so up to
+    # it), at a density other than the context's (the job's own)
+    rho = 0.72
+    pre = omd.System(7.0, 0.03, 9, omd.Params(rho=rho, **SMALL_L))
+    pre.run(300)
+    x, v = pre.get_state()
+    n = 40
+    params = dict(n_equil=0, **SMALL_L)
+    ora = omd.System(7.0, 0.03, 9, omd.Params(rho=rho, cell_w=2.8, **params))
+    ora.set_state(x, v)
+    ora.run(n)
+    po = ora.pressure_series()
+    ctx = hmd.Context(hmd.Params(force_path=path, skin=0.3, pressure=1, **params))
+    b = hmd.Batch(ctx, [(7.0, 0.03, 9, n, rho)])
+    assert b.n_fluid(0) == ora.n_fluid
+    b.set_state(0, x, v)
+    b.run(n, graph_chunk=20)
+    pg = b.pressure_series(0)
+    assert len(pg) == n == len(po)
+    assert np.abs(pg - po).max() <= 1e-4 * np.abs(po).mean(), np.abs(pg - po).max()
+    assert abs(pg[0] - po[0]) <= 1e-5 * abs(po[0])
+    r = b.results()[0]
+    m, se = ostats.geyer(pg)
+    assert r["p"] == pytest.approx(m, rel=1e-12) and r["p_se"] == pytest.approx(se, rel=1e-9)
+    # the flux of the same run is unchanged by recording the pressure
+    ctx0 = hmd.Context(hmd.Params(force_path=path, skin=0.3, **params))
+    b0 = hmd.Batch(ctx0, [(7.0, 0.03, 9, n, rho)])
+    b0.set_state(0, x, v)
+    b0.run(n, graph_chunk=20)
+    assert np.abs(b0.series(0) - b.series(0)).max() <= 1e-9 * np.abs(b.series(0)).max()
+    assert b0.results()[0]["p"] == 0.0
+    with pytest.raises(hmd.HmdError):
+        b0.pressure_series(0)
+
+
+def test_per_job_density_and_pressure_rejected_on_the_cell_path():
+    # jobs at their own densities start from the oracle's lattice at that
+    # density; the cell path does not record the wall pressure
+    ctx = hmd.Context(hmd.Params(n_equil=0, **SMALL_L))
+    jobs = [(6.0, 0.01, 3, 10, 0.65), (6.0, 0.01, 3, 10, 0.9), (6.0, 0.01, 3, 10)]
+    b = hmd.Batch(ctx, jobs)
+    for k, rho in enumerate((0.65, 0.9, 0.8)):
+        o = omd.System(6.0, 0.01, 3, omd.Params(rho=rho, **SMALL_L))
+        assert b.n_fluid(k) == o.n_fluid
+        x, v = b.get_state(k)
+        xo, vo = o.get_state()
+        assert np.array_equal(x, xo) and np.abs(v - vo).max() <= 1e-14
+    with pytest.raises(hmd.HmdError):
+        hmd.Batch(hmd.Context(hmd.Params(force_path=0, pressure=1, **SMALL_L)), jobs[:1])
