@@ -36,10 +36,10 @@ FLOP_PER_PAIR = 21
 N_EQUIL, N_SAMPLE = 10000, 20000
 PATH_NAMES = {0: "cell list", 1: "pair list", 2: "pair list, LDS-staged tiles"}
 # force kernel of a sampling step on this workload (square box, wall parameters = fluid)
-FORCE_KERNELS = {0: "k_force_cell<1>", 1: "k_force_list<1, 0, 1, 1>", 2: "k_force_tiles<1, 0, 1, 1>"}
+FORCE_KERNELS = {0: "k_force_cell<1>", 1: "k_force_list<1, 0, 1, 1, 0>", 2: "k_force_tiles<1, 0, 1, 1, 0>"}
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "force_list_batch64_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "force_tiles_batch64_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1603_04628_amd", "csrc", "md_kernels.hip")
 
 
@@ -371,6 +371,123 @@ def hybrid_bench(args, hmd, first_results):
     return out
 
 
+# The paper's benchmark channel with its full input set (Sec. 2.2; Alg. 1
+# with both GPs): 40 sections on a periodic ring (Eqs. subsEq, heightEq:
+# h from 6 to 10 sigma), driven by the external force of Eq. extForcing1
+# (amplitude 0.02 per unit mass, period 400 macro steps).  The pressure GP
+# p(h, rho) comes from pre-simulations at rest over a density sweep of every
+# section height; the flux GP over (h, rho, g) from batched runs at the
+# march's protocol.
+EG = dict(n_sections=40, h0=10.0, amp=0.2, L=400.0, geometry=1, f_amp=0.02, f_period=400.0, rho_ref=0.8)
+EG_RHOS = (0.70, 0.75, 0.80, 0.85, 0.90, 0.95)
+EG_PRE = (2000, 4000)     # pre-simulation equilibration and sampling steps
+EG_TRAIN = 128            # flux database runs
+EG_STEPS = 300            # macro steps
+
+
+def eos_gp_bench(args, hmd):
+    """The hybrid solve with the pressure GP and the 3-input flux GP on the
+    paper's periodic channel: pre-simulations, flux database, march, and the
+    all-MD price of the same march."""
+    from paper_1603_04628_amd import binding as B
+    from paper_1603_04628_amd import hybrid_binding as HB
+    box = workloads.batch_box()
+    n, L, h0, a = EG["n_sections"], EG["L"], EG["h0"], EG["amp"] * EG["h0"]
+    heights = a * (np.cos(2.0 * np.pi * (np.arange(n) * L / n) / L) - 1.0) + h0  # the march's sections
+    hu = np.unique(np.round(heights, 9))  # mirrored sections agree to the last bits: one run per height
+    ctx = hmd.Context(hmd.Params(n_equil=EG_PRE[0], pressure=1, **box))
+    t0 = time.perf_counter()
+    pre = [(h, 0.0, 200000 + k, EG_PRE[1], r) for k, (h, r) in enumerate((h, r) for h in hu for r in EG_RHOS)]
+    rp = hmd.md_flux_batch(ctx, pre)
+    t_pre = time.perf_counter() - t0
+    okp = [k for k, r in enumerate(rp) if r["status"] == 0]
+    Xp = np.array([[pre[k][0], pre[k][4]] for k in okp])
+    pp = np.array([rp[k]["p"] for k in okp])
+    pse = np.array([rp[k]["p_se"] for k in okp])
+    pre_atom_steps = float(sum(rp[k]["n_fluid"] for k in okp)) * sum(EG_PRE)
+    log(f"eos-gp: {len(okp)} pre-simulations in {t_pre:.1f} s; p from {pp.min():.3f} to {pp.max():.3f}")
+    # flux database at the march's protocol, (h, rho, g) drawn over the ring's
+    # heights, densities around the reference and forces up to 0.045
+    ctx.set_params(hmd.Params(n_equil=N_EQUIL, pressure=1, **box))
+    jobs = workloads.density_jobs(EG_TRAIN, 0, float(hu.min()), float(hu.max()), 0.72, 0.92, 0.001, 0.045)
+    t0 = time.perf_counter()
+    rq = hmd.md_flux_batch(ctx, [(j.h, j.g, j.seed, N_SAMPLE, j.rho) for j in jobs])
+    t_train = time.perf_counter() - t0
+    okq = [k for k, r in enumerate(rq) if r["status"] == 0]
+    X = np.array([[jobs[k].h, jobs[k].rho, jobs[k].g] for k in okq])
+    y = np.array([rq[k]["flux"] for k in okq])
+    se = np.array([rq[k]["flux_se"] for k in okq])
+    train_atom_steps = float(sum(rq[k]["n_fluid"] for k in okq)) * (N_EQUIL + N_SAMPLE)
+    md_rate = train_atom_steps / t_train
+    # hyperparameters by the evidence (Sec. 2.3), as for the 2-input GP
+    hp_p = B.gp_hyper(ranges=(float(np.ptp(hu)), 0.25))
+    hp_q = B.gp_hyper(ranges=(float(np.ptp(hu)), 0.2, 0.044))
+    hyp = {}
+    for name, Xd, yd, sd, hp in (("p", Xp, pp, pse, hp_p), ("q", X, y, se, hp_q)):
+        g = B.GP(ctx, Xd, yd, sd, hp)
+        lml = g.optimize(("sigma_f", "ell"))
+        hv = g.hyper()
+        g.close()
+        hyp[name] = {"sigma_f": hv["sigma_f"], "ell": hv["ell"], "lml": lml}
+    hp_p = B.gp_hyper(ranges=(float(np.ptp(hu)), 0.25), sigma_f=hyp["p"]["sigma_f"], ell=hyp["p"]["ell"])
+    hp_q = B.gp_hyper(ranges=(float(np.ptp(hu)), 0.2, 0.044), sigma_f=hyp["q"]["sigma_f"], ell=hyp["q"]["ell"])
+    hctx = hmd.Context(hmd.Params(n_equil=N_EQUIL, **box))
+    pg = B.GP(hctx, Xp, pp, pse, hp_p)
+    qg = B.GP(hctx, X, y, se, hp_q)
+    # macro step from the explicit diffusion limit, D = (dq/dg)(dp/drho) / (rho h)
+    dg, dr = 1e-3, 1e-3
+    qa, _ = qg.predict(np.column_stack([heights, np.full(n, 0.8), np.full(n, 0.02 + dg)]))
+    qb, _ = qg.predict(np.column_stack([heights, np.full(n, 0.8), np.full(n, 0.02 - dg)]))
+    pa, _ = pg.predict(np.column_stack([heights, np.full(n, 0.8 + dr)]))
+    pb, _ = pg.predict(np.column_stack([heights, np.full(n, 0.8 - dr)]))
+    D = np.abs((qa - qb) / (2 * dg)) * np.abs((pa - pb) / (2 * dr)) / (0.8 * heights)
+    dt = 0.4 * (L / n) ** 2 / float(D.max())
+    cfg = HB.hybrid_cfg(surrogate=0, eos=1, tau_rel=0.05, tau_abs=float(np.median(se)), md_sample=N_SAMPLE,
+                        dt_macro=dt, audit_every=0, **EG)
+    hy = HB.Hybrid(hctx, cfg, gp=qg, pgp=pg)
+    t0 = time.perf_counter()
+    for _ in range(EG_STEPS):
+        st = hy.step()
+        if time.perf_counter() - t0 > args.hybrid_budget:
+            break
+    wall = time.perf_counter() - t0
+    r = hy.get()
+    p, p_sd = hy.pressure()
+    # all-MD: every section every step at the march's protocol, atoms at each
+    # section's height from the pre-simulations at the reference density
+    n_at = {round(pre[k][0], 9): rp[k]["n_fluid"] for k in okp if pre[k][4] == 0.80}
+    per_step = float(sum(n_at.get(round(h, 9), 0) for h in heights)) * (N_EQUIL + N_SAMPLE)
+    done = st["steps"]
+    method_s = wall
+    all_md_s = done * per_step / md_rate
+    out = {"macro": dict(EG, dt_macro=dt, steps_done=done, tau_rel=0.05, tau_abs=float(np.median(se)),
+                         md_protocol=f"{N_EQUIL} + {N_SAMPLE} steps", eos="pressure GP p(h, rho)",
+                         flux_inputs="(h, rho, g)"),
+           "pre_simulations": {"runs": len(okp), "densities": list(EG_RHOS), "heights": len(hu),
+                               "protocol": f"{EG_PRE[0]} + {EG_PRE[1]} steps at rest", "wall_s": t_pre,
+                               "atom_steps": pre_atom_steps, "p_range": [float(pp.min()), float(pp.max())],
+                               "p_se_median": float(np.median(pse))},
+           "flux_database": {"runs": len(okq), "wall_s": t_train, "md_atom_steps_per_s": md_rate},
+           "hyperparameters": hyp,
+           "march": {"wall_s": method_s, "md_calls": st["md_calls"], "md_failed": st["md_failed"],
+                     "p_appends": st["p_appends"], "md_wall_s": st["md_wall_s"],
+                     "surrogate_wall_s": st["surrogate_wall_s"],
+                     "rho_range": [float(r["rho"].min()), float(r["rho"].max())],
+                     "g_range": [float(r["g"].min()), float(r["g"].max())],
+                     "p_range": [float(p.min()), float(p.max())], "p_std_max": float(p_sd.max())},
+           "all_md_estimated_s": all_md_s,
+           "speedup_vs_all_md": all_md_s / method_s,
+           "speedup_vs_all_md_incl_presim_and_database": all_md_s / (
+               method_s + (t_pre + t_train) * done / EG_STEPS)}
+    log(f"eos-gp: {done} steps in {method_s:.1f} s, md_calls {st['md_calls']}, p appends {st['p_appends']}, "
+        f"rho {out['march']['rho_range']}, speedup {out['speedup_vs_all_md']:.0f}x "
+        f"({out['speedup_vs_all_md_incl_presim_and_database']:.0f}x with pre-simulations and database)")
+    hy.close()
+    pg.close()
+    qg.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +521,8 @@ def main():
     ap.add_argument("--all-md-steps", type=int, default=1, help="macro steps run all-MD to price the all-MD march")
     ap.add_argument("--hybrid-budget", type=float, default=60.0,
                     help="wall-clock cap (s) of one hybrid run; the speed-up is then taken over the steps done")
+    ap.add_argument("--no-eos-gp", action="store_true",
+                    help="skip the hybrid solve with the pressure GP and the 3-input flux GP")
     ap.add_argument("--no-finish", action="store_true",
                     help="stop after the timed steps (no flux results): for short profiled runs")
     ap.add_argument("--no-autotune", action="store_true",
@@ -580,6 +699,8 @@ def main():
         out["flux_rel_se_median"] = float(np.median([r["flux_se"] / abs(r["flux"]) for r in res if r["flux"]]))
     if not args.no_hybrid:
         out.update(hybrid_bench(args, hmd, res))
+    if not args.no_hybrid and not args.no_eos_gp:
+        out["hybrid_eos_gp"] = eos_gp_bench(args, hmd)
     if not args.no_cpu:
         cb = cpu_baseline(args.cpu_seconds)
         out["cpu_baseline"] = cb

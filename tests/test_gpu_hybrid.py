@@ -292,3 +292,90 @@ def test_paper_periodic_channel_matches_oracle():
     assert oh.mass() == pytest.approx(m0, rel=1e-13)
     assert st["md_calls"] == oh.md_calls > 0 and st["audited"] == oh.audited
     assert np.any(r["g"] < 0) or np.any(oh.forces() < 0)  # the force reverses over the period
+
+
+# ---------------------------------------------------------------- the paper's full input set (eos 1)
+def law_p(h, rho):
+    # a known equation of state with a weak height dependence (the walls'
+    # layering), and the pressure-run SE
+    h, rho = np.asarray(h, dtype=np.float64), np.asarray(rho, dtype=np.float64)
+    return 1.5 + 12.0 * (rho - 0.8) + 30.0 * (rho - 0.8) ** 2 + 0.2 / h, 0.01 + 0.0 * h
+
+
+def law3(h, rho, g):
+    q = poiseuille_flux(h, g, rho=rho, eta=2.0, slip=0.5)
+    p, pse = law_p(h, rho)
+    return q, 0.002 + 1e-4 * h, p, pse
+
+
+def test_pressure_gp_march_matches_oracle():
+    # Alg. 1 with both GPs: section pressures from the pressure GP p(h, rho)
+    # (pre-simulations over a density sweep of every section height), flux
+    # queries at (h, rho, |g|), fallbacks at their sections' densities adding
+    # their pressure where (h, rho) is new; the device march equals the
+    # oracle march step by step
+    from oracle.hybrid import presimulate
+    cfg = dict(CFG, tau_rel=0.03, audit_every=0, dp_mean=0.6, dt_macro=0.01, eos=1)
+    cfg["p_out"] = float(law_p(10.0, 0.8)[0])
+    n, L = cfg["n_sections"], cfg["L"]
+    # mirrored sections' heights agree to the last bit or two: one
+    # pre-simulation per height (near-duplicate rows would leave the
+    # pressure GP's covariance needlessly ill-conditioned)
+    heights = np.unique(np.round(hy_h(cfg), 9))
+    Xp, p0, pse0 = presimulate(lambda h, r: law_p(h, r), heights, np.linspace(0.6, 1.0, 9))
+    rng = np.random.default_rng(3)
+    X0 = np.column_stack([rng.uniform(5, 15, 12), rng.uniform(0.78, 0.86, 12), rng.uniform(0.0, 0.02, 12)])
+    y0, se0, _, _ = law3(X0[:, 0], X0[:, 1], X0[:, 2])
+    ctx = hmd.Context()
+    hp_p, hp_q = dict(ranges=(16.0, 0.6)), dict(ranges=(16.0, 0.6, 0.049))
+    pg = B.GP(ctx, Xp, p0, pse0, B.gp_hyper(**hp_p))
+    qg = B.GP(ctx, X0, y0, se0, B.gp_hyper(**hp_q))
+    hy = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=0, **cfg), gp=qg, micro=law3, pgp=pg)
+    opg = OGP(Xp, p0, pse0, Hyper(**hp_p))
+    oqg = OGP(X0, y0, se0, Hyper(**hp_q))
+    oh = OHybrid(OCfg(**cfg), oqg, law3, psur=opg)
+    for step in range(30):
+        st = hy.step()
+        oh.step()
+        r = hy.get()
+        p, ps = hy.pressure()
+        assert np.array_equal(r["from_md"], oh.from_md), step
+        np.testing.assert_allclose(p, oh.p, rtol=1e-9)
+        np.testing.assert_allclose(ps, oh.p_std, rtol=1e-6, atol=1e-12)
+        np.testing.assert_allclose(r["rho"], oh.rho, rtol=1e-11)
+        np.testing.assert_allclose(r["q"], oh.q, rtol=1e-8, atol=1e-12)
+    assert st["md_calls"] == oh.md_calls > 0
+    assert st["p_appends"] == oh.p_appends > 0
+    assert len(pg) == len(p0) + oh.p_appends and len(qg) == len(y0) + oh.md_calls
+    assert oh.rho.max() - oh.rho.min() > 1e-3  # the densities did move
+
+
+def test_pressure_gp_march_with_batched_md():
+    # the same march on real MD: fallbacks run at their sections' own
+    # densities with the wall pressure recorded, and the pressure GP grows
+    params = hmd.Params(Lx_nom=12.0, Lz_nom=12.0, n_equil=300)
+    ctx = hmd.Context(params)
+    heights = hy_h(dict(n_sections=4, L=40.0, h0=10.0, amp=0.5))
+    pre = [(h, 0.0, 50 + k, 600, r) for k, (h, r) in enumerate((h, r) for h in np.unique(heights)
+                                                                 for r in (0.7, 0.8, 0.9))]
+    ctx.set_params(hmd.Params(Lx_nom=12.0, Lz_nom=12.0, n_equil=300, pressure=1))
+    res = hmd.md_flux_batch(ctx, pre)
+    ctx.set_params(params)
+    assert all(r["status"] == 0 for r in res)
+    Xp = np.array([[j[0], j[4]] for j in pre])
+    pp = np.array([r["p"] for r in res])
+    # denser liquid, higher wall pressure
+    for h in np.unique(heights):
+        row = pp[Xp[:, 0] == h]
+        assert row[0] < row[1] < row[2]
+    pg = B.GP(ctx, Xp, pp, np.array([r["p_se"] for r in res]), B.gp_hyper(ranges=(16.0, 0.6)))
+    qg = B.GP(ctx, np.zeros((0, 3)), np.zeros(0), None, B.gp_hyper(ranges=(16.0, 0.6, 0.049)))
+    cfg = HB.hybrid_cfg(surrogate=0, n_sections=4, L=40.0, h0=10.0, amp=0.5, dt_macro=1e-3, dp_mean=0.5,
+                        p_out=float(pp.mean()), md_sample=400, tau_rel=1e-9, eos=1)
+    hy = HB.Hybrid(ctx, cfg, gp=qg, pgp=pg)
+    hy.set_rho(np.array([0.82, 0.81, 0.79, 0.78]))
+    st = hy.step()
+    r = hy.get()
+    assert st["md_calls"] == 4 and np.all(r["from_md"]) and st["md_failed"] == 0
+    assert st["p_appends"] == 4 and len(pg) == len(pre) + 4 and len(qg) == 4
+    assert np.all(np.isfinite(r["q"]))

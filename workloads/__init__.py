@@ -64,3 +64,26 @@ def surrogate_training_jobs(n_train: int = 256, n_test: int = 64):
     """Training (seeds 0..255) and held-out (seeds 256..319) draws for the
     learned surrogate, with the batch protocol."""
     return batch_jobs(n_train, 0), batch_jobs(n_test, n_train)
+
+
+@dataclass(frozen=True)
+class Job3:
+    h: float
+    rho: float
+    g: float
+    seed: int
+
+
+def u3(k: int, j: int) -> float:
+    """Three independent draws per index k (j = 0, 1, 2) for the 3-input
+    workloads: SplitMix64 state 2^40 + 3k + j, clear of the 2k + j states
+    of u01 for every k below 2^38."""
+    return (splitmix64((1 << 40) + 3 * k + j) >> 11) * (1.0 / (1 << 53))
+
+
+def density_jobs(n: int, first: int, h_lo: float, h_hi: float, rho_lo: float, rho_hi: float,
+                 g_lo: float, g_hi: float) -> List[Job3]:
+    """(h, rho, g) draws for the flux database of the 3-input surrogate:
+    uniform in each range, seed 100000 + k."""
+    return [Job3(h_lo + (h_hi - h_lo) * u3(k, 0), rho_lo + (rho_hi - rho_lo) * u3(k, 1),
+                 g_lo + (g_hi - g_lo) * u3(k, 2), 100000 + k) for k in range(first, first + n)]
