@@ -108,3 +108,23 @@ def test_channel_viscosity_and_pressure_match_the_bulk_liquid(wide_channel):
     t_thermal = 0.5 * (rb["T"][1] + rb["T"][2])
     p_bulk = rho_b * t_thermal + db["virial"] / db["samples"] / (3.0 * b.Lx * b.Lz * b.h)
     assert p_wall == pytest.approx(p_bulk, rel=0.05), (p_wall, p_bulk)
+
+
+@pytest.mark.slow
+def test_isothermal_sound_speed_of_the_bulk_liquid():
+    # c^2 = dp/drho at T = 1 from the virial pressure of the bulk periodic box
+    # at densities 0.78 and 0.82 (the macro model's equation of state reading
+    # compares its artificial c^2 = 200 with this); kinetic part from the
+    # thermostatted temperature
+    ps = []
+    for rho in (0.78, 0.82):
+        b, pb = _bulk(rho, 2000)
+        b.run(2000 + 8000)
+        d = b.flow_diag()
+        r = b.result()
+        rho_b = b.n_fluid / (b.Lx * b.Lz * b.h)
+        ps.append((rho_b, rho_b * float(np.mean(r["T"])) + d["virial"] / d["samples"] / (3.0 * b.Lx * b.Lz * b.h)))
+    c2 = (ps[1][1] - ps[0][1]) / (ps[1][0] - ps[0][0])
+    print("bulk pressures", ps, "c2", c2)
+    assert ps[0][1] < ps[1][1]
+    assert 10.0 < c2 < 30.0
