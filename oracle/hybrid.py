@@ -40,7 +40,7 @@ pressure surrogate (Alg. 1 GPreg on C_p; inputs h and rho); the flux query
 is x* = (h, rho, F) (three inputs, F = g per unit mass); the micro-solver
 returns flux and pressure with their standard errors, the flux joins the flux
 database and the pressure joins the pressure database when its (h, rho) is
-not there yet.  The boundary pressures p_in(t) and p_out are then absolute.
+not there yet (both within a relative 1e-9 of an entry count as present).  The boundary pressures p_in(t) and p_out are then absolute.
 The pressure database comes from pre-simulations (``presimulate``): per
 distinct section height, runs at rest over a sweep of densities (the paper
 removes atoms progressively from one run; here each density is its own run,
@@ -130,10 +130,17 @@ class Hybrid:
         self.plan_equil = np.zeros(n, dtype=np.int64)
         self.plan_batch_equil = 0
         self.psur = psur
-        self.p_db = set() if psur is None else {(float(a), float(b)) for a, b in np.asarray(psur.X)}
+        self.p_db = np.zeros((0, 2)) if psur is None else np.asarray(psur.X, dtype=np.float64).reshape(-1, 2).copy()
         self.p_appends = 0
         self.p = np.zeros(n)
         self.p_std = np.zeros(n)
+
+    def p_known(self, xp):
+        """Whether (h, rho) is in the pressure database: both inputs equal
+        within a relative 1e-9 (a reading of Alg. 1's test; section heights
+        computed with two libraries' cosines can differ in the last bits)."""
+        d = np.abs(self.p_db - xp) <= 1e-9 * np.maximum(np.abs(self.p_db), np.abs(xp))
+        return bool(np.any(d[:, 0] & d[:, 1]))
 
     def p_in(self, t_steps):
         c = self.c
@@ -220,9 +227,10 @@ class Hybrid:
                         self.warm.append((self.h[i], gq[i]))
                     # Alg. 1: the run's pressure joins the pressure database
                     # when its (h, rho) is not there yet
-                    if c.eos == 1 and (float(self.h[i]), float(self.rho[i])) not in self.p_db:
-                        self.psur.append(np.array([self.h[i], self.rho[i]]), pm[k], pse[k])
-                        self.p_db.add((float(self.h[i]), float(self.rho[i])))
+                    xp = np.array([self.h[i], self.rho[i]])
+                    if c.eos == 1 and not self.p_known(xp):
+                        self.psur.append(xp, pm[k], pse[k])
+                        self.p_db = np.vstack([self.p_db, xp])
                         self.p_appends += 1
         self.q, self.q_std, self.from_md = q, std, flag
         if c.geometry == 1:  # periodic faces: the last one closes the ring

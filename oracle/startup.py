@@ -106,13 +106,14 @@ def startup_steps(t_s, dt, n_min):
 
 def nearest_prior(X_db, x_star, scale, has_state):
     """Index of the database entry with a stored state, the same channel
-    height as x_star (first input), and the largest squared-exponential
-    covariance with x_star over inputs normalised by `scale` (Eq.
-    quadraticKernelEq: the smallest normalised distance); -1 when none.
-    Ties go to the earliest entry."""
+    height as x_star (first input; equal within a relative 1e-9, since
+    heights computed with different libraries' cosines can differ in the
+    last bits), and the largest squared-exponential covariance with x_star
+    over inputs normalised by `scale` (Eq. quadraticKernelEq: the smallest
+    normalised distance); -1 when none.  Ties go to the earliest entry."""
     best, best_d = -1, np.inf
     for i, x in enumerate(np.asarray(X_db, dtype=np.float64)):
-        if not has_state[i] or x[0] != x_star[0]:
+        if not has_state[i] or abs(x[0] - x_star[0]) > 1e-9 * max(abs(x[0]), abs(x_star[0])):
             continue
         d = float(np.sum(((x - x_star) / scale) ** 2))
         if d < best_d:

@@ -141,9 +141,8 @@ def test_warm_start_plan_picks_nearest_same_height_run():
     # the oracle march's plan: a section's first fallback starts from the
     # lattice (n_min_cold at least); a later one from the recorded run of the
     # same height with the nearest body force, for its pseudoMD start-up.
-    # Heights are compared exactly: the mirror sections i and n-1-i differ
-    # in the last bit of their cosine, so each section restarts from its own
-    # earlier runs
+    # Heights are compared within a relative 1e-9 (the mirror sections i and
+    # n-1-i can differ in the last bit of their cosine)
     from oracle import startup
     cfg = HybridCfg(n_sections=8, L=80.0, h0=10.0, dt_macro=0.002, dp_mean=3.0, dp_amp=0.3, period=6.0,
                     tau_rel=1e-9, warm_start=True, n_min_warm=300, n_min_cold=2500)
@@ -155,9 +154,11 @@ def test_warm_start_plan_picks_nearest_same_height_run():
     assert len(hy.warm) == 16
     for i in range(8):
         h_i, g_i = hy.warm[8 + i]  # this step's run of section i (all fell back, in order)
-        cands = [j for j in range(8) if hy.warm[j][0] == h_i]
+        cands = [j for j in range(8) if abs(hy.warm[j][0] - h_i) <= 1e-9 * h_i]
         assert len(cands) >= 1
-        best = min(cands, key=lambda j: (abs(hy.warm[j][1] - g_i), j))
+        # largest covariance = smallest normalised distance (unit scales in
+        # the march), ties to the earliest
+        best = min(cands, key=lambda j: ((hy.warm[j][0] - h_i) ** 2 + (hy.warm[j][1] - g_i) ** 2, j))
         assert hy.plan_prior[i] == best
         ts = startup.startup_time(h_i, hy.warm[best][1], g_i, 2.5, 0.5, 0.01)
         assert hy.plan_equil[i] == startup.startup_steps(ts, 0.005, 300)
@@ -300,3 +301,14 @@ def test_presimulation_sweeps_every_distinct_height():
     assert seen == [18] and Xp.shape == (18, 2)
     assert sorted(set(Xp[:, 0])) == [6.0, 8.0, 10.0]
     np.testing.assert_allclose(p, 1.0 + 10.0 * (Xp[:, 1] - 0.8) + 0.01 * Xp[:, 0])
+
+
+def test_pressure_database_membership_tolerates_last_bit_differences():
+    # the same (h, rho) up to a relative 1e-9 counts as present; a real
+    # difference (1e-7) does not
+    cfg = HybridCfg(n_sections=4, L=40.0, eos=1)
+    hy = Hybrid(cfg, ThreeInput(), micro, psur=LinearP(np.array([[10.0, 0.8], [12.0, 0.75]])))
+    assert hy.p_known(np.array([10.0 * (1 + 4e-16), 0.8]))
+    assert hy.p_known(np.array([12.0, 0.75 * (1 - 5e-10)]))
+    assert not hy.p_known(np.array([10.0, 0.8 * (1 + 1e-7)]))
+    assert not hy.p_known(np.array([12.0, 0.8]))
