@@ -336,9 +336,14 @@ def hybrid_bench(args, hmd, first_results):
     log(f"all-MD: {nv} steps in {allmd['wall_s']:.1f} s, {md_rate:.3e} atom-steps/s -> {all_md_s:.0f} s for "
         f"{args.hybrid_steps} steps; training MD {train_md_s:.1f} s")
     runs = []
+    # the GP under both rules (the plain one only at the thresholds of
+    # --plain-taus: elsewhere it falls back at nearly every section and a run
+    # stops at its time budget after a step or two), the ensembles under the
+    # floor rule at --ens-taus
     plan = [(name, sid, tau, rule) for name, sid in (("gp", 0), ("ensemble", 1), ("ensemble_bootstrap", 2))
-            for tau in args.taus
-            for rule in args.rules if name == "gp" or tau in args.ens_taus]
+            for tau in args.taus for rule in args.rules
+            if (name == "gp" and (rule != "plain" or tau in args.plain_taus))
+            or (name != "gp" and tau in args.ens_taus and rule != "plain")]
     for name, sid, tau, rule in plan:
         floor = tau_abs if rule == "floor" else 0.0
         st = run(sid, tau, args.hybrid_steps, args.audit_every, budget_s=args.hybrid_budget, floor=floor)
@@ -374,14 +379,16 @@ def hybrid_bench(args, hmd, first_results):
 # The paper's benchmark channel with its full input set (Sec. 2.2; Alg. 1
 # with both GPs): 40 sections on a periodic ring (Eqs. subsEq, heightEq:
 # h from 6 to 10 sigma), driven by the external force of Eq. extForcing1
-# (amplitude 0.02 per unit mass, period 400 macro steps).  The pressure GP
-# p(h, rho) comes from pre-simulations at rest over a density sweep of every
-# section height; the flux GP over (h, rho, g) from batched runs at the
-# march's protocol.
-EG = dict(n_sections=40, h0=10.0, amp=0.2, L=400.0, geometry=1, f_amp=0.02, f_period=400.0, rho_ref=0.8)
-EG_RHOS = (0.70, 0.75, 0.80, 0.85, 0.90, 0.95)
+# (amplitude 0.01 per unit mass, period 400 macro steps: the narrowest
+# sections then see body forces up to about 0.045, the top of the flux
+# database).  The pressure GP p(h, rho) comes from pre-simulations at rest
+# over a density sweep of every section height (0.025 apart: the pressure
+# rises from about 1 to 17 between densities 0.70 and 0.95); the flux GP over
+# (h, rho, g) from batched runs at the march's protocol.
+EG = dict(n_sections=40, h0=10.0, amp=0.2, L=400.0, geometry=1, f_amp=0.01, f_period=400.0, rho_ref=0.8)
+EG_RHOS = tuple(round(0.70 + 0.025 * k, 3) for k in range(11))
 EG_PRE = (2000, 4000)     # pre-simulation equilibration and sampling steps
-EG_TRAIN = 128            # flux database runs
+EG_TRAIN = 96             # flux database runs
 EG_STEPS = 300            # macro steps
 
 
@@ -455,7 +462,7 @@ def eos_gp_bench(args, hmd):
     p, p_sd = hy.pressure()
     # all-MD: every section every step at the march's protocol, atoms at each
     # section's height from the pre-simulations at the reference density
-    n_at = {round(pre[k][0], 9): rp[k]["n_fluid"] for k in okp if pre[k][4] == 0.80}
+    n_at = {round(pre[k][0], 9): rp[k]["n_fluid"] for k in okp if abs(pre[k][4] - 0.80) < 1e-12}
     per_step = float(sum(n_at.get(round(h, 9), 0) for h in heights)) * (N_EQUIL + N_SAMPLE)
     done = st["steps"]
     method_s = wall
@@ -519,7 +526,9 @@ def main():
                     help="GP sigma_f and l: maximise the evidence on the training data (Sec. 2.3's procedure), or "
                          "the paper's values 1, 1")
     ap.add_argument("--all-md-steps", type=int, default=1, help="macro steps run all-MD to price the all-MD march")
-    ap.add_argument("--hybrid-budget", type=float, default=60.0,
+    ap.add_argument("--plain-taus", type=lambda t: [float(x) for x in t.split(",")], default=[0.10],
+                    help="thresholds at which the GP also runs under the plain relative rule")
+    ap.add_argument("--hybrid-budget", type=float, default=40.0,
                     help="wall-clock cap (s) of one hybrid run; the speed-up is then taken over the steps done")
     ap.add_argument("--no-eos-gp", action="store_true",
                     help="skip the hybrid solve with the pressure GP and the 3-input flux GP")

@@ -462,9 +462,10 @@ typedef struct {
                           MD batch (0: in the step that drew them) */
     /* Warm starts (Alg. 1 "find nearest prior input", "pseudoMD"; Sec. 2.4):
      * with warm_start on, a fallback run starts from the final state of the
-     * earlier fallback run of the same height whose input has the largest
-     * covariance with the new one (the same height leaves only the body
-     * force to compare: the nearest |g|), else from the lattice; its
+     * earlier fallback run of the same height (equal within a relative 1e-9)
+     * whose input has the largest covariance with the new one, i.e. the
+     * smallest squared distance (dh^2 + dg^2, ties to the earliest), else
+     * from the lattice; its
      * equilibration is the start-up time of the 1-D channel flow with Navier
      * slip (viscosity pseudo_nu, slip length pseudo_slip) from the prior's
      * body force (0 from the lattice) to the new one, until the flow rate is
@@ -492,7 +493,8 @@ typedef struct {
      * instead of the linear law; the flux GP takes three inputs (h, rho, |g|);
      * every fallback runs at its section's density and also returns the
      * wall pressure, which joins the pressure GP when that (h, rho) is not in
-     * it yet.  The boundary pressures p_out and p_in(t) are then absolute.
+     * it yet (an entry within a relative 1e-9 in both inputs counts as
+     * present).  The boundary pressures p_out and p_in(t) are then absolute.
      * Needs surrogate 0 and no warm starts.  eos 0: the linear law. */
     int eos;
 } hmd_hybrid_cfg;

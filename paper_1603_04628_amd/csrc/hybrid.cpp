@@ -10,7 +10,6 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <set>
 #include <string>
 #include <utility>
 #include <vector>
@@ -38,7 +37,7 @@ struct hmd_hybrid {
   hmd_micro_p_fn micro_p = nullptr;  // eos 1 replacement micro-solver
   void* micro_p_user = nullptr;
   hmd_gp* pgp = nullptr;             // eos 1: pressure GP over (h, rho)
-  std::set<std::pair<double, double>> p_db;  // eos 1: (h, rho) inputs in the pressure GP
+  std::vector<std::pair<double, double>> p_db;  // eos 1: (h, rho) inputs in the pressure GP
   double ds = 0.0;
   std::vector<double> h, rho, q, q_std, g, p, p_std;
   std::vector<uint8_t> from_md;
@@ -57,6 +56,16 @@ struct hmd_hybrid {
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586;
+
+// Whether (h, rho) is among the pressure GP's inputs: both equal within a
+// relative 1e-9 (section heights computed with different libraries'
+// cosines can differ in the last bits).
+bool p_known(const std::vector<std::pair<double, double>>& db, double h, double rho) {
+  auto near = [](double a, double b) { return std::fabs(a - b) <= 1e-9 * std::fmax(std::fabs(a), std::fabs(b)); };
+  for (const auto& e : db)
+    if (near(e.first, h) && near(e.second, rho)) return true;
+  return false;
+}
 
 using clock_t_ = std::chrono::steady_clock;
 
@@ -295,7 +304,7 @@ int hybrid_set_pressure_gp(hmd_hybrid* hy, hmd_gp* pgp) {
   if (rc != HMD_OK) return rc;
   hy->pgp = pgp;
   hy->p_db.clear();
-  for (int k = 0; k < n; ++k) hy->p_db.insert({X[2 * size_t(k)], X[2 * size_t(k) + 1]});
+  for (int k = 0; k < n; ++k) hy->p_db.push_back({X[2 * size_t(k)], X[2 * size_t(k) + 1]});
   return HMD_OK;
 }
 
@@ -408,16 +417,21 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
     }
     std::vector<std::vector<double>> xs, vs;
     if (c.warm_start) {
-      // nearest prior of the same height: with h equal, the covariance of
-      // the inputs falls with |g - g*| alone; ties go to the earliest
+      // nearest prior of the same height (within a relative 1e-9: mirrored
+      // sections' heights can differ in the last bits): the largest
+      // covariance of the inputs is the smallest distance between them;
+      // ties go to the earliest
       hmd_md_params P;
       hmd_get_params(hy->ctx, &P);
       for (size_t k = 0; k < fl.size(); ++k) {
         int best = -1;
         double bd = 0.0;
         for (size_t j = 0; j < hy->warm.size(); ++j) {
-          if (hy->warm[j].h != hh[k] || (!hy->micro && hy->warm[j].x.empty())) continue;
-          const double d = std::fabs(hy->warm[j].g - gg[k]);
+          if (std::fabs(hy->warm[j].h - hh[k]) > 1e-9 * std::fmax(hy->warm[j].h, hh[k]) ||
+              (!hy->micro && hy->warm[j].x.empty()))
+            continue;
+          const double dh = hy->warm[j].h - hh[k], dg = hy->warm[j].g - gg[k];
+          const double d = dh * dh + dg * dg;  // squared distance of the inputs (unit scales)
           if (best < 0 || d < bd) {
             best = int(j);
             bd = d;
@@ -449,7 +463,8 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
         rc = gp_append(hy->gp, x, qm[k], se[k]);
         // Alg. 1: the run's pressure joins the pressure GP when its
         // (h, rho) is not there yet
-        if (rc == HMD_OK && press && hy->p_db.insert({hy->h[i], hy->rho[i]}).second) {
+        if (rc == HMD_OK && press && !p_known(hy->p_db, hy->h[i], hy->rho[i])) {
+          hy->p_db.push_back({hy->h[i], hy->rho[i]});
           const double xp[2] = {hy->h[i], hy->rho[i]};
           rc = gp_append(hy->pgp, xp, pm[k], pse[k]);
           hy->st.p_appends += 1;

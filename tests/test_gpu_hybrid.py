@@ -334,13 +334,19 @@ def test_pressure_gp_march_matches_oracle():
     opg = OGP(Xp, p0, pse0, Hyper(**hp_p))
     oqg = OGP(X0, y0, se0, Hyper(**hp_q))
     oh = OHybrid(OCfg(**cfg), oqg, law3, psur=opg)
+    # the two pressure GPs agree before the march starts
+    Xs = np.column_stack([hy_h(cfg), np.full(n, 0.8)])
+    mg, vg = pg.predict(Xs)
+    mo, vo = opg.predict(Xs)
+    np.testing.assert_allclose(mg, mo, rtol=1e-10)
+    np.testing.assert_allclose(vg, vo, rtol=1e-6, atol=1e-14)
     for step in range(30):
         st = hy.step()
         oh.step()
         r = hy.get()
         p, ps = hy.pressure()
         assert np.array_equal(r["from_md"], oh.from_md), step
-        np.testing.assert_allclose(p, oh.p, rtol=1e-9)
+        assert np.allclose(p, oh.p, rtol=1e-9, atol=0), (step, np.abs(p / oh.p - 1).max(), len(pg), oh.p_appends)
         np.testing.assert_allclose(ps, oh.p_std, rtol=1e-6, atol=1e-12)
         np.testing.assert_allclose(r["rho"], oh.rho, rtol=1e-11)
         np.testing.assert_allclose(r["q"], oh.q, rtol=1e-8, atol=1e-12)

@@ -393,3 +393,36 @@ def test_timed_graph_replays_report_kernel_times():
     if nr > 0:
         assert tr > 5.0 * ti
         assert (nr * tr + ni * ti) / 20 == pytest.approx(b.kernel_ms("list")[0], rel=1e-9)
+
+
+@pytest.mark.parametrize("h,rho,box", [(6.0, 0.8, SMALL_L), (4.2, 0.8, LARGE), (9.87, 0.72, SMALL_L),
+                                       (15.0, 0.9, SMALL_L)])
+def test_initial_state_meets_the_reading(h, rho, box):
+    # the library's start lattice against the reading itself, not the
+    # oracle: N_f = round(rho Lx Lz h) atoms on planes within [delta, h -
+    # delta] (delta = 1), no two closer than the lattice allows, velocities
+    # with zero mean and exactly T0 over 3 N_f degrees of freedom, drawn
+    # normal (kurtosis 3) before the rescale
+    ctx = hmd.Context(hmd.Params(n_equil=0, **box))
+    b = hmd.Batch(ctx, [(h, 0.01, 21, 10, rho)])
+    x, v = b.get_state(0)
+    n = b.n_fluid(0)
+    o = omd.System(h, 0.01, 21, omd.Params(rho=rho, **box))  # only for the snapped box extents
+    Lx, Lz = o.Lx, o.Lz
+    assert n == round(rho * Lx * Lz * h) == len(x)
+    assert x[:, 1].min() >= 1.0 - 1e-12 and x[:, 1].max() <= h - 1.0 + 1e-12
+    assert np.all((x[:, 0] >= 0) & (x[:, 0] < Lx) & (x[:, 2] >= 0) & (x[:, 2] < Lz))
+    # plane structure: equally spaced planes from delta to h - delta
+    ys = np.unique(np.round(x[:, 1], 9))
+    if len(ys) > 1:
+        assert ys[0] == pytest.approx(1.0, abs=1e-9) and ys[-1] == pytest.approx(h - 1.0, abs=1e-9)
+        assert np.allclose(np.diff(ys), np.diff(ys)[0], rtol=1e-9)
+    if n <= 5000:
+        d = x[:, None, :] - x[None, :, :]
+        d[..., 0] -= Lx * np.round(d[..., 0] / Lx)
+        d[..., 2] -= Lz * np.round(d[..., 2] / Lz)
+        r = np.sqrt((d ** 2).sum(-1))[np.triu_indices(n, 1)]
+        assert r.min() > 0.95
+    assert np.abs(v.mean(0)).max() < 1e-13
+    assert (v ** 2).sum() / (3 * n) == pytest.approx(1.0, abs=1e-12)
+    assert abs(np.mean(v ** 4) / np.mean(v ** 2) ** 2 - 3.0) < 0.5
