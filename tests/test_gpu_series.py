@@ -210,3 +210,33 @@ def test_per_job_density_and_pressure_rejected_on_the_cell_path():
         assert np.array_equal(x, xo) and np.abs(v - vo).max() <= 1e-14
     with pytest.raises(hmd.HmdError):
         hmd.Batch(hmd.Context(hmd.Params(force_path=0, pressure=1, **SMALL_L)), jobs[:1])
+
+
+def test_full_batch_pressure_matches_oracle_wall_forces():
+    # the 64-channel batch (2,115,470 atoms, default path and skin), each
+    # channel at its own density around 0.8, with the wall pressure on and
+    # sampling from the first step: the last sampled step's pressure of the
+    # thinnest, a middle and the thickest channel equals the oracle's wall
+    # normal force per area at that state, (F_lo,y - F_hi,y) / (2 Lx Lz)
+    box = workloads.batch_box()
+    params = dict(n_equil=0, **box)
+    ctx = hmd.Context(hmd.Params(skin=0.35, pressure=1, **params))
+    jobs = workloads.batch_jobs(64)
+    rhos = [0.72 + 0.16 * (k % 5) / 4 for k in range(64)]
+    n = 300
+    b = hmd.Batch(ctx, [(j.h, j.g, j.seed, n, r) for j, r in zip(jobs, rhos)])
+    b.run(n, graph_chunk=100)
+    hs = [j.h for j in jobs]
+    for sim in sorted({int(np.argmin(hs)), 31, int(np.argmax(hs))}):
+        x, v = b.get_state(sim)
+        ps = b.pressure_series(sim)
+        assert len(ps) == n and np.all(np.isfinite(ps))
+        j = jobs[sim]
+        o = omd.System(j.h, j.g, j.seed, omd.Params(rho=rhos[sim], cell_w=2.5 + 0.35, **params))
+        assert o.n_fluid == b.n_fluid(sim)
+        o.set_state(x, v)
+        fd = o.force_diag()
+        po = 0.5 * (fd["wall_lo"][1] - fd["wall_hi"][1]) / (o.Lx * o.Lz)
+        assert ps[-1] == pytest.approx(po, rel=1e-5), (sim, ps[-1], po)
+    r = b.results()
+    assert all(q["status"] in (0, -5) and q["p"] > 0.0 and q["p_se"] > 0.0 for q in r)
