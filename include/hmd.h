@@ -375,6 +375,10 @@ int gp_optimize(hmd_gp* gp, int mask, double* lml);
 int gp_hyper_get(const hmd_gp* gp, hmd_gp_hyper* hyper);
 /* The database inputs (n x d row-major into X, nullable) and *n, *d. */
 int gp_inputs(const hmd_gp* gp, double* X, int* n, int* d);
+/* The database outputs and their standard errors as given to gp_fit and
+ * gp_append (n doubles each, nullable): with gp_inputs, a copy of the
+ * database, e.g. to start another march from it (Sec. 3.4). */
+int gp_outputs(const hmd_gp* gp, double* y, double* y_se);
 int gp_size(const hmd_gp* gp);
 /* The normalisation in use: per-input denominators of Eq. d2Eq (d values),
  * the output scale and sigma_n in scaled units (each nullable). */
@@ -540,6 +544,13 @@ int hybrid_set_pressure_gp(hmd_hybrid* hy, hmd_gp* pgp);
 /* eos 1: the section pressures of the last step and their GP standard
  * deviations (n_sections doubles each, nullable); eos 0: the linear law. */
 int hybrid_get_pressure(hmd_hybrid* hy, double* p, double* p_std);
+/* Forcing variants of Sec. 3.4 (the variable-frequency and
+ * variable-amplitude cases): on the periodic channel (geometry 1), macro
+ * step k takes F_ext / m = f[k] in place of Eq. extForcing1's sinusoid.
+ * f is n host doubles, copied; n = 0 restores the sinusoid.  EINVAL for
+ * geometry 0, a non-finite entry, or (from hybrid_step) a step at or past
+ * the end of the table. */
+int hybrid_set_forcing(hmd_hybrid* hy, const double* f, int64_t n);
 /* Overwrite the density of every section (n_sections doubles). */
 int hybrid_set_rho(hmd_hybrid* hy, const double* rho);
 /* The fallback plan of the last macro step, per section (each nullable):

@@ -134,6 +134,15 @@ class Hybrid:
         self.p_appends = 0
         self.p = np.zeros(n)
         self.p_std = np.zeros(n)
+        self.forcing = None       # geometry 1: F_ext / m per macro step (Sec. 3.4 forcing variants)
+
+    def set_forcing(self, f):
+        """Macro step k takes f[k] in place of Eq. extForcing1 (the
+        variable-frequency and variable-amplitude cases of Sec. 3.4)."""
+        if self.c.geometry != 1:
+            raise ValueError("a forcing table needs the periodic channel")
+        f = np.asarray(f, dtype=np.float64)
+        self.forcing = f.copy() if len(f) else None
 
     def p_known(self, xp):
         """Whether (h, rho) is in the pressure database: both inputs equal
@@ -147,8 +156,13 @@ class Hybrid:
         return c.p_out + c.dp_mean * (1.0 + c.dp_amp * np.sin(2.0 * np.pi * t_steps / c.period))
 
     def f_ext(self, t_steps):
-        """Eq. extForcing1 (geometry 1), per unit mass."""
+        """Eq. extForcing1 (geometry 1), per unit mass, or the step's entry
+        of the forcing table."""
         c = self.c
+        if self.forcing is not None:
+            if t_steps >= len(self.forcing):
+                raise ValueError("the march has reached the end of its forcing table")
+            return float(self.forcing[t_steps])
         return c.f_amp * np.sin(2.0 * np.pi * t_steps / c.f_period) if c.geometry == 1 else 0.0
 
     def pressure(self):

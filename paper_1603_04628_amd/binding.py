@@ -513,6 +513,8 @@ _sig("gp_log_marginal", i32, vp, P(d))
 _sig("gp_optimize", i32, vp, i32, P(d))
 _sig("gp_hyper_get", i32, vp, P(GpHyper))
 _sig("gp_size", i32, vp)
+_sig("gp_inputs", i32, vp, P(d), P(i32), P(i32))
+_sig("gp_outputs", i32, vp, P(d), P(d))
 _sig("gp_scales", i32, vp, P(d), P(d), P(d))
 _sig("gp_free", None, vp)
 
@@ -576,6 +578,14 @@ class GP:
         v = d()
         self.ctx.check(_lib.gp_log_marginal(self._h, _c.byref(v)))
         return v.value
+
+    def data(self):
+        """The database: inputs (n x d), outputs and their standard errors."""
+        n = len(self)
+        X, y, se = np.zeros((n, self.d)), np.zeros(n), np.zeros(n)
+        self.ctx.check(_lib.gp_inputs(self._h, _ptr(X), None, None))
+        self.ctx.check(_lib.gp_outputs(self._h, _ptr(y), _ptr(se)))
+        return X, y, se
 
     def scales(self):
         sc = np.zeros(self.d)

@@ -811,6 +811,13 @@ int gp_inputs(const hmd_gp* g, double* X, int* n, int* d) {
   return HMD_OK;
 }
 
+int gp_outputs(const hmd_gp* g, double* y, double* y_se) {
+  if (!g) return HMD_EINVAL;
+  if (y) std::copy(g->y.begin(), g->y.begin() + g->n, y);
+  if (y_se) std::copy(g->se.begin(), g->se.begin() + g->n, y_se);
+  return HMD_OK;
+}
+
 int gp_scales(const hmd_gp* g, double* scale, double* s_q, double* sigma_n) {
   if (!g) return HMD_EINVAL;
   if (scale)

@@ -38,6 +38,7 @@ struct hmd_hybrid {
   void* micro_p_user = nullptr;
   hmd_gp* pgp = nullptr;             // eos 1: pressure GP over (h, rho)
   std::vector<std::pair<double, double>> p_db;  // eos 1: (h, rho) inputs in the pressure GP
+  std::vector<double> forcing;       // geometry 1: F_ext / m per macro step, in place of the sinusoid
   double ds = 0.0;
   std::vector<double> h, rho, q, q_std, g, p, p_std;
   std::vector<uint8_t> from_md;
@@ -308,6 +309,15 @@ int hybrid_set_pressure_gp(hmd_hybrid* hy, hmd_gp* pgp) {
   return HMD_OK;
 }
 
+int hybrid_set_forcing(hmd_hybrid* hy, const double* f, int64_t n) {
+  if (!hy || n < 0 || (n > 0 && !f)) return HMD_EINVAL;
+  if (n > 0 && hy->cfg.geometry != 1) return HMD_EINVAL;  // a table needs the periodic channel
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(f[k])) return HMD_EINVAL;
+  hy->forcing.assign(f, f + n);
+  return HMD_OK;
+}
+
 int hybrid_get_pressure(hmd_hybrid* hy, double* p, double* p_std) {
   if (!hy) return HMD_EINVAL;
   const int n = hy->cfg.n_sections;
@@ -331,6 +341,8 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   const int n = c.n_sections;
   const bool press = c.eos == 1;
   if (press && !hy->pgp) return HMD_EINVAL;  // eos 1 needs hybrid_set_pressure_gp first
+  // the march has reached the end of its forcing table
+  if (!hy->forcing.empty() && hy->step_no >= int64_t(hy->forcing.size())) return HMD_EINVAL;
   // pressure (linear law, or eos 1: the pressure GP at (h, rho)),
   // central-difference gradient with ghost pressures, body force
   std::vector<double> p(n);
@@ -353,8 +365,12 @@ int hybrid_step(hmd_hybrid* hy, hmd_hybrid_stats* out) {
   }
   hy->p = p;
   const double p_in = c.p_out + c.dp_mean * (1.0 + c.dp_amp * std::sin(kTwoPi * double(hy->step_no) / c.period));
-  // Eq. extForcing1 on the periodic channel
-  const double f_ext = c.geometry == 1 ? c.f_amp * std::sin(kTwoPi * double(hy->step_no) / c.f_period) : 0.0;
+  // Eq. extForcing1 on the periodic channel, or the step's entry of a
+  // forcing table (the variable-frequency and variable-amplitude cases of
+  // Sec. 3.4)
+  const double f_ext = !hy->forcing.empty() ? hy->forcing[size_t(hy->step_no)]
+                       : c.geometry == 1   ? c.f_amp * std::sin(kTwoPi * double(hy->step_no) / c.f_period)
+                                           : 0.0;
   for (int i = 0; i < n; ++i) {
     double pl, pr;
     if (c.geometry == 1) {

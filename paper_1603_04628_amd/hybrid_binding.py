@@ -38,6 +38,7 @@ _sig("hybrid_set_micro", i32, vp, MICRO_FN, vp)
 _sig("hybrid_set_micro_p", i32, vp, MICRO_P_FN, vp)
 _sig("hybrid_set_pressure_gp", i32, vp, vp)
 _sig("hybrid_get_pressure", i32, vp, P(d), P(d))
+_sig("hybrid_set_forcing", i32, vp, P(d), i64)
 _sig("hybrid_set_rho", i32, vp, P(d))
 _sig("hybrid_step", i32, vp, P(HybridStats))
 _sig("hybrid_get", i32, vp, P(d), P(d), P(d), P(d), P(u8))
@@ -117,6 +118,12 @@ class Hybrid:
         fm = np.zeros(self.n, dtype=np.uint8)
         self.ctx.check(_lib.hybrid_get(self._h, _ptr(rho), _ptr(q), _ptr(qs), _ptr(g), _ptr(fm, u8)))
         return {"rho": rho, "q": q, "q_std": qs, "g": g, "from_md": fm.astype(bool)}
+
+    def set_forcing(self, f):
+        """Per-macro-step F_ext / m on the periodic channel (empty: the
+        sinusoid of the configuration)."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self.ctx.check(_lib.hybrid_set_forcing(self._h, _ptr(f) if len(f) else None, len(f)))
 
     def pressure(self):
         """Section pressures of the last step and their GP standard deviations."""

@@ -223,3 +223,23 @@ def test_optimised_hyperparameters_match_oracle(ctx, which, kernel):
     assert g.log_marginal() == pytest.approx(lg, rel=1e-12)
     Xs = X[:10] + 0.01
     assert np.abs(g.predict(Xs)[0] - o.predict(Xs)[0]).max() <= 1e-4 * np.abs(y).max()
+
+
+def test_database_copy_round_trips(ctx):
+    # gp_inputs + gp_outputs return the database as given (fit, then
+    # appends), and a GP fitted to that copy answers exactly as the original
+    X, y, se = data(40, 11)
+    hp = B.gp_hyper(ranges=RANGES, sigma_n=0.01, scale_mode=1, out_scale=0)
+    g = B.GP(ctx, X[:30], y[:30], se[:30], hp)
+    for k in range(30, 40):
+        g.append(X[k], y[k], se[k])
+    Xc, yc, sc = g.data()
+    assert np.array_equal(Xc, X) and np.array_equal(yc, y) and np.array_equal(sc, se)
+    c = B.GP(ctx, Xc, yc, sc, hp)
+    Xs, _, _ = data(50, 12)
+    m0, v0 = g.predict(Xs)
+    m1, v1 = c.predict(Xs)
+    np.testing.assert_allclose(m1, m0, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(v1, v0, rtol=1e-6, atol=1e-14)
+    e = B.GP(ctx, np.zeros((0, 2)), np.zeros(0), np.zeros(0), hp)
+    assert len(e) == 0 and all(len(a) == 0 for a in e.data())

@@ -385,3 +385,51 @@ def test_pressure_gp_march_with_batched_md():
     assert st["md_calls"] == 4 and np.all(r["from_md"]) and st["md_failed"] == 0
     assert st["p_appends"] == 4 and len(pg) == len(pre) + 4 and len(qg) == 4
     assert np.all(np.isfinite(r["q"]))
+
+
+def test_forcing_table_march_from_an_empty_database_matches_oracle():
+    # the paper's Case 1 set-up with a Sec. 3.4 forcing variant: five
+    # subdomains of the periodic channel starting at unequal densities, an
+    # empty flux database with fixed hyperparameters (sigma_f, sigma_n in
+    # flux units), the absolute threshold sigma_t = 0.1 sigma_f, and a
+    # forcing table whose amplitude grows by a quarter over the run; the
+    # device march equals the oracle march step by step, the first step
+    # falling back everywhere (an empty database answers with the prior)
+    from oracle.hybrid import presimulate
+    n, L, h0, amp = 5, 200.0, 10.0, 0.2
+    cfg = dict(n_sections=n, h0=h0, amp=amp, L=L, dt_macro=2.0, rho_ref=0.78, tau_rel=0.0, tau_abs=0.1,
+               audit_every=0, geometry=1, f_amp=0.03, f_period=40.0, eos=1)
+    heights = amp * h0 * (np.cos(2.0 * np.pi * np.arange(n) / n) - 1.0) + h0
+    Xp, p0, pse0 = presimulate(lambda h, r: law_p(h, r), np.unique(np.round(heights, 9)),
+                               np.linspace(0.6, 1.0, 9))
+    hp_p = dict(ranges=(16.0, 0.6))
+    hp_q = dict(ranges=(16.0, 0.6, 0.049), sigma_f=1.0, sigma_n=0.003, scale_mode=1, out_scale=0)
+    ctx = hmd.Context()
+    pg = B.GP(ctx, Xp, p0, pse0, B.gp_hyper(**hp_p))
+    qg = B.GP(ctx, np.zeros((0, 3)), np.zeros(0), np.zeros(0), B.gp_hyper(**hp_q))
+    rho0 = np.array([0.782, 0.776, 0.751, 0.748, 0.771])
+    hy = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=0, **cfg), gp=qg, micro=law3, pgp=pg)
+    hy.set_rho(rho0)
+    q_hyper = Hyper(ranges=(16.0, 0.6, 0.049), sigma_f=1.0, sigma_n=0.003, scale_mode=1, out_scale=0)
+    oh = OHybrid(OCfg(**cfg), OGP(np.zeros((0, 3)), np.zeros(0), np.zeros(0), q_hyper), law3,
+                 rho0=rho0, psur=OGP(Xp, p0, pse0, Hyper(**hp_p)))
+    K = 80
+    k = np.arange(K)
+    f = 0.03 * (1.0 + 0.25 * k / K) * np.sin(2.0 * np.pi * k / 40.0)
+    hy.set_forcing(f)
+    oh.set_forcing(f)
+    m0 = oh.mass()
+    for step in range(K):
+        st = hy.step()
+        oh.step()
+        r = hy.get()
+        assert np.array_equal(r["from_md"], oh.from_md), step
+        if step == 0:
+            assert r["from_md"].all()
+        np.testing.assert_allclose(r["rho"], oh.rho, rtol=1e-11)
+        np.testing.assert_allclose(r["q"], oh.q, rtol=1e-8, atol=1e-12)
+    assert oh.mass() == pytest.approx(m0, rel=1e-13)
+    assert st["md_calls"] == oh.md_calls and n < oh.md_calls < n * K
+    assert len(qg) == oh.md_calls
+    with pytest.raises(hmd.HmdError):
+        hy.step()  # past the end of the table

@@ -212,6 +212,31 @@ def test_periodic_channel_reaches_reynolds_lubrication_flow():
     assert hy.q.std() <= 0.001 * Q
 
 
+def test_forcing_table_replaces_the_sinusoid():
+    # Sec. 3.4 forcing variants: step k takes the table's f[k] as F_ext / m.
+    # At the first step the densities are uniform, so the pressure gradient
+    # vanishes and every section's body force is exactly f[0]: the fluxes are
+    # the lubrication law at (h_i, f[0])
+    hy = Hybrid(_paper_cfg(10), Exact(), micro, var_is_std=True)
+    f = np.array([0.021, -0.004, 0.013])
+    hy.set_forcing(f)
+    hy.step()
+    assert np.array_equal(hy.q, poiseuille_flux(hy.h, np.full(10, 0.021)))
+    hy.step()
+    hy.step()
+    with pytest.raises(ValueError):
+        hy.step()  # past the end of the table
+    # the sinusoid written out as a table gives the sinusoidal march
+    a, b = (Hybrid(_paper_cfg(10, f_period=37.0), Exact(), micro, var_is_std=True) for _ in range(2))
+    b.set_forcing(0.03 * np.sin(2.0 * np.pi * np.arange(60) / 37.0))
+    for _ in range(60):
+        a.step()
+        b.step()
+        assert np.array_equal(a.q, b.q) and np.array_equal(a.rho, b.rho)
+    with pytest.raises(ValueError):
+        Hybrid(HybridCfg(n_sections=4), Exact(), micro, var_is_std=True).set_forcing([0.1])
+
+
 # ---------------------------------------------------------------- pressure surrogate (eos = 1)
 class LinearP:
     """A pressure surrogate that is the linear law itself (zero spread)."""
