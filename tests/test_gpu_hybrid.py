@@ -433,3 +433,28 @@ def test_forcing_table_march_from_an_empty_database_matches_oracle():
     assert len(qg) == oh.md_calls
     with pytest.raises(hmd.HmdError):
         hy.step()  # past the end of the table
+
+
+def test_forcing_table_arguments():
+    # a table needs the periodic channel, finite entries; an empty table
+    # restores the configuration's sinusoid
+    ctx = hmd.Context()
+    X0 = np.array([[10.0, 0.01], [6.0, 0.02]])
+    y0, se0 = law(X0[:, 0], X0[:, 1])
+    g = B.GP(ctx, X0, y0, se0, B.gp_hyper(ranges=(16.0, 0.049)))
+    h0 = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=0, **CFG), gp=g, micro=law)
+    with pytest.raises(hmd.HmdError):
+        h0.set_forcing([0.01, 0.02])
+    cfg1 = dict(CFG, geometry=1, f_amp=0.02, f_period=10.0, L=200.0, amp=0.2, tau_rel=1e9)
+    ga, gb = (B.GP(ctx, X0, y0, se0, B.gp_hyper(ranges=(16.0, 0.049))) for _ in range(2))  # each march grows its own
+    a = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=0, **cfg1), gp=ga, micro=law)
+    b = HB.Hybrid(ctx, HB.hybrid_cfg(surrogate=0, **cfg1), gp=gb, micro=law)
+    with pytest.raises(hmd.HmdError):
+        a.set_forcing([0.01, float("nan")])
+    a.set_forcing([0.5, 0.5])
+    a.set_forcing([])
+    for _ in range(5):
+        a.step()
+        b.step()
+    ra, rb = a.get(), b.get()
+    assert np.array_equal(ra["q"], rb["q"]) and np.array_equal(ra["rho"], rb["rho"])
