@@ -36,7 +36,7 @@ typedef enum {
     HMD_EUNSTABLE = -4,  /* MD blew up: non-finite state or an atom left the gap */
     HMD_ENOTCONV = -5,   /* sampled flux not stationary (critical shear), Sec. 3.2 */
     HMD_ENOTSPD = -6,    /* GP covariance not positive definite                 */
-    HMD_ENOSYS = -7      /* not available in this build                         */
+    HMD_ENOSYS = -7      /* not available in this library                       */
 } hmd_status;
 
 typedef struct hmd_ctx hmd_ctx;
