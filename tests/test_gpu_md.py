@@ -74,6 +74,36 @@ def test_cell_membership_bit_exact(h, params, steps, path):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("path", PATHS)
+def test_cell_sort_is_stable(path):
+    # the counting sort keeps the previous slot order inside every cell:
+    # sorting an already sorted state changes nothing, and after the atoms
+    # move, the members of a new cell that came from one old cell keep
+    # their old relative order (bit-exact, whatever the cell numbering)
+    ctx, g_sys, o_sys = _pair(6.0, 0.02, 9, path, **SMALL_L)
+    o_sys.run(100)
+    x1, v1 = o_sys.get_state()
+    g_sys.set_state(x1, v1)
+    cell1, cnt1, order1 = (a.astype(np.int64) for a in g_sys.cells())
+    g_sys.set_state(x1, v1)
+    _, _, order2 = (a.astype(np.int64) for a in g_sys.cells())
+    assert np.array_equal(order2, order1)
+    o_sys.run(40)
+    x3, v3 = o_sys.get_state()
+    g_sys.set_state(x3, v3)
+    cell3, cnt3, order3 = (a.astype(np.int64) for a in g_sys.cells())
+    assert np.any(cell3 != cell1)  # some atoms changed cells
+    rank1 = np.empty_like(order1)
+    rank1[order1] = np.arange(len(order1))  # position of each atom in the old order
+    start3 = np.concatenate([[0], np.cumsum(cnt3)[:-1]])
+    for c in np.nonzero(cnt3)[0]:
+        m = order3[start3[c]:start3[c] + cnt3[c]]
+        assert np.all(cell3[m] == c)
+        for oc in np.unique(cell1[m]):
+            sub = m[cell1[m] == oc]
+            assert np.all(np.diff(rank1[sub]) > 0), (c, oc)
+
+
 @pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("h,params,steps", [(6.0, SMALL_L, 300), (4.0, SMALL_L, 100), (12.0, SMALL_L, 200),
                                             (15.0, SMALL, 200)])
