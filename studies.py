@@ -184,15 +184,20 @@ class Study:
 
     def macro_dt(self):
         """Explicit-diffusion limit of the march at N = 5 from the D5
-        surrogates, D = |dq/dg| |dp/drho| / (rho h); dt = 0.4 ds^2 / max D."""
+        surrogates, D = |dq/dg| |dp/drho| / (rho h), taken over the whole
+        database box (the three heights, its densities, forces up to F_A):
+        the liquid's dp/drho steepens fast with density, and sections that
+        compress past the initial state must stay within the limit;
+        dt = 0.4 ds^2 / max D."""
         X5, y5, s5 = self.db_union((0, 1, 2))
         qg = self.B.GP(self.ctx, X5, y5, s5, self.hp_q)
         pg = self.B.GP(self.ctx, self.Xp, self.pp, self.pse, self.hp_p)
-        h = heights(N0)
-        r = np.array(RHO0)
+        hh, rr, gg = np.meshgrid(np.array(self.h123), np.linspace(DB_RHOS[0], DB_RHOS[-1], 9),
+                                 np.linspace(0.1 * F_A, F_A, 4), indexing="ij")
+        h, r, g = hh.ravel(), rr.ravel(), gg.ravel()
         d = 1e-3
-        qa, _ = qg.predict(np.column_stack([h, r, np.full(N0, 0.5 * F_A + d)]))
-        qb, _ = qg.predict(np.column_stack([h, r, np.full(N0, 0.5 * F_A - d)]))
+        qa, _ = qg.predict(np.column_stack([h, r, g + d]))
+        qb, _ = qg.predict(np.column_stack([h, r, g - d]))
         pa, _ = pg.predict(np.column_stack([h, r + d]))
         pb, _ = pg.predict(np.column_stack([h, r - d]))
         qg.close()
