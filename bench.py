@@ -441,13 +441,18 @@ def eos_gp_bench(args, hmd):
     hctx = hmd.Context(hmd.Params(n_equil=N_EQUIL, **box))
     pg = B.GP(hctx, Xp, pp, pse, hp_p)
     qg = B.GP(hctx, X, y, se, hp_q)
-    # macro step from the explicit diffusion limit, D = (dq/dg)(dp/drho) / (rho h)
+    # macro step from the explicit diffusion limit, D = (dq/dg)(dp/drho) / (rho h),
+    # over the flux database's box (every section height, its densities and
+    # forces): the liquid's dp/drho steepens fast with density, and sections
+    # that compress past the reference must stay within the limit
     dg, dr = 1e-3, 1e-3
-    qa, _ = qg.predict(np.column_stack([heights, np.full(n, 0.8), np.full(n, 0.02 + dg)]))
-    qb, _ = qg.predict(np.column_stack([heights, np.full(n, 0.8), np.full(n, 0.02 - dg)]))
-    pa, _ = pg.predict(np.column_stack([heights, np.full(n, 0.8 + dr)]))
-    pb, _ = pg.predict(np.column_stack([heights, np.full(n, 0.8 - dr)]))
-    D = np.abs((qa - qb) / (2 * dg)) * np.abs((pa - pb) / (2 * dr)) / (0.8 * heights)
+    hh, rr, gg = (a.ravel() for a in np.meshgrid(hu, np.linspace(0.72, 0.92, 9), np.linspace(0.0045, 0.045, 4),
+                                                  indexing="ij"))
+    qa, _ = qg.predict(np.column_stack([hh, rr, gg + dg]))
+    qb, _ = qg.predict(np.column_stack([hh, rr, gg - dg]))
+    pa, _ = pg.predict(np.column_stack([hh, rr + dr]))
+    pb, _ = pg.predict(np.column_stack([hh, rr - dr]))
+    D = np.abs((qa - qb) / (2 * dg)) * np.abs((pa - pb) / (2 * dr)) / (rr * hh)
     dt = 0.4 * (L / n) ** 2 / float(D.max())
     cfg = HB.hybrid_cfg(surrogate=0, eos=1, tau_rel=0.05, tau_abs=float(np.median(se)), md_sample=N_SAMPLE,
                         dt_macro=dt, audit_every=0, **EG)
