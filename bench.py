@@ -238,11 +238,11 @@ def hybrid_bench(args, hmd, first_results):
         hyper_info.update(sigma_f=hp["sigma_f"], ell=hp["ell"], lml_at_1_1=lml0, lml=lml,
                           optimize_s=time.perf_counter() - t0)
         log(f"gp hyperparameters by evidence: {hyper_info}")
-    ecfg = B.ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3)
+    ecfg = B.ens_cfg(members=5, hidden=64, iters=args.ens_iters, lr=1e-3)
     Xq = Xt[np.arange(200) % len(Xt)]
     fits = {}
     # the bootstrap ensemble: each member on its own resample of the data
-    ecfg_boot = B.ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3, bootstrap=1)
+    ecfg_boot = B.ens_cfg(members=5, hidden=64, iters=args.ens_iters, lr=1e-3, bootstrap=1)
     variants = (("gp", 0), ("gp_per_point_noise", 0), ("ensemble", 1), ("ensemble_bootstrap", 2))
     for name, kind in variants:
         t0 = time.perf_counter()
@@ -527,6 +527,8 @@ def main():
                          "audits visit different sections (k = 1000 audits one section only)")
     ap.add_argument("--hybrid-steps", type=int, default=HY_STEPS)
     ap.add_argument("--refit-every", type=int, default=1, help="ensemble retrains after this many new MD points")
+    ap.add_argument("--ens-iters", type=int, default=20000,
+                    help="Adam iterations of each ensemble member (5000 leaves the members short of convergence)")
     ap.add_argument("--gp-hyper", choices=("evidence", "paper"), default="evidence",
                     help="GP sigma_f and l: maximise the evidence on the training data (Sec. 2.3's procedure), or "
                          "the paper's values 1, 1")
