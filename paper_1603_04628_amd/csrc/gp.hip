@@ -457,12 +457,13 @@ int upload_db(hmd_gp* g) {
   return HMD_OK;
 }
 
-int solve_alpha(hmd_gp* g, bool grown_by_row) {
+int solve_alpha(hmd_gp* g, bool grown_by_row, bool inverse = true) {
   hmd_ctx* ctx = g->ctx;
   hipStream_t s = ctx->stream;
   HMD_HIP(ctx, hipMemcpyAsync(g->dalpha, g->dy, 8 * size_t(g->n), hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_gp_solve, dim3(1), dim3(1024), 0, s, g->n, g->cap, g->dL, g->dalpha, 1);
   HMD_HIP(ctx, hipGetLastError());
+  if (!inverse) return HMD_OK;
   // L^-1 follows the factor: extended by its new row, or formed anew
   const size_t lds = sizeof(double) * size_t(g->n);
   if (grown_by_row)
@@ -474,14 +475,16 @@ int solve_alpha(hmd_gp* g, bool grown_by_row) {
   return HMD_OK;
 }
 
-// Full refit: normalisation, covariance, factorisation, weights.
-int refit(hmd_gp* g) {
+// Full refit: normalisation, covariance, factorisation, weights and L^-1.
+// The evidence search refits at fixed data (upload false: the database and
+// its scaling are already on the device) and needs no L^-1 (inverse false).
+int refit(hmd_gp* g, bool upload = true, bool inverse = true) {
   hmd_ctx* ctx = g->ctx;
   normalise(g);
   if (g->n == 0) return HMD_OK;
   int rc = reserve(g, g->n);
   if (rc != HMD_OK) return rc;
-  if ((rc = upload_db(g)) != HMD_OK) return rc;
+  if (upload && (rc = upload_db(g)) != HMD_OK) return rc;
   hipStream_t s = ctx->stream;
   const KParams P = kparams(g);
   hipLaunchKernelGGL(k_gp_cov, dim3((g->n + 255) / 256, g->n), dim3(256), 0, s, g->n, g->cap, g->dX, P,
@@ -504,7 +507,7 @@ int refit(hmd_gp* g) {
     ctx->err = "gp: covariance not positive definite at pivot " + std::to_string(info - 1);
     return HMD_ENOTSPD;
   }
-  return solve_alpha(g, false);
+  return solve_alpha(g, false, inverse);
 }
 
 }  // namespace
@@ -714,6 +717,12 @@ int gp_optimize(hmd_gp* g, int mask, double* lml) {
     return HMD_EINVAL;
   }
   if (mask & 4) g->hyp.sigma_n = g->sigma_n * g->s_q;  // held explicitly from here on
+  // the database and its scaling stay on the device through the search
+  // (they do not depend on sigma_f, ell or sigma_n); L^-1 is formed once
+  // at the end
+  HMD_TRY(reserve(g, g->n));
+  normalise(g);
+  HMD_TRY(upload_db(g));
   auto get = [&](int k) {
     return k == 0 ? g->hyp.sigma_f : (k == 1 ? g->hyp.ell : g->hyp.sigma_n / g->s_q);
   };
@@ -724,7 +733,7 @@ int gp_optimize(hmd_gp* g, int mask, double* lml) {
   };
   auto eval = [&](int k, double logv, double* out) -> int {
     set(k, std::exp(logv));
-    const int rc = refit(g);
+    const int rc = refit(g, false, false);
     if (rc == HMD_ENOTSPD) {
       *out = -INFINITY;
       return HMD_OK;
@@ -745,7 +754,7 @@ int gp_optimize(hmd_gp* g, int mask, double* lml) {
   for (int p = 0; p < total; ++p) {
     int r = p;
     for (int j = 0; j < m; ++j, r /= 17) set(idx[j], std::exp(c0[j] + std::log(10.0) * (-2.0 + 0.25 * (r % 17))));
-    const int rc = refit(g);
+    const int rc = refit(g, false, false);
     if (rc == HMD_ENOTSPD) continue;
     if (rc != HMD_OK) return rc;
     double f;
@@ -790,6 +799,7 @@ int gp_optimize(hmd_gp* g, int mask, double* lml) {
     }
     if (std::fabs(best - start) <= 1e-12 * std::fabs(best)) break;
   }
+  HMD_TRY(refit(g, false, true));  // at the kept values, with L^-1 for predictions
   if (lml) *lml = best;
   HMD_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return HMD_OK;
