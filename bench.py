@@ -663,6 +663,11 @@ def main():
     plain = plain_atoms / plain_time if plain_time > 0 else None
     log(f"plain: {plain} atom-steps/s")
 
+    # achievable device rates (outside the timed region), beside the
+    # published peaks the roofline divides by
+    from paper_1603_04628_amd import binding as B
+    peaks = B.measure_peaks(ctx)
+    log(f"achievable: {peaks}")
     force_ms = kern["force"]
     achieved = pairs_per_launch * FLOP_PER_PAIR / (force_ms * 1e-3) / 1e12
     cnt = committed_counters(FORCE_KERNELS[cfg["path"]])
@@ -694,9 +699,12 @@ def main():
                    "list_builds_per_step": builds / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": cnt["traffic"] if cnt else None,
+                     "achievable_peak": peaks["fp32_fma_tflops"],
+                     "frac_of_achievable": achieved / peaks["fp32_fma_tflops"],
                      "counter_tflops": cnt["flop"] / (force_ms * 1e-3) / 1e12 if cnt else None,
                      "kernel": FORCE_KERNELS[cfg["path"]], "avg_ms": force_ms,
                      "pairs_per_launch": pairs_per_launch, "flop_per_pair": FLOP_PER_PAIR},
+        "achievable_peaks": peaks,
         "plain_atom_steps_per_s": plain,
         "batched_over_plain": value / plain if plain else None,
         "plain_sample": f"{len(plain_jobs)} systems of the batch (every {stride}th: h = "

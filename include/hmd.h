@@ -105,6 +105,14 @@ void hmd_md_params_default(hmd_md_params* p);
 int hmd_create(const hmd_md_params* params, int device, void* hip_stream, hmd_ctx** out);
 void hmd_destroy(hmd_ctx* ctx);
 const char* hmd_last_error(const hmd_ctx* ctx);
+/* Achievable rates of the context's device, for the rooflines beside the
+ * published peaks.  Each kernel runs once to warm up, then five timed times:
+ * out[0] FP32 fused multiply-add TFLOP/s (eight independent chains per
+ * thread, unpacked as this library is compiled), out[1] FP32 reciprocals
+ * per second (x 1e12), out[2] the time of a reciprocal in fused
+ * multiply-adds, out[3] GB/s of a 1 GiB device copy (bytes read plus
+ * written).  Allocates and frees 2 GiB; ENOMEM if it cannot. */
+int hmd_measure_peaks(hmd_ctx* ctx, double* out);
 /* Replace (or read) the MD parameters used by later calls on this context. */
 int hmd_set_params(hmd_ctx* ctx, const hmd_md_params* params);
 int hmd_get_params(const hmd_ctx* ctx, hmd_md_params* params);

@@ -505,6 +505,7 @@ class GpHyper(_c.Structure):
 
 
 _sig("hmd_gp_hyper_default", None, P(GpHyper))
+_sig("hmd_measure_peaks", i32, vp, P(d))
 _sig("gp_fit", i32, vp, P(d), P(d), P(d), i32, i32, P(GpHyper), P(vp))
 _sig("gp_append", i32, vp, P(d), d, d)
 _sig("gp_predict", i32, vp, P(d), i32, P(d), P(d))
@@ -633,6 +634,15 @@ _sig("ens_loss", i32, vp, P(d))
 _sig("ens_grad_init", i32, vp, P(d), P(d), i32, P(EnsCfg), i32, P(d), P(d), P(i32))
 _sig("ens_members", i32, vp)
 _sig("ens_free", None, vp)
+
+
+def measure_peaks(ctx: Context):
+    """hmd_measure_peaks: achievable FP32 FMA TFLOP/s, reciprocals per
+    second (x 1e12), a reciprocal's time in FMAs and device-copy GB/s."""
+    out = np.zeros(4)
+    ctx.check(_lib.hmd_measure_peaks(ctx.handle, _ptr(out)))
+    return {"fp32_fma_tflops": float(out[0]), "fp32_rcp_tops": float(out[1]),
+            "rcp_cost_in_fma": float(out[2]), "copy_gbs": float(out[3])}
 
 
 def ens_cfg(members=5, hidden=64, iters=5000, lr=1e-3, seed=0, bootstrap=0):

@@ -36,6 +36,7 @@ SOURCES = [
     ("ens.hip", "hip"),
     ("hybrid.cpp", "host"),
     ("startup.cpp", "host"),
+    ("peaks.hip", "hip"),
 ]
 
 
