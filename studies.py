@@ -1,5 +1,5 @@
-"""The studies of Sec. 3 on the paper's periodic benchmark channel, judged by
-this library's own MD (no full-channel MD data is available):
+"""The studies of Sec. 3 on the paper's periodic benchmark channel, measured
+against this library's own MD (no full-channel MD data is available):
 
   T1-T6  the uncertainty threshold (Sec. 3.1-3.2), from an empty flux database;
   D1-D5  the initial database (Sec. 3.3, Table preDatabases);
@@ -8,7 +8,7 @@ this library's own MD (no full-channel MD data is available):
   F1-F2  a variable-frequency and a variable-amplitude external force,
          starting from Case 1's database (Sec. 3.4).
 
-The judge is the all-MD march: every subdomain runs MD at every macro step,
+The reference is the all-MD march: every subdomain runs MD at every macro step,
 with the same protocol and the same pressure surrogate.  Its subdomain-mean
 flux series, smoothed by the App. B periodic-kernel GP over time, is the
 reference of Eq. error; its MD atom-steps stand for the full MD's in
@@ -208,7 +208,7 @@ class Study:
         self.out["setup"]["dt_macro_at_n5"] = self.dt5
 
     # -- marches ------------------------------------------------------------
-    def march(self, name, n, flux_db, p_db, tau, forcing=None, judge=False):
+    def march(self, name, n, flux_db, p_db, tau, forcing=None, all_md=False):
         """One march of STEPS (N / 5)^2 macro steps at dt (5 / N)^2, the
         forcing period scaled alike (the same physical time)."""
         B, HB = self.B, self.HB
@@ -216,7 +216,7 @@ class Study:
         steps, period, dt = STEPS * scale, PERIOD * scale, self.dt5 / scale
         Xq, yq, sq = flux_db
         hp_q = self.hp_q
-        if judge:  # a flux surrogate that is never certain: MD everywhere
+        if all_md:  # a flux surrogate that is never certain: MD everywhere
             hp_q = B.gp_hyper(ranges=(4.0, 0.212, G_SPAN), scale_mode=1, out_scale=0, sigma_n=1e6, sigma_f=1e6)
         qg = B.GP(self.ctx, Xq, yq, sq, hp_q)
         pg = B.GP(self.ctx, p_db[0], p_db[1], p_db[2], self.hp_p)
@@ -269,14 +269,14 @@ class Study:
             f"({res['calls_by_first_peak']} by the first peak)")
         return res, qbar[scale - 1::scale], calls, final
 
-    def judge_march(self, name, forcing=None):
+    def reference_march(self, name, forcing=None):
         """An all-MD march and its subdomain-mean flux smoothed over time by
         GP regression, the hyperparameters maximising the evidence: the
         App. B periodic kernel for Eq. extForcing1, a squared-exponential
         kernel in time for a forcing table that is not periodic."""
         p_db = (self.Xp, self.pp, self.pse)
         res, q, _, _ = self.march(name, N0, (np.zeros((0, 3)), np.zeros(0), np.zeros(0)), p_db, 0.0,
-                                  forcing=forcing, judge=True)
+                                  forcing=forcing, all_md=True)
         t = np.arange(len(q), dtype=np.float64)
         B = self.B
         if forcing is None:
@@ -296,19 +296,19 @@ class Study:
         log(f"{name}: raw series vs its smoothing, Eq. error {res['raw_error_pct']:.1f}%")
         return res, q, Q
 
-    def judge(self):
+    def reference(self):
         """The all-MD march of Eq. extForcing1: the reference of Cases T, D, S."""
-        res, q, Q = self.judge_march("judge (all-MD)")
+        res, q, Q = self.reference_march("reference (all-MD)")
         self.Q, self.Qraw = Q, q
-        self.judge_atom_steps = res["md_atom_steps"]
-        self.judge_wall = res["wall_s"]
-        self.out["judge"] = res
+        self.ref_atom_steps = res["md_atom_steps"]
+        self.ref_wall = res["wall_s"]
+        self.out["reference"] = res
 
     def score(self, res, qbar):
         res["error_pct"] = eq_error(qbar, self.Q)
         res["error_pct_at_first_peak"] = float(eq_error_series(qbar, self.Q)[PERIOD // 4 - 1])
-        res["speedup_atom_steps"] = self.judge_atom_steps / res["md_atom_steps"] if res["md_atom_steps"] > 0 else None
-        res["speedup_wall"] = self.judge_wall / res["wall_s"]
+        res["speedup_atom_steps"] = self.ref_atom_steps / res["md_atom_steps"] if res["md_atom_steps"] > 0 else None
+        res["speedup_wall"] = self.ref_wall / res["wall_s"]
         return res
 
     # -- the studies ----------------------------------------------------------
@@ -317,7 +317,7 @@ class Study:
         self.presimulate()
         self.flux_database()
         self.macro_dt()
-        self.judge()
+        self.reference()
         p_db = (self.Xp, self.pp, self.pse)
         empty = (np.zeros((0, 3)), np.zeros(0), np.zeros(0))
         case1 = None
@@ -347,8 +347,8 @@ class Study:
             self.out["F"] = {}
             # Case F1 has an all-MD march of its own forcing as reference
             # (Case F2 has none, as in the paper)
-            jres, _, QF1 = self.judge_march("judge F1 (all-MD)", forcing="chirp")
-            self.out["judge_F1"] = jres
+            jres, _, QF1 = self.reference_march("reference F1 (all-MD)", forcing="chirp")
+            self.out["reference_F1"] = jres
             for name, kind in (("F1", "chirp"), ("F2", "ramp")):
                 res, q, _, _ = self.march(name, N0, case1[0], case1[1], THRESH[0] * self.sigma_f, forcing=kind)
                 if name == "F1":
@@ -374,7 +374,7 @@ def markdown(out):
             lines.append(f"| {name} | {r['n_sections']} | {tau:.2f} | {r['db_start']} | {r['md_calls']} | "
                          f"{r['calls_by_first_peak']} | {'' if err is None else f'{err:.1f}'} | "
                          f"{'inf' if sp is None else f'{sp:.1f}'} | {r['wall_s']:.1f} |")
-    for key, label in (("judge", "judge (all-MD)"), ("judge_F1", "judge F1 (all-MD, F1's forcing)")):
+    for key, label in (("reference", "reference (all-MD)"), ("reference_F1", "reference F1 (all-MD, F1's forcing)")):
         if key not in out:
             continue
         j = out[key]
