@@ -111,7 +111,9 @@ const char* hmd_last_error(const hmd_ctx* ctx);
  * thread, unpacked as this library is compiled), out[1] FP32 reciprocals
  * per second (x 1e12), out[2] the time of a reciprocal in fused
  * multiply-adds, out[3] GB/s of a 1 GiB device copy (bytes read plus
- * written).  Allocates and frees 2 GiB; ENOMEM if it cannot. */
+ * written).  `out` is a caller-owned host array of 4 doubles.  Allocates
+ * and frees 2 GiB on the device; ENOMEM if it cannot, EINVAL for a null
+ * pointer, EDEVICE for a failed launch.  Synchronises the context's stream. */
 int hmd_measure_peaks(hmd_ctx* ctx, double* out);
 /* Replace (or read) the MD parameters used by later calls on this context. */
 int hmd_set_params(hmd_ctx* ctx, const hmd_md_params* params);
