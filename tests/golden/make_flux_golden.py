@@ -59,16 +59,33 @@ def main():
     fname, cases_of, nseeds, desc = SETS[name]
     nseeds = int(sys.argv[2]) if len(sys.argv) > 2 else nseeds
     cases, box, n_equil, n_sample = cases_of()
+    out = os.path.join(HERE, fname)
+    # finished runs are kept in out + ".partial" (one row per line, the final
+    # file's format) so that an interrupted set resumes where it stopped
+    partial = out + ".partial"
+    done = {}
+    if os.path.exists(partial):
+        with open(partial) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) == 9:
+                    done[(int(f[0]), int(f[3]))] = (int(f[0]), float(f[1]), float(f[2]), int(f[3]), int(f[4]),
+                                                    float(f[5]), float(f[6]), float(f[7]), int(f[8]))
     rows = []
     for c, h, g in cases:
         for s in range(FIRST_SEED, FIRST_SEED + nseeds):
+            if (c, s) in done and done[(c, s)][1:3] == (h, g):
+                rows.append(done[(c, s)])
+                continue
             t0 = time.time()
             p = md.Params(n_equil=n_equil, **box)
             r = md.md_flux(h, g, s, n_sample, p)
-            rows.append((c, h, g, s, r["n_fluid"], r["flux"], r["flux_se"], r["T"][1], r["status"]))
+            row = (c, h, g, s, r["n_fluid"], r["flux"], r["flux_se"], r["T"][1], r["status"])
+            rows.append(row)
+            with open(partial, "a") as fh:
+                fh.write("%d %.17g %.17g %d %d %.17g %.17g %.17g %d\n" % row)
             print(f"job {c} h={h:.4f} g={g:.5f} seed {s}: flux {r['flux']:.6f} +- {r['flux_se']:.6f} "
                   f"T_y {r['T'][1]:.4f} status {r['status']} ({time.time() - t0:.0f} s)", flush=True)
-    out = os.path.join(HERE, fname)
     with open(out, "w") as fh:
         fh.write("# oracle (FP64 CPU) mass flow rate per unit span, written by make_flux_golden.py\n")
         fh.write(f"# {desc}, {n_equil} + {n_sample} steps, dt 0.005, rc 2.5, T 1 (Berendsen "
@@ -76,6 +93,8 @@ def main():
         fh.write("# job h g seed n_fluid flux flux_se T_y status\n")
         for row in rows:
             fh.write("%d %.17g %.17g %d %d %.17g %.17g %.17g %d\n" % row)
+    if os.path.exists(partial):
+        os.remove(partial)
     print("wrote", out)
 
 
