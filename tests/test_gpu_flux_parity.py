@@ -1,10 +1,11 @@
-"""Mass-flux parity against oracle runs at two configurations:
+"""Mass-flux parity against oracle runs at three configurations:
 
 * the batch's own (density 0.8, 57.15 x 57.15 sigma box, 10,000 equilibration
   + 20,000 sampling steps): two channels of the batch (h = 4.53, g = 0.0165
   and h = 9.87, g = 0.0256);
 * the 2,048-atom channel (h = 6, g = 0.02) at a long protocol, 10,000 +
-  40,000 steps.
+  40,000 steps;
+* the 39,189-atom channel (h = 15, g = 0.0288), 20,000 + 50,000 steps.
 
 The oracle values are tests/golden/flux_*.txt, written by
 tests/golden/make_flux_golden.py (oracle only, seeds from 1000).  The GPU runs
@@ -80,3 +81,8 @@ def test_flux_matches_oracle_small_channel_long_protocol():
     _compare(_golden("flux_small_long.txt"), {0: (job.h, job.g)}, hmd.Params(n_equil=10000, **box), 40000,
              range(2000, 2064))
 
+
+def test_flux_matches_oracle_paper_scale_channel():
+    box, job, (n_equil, n_sample) = workloads.paper_scale_channel()
+    _compare(_golden("flux_paper_scale.txt"), {0: (job.h, job.g)}, hmd.Params(n_equil=n_equil, **box), n_sample,
+             range(2000, 2032))
